@@ -1,0 +1,830 @@
+/*
+ * snn_oracle.c -- plain CPU oracle (TEST INFRASTRUCTURE ONLY; see header).
+ *
+ * Follows Golosio et al., arXiv 2007.14236:
+ *   - LIF exact integration on the dt grid (Sec. 2.1; membrane and exponential
+ *     PSC equations of Sec. 2.3, after Rotter & Diesmann 1999),
+ *   - multisynapse AdEx with conductance synapses (Sec. 2.4, AdEx membrane,
+ *     conductance-current and adaptation equations, Table 2) integrated by a
+ *     fifth-order Runge-Kutta method with adaptive step-size control
+ *     (Sec. 2.1, after Press et al. 1992: the Cash-Karp embedded pair),
+ *   - spike delivery (Sec. 2.2, Fig. 1): a spike emitted at step n by source s
+ *     reaches, at step n + d, exactly the synapses of s whose delay is d steps.
+ *     Here that is computed as its plain definition: for every target step,
+ *     loop over d = 1..Dmax, over the spikes emitted at step (target - d), and
+ *     over the synapses of that source with delay d.
+ *   - the fixed-indegree connection rule (Sec. 2.1) and Poisson generators
+ *     (Sec. 2.1; Table 1), with randomness from Philox4x64-10.
+ *
+ * No blocking, fusion or reordering beyond those definitions.  Compiled with
+ * -O2 -ffp-contract=off -fno-fast-math so that every float operation rounds as
+ * written.
+ */
+#include "snn_oracle.h"
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11).  Round: two 64x64->128 products of counter words */
+/* 0 and 2 with the published multipliers, output permuted and xored with    */
+/* the key; the key is bumped by the published Weyl constants between rounds. */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2E7470EE14C6C93ULL
+#define PHILOX_M1 0xCA5A826395121157ULL
+#define PHILOX_W0 0x9E3779B97F4A7C15ULL
+#define PHILOX_W1 0xBB67AE8584CAA73BULL
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += PHILOX_W0; k1 += PHILOX_W1; }
+    unsigned __int128 p0 = (unsigned __int128)PHILOX_M0 * x0;
+    unsigned __int128 p1 = (unsigned __int128)PHILOX_M1 * x2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t y0 = hi1 ^ x1 ^ k0;
+    uint64_t y1 = lo1;
+    uint64_t y2 = hi0 ^ x3 ^ k1;
+    uint64_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discretised distributions.                                                */
+/* A delay of d ms is d/dt steps rounded half up, at least 1 step (delays are */
+/* clipped at dt) and at most Dmax (upper tail folded into Dmax).  Hence      */
+/* P(D <= k) = F((k + 1/2) dt) for 1 <= k < Dmax and 1 for k = Dmax, and a    */
+/* 32-bit uniform u maps to D = min{k : u < floor(2^32 P(D <= k))}.           */
+/* ------------------------------------------------------------------------ */
+static double delay_cdf(int kind, double a, double b, double x) {
+  if (kind == ORC_DELAY_CONST) {
+    return x >= a ? 1.0 : 0.0;
+  } else if (kind == ORC_DELAY_UNIFORM) {
+    double f = (x - a) / (b - a);
+    if (f < 0.0) f = 0.0;
+    if (f > 1.0) f = 1.0;
+    return f;
+  } else {
+    /* normal with mean a, standard deviation b */
+    return 0.5 * erfc(-(x - a) / (b * sqrt(2.0)));
+  }
+}
+
+static uint64_t prob_to_threshold(double p) {
+  if (!(p > 0.0)) return 0;
+  if (p >= 1.0) return 4294967296ULL;
+  double t = floor(ldexp(p, 32));
+  if (t >= 4294967296.0) return 4294967296ULL;
+  return (uint64_t)t;
+}
+
+int orc_delay_table(int kind, double a, double b, double dt, uint32_t dmax, uint64_t* thr) {
+  if (dmax < 1 || dmax > 63 || !(dt > 0)) return -1;
+  if (kind == ORC_DELAY_UNIFORM && !(b > a)) return -1;
+  if (kind == ORC_DELAY_NORMAL_CLIPPED && !(b > 0)) return -1;
+  thr[0] = 0;
+  if (kind == ORC_DELAY_CONST) {
+    double q = floor(a / dt + 0.5);
+    uint32_t d0 = q < 1.0 ? 1u : (q > (double)dmax ? dmax : (uint32_t)q);
+    for (uint32_t k = 1; k <= dmax; ++k) thr[k] = (k >= d0) ? 4294967296ULL : 0;
+    return 0;
+  }
+  for (uint32_t k = 1; k < dmax; ++k) {
+    double x = ((double)k + 0.5) * dt;
+    thr[k] = prob_to_threshold(delay_cdf(kind, a, b, x));
+  }
+  thr[dmax] = 4294967296ULL;
+  return 0;
+}
+
+/* Poisson(lambda): p_0 = e^-lambda, p_k = p_{k-1} lambda / k, cumulated in   */
+/* order; the tail beyond kmax-1 is folded into kmax-1.                       */
+int orc_poisson_table(double lambda, uint32_t kmax, uint64_t* thr) {
+  if (!(lambda >= 0) || kmax < 2) return -1;
+  double p = exp(-lambda);
+  double c = p;
+  for (uint32_t k = 0; k + 1 < kmax; ++k) {
+    if (k > 0) { p = p * lambda / (double)k; c = c + p; }
+    thr[k] = prob_to_threshold(c);
+  }
+  thr[kmax - 1] = 4294967296ULL;
+  return 0;
+}
+
+int orc_fixed_point_shift(double max_abs_w) {
+  if (!(max_abs_w > 0)) return 0;
+  int e;
+  (void)frexp(max_abs_w, &e); /* max_abs_w = m 2^e, 0.5 <= m < 1 */
+  return 30 - e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Network                                                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  uint32_t src_first, src_n, tgt_first, tgt_n, K, port;
+  double weight;
+  uint64_t dthr[64];
+} orc_proj;
+
+typedef struct {
+  uint32_t tgt_first, tgt_n, port;
+  double weight, lambda;
+  uint64_t thr[ORC_POISSON_KMAX];
+} orc_pois;
+
+typedef struct {
+  uint32_t src, tgt;
+  uint8_t d, port;
+  int64_t wq;
+} orc_syn;
+
+struct orc_net {
+  double dt;
+  uint64_t seed;
+  uint32_t dmax;
+  int mode;
+  int built;
+  char err[256];
+  /* populations */
+  uint32_t n_pops;
+  orc_pop_params* pops;
+  uint32_t* pop_first;
+  uint32_t N;
+  uint32_t P;               /* ports per neuron slot (max over populations) */
+  uint32_t* pop_of;         /* N */
+  /* projections and Poisson drives */
+  uint32_t n_proj; orc_proj* proj;
+  uint32_t n_pois; orc_pois* pois;
+  int32_t* pois_of;         /* N: index into pois or -1 */
+  /* fixed point shifts per (population, port) */
+  int* shift;               /* n_pops * P */
+  /* synapses sorted canonically and offsets per (source, delay) */
+  uint64_t n_syn;
+  orc_syn* syn;
+  uint64_t* off;            /* N*(dmax+1)+1 */
+  /* state (double; FP32SO mode keeps float copies for LIF) */
+  double* V; double* Ie; double* w; double* g; double* I; double* h; int32_t* refr;
+  float* Vf; float* If; float* Ief;
+  /* integer input accumulator for the next step, N*P */
+  int64_t* acc;
+  uint64_t step;
+  /* spike record */
+  uint64_t n_spk, cap_spk;
+  uint64_t* spk_step; uint32_t* spk_gid; uint32_t* spk_mult;
+  /* per-step spike-record offsets: spikes of step n at [spk_at[n], spk_at[n+1]) */
+  uint64_t* spk_at; uint64_t cap_at;
+  /* optional input recording */
+  int64_t* rec; uint64_t rec_max;
+  /* counters */
+  uint64_t rk_acc, rk_rej;
+};
+
+static void set_err(orc_net* o, const char* m) { snprintf(o->err, sizeof o->err, "%s", m); }
+const char* orc_last_error(const orc_net* o) { return o ? o->err : "null net"; }
+
+orc_net* orc_create(double dt_ms, uint64_t seed, uint32_t max_delay_steps, int mode) {
+  if (!(dt_ms > 0) || max_delay_steps < 1 || max_delay_steps > 63) return NULL;
+  orc_net* o = (orc_net*)calloc(1, sizeof(orc_net));
+  o->dt = dt_ms; o->seed = seed; o->dmax = max_delay_steps; o->mode = mode;
+  return o;
+}
+
+void orc_destroy(orc_net* o) {
+  if (!o) return;
+  free(o->pops); free(o->pop_first); free(o->pop_of); free(o->proj); free(o->pois); free(o->pois_of);
+  free(o->shift); free(o->syn); free(o->off);
+  free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->I); free(o->h); free(o->refr);
+  free(o->Vf); free(o->If); free(o->Ief); free(o->acc);
+  free(o->spk_step); free(o->spk_gid); free(o->spk_mult); free(o->spk_at);
+  free(o);
+}
+
+int64_t orc_population(orc_net* o, uint32_t n, const orc_pop_params* p) {
+  if (o->built) { set_err(o, "population after build"); return -1; }
+  if (n == 0 || p->n_ports < 1 || p->n_ports > ORC_MAX_PORTS) { set_err(o, "bad population"); return -1; }
+  if (p->model == ORC_LIF_DELTA && p->n_ports != 1) { set_err(o, "lif_delta has one port"); return -1; }
+  o->pops = (orc_pop_params*)realloc(o->pops, (o->n_pops + 1) * sizeof(orc_pop_params));
+  o->pop_first = (uint32_t*)realloc(o->pop_first, (o->n_pops + 1) * sizeof(uint32_t));
+  o->pops[o->n_pops] = *p;
+  o->pop_first[o->n_pops] = o->N;
+  o->n_pops++;
+  int64_t first = o->N;
+  o->N += n;
+  return first;
+}
+
+static uint32_t pop_index(const orc_net* o, uint32_t gid) {
+  uint32_t k = 0;
+  while (k + 1 < o->n_pops && o->pop_first[k + 1] <= gid) ++k;
+  return k;
+}
+
+int orc_connect_fixed_indegree(orc_net* o, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
+                               uint32_t tgt_n, uint32_t indegree, double weight, int delay_kind,
+                               double da, double db, uint32_t port) {
+  if (o->built) { set_err(o, "connect after build"); return -1; }
+  if ((uint64_t)src_first + src_n > o->N || (uint64_t)tgt_first + tgt_n > o->N || src_n == 0) {
+    set_err(o, "range"); return -1;
+  }
+  orc_proj pr;
+  memset(&pr, 0, sizeof pr);
+  pr.src_first = src_first; pr.src_n = src_n; pr.tgt_first = tgt_first; pr.tgt_n = tgt_n;
+  pr.K = indegree; pr.port = port; pr.weight = weight;
+  if (orc_delay_table(delay_kind, da, db, o->dt, o->dmax, pr.dthr) != 0) { set_err(o, "delay"); return -1; }
+  o->proj = (orc_proj*)realloc(o->proj, (o->n_proj + 1) * sizeof(orc_proj));
+  o->proj[o->n_proj++] = pr;
+  return 0;
+}
+
+int orc_poisson(orc_net* o, uint32_t tgt_first, uint32_t tgt_n, double rate_hz, uint32_t n_inputs,
+                double weight, uint32_t port) {
+  if (o->built) { set_err(o, "poisson after build"); return -1; }
+  if ((uint64_t)tgt_first + tgt_n > o->N) { set_err(o, "range"); return -1; }
+  orc_pois q;
+  memset(&q, 0, sizeof q);
+  q.tgt_first = tgt_first; q.tgt_n = tgt_n; q.port = port; q.weight = weight;
+  /* n_inputs independent trains of rate_hz each, summed: Poisson(n nu dt) */
+  q.lambda = (double)n_inputs * rate_hz * o->dt * 1e-3;
+  if (orc_poisson_table(q.lambda, ORC_POISSON_KMAX, q.thr) != 0) { set_err(o, "poisson"); return -1; }
+  o->pois = (orc_pois*)realloc(o->pois, (o->n_pois + 1) * sizeof(orc_pois));
+  o->pois[o->n_pois++] = q;
+  return 0;
+}
+
+static void alloc_state(orc_net* o) {
+  if (o->V) return;
+  o->P = 1;
+  for (uint32_t k = 0; k < o->n_pops; ++k) if (o->pops[k].n_ports > o->P) o->P = o->pops[k].n_ports;
+  size_t N = o->N, P = o->P;
+  o->pop_of = (uint32_t*)malloc(N * sizeof(uint32_t));
+  for (uint32_t i = 0; i < o->N; ++i) o->pop_of[i] = pop_index(o, i);
+  o->V = (double*)calloc(N, sizeof(double));
+  o->Ie = (double*)calloc(N, sizeof(double));
+  o->w = (double*)calloc(N, sizeof(double));
+  o->g = (double*)calloc(N * P, sizeof(double));
+  o->I = (double*)calloc(N * P, sizeof(double));
+  o->h = (double*)malloc(N * sizeof(double));
+  for (size_t i = 0; i < N; ++i) o->h[i] = o->dt;
+  o->refr = (int32_t*)calloc(N, sizeof(int32_t));
+  o->Vf = (float*)calloc(N, sizeof(float));
+  o->If = (float*)calloc(N * P, sizeof(float));
+  o->Ief = (float*)calloc(N, sizeof(float));
+  o->acc = (int64_t*)calloc(N * P, sizeof(int64_t));
+  for (size_t i = 0; i < N; ++i) o->V[i] = o->pops[o->pop_of[i]].E_L; /* rest */
+  for (size_t i = 0; i < N; ++i) {
+    const orc_pop_params* pp = &o->pops[o->pop_of[i]];
+    if (pp->model != ORC_AEIF_COND_EXP) o->Vf[i] = (float)(o->V[i] - pp->E_L);
+  }
+}
+
+/* var: 0 V_m, 1 I_e, 2 w, 3 g[port], 4 I_syn[port], 5 refractory, 6 h */
+int orc_set_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port, const double* v) {
+  if (o->N == 0 || (uint64_t)first + n > o->N) { set_err(o, "range"); return -1; }
+  alloc_state(o);
+  if ((var == 3 || var == 4) && port >= o->P) { set_err(o, "port"); return -1; }
+  for (uint32_t j = 0; j < n; ++j) {
+    uint32_t i = first + j;
+    const orc_pop_params* pp = &o->pops[o->pop_of[i]];
+    switch (var) {
+      case 0:
+        o->V[i] = v[j];
+        /* LIF keeps y = V - E_L; the float copy is rounded once from double */
+        if (pp->model != ORC_AEIF_COND_EXP) o->Vf[i] = (float)(v[j] - pp->E_L);
+        break;
+      case 1: o->Ie[i] = v[j]; o->Ief[i] = (float)v[j]; break;
+      case 2: o->w[i] = v[j]; break;
+      case 3: o->g[(size_t)i * o->P + port] = v[j]; break;
+      case 4: o->I[(size_t)i * o->P + port] = v[j]; o->If[(size_t)i * o->P + port] = (float)v[j]; break;
+      case 5: o->refr[i] = (int32_t)v[j]; break;
+      case 6: o->h[i] = v[j]; break;
+      default: set_err(o, "var"); return -1;
+    }
+  }
+  return 0;
+}
+
+int orc_get_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port, double* v) {
+  if (o->N == 0 || (uint64_t)first + n > o->N) { set_err(o, "range"); return -1; }
+  alloc_state(o);
+  if ((var == 3 || var == 4) && port >= o->P) { set_err(o, "port"); return -1; }
+  int f32 = (o->mode == ORC_FP32SO);
+  for (uint32_t j = 0; j < n; ++j) {
+    uint32_t i = first + j;
+    const orc_pop_params* pp = &o->pops[o->pop_of[i]];
+    int lif = pp->model != ORC_AEIF_COND_EXP;
+    switch (var) {
+      case 0: v[j] = (lif && f32) ? (double)o->Vf[i] + pp->E_L : o->V[i]; break;
+      case 1: v[j] = o->Ie[i]; break;
+      case 2: v[j] = o->w[i]; break;
+      case 3: v[j] = o->g[(size_t)i * o->P + port]; break;
+      case 4: v[j] = (lif && f32) ? (double)o->If[(size_t)i * o->P + port] : o->I[(size_t)i * o->P + port]; break;
+      case 5: v[j] = (double)o->refr[i]; break;
+      case 6: v[j] = o->h[i]; break;
+      default: set_err(o, "var"); return -1;
+    }
+  }
+  return 0;
+}
+
+/* canonical order: source, delay, target, port, quantised weight */
+static int syn_cmp(const void* pa, const void* pb) {
+  const orc_syn* a = (const orc_syn*)pa;
+  const orc_syn* b = (const orc_syn*)pb;
+  if (a->src != b->src) return a->src < b->src ? -1 : 1;
+  if (a->d != b->d) return a->d < b->d ? -1 : 1;
+  if (a->tgt != b->tgt) return a->tgt < b->tgt ? -1 : 1;
+  if (a->port != b->port) return a->port < b->port ? -1 : 1;
+  if (a->wq != b->wq) return a->wq < b->wq ? -1 : 1;
+  return 0;
+}
+
+/* draw delay steps from a table */
+static uint32_t draw_delay(const uint64_t* thr, uint32_t dmax, uint32_t u) {
+  for (uint32_t k = 1; k <= dmax; ++k) if ((uint64_t)u < thr[k]) return k;
+  return dmax;
+}
+
+int orc_build(orc_net* o) {
+  if (o->built) { set_err(o, "built twice"); return -1; }
+  if (o->N == 0) { set_err(o, "empty"); return -1; }
+  alloc_state(o);
+  uint32_t P = o->P, D1 = o->dmax + 1;
+  /* Poisson drive per neuron (at most one) */
+  o->pois_of = (int32_t*)malloc(o->N * sizeof(int32_t));
+  for (uint32_t i = 0; i < o->N; ++i) o->pois_of[i] = -1;
+  for (uint32_t q = 0; q < o->n_pois; ++q) {
+    for (uint32_t j = 0; j < o->pois[q].tgt_n; ++j) {
+      uint32_t i = o->pois[q].tgt_first + j;
+      if (o->pois_of[i] >= 0) { set_err(o, "two poisson drives on one neuron"); return -1; }
+      o->pois_of[i] = (int32_t)q;
+    }
+  }
+  /* fixed-point shift per (target population, port): the largest S such that
+     every weight arriving on that port satisfies |w| 2^S < 2^30 */
+  o->shift = (int*)calloc((size_t)o->n_pops * P, sizeof(int));
+  double* maxw = (double*)calloc((size_t)o->n_pops * P, sizeof(double));
+  for (uint32_t p = 0; p < o->n_proj; ++p) {
+    const orc_proj* pr = &o->proj[p];
+    if (pr->K == 0 || pr->tgt_n == 0) continue;
+    for (uint32_t k = 0; k < o->n_pops; ++k) {
+      uint32_t lo = o->pop_first[k];
+      uint32_t hi = (k + 1 < o->n_pops) ? o->pop_first[k + 1] : o->N;
+      if (pr->tgt_first < hi && pr->tgt_first + pr->tgt_n > lo) {
+        if (pr->port >= o->pops[k].n_ports) { set_err(o, "port out of range"); free(maxw); return -1; }
+        double aw = fabs(pr->weight);
+        if (aw > maxw[k * P + pr->port]) maxw[k * P + pr->port] = aw;
+      }
+    }
+  }
+  for (uint32_t q = 0; q < o->n_pois; ++q) {
+    const orc_pois* pq = &o->pois[q];
+    for (uint32_t k = 0; k < o->n_pops; ++k) {
+      uint32_t lo = o->pop_first[k];
+      uint32_t hi = (k + 1 < o->n_pops) ? o->pop_first[k + 1] : o->N;
+      if (pq->tgt_n && pq->tgt_first < hi && pq->tgt_first + pq->tgt_n > lo) {
+        if (pq->port >= o->pops[k].n_ports) { set_err(o, "port out of range"); free(maxw); return -1; }
+        double aw = fabs(pq->weight);
+        if (aw > maxw[k * P + pq->port]) maxw[k * P + pq->port] = aw;
+      }
+    }
+  }
+  for (size_t k = 0; k < (size_t)o->n_pops * P; ++k) o->shift[k] = orc_fixed_point_shift(maxw[k]);
+  free(maxw);
+
+  /* fixed-indegree rule: for target t of projection p and k < K, one Philox
+     block per pair of synapses: counter (t, p<<40 | k>>1, CONN, 0), key
+     (seed, 0); synapse k uses words 2(k&1) (source) and 2(k&1)+1 (delay).
+     source = first + floor(u64 * n_src / 2^64); autapses and multapses kept. */
+  uint64_t total = 0;
+  for (uint32_t p = 0; p < o->n_proj; ++p) total += (uint64_t)o->proj[p].K * o->proj[p].tgt_n;
+  o->n_syn = total;
+  o->syn = (orc_syn*)malloc((total ? total : 1) * sizeof(orc_syn));
+  uint64_t pos = 0;
+  uint64_t key[2] = {o->seed, 0};
+  for (uint32_t p = 0; p < o->n_proj; ++p) {
+    const orc_proj* pr = &o->proj[p];
+    for (uint32_t j = 0; j < pr->tgt_n; ++j) {
+      uint32_t t = pr->tgt_first + j;
+      uint32_t tp = o->pop_of[t];
+      int S = o->shift[tp * P + pr->port];
+      int64_t wq = llrint(ldexp(pr->weight, S));
+      uint64_t blk[4] = {0, 0, 0, 0};
+      for (uint32_t k = 0; k < pr->K; ++k) {
+        if ((k & 1u) == 0) {
+          uint64_t ctr[4] = {t, ((uint64_t)p << 40) | (uint64_t)(k >> 1), ORC_TAG_CONN, 0};
+          orc_philox4x64_10(ctr, key, blk);
+        }
+        uint64_t us = blk[2 * (k & 1u)];
+        uint64_t ud = blk[2 * (k & 1u) + 1];
+        uint32_t s = pr->src_first + (uint32_t)(((unsigned __int128)us * pr->src_n) >> 64);
+        orc_syn sy;
+        sy.src = s; sy.tgt = t; sy.port = (uint8_t)pr->port; sy.wq = wq;
+        sy.d = (uint8_t)draw_delay(pr->dthr, o->dmax, (uint32_t)(ud >> 32));
+        o->syn[pos++] = sy;
+      }
+    }
+  }
+  /* canonical order (a library sort), then offsets of each (source, delay) run */
+  qsort(o->syn, (size_t)o->n_syn, sizeof(orc_syn), syn_cmp);
+  o->off = (uint64_t*)calloc((size_t)o->N * D1 + 1, sizeof(uint64_t));
+  for (uint64_t e = 0; e < o->n_syn; ++e) o->off[(size_t)o->syn[e].src * D1 + o->syn[e].d + 1]++;
+  for (size_t k = 1; k <= (size_t)o->N * D1; ++k) o->off[k] += o->off[k - 1];
+  /* spike record */
+  o->cap_spk = 1024;
+  o->spk_step = (uint64_t*)malloc(o->cap_spk * sizeof(uint64_t));
+  o->spk_gid = (uint32_t*)malloc(o->cap_spk * sizeof(uint32_t));
+  o->spk_mult = (uint32_t*)malloc(o->cap_spk * sizeof(uint32_t));
+  o->cap_at = 1024;
+  o->spk_at = (uint64_t*)calloc(o->cap_at, sizeof(uint64_t));
+  o->built = 1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* LIF exact integration (Sec. 2.1 and the LIF / exponential-PSC equations   */
+/* of Sec. 2.3).  With y = V - E_L the linear system                          */
+/*   dy/dt = -y/tau_m + (I + I_e)/C,  dI/dt = -I/tau_s                       */
+/* is propagated exactly over dt:                                             */
+/*   P22 = e^{-dt/tau_m},  P11 = e^{-dt/tau_s},  P20 = tau_m/C (1 - P22),     */
+/*   P21 = tau_m tau_s / (C (tau_s - tau_m)) (e^{-dt/tau_s} - e^{-dt/tau_m})  */
+/*   (limit dt/C e^{-dt/tau} when tau_s = tau_m).                             */
+/* A delta PSC adds its weight (mV) to y at the step it arrives.              */
+/* ------------------------------------------------------------------------ */
+void orc_lif_propagators(const orc_pop_params* pp, double dt, double* out) {
+  double P22 = exp(-dt / pp->tau_m);
+  double P20 = pp->tau_m / pp->C_m * (1.0 - P22);
+  out[0] = P22; out[1] = P20;
+  for (uint32_t p = 0; p < pp->n_ports; ++p) {
+    double ts = pp->tau_syn[p];
+    double P11 = (ts > 0) ? exp(-dt / ts) : 0.0;
+    double P21;
+    if (!(ts > 0)) P21 = 0.0;
+    else if (ts == pp->tau_m) P21 = dt / pp->C_m * exp(-dt / pp->tau_m);
+    else P21 = pp->tau_m * ts / (pp->C_m * (ts - pp->tau_m)) * (exp(-dt / ts) - exp(-dt / pp->tau_m));
+    out[2 + p] = P11;
+    out[2 + pp->n_ports + p] = P21;
+  }
+}
+
+static int32_t refr_steps(const orc_pop_params* pp, double dt) {
+  return (int32_t)floor(pp->t_ref / dt + 0.5);
+}
+
+/* Refractoriness: during the n_ref steps after a spike the membrane is held
+   at V_reset and (delta PSC) arriving input is discarded; the step counter is
+   decremented at each of those steps.  Threshold test V >= V_th. */
+int orc_lif_delta_step64(const orc_pop_params* pp, double dt, double* y, int32_t* refr, double I_e, double x) {
+  double pr[2 + 2 * ORC_MAX_PORTS];
+  orc_lif_propagators(pp, dt, pr);
+  double theta = pp->V_th - pp->E_L, yr = pp->V_reset - pp->E_L;
+  if (*refr > 0) {
+    *refr -= 1;
+  } else {
+    double t1 = pr[0] * (*y);
+    double t2 = pr[1] * I_e;
+    *y = (t1 + t2) + x;
+  }
+  if (*refr == 0 && *y >= theta) { *y = yr; *refr = refr_steps(pp, dt); return 1; }
+  return 0;
+}
+
+int orc_lif_delta_step32(const orc_pop_params* pp, double dt, float* y, int32_t* refr, float I_e, float x) {
+  double pr[2 + 2 * ORC_MAX_PORTS];
+  orc_lif_propagators(pp, dt, pr);
+  float P22 = (float)pr[0], P20 = (float)pr[1];
+  float theta = (float)(pp->V_th - pp->E_L), yr = (float)(pp->V_reset - pp->E_L);
+  if (*refr > 0) {
+    *refr -= 1;
+  } else {
+    float t1 = P22 * (*y);
+    float t2 = P20 * I_e;
+    float t3 = t1 + t2;
+    *y = t3 + x;
+  }
+  if (*refr == 0 && *y >= theta) { *y = yr; *refr = refr_steps(pp, dt); return 1; }
+  return 0;
+}
+
+int orc_lif_exp_step64(const orc_pop_params* pp, double dt, double* y, double* I, int32_t* refr, double I_e,
+                       const double* x) {
+  double pr[2 + 2 * ORC_MAX_PORTS];
+  orc_lif_propagators(pp, dt, pr);
+  uint32_t P = pp->n_ports;
+  double theta = pp->V_th - pp->E_L, yr = pp->V_reset - pp->E_L;
+  if (*refr == 0) {
+    double v = pr[0] * (*y);
+    for (uint32_t p = 0; p < P; ++p) v = v + pr[2 + P + p] * I[p];
+    v = v + pr[1] * I_e;
+    *y = v;
+  } else {
+    *refr -= 1;
+  }
+  for (uint32_t p = 0; p < P; ++p) I[p] = pr[2 + p] * I[p] + x[p];
+  if (*refr == 0 && *y >= theta) { *y = yr; *refr = refr_steps(pp, dt); return 1; }
+  return 0;
+}
+
+int orc_lif_exp_step32(const orc_pop_params* pp, double dt, float* y, float* I, int32_t* refr, float I_e,
+                       const float* x) {
+  double pr[2 + 2 * ORC_MAX_PORTS];
+  orc_lif_propagators(pp, dt, pr);
+  uint32_t P = pp->n_ports;
+  float theta = (float)(pp->V_th - pp->E_L), yr = (float)(pp->V_reset - pp->E_L);
+  if (*refr == 0) {
+    float v = (float)pr[0] * (*y);
+    for (uint32_t p = 0; p < P; ++p) {
+      float t = (float)pr[2 + P + p] * I[p];
+      v = v + t;
+    }
+    float te = (float)pr[1] * I_e;
+    v = v + te;
+    *y = v;
+  } else {
+    *refr -= 1;
+  }
+  for (uint32_t p = 0; p < P; ++p) {
+    float t = (float)pr[2 + p] * I[p];
+    I[p] = t + x[p];
+  }
+  if (*refr == 0 && *y >= theta) { *y = yr; *refr = refr_steps(pp, dt); return 1; }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* AdEx with conductance synapses (Sec. 2.4, Table 2):                        */
+/*   C dV/dt = -g_L (V - E_L) + g_L Delta_T exp((V - V_T)/Delta_T)            */
+/*             - sum_p g_p (V - E_rev,p) - w + I_e                            */
+/*   tau_w dw/dt = a (V - E_L) - w                                            */
+/*   dg_p/dt = -g_p / tau_syn,p      (exponential conductance per port)       */
+/* The synaptic current is taken with the sign that makes an excitatory       */
+/* conductance depolarise.  The exponential uses min(V, V_peak).  At a reset  */
+/* (V >= V_peak after an accepted substep) V -> V_r and w -> w + b.           */
+/* ------------------------------------------------------------------------ */
+void orc_adex_rhs(const orc_pop_params* pp, double I_e, const double* y, double* dy) {
+  uint32_t P = pp->n_ports;
+  double V = y[0], w = y[1];
+  double Vc = V < pp->V_peak ? V : pp->V_peak;
+  double isyn = 0.0;
+  for (uint32_t p = 0; p < P; ++p) isyn += y[2 + p] * (V - pp->E_rev[p]);
+  double ex = pp->adex_no_exp ? 0.0 : pp->g_L * pp->Delta_T * exp((Vc - pp->V_T) / pp->Delta_T);
+  dy[0] = (-pp->g_L * (V - pp->E_L) + ex - isyn - w + I_e) / pp->C_m;
+  dy[1] = (pp->a * (V - pp->E_L) - w) / pp->tau_w;
+  for (uint32_t p = 0; p < P; ++p) dy[2 + p] = -y[2 + p] / pp->tau_syn[p];
+}
+
+/* Cash-Karp embedded 5(4) Runge-Kutta pair (Cash & Karp 1990), the adaptive
+   fifth-order method of Press et al. 1992. */
+static const double CK_C[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
+static const double CK_A[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
+static const double CK_B5[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
+static const double CK_B4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0,
+                                277.0 / 14336.0, 1.0 / 4.0};
+
+void orc_cash_karp_tableau(double* c, double* a, double* b5, double* b4) {
+  for (int i = 0; i < 6; ++i) {
+    c[i] = CK_C[i]; b5[i] = CK_B5[i]; b4[i] = CK_B4[i];
+    for (int j = 0; j < 6; ++j) a[i * 6 + j] = (j < 5) ? CK_A[i][j] : 0.0;
+  }
+}
+
+/* Step-size control of Press et al. (rkqs): error measured relative to
+   |y| + |h dy/dt|, scaled by eps; a failed step shrinks h by 0.9 e^{-1/4}
+   (at most 10x), an accepted one grows it by 0.9 e^{-1/5} (at most 5x). */
+#define RK_SAFETY 0.9
+#define RK_PGROW (-0.2)
+#define RK_PSHRNK (-0.25)
+#define RK_TINY 1e-30
+#define RK_MAXIT 1000000
+
+int orc_adex_step(const orc_pop_params* pp, double dt, double* y, double* hcar, double I_e, const double* x,
+                  uint64_t* nacc, uint64_t* nrej) {
+  uint32_t P = pp->n_ports, NV = 2 + P;
+  double errcon = pow(5.0 / RK_SAFETY, 1.0 / RK_PGROW);
+  double eps = pp->rk_eps > 0 ? pp->rk_eps : 1e-6;
+  double hmin = pp->rk_hmin > 0 ? pp->rk_hmin : 1e-8;
+  /* conductance jump by the weight delivered at this step */
+  for (uint32_t p = 0; p < P; ++p) y[2 + p] += x[p];
+  double k[6][2 + ORC_MAX_PORTS], ytmp[2 + ORC_MAX_PORTS], y5[2 + ORC_MAX_PORTS], err[2 + ORC_MAX_PORTS];
+  double t = 0.0;
+  double h = *hcar;
+  if (!(h > 0) || h > dt) h = dt;
+  int mult = 0;
+  long it = 0;
+  while (t < dt) {
+    if (++it > RK_MAXIT) break;
+    int last = 0;
+    if (h >= dt - t) { h = dt - t; last = 1; }
+    orc_adex_rhs(pp, I_e, y, k[0]);
+    for (int s = 1; s < 6; ++s) {
+      for (uint32_t i = 0; i < NV; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < s; ++j) acc += CK_A[s][j] * k[j][i];
+        ytmp[i] = y[i] + h * acc;
+      }
+      orc_adex_rhs(pp, I_e, ytmp, k[s]);
+    }
+    double errmax = 0.0;
+    for (uint32_t i = 0; i < NV; ++i) {
+      double s5 = 0.0, se = 0.0;
+      for (int j = 0; j < 6; ++j) { s5 += CK_B5[j] * k[j][i]; se += (CK_B5[j] - CK_B4[j]) * k[j][i]; }
+      y5[i] = y[i] + h * s5;
+      err[i] = h * se;
+      double scale = fabs(y[i]) + fabs(h * k[0][i]) + RK_TINY;
+      double r = fabs(err[i]) / scale;
+      if (r > errmax) errmax = r;
+    }
+    errmax /= eps;
+    if (errmax > 1.0 && h > hmin) {
+      double htemp = RK_SAFETY * h * pow(errmax, RK_PSHRNK);
+      h = htemp > 0.1 * h ? htemp : 0.1 * h;
+      if (h < hmin) h = hmin;
+      (*nrej)++;
+      continue;
+    }
+    (*nacc)++;
+    t = last ? dt : t + h;
+    for (uint32_t i = 0; i < NV; ++i) y[i] = y5[i];
+    double hnext = (errmax > errcon) ? RK_SAFETY * h * pow(errmax, RK_PGROW) : 5.0 * h;
+    if (y[0] >= pp->V_peak) { y[0] = pp->V_r; y[1] += pp->b; mult++; }
+    h = hnext;
+  }
+  if (h > dt) h = dt;
+  *hcar = h;
+  return mult;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Simulation loop.  Step n: every neuron reads the integer input delivered   */
+/* for step n (plus its Poisson count for step n), converts it once with its  */
+/* fixed-point exponent, updates, and records a spike (n, gid, multiplicity). */
+/* Then the input for step n+1 is formed by the plain delivery definition:    */
+/* for d = 1..Dmax, every spike (s, m) of step n+1-d adds m w_q of each       */
+/* synapse of s with delay d to its (target, port).                           */
+/* ------------------------------------------------------------------------ */
+static void record_spike(orc_net* o, uint64_t n, uint32_t gid, uint32_t m) {
+  if (o->n_spk == o->cap_spk) {
+    o->cap_spk *= 2;
+    o->spk_step = (uint64_t*)realloc(o->spk_step, o->cap_spk * sizeof(uint64_t));
+    o->spk_gid = (uint32_t*)realloc(o->spk_gid, o->cap_spk * sizeof(uint32_t));
+    o->spk_mult = (uint32_t*)realloc(o->spk_mult, o->cap_spk * sizeof(uint32_t));
+  }
+  o->spk_step[o->n_spk] = n; o->spk_gid[o->n_spk] = gid; o->spk_mult[o->n_spk] = m;
+  o->n_spk++;
+}
+
+static uint32_t poisson_draw(const orc_net* o, const orc_pois* q, uint32_t gid, uint64_t n) {
+  uint64_t ctr[4] = {gid, n, ORC_TAG_POISSON, 0};
+  uint64_t key[2] = {o->seed, 0};
+  uint64_t blk[4];
+  orc_philox4x64_10(ctr, key, blk);
+  uint32_t u = (uint32_t)(blk[0] >> 32);
+  for (uint32_t k = 0; k < ORC_POISSON_KMAX; ++k) if ((uint64_t)u < q->thr[k]) return k;
+  return ORC_POISSON_KMAX - 1;
+}
+
+int orc_poisson_count(const orc_net* o, uint32_t gid, uint64_t step, uint32_t* k) {
+  if (!o->built || gid >= o->N || o->pois_of[gid] < 0) return -1;
+  *k = poisson_draw(o, &o->pois[o->pois_of[gid]], gid, step);
+  return 0;
+}
+
+int orc_record_input(orc_net* o, int64_t* buf, uint64_t max_steps) {
+  o->rec = buf; o->rec_max = max_steps;
+  return 0;
+}
+
+static void deliver_into(const orc_net* o, uint64_t target_step, uint64_t n_spk, const uint64_t* st,
+                         const uint32_t* gid, const uint32_t* mult, int64_t* out) {
+  uint32_t D1 = o->dmax + 1, P = o->P;
+  for (uint32_t d = 1; d <= o->dmax; ++d) {
+    if (target_step < d) break;
+    uint64_t nf = target_step - d;
+    for (uint64_t i = 0; i < n_spk; ++i) {
+      if (st[i] != nf) continue;
+      uint32_t s = gid[i];
+      int64_t m = (int64_t)mult[i];
+      uint64_t b = o->off[(size_t)s * D1 + d], e = o->off[(size_t)s * D1 + d + 1];
+      for (uint64_t q = b; q < e; ++q) {
+        const orc_syn* sy = &o->syn[q];
+        out[(size_t)sy->tgt * P + sy->port] += m * sy->wq;
+      }
+    }
+  }
+}
+
+int orc_replay_input(const orc_net* o, uint64_t n_spk, const uint64_t* step, const uint32_t* gid,
+                     const uint32_t* mult, uint64_t target_step, int64_t* out) {
+  if (!o->built) return -1;
+  memset(out, 0, (size_t)o->N * o->P * sizeof(int64_t));
+  deliver_into(o, target_step, n_spk, step, gid, mult, out);
+  return 0;
+}
+
+int orc_simulate(orc_net* o, uint64_t steps) {
+  if (!o->built) { set_err(o, "simulate before build"); return -1; }
+  uint32_t P = o->P, D1 = o->dmax + 1;
+  double xd[ORC_MAX_PORTS]; float xf[ORC_MAX_PORTS];
+  int f32 = (o->mode == ORC_FP32SO);
+  for (uint64_t it = 0; it < steps; ++it) {
+    uint64_t n = o->step;
+    if (o->rec && n < o->rec_max) memcpy(o->rec + (size_t)n * o->N * P, o->acc, (size_t)o->N * P * sizeof(int64_t));
+    if (n + 1 >= o->cap_at) {
+      o->cap_at *= 2;
+      o->spk_at = (uint64_t*)realloc(o->spk_at, o->cap_at * sizeof(uint64_t));
+    }
+    o->spk_at[n] = o->n_spk;
+    /* update of step n */
+    for (uint32_t i = 0; i < o->N; ++i) {
+      uint32_t pk = o->pop_of[i];
+      const orc_pop_params* pp = &o->pops[pk];
+      int64_t xin[ORC_MAX_PORTS];
+      for (uint32_t p = 0; p < P; ++p) { xin[p] = o->acc[(size_t)i * P + p]; o->acc[(size_t)i * P + p] = 0; }
+      if (o->pois_of[i] >= 0) {
+        const orc_pois* q = &o->pois[o->pois_of[i]];
+        int S = o->shift[pk * P + q->port];
+        int64_t wq = llrint(ldexp(q->weight, S));
+        xin[q->port] += (int64_t)poisson_draw(o, q, i, n) * wq;
+      }
+      for (uint32_t p = 0; p < pp->n_ports; ++p) {
+        int S = o->shift[pk * P + p];
+        xd[p] = ldexp((double)xin[p], -S);
+        xf[p] = ldexpf((float)xin[p], -S);
+      }
+      int m = 0;
+      if (pp->model == ORC_LIF_DELTA) {
+        if (f32) m = orc_lif_delta_step32(pp, o->dt, &o->Vf[i], &o->refr[i], o->Ief[i], xf[0]);
+        else {
+          double y = o->V[i] - pp->E_L;
+          m = orc_lif_delta_step64(pp, o->dt, &y, &o->refr[i], o->Ie[i], xd[0]);
+          o->V[i] = y + pp->E_L;
+        }
+      } else if (pp->model == ORC_LIF_EXP) {
+        if (f32) m = orc_lif_exp_step32(pp, o->dt, &o->Vf[i], &o->If[(size_t)i * P], &o->refr[i], o->Ief[i], xf);
+        else {
+          double y = o->V[i] - pp->E_L;
+          m = orc_lif_exp_step64(pp, o->dt, &y, &o->I[(size_t)i * P], &o->refr[i], o->Ie[i], xd);
+          o->V[i] = y + pp->E_L;
+        }
+      } else {
+        double yv[2 + ORC_MAX_PORTS];
+        yv[0] = o->V[i]; yv[1] = o->w[i];
+        for (uint32_t p = 0; p < pp->n_ports; ++p) yv[2 + p] = o->g[(size_t)i * P + p];
+        m = orc_adex_step(pp, o->dt, yv, &o->h[i], o->Ie[i], xd, &o->rk_acc, &o->rk_rej);
+        o->V[i] = yv[0]; o->w[i] = yv[1];
+        for (uint32_t p = 0; p < pp->n_ports; ++p) o->g[(size_t)i * P + p] = yv[2 + p];
+      }
+      if (m > 0) record_spike(o, n, i, (uint32_t)m);
+    }
+    o->spk_at[n + 1] = o->n_spk;
+    /* delivery: input of step n+1 */
+    for (uint32_t d = 1; d <= o->dmax && d <= n + 1; ++d) {
+      uint64_t nf = n + 1 - d;
+      for (uint64_t q = o->spk_at[nf]; q < o->spk_at[nf + 1]; ++q) {
+        uint32_t s = o->spk_gid[q];
+        int64_t m = (int64_t)o->spk_mult[q];
+        uint64_t b = o->off[(size_t)s * D1 + d], e = o->off[(size_t)s * D1 + d + 1];
+        for (uint64_t r = b; r < e; ++r) {
+          const orc_syn* sy = &o->syn[r];
+          o->acc[(size_t)sy->tgt * P + sy->port] += m * sy->wq;
+        }
+      }
+    }
+    o->step = n + 1;
+  }
+  return 0;
+}
+
+uint64_t orc_current_step(const orc_net* o) { return o->step; }
+uint64_t orc_n_spikes(const orc_net* o) { return o->n_spk; }
+
+void orc_get_spikes(const orc_net* o, uint64_t* step, uint32_t* gid, uint32_t* mult) {
+  /* spikes are appended in (step, gid) order by construction */
+  for (uint64_t i = 0; i < o->n_spk; ++i) { step[i] = o->spk_step[i]; gid[i] = o->spk_gid[i]; mult[i] = o->spk_mult[i]; }
+}
+
+uint64_t orc_n_synapses(const orc_net* o) { return o->built ? o->n_syn : 0; }
+
+void orc_get_synapses(const orc_net* o, uint32_t* src, uint32_t* delay, uint32_t* tgt, uint32_t* port, int64_t* wq) {
+  for (uint64_t e = 0; e < o->n_syn; ++e) {
+    src[e] = o->syn[e].src; delay[e] = o->syn[e].d; tgt[e] = o->syn[e].tgt;
+    port[e] = o->syn[e].port; wq[e] = o->syn[e].wq;
+  }
+}
+
+int orc_shift_of(const orc_net* o, uint32_t gid, uint32_t port) {
+  if (!o->built || gid >= o->N || port >= o->P) return -1000;
+  return o->shift[o->pop_of[gid] * o->P + port];
+}

@@ -1,0 +1,127 @@
+/*
+ * snn_oracle.h -- plain, slow CPU oracle for the spiking-network hot path of
+ * Golosio et al., "Fast simulations of highly-connected spiking cortical
+ * models using GPUs" (arXiv 2007.14236).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this code; only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the GPU library: it has its own counter-based generator, its
+ * own distribution tables, its own connectivity builder, neuron updates and
+ * delivery loop, each written from the paper's definitions.
+ *
+ * Modes:
+ *   ORC_FP64  : every floating-point quantity in double (physics reference).
+ *   ORC_FP32SO: LIF updates in float with a fixed, FMA-free operation order
+ *               (used for bit-exact raster comparison).  AdEx always runs in
+ *               double.
+ *
+ * Units: ms, mV, pA, nS, pF, Hz.
+ */
+#ifndef SNN_ORACLE_H
+#define SNN_ORACLE_H
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_FP64 = 0, ORC_FP32SO = 1 };
+enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2 };
+enum { ORC_DELAY_CONST = 0, ORC_DELAY_UNIFORM = 1, ORC_DELAY_NORMAL_CLIPPED = 2 };
+enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2 };
+enum { ORC_MAX_PORTS = 4, ORC_POISSON_KMAX = 128 };
+
+/* Neuron-model parameters of one population (double, NEST units). */
+typedef struct {
+  int32_t model;        /* ORC_LIF_DELTA, ORC_LIF_EXP, ORC_AEIF_COND_EXP */
+  uint32_t n_ports;     /* receptor ports (1..ORC_MAX_PORTS)              */
+  double tau_m, C_m, E_L, V_th, V_reset, t_ref;               /* LIF      */
+  double g_L, Delta_T, V_T, tau_w, a, b, V_peak, V_r;         /* AdEx     */
+  double tau_syn[ORC_MAX_PORTS];                              /* ms       */
+  double E_rev[ORC_MAX_PORTS];                                /* mV (AdEx)*/
+  double rk_eps;        /* relative tolerance of the adaptive RK45 (AdEx) */
+  double rk_hmin;       /* smallest substep; accepted regardless (ms)     */
+  int32_t adex_no_exp;  /* test switch: drop the exponential term         */
+} orc_pop_params;
+
+typedef struct orc_net orc_net;
+
+/* ---- counter-based generator: Philox4x64-10 (Salmon et al., SC'11) ---- */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* ---- discretised distribution tables (thresholds on a 32-bit uniform) ---- */
+/* thr[k] for k = 1..dmax; draw D = min{k : u32 < thr[k]}; thr[dmax] = 2^32. */
+int orc_delay_table(int kind, double a, double b, double dt, uint32_t dmax, uint64_t* thr);
+/* thr[k] for k = 0..kmax-1; draw k = min{k : u32 < thr[k]}; thr[kmax-1] = 2^32. */
+int orc_poisson_table(double lambda, uint32_t kmax, uint64_t* thr);
+/* fixed-point exponent: largest S with max_abs_w * 2^S < 2^30 (0 if max_abs_w == 0) */
+int orc_fixed_point_shift(double max_abs_w);
+
+/* ---- network ---- */
+orc_net* orc_create(double dt_ms, uint64_t seed, uint32_t max_delay_steps, int mode);
+void     orc_destroy(orc_net*);
+/* returns first gid of the new population, or -1 */
+int64_t  orc_population(orc_net*, uint32_t n, const orc_pop_params* p);
+int      orc_connect_fixed_indegree(orc_net*, uint32_t src_first, uint32_t src_n,
+                                    uint32_t tgt_first, uint32_t tgt_n, uint32_t indegree,
+                                    double weight, int delay_kind, double da, double db,
+                                    uint32_t port);
+int      orc_poisson(orc_net*, uint32_t tgt_first, uint32_t tgt_n, double rate_hz,
+                     uint32_t n_inputs, double weight, uint32_t port);
+/* state variables (per neuron).  var: 0 V_m (mV), 1 I_e (pA), 2 w (pA),
+   3 g[port] (nS), 4 I_syn[port] (pA), 5 refractory counter, 6 h (ms) */
+int      orc_set_state(orc_net*, uint32_t first, uint32_t n, int var, uint32_t port, const double* v);
+int      orc_get_state(orc_net*, uint32_t first, uint32_t n, int var, uint32_t port, double* v);
+int      orc_build(orc_net*);
+int      orc_simulate(orc_net*, uint64_t steps);
+uint64_t orc_current_step(const orc_net*);
+
+/* spikes recorded so far, sorted by (step, gid) */
+uint64_t orc_n_spikes(const orc_net*);
+void     orc_get_spikes(const orc_net*, uint64_t* step, uint32_t* gid, uint32_t* mult);
+
+/* synapses in canonical order (source, delay steps, target, port, w_q) */
+uint64_t orc_n_synapses(const orc_net*);
+void     orc_get_synapses(const orc_net*, uint32_t* src, uint32_t* delay, uint32_t* tgt,
+                          uint32_t* port, int64_t* wq);
+/* fixed-point exponent used for (neuron gid, port) */
+int      orc_shift_of(const orc_net*, uint32_t gid, uint32_t port);
+/* quantised Poisson weight and lambda table of neuron gid (-1 if none) */
+int      orc_poisson_count(const orc_net*, uint32_t gid, uint64_t step, uint32_t* k);
+
+/* record the integer input sum (network delivery only, Poisson excluded) that
+   every neuron reads at every simulated step: buffer of steps*N*P int64 */
+int      orc_record_input(orc_net*, int64_t* buf, uint64_t max_steps);
+
+/* Delivery from an external spike history (plain definition): the integer
+   input each (target, port) receives at step target_step from the spikes
+   (step[i], gid[i], mult[i]).  out has N*P entries. */
+int      orc_replay_input(const orc_net*, uint64_t n_spk, const uint64_t* step, const uint32_t* gid,
+                          const uint32_t* mult, uint64_t target_step, int64_t* out);
+
+/* ---- single-neuron update steps, exposed for the pins ---- */
+/* LIF: y = V - E_L.  x[] = converted input per port.  Returns 1 on spike. */
+int orc_lif_delta_step64(const orc_pop_params*, double dt, double* y, int32_t* refr, double I_e, double x);
+int orc_lif_delta_step32(const orc_pop_params*, double dt, float* y, int32_t* refr, float I_e, float x);
+int orc_lif_exp_step64(const orc_pop_params*, double dt, double* y, double* I, int32_t* refr, double I_e, const double* x);
+int orc_lif_exp_step32(const orc_pop_params*, double dt, float* y, float* I, int32_t* refr, float I_e, const float* x);
+/* LIF propagators in double: out = {P22, P20, P11[0..P-1], P21[0..P-1]} */
+void orc_lif_propagators(const orc_pop_params*, double dt, double* out);
+/* AdEx: y = {V, w, g_0..g_{P-1}}, h carried step size.  Adds x to g at step start,
+   integrates one dt with Cash-Karp RK45.  Returns the number of resets (multiplicity).
+   acc/rej count accepted/rejected substeps. */
+int orc_adex_step(const orc_pop_params*, double dt, double* y, double* h, double I_e,
+                  const double* x, uint64_t* acc, uint64_t* rej);
+/* Cash-Karp tableau as used: c[6], a[6*6] (row-major, strictly lower), b5[6], b4[6] */
+void orc_cash_karp_tableau(double* c, double* a, double* b5, double* b4);
+/* AdEx right-hand side (for pins): dy = f(y) */
+void orc_adex_rhs(const orc_pop_params*, double I_e, const double* y, double* dy);
+
+const char* orc_last_error(const orc_net*);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
