@@ -658,6 +658,7 @@ int orc_adex_step(const orc_pop_params* pp, double dt, double* y, double* hcar, 
     t = last ? dt : t + h;
     for (uint32_t i = 0; i < NV; ++i) y[i] = y5[i];
     double hnext = (errmax > errcon) ? RK_SAFETY * h * pow(errmax, RK_PGROW) : 5.0 * h;
+    if (hnext < hmin) hnext = hmin; /* the floor also bounds the proposed step */
     if (y[0] >= pp->V_peak) { y[0] = pp->V_r; y[1] += pp->b; mult++; }
     h = hnext;
   }
