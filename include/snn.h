@@ -1,0 +1,214 @@
+/*
+ * snn.h -- C ABI of the MI355X (gfx950) spiking-network engine.
+ *
+ * The engine implements the per-time-step hot path of the GPU simulator of
+ * Golosio et al., "Fast simulations of highly-connected spiking cortical
+ * models using GPUs" (arXiv 2007.14236):
+ *   - spike delivery (Sec. 2.2 and Fig. 1): every spike is buffered per source
+ *     neuron; each step the (source, connection-group) pairs whose delay has
+ *     just elapsed are selected, the outgoing synapses of those groups are
+ *     scanned in one flat parallel pass, and their weights are accumulated into
+ *     the receptor inputs of the targets;
+ *   - the neuron update beside it (Sec. 2.1): LIF exact integration (LIF and
+ *     exponential-PSC equations of Sec. 2.3) and multisynapse AdEx with
+ *     conductance synapses (Sec. 2.4, Table 2) integrated by an adaptive
+ *     fifth-order Runge-Kutta method.
+ * The calls follow the paper's statement of the problem (Sec. 2.1 and its
+ * code sample): create populations of a neuron model with n receptor ports,
+ * set parameters, connect by rule with weight, delay and receptor, attach
+ * Poisson generators, simulate T ms at a time step dt, read back the spike
+ * raster and the state.
+ *
+ * Conventions
+ *   - Units: ms, mV, pA, nS, pF, Hz.
+ *   - Neurons are numbered by global id (gid) in creation order.
+ *   - Every call returns SNN_OK (0) or a negative snn_status; the message of
+ *     the last failure of a handle is returned by snn_last_error().  A failed
+ *     call leaves the handle usable.  No C++ exception crosses this ABI.
+ *   - Pointers named out / v / host arrays are caller-owned HOST memory.  All
+ *     device memory is owned by the library (allocated through the optional
+ *     snn_device callbacks, else hipMalloc) and released by snn_destroy_net.
+ *   - Calls on one handle must not overlap (not thread-safe per handle).
+ *   - Phases: populations, parameters, connections and Poisson drives are
+ *     defined before snn_build(); snn_simulate() and the readback calls come
+ *     after it.  A call in the wrong phase returns SNN_E_STATE.
+ */
+#ifndef SNN_H
+#define SNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t snn_status;
+#define SNN_OK 0
+#define SNN_E_INVALID (-1)     /* bad argument                                  */
+#define SNN_E_NOMEM (-2)       /* device or host allocation failed              */
+#define SNN_E_STATE (-3)       /* call not allowed in the current phase         */
+#define SNN_E_OVERFLOW (-4)    /* a device-side capacity or range was exceeded  */
+#define SNN_E_DEVICE (-5)      /* HIP runtime error                             */
+#define SNN_E_UNSUPPORTED (-7) /* valid request outside what is implemented     */
+
+typedef struct snn_net snn_net;
+
+/* Optional device-memory provider.  alloc returns a device pointer (or NULL on
+   failure) of at least `bytes` bytes, 256-byte aligned; free releases it.
+   `stream` is a hipStream_t the caller orders its own work on (may be NULL):
+   the library runs its work on a private stream and orders it after the
+   caller's stream at the start of every call and before it at the end. */
+typedef struct snn_device {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+  void* stream;
+} snn_device;
+
+typedef struct snn_config {
+  double dt_ms;             /* simulation resolution (ms), > 0                  */
+  uint64_t seed;            /* key of the counter-based generator               */
+  uint32_t max_delay_steps; /* Dmax, 1..63; longer delays fold into Dmax        */
+  uint32_t flags;           /* SNN_F_* below                                    */
+} snn_config;
+#define SNN_F_NO_SPIKE_RECORD 1u /* do not keep the spike raster on the host */
+
+/* neuron models (Sec. 2.1, 2.3, 2.4) */
+#define SNN_LIF_PSC_DELTA 0  /* LIF, delta PSCs: weights in mV, one port      */
+#define SNN_LIF_PSC_EXP 1    /* LIF, exponential PSCs: weights in pA          */
+#define SNN_AEIF_COND_EXP 2  /* AdEx, exponential conductances: weights in nS */
+
+/* model parameters (snn_set_param); all apply to whole populations */
+#define SNN_P_TAU_M 0    /* LIF membrane time constant (ms)                   */
+#define SNN_P_C_M 1      /* membrane capacitance (pF)                         */
+#define SNN_P_E_L 2      /* leak reversal / resting potential (mV)            */
+#define SNN_P_V_TH 3     /* LIF threshold (mV)                                */
+#define SNN_P_V_RESET 4  /* LIF reset potential (mV)                          */
+#define SNN_P_T_REF 5    /* refractory time (ms); AdEx supports only 0        */
+#define SNN_P_G_L 6      /* AdEx leak conductance (nS)                        */
+#define SNN_P_DELTA_T 7  /* AdEx slope factor (mV)                            */
+#define SNN_P_V_T 8      /* AdEx spike-initiation threshold (mV)              */
+#define SNN_P_TAU_W 9    /* AdEx adaptation time constant (ms)                */
+#define SNN_P_A 10       /* AdEx subthreshold adaptation (nS)                 */
+#define SNN_P_B 11       /* AdEx spike-triggered adaptation (pA)              */
+#define SNN_P_V_PEAK 12  /* AdEx spike detection / reset trigger (mV)         */
+#define SNN_P_V_R 13     /* AdEx reset potential (mV)                         */
+#define SNN_P_RK_EPS 14  /* AdEx RK45 relative tolerance                      */
+#define SNN_P_RK_HMIN 15 /* AdEx smallest RK45 substep (ms)                   */
+/* port parameters (snn_set_port_param) */
+#define SNN_PP_TAU_SYN 0 /* synaptic time constant (ms)                       */
+#define SNN_PP_E_REV 1   /* AdEx reversal potential (mV)                      */
+
+/* state variables (snn_set_state / snn_get_state), per neuron */
+#define SNN_V_M 0        /* membrane potential (mV)                           */
+#define SNN_V_I_E 1      /* constant external current (pA)                    */
+#define SNN_V_W 2        /* AdEx adaptation current (pA)                      */
+#define SNN_V_G 3        /* AdEx conductance of `port` (nS)                   */
+#define SNN_V_I_SYN 4    /* LIF-exp synaptic current of `port` (pA)           */
+#define SNN_V_REFR 5     /* remaining refractory steps                        */
+#define SNN_V_H 6        /* AdEx carried RK45 step size (ms)                  */
+
+/* delay distributions (in ms; converted to steps of dt, rounded half up,
+   clipped to [1, Dmax]) */
+#define SNN_DELAY_CONST 0          /* a                                       */
+#define SNN_DELAY_UNIFORM 1        /* uniform on [a, b)                       */
+#define SNN_DELAY_NORMAL_CLIPPED 2 /* normal, mean a, standard deviation b    */
+
+typedef struct snn_counters {
+  uint64_t steps;          /* steps simulated so far                          */
+  uint64_t spikes;         /* spike events recorded (multiplicity counted 1)  */
+  uint64_t events;         /* synaptic events delivered (sum of group sizes)  */
+  uint64_t pairs;          /* (source, delay-group) pairs selected            */
+  uint64_t rk_accepted;    /* AdEx accepted RK45 substeps                     */
+  uint64_t rk_rejected;    /* AdEx rejected RK45 substeps                     */
+  uint64_t n_neurons, n_synapses, n_groups;
+  uint64_t device_bytes;   /* device memory held by the net                   */
+  double build_ms;         /* wall time of snn_build                          */
+  double simulate_ms;      /* wall time spent in snn_simulate                 */
+  uint32_t overflow;       /* nonzero if a device-side range check failed     */
+  uint32_t max_delay_used; /* largest delay (steps) present in the network    */
+} snn_counters;
+
+/* ---- lifecycle ---------------------------------------------------------- */
+/* Create an empty network.  dev may be NULL (hipMalloc on the current device). */
+snn_status snn_create_net(const snn_config* cfg, const snn_device* dev, snn_net** out);
+/* Release every host and device resource of the network (NULL is a no-op). */
+void snn_destroy_net(snn_net* net);
+/* Message of the last failed call on `net` ("" if none); valid until the next call. */
+const char* snn_last_error(const snn_net* net);
+
+/* ---- definition phase (before snn_build) --------------------------------- */
+/* Create n neurons of `model` with n_ports receptor ports (1..4; LIF delta: 1)
+   and NEST-like default parameters.  *first_gid receives the first gid. */
+snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports, uint32_t* first_gid);
+/* Set model parameter `param` (SNN_P_*) of the populations that make up the
+   gid range [first, first+n), which must be a union of whole populations. */
+snn_status snn_set_param(snn_net* net, uint32_t first, uint32_t n, int32_t param, double value);
+/* Set port parameter `param` (SNN_PP_*) of receptor `port`, same range rule. */
+snn_status snn_set_port_param(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int32_t param,
+                              double value);
+/* Fixed-indegree rule (Sec. 2.1): every target in [tgt_first, tgt_first+tgt_n)
+   receives `indegree` synapses from sources drawn uniformly, with replacement,
+   from [src_first, src_first+src_n) (autapses and multapses allowed), each
+   with weight `weight`, receptor `port` and a delay drawn from the given
+   distribution.  Randomness: counter-based, keyed by the config seed, the
+   projection's creation index, the target gid and the draw index, so a network
+   is identical on every run, alone or batched. */
+snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
+                                      uint32_t tgt_n, uint32_t indegree, double weight, int32_t delay_kind,
+                                      double delay_a, double delay_b, uint32_t port);
+/* Poisson generator (Sec. 2.1, Table 1): every target in the range receives,
+   independently, the summed spikes of n_inputs trains of rate_hz each, with
+   weight `weight` on `port`, drawn per target and step.  At most one drive per
+   neuron. */
+snn_status snn_poisson(snn_net* net, uint32_t tgt_first, uint32_t tgt_n, double rate_hz, uint32_t n_inputs,
+                       double weight, uint32_t port);
+
+/* ---- state (any phase) --------------------------------------------------- */
+/* Set state variable `var` (SNN_V_*) of gids [first, first+n) from v[0..nv),
+   nv == 1 broadcasts, nv == n gives one value per neuron.  After build this
+   writes device memory (synchronously). */
+snn_status snn_set_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, uint32_t port, const double* v,
+                         size_t nv);
+/* Read state variable `var` of gids [first, first+n) into out[0..n). */
+snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, uint32_t port, double* out);
+
+/* ---- build and simulation ------------------------------------------------ */
+/* Freeze the network: draw the connectivity on the device and lay it out by
+   (source, delay group) with a per-source delay bitmask; allocate state,
+   spike buffers and input accumulators.  Returns SNN_E_UNSUPPORTED for more
+   than 64 distinct (port, weight) classes or more than 2^26 neurons. */
+snn_status snn_build(snn_net* net);
+/* Advance by round(t_ms / dt) steps (resumable: later calls continue). */
+snn_status snn_simulate(snn_net* net, double t_ms);
+/* Advance by `steps` steps. */
+snn_status snn_simulate_steps(snn_net* net, uint64_t steps);
+
+/* ---- readback ------------------------------------------------------------ */
+/* Spikes with step in [step_lo, step_hi), sorted by (step, gid).  A spike in
+   step n is emitted at time (n+1) dt.  Writes min(count, cap) entries; *n_out
+   receives the total count (call with cap = 0 to size the buffers). */
+snn_status snn_get_spikes(snn_net* net, uint64_t step_lo, uint64_t step_hi, uint64_t* step, uint32_t* gid,
+                          uint32_t* mult, size_t cap, size_t* n_out);
+/* Counters (see snn_counters). */
+snn_status snn_get_counters(snn_net* net, snn_counters* out);
+/* Integer input already delivered for the next step of gids [first, first+n)
+   on `port` (network synapses only, Poisson excluded), in units of
+   2^-shift(gid, port) of the weight unit. */
+snn_status snn_get_input(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int64_t* out);
+/* Fixed-point exponent S of (gid, port): weights are stored as llrint(w 2^S). */
+snn_status snn_get_shift(snn_net* net, uint32_t gid, uint32_t port, int32_t* shift);
+/* Poisson counts the device draws for gids [first, first+n) at `step`
+   (0 where a neuron has no drive). */
+snn_status snn_poisson_counts(snn_net* net, uint64_t step, uint32_t first, uint32_t n, uint32_t* k);
+/* Connectivity in canonical order (source, delay, target, port, weight): on
+   input *n_syn is the capacity of the arrays, on output the synapse count
+   (arrays untouched when too small). */
+snn_status snn_export_synapses(snn_net* net, uint32_t* src, uint32_t* delay, uint32_t* tgt, uint32_t* port,
+                               int64_t* wq, size_t* n_syn);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNN_H */

@@ -601,12 +601,14 @@ void orc_cash_karp_tableau(double* c, double* a, double* b5, double* b4) {
 }
 
 /* Step-size control of Press et al. (rkqs): error measured relative to
-   |y| + |h dy/dt|, scaled by eps; a failed step shrinks h by 0.9 e^{-1/4}
-   (at most 10x), an accepted one grows it by 0.9 e^{-1/5} (at most 5x). */
+   |y| + |h dy/dt| + 1 (state units: mV, pA, nS; the unit floor keeps the test
+   meaningful for variables that are exactly zero, such as w and g at rest),
+   scaled by eps; a failed step shrinks h by 0.9 e^{-1/4} (at most 10x), an
+   accepted one grows it by 0.9 e^{-1/5} (at most 5x). */
 #define RK_SAFETY 0.9
 #define RK_PGROW (-0.2)
 #define RK_PSHRNK (-0.25)
-#define RK_TINY 1e-30
+#define RK_FLOOR 1.0
 #define RK_MAXIT 1000000
 
 int orc_adex_step(const orc_pop_params* pp, double dt, double* y, double* hcar, double I_e, const double* x,
@@ -642,7 +644,7 @@ int orc_adex_step(const orc_pop_params* pp, double dt, double* y, double* hcar, 
       for (int j = 0; j < 6; ++j) { s5 += CK_B5[j] * k[j][i]; se += (CK_B5[j] - CK_B4[j]) * k[j][i]; }
       y5[i] = y[i] + h * s5;
       err[i] = h * se;
-      double scale = fabs(y[i]) + fabs(h * k[0][i]) + RK_TINY;
+      double scale = fabs(y[i]) + fabs(h * k[0][i]) + RK_FLOOR;
       double r = fabs(err[i]) / scale;
       if (r > errmax) errmax = r;
     }

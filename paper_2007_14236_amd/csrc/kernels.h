@@ -1,0 +1,40 @@
+// kernels.h -- host-callable launchers of the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "snn_types.h"
+
+namespace snn {
+
+// ---- connectivity build ----
+// total_pairs = sum over projections of tgt_n * ceil(K / 2)
+hipError_t launch_gen_count(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint64_t seed,
+                            uint32_t dmax_cfg, uint32_t D1, uint32_t* cnt, hipStream_t s);
+hipError_t launch_gen_scatter(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint64_t seed,
+                              uint32_t dmax_cfg, uint32_t D1, uint64_t* cursor, uint32_t* payload,
+                              const uint8_t* cls_of, const uint32_t* pop_first, uint32_t npop, hipStream_t s);
+// exclusive scan of n u32 (in32) or u64 (in64) values into out; *total_dev receives the sum.
+// tmp must hold scan_tmp_words(n) u64 words.
+size_t scan_tmp_words(uint64_t n);
+hipError_t launch_scan_u32(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s);
+hipError_t launch_scan_u64(const uint64_t* in, uint64_t n, uint64_t* out, uint64_t* tmp, hipStream_t s);
+hipError_t launch_masks(const uint32_t* cnt, uint32_t N, uint32_t D1, uint64_t* mask, uint64_t* ngroups,
+                        hipStream_t s);
+hipError_t launch_grp_off(const uint32_t* cnt, const uint64_t* off, const uint64_t* grp_ptr64, uint32_t N,
+                          uint32_t D1, uint64_t* grp_off, uint32_t* grp_ptr32, hipStream_t s);
+// sort every group's payload ascending; groups longer than 16384 are listed in big[] (count in *nbig)
+hipError_t launch_segsort(const uint64_t* grp_off, uint64_t n_groups, uint32_t* payload, uint64_t* big,
+                          uint32_t* nbig, uint32_t big_cap, hipStream_t s);
+
+// ---- per-step pipeline (step = ctrl->step_base + rel) ----
+hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s);
+hipError_t launch_select(const NetDev& nd, uint32_t rel, hipStream_t s);
+hipError_t launch_scan_pairs(const NetDev& nd, uint32_t rel, hipStream_t s);
+hipError_t launch_deliver(const NetDev& nd, uint32_t rel, uint32_t grid, hipStream_t s);
+hipError_t launch_advance(Ctrl* ctrl, uint32_t steps, hipStream_t s);
+// model-specific update launchers (internal)
+hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,
+                                 hipStream_t s);
+
+}  // namespace snn

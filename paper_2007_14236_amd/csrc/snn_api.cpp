@@ -1,0 +1,1116 @@
+// snn_api.cpp -- host runtime behind the C ABI of include/snn.h.
+//
+// Owns the network description, the host-side tables the kernels read
+// (propagators, fixed-point exponents, weight classes, delay and Poisson
+// thresholds), device memory, the build sequence and the step loop (hipGraph
+// of K steps of update -> select -> scan -> deliver, replayed; the spike
+// ring is drained to the host raster between replays).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/snn.h"
+#include "kernels.h"
+#include "snn_types.h"
+
+using namespace snn;
+
+namespace {
+
+constexpr uint32_t kGraphSteps = 100;
+constexpr uint64_t kChunkRing = 4096;  // >= drain interval + graph length
+
+struct HostPop {
+  int32_t model = 0;
+  uint32_t n = 0, ports = 1, first = 0;
+  double tau_m = 10.0, C_m = 250.0, E_L = -70.0, V_th = -55.0, V_reset = -70.0, t_ref = 2.0;
+  double g_L = 30.0, Delta_T = 2.0, V_T = -50.4, tau_w = 144.0, a = 4.0, b = 80.5, V_peak = 0.0, V_r = -60.0;
+  double rk_eps = 1e-6, rk_hmin = 1e-8;
+  double tau_syn[kMaxPorts] = {2.0, 2.0, 2.0, 2.0};
+  double E_rev[kMaxPorts] = {0.0, -85.0, 0.0, 0.0};
+};
+
+struct HostProj {
+  uint32_t src_first, src_n, tgt_first, tgt_n, K, port;
+  double weight;
+  int32_t kind;
+  double da, db;
+};
+
+struct HostPois {
+  uint32_t tgt_first, tgt_n, n_inputs, port;
+  double rate, weight;
+};
+
+struct DevAlloc {
+  void* p;
+  size_t bytes;
+};
+
+// ---------------------------------------------------------------- tables
+// Delay d (ms) -> steps: d/dt rounded half up, at least 1, at most Dmax, so
+// P(D <= k) = F((k + 1/2) dt) below Dmax; a 32-bit uniform u selects
+// D = min{k : u < floor(2^32 P(D <= k))}.
+double delay_cdf_at(int32_t kind, double a, double b, double x) {
+  switch (kind) {
+    case SNN_DELAY_CONST: return (x >= a) ? 1.0 : 0.0;
+    case SNN_DELAY_UNIFORM: {
+      const double f = (x - a) / (b - a);
+      return f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+    }
+    default: return 0.5 * erfc(-(x - a) / (b * sqrt(2.0)));
+  }
+}
+
+uint64_t threshold_of(double p) {
+  if (!(p > 0.0)) return 0;
+  if (p >= 1.0) return 1ull << 32;
+  const double t = floor(ldexp(p, 32));
+  return (t >= 4294967296.0) ? (1ull << 32) : (uint64_t)t;
+}
+
+void delay_thresholds(int32_t kind, double a, double b, double dt, uint32_t dmax, uint64_t* thr) {
+  for (uint32_t k = 0; k < 64; ++k) thr[k] = 1ull << 32;
+  thr[0] = 0;
+  if (kind == SNN_DELAY_CONST) {
+    const double q = floor(a / dt + 0.5);
+    const uint32_t d0 = q < 1.0 ? 1u : (q > (double)dmax ? dmax : (uint32_t)q);
+    for (uint32_t k = 1; k <= dmax; ++k) thr[k] = (k >= d0) ? (1ull << 32) : 0;
+    return;
+  }
+  for (uint32_t k = 1; k < dmax; ++k) thr[k] = threshold_of(delay_cdf_at(kind, a, b, ((double)k + 0.5) * dt));
+  thr[dmax] = 1ull << 32;
+}
+
+// Poisson(lambda) cumulative thresholds (tail folded into the last entry).
+void poisson_thresholds(double lambda, uint64_t* thr) {
+  double p = exp(-lambda), c = p;
+  for (int k = 0; k + 1 < kPoisKmax; ++k) {
+    if (k > 0) {
+      p = p * lambda / (double)k;
+      c = c + p;
+    }
+    thr[k] = threshold_of(c);
+  }
+  thr[kPoisKmax - 1] = 1ull << 32;
+}
+
+// Largest S with max_w * 2^S < 2^30.
+int fixed_shift(double max_w) {
+  if (!(max_w > 0)) return 0;
+  int e;
+  (void)frexp(max_w, &e);
+  return 30 - e;
+}
+
+}  // namespace
+
+struct snn_net {
+  snn_config cfg{};
+  snn_device dev{};
+  bool have_dev = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_user = nullptr;
+  std::string err;
+  bool built = false;
+
+  std::vector<HostPop> pops;
+  std::vector<HostProj> projs;
+  std::vector<HostPois> pois;
+  uint32_t N = 0;
+  // host state before build (per port arrays are [N][kMaxPorts])
+  std::vector<double> V, Ie, w, h;
+  std::vector<double> g, Isyn;
+  std::vector<int32_t> refr;
+
+  // after build
+  uint32_t P = 1;
+  uint32_t dmax_used = 1;
+  std::vector<int> shift;          // [npop][P]
+  std::vector<int64_t> cls_wq;     // classes sorted by (port, w_q)
+  std::vector<uint32_t> cls_port;
+  bool has_lif = false, has_adex = false;
+  NetDev nd{};
+  std::vector<DevAlloc> allocs;
+  size_t dev_bytes = 0;
+  uint64_t n_syn = 0, n_groups = 0;
+  uint64_t cur_step = 0, drained_step = 0;
+  uint64_t log_cap = 0;
+  uint64_t drain_steps = 0;
+  uint32_t dlv_grid = 1024;
+  hipGraphExec_t graph_k = nullptr, graph_1 = nullptr;
+  uint64_t* pinned = nullptr;
+  size_t pinned_words = 0;
+
+  // host raster
+  std::vector<uint64_t> r_step;
+  std::vector<uint32_t> r_gid, r_mult;
+
+  double build_ms = 0.0, sim_ms = 0.0;
+};
+
+namespace {
+
+snn_status fail(snn_net* net, snn_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (net) net->err = buf;
+  return code;
+}
+
+#define HIPCHK(net, expr)                                                                     \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return fail((net), SNN_E_DEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+void* dev_alloc(snn_net* net, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (net->have_dev && net->dev.alloc) {
+    p = net->dev.alloc(bytes, net->dev.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) {
+    net->allocs.push_back({p, bytes});
+    net->dev_bytes += bytes;
+  }
+  return p;
+}
+
+void dev_free(snn_net* net, void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < net->allocs.size(); ++i) {
+    if (net->allocs[i].p == p) {
+      net->dev_bytes -= net->allocs[i].bytes;
+      net->allocs.erase(net->allocs.begin() + (long)i);
+      break;
+    }
+  }
+  if (net->have_dev && net->dev.free) net->dev.free(p, net->dev.user);
+  else (void)hipFree(p);
+}
+
+template <typename T>
+T* dalloc(snn_net* net, size_t count) {
+  return static_cast<T*>(dev_alloc(net, count * sizeof(T)));
+}
+
+int pop_of(const snn_net* net, uint32_t gid) {
+  for (size_t k = 0; k < net->pops.size(); ++k)
+    if (gid >= net->pops[k].first && gid < net->pops[k].first + net->pops[k].n) return (int)k;
+  return -1;
+}
+
+// populations exactly covering [first, first+n), or empty if the range is not a union of whole populations
+std::vector<int> whole_pops(const snn_net* net, uint32_t first, uint32_t n) {
+  std::vector<int> out;
+  uint64_t cur = first, end = (uint64_t)first + n;
+  while (cur < end) {
+    int k = pop_of(net, (uint32_t)cur);
+    if (k < 0 || net->pops[k].first != cur || net->pops[k].first + net->pops[k].n > end) return {};
+    out.push_back(k);
+    cur += net->pops[k].n;
+  }
+  return out;
+}
+
+snn_status enter(snn_net* net) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->have_dev && net->dev.stream) {
+    HIPCHK(net, hipEventRecord(net->ev_user, (hipStream_t)net->dev.stream));
+    HIPCHK(net, hipStreamWaitEvent(net->stream, net->ev_user, 0));
+  }
+  return SNN_OK;
+}
+
+snn_status leave(snn_net* net) {
+  if (net->have_dev && net->dev.stream) {
+    HIPCHK(net, hipEventRecord(net->ev_user, net->stream));
+    HIPCHK(net, hipStreamWaitEvent((hipStream_t)net->dev.stream, net->ev_user, 0));
+  }
+  return SNN_OK;
+}
+
+void lif_propagators(const HostPop& p, double dt, PopDev& d) {
+  const double P22 = exp(-dt / p.tau_m);
+  const double P20 = p.tau_m / p.C_m * (1.0 - P22);
+  d.P22 = (float)P22;
+  d.P20 = (float)P20;
+  for (uint32_t q = 0; q < kMaxPorts; ++q) {
+    double P11 = 0.0, P21 = 0.0;
+    if (q < p.ports) {
+      const double ts = p.tau_syn[q];
+      if (ts > 0) {
+        P11 = exp(-dt / ts);
+        if (ts == p.tau_m) P21 = dt / p.C_m * exp(-dt / p.tau_m);
+        else P21 = p.tau_m * ts / (p.C_m * (ts - p.tau_m)) * (exp(-dt / ts) - exp(-dt / p.tau_m));
+      }
+    }
+    d.P11[q] = (float)P11;
+    d.P21[q] = (float)P21;
+  }
+  d.theta = (float)(p.V_th - p.E_L);
+  d.y_reset = (float)(p.V_reset - p.E_L);
+  d.n_ref = (int32_t)floor(p.t_ref / dt + 0.5);
+}
+
+uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// device value of state variable `var` for neuron i (and the inverse)
+float to_device_state(const snn_net* net, int var, uint32_t i, double v) {
+  const HostPop& pp = net->pops[pop_of(net, i)];
+  if (var == SNN_V_M && pp.model != SNN_AEIF_COND_EXP) return (float)(v - pp.E_L);
+  return (float)v;
+}
+
+double from_device_state(const snn_net* net, int var, uint32_t i, float v) {
+  const HostPop& pp = net->pops[pop_of(net, i)];
+  if (var == SNN_V_M && pp.model != SNN_AEIF_COND_EXP) return (double)v + pp.E_L;
+  return (double)v;
+}
+
+snn_status drain(snn_net* net);
+snn_status build_graphs(snn_net* net);
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+snn_status snn_create_net(const snn_config* cfg, const snn_device* dev, snn_net** out) {
+  if (!cfg || !out) return SNN_E_INVALID;
+  *out = nullptr;
+  if (!(cfg->dt_ms > 0) || cfg->max_delay_steps < 1 || cfg->max_delay_steps > 63) return SNN_E_INVALID;
+  snn_net* net = new (std::nothrow) snn_net();
+  if (!net) return SNN_E_NOMEM;
+  net->cfg = *cfg;
+  if (dev) {
+    net->dev = *dev;
+    net->have_dev = true;
+    if ((dev->alloc == nullptr) != (dev->free == nullptr)) {
+      delete net;
+      return SNN_E_INVALID;
+    }
+  }
+  if (hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&net->ev_user, hipEventDisableTiming) != hipSuccess) {
+    delete net;
+    return SNN_E_DEVICE;
+  }
+  *out = net;
+  return SNN_OK;
+}
+
+void snn_destroy_net(snn_net* net) {
+  if (!net) return;
+  if (net->stream) (void)hipStreamSynchronize(net->stream);
+  if (net->graph_k) (void)hipGraphExecDestroy(net->graph_k);
+  if (net->graph_1) (void)hipGraphExecDestroy(net->graph_1);
+  while (!net->allocs.empty()) dev_free(net, net->allocs.back().p);
+  if (net->pinned) (void)hipHostFree(net->pinned);
+  if (net->ev_user) (void)hipEventDestroy(net->ev_user);
+  if (net->stream) (void)hipStreamDestroy(net->stream);
+  delete net;
+}
+
+const char* snn_last_error(const snn_net* net) { return net ? net->err.c_str() : "null network"; }
+
+snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports, uint32_t* first_gid) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "snn_create after snn_build");
+  if (model < SNN_LIF_PSC_DELTA || model > SNN_AEIF_COND_EXP) return fail(net, SNN_E_INVALID, "unknown model %d", model);
+  if (n == 0 || n_ports < 1 || n_ports > (uint32_t)kMaxPorts) return fail(net, SNN_E_INVALID, "bad size or port count");
+  if (model == SNN_LIF_PSC_DELTA && n_ports != 1) return fail(net, SNN_E_INVALID, "LIF delta has one port");
+  if ((uint64_t)net->N + n > kMaxNeurons) return fail(net, SNN_E_UNSUPPORTED, "more than 2^26 neurons");
+  HostPop p;
+  p.model = model;
+  p.n = n;
+  p.ports = n_ports;
+  p.first = net->N;
+  if (model == SNN_AEIF_COND_EXP) {
+    p.C_m = 281.0; p.E_L = -70.6; p.t_ref = 0.0;
+    for (int q = 0; q < kMaxPorts; ++q) p.tau_syn[q] = 1.0;
+  }
+  net->pops.push_back(p);
+  net->N += n;
+  net->V.resize(net->N, std::nan(""));
+  net->Ie.resize(net->N, 0.0);
+  net->w.resize(net->N, 0.0);
+  net->h.resize(net->N, net->cfg.dt_ms);
+  net->refr.resize(net->N, 0);
+  net->g.resize((size_t)net->N * kMaxPorts, 0.0);
+  net->Isyn.resize((size_t)net->N * kMaxPorts, 0.0);
+  if (first_gid) *first_gid = p.first;
+  return SNN_OK;
+}
+
+snn_status snn_set_param(snn_net* net, uint32_t first, uint32_t n, int32_t param, double value) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "parameters are frozen after snn_build");
+  std::vector<int> ks = whole_pops(net, first, n);
+  if (ks.empty()) return fail(net, SNN_E_INVALID, "range [%u, %u) is not a union of whole populations", first, first + n);
+  for (int k : ks) {
+    HostPop& p = net->pops[k];
+    switch (param) {
+      case SNN_P_TAU_M: p.tau_m = value; break;
+      case SNN_P_C_M: p.C_m = value; break;
+      case SNN_P_E_L: p.E_L = value; break;
+      case SNN_P_V_TH: p.V_th = value; break;
+      case SNN_P_V_RESET: p.V_reset = value; break;
+      case SNN_P_T_REF: p.t_ref = value; break;
+      case SNN_P_G_L: p.g_L = value; break;
+      case SNN_P_DELTA_T: p.Delta_T = value; break;
+      case SNN_P_V_T: p.V_T = value; break;
+      case SNN_P_TAU_W: p.tau_w = value; break;
+      case SNN_P_A: p.a = value; break;
+      case SNN_P_B: p.b = value; break;
+      case SNN_P_V_PEAK: p.V_peak = value; break;
+      case SNN_P_V_R: p.V_r = value; break;
+      case SNN_P_RK_EPS: p.rk_eps = value; break;
+      case SNN_P_RK_HMIN: p.rk_hmin = value; break;
+      default: return fail(net, SNN_E_INVALID, "unknown parameter %d", param);
+    }
+  }
+  return SNN_OK;
+}
+
+snn_status snn_set_port_param(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int32_t param, double value) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "parameters are frozen after snn_build");
+  std::vector<int> ks = whole_pops(net, first, n);
+  if (ks.empty()) return fail(net, SNN_E_INVALID, "range is not a union of whole populations");
+  for (int k : ks) {
+    HostPop& p = net->pops[k];
+    if (port >= p.ports) return fail(net, SNN_E_INVALID, "port %u out of range", port);
+    if (param == SNN_PP_TAU_SYN) {
+      if (!(value > 0)) return fail(net, SNN_E_INVALID, "tau_syn must be positive");
+      p.tau_syn[port] = value;
+    } else if (param == SNN_PP_E_REV) {
+      p.E_rev[port] = value;
+    } else {
+      return fail(net, SNN_E_INVALID, "unknown port parameter %d", param);
+    }
+  }
+  return SNN_OK;
+}
+
+snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
+                                      uint32_t tgt_n, uint32_t indegree, double weight, int32_t delay_kind,
+                                      double delay_a, double delay_b, uint32_t port) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "connect after snn_build");
+  if (src_n == 0 || (uint64_t)src_first + src_n > net->N || (uint64_t)tgt_first + tgt_n > net->N)
+    return fail(net, SNN_E_INVALID, "source or target range outside the network");
+  if (delay_kind < SNN_DELAY_CONST || delay_kind > SNN_DELAY_NORMAL_CLIPPED)
+    return fail(net, SNN_E_INVALID, "unknown delay distribution %d", delay_kind);
+  if (delay_kind == SNN_DELAY_UNIFORM && !(delay_b > delay_a)) return fail(net, SNN_E_INVALID, "uniform delay needs b > a");
+  if (delay_kind == SNN_DELAY_NORMAL_CLIPPED && !(delay_b > 0)) return fail(net, SNN_E_INVALID, "normal delay needs sd > 0");
+  if (!std::isfinite(weight)) return fail(net, SNN_E_INVALID, "weight must be finite");
+  for (uint32_t t = tgt_first; t < tgt_first + tgt_n;) {
+    const HostPop& pp = net->pops[pop_of(net, t)];
+    if (port >= pp.ports) return fail(net, SNN_E_INVALID, "port %u out of range for target population", port);
+    if (pp.model == SNN_AEIF_COND_EXP && weight < 0) return fail(net, SNN_E_INVALID, "conductance weights must be >= 0");
+    t = pp.first + pp.n;
+  }
+  if (net->projs.size() >= (1u << 23)) return fail(net, SNN_E_UNSUPPORTED, "too many projections");
+  net->projs.push_back({src_first, src_n, tgt_first, tgt_n, indegree, port, weight, delay_kind, delay_a, delay_b});
+  return SNN_OK;
+}
+
+snn_status snn_poisson(snn_net* net, uint32_t tgt_first, uint32_t tgt_n, double rate_hz, uint32_t n_inputs,
+                       double weight, uint32_t port) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "poisson after snn_build");
+  if ((uint64_t)tgt_first + tgt_n > net->N || !(rate_hz >= 0)) return fail(net, SNN_E_INVALID, "bad Poisson drive");
+  std::vector<int> ks = whole_pops(net, tgt_first, tgt_n);
+  if (ks.empty()) return fail(net, SNN_E_UNSUPPORTED, "a Poisson drive must cover whole populations");
+  for (int k : ks)
+    if (port >= net->pops[k].ports) return fail(net, SNN_E_INVALID, "port out of range");
+  const double lam = (double)n_inputs * rate_hz * net->cfg.dt_ms * 1e-3;
+  if (lam > 60.0) return fail(net, SNN_E_UNSUPPORTED, "Poisson mean per step %.3g > 60", lam);
+  net->pois.push_back({tgt_first, tgt_n, n_inputs, port, rate_hz, weight});
+  return SNN_OK;
+}
+
+snn_status snn_set_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, uint32_t port, const double* v,
+                         size_t nv) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if ((uint64_t)first + n > net->N || !v || (nv != 1 && nv != n)) return fail(net, SNN_E_INVALID, "bad state range");
+  if (port >= (uint32_t)kMaxPorts) return fail(net, SNN_E_INVALID, "bad port");
+  if (!net->built) {
+    for (uint32_t j = 0; j < n; ++j) {
+      const double x = v[nv == 1 ? 0 : j];
+      const uint32_t i = first + j;
+      switch (var) {
+        case SNN_V_M: net->V[i] = x; break;
+        case SNN_V_I_E: net->Ie[i] = x; break;
+        case SNN_V_W: net->w[i] = x; break;
+        case SNN_V_G: net->g[(size_t)i * kMaxPorts + port] = x; break;
+        case SNN_V_I_SYN: net->Isyn[(size_t)i * kMaxPorts + port] = x; break;
+        case SNN_V_REFR: net->refr[i] = (int32_t)x; break;
+        case SNN_V_H: net->h[i] = x; break;
+        default: return fail(net, SNN_E_INVALID, "unknown state variable %d", var);
+      }
+    }
+    return SNN_OK;
+  }
+  snn_status st = enter(net);
+  if (st) return st;
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  const NetDev& nd = net->nd;
+  if ((var == SNN_V_G || var == SNN_V_I_SYN) && port >= net->P) return fail(net, SNN_E_INVALID, "port out of range");
+  if (var == SNN_V_REFR) {
+    std::vector<int32_t> buf(n);
+    for (uint32_t j = 0; j < n; ++j) buf[j] = (int32_t)v[nv == 1 ? 0 : j];
+    if (!nd.refr) return fail(net, SNN_E_INVALID, "no refractory state in this network");
+    HIPCHK(net, hipMemcpy(nd.refr + first, buf.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+    return leave(net);
+  }
+  float* base = nullptr;
+  size_t stride = 1, off = 0;
+  switch (var) {
+    case SNN_V_M: base = nd.V; break;
+    case SNN_V_I_E: base = nd.Ie; break;
+    case SNN_V_W: base = nd.w; break;
+    case SNN_V_G: base = nd.g; stride = net->P; off = port; break;
+    case SNN_V_I_SYN: base = nd.Isyn; stride = net->P; off = port; break;
+    case SNN_V_H: base = nd.h; break;
+    default: return fail(net, SNN_E_INVALID, "unknown state variable %d", var);
+  }
+  if (!base) return fail(net, SNN_E_INVALID, "state variable not present in this network");
+  std::vector<float> buf(n);
+  for (uint32_t j = 0; j < n; ++j) buf[j] = to_device_state(net, var, first + j, v[nv == 1 ? 0 : j]);
+  if (stride == 1) {
+    HIPCHK(net, hipMemcpy(base + first, buf.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  } else {
+    HIPCHK(net, hipMemcpy2D(base + (size_t)first * stride + off, stride * sizeof(float), buf.data(), sizeof(float),
+                            sizeof(float), n, hipMemcpyHostToDevice));
+  }
+  return leave(net);
+}
+
+snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, uint32_t port, double* out) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if ((uint64_t)first + n > net->N || !out) return fail(net, SNN_E_INVALID, "bad state range");
+  if (!net->built) {
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint32_t i = first + j;
+      const HostPop& pp = net->pops[pop_of(net, i)];
+      switch (var) {
+        case SNN_V_M: out[j] = std::isnan(net->V[i]) ? pp.E_L : net->V[i]; break;
+        case SNN_V_I_E: out[j] = net->Ie[i]; break;
+        case SNN_V_W: out[j] = net->w[i]; break;
+        case SNN_V_G: out[j] = net->g[(size_t)i * kMaxPorts + port]; break;
+        case SNN_V_I_SYN: out[j] = net->Isyn[(size_t)i * kMaxPorts + port]; break;
+        case SNN_V_REFR: out[j] = net->refr[i]; break;
+        case SNN_V_H: out[j] = net->h[i]; break;
+        default: return fail(net, SNN_E_INVALID, "unknown state variable %d", var);
+      }
+    }
+    return SNN_OK;
+  }
+  snn_status st = enter(net);
+  if (st) return st;
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  const NetDev& nd = net->nd;
+  if ((var == SNN_V_G || var == SNN_V_I_SYN) && port >= net->P) return fail(net, SNN_E_INVALID, "port out of range");
+  if (var == SNN_V_REFR) {
+    if (!nd.refr) return fail(net, SNN_E_INVALID, "no refractory state in this network");
+    std::vector<int32_t> buf(n);
+    HIPCHK(net, hipMemcpy(buf.data(), nd.refr + first, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (uint32_t j = 0; j < n; ++j) out[j] = buf[j];
+    return leave(net);
+  }
+  const float* base = nullptr;
+  size_t stride = 1, off = 0;
+  switch (var) {
+    case SNN_V_M: base = nd.V; break;
+    case SNN_V_I_E: base = nd.Ie; break;
+    case SNN_V_W: base = nd.w; break;
+    case SNN_V_G: base = nd.g; stride = net->P; off = port; break;
+    case SNN_V_I_SYN: base = nd.Isyn; stride = net->P; off = port; break;
+    case SNN_V_H: base = nd.h; break;
+    default: return fail(net, SNN_E_INVALID, "unknown state variable %d", var);
+  }
+  if (!base) return fail(net, SNN_E_INVALID, "state variable not present in this network");
+  std::vector<float> buf(n);
+  if (stride == 1) {
+    HIPCHK(net, hipMemcpy(buf.data(), base + first, n * sizeof(float), hipMemcpyDeviceToHost));
+  } else {
+    HIPCHK(net, hipMemcpy2D(buf.data(), sizeof(float), base + (size_t)first * stride + off, stride * sizeof(float),
+                            sizeof(float), n, hipMemcpyDeviceToHost));
+  }
+  for (uint32_t j = 0; j < n; ++j) out[j] = from_device_state(net, var, first + j, buf[j]);
+  return leave(net);
+}
+
+snn_status snn_build(snn_net* net) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "already built");
+  if (net->N == 0) return fail(net, SNN_E_INVALID, "empty network");
+  snn_status st = enter(net);
+  if (st) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  const double dt = net->cfg.dt_ms;
+  const uint32_t npop = (uint32_t)net->pops.size();
+  const uint32_t N = net->N;
+  uint32_t P = 1;
+  for (const HostPop& p : net->pops) {
+    P = std::max(P, p.ports);
+    if (p.model == SNN_AEIF_COND_EXP) {
+      net->has_adex = true;
+      if (p.t_ref != 0.0) return fail(net, SNN_E_UNSUPPORTED, "AdEx refractory time must be 0");
+      if (!(p.Delta_T > 0) || !(p.tau_w > 0) || !(p.C_m > 0) || !(p.rk_eps > 0))
+        return fail(net, SNN_E_INVALID, "invalid AdEx parameters");
+    } else {
+      net->has_lif = true;
+      if (!(p.tau_m > 0) || !(p.C_m > 0) || p.t_ref < 0) return fail(net, SNN_E_INVALID, "invalid LIF parameters");
+    }
+  }
+  net->P = P;
+  // Poisson drive per population (drives cover whole populations)
+  std::vector<int> pois_of_pop(npop, -1);
+  for (size_t q = 0; q < net->pois.size(); ++q) {
+    for (int k : whole_pops(net, net->pois[q].tgt_first, net->pois[q].tgt_n)) {
+      if (pois_of_pop[k] >= 0) return fail(net, SNN_E_INVALID, "two Poisson drives on one population");
+      pois_of_pop[k] = (int)q;
+    }
+  }
+  // fixed-point exponent per (population, port)
+  std::vector<double> maxw((size_t)npop * P, 0.0);
+  auto overlaps = [&](uint32_t k, uint32_t first, uint32_t n) {
+    const HostPop& p = net->pops[k];
+    return n > 0 && first < p.first + p.n && first + n > p.first;
+  };
+  for (const HostProj& pr : net->projs) {
+    if (pr.K == 0) continue;
+    for (uint32_t k = 0; k < npop; ++k)
+      if (overlaps(k, pr.tgt_first, pr.tgt_n)) maxw[k * P + pr.port] = std::max(maxw[k * P + pr.port], fabs(pr.weight));
+  }
+  for (const HostPois& q : net->pois)
+    for (uint32_t k = 0; k < npop; ++k)
+      if (overlaps(k, q.tgt_first, q.tgt_n)) maxw[k * P + q.port] = std::max(maxw[k * P + q.port], fabs(q.weight));
+  net->shift.assign((size_t)npop * P, 0);
+  for (size_t k = 0; k < maxw.size(); ++k) net->shift[k] = fixed_shift(maxw[k]);
+  // weight classes: distinct (port, w_q) sorted, per (projection, target population)
+  std::map<std::pair<uint32_t, int64_t>, uint8_t> classes;
+  std::vector<std::pair<uint32_t, int64_t>> cls_key((size_t)net->projs.size() * npop, {0, 0});
+  for (size_t p = 0; p < net->projs.size(); ++p) {
+    const HostProj& pr = net->projs[p];
+    for (uint32_t k = 0; k < npop; ++k) {
+      if (!overlaps(k, pr.tgt_first, pr.tgt_n) || pr.K == 0) continue;
+      const int64_t wq = llrint(ldexp(pr.weight, net->shift[k * P + pr.port]));
+      cls_key[p * npop + k] = {pr.port, wq};
+      classes[{pr.port, wq}] = 0;
+    }
+  }
+  if (classes.size() > (size_t)kMaxClasses) return fail(net, SNN_E_UNSUPPORTED, "more than 64 weight classes");
+  net->cls_wq.assign(kMaxClasses, 0);
+  net->cls_port.assign(kMaxClasses, 0);
+  {
+    uint8_t id = 0;
+    for (auto& kv : classes) {
+      kv.second = id;
+      net->cls_port[id] = kv.first.first;
+      net->cls_wq[id] = kv.first.second;
+      ++id;
+    }
+  }
+  std::vector<uint8_t> cls_of((size_t)std::max<size_t>(1, net->projs.size()) * npop, 0);
+  for (size_t p = 0; p < net->projs.size(); ++p)
+    for (uint32_t k = 0; k < npop; ++k)
+      if (overlaps(k, net->projs[p].tgt_first, net->projs[p].tgt_n) && net->projs[p].K)
+        cls_of[p * npop + k] = classes[cls_key[p * npop + k]];
+  // projections, delay tables, largest delay present
+  const uint32_t dmax_cfg = net->cfg.max_delay_steps;
+  std::vector<ProjDev> pd(net->projs.size());
+  uint64_t total_pairs = 0, total_syn = 0;
+  uint32_t dmax_used = 1;
+  for (size_t p = 0; p < net->projs.size(); ++p) {
+    const HostProj& pr = net->projs[p];
+    ProjDev& d = pd[p];
+    memset(&d, 0, sizeof d);
+    d.src_first = pr.src_first; d.src_n = pr.src_n; d.tgt_first = pr.tgt_first; d.tgt_n = pr.tgt_n;
+    d.K = pr.K; d.kpairs = (pr.K + 1) / 2; d.index = (uint32_t)p;
+    d.pair_begin = total_pairs;
+    delay_thresholds(pr.kind, pr.da, pr.db, dt, dmax_cfg, d.thr);
+    total_pairs += (uint64_t)pr.tgt_n * d.kpairs;
+    total_syn += (uint64_t)pr.tgt_n * pr.K;
+    if (pr.K && pr.tgt_n) {
+      uint32_t dm = 1;
+      while (dm < dmax_cfg && d.thr[dm] < (1ull << 32)) ++dm;
+      dmax_used = std::max(dmax_used, dm);
+    }
+  }
+  if (total_syn >= (1ull << 35)) return fail(net, SNN_E_UNSUPPORTED, "more than 2^35 synapses");
+  net->dmax_used = dmax_used;
+  const uint32_t D1 = dmax_used + 1;
+  // population table
+  std::vector<PopDev> popdev(npop);
+  std::vector<uint64_t> pois_thr;
+  for (uint32_t k = 0; k < npop; ++k) {
+    const HostPop& p = net->pops[k];
+    PopDev& d = popdev[k];
+    memset(&d, 0, sizeof d);
+    d.first = p.first; d.n = p.n; d.model = p.model; d.n_ports = (int32_t)p.ports;
+    if (p.model != SNN_AEIF_COND_EXP) lif_propagators(p, dt, d);
+    d.inv_C = (float)(1.0 / p.C_m); d.g_L = (float)p.g_L; d.E_L = (float)p.E_L; d.Delta_T = (float)p.Delta_T;
+    d.inv_Delta_T = (float)(1.0 / p.Delta_T); d.V_T = (float)p.V_T; d.inv_tau_w = (float)(1.0 / p.tau_w);
+    d.a = (float)p.a; d.b = (float)p.b; d.V_peak = (float)p.V_peak; d.V_r = (float)p.V_r;
+    for (int q = 0; q < kMaxPorts; ++q) {
+      d.E_rev[q] = (float)p.E_rev[q];
+      d.inv_tau_syn[q] = (float)(1.0 / p.tau_syn[q]);
+      d.scale[q] = (q < (int)P) ? (float)ldexp(1.0, -net->shift[k * P + q]) : 0.f;
+    }
+    d.rk_eps = (float)p.rk_eps; d.rk_hmin = (float)p.rk_hmin; d.dt = (float)dt;
+    d.pois = -1;
+    if (pois_of_pop[k] >= 0) {
+      const HostPois& q = net->pois[pois_of_pop[k]];
+      d.pois = (int32_t)(pois_thr.size() / kPoisKmax);
+      d.pois_port = (int32_t)q.port;
+      d.pois_wq = llrint(ldexp(q.weight, net->shift[k * P + q.port]));
+      std::vector<uint64_t> thr(kPoisKmax);
+      poisson_thresholds((double)q.n_inputs * q.rate * dt * 1e-3, thr.data());
+      pois_thr.insert(pois_thr.end(), thr.begin(), thr.end());
+    }
+  }
+  if (pois_thr.empty()) pois_thr.resize(kPoisKmax, 1ull << 32);
+
+  NetDev& nd = net->nd;
+  memset(&nd, 0, sizeof nd);
+  nd.N = N; nd.P = P; nd.npop = npop; nd.dmax = dmax_used; nd.R = dmax_used + 1;
+  nd.nblk_upd = (N + kUpdBlock - 1) / kUpdBlock;
+  nd.seed = net->cfg.seed;
+  nd.pad0 = (net->has_lif ? 1u : 0u) | (net->has_adex ? 2u : 0u);
+  hipStream_t s = net->stream;
+#define ALLOC(ptr, T, count)                                                              \
+  do {                                                                                    \
+    ptr = dalloc<T>(net, (count));                                                        \
+    if (!ptr) return fail(net, SNN_E_NOMEM, "device allocation of %zu bytes failed", (size_t)(count) * sizeof(T)); \
+  } while (0)
+  PopDev* d_pops; ALLOC(d_pops, PopDev, npop);
+  HIPCHK(net, hipMemcpyAsync(d_pops, popdev.data(), npop * sizeof(PopDev), hipMemcpyHostToDevice, s));
+  nd.pops = d_pops;
+  uint64_t* d_pthr; ALLOC(d_pthr, uint64_t, pois_thr.size());
+  HIPCHK(net, hipMemcpyAsync(d_pthr, pois_thr.data(), pois_thr.size() * 8, hipMemcpyHostToDevice, s));
+  nd.pois_thr = d_pthr;
+  int64_t* d_cw; ALLOC(d_cw, int64_t, kMaxClasses);
+  uint32_t* d_cp; ALLOC(d_cp, uint32_t, kMaxClasses);
+  HIPCHK(net, hipMemcpyAsync(d_cw, net->cls_wq.data(), kMaxClasses * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(net, hipMemcpyAsync(d_cp, net->cls_port.data(), kMaxClasses * 4, hipMemcpyHostToDevice, s));
+  nd.cls_wq = d_cw; nd.cls_port = d_cp;
+
+  // ---- connectivity: count, scan, masks, group offsets, scatter, sort ----
+  const uint64_t M = (uint64_t)N * D1;
+  uint32_t* d_cnt; ALLOC(d_cnt, uint32_t, M);
+  uint64_t* d_off; ALLOC(d_off, uint64_t, M + 1);
+  uint64_t* d_ng; ALLOC(d_ng, uint64_t, N);
+  uint64_t* d_gp64; ALLOC(d_gp64, uint64_t, (size_t)N + 1);
+  uint64_t* d_tmp; ALLOC(d_tmp, uint64_t, scan_tmp_words(M));
+  uint64_t* d_mask; ALLOC(d_mask, uint64_t, N);
+  uint32_t* d_gp32; ALLOC(d_gp32, uint32_t, (size_t)N + 1);
+  ProjDev* d_proj = nullptr;
+  uint8_t* d_clsof = nullptr;
+  uint32_t* d_popfirst = nullptr;
+  ALLOC(d_proj, ProjDev, std::max<size_t>(1, pd.size()));
+  ALLOC(d_clsof, uint8_t, cls_of.size());
+  ALLOC(d_popfirst, uint32_t, npop);
+  std::vector<uint32_t> pf(npop);
+  for (uint32_t k = 0; k < npop; ++k) pf[k] = net->pops[k].first;
+  if (!pd.empty()) HIPCHK(net, hipMemcpyAsync(d_proj, pd.data(), pd.size() * sizeof(ProjDev), hipMemcpyHostToDevice, s));
+  HIPCHK(net, hipMemcpyAsync(d_clsof, cls_of.data(), cls_of.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(net, hipMemcpyAsync(d_popfirst, pf.data(), npop * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(net, hipMemsetAsync(d_cnt, 0, M * sizeof(uint32_t), s));
+  HIPCHK(net, launch_gen_count(d_proj, (uint32_t)pd.size(), total_pairs, nd.seed, dmax_cfg, D1, d_cnt, s));
+  HIPCHK(net, launch_scan_u32(d_cnt, M, d_off, d_tmp, s));
+  HIPCHK(net, launch_masks(d_cnt, N, D1, d_mask, d_ng, s));
+  HIPCHK(net, launch_scan_u64(d_ng, N, d_gp64, d_tmp, s));
+  uint64_t G = 0, S = 0;
+  HIPCHK(net, hipMemcpyAsync(&G, d_gp64 + N, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(net, hipMemcpyAsync(&S, d_off + M, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(net, hipStreamSynchronize(s));
+  if (S != total_syn) return fail(net, SNN_E_DEVICE, "synapse count mismatch (%llu vs %llu)",
+                                  (unsigned long long)S, (unsigned long long)total_syn);
+  uint64_t* d_goff; ALLOC(d_goff, uint64_t, G + 1);
+  HIPCHK(net, launch_grp_off(d_cnt, d_off, d_gp64, N, D1, d_goff, d_gp32, s));
+  HIPCHK(net, hipMemcpyAsync(d_goff + G, &S, 8, hipMemcpyHostToDevice, s));
+  uint32_t* d_pay; ALLOC(d_pay, uint32_t, std::max<uint64_t>(1, S));
+  HIPCHK(net, launch_gen_scatter(d_proj, (uint32_t)pd.size(), total_pairs, nd.seed, dmax_cfg, D1, d_off, d_pay, d_clsof,
+                                 d_popfirst, npop, s));
+  const uint32_t big_cap = 4096;
+  uint64_t* d_big; ALLOC(d_big, uint64_t, big_cap);
+  uint32_t* d_nbig; ALLOC(d_nbig, uint32_t, 1);
+  HIPCHK(net, hipMemsetAsync(d_nbig, 0, 4, s));
+  HIPCHK(net, launch_segsort(d_goff, G, d_pay, d_big, d_nbig, big_cap, s));
+  uint32_t nbig = 0;
+  HIPCHK(net, hipMemcpyAsync(&nbig, d_nbig, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(net, hipStreamSynchronize(s));
+  if (nbig > big_cap) return fail(net, SNN_E_UNSUPPORTED, "too many connection groups above 16384 synapses");
+  if (nbig) {  // rare: very large groups are sorted on the host
+    std::vector<uint64_t> big(nbig);
+    HIPCHK(net, hipMemcpy(big.data(), d_big, nbig * 8, hipMemcpyDeviceToHost));
+    for (uint64_t gi : big) {
+      uint64_t be[2];
+      HIPCHK(net, hipMemcpy(be, d_goff + gi, 16, hipMemcpyDeviceToHost));
+      std::vector<uint32_t> seg(be[1] - be[0]);
+      HIPCHK(net, hipMemcpy(seg.data(), d_pay + be[0], seg.size() * 4, hipMemcpyDeviceToHost));
+      std::sort(seg.begin(), seg.end());
+      HIPCHK(net, hipMemcpy(d_pay + be[0], seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
+    }
+  }
+  dev_free(net, d_big); dev_free(net, d_nbig);
+  dev_free(net, d_cnt); dev_free(net, d_off); dev_free(net, d_ng); dev_free(net, d_gp64); dev_free(net, d_tmp);
+  dev_free(net, d_proj); dev_free(net, d_clsof); dev_free(net, d_popfirst);
+  nd.src_mask = d_mask; nd.grp_ptr = d_gp32; nd.grp_off = d_goff; nd.payload = d_pay;
+  nd.n_groups = G; nd.n_syn = S;
+  net->n_groups = G; net->n_syn = S;
+
+  // ---- state ----
+  float* d_V; ALLOC(d_V, float, N);
+  float* d_Ie; ALLOC(d_Ie, float, N);
+  std::vector<float> hv(N), hie(N);
+  for (uint32_t i = 0; i < N; ++i) {
+    const HostPop& pp = net->pops[pop_of(net, i)];
+    const double V = std::isnan(net->V[i]) ? pp.E_L : net->V[i];
+    hv[i] = (pp.model == SNN_AEIF_COND_EXP) ? (float)V : (float)(V - pp.E_L);
+    hie[i] = (float)net->Ie[i];
+  }
+  HIPCHK(net, hipMemcpy(d_V, hv.data(), N * 4, hipMemcpyHostToDevice));
+  HIPCHK(net, hipMemcpy(d_Ie, hie.data(), N * 4, hipMemcpyHostToDevice));
+  nd.V = d_V; nd.Ie = d_Ie;
+  std::vector<float> hp((size_t)N * P);
+  if (net->has_lif) {
+    int32_t* d_r; ALLOC(d_r, int32_t, N);
+    HIPCHK(net, hipMemcpy(d_r, net->refr.data(), N * 4, hipMemcpyHostToDevice));
+    nd.refr = d_r;
+    float* d_I; ALLOC(d_I, float, (size_t)N * P);
+    for (uint32_t i = 0; i < N; ++i)
+      for (uint32_t q = 0; q < P; ++q) hp[(size_t)i * P + q] = (float)net->Isyn[(size_t)i * kMaxPorts + q];
+    HIPCHK(net, hipMemcpy(d_I, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
+    nd.Isyn = d_I;
+  }
+  if (net->has_adex) {
+    float* d_w; ALLOC(d_w, float, N);
+    float* d_h; ALLOC(d_h, float, N);
+    float* d_g; ALLOC(d_g, float, (size_t)N * P);
+    std::vector<float> hw(N), hh(N);
+    for (uint32_t i = 0; i < N; ++i) { hw[i] = (float)net->w[i]; hh[i] = (float)net->h[i]; }
+    for (uint32_t i = 0; i < N; ++i)
+      for (uint32_t q = 0; q < P; ++q) hp[(size_t)i * P + q] = (float)net->g[(size_t)i * kMaxPorts + q];
+    HIPCHK(net, hipMemcpy(d_w, hw.data(), N * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, hipMemcpy(d_h, hh.data(), N * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, hipMemcpy(d_g, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
+    nd.w = d_w; nd.h = d_h; nd.g = d_g;
+  }
+  int64_t* d_acc; ALLOC(d_acc, int64_t, (size_t)2 * N * P);
+  HIPCHK(net, hipMemsetAsync(d_acc, 0, (size_t)2 * N * P * 8, s));
+  nd.acc = d_acc;
+
+  // ---- spike buffers ----
+  net->drain_steps = std::max<uint64_t>(kGraphSteps, std::min<uint64_t>(1000, ((1ull << 25) / N) / kGraphSteps * kGraphSteps));
+  net->log_cap = next_pow2((uint64_t)N * (nd.R + net->drain_steps + kGraphSteps + 1));
+  uint32_t* d_stage; ALLOC(d_stage, uint32_t, (size_t)nd.nblk_upd * kUpdBlock);
+  uint32_t* d_scnt; ALLOC(d_scnt, uint32_t, nd.nblk_upd);
+  uint32_t* d_log; ALLOC(d_log, uint32_t, net->log_cap);
+  uint64_t* d_rb; ALLOC(d_rb, uint64_t, nd.R);
+  uint32_t* d_rc; ALLOC(d_rc, uint32_t, nd.R);
+  uint64_t* d_cb; ALLOC(d_cb, uint64_t, kChunkRing);
+  HIPCHK(net, hipMemsetAsync(d_scnt, 0, nd.nblk_upd * 4, s));
+  HIPCHK(net, hipMemsetAsync(d_rb, 0, nd.R * 8, s));
+  HIPCHK(net, hipMemsetAsync(d_rc, 0, nd.R * 4, s));
+  HIPCHK(net, hipMemsetAsync(d_cb, 0, kChunkRing * 8, s));
+  nd.stage = d_stage; nd.stage_cnt = d_scnt; nd.log = d_log; nd.ring_base = d_rb; nd.ring_cnt = d_rc;
+  nd.chunk_base = d_cb; nd.log_mask = net->log_cap - 1; nd.chunk_ring = kChunkRing;
+
+  // ---- selection / delivery ----
+  uint64_t max_items = (uint64_t)N * dmax_used;
+  nd.sel_grid = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(32, std::min<uint64_t>(G / 64 + 1, 256)));
+  nd.pair_cap = max_items + nd.sel_grid;
+  ALLOC(nd.seg_off, uint64_t, nd.pair_cap);
+  ALLOC(nd.seg_len, uint32_t, nd.pair_cap);
+  ALLOC(nd.seg_mult, uint32_t, nd.pair_cap);
+  ALLOC(nd.seg_cnt, uint32_t, nd.sel_grid);
+  const uint64_t pr_cap = std::min<uint64_t>(nd.pair_cap, G) + 1;
+  ALLOC(nd.pr_off, uint64_t, pr_cap);
+  ALLOC(nd.pr_mult, uint32_t, pr_cap);
+  ALLOC(nd.pr_start, uint64_t, pr_cap + 1);
+  nd.chunk_cap = S / kDlvChunk + 2;
+  ALLOC(nd.chunk_first, uint32_t, nd.chunk_cap);
+  ALLOC(nd.blk_stats, uint64_t, (size_t)2 * nd.nblk_upd);
+  HIPCHK(net, hipMemsetAsync(nd.blk_stats, 0, (size_t)2 * nd.nblk_upd * 8, s));
+  ALLOC(nd.ctrl, Ctrl, 1);
+  HIPCHK(net, hipMemsetAsync(nd.ctrl, 0, sizeof(Ctrl), s));
+  net->dlv_grid = 1024;
+  net->pinned_words = 0;
+  HIPCHK(net, hipStreamSynchronize(s));
+#undef ALLOC
+  net->built = true;
+  net->cur_step = net->drained_step = 0;
+  st = build_graphs(net);
+  if (st) return st;
+  net->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return leave(net);
+}
+
+snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "simulate before snn_build");
+  snn_status st = enter(net);
+  if (st) return st;
+  const auto t0 = std::chrono::steady_clock::now();
+  uint64_t left = steps;
+  while (left > 0) {
+    if (left >= kGraphSteps) {
+      HIPCHK(net, hipGraphLaunch(net->graph_k, net->stream));
+      net->cur_step += kGraphSteps;
+      left -= kGraphSteps;
+    } else {
+      HIPCHK(net, hipGraphLaunch(net->graph_1, net->stream));
+      net->cur_step += 1;
+      left -= 1;
+    }
+    if (net->cur_step - net->drained_step >= net->drain_steps || left == 0) {
+      st = drain(net);
+      if (st) return st;
+    }
+  }
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  net->sim_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  Ctrl c;
+  HIPCHK(net, hipMemcpy(&c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
+  if (c.overflow) return fail(net, SNN_E_OVERFLOW, "device range check failed (flags 0x%x)", c.overflow);
+  return leave(net);
+}
+
+snn_status snn_simulate(snn_net* net, double t_ms) {
+  if (!net) return SNN_E_INVALID;
+  if (!(t_ms >= 0)) return fail(net, SNN_E_INVALID, "negative time");
+  return snn_simulate_steps(net, (uint64_t)floor(t_ms / net->cfg.dt_ms + 0.5));
+}
+
+snn_status snn_get_spikes(snn_net* net, uint64_t step_lo, uint64_t step_hi, uint64_t* step, uint32_t* gid,
+                          uint32_t* mult, size_t cap, size_t* n_out) {
+  if (!net || !n_out) return SNN_E_INVALID;
+  net->err.clear();
+  const auto lo = std::lower_bound(net->r_step.begin(), net->r_step.end(), step_lo);
+  const auto hi = std::lower_bound(net->r_step.begin(), net->r_step.end(), step_hi);
+  const size_t a = (size_t)(lo - net->r_step.begin()), b = (size_t)(hi - net->r_step.begin());
+  const size_t n = (b > a) ? b - a : 0;
+  *n_out = n;
+  const size_t m = std::min(n, cap);
+  for (size_t j = 0; j < m; ++j) {
+    if (step) step[j] = net->r_step[a + j];
+    if (gid) gid[j] = net->r_gid[a + j];
+    if (mult) mult[j] = net->r_mult[a + j];
+  }
+  return SNN_OK;
+}
+
+snn_status snn_get_counters(snn_net* net, snn_counters* out) {
+  if (!net || !out) return SNN_E_INVALID;
+  net->err.clear();
+  memset(out, 0, sizeof *out);
+  out->n_neurons = net->N;
+  out->build_ms = net->build_ms;
+  out->simulate_ms = net->sim_ms;
+  if (!net->built) return SNN_OK;
+  snn_status st = enter(net);
+  if (st) return st;
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  Ctrl c;
+  HIPCHK(net, hipMemcpy(&c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
+  std::vector<uint64_t> bs((size_t)2 * net->nd.nblk_upd);
+  HIPCHK(net, hipMemcpy(bs.data(), net->nd.blk_stats, bs.size() * 8, hipMemcpyDeviceToHost));
+  for (size_t b = 0; b < net->nd.nblk_upd; ++b) {
+    out->rk_accepted += bs[2 * b];
+    out->rk_rejected += bs[2 * b + 1];
+  }
+  out->steps = net->cur_step;
+  out->spikes = c.tot_spikes;
+  out->events = c.tot_events;
+  out->pairs = c.tot_pairs;
+  out->n_synapses = net->n_syn;
+  out->n_groups = net->n_groups;
+  out->device_bytes = net->dev_bytes;
+  out->overflow = c.overflow;
+  out->max_delay_used = net->dmax_used;
+  return leave(net);
+}
+
+snn_status snn_get_input(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int64_t* out) {
+  if (!net || !out) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "not built");
+  if ((uint64_t)first + n > net->N || port >= net->P) return fail(net, SNN_E_INVALID, "bad range");
+  snn_status st = enter(net);
+  if (st) return st;
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  const int64_t* base = net->nd.acc + (size_t)(net->cur_step & 1) * net->N * net->P;
+  HIPCHK(net, hipMemcpy2D(out, 8, base + (size_t)first * net->P + port, net->P * 8, 8, n, hipMemcpyDeviceToHost));
+  return leave(net);
+}
+
+snn_status snn_get_shift(snn_net* net, uint32_t gid, uint32_t port, int32_t* shift) {
+  if (!net || !shift) return SNN_E_INVALID;
+  if (!net->built) return fail(net, SNN_E_STATE, "not built");
+  if (gid >= net->N || port >= net->P) return fail(net, SNN_E_INVALID, "bad gid or port");
+  *shift = net->shift[(size_t)pop_of(net, gid) * net->P + port];
+  return SNN_OK;
+}
+
+snn_status snn_poisson_counts(snn_net* net, uint64_t step, uint32_t first, uint32_t n, uint32_t* k) {
+  if (!net || !k) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "not built");
+  if ((uint64_t)first + n > net->N) return fail(net, SNN_E_INVALID, "bad range");
+  snn_status st = enter(net);
+  if (st) return st;
+  uint32_t* d = dalloc<uint32_t>(net, std::max<uint32_t>(1, n));
+  if (!d) return fail(net, SNN_E_NOMEM, "allocation failed");
+  hipError_t e = launch_poisson_counts(net->nd, step, first, n, d, net->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+  if (e == hipSuccess) e = hipMemcpy(k, d, (size_t)n * 4, hipMemcpyDeviceToHost);
+  dev_free(net, d);
+  if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "poisson counts: %s", hipGetErrorString(e));
+  return leave(net);
+}
+
+snn_status snn_export_synapses(snn_net* net, uint32_t* src, uint32_t* delay, uint32_t* tgt, uint32_t* port,
+                               int64_t* wq, size_t* n_syn) {
+  if (!net || !n_syn) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "not built");
+  const size_t capn = *n_syn;
+  *n_syn = net->n_syn;
+  if (capn < net->n_syn || !src || !delay || !tgt || !port || !wq) return SNN_OK;
+  snn_status st = enter(net);
+  if (st) return st;
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  const uint32_t N = net->N;
+  std::vector<uint64_t> mask(N), goff(net->n_groups + 1);
+  std::vector<uint32_t> gp((size_t)N + 1), pay(net->n_syn);
+  HIPCHK(net, hipMemcpy(mask.data(), net->nd.src_mask, (size_t)N * 8, hipMemcpyDeviceToHost));
+  HIPCHK(net, hipMemcpy(gp.data(), net->nd.grp_ptr, ((size_t)N + 1) * 4, hipMemcpyDeviceToHost));
+  HIPCHK(net, hipMemcpy(goff.data(), net->nd.grp_off, (net->n_groups + 1) * 8, hipMemcpyDeviceToHost));
+  if (net->n_syn) HIPCHK(net, hipMemcpy(pay.data(), net->nd.payload, net->n_syn * 4, hipMemcpyDeviceToHost));
+  size_t e = 0;
+  for (uint32_t s = 0; s < N; ++s) {
+    uint64_t m = mask[s];
+    uint32_t g = gp[s];
+    for (uint32_t d = 1; d < 64; ++d) {
+      if (!((m >> d) & 1ull)) continue;
+      for (uint64_t q = goff[g]; q < goff[g + 1]; ++q, ++e) {
+        const uint32_t pl = pay[q];
+        src[e] = s; delay[e] = d; tgt[e] = pl >> kClassBits;
+        port[e] = net->cls_port[pl & (kMaxClasses - 1)];
+        wq[e] = net->cls_wq[pl & (kMaxClasses - 1)];
+      }
+      ++g;
+    }
+    if (g != gp[s + 1]) return fail(net, SNN_E_DEVICE, "group table inconsistent at source %u", s);
+  }
+  if (e != net->n_syn) return fail(net, SNN_E_DEVICE, "exported %zu of %llu synapses", e, (unsigned long long)net->n_syn);
+  return leave(net);
+}
+
+}  // extern "C"
+
+namespace {
+
+snn_status record_graph(snn_net* net, uint32_t steps, hipGraphExec_t* out) {
+  hipGraph_t g;
+  HIPCHK(net, hipStreamBeginCapture(net->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (uint32_t r = 0; r < steps && e == hipSuccess; ++r) {
+    e = launch_update(net->nd, r, net->stream);
+    if (e == hipSuccess) e = launch_select(net->nd, r, net->stream);
+    if (e == hipSuccess) e = launch_scan_pairs(net->nd, r, net->stream);
+    if (e == hipSuccess) e = launch_deliver(net->nd, r, net->dlv_grid, net->stream);
+  }
+  if (e == hipSuccess) e = launch_advance(net->nd.ctrl, steps, net->stream);
+  hipError_t e2 = hipStreamEndCapture(net->stream, &g);
+  if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "capture: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(net, SNN_E_DEVICE, "end capture: %s", hipGetErrorString(e2));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "instantiate: %s", hipGetErrorString(e));
+  return SNN_OK;
+}
+
+snn_status build_graphs(snn_net* net) {
+  snn_status st = record_graph(net, kGraphSteps, &net->graph_k);
+  if (st) return st;
+  return record_graph(net, 1, &net->graph_1);
+}
+
+// Copy the spikes of steps [drained_step, cur_step) from the device ring
+// into the host raster (sorted by gid within a step).
+snn_status drain(snn_net* net) {
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  const uint64_t a = net->drained_step, b = net->cur_step;
+  if (b <= a) return SNN_OK;
+  if (net->cfg.flags & SNN_F_NO_SPIKE_RECORD) {
+    net->drained_step = b;
+    return SNN_OK;
+  }
+  const NetDev& nd = net->nd;
+  std::vector<uint64_t> cb(kChunkRing);
+  std::vector<uint32_t> rc(nd.R);
+  HIPCHK(net, hipMemcpy(cb.data(), nd.chunk_base, kChunkRing * 8, hipMemcpyDeviceToHost));
+  HIPCHK(net, hipMemcpy(rc.data(), nd.ring_cnt, nd.R * 4, hipMemcpyDeviceToHost));
+  const uint64_t base_a = cb[a % kChunkRing];
+  const uint64_t end = cb[(b - 1) % kChunkRing] + rc[(b - 1) % nd.R];
+  const uint64_t total = end - base_a;
+  if (total > net->log_cap) return fail(net, SNN_E_OVERFLOW, "spike ring overrun");
+  std::vector<uint32_t> buf(total);
+  const uint64_t p0 = base_a & nd.log_mask;
+  const uint64_t first_part = std::min<uint64_t>(total, net->log_cap - p0);
+  if (first_part) HIPCHK(net, hipMemcpy(buf.data(), nd.log + p0, first_part * 4, hipMemcpyDeviceToHost));
+  if (total > first_part)
+    HIPCHK(net, hipMemcpy(buf.data() + first_part, nd.log, (total - first_part) * 4, hipMemcpyDeviceToHost));
+  for (uint64_t n = a; n < b; ++n) {
+    const uint64_t s0 = cb[n % kChunkRing] - base_a;
+    const uint64_t s1 = (n + 1 < b) ? cb[(n + 1) % kChunkRing] - base_a : total;
+    std::sort(buf.begin() + (long)s0, buf.begin() + (long)s1,
+              [](uint32_t x, uint32_t y) { return (x & kGidMask) < (y & kGidMask); });
+    for (uint64_t q = s0; q < s1; ++q) {
+      net->r_step.push_back(n);
+      net->r_gid.push_back(buf[q] & kGidMask);
+      net->r_mult.push_back(buf[q] >> kMultShift);
+    }
+  }
+  net->drained_step = b;
+  return SNN_OK;
+}
+
+}  // namespace

@@ -1,0 +1,106 @@
+// snn_types.h -- device-visible data layout of one network (host and device).
+//
+// HBM layout (all arrays device-resident for the life of the network):
+//   neuron state (SoA, fp32): V (LIF: V - E_L), I_e, and per model
+//     LIF-exp: I_syn[N][P];  AdEx: w, g[N][P], h;  refr (int32) for LIF.
+//   acc[2][N][P]  int64 fixed-point input, double-buffered by step parity.
+//   CSR by (source, delay group):
+//     src_mask[N]   u64, bit d set <=> source has a group with delay d steps
+//     grp_ptr[N+1]  u32, index of the source's first group
+//     grp_off[G+1]  u64, first synapse of each group (groups ordered by delay)
+//     payload[S]    u32, target << 6 | weight class (class -> port, w_q)
+//   spike buffer: stage[nblk][256] per-update-block spike lists of the
+//     current step, log[CAP] ring of compacted per-step spike lists
+//     (gid | mult << 27) with ring_base/ring_cnt per step slot (Dmax + 1).
+//   selection output: pair segments per select block, compacted pairs with
+//     exclusive event prefix, first pair of every delivery chunk.
+#pragma once
+#include <stdint.h>
+
+namespace snn {
+
+constexpr int kMaxPorts = 4;
+constexpr int kMaxClasses = 64;
+constexpr int kClassBits = 6;
+constexpr uint32_t kMaxNeurons = 1u << 26;
+constexpr int kPoisKmax = 128;
+constexpr int kMultShift = 27;
+constexpr uint32_t kGidMask = (1u << kMultShift) - 1;
+constexpr uint32_t kMaxMult = 31;
+constexpr int kUpdBlock = 256;      // neurons per update block (= stage segment)
+constexpr int kDlvChunk = 1024;     // events per delivery chunk
+constexpr int kTagConn = 1;
+constexpr int kTagPoisson = 2;
+
+enum Model : int32_t { kLifDelta = 0, kLifExp = 1, kAdex = 2 };
+
+// Parameters of one population as the kernels use them (fp32, propagators
+// precomputed in double on the host).
+struct PopDev {
+  uint32_t first, n;
+  int32_t model, n_ports;
+  // LIF exact integration
+  float P22, P20, theta, y_reset;
+  float P11[kMaxPorts], P21[kMaxPorts];
+  int32_t n_ref;
+  // AdEx
+  float inv_C, g_L, E_L, Delta_T, inv_Delta_T, V_T, inv_tau_w, a, b, V_peak, V_r;
+  float E_rev[kMaxPorts], inv_tau_syn[kMaxPorts];
+  float rk_eps, rk_hmin, dt;
+  // fixed-point input conversion: x = (float)acc * scale[port], scale = 2^-S
+  float scale[kMaxPorts];
+  // Poisson drive (index into the threshold table, -1 if none)
+  int32_t pois;
+  int32_t pois_port;
+  int64_t pois_wq;
+};
+
+struct ProjDev {
+  uint32_t src_first, src_n, tgt_first, tgt_n, K, kpairs;
+  uint32_t index;          // creation index (Philox counter word 1, bits 40+)
+  uint32_t pad;
+  uint64_t pair_begin;     // prefix of tgt_n * kpairs over projections
+  uint64_t thr[64];        // delay thresholds, thr[d] for d = 1..Dmax
+};
+
+// Scalars written by the kernels.
+struct Ctrl {
+  uint64_t step_base;      // absolute step of relative step 0 of a launch
+  uint64_t n_events;       // events of the pending delivery
+  uint32_t n_pairs;        // pairs of the pending delivery
+  uint32_t overflow;       // sticky flags (bit 0 mult, 1 rk iterations, 2 pairs)
+  uint64_t tot_events, tot_pairs, tot_spikes;
+  uint64_t sel_items;      // selection items of the current step
+  uint64_t sel_ipb;        // items per select block (segment stride of the pair segments)
+};
+
+struct NetDev {
+  uint32_t N, P, npop, dmax;   // dmax = largest delay present (ring has dmax+1 slots)
+  uint32_t R, nblk_upd, sel_grid, pad0;
+  uint64_t log_mask;           // CAP - 1
+  uint64_t chunk_ring;         // slots of chunk_base (power of two)
+  uint64_t seed;
+  uint64_t pair_cap;           // capacity of pair arrays
+  uint64_t n_groups, n_syn;
+  const PopDev* pops;
+  const uint64_t* pois_thr;    // [npois][kPoisKmax]
+  const int64_t* cls_wq;       // [kMaxClasses]
+  const uint32_t* cls_port;    // [kMaxClasses]
+  // state
+  float* V; float* Ie; float* Isyn; float* w; float* g; float* h; int32_t* refr;
+  // CSR
+  const uint64_t* src_mask; const uint32_t* grp_ptr; const uint64_t* grp_off; const uint32_t* payload;
+  int64_t* acc;
+  // spikes
+  uint32_t* stage; uint32_t* stage_cnt;
+  uint32_t* log; uint64_t* ring_base; uint32_t* ring_cnt; uint64_t* chunk_base;
+  // selection / delivery
+  uint64_t* seg_off; uint32_t* seg_len; uint32_t* seg_mult; uint32_t* seg_cnt;
+  uint64_t* pr_off; uint32_t* pr_mult; uint64_t* pr_start; uint32_t* chunk_first;
+  uint64_t chunk_cap;
+  // per-block statistics of the update kernel: [nblk_upd][2] (rk accepted, rejected)
+  uint64_t* blk_stats;
+  Ctrl* ctrl;
+};
+
+}  // namespace snn

@@ -1,0 +1,262 @@
+"""Python binding of libsnn.so (argument marshalling only).
+
+Every step of the simulation runs in the HIP kernels behind the C ABI of
+include/snn.h; this module converts a network specification dictionary (see
+workloads.py) into those calls and hands the library device memory from
+PyTorch's allocator and PyTorch's current stream.  If libsnn.so is missing it
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsnn.so")
+
+SNN_OK = 0
+ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "STATE", -4: "OVERFLOW", -5: "DEVICE", -7: "UNSUPPORTED"}
+MODELS = {"lif_delta": 0, "lif_exp": 1, "aeif_cond_exp": 2}
+PARAMS = {"tau_m": 0, "C_m": 1, "E_L": 2, "V_th": 3, "V_reset": 4, "t_ref": 5, "g_L": 6, "Delta_T": 7,
+          "V_T": 8, "tau_w": 9, "a": 10, "b": 11, "V_peak": 12, "V_r": 13, "rk_eps": 14, "rk_hmin": 15}
+PORT_PARAMS = {"tau_syn": 0, "E_rev": 1}
+STATE = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6}
+DELAYS = {"const": 0, "uniform": 1, "normal": 2}
+F_NO_SPIKE_RECORD = 1
+
+
+class SnnError(RuntimeError):
+    pass
+
+
+class Config(C.Structure):
+    _fields_ = [("dt_ms", C.c_double), ("seed", C.c_uint64), ("max_delay_steps", C.c_uint32),
+                ("flags", C.c_uint32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Device(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p), ("stream", C.c_void_p)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("steps", C.c_uint64), ("spikes", C.c_uint64), ("events", C.c_uint64), ("pairs", C.c_uint64),
+                ("rk_accepted", C.c_uint64), ("rk_rejected", C.c_uint64), ("n_neurons", C.c_uint64),
+                ("n_synapses", C.c_uint64), ("n_groups", C.c_uint64), ("device_bytes", C.c_uint64),
+                ("build_ms", C.c_double), ("simulate_ms", C.c_double), ("overflow", C.c_uint32),
+                ("max_delay_used", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# function name -> (restype, argtypes) as declared in include/snn.h
+_P = C.c_void_p
+_SIGS = {
+    "snn_create_net": (C.c_int32, [C.POINTER(Config), C.POINTER(Device), C.POINTER(C.c_void_p)]),
+    "snn_destroy_net": (None, [_P]),
+    "snn_last_error": (C.c_char_p, [_P]),
+    "snn_create": (C.c_int32, [_P, C.c_int32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
+    "snn_set_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
+    "snn_set_port_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
+    "snn_connect_fixed_indegree": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                               C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
+    "snn_poisson": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double, C.c_uint32]),
+    "snn_set_state": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_uint32, C.POINTER(C.c_double),
+                                  C.c_size_t]),
+    "snn_get_state": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_uint32, C.POINTER(C.c_double)]),
+    "snn_build": (C.c_int32, [_P]),
+    "snn_simulate": (C.c_int32, [_P, C.c_double]),
+    "snn_simulate_steps": (C.c_int32, [_P, C.c_uint64]),
+    "snn_get_spikes": (C.c_int32, [_P, C.c_uint64, C.c_uint64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
+                                   C.POINTER(C.c_uint32), C.c_size_t, C.POINTER(C.c_size_t)]),
+    "snn_get_counters": (C.c_int32, [_P, C.POINTER(Counters)]),
+    "snn_get_input": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64)]),
+    "snn_get_shift": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32)]),
+    "snn_poisson_counts": (C.c_int32, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
+    "snn_export_synapses": (C.c_int32, [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                        C.POINTER(C.c_uint32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsnn.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_14236_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+class TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator."""
+
+    def __init__(self, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.live = {}
+        self._alloc = ALLOC_FN(self._a)
+        self._free = FREE_FN(self._f)
+
+    def _a(self, nbytes, user):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _f(self, ptr, user):
+        self.live.pop(ptr, None)
+
+    def device_struct(self) -> Device:
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        return Device(self._alloc, self._free, None, s or None)
+
+
+class Net:
+    """A network on the GPU, defined from a specification dictionary."""
+
+    def __init__(self, spec: dict, allocator: TorchAllocator | None = None, record: bool = True, build: bool = True):
+        self.L = lib()
+        self.spec = spec
+        self.alloc = allocator if allocator is not None else TorchAllocator()
+        cfg = Config(spec["dt"], spec["seed"], spec["dmax"], 0 if record else F_NO_SPIKE_RECORD)
+        self._dev = self.alloc.device_struct()
+        h = C.c_void_p()
+        self._check(self.L.snn_create_net(C.byref(cfg), C.byref(self._dev), C.byref(h)), None)
+        self.h = h
+        self.ranges = {}
+        self.N = 0
+        for p in spec["populations"]:
+            first = C.c_uint32()
+            self._check(self.L.snn_create(self.h, MODELS[p["model"]], p["n"], p["ports"], C.byref(first)))
+            self.ranges[p["name"]] = (first.value, p["n"])
+            self.N += p["n"]
+            for k, v in p["params"].items():
+                if k in PARAMS:
+                    self._check(self.L.snn_set_param(self.h, first.value, p["n"], PARAMS[k], float(v)))
+                elif k in PORT_PARAMS:
+                    for port, x in enumerate(v[: p["ports"]]):
+                        self._check(self.L.snn_set_port_param(self.h, first.value, p["n"], port,
+                                                              PORT_PARAMS[k], float(x)))
+        for pr in spec["projections"]:
+            s0, sn = self.ranges[pr["src"]]
+            t0, tn = self.ranges[pr["tgt"]]
+            kind, a, b = (list(pr["delay"]) + [0.0, 0.0])[:3]
+            self._check(self.L.snn_connect_fixed_indegree(self.h, s0, sn, t0, tn, pr["K"], float(pr["weight"]),
+                                                          DELAYS[kind], float(a), float(b), pr["port"]))
+        for q in spec.get("poisson", []):
+            t0, tn = self.ranges[q["tgt"]]
+            self._check(self.L.snn_poisson(self.h, t0, tn, float(q["rate"]), int(q["n_inputs"]),
+                                           float(q["weight"]), q["port"]))
+        for p in spec["populations"]:
+            t0, tn = self.ranges[p["name"]]
+            if p.get("V0") is not None:
+                self.set_state("V_m", t0, np.asarray(p["V0"], dtype=np.float64))
+            ie = p.get("I_e", 0.0)
+            self.set_state("I_e", t0, np.atleast_1d(np.asarray(ie, dtype=np.float64)), n=tn)
+        if build:
+            self.build()
+
+    def _check(self, rc, h=-1):
+        if rc != SNN_OK:
+            hh = self.h if h == -1 else h
+            msg = self.L.snn_last_error(hh).decode() if hh else ""
+            raise SnnError(f"{ERRORS.get(rc, rc)}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.snn_destroy_net(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- calls
+    def build(self):
+        self._check(self.L.snn_build(self.h))
+
+    def simulate(self, steps: int):
+        self._check(self.L.snn_simulate_steps(self.h, int(steps)))
+
+    def simulate_ms(self, t_ms: float):
+        self._check(self.L.snn_simulate(self.h, float(t_ms)))
+
+    def set_state(self, var: str, first: int, values, port: int = 0, n: int | None = None):
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        n = len(v) if n is None else n
+        self._check(self.L.snn_set_state(self.h, first, n, STATE[var], port, _ptr(v, C.c_double), len(v)))
+
+    def get_state(self, var: str, first: int = 0, n: int | None = None, port: int = 0) -> np.ndarray:
+        n = self.N - first if n is None else n
+        out = np.zeros(n, dtype=np.float64)
+        self._check(self.L.snn_get_state(self.h, first, n, STATE[var], port, _ptr(out, C.c_double)))
+        return out
+
+    def spikes(self, step_lo: int = 0, step_hi: int = 2**63):
+        """(step, gid, mult) sorted by (step, gid)."""
+        n = C.c_size_t(0)
+        self._check(self.L.snn_get_spikes(self.h, step_lo, step_hi, None, None, None, 0, C.byref(n)))
+        m = n.value
+        st = np.zeros(m, np.uint64); gid = np.zeros(m, np.uint32); mult = np.zeros(m, np.uint32)
+        if m:
+            self._check(self.L.snn_get_spikes(self.h, step_lo, step_hi, _ptr(st, C.c_uint64), _ptr(gid, C.c_uint32),
+                                              _ptr(mult, C.c_uint32), m, C.byref(n)))
+        return st, gid, mult
+
+    def counters(self) -> dict:
+        c = Counters()
+        self._check(self.L.snn_get_counters(self.h, C.byref(c)))
+        return c.as_dict()
+
+    def get_input(self, port: int = 0, first: int = 0, n: int | None = None) -> np.ndarray:
+        n = self.N - first if n is None else n
+        out = np.zeros(n, dtype=np.int64)
+        self._check(self.L.snn_get_input(self.h, first, n, port, _ptr(out, C.c_int64)))
+        return out
+
+    def shift(self, gid: int, port: int = 0) -> int:
+        s = C.c_int32()
+        self._check(self.L.snn_get_shift(self.h, gid, port, C.byref(s)))
+        return s.value
+
+    def poisson_counts(self, step: int, first: int = 0, n: int | None = None) -> np.ndarray:
+        n = self.N - first if n is None else n
+        out = np.zeros(n, dtype=np.uint32)
+        self._check(self.L.snn_poisson_counts(self.h, step, first, n, _ptr(out, C.c_uint32)))
+        return out
+
+    def synapses(self) -> dict:
+        n = C.c_size_t(0)
+        self._check(self.L.snn_export_synapses(self.h, None, None, None, None, None, C.byref(n)))
+        m = n.value
+        src = np.zeros(m, np.uint32); d = np.zeros(m, np.uint32); tgt = np.zeros(m, np.uint32)
+        port = np.zeros(m, np.uint32); wq = np.zeros(m, np.int64)
+        n = C.c_size_t(m)
+        self._check(self.L.snn_export_synapses(self.h, _ptr(src, C.c_uint32), _ptr(d, C.c_uint32),
+                                               _ptr(tgt, C.c_uint32), _ptr(port, C.c_uint32),
+                                               _ptr(wq, C.c_int64), C.byref(n)))
+        return dict(src=src, delay=d, tgt=tgt, port=port, wq=wq)

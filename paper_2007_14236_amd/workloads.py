@@ -95,10 +95,11 @@ def c0(active: bool = False) -> dict:
 
 
 def _mc_table(seed: int = 11) -> np.ndarray:
-    """Synthetic 8x8 connection probabilities p[target, source]: 0.10 from a
-    same-layer E source, 0.12 from a same-layer I source, 0.02 from a
+    """Synthetic 8x8 connection probabilities p[target, source]: 0.08 from a
+    same-layer E source, 0.25 from a same-layer I source, 0.02 from a
     cross-layer E source, 0.01 from a cross-layer I source, each times
-    U[0.5, 1.5) (numpy Philox, key (seed, 0))."""
+    U[0.5, 1.5) (numpy Philox, key (seed, 0)).  Inhibition dominates every
+    population's input, as in layered cortical models."""
     g = np.random.Generator(np.random.Philox(key=[seed, 0]))
     mult = g.uniform(0.5, 1.5, size=(8, 8))
     p = np.zeros((8, 8))
@@ -107,7 +108,7 @@ def _mc_table(seed: int = 11) -> np.ndarray:
             same = (t // 2) == (s // 2)
             src_e = (s % 2) == 0
             if same:
-                p[t, s] = 0.10 if src_e else 0.12
+                p[t, s] = 0.08 if src_e else 0.25
             else:
                 p[t, s] = 0.02 if src_e else 0.01
     return p * mult
@@ -156,12 +157,16 @@ def microcircuit(scale: float = 1.0, k_scale: float | None = None, k_ext: int = 
 
 
 def adex_balanced(n: int = 1_000_000, k: int = 1000, seed: int = 1, dmax: int = 63,
-                  delay=("uniform", 1.0, 2.0), w_ex: float = 0.05, w_in: float = 0.35,
-                  poisson_rate: float = 20000.0, w_poisson: float = 0.37) -> dict:
-    """Balanced AdEx network (Sec. 2.4): N_in = N_ex/4, CI = CE/4, weights in
-    nS (Table 1: W_ex 0.05 on port 0 with E_rev 0 mV, W_in 0.35 on port 1 with
-    E_rev -85 mV), Poisson 20 kHz x 0.37 nS on port 0, delays U[1, 2) ms,
-    Table 2 neuron parameters, exponential conductances, RK45 tolerance 1e-6."""
+                  delay=("uniform", 1.0, 2.0), w_ex: float = 0.05 * math.e, w_in: float = 0.35 * math.e,
+                  poisson_rate: float = 20000.0, w_poisson: float = 0.37 * math.e) -> dict:
+    """Balanced AdEx network (Sec. 2.4): N_in = N_ex/4, CI = CE/4, Table 2
+    neuron parameters, Poisson 20 kHz on port 0, delays U[1, 2) ms, RK45
+    tolerance 1e-6, exponential conductances (tau 1 ms; port 0 E_rev 0 mV,
+    port 1 E_rev -85 mV).  Table 1 gives the peak conductances W_ex 0.05,
+    W_in 0.35, W_poisson 0.37 nS of the paper's alpha-shaped conductance; an
+    alpha kernel with peak w carries e w tau of charge, an exponential kernel
+    with jump w carries w tau, so the exponential weights are the Table 1
+    values times e (same charge per spike)."""
     ne = (n * 4) // 5
     ni = n - ne
     ke = (k * 4) // 5
