@@ -155,7 +155,7 @@ __device__ __forceinline__ void adex_rhs(const PopDev& pp, float Ie, const float
 
 // One dt with the Cash-Karp embedded 5(4) pair and the step-size control of
 // Press et al. (adaptive fifth-order Runge-Kutta, Sec. 2.1): relative error
-// against |y| + |h dy/dt|, shrink by 0.9 e^-1/4 (>= 0.1x) on failure, grow by
+// against |y| + |h dy/dt| + 1 (state units; a floor for variables at zero), shrink by 0.9 e^-1/4 (>= 0.1x) on failure, grow by
 // 0.9 e^-1/5 (<= 5x) on success; the last substep lands on the step end; h is
 // carried to the next step.  A reset (V >= V_peak) is applied after every
 // accepted substep.  Returns the number of resets.
@@ -211,7 +211,7 @@ __device__ uint32_t adex_step(const PopDev& pp, float* y, float& h, float Ie, ui
     for (int i = 0; i < NV; ++i) {
       y5[i] = __builtin_fmaf(h, b1 * k1[i] + b3 * k3[i] + b4 * k4[i] + b6 * k6[i], y[i]);
       const float err = h * (e1 * k1[i] + e3 * k3[i] + e4 * k4[i] + e5 * k5[i] + e6 * k6[i]);
-      const float scale = fabsf(y[i]) + fabsf(h * k1[i]) + 1e-30f;
+      const float scale = fabsf(y[i]) + fabsf(h * k1[i]) + 1.f;
       errmax = fmaxf(errmax, fabsf(err) / scale);
     }
     errmax = errmax / pp.rk_eps;

@@ -173,7 +173,7 @@ def test_adex_700pA_trajectory(snn):
     o.set_state("I_e", 0, np.array([700.0, 0.0, 300.0]))
     first_div = None
     vs_g, vs_o = [], []
-    for n in range(3000):
+    for n in range(5000):
         g.simulate(1)
         o.simulate(1)
         vs_g.append(g.get_state("V_m"))
@@ -184,21 +184,26 @@ def test_adex_700pA_trajectory(snn):
     # spike trains of the 700 pA neuron: identical until the first divergence
     a = gs[gg == 0]
     b = os_[og == 0]
-    assert len(b) >= 5
+    assert len(b) >= 4
     k = 0
     while k < min(len(a), len(b)) and a[k] == b[k]:
         k += 1
     first_div = b[k] if k < len(b) else len(vs_o)
     assert k >= 3, (a[:6], b[:6])
     upto = int(first_div)
-    rel = np.abs(vs_g[:upto, 0] - vs_o[:upto, 0]) / np.abs(vs_o[:upto, 0])
+    # away from the peaks: above V_T the upswing is explosive and a tiny time
+    # shift changes V by millivolts (the comparison with NEST in Sec. 3.2
+    # also excludes the peaks)
+    sub = vs_o[:upto, 0] < W.ADEX_T2["V_T"]
+    rel = np.abs(vs_g[:upto, 0] - vs_o[:upto, 0])[sub] / np.abs(vs_o[:upto, 0])[sub]
+    assert sub.mean() > 0.95
     assert rel.max() < 1e-4, rel.max()
     # resting and subthreshold neurons agree over the whole run
     for j in (1, 2):
         rel = np.abs(vs_g[:, j] - vs_o[:, j]) / np.abs(vs_o[:, j])
         assert rel.max() < 1e-4, (j, rel.max())
     c = g.counters()
-    assert c["rk_accepted"] > 3 * 3000 * 0.9 and c["overflow"] == 0
+    assert c["rk_accepted"] > 3 * 5000 * 0.9 and c["overflow"] == 0
 
 
 def test_adex_three_ports_subthreshold(snn):
