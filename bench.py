@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark: full-scale cortical-microcircuit stand-in on one MI355X.
+
+One step = one simulation time step of dt = 0.1 ms through the whole hot path
+(Poisson drive, LIF exact update, spike staging, selection of matured
+(source, delay-group) pairs, flat scan of their synapses, fixed-point
+accumulation).  Default: 1,000 warm-up steps, then 100,000 timed steps
+(10 s of biological time).  Inputs (network, state) are resident in HBM before
+the timed region starts.
+
+Prints ONE JSON line.  `value` is synaptic events/s (synapse deliveries per
+wall-clock second over the timed steps); the real-time factor is reported
+beside it.  The `roofline` object covers the dominant kernel (delivery) with
+per-launch durations measured by HIP events inside this run; `cpu_baseline`
+times the CPU oracle on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 100000] [--warmup 1000]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "real-time factor & synaptic events/s on 1 GPU; batched p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of the delivery kernel: per delivered synapse one 4-byte
+# synapse word read and one int64 accumulator read-modify-write (16 B); per
+# selected (source, group) pair one 16-byte record read (offset, size, mult).
+DLV_BYTES_PER_EVENT = 4 + 16
+DLV_BYTES_PER_PAIR = 16
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100_000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--profile-steps", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=10_000)
+    ap.add_argument("--k-ext", type=int, default=None)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a device copy of this many MiB (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def cpu_baseline(steps: int) -> dict:
+    """Oracle (plain C, fp64, one thread) on the microcircuit stand-in at N/10
+    with the full in-degrees and drive: same per-neuron input statistics and
+    rates as the full network, one tenth of the neurons and synapses."""
+    from oracle import oracle as O
+    from paper_2007_14236_amd import workloads as W
+    spec = W.microcircuit(scale=0.1, k_scale=1.0)
+    t0 = time.perf_counter()
+    net = O.OracleNet(spec, O.FP64)
+    t_build = time.perf_counter() - t0
+    net.simulate(1000)
+    e0 = net.events
+    t0 = time.perf_counter()
+    net.simulate(steps)
+    wall = time.perf_counter() - t0
+    ev = net.events - e0
+    bio = steps * spec["dt"] * 1e-3
+    return {"value": ev / wall, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": (f"microcircuit stand-in at N/10 with full in-degrees ({net.N} neurons, "
+                       f"{W.count_synapses(spec):.3g} synapses), fp64 oracle, {steps} steps "
+                       f"({bio:g} s bio) after 1000 warm-up steps, one thread; build ({t_build:.1f} s) excluded"),
+            "rtf": wall / bio, "host": platform.processor() or platform.machine(),
+            "host_cpus": os.cpu_count()}
+
+
+def copy_calibration(mib: int):
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": mib << 20}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    from paper_2007_14236_amd import snn as S
+    from paper_2007_14236_amd import workloads as W
+
+    kw = {} if args.k_ext is None else {"k_ext": args.k_ext}
+    spec = W.microcircuit(scale=1.0, **kw)
+    dt = spec["dt"]
+    print(f"[bench] building {spec['name']}: {W.total_neurons(spec)} neurons, "
+          f"{W.count_synapses(spec):.4g} synapses", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    net = S.Net(spec)
+    build_s = time.perf_counter() - t0
+    net.simulate(args.warmup)
+    torch.cuda.synchronize()
+    c0 = net.counters()
+    print(f"[bench] warm-up {args.warmup} steps done; timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.simulate(args.steps)  # returns after the device has finished
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c1 = net.counters()
+    events = c1["events"] - c0["events"]
+    pairs = c1["pairs"] - c0["pairs"]
+    spikes = c1["spikes"] - c0["spikes"]
+    bio_s = args.steps * dt * 1e-3
+    ms_per_step = wall * 1e3 / args.steps
+    print(f"[bench] {args.steps} steps in {wall:.3f} s (RTF {wall / bio_s:.4f}); profiling "
+          f"{args.profile_steps} steps", file=sys.stderr, flush=True)
+
+    # per-kernel device time with HIP events on the library's stream
+    c2 = net.counters()
+    prof = net.profile(args.profile_steps)
+    c3 = net.counters()
+    ps = max(1, args.profile_steps)
+    ev_p = (c3["events"] - c2["events"]) / ps
+    pr_p = (c3["pairs"] - c2["pairs"]) / ps
+    dlv_ms = prof["deliver"] / ps
+    dominant = max(prof, key=prof.get)
+    dlv_bytes = ev_p * DLV_BYTES_PER_EVENT + pr_p * DLV_BYTES_PER_PAIR
+    achieved = dlv_bytes / (dlv_ms * 1e-3) / 1e9 if dlv_ms > 0 else 0.0
+    roofline = {
+        "kernel": "k_deliver", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+        "avg_launch_us": round(dlv_ms * 1e3, 3), "bytes_per_launch": round(dlv_bytes),
+        "events_per_launch": round(ev_p, 1), "pairs_per_launch": round(pr_p, 1),
+        "atomics_per_s": round(ev_p / (dlv_ms * 1e-3), 1) if dlv_ms > 0 else None,
+        "kernel_us_per_step": {k: round(v * 1e3 / ps, 3) for k, v in prof.items()},
+        "dominant_kernel_by_time": dominant,
+    }
+    out = {
+        "metric": METRIC,
+        "value": events / wall,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state, i64 fixed-point input",
+        "data": "synthetic",
+        "rtf": wall / bio_s,
+        "bio_seconds": bio_s,
+        "build_s": build_s,
+        "spikes_per_s_bio": spikes / bio_s,
+        "mean_rate_hz": spikes / bio_s / W.total_neurons(spec),
+        "events_per_step": events / args.steps,
+        "pairs_per_step": pairs / args.steps,
+        "config": {"workload": "cortical microcircuit stand-in: 8 LIF-exp populations, 77,169 neurons, 3.0e8 synapses",
+                   "neurons": W.total_neurons(spec), "synapses": W.count_synapses(spec),
+                   "populations": dict(zip(W.MC_NAMES, W.MC_SIZES)), "dt_ms": dt,
+                   "t_bio_s": bio_s, "k_ext": spec["poisson"][0]["n_inputs"],
+                   "parallelism": "single GPU"},
+        "paper_context": {"rtf_rtx2080ti": 1.055, "rtf_v100": 1.641,
+                          "note": "real microcircuit (this is a synthetic stand-in of the same size)"},
+        "roofline": roofline,
+    }
+    net.close()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,6 +77,8 @@ def lib():
         L.orc_simulate.argtypes = [C.c_void_p, C.c_uint64]
         L.orc_current_step.restype = C.c_uint64
         L.orc_current_step.argtypes = [C.c_void_p]
+        L.orc_n_events.restype = C.c_uint64
+        L.orc_n_events.argtypes = [C.c_void_p]
         L.orc_n_spikes.restype = C.c_uint64
         L.orc_n_spikes.argtypes = [C.c_void_p]
         L.orc_get_spikes.argtypes = [C.c_void_p, P64, P32, P32]
@@ -252,6 +254,10 @@ class OracleNet:
     @property
     def step(self) -> int:
         return int(self.L.orc_current_step(self.h))
+
+    @property
+    def events(self) -> int:
+        return int(self.L.orc_n_events(self.h))
 
     def spikes(self):
         """(step, gid, mult) arrays sorted by (step, gid)."""

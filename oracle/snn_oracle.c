@@ -184,6 +184,7 @@ struct orc_net {
   int64_t* rec; uint64_t rec_max;
   /* counters */
   uint64_t rk_acc, rk_rej;
+  uint64_t n_events;        /* synapse deliveries (group sizes summed) */
 };
 
 static void set_err(orc_net* o, const char* m) { snprintf(o->err, sizeof o->err, "%s", m); }
@@ -799,6 +800,7 @@ int orc_simulate(orc_net* o, uint64_t steps) {
         uint32_t s = o->spk_gid[q];
         int64_t m = (int64_t)o->spk_mult[q];
         uint64_t b = o->off[(size_t)s * D1 + d], e = o->off[(size_t)s * D1 + d + 1];
+        o->n_events += e - b;
         for (uint64_t r = b; r < e; ++r) {
           const orc_syn* sy = &o->syn[r];
           o->acc[(size_t)sy->tgt * P + sy->port] += m * sy->wq;
@@ -811,6 +813,7 @@ int orc_simulate(orc_net* o, uint64_t steps) {
 }
 
 uint64_t orc_current_step(const orc_net* o) { return o->step; }
+uint64_t orc_n_events(const orc_net* o) { return o->n_events; }
 uint64_t orc_n_spikes(const orc_net* o) { return o->n_spk; }
 
 void orc_get_spikes(const orc_net* o, uint64_t* step, uint32_t* gid, uint32_t* mult) {

@@ -77,6 +77,8 @@ int      orc_get_state(orc_net*, uint32_t first, uint32_t n, int var, uint32_t p
 int      orc_build(orc_net*);
 int      orc_simulate(orc_net*, uint64_t steps);
 uint64_t orc_current_step(const orc_net*);
+/* synapse deliveries so far (sum of the sizes of the delivered groups) */
+uint64_t orc_n_events(const orc_net*);
 
 /* spikes recorded so far, sorted by (step, gid) */
 uint64_t orc_n_spikes(const orc_net*);

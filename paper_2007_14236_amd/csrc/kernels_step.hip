@@ -12,10 +12,9 @@
 //                 found by a popcount of the lower bits, so no loop over the
 //                 groups is needed -- the role of the ordered group index of
 //                 Fig. 1).
-//   3. scan     : exclusive scan of the selected groups' sizes: one flat index
-//                 space over all synapses to deliver, plus the first pair of
-//                 every fixed-size chunk of it.
-//   4. deliver  : chunks of that index space are scanned in parallel; each
+//   3. deliver  : every select block's list of selected groups is scanned in
+//                 LDS (exclusive prefix of the group sizes) into one flat index
+//                 space over their synapses, which several blocks share; each
 //                 synapse adds multiplicity x quantised weight to the int64
 //                 input of its (target, port) for step n+1 (integer atomics:
 //                 the sum does not depend on their order).
@@ -27,8 +26,7 @@ namespace snn {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kScanThreads = 1024;
-constexpr int kScanItems = 4;
+constexpr int kDlvPerThread = kDlvTile / kB;
 constexpr uint32_t kRkMaxIter = 100000;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -320,7 +318,8 @@ __global__ void __launch_bounds__(kB) k_update(NetDev nd, uint32_t rel) {
 }
 
 // ------------------------------------------------------------------ select
-__device__ __forceinline__ void probe(const NetDev& nd, uint32_t entry, uint32_t d, uint32_t* lcnt, uint64_t seg_base) {
+__device__ __forceinline__ void probe(const NetDev& nd, uint32_t entry, uint32_t d, uint32_t* lcnt,
+                                      unsigned long long* levents, uint64_t seg_base) {
   const uint32_t s = entry & kGidMask;
   if (s >= nd.N) {  // never true for entries written by this pipeline
     atomicOr(&nd.ctrl->overflow, 4u);
@@ -337,6 +336,7 @@ __device__ __forceinline__ void probe(const NetDev& nd, uint32_t entry, uint32_t
       atomicOr(&nd.ctrl->overflow, 4u);
       return;
     }
+    atomicAdd(levents, (unsigned long long)len);
     nd.seg_off[q] = off;
     nd.seg_len[q] = len;
     nd.seg_mult[q] = entry >> kMultShift;
@@ -348,6 +348,7 @@ __global__ void __launch_bounds__(kB) k_select(NetDev nd, uint32_t rel) {
   __shared__ uint64_t seg[66];
   __shared__ uint64_t sbase[66];
   __shared__ uint32_t lcnt;
+  __shared__ unsigned long long levents;
   const uint64_t n = nd.ctrl->step_base + rel;
   const uint32_t R = nd.R, dmax = nd.dmax;
   // |S_n|: spikes staged by the update blocks of step n
@@ -364,7 +365,7 @@ __global__ void __launch_bounds__(kB) k_select(NetDev nd, uint32_t rel) {
     seg[d] = incl - cnt;  // start of delay d's items
     if (d == 64) seg[65] = incl;
     sbase[d] = b;
-    if (threadIdx.x == 0) lcnt = 0;
+    if (threadIdx.x == 0) { lcnt = 0; levents = 0; }
   }
   __syncthreads();
   const uint64_t items = seg[65];
@@ -396,7 +397,7 @@ __global__ void __launch_bounds__(kB) k_select(NetDev nd, uint32_t rel) {
       for (uint64_t e = lo; e < hi; ++e) {
         const uint32_t entry = nd.stage[(size_t)ub * kB + (e - p_ub)];
         nd.log[(base_n + e) & nd.log_mask] = entry;
-        probe(nd, entry, 1, &lcnt, seg_base);
+        probe(nd, entry, 1, &lcnt, &levents, seg_base);
       }
       run += tsum;
     }
@@ -407,106 +408,64 @@ __global__ void __launch_bounds__(kB) k_select(NetDev nd, uint32_t rel) {
     uint32_t d = 2;
     while (d < 64 && seg[d + 1] <= e) ++d;
     const uint32_t entry = nd.log[(sbase[d] + (e - seg[d])) & nd.log_mask];
-    probe(nd, entry, d, &lcnt, seg_base);
+    probe(nd, entry, d, &lcnt, &levents, seg_base);
   }
   __syncthreads();
-  if (threadIdx.x == 0) nd.seg_cnt[blockIdx.x] = lcnt;
-}
-
-// --------------------------------------------------------------- scan pairs
-__global__ void __launch_bounds__(kScanThreads) k_scan_pairs(NetDev nd) {
-  __shared__ uint64_t red[kScanThreads / 64];
-  __shared__ uint64_t segpre[1025];
-  const uint32_t G = nd.sel_grid;
-  const uint64_t ipb = nd.ctrl->sel_ipb;
-  {
-    const uint64_t c = (threadIdx.x < G) ? nd.seg_cnt[threadIdx.x] : 0;
-    uint64_t tot;
-    const uint64_t ex = block_excl_scan(c, red, &tot);
-    if (threadIdx.x < G) segpre[threadIdx.x] = ex;
-    if (threadIdx.x == 0) segpre[G] = tot;
-    __syncthreads();
-  }
-  const uint64_t A = segpre[G];
-  uint64_t run = 0;
-  constexpr uint64_t tile = (uint64_t)kScanThreads * kScanItems;
-  for (uint64_t t0 = 0; t0 < A; t0 += tile) {
-    uint64_t off[kScanItems];
-    uint32_t len[kScanItems], mul[kScanItems];
-    uint64_t sum = 0;
-#pragma unroll
-    for (int q = 0; q < kScanItems; ++q) {
-      const uint64_t gi = t0 + (uint64_t)threadIdx.x * kScanItems + q;
-      len[q] = 0; off[q] = 0; mul[q] = 0;
-      if (gi < A) {
-        uint32_t lo = 0, hi = G;  // segment b: segpre[b] <= gi < segpre[b+1]
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (segpre[mid] <= gi) lo = mid; else hi = mid;
-        }
-        const uint64_t src = lo * ipb + (gi - segpre[lo]);
-        off[q] = nd.seg_off[src];
-        len[q] = nd.seg_len[src];
-        mul[q] = nd.seg_mult[src];
-      }
-      sum += len[q];
-    }
-    uint64_t tsum;
-    uint64_t start = run + block_excl_scan(sum, red, &tsum);
-#pragma unroll
-    for (int q = 0; q < kScanItems; ++q) {
-      const uint64_t gi = t0 + (uint64_t)threadIdx.x * kScanItems + q;
-      if (gi < A && gi < nd.n_groups && len[q] > 0) {
-        nd.pr_off[gi] = off[q];
-        nd.pr_mult[gi] = mul[q];
-        nd.pr_start[gi] = start;
-        // chunks whose first event lies in this pair
-        const uint64_t c0 = (start + kDlvChunk - 1) / kDlvChunk;
-        const uint64_t c1 = (start + len[q] - 1) / kDlvChunk;
-        for (uint64_t cc = c0; cc <= c1; ++cc) nd.chunk_first[cc] = (uint32_t)gi;
-      }
-      start += len[q];
-    }
-    run += tsum;
-  }
   if (threadIdx.x == 0) {
-    nd.pr_start[A] = run;
-    nd.ctrl->n_pairs = (uint32_t)A;
-    nd.ctrl->n_events = run;
-    nd.ctrl->tot_events += run;
-    nd.ctrl->tot_pairs += A;
+    nd.seg_cnt[blockIdx.x] = lcnt;
+    nd.sel_stats[2 * blockIdx.x] += lcnt;
+    nd.sel_stats[2 * blockIdx.x + 1] += levents;
   }
 }
 
 // ------------------------------------------------------------------ deliver
+// Block (b, j) of the grid sel_grid x dlv_sub: segment b of the selection, the
+// j-th of dlv_sub equal shares of its events.  Pairs are staged in LDS in
+// tiles of kDlvTile with their exclusive event prefix; each event finds its
+// pair by binary search and reads one synapse word, so consecutive lanes read
+// consecutive synapses of a group (coalesced).
 __global__ void __launch_bounds__(kB) k_deliver(NetDev nd, uint32_t rel) {
-  __shared__ uint64_t st[kDlvChunk + 1];
-  __shared__ uint64_t so[kDlvChunk + 1];
-  __shared__ uint32_t sm[kDlvChunk + 1];
+  __shared__ uint64_t st[kDlvTile];
+  __shared__ uint64_t so[kDlvTile];
+  __shared__ uint32_t sm[kDlvTile];
   __shared__ int64_t wq[kMaxClasses];
   __shared__ uint32_t wp[kMaxClasses];
+  __shared__ uint64_t red[kB / 64];
   const uint64_t n = nd.ctrl->step_base + rel;
-  const uint64_t E = nd.ctrl->n_events;
-  const uint32_t A = nd.ctrl->n_pairs;
+  const uint32_t sub = nd.dlv_sub;
+  const uint32_t b = blockIdx.x / sub, j = blockIdx.x - b * sub;
   if (threadIdx.x < kMaxClasses) { wq[threadIdx.x] = nd.cls_wq[threadIdx.x]; wp[threadIdx.x] = nd.cls_port[threadIdx.x]; }
+  const uint64_t base = (uint64_t)b * nd.ctrl->sel_ipb;
+  uint32_t A = nd.seg_cnt[b];
+  if (base + A > nd.pair_cap) A = (base < nd.pair_cap) ? (uint32_t)(nd.pair_cap - base) : 0u;  // flagged by select
   int64_t* acc = nd.acc + (size_t)((n + 1) & 1) * nd.N * nd.P;
   const uint32_t P = nd.P;
-  const uint64_t nchunks = (E + kDlvChunk - 1) / kDlvChunk;
-  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const uint64_t e0 = c * kDlvChunk;
-    const uint64_t e1 = (e0 + kDlvChunk < E) ? e0 + kDlvChunk : E;
-    const uint32_t p0 = nd.chunk_first[c];
-    const uint32_t p1 = (c + 1 < nchunks) ? nd.chunk_first[c + 1] : A - 1;
-    const uint32_t np = p1 - p0 + 1;
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < np; j += kB) {
-      st[j] = nd.pr_start[p0 + j];
-      so[j] = nd.pr_off[p0 + j];
-      sm[j] = nd.pr_mult[p0 + j];
+  for (uint32_t t0 = 0; t0 < A; t0 += kDlvTile) {
+    const uint32_t np = (A - t0 < (uint32_t)kDlvTile) ? A - t0 : (uint32_t)kDlvTile;
+    uint32_t L[kDlvPerThread];
+    uint64_t lsum = 0;
+#pragma unroll
+    for (int q = 0; q < kDlvPerThread; ++q) {
+      const uint32_t i = threadIdx.x * kDlvPerThread + q;
+      L[q] = (i < np) ? nd.seg_len[base + t0 + i] : 0u;
+      lsum += L[q];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl_scan(lsum, red, &tot);
+#pragma unroll
+    for (int q = 0; q < kDlvPerThread; ++q) {
+      const uint32_t i = threadIdx.x * kDlvPerThread + q;
+      if (i < np) {
+        st[i] = run;
+        so[i] = nd.seg_off[base + t0 + i];
+        sm[i] = nd.seg_mult[base + t0 + i];
+      }
+      run += L[q];
     }
     __syncthreads();
-    for (uint64_t e = e0 + threadIdx.x; e < e1; e += kB) {
-      uint32_t lo = 0, hi = np;  // last j with st[j] <= e
+    const uint64_t e_lo = tot * j / sub, e_hi = tot * (j + 1) / sub;
+    for (uint64_t e = e_lo + threadIdx.x; e < e_hi; e += kB) {
+      uint32_t lo = 0, hi = np;  // last pair with st <= e
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (st[mid] <= e) lo = mid; else hi = mid;
@@ -517,6 +476,7 @@ __global__ void __launch_bounds__(kB) k_deliver(NetDev nd, uint32_t rel) {
       __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> kClassBits) * P + wp[cls]],
                              (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();
   }
 }
 
@@ -561,14 +521,8 @@ hipError_t launch_select(const NetDev& nd, uint32_t rel, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan_pairs(const NetDev& nd, uint32_t rel, hipStream_t s) {
-  (void)rel;
-  hipLaunchKernelGGL(k_scan_pairs, dim3(1), dim3(kScanThreads), 0, s, nd);
-  return hipGetLastError();
-}
-
-hipError_t launch_deliver(const NetDev& nd, uint32_t rel, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_deliver, dim3(grid), dim3(kB), 0, s, nd, rel);
+hipError_t launch_deliver(const NetDev& nd, uint32_t rel, hipStream_t s) {
+  hipLaunchKernelGGL(k_deliver, dim3(nd.sel_grid * nd.dlv_sub), dim3(kB), 0, s, nd, rel);
   return hipGetLastError();
 }
 

@@ -3,7 +3,7 @@
 // Owns the network description, the host-side tables the kernels read
 // (propagators, fixed-point exponents, weight classes, delay and Poisson
 // thresholds), device memory, the build sequence and the step loop (hipGraph
-// of K steps of update -> select -> scan -> deliver, replayed; the spike
+// of K steps of update -> select -> deliver, replayed; the spike
 // ring is drained to the host raster between replays).
 #include <hip/hip_runtime.h>
 
@@ -147,7 +147,6 @@ struct snn_net {
   uint64_t cur_step = 0, drained_step = 0;
   uint64_t log_cap = 0;
   uint64_t drain_steps = 0;
-  uint32_t dlv_grid = 1024;
   hipGraphExec_t graph_k = nullptr, graph_1 = nullptr;
   uint64_t* pinned = nullptr;
   size_t pinned_words = 0;
@@ -859,17 +858,13 @@ snn_status snn_build(snn_net* net) {
   ALLOC(nd.seg_len, uint32_t, nd.pair_cap);
   ALLOC(nd.seg_mult, uint32_t, nd.pair_cap);
   ALLOC(nd.seg_cnt, uint32_t, nd.sel_grid);
-  const uint64_t pr_cap = std::min<uint64_t>(nd.pair_cap, G) + 1;
-  ALLOC(nd.pr_off, uint64_t, pr_cap);
-  ALLOC(nd.pr_mult, uint32_t, pr_cap);
-  ALLOC(nd.pr_start, uint64_t, pr_cap + 1);
-  nd.chunk_cap = S / kDlvChunk + 2;
-  ALLOC(nd.chunk_first, uint32_t, nd.chunk_cap);
+  ALLOC(nd.sel_stats, uint64_t, (size_t)2 * nd.sel_grid);
+  HIPCHK(net, hipMemsetAsync(nd.sel_stats, 0, (size_t)2 * nd.sel_grid * 8, s));
+  nd.dlv_sub = 4;
   ALLOC(nd.blk_stats, uint64_t, (size_t)2 * nd.nblk_upd);
   HIPCHK(net, hipMemsetAsync(nd.blk_stats, 0, (size_t)2 * nd.nblk_upd * 8, s));
   ALLOC(nd.ctrl, Ctrl, 1);
   HIPCHK(net, hipMemsetAsync(nd.ctrl, 0, sizeof(Ctrl), s));
-  net->dlv_grid = 1024;
   net->pinned_words = 0;
   HIPCHK(net, hipStreamSynchronize(s));
 #undef ALLOC
@@ -912,6 +907,41 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
   return leave(net);
 }
 
+snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms) {
+  if (!net || !kernel_ms) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "profile before snn_build");
+  snn_status st = enter(net);
+  if (st) return st;
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIPCHK(net, hipEventCreate(&e));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t k = 0; k < steps; ++k) {
+    HIPCHK(net, hipEventRecord(ev[0], net->stream));
+    HIPCHK(net, launch_update(net->nd, 0, net->stream));
+    HIPCHK(net, hipEventRecord(ev[1], net->stream));
+    HIPCHK(net, launch_select(net->nd, 0, net->stream));
+    HIPCHK(net, hipEventRecord(ev[2], net->stream));
+    HIPCHK(net, launch_deliver(net->nd, 0, net->stream));
+    HIPCHK(net, hipEventRecord(ev[3], net->stream));
+    HIPCHK(net, launch_advance(net->nd.ctrl, 1, net->stream));
+    HIPCHK(net, hipEventSynchronize(ev[3]));
+    for (int q = 0; q < 3; ++q) {
+      float ms = 0.f;
+      HIPCHK(net, hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
+      kernel_ms[q] += ms;
+    }
+    net->cur_step += 1;
+    if (net->cur_step - net->drained_step >= net->drain_steps || k + 1 == steps) {
+      st = drain(net);
+      if (st) return st;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  net->sim_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return leave(net);
+}
+
 snn_status snn_simulate(snn_net* net, double t_ms) {
   if (!net) return SNN_E_INVALID;
   if (!(t_ms >= 0)) return fail(net, SNN_E_INVALID, "negative time");
@@ -949,6 +979,12 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   HIPCHK(net, hipStreamSynchronize(net->stream));
   Ctrl c;
   HIPCHK(net, hipMemcpy(&c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
+  std::vector<uint64_t> ss((size_t)2 * net->nd.sel_grid);
+  HIPCHK(net, hipMemcpy(ss.data(), net->nd.sel_stats, ss.size() * 8, hipMemcpyDeviceToHost));
+  for (size_t b = 0; b < net->nd.sel_grid; ++b) {
+    out->pairs += ss[2 * b];
+    out->events += ss[2 * b + 1];
+  }
   std::vector<uint64_t> bs((size_t)2 * net->nd.nblk_upd);
   HIPCHK(net, hipMemcpy(bs.data(), net->nd.blk_stats, bs.size() * 8, hipMemcpyDeviceToHost));
   for (size_t b = 0; b < net->nd.nblk_upd; ++b) {
@@ -957,8 +993,6 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   }
   out->steps = net->cur_step;
   out->spikes = c.tot_spikes;
-  out->events = c.tot_events;
-  out->pairs = c.tot_pairs;
   out->n_synapses = net->n_syn;
   out->n_groups = net->n_groups;
   out->device_bytes = net->dev_bytes;
@@ -1054,8 +1088,7 @@ snn_status record_graph(snn_net* net, uint32_t steps, hipGraphExec_t* out) {
   for (uint32_t r = 0; r < steps && e == hipSuccess; ++r) {
     e = launch_update(net->nd, r, net->stream);
     if (e == hipSuccess) e = launch_select(net->nd, r, net->stream);
-    if (e == hipSuccess) e = launch_scan_pairs(net->nd, r, net->stream);
-    if (e == hipSuccess) e = launch_deliver(net->nd, r, net->dlv_grid, net->stream);
+    if (e == hipSuccess) e = launch_deliver(net->nd, r, net->stream);
   }
   if (e == hipSuccess) e = launch_advance(net->nd.ctrl, steps, net->stream);
   hipError_t e2 = hipStreamEndCapture(net->stream, &g);

@@ -12,8 +12,8 @@
 //   spike buffer: stage[nblk][256] per-update-block spike lists of the
 //     current step, log[CAP] ring of compacted per-step spike lists
 //     (gid | mult << 27) with ring_base/ring_cnt per step slot (Dmax + 1).
-//   selection output: pair segments per select block, compacted pairs with
-//     exclusive event prefix, first pair of every delivery chunk.
+//   selection output: one segment of (synapse offset, size, multiplicity)
+//     records per select block; delivery scans each segment in LDS.
 #pragma once
 #include <stdint.h>
 
@@ -28,7 +28,7 @@ constexpr int kMultShift = 27;
 constexpr uint32_t kGidMask = (1u << kMultShift) - 1;
 constexpr uint32_t kMaxMult = 31;
 constexpr int kUpdBlock = 256;      // neurons per update block (= stage segment)
-constexpr int kDlvChunk = 1024;     // events per delivery chunk
+constexpr int kDlvTile = 2048;      // pairs staged in LDS per delivery tile
 constexpr int kTagConn = 1;
 constexpr int kTagPoisson = 2;
 
@@ -66,10 +66,9 @@ struct ProjDev {
 // Scalars written by the kernels.
 struct Ctrl {
   uint64_t step_base;      // absolute step of relative step 0 of a launch
-  uint64_t n_events;       // events of the pending delivery
-  uint32_t n_pairs;        // pairs of the pending delivery
-  uint32_t overflow;       // sticky flags (bit 0 mult, 1 rk iterations, 2 pairs)
-  uint64_t tot_events, tot_pairs, tot_spikes;
+  uint32_t overflow;       // sticky flags (bit 0 mult, 1 rk iterations, 2 ranges)
+  uint32_t pad;
+  uint64_t tot_spikes;
   uint64_t sel_items;      // selection items of the current step
   uint64_t sel_ipb;        // items per select block (segment stride of the pair segments)
 };
@@ -96,8 +95,8 @@ struct NetDev {
   uint32_t* log; uint64_t* ring_base; uint32_t* ring_cnt; uint64_t* chunk_base;
   // selection / delivery
   uint64_t* seg_off; uint32_t* seg_len; uint32_t* seg_mult; uint32_t* seg_cnt;
-  uint64_t* pr_off; uint32_t* pr_mult; uint64_t* pr_start; uint32_t* chunk_first;
-  uint64_t chunk_cap;
+  uint64_t* sel_stats;         // [sel_grid][2]: pairs and events selected (cumulative)
+  uint32_t dlv_sub, pad1;      // delivery blocks per select segment
   // per-block statistics of the update kernel: [nblk_upd][2] (rk accepted, rejected)
   uint64_t* blk_stats;
   Ctrl* ctrl;

@@ -79,6 +79,7 @@ _SIGS = {
     "snn_get_input": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64)]),
     "snn_get_shift": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32)]),
     "snn_poisson_counts": (C.c_int32, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
+    "snn_profile_steps": (C.c_int32, [_P, C.c_uint64, C.POINTER(C.c_double)]),
     "snn_export_synapses": (C.c_int32, [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                         C.POINTER(C.c_uint32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
 }
@@ -90,6 +91,10 @@ def lib():
     """Load libsnn.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch's HIP runtime (and the HSA runtime it loads) must be in the
+        # process before libsnn.so resolves libhsa-runtime64.so.1, so that one
+        # HSA runtime serves both the library and torch's allocator
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_14236_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -204,6 +209,12 @@ class Net:
 
     def simulate_ms(self, t_ms: float):
         self._check(self.L.snn_simulate(self.h, float(t_ms)))
+
+    def profile(self, steps: int) -> dict:
+        """Advance `steps` steps with per-kernel HIP event timing (ms summed)."""
+        ms = np.zeros(3, dtype=np.float64)
+        self._check(self.L.snn_profile_steps(self.h, int(steps), _ptr(ms, C.c_double)))
+        return dict(update=ms[0], select=ms[1], deliver=ms[2])
 
     def set_state(self, var: str, first: int, values, port: int = 0, n: int | None = None):
         v = np.ascontiguousarray(values, dtype=np.float64)

@@ -94,29 +94,34 @@ def c0(active: bool = False) -> dict:
     return brunel_lif(nu_ext=250.0 if active else 20.0)
 
 
-def _mc_table(seed: int = 11) -> np.ndarray:
-    """Synthetic 8x8 connection probabilities p[target, source]: 0.08 from a
-    same-layer E source, 0.25 from a same-layer I source, 0.02 from a
-    cross-layer E source, 0.01 from a cross-layer I source, each times
-    U[0.5, 1.5) (numpy Philox, key (seed, 0)).  Inhibition dominates every
-    population's input, as in layered cortical models."""
+MC_TABLE = (0.08, 0.16, 0.25, 0.25, 0.02, 0.01)
+
+
+def _mc_table(seed: int = 11, base=MC_TABLE) -> np.ndarray:
+    """Synthetic 8x8 connection probabilities p[target, source] from the base
+    values (same-layer E->E, E->I, I->E, I->I, cross-layer from E, cross-layer
+    from I), each times U[0.5, 1.5) (numpy Philox, key (seed, 0)).
+    Inhibition dominates every population's input and inhibitory populations
+    receive more excitation than excitatory ones, as in layered cortical
+    models."""
+    ee, ei, ie, ii, xe, xi = base
     g = np.random.Generator(np.random.Philox(key=[seed, 0]))
     mult = g.uniform(0.5, 1.5, size=(8, 8))
     p = np.zeros((8, 8))
     for t in range(8):
         for s in range(8):
             same = (t // 2) == (s // 2)
-            src_e = (s % 2) == 0
+            src_e, tgt_e = (s % 2) == 0, (t % 2) == 0
             if same:
-                p[t, s] = 0.08 if src_e else 0.25
+                p[t, s] = (ee if tgt_e else ei) if src_e else (ie if tgt_e else ii)
             else:
-                p[t, s] = 0.02 if src_e else 0.01
+                p[t, s] = xe if src_e else xi
     return p * mult
 
 
-def microcircuit(scale: float = 1.0, k_scale: float | None = None, k_ext: int = 1200,
+def microcircuit(scale: float = 1.0, k_scale: float | None = None, k_ext: int = 2800,
                  nu_bg: float = 8.0, seed: int = 1, total_synapses: float = 3.0e8,
-                 dmax: int = 63) -> dict:
+                 dmax: int = 63, table=MC_TABLE) -> dict:
     """Microcircuit stand-in: LIF neurons with exponential PSCs (one port,
     signed weights), tau_m 10 ms, C_m 250 pF, tau_syn 0.5 ms, E_L = V_reset =
     -65 mV, V_th -50 mV, t_ref 2 ms; w_E 87.8 pA (L4E->L2/3E doubled), w_I =
@@ -126,7 +131,7 @@ def microcircuit(scale: float = 1.0, k_scale: float | None = None, k_ext: int = 
     `scale`, i.e. fixed connection probabilities)."""
     if k_scale is None:
         k_scale = scale
-    p = _mc_table()
+    p = _mc_table(base=table)
     n_full = np.array(MC_SIZES, dtype=np.float64)
     # global factor so that sum_ij p_ij N_i N_j = total_synapses at full scale
     p = p * (total_synapses / float(np.sum(p * np.outer(n_full, n_full))))
