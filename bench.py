@@ -30,11 +30,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "real-time factor & synaptic events/s on 1 GPU; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the delivery kernel: per delivered synapse one 4-byte
-# synapse word read and one int64 accumulator read-modify-write (16 B); per
-# selected (source, group) pair one 16-byte record read (offset, size, mult).
+# Algorithmic bytes of the select+deliver kernel: per delivered synapse one
+# 4-byte synapse word read and one int64 accumulator read-modify-write
+# (16 B); per selected (source, group) pair the 8-byte delay mask, 4-byte
+# group index and two 8-byte group offsets (28 B, rounded to 16 + 8 + 4).
 DLV_BYTES_PER_EVENT = 4 + 16
-DLV_BYTES_PER_PAIR = 16
+DLV_BYTES_PER_PAIR = 28
 
 
 def parse():
@@ -136,12 +137,12 @@ def main():
     ps = max(1, args.profile_steps)
     ev_p = (c3["events"] - c2["events"]) / ps
     pr_p = (c3["pairs"] - c2["pairs"]) / ps
-    dlv_ms = prof["deliver"] / ps
+    dlv_ms = prof["select_deliver"] / ps
     dominant = max(prof, key=prof.get)
     dlv_bytes = ev_p * DLV_BYTES_PER_EVENT + pr_p * DLV_BYTES_PER_PAIR
     achieved = dlv_bytes / (dlv_ms * 1e-3) / 1e9 if dlv_ms > 0 else 0.0
     roofline = {
-        "kernel": "k_deliver", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "kernel": "k_select_deliver", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
         "avg_launch_us": round(dlv_ms * 1e3, 3), "bytes_per_launch": round(dlv_bytes),
         "events_per_launch": round(ev_p, 1), "pairs_per_launch": round(pr_p, 1),

@@ -29,8 +29,7 @@ hipError_t launch_segsort(const uint64_t* grp_off, uint64_t n_groups, uint32_t* 
 
 // ---- per-step pipeline (step = ctrl->step_base + rel) ----
 hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s);
-hipError_t launch_select(const NetDev& nd, uint32_t rel, hipStream_t s);
-hipError_t launch_deliver(const NetDev& nd, uint32_t rel, hipStream_t s);
+hipError_t launch_select_deliver(const NetDev& nd, uint32_t rel, hipStream_t s);
 hipError_t launch_advance(Ctrl* ctrl, uint32_t steps, hipStream_t s);
 // model-specific update launchers (internal)
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,

@@ -5,19 +5,17 @@
 //                 (plus its Poisson count) into fp32, advances its dynamics
 //                 over dt and, if it fires, is appended to the block's spike
 //                 list (wave ballot + lane prefix + block prefix, gid order).
-//   2. select   : compacts the block lists of step n into the spike ring and
-//                 selects every (source, delay group) pair whose delay d has
-//                 just elapsed: spikes of step n+1-d whose source has a group
-//                 of delay d (bit d of the source's delay mask; the group is
-//                 found by a popcount of the lower bits, so no loop over the
+//   2. select + deliver: compacts the block lists of step n into the spike
+//                 ring and selects every (source, delay group) pair whose delay
+//                 d has just elapsed: spikes of step n+1-d whose source has a
+//                 group of delay d (bit d of the source's delay mask; the group
+//                 is found by a popcount of the lower bits, so no loop over the
 //                 groups is needed -- the role of the ordered group index of
-//                 Fig. 1).
-//   3. deliver  : every select block's list of selected groups is scanned in
-//                 LDS (exclusive prefix of the group sizes) into one flat index
-//                 space over their synapses, which several blocks share; each
-//                 synapse adds multiplicity x quantised weight to the int64
-//                 input of its (target, port) for step n+1 (integer atomics:
-//                 the sum does not depend on their order).
+//                 Fig. 1).  The selected groups are scanned in LDS into one
+//                 flat index space over their synapses; each synapse adds
+//                 multiplicity x quantised weight to the int64 input of its
+//                 (target, port) for step n+1 (integer atomics: the sum does
+//                 not depend on their order).
 #include "kernels.h"
 #include "philox_dev.h"
 
@@ -26,7 +24,6 @@ namespace snn {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kDlvPerThread = kDlvTile / kB;
 constexpr uint32_t kRkMaxIter = 100000;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -232,17 +229,28 @@ __device__ uint32_t adex_step(const PopDev& pp, float* y, float& h, float Ie, ui
   return mult;
 }
 
+constexpr uint32_t kPopLds = 16;  // population tables up to this size are read from LDS
+
 template <bool kLif, bool kAdexOn, int P>
 __global__ void __launch_bounds__(kB) k_update(NetDev nd, uint32_t rel) {
   __shared__ uint32_t wcnt[kB / 64];
+  __shared__ PopDev spops[kPopLds];
   const uint64_t n = nd.ctrl->step_base + rel;
   const uint32_t i = blockIdx.x * kB + threadIdx.x;
+  const bool lds_pops = nd.npop <= kPopLds;
+  if (lds_pops) {
+    const uint32_t words = nd.npop * (uint32_t)(sizeof(PopDev) / 4);
+    for (uint32_t w = threadIdx.x; w < words; w += kB)
+      reinterpret_cast<uint32_t*>(spops)[w] = reinterpret_cast<const uint32_t*>(nd.pops)[w];
+  }
+  __syncthreads();
+  const PopDev* pops = lds_pops ? spops : nd.pops;
   bool spk = false;
   uint32_t entry = 0;
   uint32_t nacc = 0, nrej = 0;
   bool capped = false, mover = false;
   if (i < nd.N) {
-    const PopDev& pp = nd.pops[find_pop(nd.pops, nd.npop, i)];
+    const PopDev& pp = pops[find_pop(pops, nd.npop, i)];
     int64_t* acc = nd.acc + ((size_t)(n & 1) * nd.N + i) * nd.P;
     int64_t a[kMaxPorts];
 #pragma unroll
@@ -318,54 +326,48 @@ __global__ void __launch_bounds__(kB) k_update(NetDev nd, uint32_t rel) {
 }
 
 // ------------------------------------------------------------------ select
-__device__ __forceinline__ void probe(const NetDev& nd, uint32_t entry, uint32_t d, uint32_t* lcnt,
-                                      unsigned long long* levents, uint64_t seg_base) {
-  const uint32_t s = entry & kGidMask;
-  if (s >= nd.N) {  // never true for entries written by this pipeline
-    atomicOr(&nd.ctrl->overflow, 4u);
-    return;
-  }
-  const uint64_t mask = nd.src_mask[s];
-  if ((mask >> d) & 1ull) {
-    const uint32_t g = nd.grp_ptr[s] + (uint32_t)__popcll(mask & ((1ull << d) - 1ull));
-    const uint64_t off = nd.grp_off[g];
-    const uint32_t len = (uint32_t)(nd.grp_off[g + 1] - off);
-    const uint32_t k = atomicAdd(lcnt, 1u);  // LDS counter
-    const uint64_t q = seg_base + k;
-    if (q >= nd.pair_cap) {
-      atomicOr(&nd.ctrl->overflow, 4u);
-      return;
-    }
-    atomicAdd(levents, (unsigned long long)len);
-    nd.seg_off[q] = off;
-    nd.seg_len[q] = len;
-    nd.seg_mult[q] = entry >> kMultShift;
-  }
-}
+// ----------------------------------------------------------- select+deliver
+// Block b owns the item range [i0, i1) of step n's selection items: first the
+// spikes of step n (delay 1, read from the update blocks' lists and copied into
+// the spike ring by the block that owns them), then those of steps n-1 ..
+// n+1-Dmax (delays 2..Dmax, read from the ring).  Items are taken in chunks of
+// kSelChunk: every item whose source has a group of the item's delay yields
+// one (synapse offset, group size, multiplicity) record in LDS; the chunk's
+// records are scanned in LDS (exclusive prefix of the sizes) and their
+// synapses delivered in one flat pass by the whole block, so consecutive
+// lanes read consecutive synapses of a group.  Integer atomics make the result
+// independent of the order in which blocks and lanes deliver.
+constexpr int kSelChunk = 1024;
+constexpr int kSelPerThread = kSelChunk / kB;
 
-__global__ void __launch_bounds__(kB) k_select(NetDev nd, uint32_t rel) {
+__global__ void __launch_bounds__(kB) k_select_deliver(NetDev nd, uint32_t rel) {
   __shared__ uint64_t red[kB / 64];
   __shared__ uint64_t seg[66];
   __shared__ uint64_t sbase[66];
-  __shared__ uint32_t lcnt;
-  __shared__ unsigned long long levents;
+  __shared__ uint64_t p_off[kSelChunk];
+  __shared__ uint64_t p_st[kSelChunk];
+  __shared__ uint32_t p_len[kSelChunk];
+  __shared__ uint32_t p_mult[kSelChunk];
+  __shared__ int64_t wq[kMaxClasses];
+  __shared__ uint32_t wp[kMaxClasses];
+  __shared__ uint32_t npair;
   const uint64_t n = nd.ctrl->step_base + rel;
   const uint32_t R = nd.R, dmax = nd.dmax;
+  if (threadIdx.x < kMaxClasses) { wq[threadIdx.x] = nd.cls_wq[threadIdx.x]; wp[threadIdx.x] = nd.cls_port[threadIdx.x]; }
   // |S_n|: spikes staged by the update blocks of step n
   uint64_t c = 0;
   for (uint32_t ub = threadIdx.x; ub < nd.nblk_upd; ub += kB) c += nd.stage_cnt[ub];
   const uint64_t tot = block_sum(c, red);
   const uint64_t base_n = (n == 0) ? 0 : nd.ring_base[(n - 1) % R] + nd.ring_cnt[(n - 1) % R];
   if (threadIdx.x < 64) {
-    const uint32_t d = threadIdx.x + 1;  // delay of this segment
-    uint64_t cnt = 0, b = 0;
-    if (d == 1) { cnt = tot; b = base_n; }
-    else if (d <= dmax && n + 1 >= d) { cnt = nd.ring_cnt[(n + 1 - d) % R]; b = nd.ring_base[(n + 1 - d) % R]; }
+    const uint32_t d = threadIdx.x + 1;  // delay of this item segment
+    uint64_t cnt = 0, bb = 0;
+    if (d == 1) { cnt = tot; bb = base_n; }
+    else if (d <= dmax && n + 1 >= d) { cnt = nd.ring_cnt[(n + 1 - d) % R]; bb = nd.ring_base[(n + 1 - d) % R]; }
     const uint64_t incl = wave_incl_scan(cnt);
-    seg[d] = incl - cnt;  // start of delay d's items
+    seg[d] = incl - cnt;
     if (d == 64) seg[65] = incl;
-    sbase[d] = b;
-    if (threadIdx.x == 0) { lcnt = 0; levents = 0; }
+    sbase[d] = bb;
   }
   __syncthreads();
   const uint64_t items = seg[65];
@@ -373,17 +375,13 @@ __global__ void __launch_bounds__(kB) k_select(NetDev nd, uint32_t rel) {
   const uint64_t ipb = (items + G - 1) / G;
   const uint64_t i0 = blockIdx.x * ipb;
   const uint64_t i1 = (i0 + ipb < items) ? i0 + ipb : items;
-  const uint64_t seg_base = blockIdx.x * ipb;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     nd.ring_base[n % R] = base_n;
     nd.ring_cnt[n % R] = (uint32_t)tot;
     nd.chunk_base[n & (nd.chunk_ring - 1)] = base_n;
-    nd.ctrl->sel_items = items;
-    nd.ctrl->sel_ipb = ipb;
     nd.ctrl->tot_spikes += tot;
   }
-  // delay 1: the spikes of step n, read from the block lists; they are also
-  // copied into the ring at base_n + (rank in step n)
+  // copy this block's share of step n's spikes into the ring (gid order)
   const uint64_t e1 = (i1 < tot) ? i1 : tot;
   if (i0 < e1) {
     uint64_t run = 0;
@@ -392,91 +390,81 @@ __global__ void __launch_bounds__(kB) k_select(NetDev nd, uint32_t rel) {
       const uint32_t cc = (ub < nd.nblk_upd) ? nd.stage_cnt[ub] : 0;
       uint64_t tsum;
       const uint64_t p_ub = run + block_excl_scan(cc, red, &tsum);
-      uint64_t lo = p_ub > i0 ? p_ub : i0;
+      const uint64_t lo = p_ub > i0 ? p_ub : i0;
       const uint64_t hi = (p_ub + cc < e1) ? p_ub + cc : e1;
-      for (uint64_t e = lo; e < hi; ++e) {
-        const uint32_t entry = nd.stage[(size_t)ub * kB + (e - p_ub)];
-        nd.log[(base_n + e) & nd.log_mask] = entry;
-        probe(nd, entry, 1, &lcnt, &levents, seg_base);
-      }
+      for (uint64_t e = lo; e < hi; ++e) nd.log[(base_n + e) & nd.log_mask] = nd.stage[(size_t)ub * kB + (e - p_ub)];
       run += tsum;
     }
   }
-  // delays 2..dmax: spikes of earlier steps from the ring
-  const uint64_t s0 = (i0 > tot) ? i0 : tot;
-  for (uint64_t e = s0 + threadIdx.x; e < i1; e += kB) {
-    uint32_t d = 2;
-    while (d < 64 && seg[d + 1] <= e) ++d;
-    const uint32_t entry = nd.log[(sbase[d] + (e - seg[d])) & nd.log_mask];
-    probe(nd, entry, d, &lcnt, &levents, seg_base);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    nd.seg_cnt[blockIdx.x] = lcnt;
-    nd.sel_stats[2 * blockIdx.x] += lcnt;
-    nd.sel_stats[2 * blockIdx.x + 1] += levents;
-  }
-}
-
-// ------------------------------------------------------------------ deliver
-// Block (b, j) of the grid sel_grid x dlv_sub: segment b of the selection, the
-// j-th of dlv_sub equal shares of its events.  Pairs are staged in LDS in
-// tiles of kDlvTile with their exclusive event prefix; each event finds its
-// pair by binary search and reads one synapse word, so consecutive lanes read
-// consecutive synapses of a group (coalesced).
-__global__ void __launch_bounds__(kB) k_deliver(NetDev nd, uint32_t rel) {
-  __shared__ uint64_t st[kDlvTile];
-  __shared__ uint64_t so[kDlvTile];
-  __shared__ uint32_t sm[kDlvTile];
-  __shared__ int64_t wq[kMaxClasses];
-  __shared__ uint32_t wp[kMaxClasses];
-  __shared__ uint64_t red[kB / 64];
-  const uint64_t n = nd.ctrl->step_base + rel;
-  const uint32_t sub = nd.dlv_sub;
-  const uint32_t b = blockIdx.x / sub, j = blockIdx.x - b * sub;
-  if (threadIdx.x < kMaxClasses) { wq[threadIdx.x] = nd.cls_wq[threadIdx.x]; wp[threadIdx.x] = nd.cls_port[threadIdx.x]; }
-  const uint64_t base = (uint64_t)b * nd.ctrl->sel_ipb;
-  uint32_t A = nd.seg_cnt[b];
-  if (base + A > nd.pair_cap) A = (base < nd.pair_cap) ? (uint32_t)(nd.pair_cap - base) : 0u;  // flagged by select
+  __syncthreads();  // the block reads back only the ring entries it wrote itself
   int64_t* acc = nd.acc + (size_t)((n + 1) & 1) * nd.N * nd.P;
   const uint32_t P = nd.P;
-  for (uint32_t t0 = 0; t0 < A; t0 += kDlvTile) {
-    const uint32_t np = (A - t0 < (uint32_t)kDlvTile) ? A - t0 : (uint32_t)kDlvTile;
-    uint32_t L[kDlvPerThread];
+  uint64_t blk_pairs = 0, blk_events = 0;
+  for (uint64_t c0 = i0; c0 < i1; c0 += kSelChunk) {  // block-uniform
+    if (threadIdx.x == 0) npair = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kSelPerThread; ++q) {
+      const uint64_t e = c0 + (uint64_t)q * kB + threadIdx.x;
+      if (e >= i1) continue;
+      uint32_t d = 1;
+      while (d < 64 && seg[d + 1] <= e) ++d;
+      const uint32_t entry = nd.log[(sbase[d] + (e - seg[d])) & nd.log_mask];
+      const uint32_t src = entry & kGidMask;
+      if (src >= nd.N) {  // never true for entries written by this pipeline
+        atomicOr(&nd.ctrl->overflow, 4u);
+        continue;
+      }
+      const uint64_t mask = nd.src_mask[src];
+      if ((mask >> d) & 1ull) {
+        const uint32_t g = nd.grp_ptr[src] + (uint32_t)__popcll(mask & ((1ull << d) - 1ull));
+        const uint64_t off = nd.grp_off[g];
+        const uint32_t len = (uint32_t)(nd.grp_off[g + 1] - off);
+        const uint32_t k = atomicAdd(&npair, 1u);  // LDS counter, k < kSelChunk
+        p_off[k] = off;
+        p_len[k] = len;
+        p_mult[k] = entry >> kMultShift;
+      }
+    }
+    __syncthreads();
+    const uint32_t np = npair;
+    // exclusive prefix of the group sizes (each thread owns kSelPerThread records)
+    uint32_t L[kSelPerThread];
     uint64_t lsum = 0;
 #pragma unroll
-    for (int q = 0; q < kDlvPerThread; ++q) {
-      const uint32_t i = threadIdx.x * kDlvPerThread + q;
-      L[q] = (i < np) ? nd.seg_len[base + t0 + i] : 0u;
+    for (int q = 0; q < kSelPerThread; ++q) {
+      const uint32_t i = threadIdx.x * kSelPerThread + q;
+      L[q] = (i < np) ? p_len[i] : 0u;
       lsum += L[q];
     }
-    uint64_t tot;
-    uint64_t run = block_excl_scan(lsum, red, &tot);
+    uint64_t ev;
+    uint64_t run = block_excl_scan(lsum, red, &ev);
 #pragma unroll
-    for (int q = 0; q < kDlvPerThread; ++q) {
-      const uint32_t i = threadIdx.x * kDlvPerThread + q;
-      if (i < np) {
-        st[i] = run;
-        so[i] = nd.seg_off[base + t0 + i];
-        sm[i] = nd.seg_mult[base + t0 + i];
-      }
+    for (int q = 0; q < kSelPerThread; ++q) {
+      const uint32_t i = threadIdx.x * kSelPerThread + q;
+      if (i < np) p_st[i] = run;
       run += L[q];
     }
     __syncthreads();
-    const uint64_t e_lo = tot * j / sub, e_hi = tot * (j + 1) / sub;
-    for (uint64_t e = e_lo + threadIdx.x; e < e_hi; e += kB) {
-      uint32_t lo = 0, hi = np;  // last pair with st <= e
+    for (uint64_t e = threadIdx.x; e < ev; e += kB) {
+      uint32_t lo = 0, hi = np;  // last record with p_st <= e
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (st[mid] <= e) lo = mid; else hi = mid;
+        if (p_st[mid] <= e) lo = mid; else hi = mid;
       }
-      const uint32_t pl = nd.payload[so[lo] + (e - st[lo])];
+      const uint32_t pl = nd.payload[p_off[lo] + (e - p_st[lo])];
       const uint32_t cls = pl & (kMaxClasses - 1);
-      const int64_t v = wq[cls] * (int64_t)sm[lo];
+      const int64_t v = wq[cls] * (int64_t)p_mult[lo];
       __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> kClassBits) * P + wp[cls]],
                              (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    blk_pairs += np;
+    blk_events += ev;
     __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    nd.sel_stats[2 * blockIdx.x] += blk_pairs;
+    nd.sel_stats[2 * blockIdx.x + 1] += blk_events;
   }
 }
 
@@ -516,13 +504,8 @@ hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_select(const NetDev& nd, uint32_t rel, hipStream_t s) {
-  hipLaunchKernelGGL(k_select, dim3(nd.sel_grid), dim3(kB), 0, s, nd, rel);
-  return hipGetLastError();
-}
-
-hipError_t launch_deliver(const NetDev& nd, uint32_t rel, hipStream_t s) {
-  hipLaunchKernelGGL(k_deliver, dim3(nd.sel_grid * nd.dlv_sub), dim3(kB), 0, s, nd, rel);
+hipError_t launch_select_deliver(const NetDev& nd, uint32_t rel, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_deliver, dim3(nd.sel_grid), dim3(kB), 0, s, nd, rel);
   return hipGetLastError();
 }
 

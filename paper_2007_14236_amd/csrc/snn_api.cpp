@@ -3,7 +3,7 @@
 // Owns the network description, the host-side tables the kernels read
 // (propagators, fixed-point exponents, weight classes, delay and Poisson
 // thresholds), device memory, the build sequence and the step loop (hipGraph
-// of K steps of update -> select -> deliver, replayed; the spike
+// of K steps of update -> select+deliver, replayed; the spike
 // ring is drained to the host raster between replays).
 #include <hip/hip_runtime.h>
 
@@ -851,16 +851,9 @@ snn_status snn_build(snn_net* net) {
   nd.chunk_base = d_cb; nd.log_mask = net->log_cap - 1; nd.chunk_ring = kChunkRing;
 
   // ---- selection / delivery ----
-  uint64_t max_items = (uint64_t)N * dmax_used;
-  nd.sel_grid = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(32, std::min<uint64_t>(G / 64 + 1, 256)));
-  nd.pair_cap = max_items + nd.sel_grid;
-  ALLOC(nd.seg_off, uint64_t, nd.pair_cap);
-  ALLOC(nd.seg_len, uint32_t, nd.pair_cap);
-  ALLOC(nd.seg_mult, uint32_t, nd.pair_cap);
-  ALLOC(nd.seg_cnt, uint32_t, nd.sel_grid);
+  nd.sel_grid = std::min<uint32_t>(2048, std::max<uint32_t>(64, nd.nblk_upd));
   ALLOC(nd.sel_stats, uint64_t, (size_t)2 * nd.sel_grid);
   HIPCHK(net, hipMemsetAsync(nd.sel_stats, 0, (size_t)2 * nd.sel_grid * 8, s));
-  nd.dlv_sub = 4;
   ALLOC(nd.blk_stats, uint64_t, (size_t)2 * nd.nblk_upd);
   HIPCHK(net, hipMemsetAsync(nd.blk_stats, 0, (size_t)2 * nd.nblk_upd * 8, s));
   ALLOC(nd.ctrl, Ctrl, 1);
@@ -913,20 +906,18 @@ snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms) {
   if (!net->built) return fail(net, SNN_E_STATE, "profile before snn_build");
   snn_status st = enter(net);
   if (st) return st;
-  hipEvent_t ev[4];
+  hipEvent_t ev[3];
   for (auto& e : ev) HIPCHK(net, hipEventCreate(&e));
   const auto t0 = std::chrono::steady_clock::now();
   for (uint64_t k = 0; k < steps; ++k) {
     HIPCHK(net, hipEventRecord(ev[0], net->stream));
     HIPCHK(net, launch_update(net->nd, 0, net->stream));
     HIPCHK(net, hipEventRecord(ev[1], net->stream));
-    HIPCHK(net, launch_select(net->nd, 0, net->stream));
+    HIPCHK(net, launch_select_deliver(net->nd, 0, net->stream));
     HIPCHK(net, hipEventRecord(ev[2], net->stream));
-    HIPCHK(net, launch_deliver(net->nd, 0, net->stream));
-    HIPCHK(net, hipEventRecord(ev[3], net->stream));
     HIPCHK(net, launch_advance(net->nd.ctrl, 1, net->stream));
-    HIPCHK(net, hipEventSynchronize(ev[3]));
-    for (int q = 0; q < 3; ++q) {
+    HIPCHK(net, hipEventSynchronize(ev[2]));
+    for (int q = 0; q < 2; ++q) {
       float ms = 0.f;
       HIPCHK(net, hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
       kernel_ms[q] += ms;
@@ -1087,8 +1078,7 @@ snn_status record_graph(snn_net* net, uint32_t steps, hipGraphExec_t* out) {
   hipError_t e = hipSuccess;
   for (uint32_t r = 0; r < steps && e == hipSuccess; ++r) {
     e = launch_update(net->nd, r, net->stream);
-    if (e == hipSuccess) e = launch_select(net->nd, r, net->stream);
-    if (e == hipSuccess) e = launch_deliver(net->nd, r, net->stream);
+    if (e == hipSuccess) e = launch_select_deliver(net->nd, r, net->stream);
   }
   if (e == hipSuccess) e = launch_advance(net->nd.ctrl, steps, net->stream);
   hipError_t e2 = hipStreamEndCapture(net->stream, &g);

@@ -12,8 +12,8 @@
 //   spike buffer: stage[nblk][256] per-update-block spike lists of the
 //     current step, log[CAP] ring of compacted per-step spike lists
 //     (gid | mult << 27) with ring_base/ring_cnt per step slot (Dmax + 1).
-//   selection output: one segment of (synapse offset, size, multiplicity)
-//     records per select block; delivery scans each segment in LDS.
+//   selection and delivery keep the selected (synapse offset, group size,
+//     multiplicity) records in LDS only.
 #pragma once
 #include <stdint.h>
 
@@ -28,7 +28,6 @@ constexpr int kMultShift = 27;
 constexpr uint32_t kGidMask = (1u << kMultShift) - 1;
 constexpr uint32_t kMaxMult = 31;
 constexpr int kUpdBlock = 256;      // neurons per update block (= stage segment)
-constexpr int kDlvTile = 2048;      // pairs staged in LDS per delivery tile
 constexpr int kTagConn = 1;
 constexpr int kTagPoisson = 2;
 
@@ -55,6 +54,8 @@ struct PopDev {
   int64_t pois_wq;
 };
 
+static_assert(sizeof(PopDev) % 8 == 0, "PopDev is copied to LDS in 32-bit words");
+
 struct ProjDev {
   uint32_t src_first, src_n, tgt_first, tgt_n, K, kpairs;
   uint32_t index;          // creation index (Philox counter word 1, bits 40+)
@@ -69,8 +70,6 @@ struct Ctrl {
   uint32_t overflow;       // sticky flags (bit 0 mult, 1 rk iterations, 2 ranges)
   uint32_t pad;
   uint64_t tot_spikes;
-  uint64_t sel_items;      // selection items of the current step
-  uint64_t sel_ipb;        // items per select block (segment stride of the pair segments)
 };
 
 struct NetDev {
@@ -79,7 +78,6 @@ struct NetDev {
   uint64_t log_mask;           // CAP - 1
   uint64_t chunk_ring;         // slots of chunk_base (power of two)
   uint64_t seed;
-  uint64_t pair_cap;           // capacity of pair arrays
   uint64_t n_groups, n_syn;
   const PopDev* pops;
   const uint64_t* pois_thr;    // [npois][kPoisKmax]
@@ -94,9 +92,7 @@ struct NetDev {
   uint32_t* stage; uint32_t* stage_cnt;
   uint32_t* log; uint64_t* ring_base; uint32_t* ring_cnt; uint64_t* chunk_base;
   // selection / delivery
-  uint64_t* seg_off; uint32_t* seg_len; uint32_t* seg_mult; uint32_t* seg_cnt;
   uint64_t* sel_stats;         // [sel_grid][2]: pairs and events selected (cumulative)
-  uint32_t dlv_sub, pad1;      // delivery blocks per select segment
   // per-block statistics of the update kernel: [nblk_upd][2] (rk accepted, rejected)
   uint64_t* blk_stats;
   Ctrl* ctrl;
