@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10_000)
     ap.add_argument("--k-ext", type=int, default=None)
+    ap.add_argument("--workload", choices=["microcircuit", "adex", "sweep"], default="microcircuit",
+                    help="microcircuit (default line); adex: 1e6 AdEx neurons, in-degree 1000; "
+                         "sweep: batched Brunel instances vs the same instances run one by one")
+    ap.add_argument("--instances", type=int, default=128, help="sweep: number of instances")
+    ap.add_argument("--seq-instances", type=int, default=16,
+                    help="sweep: instances also run one by one (sequential baseline sample)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -104,8 +110,13 @@ def main():
     from paper_2007_14236_amd import snn as S
     from paper_2007_14236_amd import workloads as W
 
-    kw = {} if args.k_ext is None else {"k_ext": args.k_ext}
-    spec = W.microcircuit(scale=1.0, **kw)
+    if args.workload == "sweep":
+        return bench_sweep(args, S, W, torch)
+    if args.workload == "adex":
+        spec = W.adex_balanced()
+    else:
+        kw = {} if args.k_ext is None else {"k_ext": args.k_ext}
+        spec = W.microcircuit(scale=1.0, **kw)
     dt = spec["dt"]
     print(f"[bench] building {spec['name']}: {W.total_neurons(spec)} neurons, "
           f"{W.count_synapses(spec):.4g} synapses", file=sys.stderr, flush=True)
@@ -179,10 +190,69 @@ def main():
                           "note": "real microcircuit (this is a synthetic stand-in of the same size)"},
         "roofline": roofline,
     }
+    if args.workload == "adex":
+        out["config"] = {"workload": "balanced AdEx network: 1,000,000 neurons (800k E / 200k I), in-degree 1000, "
+                                     "exponential conductances on 2 ports, RK45 rtol 1e-6, delays U[1,2) ms",
+                         "neurons": W.total_neurons(spec), "synapses": W.count_synapses(spec), "dt_ms": dt,
+                         "t_bio_s": bio_s, "parallelism": "single GPU"}
+        out["paper_context"] = {"rtf_rtx2080ti": 70.0, "note": "alpha conductances in the paper"}
+        out["rk45"] = {"accepted_per_step": (c1["rk_accepted"] - c0["rk_accepted"]) / args.steps,
+                       "rejected_per_step": (c1["rk_rejected"] - c0["rk_rejected"]) / args.steps}
     net.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "microcircuit":
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args, S, W, torch):
+    """Batched sweep: all instances in one network (one set of launches per
+    step) against the same instances simulated one after another."""
+    specs = [W.brunel_sweep_instance(i) for i in range(args.instances)]
+    steps = args.steps
+    t0 = time.perf_counter()
+    net = S.Net(specs, record=True)
+    build_s = time.perf_counter() - t0
+    net.simulate(args.warmup)
+    torch.cuda.synchronize()
+    c0 = net.counters()
+    t0 = time.perf_counter()
+    net.simulate(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c1 = net.counters()
+    events = c1["events"] - c0["events"]
+    net.close()
+    del net
+    # sequential baseline: a sample of the instances, one at a time, same steps
+    nseq = min(args.seq_instances, args.instances)
+    seq_wall, seq_events = 0.0, 0
+    for i in range(nseq):
+        n1 = S.Net(specs[i], record=True)
+        n1.simulate(args.warmup)
+        torch.cuda.synchronize()
+        e0 = n1.counters()["events"]
+        t0 = time.perf_counter()
+        n1.simulate(steps)
+        torch.cuda.synchronize()
+        seq_wall += time.perf_counter() - t0
+        seq_events += n1.counters()["events"] - e0
+        n1.close()
+    bio = steps * specs[0]["dt"] * 1e-3
+    sizes = [W.total_neurons(sp) for sp in specs]
+    seq_est = seq_wall * args.instances / nseq
+    out = {"metric": METRIC, "value": events / wall, "unit": "events/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 state, i64 fixed-point input", "data": "synthetic",
+           "rtf": wall / bio, "build_s": build_s,
+           "batched_instance_seconds_per_wall_second": args.instances * bio / wall,
+           "sequential_sample": {"instances": nseq, "wall_s": seq_wall, "events_per_s": seq_events / seq_wall,
+                                 "estimated_wall_all_s": seq_est},
+           "speedup_vs_sequential": seq_est / wall,
+           "config": {"workload": f"batched sweep of {args.instances} Brunel LIF instances, N in [2k, 40k], "
+                                  "in-degree 0.1 N, g in [3,7], drive 10-30 Hz, delays U[0.1,3) ms",
+                      "neurons": sum(sizes), "synapses": sum(W.count_synapses(sp) for sp in specs),
+                      "t_bio_s": bio, "parallelism": "single GPU"}}
     print(json.dumps(out), flush=True)
 
 

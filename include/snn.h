@@ -139,6 +139,16 @@ void snn_destroy_net(snn_net* net);
 const char* snn_last_error(const snn_net* net);
 
 /* ---- definition phase (before snn_build) --------------------------------- */
+/* Start a new independent network inside this one (a batch member; the net
+   created by snn_create_net is instance 0 with the config seed).  Populations,
+   connections and drives created until the next call belong to the new
+   instance; connections must stay inside one instance.  Its randomness is
+   keyed by `seed` with gids and projection indices counted from the instance's
+   own first neuron and first projection, so it draws exactly what a network
+   built alone with that seed draws and its results are the same alone and in
+   the batch.  All instances share dt, Dmax and the step counter and advance in
+   the same kernels.  Called before any population, it sets instance 0's seed. */
+snn_status snn_begin_instance(snn_net* net, uint64_t seed, uint32_t* instance_id);
 /* Create n neurons of `model` with n_ports receptor ports (1..4; LIF delta: 1)
    and NEST-like default parameters.  *first_gid receives the first gid. */
 snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports, uint32_t* first_gid);
@@ -178,7 +188,8 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
 /* Freeze the network: draw the connectivity on the device and lay it out by
    (source, delay group) with a per-source delay bitmask; allocate state,
    spike buffers and input accumulators.  Returns SNN_E_UNSUPPORTED for more
-   than 64 distinct (port, weight) classes or more than 2^26 neurons. */
+   distinct (port, weight) classes than fit next to the target index in 32
+   bits (at most 1024). */
 snn_status snn_build(snn_net* net);
 /* Advance by round(t_ms / dt) steps (resumable: later calls continue). */
 snn_status snn_simulate(snn_net* net, double t_ms);

@@ -9,11 +9,11 @@ namespace snn {
 
 // ---- connectivity build ----
 // total_pairs = sum over projections of tgt_n * ceil(K / 2)
-hipError_t launch_gen_count(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint64_t seed,
-                            uint32_t dmax_cfg, uint32_t D1, uint32_t* cnt, hipStream_t s);
-hipError_t launch_gen_scatter(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint64_t seed,
-                              uint32_t dmax_cfg, uint32_t D1, uint64_t* cursor, uint32_t* payload,
-                              const uint8_t* cls_of, const uint32_t* pop_first, uint32_t npop, hipStream_t s);
+hipError_t launch_gen_count(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint32_t dmax_cfg,
+                            uint32_t D1, uint32_t* cnt, hipStream_t s);
+hipError_t launch_gen_scatter(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint32_t dmax_cfg,
+                              uint32_t D1, uint64_t* cursor, uint32_t* payload, const uint16_t* cls_of,
+                              const uint32_t* pop_first, uint32_t npop, uint32_t cls_bits, hipStream_t s);
 // exclusive scan of n u32 (in32) or u64 (in64) values into out; *total_dev receives the sum.
 // tmp must hold scan_tmp_words(n) u64 words.
 size_t scan_tmp_words(uint64_t n);
@@ -28,8 +28,11 @@ hipError_t launch_segsort(const uint64_t* grp_off, uint64_t n_groups, uint32_t* 
                           uint32_t* nbig, uint32_t big_cap, hipStream_t s);
 
 // ---- per-step pipeline (step = ctrl->step_base + rel) ----
-hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s);
-hipError_t launch_select_deliver(const NetDev& nd, uint32_t rel, hipStream_t s);
+// with start/stop events the events are recorded on the kernel's own dispatch
+hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start = nullptr,
+                         hipEvent_t stop = nullptr);
+hipError_t launch_select_deliver(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start = nullptr,
+                                 hipEvent_t stop = nullptr);
 hipError_t launch_advance(Ctrl* ctrl, uint32_t steps, hipStream_t s);
 // model-specific update launchers (internal)
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,

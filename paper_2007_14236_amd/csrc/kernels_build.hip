@@ -3,7 +3,8 @@
 //
 // Fixed-indegree rule (Sec. 2.1): target t of projection p draws K sources
 // uniformly with replacement; one Philox4x64-10 block per pair of draws,
-// counter (t, p << 40 | k >> 1, CONN, 0), key (seed, 0); draw k uses words
+// counter (t, p << 40 | k >> 1, CONN, 0), key (seed, 0), with t and p counted
+// inside the projection's instance and seed the instance's; draw k uses words
 // 2(k&1) (source: first + floor(u n_src / 2^64)) and 2(k&1)+1 (delay: top 32
 // bits against the projection's threshold table).
 //
@@ -51,9 +52,9 @@ __device__ __forceinline__ uint32_t find_pop(const uint32_t* pop_first, uint32_t
 
 template <bool kScatter>
 __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, uint32_t nproj, uint64_t total_pairs,
-                                             uint64_t seed, uint32_t dmax_cfg, uint32_t D1, uint32_t* cnt,
-                                             unsigned long long* cursor, uint32_t* payload, const uint8_t* cls_of,
-                                             const uint32_t* pop_first, uint32_t npop) {
+                                             uint32_t dmax_cfg, uint32_t D1, uint32_t* cnt,
+                                             unsigned long long* cursor, uint32_t* payload, const uint16_t* cls_of,
+                                             const uint32_t* pop_first, uint32_t npop, uint32_t cls_bits) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total_pairs; q += stride) {
     const uint32_t p = find_proj(projs, nproj, q);
@@ -62,7 +63,7 @@ __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, u
     const uint64_t tl = local / pr.kpairs;
     const uint32_t kp = (uint32_t)(local - tl * pr.kpairs);
     const uint32_t tgt = pr.tgt_first + (uint32_t)tl;
-    const U64x4 blk = philox4x64_10(tgt, ((uint64_t)pr.index << 40) | kp, kTagConn, 0, seed, 0);
+    const U64x4 blk = philox4x64_10(tgt - pr.gid_base, ((uint64_t)pr.index << 40) | kp, kTagConn, 0, pr.seed, 0);
     uint32_t cls = 0;
     if (kScatter) cls = cls_of[(size_t)p * npop + find_pop(pop_first, npop, tgt)];
 #pragma unroll
@@ -76,7 +77,7 @@ __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, u
         atomicAdd(&cnt[bucket], 1u);
       } else {
         const unsigned long long slot = atomicAdd(&cursor[bucket], 1ull);
-        payload[slot] = (tgt << kClassBits) | cls;
+        payload[slot] = (tgt << cls_bits) | cls;
       }
     }
   }
@@ -288,22 +289,22 @@ __global__ void __launch_bounds__(kSB) k_segsort_block(const uint64_t* __restric
 
 }  // namespace
 
-hipError_t launch_gen_count(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint64_t seed,
-                            uint32_t dmax_cfg, uint32_t D1, uint32_t* cnt, hipStream_t s) {
+hipError_t launch_gen_count(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint32_t dmax_cfg,
+                            uint32_t D1, uint32_t* cnt, hipStream_t s) {
   if (total_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gen<false>, dim3(grid_for(total_pairs, kB, 65536)), dim3(kB), 0, s, projs, nproj, total_pairs,
-                     seed, dmax_cfg, D1, cnt, (unsigned long long*)nullptr, (uint32_t*)nullptr,
-                     (const uint8_t*)nullptr, (const uint32_t*)nullptr, 0u);
+                     dmax_cfg, D1, cnt, (unsigned long long*)nullptr, (uint32_t*)nullptr, (const uint16_t*)nullptr,
+                     (const uint32_t*)nullptr, 0u, 0u);
   return hipGetLastError();
 }
 
-hipError_t launch_gen_scatter(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint64_t seed,
-                              uint32_t dmax_cfg, uint32_t D1, uint64_t* cursor, uint32_t* payload,
-                              const uint8_t* cls_of, const uint32_t* pop_first, uint32_t npop, hipStream_t s) {
+hipError_t launch_gen_scatter(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint32_t dmax_cfg,
+                              uint32_t D1, uint64_t* cursor, uint32_t* payload, const uint16_t* cls_of,
+                              const uint32_t* pop_first, uint32_t npop, uint32_t cls_bits, hipStream_t s) {
   if (total_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gen<true>, dim3(grid_for(total_pairs, kB, 65536)), dim3(kB), 0, s, projs, nproj, total_pairs,
-                     seed, dmax_cfg, D1, (uint32_t*)nullptr, (unsigned long long*)cursor, payload, cls_of, pop_first,
-                     npop);
+                     dmax_cfg, D1, (uint32_t*)nullptr, (unsigned long long*)cursor, payload, cls_of, pop_first, npop,
+                     cls_bits);
   return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@
 //                 multiplicity x quantised weight to the int64 input of its
 //                 (target, port) for step n+1 (integer atomics: the sum does
 //                 not depend on their order).
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 #include "philox_dev.h"
 
@@ -74,7 +76,8 @@ __device__ __forceinline__ uint64_t block_sum(uint64_t v, uint64_t* lds) {
 }
 
 // Poisson count of neuron gid at step n: inverse CDF of a 32-bit uniform
-// (top bits of Philox word 0 at counter (gid, n, POISSON, 0)).
+// (top bits of Philox word 0 at counter (gid, n, POISSON, 0), gid counted
+// inside the neuron's instance, key (instance seed, 0)).
 __device__ __forceinline__ uint32_t poisson_draw(const uint64_t* thr, uint64_t seed, uint32_t gid, uint64_t n) {
   const U64x4 r = philox4x64_10(gid, n, kTagPoisson, 0, seed, 0);
   const uint64_t u = r.w[0] >> 32;
@@ -230,21 +233,27 @@ __device__ uint32_t adex_step(const PopDev& pp, float* y, float& h, float Ie, ui
 }
 
 constexpr uint32_t kPopLds = 16;  // population tables up to this size are read from LDS
+constexpr uint32_t kPoisLds = 8;  // Poisson threshold tables up to this count are read from LDS
 
 template <bool kLif, bool kAdexOn, int P>
 __global__ void __launch_bounds__(kB) k_update(NetDev nd, uint32_t rel) {
   __shared__ uint32_t wcnt[kB / 64];
   __shared__ PopDev spops[kPopLds];
+  __shared__ uint64_t sthr[kPoisLds * kPoisKmax];
   const uint64_t n = nd.ctrl->step_base + rel;
   const uint32_t i = blockIdx.x * kB + threadIdx.x;
   const bool lds_pops = nd.npop <= kPopLds;
+  const bool lds_thr = nd.npois <= kPoisLds;
   if (lds_pops) {
     const uint32_t words = nd.npop * (uint32_t)(sizeof(PopDev) / 4);
     for (uint32_t w = threadIdx.x; w < words; w += kB)
       reinterpret_cast<uint32_t*>(spops)[w] = reinterpret_cast<const uint32_t*>(nd.pops)[w];
   }
+  if (lds_thr)
+    for (uint32_t w = threadIdx.x; w < nd.npois * kPoisKmax; w += kB) sthr[w] = nd.pois_thr[w];
   __syncthreads();
   const PopDev* pops = lds_pops ? spops : nd.pops;
+  const uint64_t* pthr = lds_thr ? sthr : nd.pois_thr;
   bool spk = false;
   uint32_t entry = 0;
   uint32_t nacc = 0, nrej = 0;
@@ -262,7 +271,7 @@ __global__ void __launch_bounds__(kB) k_update(NetDev nd, uint32_t rel) {
       }
     }
     if (pp.pois >= 0) {
-      const uint32_t k = poisson_draw(nd.pois_thr + (size_t)pp.pois * kPoisKmax, nd.seed, i, n);
+      const uint32_t k = poisson_draw(pthr + (size_t)pp.pois * kPoisKmax, pp.seed, i - pp.gid_base, n);
 #pragma unroll
       for (int p = 0; p < kMaxPorts; ++p)
         if (p == pp.pois_port) a[p] += (int64_t)k * pp.pois_wq;
@@ -353,21 +362,26 @@ __global__ void __launch_bounds__(kB) k_select_deliver(NetDev nd, uint32_t rel) 
   __shared__ uint32_t npair;
   const uint64_t n = nd.ctrl->step_base + rel;
   const uint32_t R = nd.R, dmax = nd.dmax;
-  if (threadIdx.x < kMaxClasses) { wq[threadIdx.x] = nd.cls_wq[threadIdx.x]; wp[threadIdx.x] = nd.cls_port[threadIdx.x]; }
+  for (uint32_t c = threadIdx.x; c < nd.n_classes; c += kB) { wq[c] = nd.cls_wq[c]; wp[c] = nd.cls_port[c]; }
+  const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u;
+  // ring entries of the earlier steps (independent of the reduction below)
+  uint64_t cnt = 0, bb = 0;
+  const uint32_t dseg = threadIdx.x + 1;  // delay of this item segment (threads 0..63)
+  if (threadIdx.x < 64 && dseg >= 2 && dseg <= dmax && n + 1 >= dseg) {
+    cnt = nd.ring_cnt[(n + 1 - dseg) % R];
+    bb = nd.ring_base[(n + 1 - dseg) % R];
+  }
+  const uint64_t base_n = (n == 0) ? 0 : nd.ring_base[(n - 1) % R] + nd.ring_cnt[(n - 1) % R];
   // |S_n|: spikes staged by the update blocks of step n
   uint64_t c = 0;
   for (uint32_t ub = threadIdx.x; ub < nd.nblk_upd; ub += kB) c += nd.stage_cnt[ub];
   const uint64_t tot = block_sum(c, red);
-  const uint64_t base_n = (n == 0) ? 0 : nd.ring_base[(n - 1) % R] + nd.ring_cnt[(n - 1) % R];
   if (threadIdx.x < 64) {
-    const uint32_t d = threadIdx.x + 1;  // delay of this item segment
-    uint64_t cnt = 0, bb = 0;
-    if (d == 1) { cnt = tot; bb = base_n; }
-    else if (d <= dmax && n + 1 >= d) { cnt = nd.ring_cnt[(n + 1 - d) % R]; bb = nd.ring_base[(n + 1 - d) % R]; }
+    if (dseg == 1) { cnt = tot; bb = base_n; }
     const uint64_t incl = wave_incl_scan(cnt);
-    seg[d] = incl - cnt;
-    if (d == 64) seg[65] = incl;
-    sbase[d] = bb;
+    seg[dseg] = incl - cnt;
+    if (dseg == 64) seg[65] = incl;
+    sbase[dseg] = bb;
   }
   __syncthreads();
   const uint64_t items = seg[65];
@@ -453,9 +467,9 @@ __global__ void __launch_bounds__(kB) k_select_deliver(NetDev nd, uint32_t rel) 
         if (p_st[mid] <= e) lo = mid; else hi = mid;
       }
       const uint32_t pl = nd.payload[p_off[lo] + (e - p_st[lo])];
-      const uint32_t cls = pl & (kMaxClasses - 1);
+      const uint32_t cls = pl & cls_mask;
       const int64_t v = wq[cls] * (int64_t)p_mult[lo];
-      __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> kClassBits) * P + wp[cls]],
+      __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> cls_bits) * P + wp[cls]],
                              (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     blk_pairs += np;
@@ -478,34 +492,42 @@ __global__ void __launch_bounds__(kB) k_poisson_counts(NetDev nd, uint64_t step,
   if (j >= n) return;
   const uint32_t i = first + j;
   const PopDev& pp = nd.pops[find_pop(nd.pops, nd.npop, i)];
-  out[j] = (pp.pois >= 0) ? poisson_draw(nd.pois_thr + (size_t)pp.pois * kPoisKmax, nd.seed, i, step) : 0u;
+  out[j] = (pp.pois >= 0) ? poisson_draw(nd.pois_thr + (size_t)pp.pois * kPoisKmax, pp.seed, i - pp.gid_base, step) : 0u;
 }
 
 }  // namespace
 
-hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s) {
+// Launch helper: with events, the kernel is launched by hipExtLaunchKernelGGL,
+// which records `start` and `stop` on the dispatch itself (kernel duration).
+template <typename K, typename... Args>
+static void launch(K kernel, dim3 grid, dim3 blk, hipStream_t s, hipEvent_t start, hipEvent_t stop, Args... args) {
+  if (start) hipExtLaunchKernelGGL(kernel, grid, blk, 0, s, start, stop, 0, args...);
+  else hipLaunchKernelGGL(kernel, grid, blk, 0, s, args...);
+}
+
+hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   // which models are present is encoded in nd.pad0: bit 0 LIF, bit 1 AdEx
   const bool lif = nd.pad0 & 1u, adex = nd.pad0 & 2u;
   const dim3 grid(nd.nblk_upd), blk(kB);
   if (!adex) {
-    hipLaunchKernelGGL((k_update<true, false, 1>), grid, blk, 0, s, nd, rel);
+    launch(k_update<true, false, 1>, grid, blk, s, start, stop, nd, rel);
   } else {
     switch (nd.P) {
-      case 1: if (lif) hipLaunchKernelGGL((k_update<true, true, 1>), grid, blk, 0, s, nd, rel);
-              else hipLaunchKernelGGL((k_update<false, true, 1>), grid, blk, 0, s, nd, rel); break;
-      case 2: if (lif) hipLaunchKernelGGL((k_update<true, true, 2>), grid, blk, 0, s, nd, rel);
-              else hipLaunchKernelGGL((k_update<false, true, 2>), grid, blk, 0, s, nd, rel); break;
-      case 3: if (lif) hipLaunchKernelGGL((k_update<true, true, 3>), grid, blk, 0, s, nd, rel);
-              else hipLaunchKernelGGL((k_update<false, true, 3>), grid, blk, 0, s, nd, rel); break;
-      default: if (lif) hipLaunchKernelGGL((k_update<true, true, 4>), grid, blk, 0, s, nd, rel);
-               else hipLaunchKernelGGL((k_update<false, true, 4>), grid, blk, 0, s, nd, rel); break;
+      case 1: if (lif) launch(k_update<true, true, 1>, grid, blk, s, start, stop, nd, rel);
+              else launch(k_update<false, true, 1>, grid, blk, s, start, stop, nd, rel); break;
+      case 2: if (lif) launch(k_update<true, true, 2>, grid, blk, s, start, stop, nd, rel);
+              else launch(k_update<false, true, 2>, grid, blk, s, start, stop, nd, rel); break;
+      case 3: if (lif) launch(k_update<true, true, 3>, grid, blk, s, start, stop, nd, rel);
+              else launch(k_update<false, true, 3>, grid, blk, s, start, stop, nd, rel); break;
+      default: if (lif) launch(k_update<true, true, 4>, grid, blk, s, start, stop, nd, rel);
+               else launch(k_update<false, true, 4>, grid, blk, s, start, stop, nd, rel); break;
     }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_select_deliver(const NetDev& nd, uint32_t rel, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_deliver, dim3(nd.sel_grid), dim3(kB), 0, s, nd, rel);
+hipError_t launch_select_deliver(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  launch(k_select_deliver, dim3(nd.sel_grid), dim3(kB), s, start, stop, nd, rel);
   return hipGetLastError();
 }
 

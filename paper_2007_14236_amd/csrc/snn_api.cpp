@@ -33,6 +33,7 @@ constexpr uint64_t kChunkRing = 4096;  // >= drain interval + graph length
 struct HostPop {
   int32_t model = 0;
   uint32_t n = 0, ports = 1, first = 0;
+  uint32_t inst = 0;
   double tau_m = 10.0, C_m = 250.0, E_L = -70.0, V_th = -55.0, V_reset = -70.0, t_ref = 2.0;
   double g_L = 30.0, Delta_T = 2.0, V_T = -50.4, tau_w = 144.0, a = 4.0, b = 80.5, V_peak = 0.0, V_r = -60.0;
   double rk_eps = 1e-6, rk_hmin = 1e-8;
@@ -42,6 +43,7 @@ struct HostPop {
 
 struct HostProj {
   uint32_t src_first, src_n, tgt_first, tgt_n, K, port;
+  uint32_t inst, local;  // instance and creation index within it
   double weight;
   int32_t kind;
   double da, db;
@@ -50,6 +52,14 @@ struct HostProj {
 struct HostPois {
   uint32_t tgt_first, tgt_n, n_inputs, port;
   double rate, weight;
+};
+
+// An independent network inside this one (a batch member): randomness keyed
+// by its own seed, gids and projection indices counted from its own start.
+struct Inst {
+  uint64_t seed;
+  uint32_t first_gid;
+  uint32_t n_proj;
 };
 
 struct DevAlloc {
@@ -124,6 +134,7 @@ struct snn_net {
   std::string err;
   bool built = false;
 
+  std::vector<Inst> insts;
   std::vector<HostPop> pops;
   std::vector<HostProj> projs;
   std::vector<HostPois> pois;
@@ -139,6 +150,7 @@ struct snn_net {
   std::vector<int> shift;          // [npop][P]
   std::vector<int64_t> cls_wq;     // classes sorted by (port, w_q)
   std::vector<uint32_t> cls_port;
+  uint32_t cls_bits = 6;
   bool has_lif = false, has_adex = false;
   NetDev nd{};
   std::vector<DevAlloc> allocs;
@@ -304,6 +316,7 @@ snn_status snn_create_net(const snn_config* cfg, const snn_device* dev, snn_net*
   snn_net* net = new (std::nothrow) snn_net();
   if (!net) return SNN_E_NOMEM;
   net->cfg = *cfg;
+  net->insts.push_back({cfg->seed, 0, 0});
   if (dev) {
     net->dev = *dev;
     net->have_dev = true;
@@ -348,6 +361,7 @@ snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports,
   p.n = n;
   p.ports = n_ports;
   p.first = net->N;
+  p.inst = (uint32_t)net->insts.size() - 1;
   if (model == SNN_AEIF_COND_EXP) {
     p.C_m = 281.0; p.E_L = -70.6; p.t_ref = 0.0;
     for (int q = 0; q < kMaxPorts; ++q) p.tau_syn[q] = 1.0;
@@ -362,6 +376,21 @@ snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports,
   net->g.resize((size_t)net->N * kMaxPorts, 0.0);
   net->Isyn.resize((size_t)net->N * kMaxPorts, 0.0);
   if (first_gid) *first_gid = p.first;
+  return SNN_OK;
+}
+
+snn_status snn_begin_instance(snn_net* net, uint64_t seed, uint32_t* instance_id) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "snn_begin_instance after snn_build");
+  if (net->insts.back().first_gid == net->N && net->insts.size() > 1)
+    return fail(net, SNN_E_STATE, "the current instance has no populations yet");
+  if (net->N == 0) {  // no population yet: the first instance takes this seed
+    net->insts.back().seed = seed;
+  } else {
+    net->insts.push_back({seed, net->N, 0});
+  }
+  if (instance_id) *instance_id = (uint32_t)net->insts.size() - 1;
   return SNN_OK;
 }
 
@@ -430,14 +459,22 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
   if (delay_kind == SNN_DELAY_UNIFORM && !(delay_b > delay_a)) return fail(net, SNN_E_INVALID, "uniform delay needs b > a");
   if (delay_kind == SNN_DELAY_NORMAL_CLIPPED && !(delay_b > 0)) return fail(net, SNN_E_INVALID, "normal delay needs sd > 0");
   if (!std::isfinite(weight)) return fail(net, SNN_E_INVALID, "weight must be finite");
+  const uint32_t inst = net->pops[pop_of(net, src_first)].inst;
+  for (uint32_t t = src_first; t < src_first + src_n;) {
+    const HostPop& pp = net->pops[pop_of(net, t)];
+    if (pp.inst != inst) return fail(net, SNN_E_INVALID, "a projection must stay inside one instance");
+    t = pp.first + pp.n;
+  }
   for (uint32_t t = tgt_first; t < tgt_first + tgt_n;) {
     const HostPop& pp = net->pops[pop_of(net, t)];
+    if (pp.inst != inst) return fail(net, SNN_E_INVALID, "a projection must stay inside one instance");
     if (port >= pp.ports) return fail(net, SNN_E_INVALID, "port %u out of range for target population", port);
     if (pp.model == SNN_AEIF_COND_EXP && weight < 0) return fail(net, SNN_E_INVALID, "conductance weights must be >= 0");
     t = pp.first + pp.n;
   }
   if (net->projs.size() >= (1u << 23)) return fail(net, SNN_E_UNSUPPORTED, "too many projections");
-  net->projs.push_back({src_first, src_n, tgt_first, tgt_n, indegree, port, weight, delay_kind, delay_a, delay_b});
+  net->projs.push_back({src_first, src_n, tgt_first, tgt_n, indegree, port, inst, net->insts[inst].n_proj++, weight,
+                        delay_kind, delay_a, delay_b});
   return SNN_OK;
 }
 
@@ -621,7 +658,7 @@ snn_status snn_build(snn_net* net) {
   net->shift.assign((size_t)npop * P, 0);
   for (size_t k = 0; k < maxw.size(); ++k) net->shift[k] = fixed_shift(maxw[k]);
   // weight classes: distinct (port, w_q) sorted, per (projection, target population)
-  std::map<std::pair<uint32_t, int64_t>, uint8_t> classes;
+  std::map<std::pair<uint32_t, int64_t>, uint32_t> classes;
   std::vector<std::pair<uint32_t, int64_t>> cls_key((size_t)net->projs.size() * npop, {0, 0});
   for (size_t p = 0; p < net->projs.size(); ++p) {
     const HostProj& pr = net->projs[p];
@@ -632,11 +669,18 @@ snn_status snn_build(snn_net* net) {
       classes[{pr.port, wq}] = 0;
     }
   }
-  if (classes.size() > (size_t)kMaxClasses) return fail(net, SNN_E_UNSUPPORTED, "more than 64 weight classes");
-  net->cls_wq.assign(kMaxClasses, 0);
-  net->cls_port.assign(kMaxClasses, 0);
+  uint32_t tbits = 1;
+  while (tbits < 32 && (1ull << tbits) < (uint64_t)N) ++tbits;  // bits of the largest gid
+  net->cls_bits = 32 - tbits;
+  const size_t max_cls = std::min<size_t>(kMaxClasses, (size_t)1 << std::min<uint32_t>(net->cls_bits, 20));
+  if (classes.size() > max_cls)
+    return fail(net, SNN_E_UNSUPPORTED, "%zu (port, weight) classes; at most %zu for this network size", classes.size(),
+                max_cls);
+  const size_t ncls = std::max<size_t>(1, classes.size());
+  net->cls_wq.assign(ncls, 0);
+  net->cls_port.assign(ncls, 0);
   {
-    uint8_t id = 0;
+    uint32_t id = 0;
     for (auto& kv : classes) {
       kv.second = id;
       net->cls_port[id] = kv.first.first;
@@ -644,11 +688,11 @@ snn_status snn_build(snn_net* net) {
       ++id;
     }
   }
-  std::vector<uint8_t> cls_of((size_t)std::max<size_t>(1, net->projs.size()) * npop, 0);
+  std::vector<uint16_t> cls_of((size_t)std::max<size_t>(1, net->projs.size()) * npop, 0);
   for (size_t p = 0; p < net->projs.size(); ++p)
     for (uint32_t k = 0; k < npop; ++k)
       if (overlaps(k, net->projs[p].tgt_first, net->projs[p].tgt_n) && net->projs[p].K)
-        cls_of[p * npop + k] = classes[cls_key[p * npop + k]];
+        cls_of[p * npop + k] = (uint16_t)classes[cls_key[p * npop + k]];
   // projections, delay tables, largest delay present
   const uint32_t dmax_cfg = net->cfg.max_delay_steps;
   std::vector<ProjDev> pd(net->projs.size());
@@ -659,7 +703,8 @@ snn_status snn_build(snn_net* net) {
     ProjDev& d = pd[p];
     memset(&d, 0, sizeof d);
     d.src_first = pr.src_first; d.src_n = pr.src_n; d.tgt_first = pr.tgt_first; d.tgt_n = pr.tgt_n;
-    d.K = pr.K; d.kpairs = (pr.K + 1) / 2; d.index = (uint32_t)p;
+    d.K = pr.K; d.kpairs = (pr.K + 1) / 2; d.index = pr.local;
+    d.gid_base = net->insts[pr.inst].first_gid; d.seed = net->insts[pr.inst].seed;
     d.pair_begin = total_pairs;
     delay_thresholds(pr.kind, pr.da, pr.db, dt, dmax_cfg, d.thr);
     total_pairs += (uint64_t)pr.tgt_n * d.kpairs;
@@ -681,6 +726,7 @@ snn_status snn_build(snn_net* net) {
     PopDev& d = popdev[k];
     memset(&d, 0, sizeof d);
     d.first = p.first; d.n = p.n; d.model = p.model; d.n_ports = (int32_t)p.ports;
+    d.gid_base = net->insts[p.inst].first_gid; d.seed = net->insts[p.inst].seed;
     if (p.model != SNN_AEIF_COND_EXP) lif_propagators(p, dt, d);
     d.inv_C = (float)(1.0 / p.C_m); d.g_L = (float)p.g_L; d.E_L = (float)p.E_L; d.Delta_T = (float)p.Delta_T;
     d.inv_Delta_T = (float)(1.0 / p.Delta_T); d.V_T = (float)p.V_T; d.inv_tau_w = (float)(1.0 / p.tau_w);
@@ -707,8 +753,8 @@ snn_status snn_build(snn_net* net) {
   NetDev& nd = net->nd;
   memset(&nd, 0, sizeof nd);
   nd.N = N; nd.P = P; nd.npop = npop; nd.dmax = dmax_used; nd.R = dmax_used + 1;
+  nd.npois = (uint32_t)(pois_thr.size() / kPoisKmax);
   nd.nblk_upd = (N + kUpdBlock - 1) / kUpdBlock;
-  nd.seed = net->cfg.seed;
   nd.pad0 = (net->has_lif ? 1u : 0u) | (net->has_adex ? 2u : 0u);
   hipStream_t s = net->stream;
 #define ALLOC(ptr, T, count)                                                              \
@@ -722,11 +768,12 @@ snn_status snn_build(snn_net* net) {
   uint64_t* d_pthr; ALLOC(d_pthr, uint64_t, pois_thr.size());
   HIPCHK(net, hipMemcpyAsync(d_pthr, pois_thr.data(), pois_thr.size() * 8, hipMemcpyHostToDevice, s));
   nd.pois_thr = d_pthr;
-  int64_t* d_cw; ALLOC(d_cw, int64_t, kMaxClasses);
-  uint32_t* d_cp; ALLOC(d_cp, uint32_t, kMaxClasses);
-  HIPCHK(net, hipMemcpyAsync(d_cw, net->cls_wq.data(), kMaxClasses * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(net, hipMemcpyAsync(d_cp, net->cls_port.data(), kMaxClasses * 4, hipMemcpyHostToDevice, s));
+  int64_t* d_cw; ALLOC(d_cw, int64_t, ncls);
+  uint32_t* d_cp; ALLOC(d_cp, uint32_t, ncls);
+  HIPCHK(net, hipMemcpyAsync(d_cw, net->cls_wq.data(), ncls * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(net, hipMemcpyAsync(d_cp, net->cls_port.data(), ncls * 4, hipMemcpyHostToDevice, s));
   nd.cls_wq = d_cw; nd.cls_port = d_cp;
+  nd.n_classes = (uint32_t)ncls; nd.cls_bits = net->cls_bits;
 
   // ---- connectivity: count, scan, masks, group offsets, scatter, sort ----
   const uint64_t M = (uint64_t)N * D1;
@@ -738,18 +785,18 @@ snn_status snn_build(snn_net* net) {
   uint64_t* d_mask; ALLOC(d_mask, uint64_t, N);
   uint32_t* d_gp32; ALLOC(d_gp32, uint32_t, (size_t)N + 1);
   ProjDev* d_proj = nullptr;
-  uint8_t* d_clsof = nullptr;
+  uint16_t* d_clsof = nullptr;
   uint32_t* d_popfirst = nullptr;
   ALLOC(d_proj, ProjDev, std::max<size_t>(1, pd.size()));
-  ALLOC(d_clsof, uint8_t, cls_of.size());
+  ALLOC(d_clsof, uint16_t, cls_of.size());
   ALLOC(d_popfirst, uint32_t, npop);
   std::vector<uint32_t> pf(npop);
   for (uint32_t k = 0; k < npop; ++k) pf[k] = net->pops[k].first;
   if (!pd.empty()) HIPCHK(net, hipMemcpyAsync(d_proj, pd.data(), pd.size() * sizeof(ProjDev), hipMemcpyHostToDevice, s));
-  HIPCHK(net, hipMemcpyAsync(d_clsof, cls_of.data(), cls_of.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(net, hipMemcpyAsync(d_clsof, cls_of.data(), cls_of.size() * 2, hipMemcpyHostToDevice, s));
   HIPCHK(net, hipMemcpyAsync(d_popfirst, pf.data(), npop * 4, hipMemcpyHostToDevice, s));
   HIPCHK(net, hipMemsetAsync(d_cnt, 0, M * sizeof(uint32_t), s));
-  HIPCHK(net, launch_gen_count(d_proj, (uint32_t)pd.size(), total_pairs, nd.seed, dmax_cfg, D1, d_cnt, s));
+  HIPCHK(net, launch_gen_count(d_proj, (uint32_t)pd.size(), total_pairs, dmax_cfg, D1, d_cnt, s));
   HIPCHK(net, launch_scan_u32(d_cnt, M, d_off, d_tmp, s));
   HIPCHK(net, launch_masks(d_cnt, N, D1, d_mask, d_ng, s));
   HIPCHK(net, launch_scan_u64(d_ng, N, d_gp64, d_tmp, s));
@@ -763,8 +810,8 @@ snn_status snn_build(snn_net* net) {
   HIPCHK(net, launch_grp_off(d_cnt, d_off, d_gp64, N, D1, d_goff, d_gp32, s));
   HIPCHK(net, hipMemcpyAsync(d_goff + G, &S, 8, hipMemcpyHostToDevice, s));
   uint32_t* d_pay; ALLOC(d_pay, uint32_t, std::max<uint64_t>(1, S));
-  HIPCHK(net, launch_gen_scatter(d_proj, (uint32_t)pd.size(), total_pairs, nd.seed, dmax_cfg, D1, d_off, d_pay, d_clsof,
-                                 d_popfirst, npop, s));
+  HIPCHK(net, launch_gen_scatter(d_proj, (uint32_t)pd.size(), total_pairs, dmax_cfg, D1, d_off, d_pay, d_clsof,
+                                 d_popfirst, npop, net->cls_bits, s));
   const uint32_t big_cap = 4096;
   uint64_t* d_big; ALLOC(d_big, uint64_t, big_cap);
   uint32_t* d_nbig; ALLOC(d_nbig, uint32_t, 1);
@@ -906,20 +953,17 @@ snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms) {
   if (!net->built) return fail(net, SNN_E_STATE, "profile before snn_build");
   snn_status st = enter(net);
   if (st) return st;
-  hipEvent_t ev[3];
+  hipEvent_t ev[4];
   for (auto& e : ev) HIPCHK(net, hipEventCreate(&e));
   const auto t0 = std::chrono::steady_clock::now();
   for (uint64_t k = 0; k < steps; ++k) {
-    HIPCHK(net, hipEventRecord(ev[0], net->stream));
-    HIPCHK(net, launch_update(net->nd, 0, net->stream));
-    HIPCHK(net, hipEventRecord(ev[1], net->stream));
-    HIPCHK(net, launch_select_deliver(net->nd, 0, net->stream));
-    HIPCHK(net, hipEventRecord(ev[2], net->stream));
+    HIPCHK(net, launch_update(net->nd, 0, net->stream, ev[0], ev[1]));
+    HIPCHK(net, launch_select_deliver(net->nd, 0, net->stream, ev[2], ev[3]));
     HIPCHK(net, launch_advance(net->nd.ctrl, 1, net->stream));
-    HIPCHK(net, hipEventSynchronize(ev[2]));
+    HIPCHK(net, hipEventSynchronize(ev[3]));
     for (int q = 0; q < 2; ++q) {
       float ms = 0.f;
-      HIPCHK(net, hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
+      HIPCHK(net, hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]));
       kernel_ms[q] += ms;
     }
     net->cur_step += 1;
@@ -1056,9 +1100,10 @@ snn_status snn_export_synapses(snn_net* net, uint32_t* src, uint32_t* delay, uin
       if (!((m >> d) & 1ull)) continue;
       for (uint64_t q = goff[g]; q < goff[g + 1]; ++q, ++e) {
         const uint32_t pl = pay[q];
-        src[e] = s; delay[e] = d; tgt[e] = pl >> kClassBits;
-        port[e] = net->cls_port[pl & (kMaxClasses - 1)];
-        wq[e] = net->cls_wq[pl & (kMaxClasses - 1)];
+        const uint32_t cls = pl & ((1u << net->cls_bits) - 1u);
+        src[e] = s; delay[e] = d; tgt[e] = pl >> net->cls_bits;
+        port[e] = net->cls_port[cls];
+        wq[e] = net->cls_wq[cls];
       }
       ++g;
     }

@@ -8,7 +8,8 @@
 //     src_mask[N]   u64, bit d set <=> source has a group with delay d steps
 //     grp_ptr[N+1]  u32, index of the source's first group
 //     grp_off[G+1]  u64, first synapse of each group (groups ordered by delay)
-//     payload[S]    u32, target << 6 | weight class (class -> port, w_q)
+//     payload[S]    u32, target << b | weight class (class -> port, w_q),
+//                   b = 32 - bits(N), at most 1024 classes
 //   spike buffer: stage[nblk][256] per-update-block spike lists of the
 //     current step, log[CAP] ring of compacted per-step spike lists
 //     (gid | mult << 27) with ring_base/ring_cnt per step slot (Dmax + 1).
@@ -20,8 +21,7 @@
 namespace snn {
 
 constexpr int kMaxPorts = 4;
-constexpr int kMaxClasses = 64;
-constexpr int kClassBits = 6;
+constexpr int kMaxClasses = 1024;   // (port, quantised weight) classes per network
 constexpr uint32_t kMaxNeurons = 1u << 26;
 constexpr int kPoisKmax = 128;
 constexpr int kMultShift = 27;
@@ -52,14 +52,18 @@ struct PopDev {
   int32_t pois;
   int32_t pois_port;
   int64_t pois_wq;
+  // instance of the population: first gid and generator key
+  uint32_t gid_base, pad;
+  uint64_t seed;
 };
 
 static_assert(sizeof(PopDev) % 8 == 0, "PopDev is copied to LDS in 32-bit words");
 
 struct ProjDev {
   uint32_t src_first, src_n, tgt_first, tgt_n, K, kpairs;
-  uint32_t index;          // creation index (Philox counter word 1, bits 40+)
-  uint32_t pad;
+  uint32_t index;          // creation index within its instance (Philox counter word 1, bits 40+)
+  uint32_t gid_base;       // first gid of its instance (counters use instance-local gids)
+  uint64_t seed;           // generator key of its instance
   uint64_t pair_begin;     // prefix of tgt_n * kpairs over projections
   uint64_t thr[64];        // delay thresholds, thr[d] for d = 1..Dmax
 };
@@ -74,15 +78,16 @@ struct Ctrl {
 
 struct NetDev {
   uint32_t N, P, npop, dmax;   // dmax = largest delay present (ring has dmax+1 slots)
+  uint32_t npois, pad2;        // Poisson threshold tables
   uint32_t R, nblk_upd, sel_grid, pad0;
   uint64_t log_mask;           // CAP - 1
   uint64_t chunk_ring;         // slots of chunk_base (power of two)
-  uint64_t seed;
   uint64_t n_groups, n_syn;
   const PopDev* pops;
   const uint64_t* pois_thr;    // [npois][kPoisKmax]
-  const int64_t* cls_wq;       // [kMaxClasses]
-  const uint32_t* cls_port;    // [kMaxClasses]
+  const int64_t* cls_wq;       // [n_classes]
+  const uint32_t* cls_port;    // [n_classes]
+  uint32_t n_classes, cls_bits; // payload = target << cls_bits | class
   // state
   float* V; float* Ie; float* Isyn; float* w; float* g; float* h; int32_t* refr;
   // CSR

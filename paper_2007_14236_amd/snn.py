@@ -62,6 +62,7 @@ _SIGS = {
     "snn_destroy_net": (None, [_P]),
     "snn_last_error": (C.c_char_p, [_P]),
     "snn_create": (C.c_int32, [_P, C.c_int32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
+    "snn_begin_instance": (C.c_int32, [_P, C.c_uint64, C.POINTER(C.c_uint32)]),
     "snn_set_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
     "snn_set_port_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
     "snn_connect_fixed_indegree": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -139,23 +140,41 @@ class TorchAllocator:
 
 
 class Net:
-    """A network on the GPU, defined from a specification dictionary."""
+    """A network on the GPU, defined from a specification dictionary, or a
+    batch of independent networks (one instance per specification) that
+    advance together in the same kernels."""
 
-    def __init__(self, spec: dict, allocator: TorchAllocator | None = None, record: bool = True, build: bool = True):
+    def __init__(self, spec, allocator: TorchAllocator | None = None, record: bool = True, build: bool = True):
         self.L = lib()
+        specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
         self.spec = spec
         self.alloc = allocator if allocator is not None else TorchAllocator()
-        cfg = Config(spec["dt"], spec["seed"], spec["dmax"], 0 if record else F_NO_SPIKE_RECORD)
+        dt, dmax = specs[0]["dt"], specs[0]["dmax"]
+        for sp in specs:
+            if sp["dt"] != dt or sp["dmax"] != dmax:
+                raise ValueError("all instances of a batch share dt and Dmax")
+        cfg = Config(dt, specs[0]["seed"], dmax, 0 if record else F_NO_SPIKE_RECORD)
         self._dev = self.alloc.device_struct()
         h = C.c_void_p()
         self._check(self.L.snn_create_net(C.byref(cfg), C.byref(self._dev), C.byref(h)), None)
         self.h = h
-        self.ranges = {}
         self.N = 0
+        self.instances = []
+        for sp in specs:
+            iid = C.c_uint32()
+            self._check(self.L.snn_begin_instance(self.h, int(sp["seed"]), C.byref(iid)))
+            self.instances.append(self._define(sp))
+        self.ranges = self.instances[0]["ranges"]
+        if build:
+            self.build()
+
+    def _define(self, spec) -> dict:
+        first_gid = self.N
+        ranges = {}
         for p in spec["populations"]:
             first = C.c_uint32()
             self._check(self.L.snn_create(self.h, MODELS[p["model"]], p["n"], p["ports"], C.byref(first)))
-            self.ranges[p["name"]] = (first.value, p["n"])
+            ranges[p["name"]] = (first.value, p["n"])
             self.N += p["n"]
             for k, v in p["params"].items():
                 if k in PARAMS:
@@ -165,23 +184,22 @@ class Net:
                         self._check(self.L.snn_set_port_param(self.h, first.value, p["n"], port,
                                                               PORT_PARAMS[k], float(x)))
         for pr in spec["projections"]:
-            s0, sn = self.ranges[pr["src"]]
-            t0, tn = self.ranges[pr["tgt"]]
+            s0, sn = ranges[pr["src"]]
+            t0, tn = ranges[pr["tgt"]]
             kind, a, b = (list(pr["delay"]) + [0.0, 0.0])[:3]
             self._check(self.L.snn_connect_fixed_indegree(self.h, s0, sn, t0, tn, pr["K"], float(pr["weight"]),
                                                           DELAYS[kind], float(a), float(b), pr["port"]))
         for q in spec.get("poisson", []):
-            t0, tn = self.ranges[q["tgt"]]
+            t0, tn = ranges[q["tgt"]]
             self._check(self.L.snn_poisson(self.h, t0, tn, float(q["rate"]), int(q["n_inputs"]),
                                            float(q["weight"]), q["port"]))
         for p in spec["populations"]:
-            t0, tn = self.ranges[p["name"]]
+            t0, tn = ranges[p["name"]]
             if p.get("V0") is not None:
                 self.set_state("V_m", t0, np.asarray(p["V0"], dtype=np.float64))
             ie = p.get("I_e", 0.0)
             self.set_state("I_e", t0, np.atleast_1d(np.asarray(ie, dtype=np.float64)), n=tn)
-        if build:
-            self.build()
+        return dict(ranges=ranges, first=first_gid, n=self.N - first_gid)
 
     def _check(self, rc, h=-1):
         if rc != SNN_OK:
