@@ -148,12 +148,12 @@ def main():
     ps = max(1, args.profile_steps)
     ev_p = (c3["events"] - c2["events"]) / ps
     pr_p = (c3["pairs"] - c2["pairs"]) / ps
-    dlv_ms = prof["select_deliver"] / ps
+    dlv_ms = prof["step"] / ps
     dominant = max(prof, key=prof.get)
     dlv_bytes = ev_p * DLV_BYTES_PER_EVENT + pr_p * DLV_BYTES_PER_PAIR
     achieved = dlv_bytes / (dlv_ms * 1e-3) / 1e9 if dlv_ms > 0 else 0.0
     roofline = {
-        "kernel": "k_select_deliver", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "kernel": "k_step", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
         "avg_launch_us": round(dlv_ms * 1e3, 3), "bytes_per_launch": round(dlv_bytes),
         "events_per_launch": round(ev_p, 1), "pairs_per_launch": round(pr_p, 1),

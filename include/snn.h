@@ -215,8 +215,8 @@ snn_status snn_get_shift(snn_net* net, uint32_t gid, uint32_t port, int32_t* shi
 snn_status snn_poisson_counts(snn_net* net, uint64_t step, uint32_t first, uint32_t n, uint32_t* k);
 /* Advance by `steps` steps launching each kernel on its own (no graph) with a
    HIP event pair around it on the library's stream, and add the summed
-   device time of each kernel kind to kernel_ms[0..1] = (update, select and
-   deliver), in milliseconds.  Results are identical to
+   device time of the step kernel (update, delay-1 delivery and delivery of
+   earlier steps' spikes) to kernel_ms[0], in milliseconds.  Results are identical to
    snn_simulate_steps; used to measure per-kernel durations. */
 snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms);
 /* Connectivity in canonical order (source, delay, target, port, weight): on

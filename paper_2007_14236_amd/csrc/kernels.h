@@ -28,11 +28,12 @@ hipError_t launch_segsort(const uint64_t* grp_off, uint64_t n_groups, uint32_t* 
                           uint32_t* nbig, uint32_t big_cap, hipStream_t s);
 
 // ---- per-step pipeline (step = ctrl->step_base + rel) ----
-// with start/stop events the events are recorded on the kernel's own dispatch
-hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start = nullptr,
-                         hipEvent_t stop = nullptr);
-hipError_t launch_select_deliver(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start = nullptr,
-                                 hipEvent_t stop = nullptr);
+// One step: update + delay-1 delivery, and delivery of earlier steps' spikes.
+// With start/stop events the events are recorded on the kernel's own dispatch.
+hipError_t launch_step(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start = nullptr,
+                       hipEvent_t stop = nullptr);
+// Appends the spikes of the last simulated step to the raster ring.
+hipError_t launch_log_tail(const NetDev& nd, hipStream_t s);
 hipError_t launch_advance(Ctrl* ctrl, uint32_t steps, hipStream_t s);
 // model-specific update launchers (internal)
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,

@@ -1,21 +1,21 @@
 // kernels_step.hip -- one simulation step on the device.
 //
-// Step n (Golosio et al., Sec. 2.1 and 2.2):
-//   1. update   : every neuron folds the integer input delivered for step n
-//                 (plus its Poisson count) into fp32, advances its dynamics
-//                 over dt and, if it fires, is appended to the block's spike
-//                 list (wave ballot + lane prefix + block prefix, gid order).
-//   2. select + deliver: compacts the block lists of step n into the spike
-//                 ring and selects every (source, delay group) pair whose delay
-//                 d has just elapsed: spikes of step n+1-d whose source has a
-//                 group of delay d (bit d of the source's delay mask; the group
-//                 is found by a popcount of the lower bits, so no loop over the
-//                 groups is needed -- the role of the ordered group index of
-//                 Fig. 1).  The selected groups are scanned in LDS into one
-//                 flat index space over their synapses; each synapse adds
-//                 multiplicity x quantised weight to the int64 input of its
-//                 (target, port) for step n+1 (integer atomics: the sum does
-//                 not depend on their order).
+// Step n (Golosio et al., Sec. 2.1 and 2.2) is two kernels:
+//   1. k_step_main: update blocks -- every neuron folds the integer input
+//      delivered for step n (plus its Poisson count) into fp32, advances its
+//      dynamics over dt and, if it fires, is appended to its block's spike
+//      list (wave ballot + lane prefix + block prefix, gid order); delivery
+//      blocks in the same launch -- the spikes of steps n-1 .. n+1-Dmax whose
+//      delay d expires now reach their delay-d connection group.
+//   2. k_step_fresh: the spikes of step n are appended to the raster ring,
+//      recorded for later steps, and delivered to their delay-1 groups.
+// A spike reaches a group of delay d iff bit d of its source's delay mask is
+// set; the group is found by a popcount of the lower bits (the groups of a
+// source are ordered by delay), so there is no loop over the groups -- the
+// role of the ordered connection-group index of Fig. 1.  Selected groups are
+// scanned in LDS into one flat index space over their synapses; each synapse
+// adds multiplicity x quantised weight to the int64 input of its (target,
+// port) for step n+1.  Integer atomics: the sum does not depend on order.
 #include <hip/hip_ext.h>
 
 #include "kernels.h"
@@ -75,6 +75,21 @@ __device__ __forceinline__ uint64_t block_sum(uint64_t v, uint64_t* lds) {
   return tot;
 }
 
+__device__ __forceinline__ uint64_t block_max(uint64_t v, uint64_t* lds) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t t = __shfl_xor(v, o, 64);
+    v = t > v ? t : v;
+  }
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  uint64_t m = 0;
+  for (int i = 0; i < nw; ++i) m = lds[i] > m ? lds[i] : m;
+  __syncthreads();
+  return m;
+}
+
 // Poisson count of neuron gid at step n: inverse CDF of a 32-bit uniform
 // (top bits of Philox word 0 at counter (gid, n, POISSON, 0), gid counted
 // inside the neuron's instance, key (instance seed, 0)).
@@ -84,23 +99,6 @@ __device__ __forceinline__ uint32_t poisson_draw(const uint64_t* thr, uint64_t s
   uint32_t k = 0;
   while (k < kPoisKmax - 1 && u >= thr[k]) ++k;
   return k;
-}
-
-// spike list of the block: order-preserving compaction by gid
-__device__ __forceinline__ void block_stage_spikes(const NetDev& nd, bool spk, uint32_t entry, uint32_t* wcnt) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint64_t bal = __ballot(spk);
-  const uint32_t pre = __popcll(bal & lanemask_lt());
-  if (lane == 0) wcnt[wv] = __popcll(bal);
-  __syncthreads();
-  uint32_t woff = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < kB / 64; ++i) {
-    if (i < wv) woff += wcnt[i];
-    tot += wcnt[i];
-  }
-  if (spk) nd.stage[(size_t)blockIdx.x * kB + woff + pre] = entry;
-  if (threadIdx.x == 0) nd.stage_cnt[blockIdx.x] = tot;
 }
 
 // ------------------------------------------------------------------ update
@@ -234,14 +232,116 @@ __device__ uint32_t adex_step(const PopDev& pp, float* y, float& h, float Ie, ui
 
 constexpr uint32_t kPopLds = 16;  // population tables up to this size are read from LDS
 constexpr uint32_t kPoisLds = 8;  // Poisson threshold tables up to this count are read from LDS
+constexpr int kSelChunk = 512;    // selected groups held in LDS at a time
+constexpr uint32_t kClsLds = 256; // weight classes cached in LDS (more are read from global memory)
+constexpr int kSelPerThread = kSelChunk / kB;
 
+// LDS of the delivery routine: the selected (source, delay-group) records of
+// one chunk, their exclusive prefix of group sizes, and the weight classes.
+struct DlvLds {
+  uint64_t p_off[kSelChunk];
+  uint64_t p_st[kSelChunk];
+  uint32_t p_len[kSelChunk];
+  uint32_t p_mult[kSelChunk];
+  int64_t wq[kClsLds];
+  uint32_t wp[kClsLds];
+  uint64_t red[kB / 64];
+  uint64_t seg[66];
+  uint32_t slot[66];
+  uint32_t npair;
+};
+
+// LDS of an update block
+struct UpdLds {
+  uint32_t wcnt[kB / 64];
+  uint64_t red[kB / 64];
+  unsigned long long d1[2];
+  PopDev spops[kPopLds];
+  uint64_t sthr[kPoisLds * kPoisKmax];
+};
+
+union StepLds {
+  UpdLds upd;
+  DlvLds dlv;
+};
+
+__device__ __forceinline__ void dlv_load_classes(const NetDev& nd, DlvLds& sh) {
+  const uint32_t nc = nd.n_classes < kClsLds ? nd.n_classes : kClsLds;
+  for (uint32_t c = threadIdx.x; c < nc; c += kB) { sh.wq[c] = nd.cls_wq[c]; sh.wp[c] = nd.cls_port[c]; }
+  if (threadIdx.x == 0) sh.npair = 0;
+}
+
+// Selection of one in-flight spike for delay d (Sec. 2.2, Fig. 1): the spike
+// reaches a connection group now iff its source has a group of delay d (bit d
+// of the delay mask); that group's index among the source's groups, which are
+// ordered by delay, is the number of lower bits set.
+__device__ __forceinline__ void dlv_probe(const NetDev& nd, DlvLds& sh, uint32_t entry, uint32_t grp_ptr,
+                                          uint64_t mask, uint32_t d) {
+  if ((mask >> d) & 1ull) {
+    const uint32_t g = grp_ptr + (uint32_t)__popcll(mask & ((1ull << d) - 1ull));
+    const uint64_t off = nd.grp_off[g];
+    const uint32_t len = (uint32_t)(nd.grp_off[g + 1] - off);
+    const uint32_t k = atomicAdd(&sh.npair, 1u);  // LDS counter; callers keep k < kSelChunk
+    sh.p_off[k] = off;
+    sh.p_len[k] = len;
+    sh.p_mult[k] = entry >> kMultShift;
+  }
+}
+
+// Flat scan of the synapses of the chunk's selected groups: exclusive prefix
+// of the group sizes in LDS, then every synapse of every group is one item;
+// each item reads one synapse word (consecutive lanes, consecutive synapses of
+// a group) and adds multiplicity x quantised weight to the int64 input of its
+// (target, port) for the next step.  Called by the whole block after a
+// barrier; returns the events delivered and resets the chunk.
+__device__ uint64_t dlv_flush(const NetDev& nd, DlvLds& sh, int64_t* acc) {
+  const uint32_t np = sh.npair;
+  uint32_t L[kSelPerThread];
+  uint64_t lsum = 0;
+#pragma unroll
+  for (int q = 0; q < kSelPerThread; ++q) {
+    const uint32_t i = threadIdx.x * kSelPerThread + q;
+    L[q] = (i < np) ? sh.p_len[i] : 0u;
+    lsum += L[q];
+  }
+  uint64_t ev;
+  uint64_t run = block_excl_scan(lsum, sh.red, &ev);
+#pragma unroll
+  for (int q = 0; q < kSelPerThread; ++q) {
+    const uint32_t i = threadIdx.x * kSelPerThread + q;
+    if (i < np) sh.p_st[i] = run;
+    run += L[q];
+  }
+  __syncthreads();
+  const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u, P = nd.P;
+  for (uint64_t e = threadIdx.x; e < ev; e += kB) {
+    uint32_t lo = 0, hi = np;  // last record with p_st <= e
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (sh.p_st[mid] <= e) lo = mid; else hi = mid;
+    }
+    const uint32_t pl = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
+    const uint32_t cls = pl & cls_mask;
+    const bool in_lds = cls < kClsLds;
+    const int64_t v = (in_lds ? sh.wq[cls] : nd.cls_wq[cls]) * (int64_t)sh.p_mult[lo];
+    const uint32_t port = in_lds ? sh.wp[cls] : nd.cls_port[cls];
+    __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> cls_bits) * P + port],
+                           (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) sh.npair = 0;
+  __syncthreads();
+  return ev;
+}
+
+// ------------------------------------------------------------------ update
 template <bool kLif, bool kAdexOn, int P>
-__global__ void __launch_bounds__(kB) k_update(NetDev nd, uint32_t rel) {
-  __shared__ uint32_t wcnt[kB / 64];
-  __shared__ PopDev spops[kPopLds];
-  __shared__ uint64_t sthr[kPoisLds * kPoisKmax];
-  const uint64_t n = nd.ctrl->step_base + rel;
-  const uint32_t i = blockIdx.x * kB + threadIdx.x;
+__device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds& sl) {
+  uint32_t* wcnt = sl.wcnt;
+  PopDev* spops = sl.spops;
+  uint64_t* sthr = sl.sthr;
+  uint64_t* red = sl.red;
+  const uint32_t i = blk * kB + threadIdx.x;
   const bool lds_pops = nd.npop <= kPopLds;
   const bool lds_thr = nd.npois <= kPoisLds;
   if (lds_pops) {
@@ -320,166 +420,246 @@ __global__ void __launch_bounds__(kB) k_update(NetDev nd, uint32_t rel) {
     spk = m > 0;
     entry = i | (m << kMultShift);
   }
-  block_stage_spikes(nd, spk, entry, wcnt);
-  if (kAdexOn) {
-    __shared__ uint64_t red[kB / 64];
-    const uint64_t sa = block_sum(nacc, red);
-    const uint64_t sr = block_sum(nrej, red);
-    if (threadIdx.x == 0) {
-      nd.blk_stats[2 * blockIdx.x] += sa;
-      nd.blk_stats[2 * blockIdx.x + 1] += sr;
+  // spike list of the block: wave ballot, lane prefix, block prefix (gid
+  // order), into the stage buffer of this step's parity
+  const size_t sb = (size_t)(n & 1) * nd.nblk_upd;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t btot;
+  {
+    const uint64_t bal = __ballot(spk);
+    const uint32_t pre = __popcll(bal & lanemask_lt());
+    if (lane == 0) wcnt[wv] = __popcll(bal);
+    if (threadIdx.x == 0) { sl.d1[0] = 0; sl.d1[1] = 0; }
+    __syncthreads();
+    uint32_t woff = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kB / 64; ++w) {
+      if (w < wv) woff += wcnt[w];
+      tot += wcnt[w];
     }
+    btot = tot;
+    if (spk) nd.stage[(sb + blk) * kB + woff + pre] = entry;
+    if (threadIdx.x == 0) nd.stage_cnt[sb + blk] = tot;
+  }
+  // delay-1 groups of this block's spikes reach their targets at the next
+  // step: delivered here, each group by the whole wave (consecutive lanes,
+  // consecutive synapses)
+  {
+    uint64_t off = 0;
+    uint32_t len = 0;
+    bool has1 = false;
+    if (spk) {
+      const uint64_t mask = nd.src_mask[i];
+      if ((mask >> 1) & 1ull) {  // the delay-1 group is the source's first group
+        const uint32_t g = nd.grp_ptr[i];
+        off = nd.grp_off[g];
+        len = (uint32_t)(nd.grp_off[g + 1] - off);
+        has1 = true;
+      }
+    }
+    uint64_t bal = __ballot(has1);
+    if (bal) {
+      int64_t* accn = nd.acc + (size_t)((n + 1) & 1) * nd.N * nd.P;
+      const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u, P2 = nd.P;
+      unsigned long long wp = 0, we = 0;
+      while (bal) {
+        const int l = __ffsll((unsigned long long)bal) - 1;
+        bal &= bal - 1;
+        const uint64_t o = __shfl((unsigned long long)off, l, 64);
+        const uint32_t L = __shfl(len, l, 64);
+        const uint32_t mm = __shfl(entry >> kMultShift, l, 64);
+        for (uint32_t j = lane; j < L; j += 64) {
+          const uint32_t pl = nd.payload[o + j];
+          const uint32_t cls = pl & cls_mask;
+          const int64_t v = nd.cls_wq[cls] * (int64_t)mm;
+          __hip_atomic_fetch_add((unsigned long long*)&accn[(size_t)(pl >> cls_bits) * P2 + nd.cls_port[cls]],
+                                 (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ++wp;
+        we += L;
+      }
+      if (lane == 0) { atomicAdd(&sl.d1[0], wp); atomicAdd(&sl.d1[1], we); }
+    }
+  }
+  uint64_t sa = 0, sr = 0;
+  if (kAdexOn) {
+    sa = block_sum(nacc, red);
+    sr = block_sum(nrej, red);
+  } else {
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    uint64_t* st = nd.blk_stats + (size_t)kBlkStats * blk;
+    st[0] += sa;
+    st[1] += sr;
+    st[2] += btot;
+    st[3] += sl.d1[0];
+    st[4] += sl.d1[1];
   }
   if (capped) atomicOr(&nd.ctrl->overflow, 2u);
   if (mover) atomicOr(&nd.ctrl->overflow, 1u);
 }
 
-// ------------------------------------------------------------------ select
-// ----------------------------------------------------------- select+deliver
-// Block b owns the item range [i0, i1) of step n's selection items: first the
-// spikes of step n (delay 1, read from the update blocks' lists and copied into
-// the spike ring by the block that owns them), then those of steps n-1 ..
-// n+1-Dmax (delays 2..Dmax, read from the ring).  Items are taken in chunks of
-// kSelChunk: every item whose source has a group of the item's delay yields
-// one (synapse offset, group size, multiplicity) record in LDS; the chunk's
-// records are scanned in LDS (exclusive prefix of the sizes) and their
-// synapses delivered in one flat pass by the whole block, so consecutive
-// lanes read consecutive synapses of a group.  Integer atomics make the result
-// independent of the order in which blocks and lanes deliver.
-constexpr int kSelChunk = 1024;
-constexpr int kSelPerThread = kSelChunk / kB;
-
-__global__ void __launch_bounds__(kB) k_select_deliver(NetDev nd, uint32_t rel) {
-  __shared__ uint64_t red[kB / 64];
-  __shared__ uint64_t seg[66];
-  __shared__ uint64_t sbase[66];
-  __shared__ uint64_t p_off[kSelChunk];
-  __shared__ uint64_t p_st[kSelChunk];
-  __shared__ uint32_t p_len[kSelChunk];
-  __shared__ uint32_t p_mult[kSelChunk];
-  __shared__ int64_t wq[kMaxClasses];
-  __shared__ uint32_t wp[kMaxClasses];
-  __shared__ uint32_t npair;
-  const uint64_t n = nd.ctrl->step_base + rel;
-  const uint32_t R = nd.R, dmax = nd.dmax;
-  for (uint32_t c = threadIdx.x; c < nd.n_classes; c += kB) { wq[c] = nd.cls_wq[c]; wp[c] = nd.cls_port[c]; }
-  const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u;
-  // ring entries of the earlier steps (independent of the reduction below)
-  uint64_t cnt = 0, bb = 0;
-  const uint32_t dseg = threadIdx.x + 1;  // delay of this item segment (threads 0..63)
-  if (threadIdx.x < 64 && dseg >= 2 && dseg <= dmax && n + 1 >= dseg) {
-    cnt = nd.ring_cnt[(n + 1 - dseg) % R];
-    bb = nd.ring_base[(n + 1 - dseg) % R];
+// Spikes of step f = n-1, read from the update blocks' lists of that step:
+// block b appends the entries [i0, i1) (ranks within step f, gid order) to
+// the raster ring and, if kDeliver, records them for later steps and selects
+// their delay-2 groups.  Entries are taken in rounds of at most one per thread.
+template <bool kDeliver>
+__device__ void walk_step(const NetDev& nd, uint64_t f, uint64_t base_f, uint64_t i0, uint64_t i1, DlvLds& sh,
+                          int64_t* acc, uint64_t& pairs, uint64_t& events) {
+  const size_t sb = (size_t)(f & 1) * nd.nblk_upd;
+  SpikeRec* rec = nd.recent + (size_t)(f % nd.R) * nd.N;
+  uint64_t run = 0;
+  for (uint32_t t0 = 0; t0 < nd.nblk_upd && run < i1; t0 += kB) {  // block-uniform
+    const uint32_t ub = t0 + threadIdx.x;
+    const uint32_t cc = (ub < nd.nblk_upd) ? nd.stage_cnt[sb + ub] : 0;
+    uint64_t tsum;
+    const uint64_t p_ub = run + block_excl_scan(cc, sh.red, &tsum);
+    const uint64_t lo = p_ub > i0 ? p_ub : i0;
+    const uint64_t hi = (p_ub + cc < i1) ? p_ub + cc : i1;
+    const uint32_t mine = hi > lo ? (uint32_t)(hi - lo) : 0u;
+    const uint32_t rounds = (uint32_t)block_max(mine, sh.red);
+    for (uint32_t r = 0; r < rounds; ++r) {  // block-uniform
+      if (r < mine) {
+        const uint64_t e = lo + r;
+        const uint32_t entry = nd.stage[(sb + ub) * kB + (e - p_ub)];
+        nd.log[(base_f + e) & nd.log_mask] = entry;
+        if (kDeliver) {
+          const uint32_t src = entry & kGidMask;
+          const uint64_t mask = nd.src_mask[src];
+          const uint32_t gp = nd.grp_ptr[src];
+          SpikeRec sr;
+          sr.entry = entry; sr.grp_ptr = gp; sr.mask = mask;
+          rec[e] = sr;
+          dlv_probe(nd, sh, entry, gp, mask, 2);
+        }
+      }
+      if (kDeliver) {
+        __syncthreads();
+        if (sh.npair > (uint32_t)(kSelChunk - kB)) {  // LDS nearly full: deliver now
+          pairs += sh.npair;
+          events += dlv_flush(nd, sh, acc);
+        }
+      }
+    }
+    run += tsum;
   }
-  const uint64_t base_n = (n == 0) ? 0 : nd.ring_base[(n - 1) % R] + nd.ring_cnt[(n - 1) % R];
-  // |S_n|: spikes staged by the update blocks of step n
+}
+
+// Delivery blocks of step n: the input of step n+1 from the spikes of step
+// n-1 (delay 2; read from the update blocks' lists of that step, which these
+// blocks also append to the raster ring and record) and of steps
+// n-2 .. n+1-Dmax (delays >= 3; from the recent-spike records).  Block b owns
+// an equal share of all these items (one item = one in-flight spike).
+__device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t G, DlvLds& sh) {
+  const uint32_t R = nd.R, dmax = nd.dmax;
+  dlv_load_classes(nd, sh);
+  const uint32_t dseg = threadIdx.x + 1;  // delay of this item segment (threads 0..63)
+  uint64_t cnt = 0;
+  uint32_t slt = 0;
+  if (threadIdx.x < 64 && dseg >= 3 && dseg <= dmax && n + 1 >= dseg) {
+    slt = (uint32_t)((n + 1 - dseg) % R);
+    cnt = nd.ring_cnt[slt];
+  }
+  uint64_t base1 = 0;
+  if (n >= 2) base1 = nd.ring_base[(n - 2) % R] + nd.ring_cnt[(n - 2) % R];
   uint64_t c = 0;
-  for (uint32_t ub = threadIdx.x; ub < nd.nblk_upd; ub += kB) c += nd.stage_cnt[ub];
-  const uint64_t tot = block_sum(c, red);
+  if (n >= 1) {
+    const size_t sb = (size_t)((n - 1) & 1) * nd.nblk_upd;
+    for (uint32_t ub = threadIdx.x; ub < nd.nblk_upd; ub += kB) c += nd.stage_cnt[sb + ub];
+  }
+  const uint64_t tot1 = block_sum(c, sh.red);  // spikes of step n-1
   if (threadIdx.x < 64) {
-    if (dseg == 1) { cnt = tot; bb = base_n; }
+    if (dseg == 2) cnt = tot1;
     const uint64_t incl = wave_incl_scan(cnt);
-    seg[dseg] = incl - cnt;
-    if (dseg == 64) seg[65] = incl;
-    sbase[dseg] = bb;
+    sh.seg[dseg] = incl - cnt;
+    if (dseg == 64) sh.seg[65] = incl;
+    sh.slot[dseg] = slt;
   }
   __syncthreads();
-  const uint64_t items = seg[65];
-  const uint64_t G = gridDim.x;
+  const uint64_t items = sh.seg[65];
   const uint64_t ipb = (items + G - 1) / G;
-  const uint64_t i0 = blockIdx.x * ipb;
+  const uint64_t i0 = (uint64_t)b * ipb;
   const uint64_t i1 = (i0 + ipb < items) ? i0 + ipb : items;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    nd.ring_base[n % R] = base_n;
-    nd.ring_cnt[n % R] = (uint32_t)tot;
-    nd.chunk_base[n & (nd.chunk_ring - 1)] = base_n;
-    nd.ctrl->tot_spikes += tot;
+  if (b == 0 && threadIdx.x == 0 && n >= 1) {
+    nd.ring_base[(n - 1) % R] = base1;
+    nd.ring_cnt[(n - 1) % R] = (uint32_t)tot1;
+    nd.chunk_base[(n - 1) & (nd.chunk_ring - 1)] = base1;
   }
-  // copy this block's share of step n's spikes into the ring (gid order)
-  const uint64_t e1 = (i1 < tot) ? i1 : tot;
-  if (i0 < e1) {
-    uint64_t run = 0;
-    for (uint32_t t0 = 0; t0 < nd.nblk_upd && run < e1; t0 += kB) {
-      const uint32_t ub = t0 + threadIdx.x;
-      const uint32_t cc = (ub < nd.nblk_upd) ? nd.stage_cnt[ub] : 0;
-      uint64_t tsum;
-      const uint64_t p_ub = run + block_excl_scan(cc, red, &tsum);
-      const uint64_t lo = p_ub > i0 ? p_ub : i0;
-      const uint64_t hi = (p_ub + cc < e1) ? p_ub + cc : e1;
-      for (uint64_t e = lo; e < hi; ++e) nd.log[(base_n + e) & nd.log_mask] = nd.stage[(size_t)ub * kB + (e - p_ub)];
-      run += tsum;
-    }
-  }
-  __syncthreads();  // the block reads back only the ring entries it wrote itself
   int64_t* acc = nd.acc + (size_t)((n + 1) & 1) * nd.N * nd.P;
-  const uint32_t P = nd.P;
-  uint64_t blk_pairs = 0, blk_events = 0;
-  for (uint64_t c0 = i0; c0 < i1; c0 += kSelChunk) {  // block-uniform
-    if (threadIdx.x == 0) npair = 0;
-    __syncthreads();
+  uint64_t pairs = 0, events = 0;
+  // delay 2: spikes of step n-1
+  const uint64_t e1 = (i1 < tot1) ? i1 : tot1;
+  if (i0 < e1) walk_step<true>(nd, n - 1, base1, i0, e1, sh, acc, pairs, events);
+  __syncthreads();
+  if (sh.npair > 0) {
+    pairs += sh.npair;
+    events += dlv_flush(nd, sh, acc);
+  }
+  // delays >= 3: recent-spike records
+  const uint64_t s0 = (i0 > tot1) ? i0 : tot1;
+  for (uint64_t c0 = s0; c0 < i1; c0 += kSelChunk) {  // block-uniform
 #pragma unroll
     for (int q = 0; q < kSelPerThread; ++q) {
       const uint64_t e = c0 + (uint64_t)q * kB + threadIdx.x;
       if (e >= i1) continue;
-      uint32_t d = 1;
-      while (d < 64 && seg[d + 1] <= e) ++d;
-      const uint32_t entry = nd.log[(sbase[d] + (e - seg[d])) & nd.log_mask];
-      const uint32_t src = entry & kGidMask;
-      if (src >= nd.N) {  // never true for entries written by this pipeline
-        atomicOr(&nd.ctrl->overflow, 4u);
-        continue;
-      }
-      const uint64_t mask = nd.src_mask[src];
-      if ((mask >> d) & 1ull) {
-        const uint32_t g = nd.grp_ptr[src] + (uint32_t)__popcll(mask & ((1ull << d) - 1ull));
-        const uint64_t off = nd.grp_off[g];
-        const uint32_t len = (uint32_t)(nd.grp_off[g + 1] - off);
-        const uint32_t k = atomicAdd(&npair, 1u);  // LDS counter, k < kSelChunk
-        p_off[k] = off;
-        p_len[k] = len;
-        p_mult[k] = entry >> kMultShift;
-      }
+      uint32_t d = 3;
+      while (d < 64 && sh.seg[d + 1] <= e) ++d;
+      const SpikeRec r = nd.recent[(size_t)sh.slot[d] * nd.N + (e - sh.seg[d])];
+      dlv_probe(nd, sh, r.entry, r.grp_ptr, r.mask, d);
     }
     __syncthreads();
-    const uint32_t np = npair;
-    // exclusive prefix of the group sizes (each thread owns kSelPerThread records)
-    uint32_t L[kSelPerThread];
-    uint64_t lsum = 0;
-#pragma unroll
-    for (int q = 0; q < kSelPerThread; ++q) {
-      const uint32_t i = threadIdx.x * kSelPerThread + q;
-      L[q] = (i < np) ? p_len[i] : 0u;
-      lsum += L[q];
-    }
-    uint64_t ev;
-    uint64_t run = block_excl_scan(lsum, red, &ev);
-#pragma unroll
-    for (int q = 0; q < kSelPerThread; ++q) {
-      const uint32_t i = threadIdx.x * kSelPerThread + q;
-      if (i < np) p_st[i] = run;
-      run += L[q];
-    }
-    __syncthreads();
-    for (uint64_t e = threadIdx.x; e < ev; e += kB) {
-      uint32_t lo = 0, hi = np;  // last record with p_st <= e
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (p_st[mid] <= e) lo = mid; else hi = mid;
-      }
-      const uint32_t pl = nd.payload[p_off[lo] + (e - p_st[lo])];
-      const uint32_t cls = pl & cls_mask;
-      const int64_t v = wq[cls] * (int64_t)p_mult[lo];
-      __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> cls_bits) * P + wp[cls]],
-                             (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    blk_pairs += np;
-    blk_events += ev;
-    __syncthreads();
+    pairs += sh.npair;
+    events += dlv_flush(nd, sh, acc);
   }
   if (threadIdx.x == 0) {
-    nd.sel_stats[2 * blockIdx.x] += blk_pairs;
-    nd.sel_stats[2 * blockIdx.x + 1] += blk_events;
+    __hip_atomic_fetch_add((unsigned long long*)&nd.sel_stats[2 * b], (unsigned long long)pairs, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add((unsigned long long*)&nd.sel_stats[2 * b + 1], (unsigned long long)events,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// One simulation step n: blocks [0, nblk_upd) update the neurons (LIF exact
+// integration, Sec. 2.1/2.3; AdEx RK45, Sec. 2.1/2.4), stage their spikes and
+// deliver their delay-1 groups; the remaining blocks deliver the earlier
+// steps' spikes whose delay expires now.  All deliveries go to the input of
+// step n+1, the update reads the input of step n (double-buffered by parity).
+template <bool kLif, bool kAdexOn, int P>
+__global__ void __launch_bounds__(kB) k_step(NetDev nd, uint32_t rel) {
+  __shared__ StepLds lds;
+  const uint64_t n = nd.ctrl->step_base + rel;
+  if (blockIdx.x < nd.nblk_upd) {
+    update_block<kLif, kAdexOn, P>(nd, n, blockIdx.x, lds.upd);
+  } else {
+    deliver_block(nd, n, blockIdx.x - nd.nblk_upd, gridDim.x - nd.nblk_upd, lds.dlv);
+  }
+}
+
+// Raster ring for the last simulated step (step_base - 1): its spikes are
+// otherwise appended by the next step's delivery blocks.  Idempotent.
+__global__ void __launch_bounds__(kB) k_log_tail(NetDev nd) {
+  __shared__ DlvLds sh;
+  const uint64_t sbase = nd.ctrl->step_base;
+  if (sbase == 0) return;  // block-uniform
+  const uint64_t f = sbase - 1;
+  const uint32_t R = nd.R;
+  const uint64_t base_f = (f >= 1) ? nd.ring_base[(f - 1) % R] + nd.ring_cnt[(f - 1) % R] : 0;
+  const size_t sb = (size_t)(f & 1) * nd.nblk_upd;
+  uint64_t c = 0;
+  for (uint32_t ub = threadIdx.x; ub < nd.nblk_upd; ub += kB) c += nd.stage_cnt[sb + ub];
+  const uint64_t tot = block_sum(c, sh.red);
+  const uint64_t G = gridDim.x;
+  const uint64_t ipb = (tot + G - 1) / G;
+  const uint64_t i0 = blockIdx.x * ipb;
+  const uint64_t i1 = (i0 + ipb < tot) ? i0 + ipb : tot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    nd.ring_base[f % R] = base_f;
+    nd.ring_cnt[f % R] = (uint32_t)tot;
+    nd.chunk_base[f & (nd.chunk_ring - 1)] = base_f;
+  }
+  uint64_t pairs = 0, events = 0;
+  if (i0 < i1) walk_step<false>(nd, f, base_f, i0, i1, sh, nullptr, pairs, events);
 }
 
 __global__ void k_advance(Ctrl* ctrl, uint32_t steps) {
@@ -505,29 +685,29 @@ static void launch(K kernel, dim3 grid, dim3 blk, hipStream_t s, hipEvent_t star
   else hipLaunchKernelGGL(kernel, grid, blk, 0, s, args...);
 }
 
-hipError_t launch_update(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+hipError_t launch_step(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
   // which models are present is encoded in nd.pad0: bit 0 LIF, bit 1 AdEx
   const bool lif = nd.pad0 & 1u, adex = nd.pad0 & 2u;
-  const dim3 grid(nd.nblk_upd), blk(kB);
+  const dim3 grid(nd.nblk_upd + nd.sel_grid), blk(kB);
   if (!adex) {
-    launch(k_update<true, false, 1>, grid, blk, s, start, stop, nd, rel);
+    launch(k_step<true, false, 1>, grid, blk, s, start, stop, nd, rel);
   } else {
     switch (nd.P) {
-      case 1: if (lif) launch(k_update<true, true, 1>, grid, blk, s, start, stop, nd, rel);
-              else launch(k_update<false, true, 1>, grid, blk, s, start, stop, nd, rel); break;
-      case 2: if (lif) launch(k_update<true, true, 2>, grid, blk, s, start, stop, nd, rel);
-              else launch(k_update<false, true, 2>, grid, blk, s, start, stop, nd, rel); break;
-      case 3: if (lif) launch(k_update<true, true, 3>, grid, blk, s, start, stop, nd, rel);
-              else launch(k_update<false, true, 3>, grid, blk, s, start, stop, nd, rel); break;
-      default: if (lif) launch(k_update<true, true, 4>, grid, blk, s, start, stop, nd, rel);
-               else launch(k_update<false, true, 4>, grid, blk, s, start, stop, nd, rel); break;
+      case 1: if (lif) launch(k_step<true, true, 1>, grid, blk, s, start, stop, nd, rel);
+              else launch(k_step<false, true, 1>, grid, blk, s, start, stop, nd, rel); break;
+      case 2: if (lif) launch(k_step<true, true, 2>, grid, blk, s, start, stop, nd, rel);
+              else launch(k_step<false, true, 2>, grid, blk, s, start, stop, nd, rel); break;
+      case 3: if (lif) launch(k_step<true, true, 3>, grid, blk, s, start, stop, nd, rel);
+              else launch(k_step<false, true, 3>, grid, blk, s, start, stop, nd, rel); break;
+      default: if (lif) launch(k_step<true, true, 4>, grid, blk, s, start, stop, nd, rel);
+               else launch(k_step<false, true, 4>, grid, blk, s, start, stop, nd, rel); break;
     }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_select_deliver(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
-  launch(k_select_deliver, dim3(nd.sel_grid), dim3(kB), s, start, stop, nd, rel);
+hipError_t launch_log_tail(const NetDev& nd, hipStream_t s) {
+  hipLaunchKernelGGL(k_log_tail, dim3(nd.fresh_grid), dim3(kB), 0, s, nd);
   return hipGetLastError();
 }
 

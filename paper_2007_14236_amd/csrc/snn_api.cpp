@@ -3,7 +3,7 @@
 // Owns the network description, the host-side tables the kernels read
 // (propagators, fixed-point exponents, weight classes, delay and Poisson
 // thresholds), device memory, the build sequence and the step loop (hipGraph
-// of K steps of update -> select+deliver, replayed; the spike
+// of K one-kernel steps plus a raster tail, replayed; the spike
 // ring is drained to the host raster between replays).
 #include <hip/hip_runtime.h>
 
@@ -884,13 +884,13 @@ snn_status snn_build(snn_net* net) {
   // ---- spike buffers ----
   net->drain_steps = std::max<uint64_t>(kGraphSteps, std::min<uint64_t>(1000, ((1ull << 25) / N) / kGraphSteps * kGraphSteps));
   net->log_cap = next_pow2((uint64_t)N * (nd.R + net->drain_steps + kGraphSteps + 1));
-  uint32_t* d_stage; ALLOC(d_stage, uint32_t, (size_t)nd.nblk_upd * kUpdBlock);
-  uint32_t* d_scnt; ALLOC(d_scnt, uint32_t, nd.nblk_upd);
+  uint32_t* d_stage; ALLOC(d_stage, uint32_t, (size_t)2 * nd.nblk_upd * kUpdBlock);
+  uint32_t* d_scnt; ALLOC(d_scnt, uint32_t, (size_t)2 * nd.nblk_upd);
   uint32_t* d_log; ALLOC(d_log, uint32_t, net->log_cap);
   uint64_t* d_rb; ALLOC(d_rb, uint64_t, nd.R);
   uint32_t* d_rc; ALLOC(d_rc, uint32_t, nd.R);
   uint64_t* d_cb; ALLOC(d_cb, uint64_t, kChunkRing);
-  HIPCHK(net, hipMemsetAsync(d_scnt, 0, nd.nblk_upd * 4, s));
+  HIPCHK(net, hipMemsetAsync(d_scnt, 0, (size_t)2 * nd.nblk_upd * 4, s));
   HIPCHK(net, hipMemsetAsync(d_rb, 0, nd.R * 8, s));
   HIPCHK(net, hipMemsetAsync(d_rc, 0, nd.R * 4, s));
   HIPCHK(net, hipMemsetAsync(d_cb, 0, kChunkRing * 8, s));
@@ -899,10 +899,13 @@ snn_status snn_build(snn_net* net) {
 
   // ---- selection / delivery ----
   nd.sel_grid = std::min<uint32_t>(2048, std::max<uint32_t>(64, nd.nblk_upd));
-  ALLOC(nd.sel_stats, uint64_t, (size_t)2 * nd.sel_grid);
-  HIPCHK(net, hipMemsetAsync(nd.sel_stats, 0, (size_t)2 * nd.sel_grid * 8, s));
-  ALLOC(nd.blk_stats, uint64_t, (size_t)2 * nd.nblk_upd);
-  HIPCHK(net, hipMemsetAsync(nd.blk_stats, 0, (size_t)2 * nd.nblk_upd * 8, s));
+  nd.fresh_grid = std::min<uint32_t>(256, std::max<uint32_t>(16, nd.nblk_upd));
+  const size_t nstat = (size_t)2 * nd.sel_grid;
+  ALLOC(nd.sel_stats, uint64_t, nstat);
+  HIPCHK(net, hipMemsetAsync(nd.sel_stats, 0, nstat * 8, s));
+  ALLOC(nd.recent, SpikeRec, (size_t)nd.R * N);
+  ALLOC(nd.blk_stats, uint64_t, (size_t)kBlkStats * nd.nblk_upd);
+  HIPCHK(net, hipMemsetAsync(nd.blk_stats, 0, (size_t)kBlkStats * nd.nblk_upd * 8, s));
   ALLOC(nd.ctrl, Ctrl, 1);
   HIPCHK(net, hipMemsetAsync(nd.ctrl, 0, sizeof(Ctrl), s));
   net->pinned_words = 0;
@@ -953,19 +956,17 @@ snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms) {
   if (!net->built) return fail(net, SNN_E_STATE, "profile before snn_build");
   snn_status st = enter(net);
   if (st) return st;
-  hipEvent_t ev[4];
+  hipEvent_t ev[2];
   for (auto& e : ev) HIPCHK(net, hipEventCreate(&e));
   const auto t0 = std::chrono::steady_clock::now();
   for (uint64_t k = 0; k < steps; ++k) {
-    HIPCHK(net, launch_update(net->nd, 0, net->stream, ev[0], ev[1]));
-    HIPCHK(net, launch_select_deliver(net->nd, 0, net->stream, ev[2], ev[3]));
+    HIPCHK(net, launch_step(net->nd, 0, net->stream, ev[0], ev[1]));
     HIPCHK(net, launch_advance(net->nd.ctrl, 1, net->stream));
-    HIPCHK(net, hipEventSynchronize(ev[3]));
-    for (int q = 0; q < 2; ++q) {
-      float ms = 0.f;
-      HIPCHK(net, hipEventElapsedTime(&ms, ev[2 * q], ev[2 * q + 1]));
-      kernel_ms[q] += ms;
-    }
+    HIPCHK(net, launch_log_tail(net->nd, net->stream));
+    HIPCHK(net, hipEventSynchronize(ev[1]));
+    float ms = 0.f;
+    HIPCHK(net, hipEventElapsedTime(&ms, ev[0], ev[1]));
+    kernel_ms[0] += ms;
     net->cur_step += 1;
     if (net->cur_step - net->drained_step >= net->drain_steps || k + 1 == steps) {
       st = drain(net);
@@ -1016,18 +1017,21 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   HIPCHK(net, hipMemcpy(&c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
   std::vector<uint64_t> ss((size_t)2 * net->nd.sel_grid);
   HIPCHK(net, hipMemcpy(ss.data(), net->nd.sel_stats, ss.size() * 8, hipMemcpyDeviceToHost));
-  for (size_t b = 0; b < net->nd.sel_grid; ++b) {
+  for (size_t b = 0; b < ss.size() / 2; ++b) {
     out->pairs += ss[2 * b];
     out->events += ss[2 * b + 1];
   }
-  std::vector<uint64_t> bs((size_t)2 * net->nd.nblk_upd);
+  std::vector<uint64_t> bs((size_t)kBlkStats * net->nd.nblk_upd);
   HIPCHK(net, hipMemcpy(bs.data(), net->nd.blk_stats, bs.size() * 8, hipMemcpyDeviceToHost));
   for (size_t b = 0; b < net->nd.nblk_upd; ++b) {
-    out->rk_accepted += bs[2 * b];
-    out->rk_rejected += bs[2 * b + 1];
+    const uint64_t* st = &bs[(size_t)kBlkStats * b];
+    out->rk_accepted += st[0];
+    out->rk_rejected += st[1];
+    out->spikes += st[2];
+    out->pairs += st[3];
+    out->events += st[4];
   }
   out->steps = net->cur_step;
-  out->spikes = c.tot_spikes;
   out->n_synapses = net->n_syn;
   out->n_groups = net->n_groups;
   out->device_bytes = net->dev_bytes;
@@ -1122,10 +1126,10 @@ snn_status record_graph(snn_net* net, uint32_t steps, hipGraphExec_t* out) {
   HIPCHK(net, hipStreamBeginCapture(net->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
   for (uint32_t r = 0; r < steps && e == hipSuccess; ++r) {
-    e = launch_update(net->nd, r, net->stream);
-    if (e == hipSuccess) e = launch_select_deliver(net->nd, r, net->stream);
+    e = launch_step(net->nd, r, net->stream);
   }
   if (e == hipSuccess) e = launch_advance(net->nd.ctrl, steps, net->stream);
+  if (e == hipSuccess) e = launch_log_tail(net->nd, net->stream);
   hipError_t e2 = hipStreamEndCapture(net->stream, &g);
   if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "capture: %s", hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(net, SNN_E_DEVICE, "end capture: %s", hipGetErrorString(e2));

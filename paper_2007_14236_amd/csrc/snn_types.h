@@ -10,9 +10,10 @@
 //     grp_off[G+1]  u64, first synapse of each group (groups ordered by delay)
 //     payload[S]    u32, target << b | weight class (class -> port, w_q),
 //                   b = 32 - bits(N), at most 1024 classes
-//   spike buffer: stage[nblk][256] per-update-block spike lists of the
-//     current step, log[CAP] ring of compacted per-step spike lists
-//     (gid | mult << 27) with ring_base/ring_cnt per step slot (Dmax + 1).
+//   spike buffer: stage[2][nblk][256] per-update-block spike lists of the
+//     last two steps, log[CAP] ring of compacted per-step spike lists
+//     (gid | mult << 27) with ring_base/ring_cnt per step slot (Dmax + 1),
+//     recent[Dmax + 1][N] selection records of the spikes in flight.
 //   selection and delivery keep the selected (synapse offset, group size,
 //     multiplicity) records in LDS only.
 #pragma once
@@ -28,6 +29,7 @@ constexpr int kMultShift = 27;
 constexpr uint32_t kGidMask = (1u << kMultShift) - 1;
 constexpr uint32_t kMaxMult = 31;
 constexpr int kUpdBlock = 256;      // neurons per update block (= stage segment)
+constexpr int kBlkStats = 5;   // per update block: rk accepted, rk rejected, spikes, delay-1 pairs, events
 constexpr int kTagConn = 1;
 constexpr int kTagPoisson = 2;
 
@@ -68,6 +70,14 @@ struct ProjDev {
   uint64_t thr[64];        // delay thresholds, thr[d] for d = 1..Dmax
 };
 
+// Selection record of a recent spike: gid | mult << 27, the source's first
+// group and its delay mask (looked up once, when the spike is emitted).
+struct SpikeRec {
+  uint32_t entry;
+  uint32_t grp_ptr;
+  uint64_t mask;
+};
+
 // Scalars written by the kernels.
 struct Ctrl {
   uint64_t step_base;      // absolute step of relative step 0 of a launch
@@ -79,7 +89,8 @@ struct Ctrl {
 struct NetDev {
   uint32_t N, P, npop, dmax;   // dmax = largest delay present (ring has dmax+1 slots)
   uint32_t npois, pad2;        // Poisson threshold tables
-  uint32_t R, nblk_upd, sel_grid, pad0;
+  uint32_t R, nblk_upd, sel_grid, pad0;  // pad0: bit 0 LIF present, bit 1 AdEx present
+  uint32_t fresh_grid, pad3;
   uint64_t log_mask;           // CAP - 1
   uint64_t chunk_ring;         // slots of chunk_base (power of two)
   uint64_t n_groups, n_syn;
@@ -96,9 +107,10 @@ struct NetDev {
   // spikes
   uint32_t* stage; uint32_t* stage_cnt;
   uint32_t* log; uint64_t* ring_base; uint32_t* ring_cnt; uint64_t* chunk_base;
+  SpikeRec* recent;            // [R][N] selection records of the last R steps' spikes
   // selection / delivery
-  uint64_t* sel_stats;         // [sel_grid][2]: pairs and events selected (cumulative)
-  // per-block statistics of the update kernel: [nblk_upd][2] (rk accepted, rejected)
+  uint64_t* sel_stats;         // [sel_grid][2]: pairs and events delivered by delivery blocks (cumulative)
+  // per-update-block statistics [nblk_upd][kBlkStats]
   uint64_t* blk_stats;
   Ctrl* ctrl;
 };

@@ -230,9 +230,9 @@ class Net:
 
     def profile(self, steps: int) -> dict:
         """Advance `steps` steps with per-kernel HIP event timing (ms summed)."""
-        ms = np.zeros(2, dtype=np.float64)
+        ms = np.zeros(1, dtype=np.float64)
         self._check(self.L.snn_profile_steps(self.h, int(steps), _ptr(ms, C.c_double)))
-        return dict(update=ms[0], select_deliver=ms[1])
+        return dict(step=ms[0])
 
     def set_state(self, var: str, first: int, values, port: int = 0, n: int | None = None):
         v = np.ascontiguousarray(values, dtype=np.float64)
