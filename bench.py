@@ -30,12 +30,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "real-time factor & synaptic events/s on 1 GPU; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the select+deliver kernel: per delivered synapse one
-# 4-byte synapse word read and one int64 accumulator read-modify-write
-# (16 B); per selected (source, group) pair the 8-byte delay mask, 4-byte
-# group index and two 8-byte group offsets (28 B, rounded to 16 + 8 + 4).
-DLV_BYTES_PER_EVENT = 4 + 16
-DLV_BYTES_PER_PAIR = 28
+# Algorithmic HBM bytes of one step kernel (update + delivery):
+#  - per delivered synapse: its 4-byte synapse word, plus
+#      direct: one int64 accumulator read-modify-write (16 B),
+#      binned: one 4-byte bin entry written and read back (8 B);
+#  - per selected (source, delay-group) pair: 8-byte delay mask, 4-byte group
+#    index, two 8-byte group offsets (28 B);
+#  - per spike: stage entry written and read, raster entry, 16-byte record (28 B);
+#  - per neuron: its state read and written (LIF: V, refractory count,
+#    P synaptic currents; AdEx: V, w, h, P conductances) and I_e read;
+#    direct delivery also reads its P int64 inputs.
+BYTES_PER_EVENT = {"direct": 4 + 16, "binned": 4 + 8}
+BYTES_PER_PAIR = 28
+BYTES_PER_SPIKE = 28
+
+
+def bytes_per_step_neurons(spec: dict, delivery: str) -> int:
+    tot = 0
+    for p in spec["populations"]:
+        ports = p["ports"]
+        if p["model"] == "aeif_cond_exp":
+            b = 8 * 3 + 8 * ports + 4
+        elif p["model"] == "lif_exp":
+            b = 8 * 2 + 8 * ports + 4
+        else:
+            b = 8 * 2 + 4
+        if delivery == "direct":
+            b += 8 * ports
+        tot += b * p["n"]
+    return tot
 
 
 def parse():
@@ -53,6 +76,10 @@ def parse():
     ap.add_argument("--instances", type=int, default=128, help="sweep: number of instances")
     ap.add_argument("--seq-instances", type=int, default=16,
                     help="sweep: instances also run one by one (sequential baseline sample)")
+    ap.add_argument("--delivery", choices=["auto", "direct", "binned"], default="auto",
+                    help="how events are summed: device atomics, or bins per target tile summed in LDS")
+    ap.add_argument("--tile-neurons", type=int, default=0, help="binned delivery: neurons per tile (0: library)")
+    ap.add_argument("--bin-capacity", type=int, default=0, help="binned delivery: entries per tile bin (0: library)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -121,8 +148,9 @@ def main():
     print(f"[bench] building {spec['name']}: {W.total_neurons(spec)} neurons, "
           f"{W.count_synapses(spec):.4g} synapses", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    net = S.Net(spec)
+    net = S.Net(spec, delivery=args.delivery, tile_neurons=args.tile_neurons, bin_capacity=args.bin_capacity)
     build_s = time.perf_counter() - t0
+    mode = "binned" if net.counters()["delivery"] == 2 else "direct"
     net.simulate(args.warmup)
     torch.cuda.synchronize()
     c0 = net.counters()
@@ -148,16 +176,22 @@ def main():
     ps = max(1, args.profile_steps)
     ev_p = (c3["events"] - c2["events"]) / ps
     pr_p = (c3["pairs"] - c2["pairs"]) / ps
+    sp_p = (c3["spikes"] - c2["spikes"]) / ps
     dlv_ms = prof["step"] / ps
     dominant = max(prof, key=prof.get)
-    dlv_bytes = ev_p * DLV_BYTES_PER_EVENT + pr_p * DLV_BYTES_PER_PAIR
+    neuron_bytes = bytes_per_step_neurons(spec, mode)
+    dlv_bytes = neuron_bytes + ev_p * BYTES_PER_EVENT[mode] + pr_p * BYTES_PER_PAIR + sp_p * BYTES_PER_SPIKE
     achieved = dlv_bytes / (dlv_ms * 1e-3) / 1e9 if dlv_ms > 0 else 0.0
     roofline = {
-        "kernel": "k_step", "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "kernel": "k_step_binned" if mode == "binned" else "k_step", "bound": "hbm",
+        "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
         "avg_launch_us": round(dlv_ms * 1e3, 3), "bytes_per_launch": round(dlv_bytes),
+        "neuron_bytes_per_launch": neuron_bytes,
         "events_per_launch": round(ev_p, 1), "pairs_per_launch": round(pr_p, 1),
-        "atomics_per_s": round(ev_p / (dlv_ms * 1e-3), 1) if dlv_ms > 0 else None,
+        "spikes_per_launch": round(sp_p, 1), "delivery": mode, "tile_neurons": c3["tile_neurons"],
+        "spill_events": c3["spill_events"],
+        "events_per_s_in_kernel": round(ev_p / (dlv_ms * 1e-3), 1) if dlv_ms > 0 else None,
         "kernel_us_per_step": {k: round(v * 1e3 / ps, 3) for k, v in prof.items()},
         "dominant_kernel_by_time": dominant,
     }
@@ -211,8 +245,10 @@ def bench_sweep(args, S, W, torch):
     specs = [W.brunel_sweep_instance(i) for i in range(args.instances)]
     steps = args.steps
     t0 = time.perf_counter()
-    net = S.Net(specs, record=True)
+    net = S.Net(specs, record=True, delivery=args.delivery, tile_neurons=args.tile_neurons,
+                bin_capacity=args.bin_capacity)
     build_s = time.perf_counter() - t0
+    mode = "binned" if net.counters()["delivery"] == 2 else "direct"
     net.simulate(args.warmup)
     torch.cuda.synchronize()
     c0 = net.counters()
@@ -228,7 +264,8 @@ def bench_sweep(args, S, W, torch):
     nseq = min(args.seq_instances, args.instances)
     seq_wall, seq_events = 0.0, 0
     for i in range(nseq):
-        n1 = S.Net(specs[i], record=True)
+        n1 = S.Net(specs[i], record=True, delivery=args.delivery, tile_neurons=args.tile_neurons,
+                   bin_capacity=args.bin_capacity)
         n1.simulate(args.warmup)
         torch.cuda.synchronize()
         e0 = n1.counters()["events"]
@@ -244,7 +281,7 @@ def bench_sweep(args, S, W, torch):
     out = {"metric": METRIC, "value": events / wall, "unit": "events/s", "n_gpus": 1, "steps": steps,
            "warmup": args.warmup, "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32 state, i64 fixed-point input", "data": "synthetic",
-           "rtf": wall / bio, "build_s": build_s,
+           "rtf": wall / bio, "build_s": build_s, "delivery": mode,
            "batched_instance_seconds_per_wall_second": args.instances * bio / wall,
            "sequential_sample": {"instances": nseq, "wall_s": seq_wall, "events_per_s": seq_events / seq_wall,
                                  "estimated_wall_all_s": seq_est},

@@ -71,8 +71,23 @@ typedef struct snn_config {
   uint64_t seed;            /* key of the counter-based generator               */
   uint32_t max_delay_steps; /* Dmax, 1..63; longer delays fold into Dmax        */
   uint32_t flags;           /* SNN_F_* below                                    */
+  uint32_t tile_neurons;    /* binned delivery: neurons per target tile, a power
+                               of two in [256, 4096 / P2] with P2 the port count
+                               rounded up to a power of two; 0 = library choice */
+  uint32_t bin_capacity;    /* binned delivery: entries per tile bin (each of
+                               two parities); 0 = library choice, at most the
+                               number of synapses onto the tile.  Events beyond
+                               it are still delivered exactly (by atomics)    */
 } snn_config;
 #define SNN_F_NO_SPIKE_RECORD 1u /* do not keep the spike raster on the host */
+/* How a step's synaptic events are summed into the targets' integer inputs
+   (Sec. 2.2; the sum is the same either way).  Neither flag: binned for
+   networks with AdEx neurons when they fit its limits (at most 2048 tiles),
+   else direct. */
+#define SNN_F_DELIVERY_DIRECT 2u /* each event one device-scope int64 atomic add */
+#define SNN_F_DELIVERY_BINNED 4u /* each event a 32-bit entry in its target tile's
+                                    bin, summed in LDS by the tile's block at the
+                                    next step; SNN_E_UNSUPPORTED if it does not fit */
 
 /* neuron models (Sec. 2.1, 2.3, 2.4) */
 #define SNN_LIF_PSC_DELTA 0  /* LIF, delta PSCs: weights in mV, one port      */
@@ -128,6 +143,10 @@ typedef struct snn_counters {
   double simulate_ms;      /* wall time spent in snn_simulate                 */
   uint32_t overflow;       /* nonzero if a device-side range check failed     */
   uint32_t max_delay_used; /* largest delay (steps) present in the network    */
+  uint64_t spill_events;   /* binned delivery: events that found their tile's
+                              bin full and were added by atomics instead     */
+  uint32_t delivery;       /* 1 direct, 2 binned (after build)                */
+  uint32_t tile_neurons;   /* binned delivery: neurons per target tile        */
 } snn_counters;
 
 /* ---- lifecycle ---------------------------------------------------------- */

@@ -35,7 +35,10 @@ hipError_t launch_step(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t
 // Appends the spikes of the last simulated step to the raster ring.
 hipError_t launch_log_tail(const NetDev& nd, hipStream_t s);
 hipError_t launch_advance(Ctrl* ctrl, uint32_t steps, hipStream_t s);
-// model-specific update launchers (internal)
+// Binned delivery: add the pending bin entries of the step of parity `par` on
+// `port` for gids [first, first+n) to out[0..n) (device int64).
+hipError_t launch_pending_input(const NetDev& nd, uint32_t par, uint32_t first, uint32_t n, uint32_t port,
+                                int64_t* out, hipStream_t s);
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,
                                  hipStream_t s);
 

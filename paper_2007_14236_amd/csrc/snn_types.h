@@ -3,7 +3,14 @@
 // HBM layout (all arrays device-resident for the life of the network):
 //   neuron state (SoA, fp32): V (LIF: V - E_L), I_e, and per model
 //     LIF-exp: I_syn[N][P];  AdEx: w, g[N][P], h;  refr (int32) for LIF.
-//   acc[2][N][P]  int64 fixed-point input, double-buffered by step parity.
+//   acc[2][N][P]  int64 fixed-point input, double-buffered by step parity
+//                 (direct delivery: all input; binned delivery: only the
+//                 events that did not fit their tile's bin).
+//   binned delivery: targets are cut into tiles of 2^tile_shift neurons;
+//     bins[2][bins_total] u32 entries local << 15 | mult << 10 | class, the
+//     tile t region at bin_off[t] holding up to bin_cap[t] entries,
+//     bin_cnt[2][n_tiles] entries written, ovf_flag[2][n_tiles] set when a
+//     tile's events spilled into acc.
 //   CSR by (source, delay group):
 //     src_mask[N]   u64, bit d set <=> source has a group with delay d steps
 //     grp_ptr[N+1]  u32, index of the source's first group
@@ -30,6 +37,10 @@ constexpr uint32_t kGidMask = (1u << kMultShift) - 1;
 constexpr uint32_t kMaxMult = 31;
 constexpr int kUpdBlock = 256;      // neurons per update block (= stage segment)
 constexpr int kBlkStats = 5;   // per update block: rk accepted, rk rejected, spikes, delay-1 pairs, events
+constexpr int kTileAccWords = 4096; // int64 LDS accumulators of a tile block (tile neurons x ports)
+constexpr uint32_t kMaxTiles = 2048; // tiles of the binned delivery
+constexpr int kBinLocalShift = 15;   // bin entry: local target << 15 | mult << 10 | class
+constexpr int kBinMultShift = 10;
 constexpr int kTagConn = 1;
 constexpr int kTagPoisson = 2;
 
@@ -83,7 +94,7 @@ struct Ctrl {
   uint64_t step_base;      // absolute step of relative step 0 of a launch
   uint32_t overflow;       // sticky flags (bit 0 mult, 1 rk iterations, 2 ranges)
   uint32_t pad;
-  uint64_t tot_spikes;
+  uint64_t spill_events;   // binned delivery: events that did not fit their tile's bin
 };
 
 struct NetDev {
@@ -91,6 +102,8 @@ struct NetDev {
   uint32_t npois, pad2;        // Poisson threshold tables
   uint32_t R, nblk_upd, sel_grid, pad0;  // pad0: bit 0 LIF present, bit 1 AdEx present
   uint32_t fresh_grid, pad3;
+  uint32_t n_tiles, tile_shift;  // binned delivery (n_tiles == 0: direct atomics)
+  uint64_t bins_total;           // bin entries per parity
   uint64_t log_mask;           // CAP - 1
   uint64_t chunk_ring;         // slots of chunk_base (power of two)
   uint64_t n_groups, n_syn;
@@ -104,6 +117,7 @@ struct NetDev {
   // CSR
   const uint64_t* src_mask; const uint32_t* grp_ptr; const uint64_t* grp_off; const uint32_t* payload;
   int64_t* acc;
+  uint32_t* bins; uint32_t* bin_cnt; uint32_t* ovf_flag; const uint64_t* bin_off; const uint32_t* bin_cap;
   // spikes
   uint32_t* stage; uint32_t* stage_cnt;
   uint32_t* log; uint64_t* ring_base; uint32_t* ring_cnt; uint64_t* chunk_base;

@@ -25,6 +25,9 @@ PORT_PARAMS = {"tau_syn": 0, "E_rev": 1}
 STATE = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6}
 DELAYS = {"const": 0, "uniform": 1, "normal": 2}
 F_NO_SPIKE_RECORD = 1
+F_DELIVERY_DIRECT = 2
+F_DELIVERY_BINNED = 4
+DELIVERY = {"auto": 0, "direct": F_DELIVERY_DIRECT, "binned": F_DELIVERY_BINNED}
 
 
 class SnnError(RuntimeError):
@@ -33,7 +36,7 @@ class SnnError(RuntimeError):
 
 class Config(C.Structure):
     _fields_ = [("dt_ms", C.c_double), ("seed", C.c_uint64), ("max_delay_steps", C.c_uint32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("tile_neurons", C.c_uint32), ("bin_capacity", C.c_uint32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -49,7 +52,8 @@ class Counters(C.Structure):
                 ("rk_accepted", C.c_uint64), ("rk_rejected", C.c_uint64), ("n_neurons", C.c_uint64),
                 ("n_synapses", C.c_uint64), ("n_groups", C.c_uint64), ("device_bytes", C.c_uint64),
                 ("build_ms", C.c_double), ("simulate_ms", C.c_double), ("overflow", C.c_uint32),
-                ("max_delay_used", C.c_uint32)]
+                ("max_delay_used", C.c_uint32), ("spill_events", C.c_uint64), ("delivery", C.c_uint32),
+                ("tile_neurons", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -144,7 +148,8 @@ class Net:
     batch of independent networks (one instance per specification) that
     advance together in the same kernels."""
 
-    def __init__(self, spec, allocator: TorchAllocator | None = None, record: bool = True, build: bool = True):
+    def __init__(self, spec, allocator: TorchAllocator | None = None, record: bool = True, build: bool = True,
+                 delivery: str = "auto", tile_neurons: int = 0, bin_capacity: int = 0):
         self.L = lib()
         specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
         self.spec = spec
@@ -153,7 +158,8 @@ class Net:
         for sp in specs:
             if sp["dt"] != dt or sp["dmax"] != dmax:
                 raise ValueError("all instances of a batch share dt and Dmax")
-        cfg = Config(dt, specs[0]["seed"], dmax, 0 if record else F_NO_SPIKE_RECORD)
+        flags = (0 if record else F_NO_SPIKE_RECORD) | DELIVERY[delivery]
+        cfg = Config(dt, specs[0]["seed"], dmax, flags, tile_neurons, bin_capacity)
         self._dev = self.alloc.device_struct()
         h = C.c_void_p()
         self._check(self.L.snn_create_net(C.byref(cfg), C.byref(self._dev), C.byref(h)), None)

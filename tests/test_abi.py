@@ -53,4 +53,11 @@ def test_argument_validation_without_device():
     assert L.snn_create_net(ctypes.byref(bad), None, ctypes.byref(out)) == -1
     bad = snn.Config(0.1, 1, 64, 0)  # Dmax above 63
     assert L.snn_create_net(ctypes.byref(bad), None, ctypes.byref(out)) == -1
+    bad = snn.Config(0.1, 1, 15, snn.F_DELIVERY_DIRECT | snn.F_DELIVERY_BINNED)  # two delivery modes
+    assert L.snn_create_net(ctypes.byref(bad), None, ctypes.byref(out)) == -1
+    bad = snn.Config(0.1, 1, 15, 1 << 7)  # unknown flag
+    assert L.snn_create_net(ctypes.byref(bad), None, ctypes.byref(out)) == -1
+    for tile in (128, 768, 8192):  # tile size: power of two in [256, 4096]
+        bad = snn.Config(0.1, 1, 15, 0, tile)
+        assert L.snn_create_net(ctypes.byref(bad), None, ctypes.byref(out)) == -1
     assert L.snn_build(None) == -1

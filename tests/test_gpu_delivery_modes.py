@@ -1,0 +1,127 @@
+"""GPU parity of the two ways a step's events are summed (direct device
+atomics; bins per target tile summed in LDS), across tile sizes and with bins
+too small for the traffic so that events spill into the atomic path: every
+configuration gives the oracle's rasters and per-step integer inputs
+exactly (the sum is over integers, so neither order nor route may change it).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2007_14236_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SPECS = {
+    "c0a": lambda: W.c0(True),
+    "brunel_ragged": lambda: W.brunel_lif(n=333, k=17, seed=7, delay=("uniform", 0.1, 2.0), dmax=25, nu_ext=300.0),
+    "brunel_k1_const": lambda: W.brunel_lif(n=50, k=1, seed=2, delay=("const", 0.1, 0.0), dmax=1, nu_ext=300.0),
+    "brunel_normal": lambda: W.brunel_lif(n=700, k=60, seed=11, delay=("normal", 1.5, 0.75), dmax=63, nu_ext=250.0),
+    "mc_small": lambda: W.microcircuit(scale=0.05, k_scale=0.25, k_ext=3500, seed=3),
+}
+
+# (delivery, tile_neurons, bin_capacity); capacity 24 makes busy tiles spill
+MODES = {
+    "direct": ("direct", 0, 0),
+    "binned_auto": ("binned", 0, 0),
+    "binned_t256": ("binned", 256, 0),
+    "binned_t512_spill": ("binned", 512, 24),
+}
+
+STEPS = 600
+_oracle_cache = {}
+
+
+@pytest.fixture(autouse=True)
+def _name(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def snn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_14236_amd import snn as S
+    S.lib()
+    return S
+
+
+def oracle_raster(name):
+    if name not in _oracle_cache:
+        o = O.OracleNet(SPECS[name](), O.FP32SO)
+        o.simulate(STEPS)
+        _oracle_cache[name] = (o.spikes(), o.get_state("V_m").astype(np.float32))
+    return _oracle_cache[name]
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("name", list(SPECS))
+def test_raster_bit_exact_every_mode(snn, name, mode):
+    delivery, tile, cap = MODES[mode]
+    g = snn.Net(SPECS[name](), delivery=delivery, tile_neurons=tile, bin_capacity=cap)
+    g.simulate(STEPS)
+    (os_, og, om), oV = oracle_raster(name)
+    gs, gg, gm = g.spikes()
+    assert np.array_equal(gs, os_) and np.array_equal(gg, og) and np.array_equal(gm, om)
+    assert np.array_equal(g.get_state("V_m").astype(np.float32), oV)
+    c = g.counters()
+    assert c["delivery"] == (1 if delivery == "direct" else 2)
+    if delivery == "binned":
+        assert c["tile_neurons"] == (tile or c["tile_neurons"]) and c["tile_neurons"] >= 256
+    assert c["overflow"] == 0
+
+
+def test_spill_path_is_taken_and_exact(snn):
+    """Tiny bins: most events spill; input per step still equals the oracle's."""
+    spec = W.c0(True)
+    steps = 80
+    o = O.OracleNet(spec, O.FP32SO)
+    rec = o.record_input(steps + 1)
+    o.simulate(steps + 1)
+    g = snn.Net(spec, delivery="binned", tile_neurons=256, bin_capacity=4)
+    for n in range(steps):
+        g.simulate(1)
+        assert np.array_equal(g.get_input(0), rec[n + 1][:, 0]), n
+    c = g.counters()
+    assert c["spill_events"] > 0 and c["events"] > c["spill_events"]
+
+
+@pytest.mark.parametrize("mode", ["direct", "binned_t256", "binned_t512_spill"])
+def test_adex_replay_every_mode(snn, mode):
+    """Two-port AdEx: the delivered input of both ports equals the oracle's
+    replay of the GPU's own spikes, in every mode."""
+    delivery, tile, cap = MODES[mode]
+    spec = W.adex_balanced(n=2000, k=200, seed=5)
+    g = snn.Net(spec, delivery=delivery, tile_neurons=tile, bin_capacity=cap)
+    o = O.OracleNet(spec)
+    steps = 150
+    for n in range(steps):
+        g.simulate(1)
+        if n % 15 == 14:
+            st, gid, m = g.spikes()
+            ref = o.replay_input(st, gid, m, n + 1)
+            for port in (0, 1):
+                assert np.array_equal(g.get_input(port), ref[:, port]), (n, port)
+    assert len(g.spikes()[0]) > 0
+
+
+def test_modes_count_the_same_events(snn):
+    spec = W.microcircuit(scale=0.05, k_scale=0.25, k_ext=3500, seed=3)
+    a = snn.Net(spec, delivery="direct")
+    b = snn.Net(spec, delivery="binned", tile_neurons=256)
+    a.simulate(400)
+    b.simulate(400)
+    ca, cb = a.counters(), b.counters()
+    for k in ("spikes", "events", "pairs"):
+        assert ca[k] == cb[k], k
+    assert ca["events"] > 0
+
+
+def test_binned_tile_too_large_for_ports_is_rejected(snn):
+    spec = W.adex_balanced(n=2000, k=200, seed=5)  # two ports: tiles of at most 2048 neurons
+    with pytest.raises(snn.SnnError):
+        snn.Net(spec, delivery="binned", tile_neurons=4096)
