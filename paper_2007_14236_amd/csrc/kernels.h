@@ -28,16 +28,15 @@ hipError_t launch_segsort(const uint64_t* grp_off, uint64_t n_groups, uint32_t* 
                           uint32_t* nbig, uint32_t big_cap, hipStream_t s);
 
 // ---- per-step pipeline (step = ctrl->step_base + rel) ----
-// One step: update + delay-1 delivery, and delivery of earlier steps' spikes.
-// With start/stop events the events are recorded on the kernel's own dispatch.
+// One step: update, spike emission and delay-1/-2 delivery, and delivery of
+// earlier steps' spikes.  With start/stop events the events are recorded on
+// the kernel's own dispatch.
 hipError_t launch_step(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start = nullptr,
                        hipEvent_t stop = nullptr);
-// Appends the spikes of the last simulated step to the raster ring.
-hipError_t launch_log_tail(const NetDev& nd, hipStream_t s);
 hipError_t launch_advance(Ctrl* ctrl, uint32_t steps, hipStream_t s);
-// Binned delivery: add the pending bin entries of the step of parity `par` on
-// `port` for gids [first, first+n) to out[0..n) (device int64).
-hipError_t launch_pending_input(const NetDev& nd, uint32_t par, uint32_t first, uint32_t n, uint32_t port,
+// Binned delivery: add the pending bin entries of input buffer `buf` on `port`
+// for gids [first, first+n) to out[0..n) (device int64).
+hipError_t launch_pending_input(const NetDev& nd, uint32_t buf, uint32_t first, uint32_t n, uint32_t port,
                                 int64_t* out, hipStream_t s);
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,
                                  hipStream_t s);

@@ -137,18 +137,45 @@ __device__ __forceinline__ bool lif_exp_step(const PopDev& pp, float& y, float* 
   return false;
 }
 
+// AdEx parameters of one neuron as the integrator uses them, held in
+// registers for the whole step (the population record may sit behind a
+// generic pointer that the compiler would otherwise reload every substep).
+template <int P>
+struct AdexPar {
+  float V_peak, g_L, gLDT, V_T, k_exp, E_L, inv_C, a, inv_tau_w, b, V_r;
+  float dt, hmin, inv_eps;
+  float E_rev[P], inv_tau_syn[P];
+};
+
+template <int P>
+__device__ __forceinline__ AdexPar<P> adex_par(const PopDev& pp) {
+  AdexPar<P> q;
+  q.V_peak = pp.V_peak; q.g_L = pp.g_L; q.V_T = pp.V_T;
+  q.gLDT = pp.g_L * pp.Delta_T;
+  q.k_exp = pp.inv_Delta_T * 1.4426950408889634f;  // exp(x / Delta_T) = 2^(x k_exp)
+  q.E_L = pp.E_L; q.inv_C = pp.inv_C; q.a = pp.a; q.inv_tau_w = pp.inv_tau_w; q.b = pp.b; q.V_r = pp.V_r;
+  q.dt = pp.dt;
+  // smallest substep: the configured floor, but never below 2^-22 dt so that
+  // t + h still advances in fp32
+  q.hmin = fmaxf(pp.rk_hmin, pp.dt * 2.384185791015625e-7f);
+  q.inv_eps = 1.f / pp.rk_eps;
+#pragma unroll
+  for (int p = 0; p < P; ++p) { q.E_rev[p] = pp.E_rev[p]; q.inv_tau_syn[p] = pp.inv_tau_syn[p]; }
+  return q;
+}
+
 // AdEx with exponential conductances (Sec. 2.4, Table 2), right-hand side in
 // fp32.  y = (V, w, g_0..g_{P-1}); the synaptic current is sum g_p (V - E_p)
 // entering with the sign that lets an excitatory conductance depolarise; the
 // exponential uses min(V, V_peak).
 template <int P>
-__device__ __forceinline__ void adex_rhs(const PopDev& pp, float Ie, const float* y, float* dy) {
+__device__ __forceinline__ void adex_rhs(const AdexPar<P>& pp, float Ie, const float* y, float* dy) {
   const float V = y[0], w = y[1];
   const float Vc = fminf(V, pp.V_peak);
   float isyn = 0.f;
 #pragma unroll
   for (int p = 0; p < P; ++p) isyn = __builtin_fmaf(y[2 + p], V - pp.E_rev[p], isyn);
-  const float ex = pp.g_L * pp.Delta_T * __expf((Vc - pp.V_T) * pp.inv_Delta_T);
+  const float ex = pp.gLDT * __builtin_amdgcn_exp2f((Vc - pp.V_T) * pp.k_exp);
   dy[0] = (__builtin_fmaf(-pp.g_L, V - pp.E_L, ex) - isyn - w + Ie) * pp.inv_C;
   dy[1] = __builtin_fmaf(pp.a, V - pp.E_L, -w) * pp.inv_tau_w;
 #pragma unroll
@@ -162,9 +189,11 @@ __device__ __forceinline__ void adex_rhs(const PopDev& pp, float Ie, const float
 // 0.9 e^-1/5 (<= 5x) on success; the last substep lands on the step end.  A
 // reset (V >= V_peak) is applied after every accepted substep.  t is the time
 // reached inside the step, it the attempts so far, mult the resets.  Returns
-// true when the step is complete (t = dt, or the attempt cap reached).
+// true when the step is complete (t = dt, or the attempt cap reached).  The
+// stage sums are fma chains; the error ratio uses the hardware reciprocal (it
+// only steers the step size).
 template <int P>
-__device__ __forceinline__ bool adex_substep(const PopDev& pp, float* y, float& h, float& t, uint32_t& it,
+__device__ __forceinline__ bool adex_substep(const AdexPar<P>& pp, float* y, float& h, float& t, uint32_t& it,
                                              uint32_t& mult, float Ie, uint32_t& nacc, uint32_t& nrej,
                                              bool& capped) {
   constexpr int NV = 2 + P;
@@ -181,9 +210,7 @@ __device__ __forceinline__ bool adex_substep(const PopDev& pp, float* y, float& 
               e4 = (float)(125.0 / 594.0 - 13525.0 / 55296.0), e5 = (float)(-277.0 / 14336.0),
               e6 = (float)(512.0 / 1771.0 - 0.25);
   const float errcon = 1.89e-4f;  // (5 / 0.9)^-5
-  // smallest substep: the configured floor, but never below 2^-22 dt so that
-  // t + h still advances in fp32
-  const float hmin = fmaxf(pp.rk_hmin, dt * 2.384185791015625e-7f);
+  const float hmin = pp.hmin;
   if (++it > kRkMaxIter) { capped = true; return true; }
   bool last = false;
   if (h >= dt - t) { h = dt - t; last = true; }
@@ -193,29 +220,38 @@ __device__ __forceinline__ bool adex_substep(const PopDev& pp, float* y, float& 
   for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(h, c21 * k1[i], y[i]);
   adex_rhs<P>(pp, Ie, yt, k2);
 #pragma unroll
-  for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(h, c31 * k1[i] + c32 * k2[i], y[i]);
+  for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(h, __builtin_fmaf(c32, k2[i], c31 * k1[i]), y[i]);
   adex_rhs<P>(pp, Ie, yt, k3);
 #pragma unroll
-  for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(h, c41 * k1[i] + c42 * k2[i] + c43 * k3[i], y[i]);
+  for (int i = 0; i < NV; ++i)
+    yt[i] = __builtin_fmaf(h, __builtin_fmaf(c43, k3[i], __builtin_fmaf(c42, k2[i], c41 * k1[i])), y[i]);
   adex_rhs<P>(pp, Ie, yt, k4);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
-    yt[i] = __builtin_fmaf(h, c51 * k1[i] + c52 * k2[i] + c53 * k3[i] + c54 * k4[i], y[i]);
+    yt[i] = __builtin_fmaf(
+        h, __builtin_fmaf(c54, k4[i], __builtin_fmaf(c53, k3[i], __builtin_fmaf(c52, k2[i], c51 * k1[i]))), y[i]);
   adex_rhs<P>(pp, Ie, yt, k5);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
-    yt[i] = __builtin_fmaf(h, c61 * k1[i] + c62 * k2[i] + c63 * k3[i] + c64 * k4[i] + c65 * k5[i], y[i]);
+    yt[i] = __builtin_fmaf(
+        h,
+        __builtin_fmaf(c65, k5[i],
+                       __builtin_fmaf(c64, k4[i], __builtin_fmaf(c63, k3[i], __builtin_fmaf(c62, k2[i], c61 * k1[i])))),
+        y[i]);
   adex_rhs<P>(pp, Ie, yt, k6);
   float errmax = 0.f;
   float y5[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    y5[i] = __builtin_fmaf(h, b1 * k1[i] + b3 * k3[i] + b4 * k4[i] + b6 * k6[i], y[i]);
-    const float err = h * (e1 * k1[i] + e3 * k3[i] + e4 * k4[i] + e5 * k5[i] + e6 * k6[i]);
+    y5[i] = __builtin_fmaf(
+        h, __builtin_fmaf(b6, k6[i], __builtin_fmaf(b4, k4[i], __builtin_fmaf(b3, k3[i], b1 * k1[i]))), y[i]);
+    const float err =
+        h * __builtin_fmaf(e6, k6[i],
+                           __builtin_fmaf(e5, k5[i], __builtin_fmaf(e4, k4[i], __builtin_fmaf(e3, k3[i], e1 * k1[i]))));
     const float scale = fabsf(y[i]) + fabsf(h * k1[i]) + 1.f;
-    errmax = fmaxf(errmax, fabsf(err) / scale);
+    errmax = fmaxf(errmax, fabsf(err) * __builtin_amdgcn_rcpf(scale));
   }
-  errmax = errmax / pp.rk_eps;
+  errmax = errmax * pp.inv_eps;
   if (errmax > 1.f && h > hmin) {
     const float ht = 0.9f * h * exp2f(-0.25f * __log2f(errmax));
     h = fmaxf(ht, 0.1f * h);
@@ -236,8 +272,9 @@ __device__ __forceinline__ bool adex_substep(const PopDev& pp, float* y, float& 
 // One dt of the AdEx model: substeps until the step end, h carried to the
 // next step (at most dt).  Returns the number of resets.
 template <int P>
-__device__ uint32_t adex_step(const PopDev& pp, float* y, float& h, float Ie, uint32_t& nacc, uint32_t& nrej,
+__device__ uint32_t adex_step(const PopDev& pop, float* y, float& h, float Ie, uint32_t& nacc, uint32_t& nrej,
                               bool& capped) {
+  const AdexPar<P> pp = adex_par<P>(pop);
   const float dt = pp.dt;
   if (!(h > 0.f) || h > dt) h = dt;
   float t = 0.f;
@@ -255,6 +292,7 @@ constexpr uint32_t kClsLds = 256; // weight classes cached in LDS by direct deli
 constexpr int kSelPerThread = kSelChunk / kB;
 constexpr uint32_t kTilePopLds = 8;  // population tables a tile block keeps in LDS
 constexpr int kTileSubs = kTileAccWords / kB;  // most 256-neuron sub-blocks of a tile
+constexpr uint32_t kHotCap = 256;  // AdEx neurons of a tile queued ahead of the others
 
 // LDS of the selection: the selected (source, delay-group) records of one
 // chunk and their exclusive prefix of group sizes.
@@ -263,6 +301,7 @@ struct SelLds {
   uint64_t p_st[kSelChunk];
   uint32_t p_len[kSelChunk];
   uint32_t p_mult[kSelChunk];
+  uint8_t p_buf[kSelChunk];  // direct delivery: input buffer of the pair's arrival step
   uint64_t red[kB / 64];
   uint64_t seg[66];
   uint32_t slot[66];
@@ -278,18 +317,28 @@ struct DirectLds : SelLds {
 // binned delivery: events per target tile of the chunk, then each tile's
 // reserved position in its bin
 struct BinLds : SelLds {
-  uint32_t tcnt[kMaxTiles];
-  uint32_t tbase[kMaxTiles];
+  uint32_t tcnt[kMaxTiles];   // events per tile, then the write cursor
+  uint32_t tbase[kMaxTiles];  // absolute bin index of the reserved range
+  uint32_t tavail[kMaxTiles]; // entries of the range inside the bin's capacity
 };
 
 // LDS of a direct-delivery update block
-struct UpdLds {
-  uint32_t wcnt[kB / 64];
-  uint64_t red[kB / 64];
-  unsigned long long d1[2];
+struct UpdTables {
   PopDev spops[kPopLds];
   uint64_t sthr[kPoisLds * kPoisKmax];
 };
+
+struct UpdLds {
+  uint32_t wcnt[kB / 64];
+  uint32_t emit;  // first position of the block's spikes in the step
+  uint64_t red[kB / 64];
+  union {
+    UpdTables t;  // population and Poisson tables, during the update
+    DirectLds d;  // selection of the block's delay-1 and delay-2 groups, after it
+  } u;
+};
+// the weight classes of DirectLds lie beyond the tables: loaded with them
+static_assert(sizeof(SelLds) >= sizeof(UpdTables), "class cache must not overlap the update tables");
 
 // LDS of a tile block: the tile's int64 input (dead after the update, then
 // reused by the delay-1 binning), weight classes, population and Poisson tables
@@ -298,14 +347,21 @@ struct TileLds {
     int64_t acc[kTileAccWords];
     BinLds d1;
   } u;
-  int64_t wq[kMaxClasses];
+  union {
+    int64_t wq[kMaxClasses];      // weight of each class: summing the bin
+    uint8_t mk[kTileAccWords];    // spike count of each neuron: after the update
+  } c;
   uint8_t wp[kMaxClasses];
   PopDev spops[kTilePopLds];
   uint64_t sthr[kPoisLds * kPoisKmax];
   uint32_t wcnt[kTileSubs][kB / 64];
   uint64_t red[kB / 64];
-  uint32_t sub_cnt[kTileSubs];
-  uint32_t next;  // AdEx work queue: next local neuron to take
+  uint32_t emit;  // first position of the tile's spikes in the step
+  // AdEx work queue: neurons at or above V_T (likely to spike and to need many
+  // substeps) first, from a short list, then the others in index order
+  uint32_t next, hq_next, hq_n;
+  uint16_t hq[kHotCap];
+  uint32_t hot[kTileAccWords / 32];
 };
 static_assert(sizeof(BinLds) <= sizeof(int64_t) * kTileAccWords, "delay-1 binning reuses the tile input");
 
@@ -319,9 +375,13 @@ union BinStepLds {
   BinLds dlv;
 };
 
-__device__ __forceinline__ void dlv_init(const NetDev& nd, DirectLds& sh) {
+__device__ __forceinline__ void dlv_load_classes(const NetDev& nd, DirectLds& sh) {
   const uint32_t nc = nd.n_classes < kClsLds ? nd.n_classes : kClsLds;
   for (uint32_t c = threadIdx.x; c < nc; c += kB) { sh.wq[c] = nd.cls_wq[c]; sh.wp[c] = nd.cls_port[c]; }
+}
+
+__device__ __forceinline__ void dlv_init(const NetDev& nd, DirectLds& sh) {
+  dlv_load_classes(nd, sh);
   if (threadIdx.x == 0) sh.npair = 0;
 }
 
@@ -334,16 +394,20 @@ __device__ __forceinline__ void dlv_init(const NetDev& nd, BinLds& sh) {
 // reaches a connection group now iff its source has a group of delay d (bit d
 // of the delay mask); that group's index among the source's groups, which are
 // ordered by delay, is the number of lower bits set.
+__device__ __forceinline__ void sel_add(SelLds& sh, uint64_t off, uint32_t len, uint32_t mult, uint32_t buf) {
+  const uint32_t k = atomicAdd(&sh.npair, 1u);  // LDS counter; callers keep k < kSelChunk
+  sh.p_off[k] = off;
+  sh.p_len[k] = len;
+  sh.p_mult[k] = mult;
+  sh.p_buf[k] = (uint8_t)buf;
+}
+
 __device__ __forceinline__ void dlv_probe(const NetDev& nd, SelLds& sh, uint32_t entry, uint32_t grp_ptr,
-                                          uint64_t mask, uint32_t d) {
+                                          uint64_t mask, uint32_t d, uint32_t buf) {
   if ((mask >> d) & 1ull) {
     const uint32_t g = grp_ptr + (uint32_t)__popcll(mask & ((1ull << d) - 1ull));
     const uint64_t off = nd.grp_off[g];
-    const uint32_t len = (uint32_t)(nd.grp_off[g + 1] - off);
-    const uint32_t k = atomicAdd(&sh.npair, 1u);  // LDS counter; callers keep k < kSelChunk
-    sh.p_off[k] = off;
-    sh.p_len[k] = len;
-    sh.p_mult[k] = entry >> kMultShift;
+    sel_add(sh, off, (uint32_t)(nd.grp_off[g + 1] - off), entry >> kMultShift, buf);
   }
 }
 
@@ -381,26 +445,54 @@ __device__ __forceinline__ uint32_t sel_find(const SelLds& sh, uint32_t np, uint
   return lo;
 }
 
+// Record holding flat event e >= p_st[lo]: a lane's events grow by the block
+// size between calls, which spans a few groups, so a short linear advance
+// usually suffices; otherwise binary search over the rest.
+__device__ __forceinline__ uint32_t sel_advance(const SelLds& sh, uint32_t np, uint32_t lo, uint64_t e) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (lo + 1 >= np || sh.p_st[lo + 1] > e) return lo;
+    ++lo;
+  }
+  uint32_t hi = np;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (sh.p_st[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Direct delivery of the chunk (flat scan of the synapses of its selected
 // groups): every synapse is one item, consecutive lanes take consecutive
 // synapses of a group, and each adds multiplicity x quantised weight to the
-// int64 input of its (target, port) for the step of parity par1 with a
-// device-scope atomic.  Called by the whole block after a barrier; returns
+// int64 input of its (target, port) in the input buffer of the pair's arrival
+// step with a device-scope atomic.  Called by the whole block after a barrier; returns
 // the events delivered and resets the chunk.
-__device__ uint64_t dlv_flush(const NetDev& nd, DirectLds& sh, uint32_t par1) {
+__device__ uint64_t dlv_flush(const NetDev& nd, DirectLds& sh, uint32_t /*buf: per pair*/) {
   const uint32_t np = sh.npair;
   const uint64_t ev = sel_scan(sh);
-  int64_t* acc = nd.acc + (size_t)par1 * nd.N * nd.P;
+  const size_t bstride = (size_t)nd.N * nd.P;
   const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u, P = nd.P;
-  for (uint64_t e = threadIdx.x; e < ev; e += kB) {
-    const uint32_t lo = sel_find(sh, np, e);
-    const uint32_t pl = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
-    const uint32_t cls = pl & cls_mask;
-    const bool in_lds = cls < kClsLds;
-    const int64_t v = (in_lds ? sh.wq[cls] : nd.cls_wq[cls]) * (int64_t)sh.p_mult[lo];
-    const uint32_t port = in_lds ? sh.wp[cls] : nd.cls_port[cls];
-    __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> cls_bits) * P + port],
-                           (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t lo = 0;
+  for (uint64_t e = threadIdx.x; e < ev; e += 2 * kB) {  // two independent events per lane and round
+    const uint64_t e1 = e + kB;
+    lo = sel_advance(sh, np, lo, e);
+    const uint32_t lo1 = (e1 < ev) ? sel_advance(sh, np, lo, e1) : lo;
+    const uint32_t pl0 = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
+    const uint32_t pl1 = (e1 < ev) ? nd.payload[sh.p_off[lo1] + (e1 - sh.p_st[lo1])] : 0u;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q == 1 && e1 >= ev) break;
+      const uint32_t pl = q ? pl1 : pl0, r = q ? lo1 : lo;
+      const uint32_t cls = pl & cls_mask;
+      const bool in_lds = cls < kClsLds;
+      const int64_t v = (in_lds ? sh.wq[cls] : nd.cls_wq[cls]) * (int64_t)sh.p_mult[r];
+      const uint32_t port = in_lds ? sh.wp[cls] : nd.cls_port[cls];
+      int64_t* acc = nd.acc + bstride * sh.p_buf[r];
+      __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> cls_bits) * P + port],
+                             (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    lo = lo1;
   }
   __syncthreads();
   if (threadIdx.x == 0) sh.npair = 0;
@@ -411,24 +503,25 @@ __device__ uint64_t dlv_flush(const NetDev& nd, DirectLds& sh, uint32_t par1) {
 // An event that found its tile's bin full: added to the spill accumulator of
 // its (target, port) and the tile flagged, so that the tile block of the next
 // step adds the spill to the bin's sum.
-__device__ __forceinline__ void bin_spill(const NetDev& nd, uint32_t par1, uint32_t tgt, uint32_t cls, uint32_t mult,
+__device__ __forceinline__ void bin_spill(const NetDev& nd, uint32_t buf, uint32_t tgt, uint32_t cls, uint32_t mult,
                                        uint32_t tile) {
   const int64_t v = nd.cls_wq[cls] * (int64_t)mult;
-  __hip_atomic_fetch_add((unsigned long long*)&nd.acc[((size_t)par1 * nd.N + tgt) * nd.P + nd.cls_port[cls]],
+  __hip_atomic_fetch_add((unsigned long long*)&nd.acc[((size_t)buf * nd.N + tgt) * nd.P + nd.cls_port[cls]],
                          (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  nd.ovf_flag[(size_t)par1 * nd.n_tiles + tile] = 1u;
+  nd.ovf_flag[(size_t)buf * nd.n_tiles + tile] = 1u;
   __hip_atomic_fetch_add((unsigned long long*)&nd.ctrl->spill_events, 1ull, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Binned delivery of the chunk: the same flat scan, but each event becomes
 // one 32-bit entry (local target, multiplicity, weight class) in the bin of
-// its target tile for the step of parity par1; the tile block of that step
+// its target tile in input buffer buf; the tile block of that step
 // sums its bin in LDS.  Two passes over the chunk's synapses: count the
 // events per tile (LDS), reserve each tile's range with one device atomic,
 // then write the entries.  Called by the whole block after a barrier;
 // returns the events delivered and resets the chunk.
-__device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t par1) {
+__device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
+  // every pair of a binned chunk arrives at the same step (buffer buf)
   const uint32_t np = sh.npair;
   const uint64_t ev = sel_scan(sh);
   // target = pl >> cls_bits, tile = target >> tile_shift: two shifts, each
@@ -436,35 +529,58 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t par1) {
   const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u;
   const uint32_t tsh = nd.tile_shift, lmask = (1u << tsh) - 1u, ntl = nd.n_tiles;
   bool bad = false;
-  for (uint64_t e = threadIdx.x; e < ev; e += kB) {
-    const uint32_t lo = sel_find(sh, np, e);
-    const uint32_t pl = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
-    const uint32_t t = (pl >> cls_bits) >> tsh;
-    if (t < ntl) atomicAdd(&sh.tcnt[t], 1u);
+  uint32_t lo = 0;
+  for (uint64_t e = threadIdx.x; e < ev; e += 2 * kB) {  // two independent events per lane and round
+    const uint64_t e1 = e + kB;
+    lo = sel_advance(sh, np, lo, e);
+    const uint32_t lo1 = (e1 < ev) ? sel_advance(sh, np, lo, e1) : lo;
+    const uint32_t pl0 = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
+    const uint32_t pl1 = (e1 < ev) ? nd.payload[sh.p_off[lo1] + (e1 - sh.p_st[lo1])] : 0u;
+    const uint32_t t0 = (pl0 >> cls_bits) >> tsh;
+    if (t0 < ntl) atomicAdd(&sh.tcnt[t0], 1u);
     else bad = true;
+    if (e1 < ev) {
+      const uint32_t t1 = (pl1 >> cls_bits) >> tsh;
+      if (t1 < ntl) atomicAdd(&sh.tcnt[t1], 1u);
+      else bad = true;
+    }
+    lo = lo1;
   }
   __syncthreads();
-  uint32_t* cnt = nd.bin_cnt + (size_t)par1 * ntl;
+  uint32_t* cnt = nd.bin_cnt + (size_t)buf * ntl;
   for (uint32_t t = threadIdx.x; t < ntl; t += kB) {
     const uint32_t c = sh.tcnt[t];
     if (c) {
-      sh.tbase[t] = __hip_atomic_fetch_add(&cnt[t], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t base = __hip_atomic_fetch_add(&cnt[t], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t cap = nd.bin_cap[t];
+      sh.tbase[t] = (uint32_t)nd.bin_off[t] + base;
+      sh.tavail[t] = (base < cap) ? min(c, cap - base) : 0u;
       sh.tcnt[t] = 0;
     }
   }
   __syncthreads();
-  uint32_t* bins = nd.bins + (size_t)par1 * nd.bins_total;
-  for (uint64_t e = threadIdx.x; e < ev; e += kB) {
-    const uint32_t lo = sel_find(sh, np, e);
-    const uint32_t pl = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
-    const uint32_t tgt = pl >> cls_bits, t = tgt >> tsh;
-    if (t >= ntl) continue;
-    const uint32_t slot = sh.tbase[t] + atomicAdd(&sh.tcnt[t], 1u);
-    const uint32_t cls = pl & cls_mask, mult = sh.p_mult[lo];
-    if (slot < nd.bin_cap[t])
-      bins[nd.bin_off[t] + slot] = ((tgt & lmask) << kBinLocalShift) | (mult << kBinMultShift) | cls;
-    else
-      bin_spill(nd, par1, tgt, cls, mult, t);
+  uint32_t* bins = nd.bins + (size_t)buf * nd.bins_total;
+  lo = 0;
+  for (uint64_t e = threadIdx.x; e < ev; e += 2 * kB) {
+    const uint64_t e1 = e + kB;
+    lo = sel_advance(sh, np, lo, e);
+    const uint32_t lo1 = (e1 < ev) ? sel_advance(sh, np, lo, e1) : lo;
+    const uint32_t pl0 = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
+    const uint32_t pl1 = (e1 < ev) ? nd.payload[sh.p_off[lo1] + (e1 - sh.p_st[lo1])] : 0u;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (q == 1 && e1 >= ev) break;
+      const uint32_t pl = q ? pl1 : pl0, r = q ? lo1 : lo;
+      const uint32_t tgt = pl >> cls_bits, t = tgt >> tsh;
+      if (t >= ntl) continue;
+      const uint32_t slot = atomicAdd(&sh.tcnt[t], 1u);
+      const uint32_t cls = pl & cls_mask, mult = sh.p_mult[r];
+      if (slot < sh.tavail[t])
+        bins[sh.tbase[t] + slot] = ((tgt & lmask) << kBinLocalShift) | (mult << kBinMultShift) | cls;
+      else
+        bin_spill(nd, buf, tgt, cls, mult, t);
+    }
+    lo = lo1;
   }
   if (bad) atomicOr(&nd.ctrl->overflow, 4u);  // a target outside the tiles: reported, not written
   __syncthreads();
@@ -534,29 +650,6 @@ __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* 
   return m;
 }
 
-// Spike list of 256-neuron sub-block ub at step n: wave ballot, lane prefix,
-// block prefix (gid order), into the stage buffer of the step's parity.
-// Returns the sub-block's spike count (block-uniform).  Two barriers.
-__device__ __forceinline__ uint32_t stage_spikes(const NetDev& nd, uint64_t n, uint32_t ub, bool spk,
-                                                 uint32_t entry, uint32_t* wcnt) {
-  const size_t sb = (size_t)(n & 1) * nd.nblk_upd;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint64_t bal = __ballot(spk);
-  const uint32_t pre = __popcll(bal & lanemask_lt());
-  if (lane == 0) wcnt[wv] = __popcll(bal);
-  __syncthreads();
-  uint32_t woff = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kB / 64; ++w) {
-    if (w < wv) woff += wcnt[w];
-    tot += wcnt[w];
-  }
-  if (spk) nd.stage[(sb + ub) * kB + woff + pre] = entry;
-  if (threadIdx.x == 0) nd.stage_cnt[sb + ub] = tot;
-  __syncthreads();
-  return tot;
-}
-
 __device__ __forceinline__ void load_tables(const NetDev& nd, PopDev* spops, uint32_t pop_cap, uint64_t* sthr,
                                             const PopDev*& pops, const uint64_t*& pthr) {
   const bool lds_pops = nd.npop <= pop_cap;
@@ -572,14 +665,50 @@ __device__ __forceinline__ void load_tables(const NetDev& nd, PopDev* spops, uin
   pthr = lds_thr ? sthr : nd.pois_thr;
 }
 
-// Direct-delivery update block: 256 neurons, input from acc[n & 1] (read and
-// cleared), spikes staged, delay-1 groups delivered at once.
+__device__ __forceinline__ uint32_t inbuf(uint64_t n) { return (uint32_t)(n % kInBuf); }
+
+// First raster-ring position of the spikes of step n: the positions of the
+// earlier steps' spikes end here.
+__device__ __forceinline__ uint64_t step_pos(const NetDev& nd, uint64_t n) {
+  if (n == 0) return 0;
+  const uint32_t s = (uint32_t)((n - 1) % nd.R);
+  return nd.ring_base[s] + nd.ring_cnt[s];
+}
+
+// Once per step (block 0): the step's raster position for the readers of the
+// next steps and the drain, and the spike counter of step n + 1 cleared (its
+// slot holds step n + 1 - R, which no block reads during step n).
+__device__ __forceinline__ void step_books(const NetDev& nd, uint64_t n) {
+  const uint64_t pos = step_pos(nd, n);
+  nd.ring_base[n % nd.R] = pos;
+  nd.chunk_base[n & (nd.chunk_ring - 1)] = pos;
+  nd.ring_cnt[(n + 1) % nd.R] = 0;
+}
+
+// A spike of step n at position pos among the step's spikes: raster entry and
+// the selection record that the delivery of later steps reads.
+__device__ __forceinline__ void emit_spike(const NetDev& nd, uint64_t n, uint64_t pos_n, uint32_t pos,
+                                           uint32_t entry, uint32_t grp_ptr, uint64_t mask) {
+  nd.log[(pos_n + pos) & nd.log_mask] = entry;
+  SpikeRec r;
+  r.entry = entry;
+  r.grp_ptr = grp_ptr;
+  r.mask = mask;
+  nd.recent[(size_t)(n % nd.R) * nd.N + pos] = r;
+}
+
+// Direct-delivery update block: 256 neurons, input from acc[n % 3] (read and
+// cleared); spikes get their positions from one atomic on the step's counter
+// (wave ballot + lane prefix + block prefix inside the block), their raster
+// entries and records written here; their delay-1 and delay-2 groups are
+// delivered at once, each group by the whole wave (consecutive lanes,
+// consecutive synapses), into the buffers of steps n + 1 and n + 2.
 template <bool kLif, bool kAdexOn, int P>
 __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds& sl) {
   const PopDev* pops;
   const uint64_t* pthr;
-  load_tables(nd, sl.spops, kPopLds, sl.sthr, pops, pthr);
-  if (threadIdx.x == 0) { sl.d1[0] = 0; sl.d1[1] = 0; }
+  load_tables(nd, sl.u.t.spops, kPopLds, sl.u.t.sthr, pops, pthr);
+  dlv_load_classes(nd, sl.u.d);
   __syncthreads();
   const uint32_t i = blk * kB + threadIdx.x;
   bool spk = false;
@@ -587,7 +716,7 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
   uint32_t nacc = 0, nrej = 0;
   bool capped = false, mover = false;
   if (i < nd.N) {
-    int64_t* acc = nd.acc + ((size_t)(n & 1) * nd.N + i) * nd.P;
+    int64_t* acc = nd.acc + ((size_t)inbuf(n) * nd.N + i) * nd.P;
     int64_t a[kMaxPorts];
 #pragma unroll
     for (int p = 0; p < kMaxPorts; ++p) {
@@ -601,46 +730,50 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
     spk = m > 0;
     entry = i | (m << kMultShift);
   }
-  const uint32_t btot = stage_spikes(nd, n, blk, spk, entry, sl.wcnt);
-  // delay-1 groups of this block's spikes reach their targets at the next
-  // step: delivered here, each group by the whole wave (consecutive lanes,
-  // consecutive synapses)
-  {
-    const int lane = threadIdx.x & 63;
-    uint64_t off = 0;
-    uint32_t len = 0;
-    bool has1 = false;
-    if (spk) {
-      const uint64_t mask = nd.src_mask[i];
-      if ((mask >> 1) & 1ull) {  // the delay-1 group is the source's first group
-        const uint32_t g = nd.grp_ptr[i];
-        off = nd.grp_off[g];
-        len = (uint32_t)(nd.grp_off[g + 1] - off);
-        has1 = true;
-      }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t bal = __ballot(spk);
+  if (lane == 0) sl.wcnt[wv] = __popcll(bal);
+  // a spiking neuron's delay mask, first group and the offsets of its delay-1
+  // and delay-2 groups, loaded while the block reserves its positions
+  uint64_t mask = 0, o1 = 0, o2 = 0;
+  uint32_t gp = 0, l1 = 0, l2 = 0;
+  if (spk) {
+    mask = nd.src_mask[i];
+    gp = nd.grp_ptr[i];
+    if ((mask >> 1) & 1ull) { o1 = nd.grp_off[gp]; l1 = (uint32_t)(nd.grp_off[gp + 1] - o1); }
+    if ((mask >> 2) & 1ull) {
+      const uint32_t g2 = gp + (uint32_t)__popcll(mask & 3ull);
+      o2 = nd.grp_off[g2];
+      l2 = (uint32_t)(nd.grp_off[g2 + 1] - o2);
     }
-    uint64_t bal = __ballot(has1);
-    if (bal) {
-      int64_t* accn = nd.acc + (size_t)((n + 1) & 1) * nd.N * nd.P;
-      const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u, P2 = nd.P;
-      unsigned long long wp = 0, we = 0;
-      while (bal) {
-        const int l = __ffsll((unsigned long long)bal) - 1;
-        bal &= bal - 1;
-        const uint64_t o = __shfl((unsigned long long)off, l, 64);
-        const uint32_t L = __shfl(len, l, 64);
-        const uint32_t mm = __shfl(entry >> kMultShift, l, 64);
-        for (uint32_t j = lane; j < L; j += 64) {
-          const uint32_t pl = nd.payload[o + j];
-          const uint32_t cls = pl & cls_mask;
-          const int64_t v = nd.cls_wq[cls] * (int64_t)mm;
-          __hip_atomic_fetch_add((unsigned long long*)&accn[(size_t)(pl >> cls_bits) * P2 + nd.cls_port[cls]],
-                                 (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        ++wp;
-        we += L;
-      }
-      if (lane == 0) { atomicAdd(&sl.d1[0], wp); atomicAdd(&sl.d1[1], we); }
+  }
+  __syncthreads();
+  uint32_t woff = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < kB / 64; ++w) {
+    if (w < wv) woff += sl.wcnt[w];
+    btot += sl.wcnt[w];
+  }
+  // spikes: positions, raster entries and records; their delay-1 and delay-2
+  // groups selected into LDS (the tables are dead now) and delivered by the
+  // block's flat scan into the buffers of steps n+1 and n+2
+  uint64_t pairs = 0, events = 0;
+  if (btot) {  // block-uniform
+    DirectLds& sh = sl.u.d;
+    if (threadIdx.x == 0) {
+      sl.emit = __hip_atomic_fetch_add(&nd.ring_cnt[n % nd.R], btot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sh.npair = 0;
+    }
+    __syncthreads();
+    if (spk) {
+      emit_spike(nd, n, step_pos(nd, n), sl.emit + woff + (uint32_t)__popcll(bal & lanemask_lt()), entry, gp, mask);
+      if (l1) sel_add(sh, o1, l1, entry >> kMultShift, inbuf(n + 1));
+      if (l2) sel_add(sh, o2, l2, entry >> kMultShift, inbuf(n + 2));
+    }
+    __syncthreads();
+    if (sh.npair) {
+      pairs += sh.npair;
+      events += dlv_flush(nd, sh, 0u);
     }
   }
   uint64_t sa = 0, sr = 0;
@@ -655,8 +788,8 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
     st[0] += sa;
     st[1] += sr;
     st[2] += btot;
-    st[3] += sl.d1[0];
-    st[4] += sl.d1[1];
+    st[3] += pairs;
+    st[4] += events;
   }
   if (capped) atomicOr(&nd.ctrl->overflow, 2u);
   if (mover) atomicOr(&nd.ctrl->overflow, 1u);
@@ -666,7 +799,7 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
 // loaded, then advanced one RK45 substep per call of adex_substep.
 template <int P>
 struct AdexItem {
-  const PopDev* pp;
+  AdexPar<P> q;
   float y[2 + P];
   float h, t, Ie;
   uint32_t it, mult;
@@ -682,7 +815,7 @@ __device__ __forceinline__ void adex_load(const NetDev& nd, const PopDev* pops, 
     for (int p = 0; p < kMaxPorts; ++p)
       if (p == pp.pois_port) a[p] += (int64_t)k * pp.pois_wq;
   }
-  w.pp = &pp;
+  w.q = adex_par<P>(pp);
   w.y[0] = nd.V[i];
   w.y[1] = nd.w[i];
 #pragma unroll
@@ -701,52 +834,53 @@ __device__ __forceinline__ uint32_t adex_store(const NetDev& nd, uint32_t i, Ade
   nd.w[i] = w.y[1];
 #pragma unroll
   for (int p = 0; p < P; ++p) nd.g[(size_t)i * nd.P + p] = w.y[2 + p];
-  nd.h[i] = (w.h > w.pp->dt) ? w.pp->dt : w.h;
+  nd.h[i] = (w.h > w.q.dt) ? w.q.dt : w.h;
   uint32_t m = w.mult;
   if (m > kMaxMult) { mover = true; m = kMaxMult; }
   return m;
 }
 
 // Binned-delivery tile block t at step n: sums the tile's bin (the events
-// written for step n by the previous step, plus any spill) into int64 LDS
-// accumulators, updates the tile's neurons from them, stages their spikes per
-// 256-neuron sub-block and bins the delay-1 groups of those spikes for step
-// n+1.  The spike count of a neuron is kept in its (then dead) first LDS
-// input slot until all neurons are done.  AdEx-only networks take their
-// neurons from a work queue: a lane whose neuron has reached the step end
-// takes the next one, so waves stay full while neurons near a spike need many
-// RK45 substeps and the others one.
+// written for step n during earlier steps, plus any spill) into int64 LDS
+// accumulators, updates the tile's neurons from them, emits their spikes
+// (one atomic on the step's counter for the whole tile) and bins the delay-1
+// and delay-2 groups of those spikes for steps n+1 and n+2.  The spike count
+// of a neuron is kept in its (then dead) first LDS input slot until all
+// neurons are done.  AdEx-only networks take their neurons from a work queue:
+// a lane whose neuron has reached the step end takes the next one, so waves
+// stay full while neurons near a spike need many RK45 substeps and the
+// others one.
 template <bool kLif, bool kAdexOn, int P>
 __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl) {
-  const uint32_t par = (uint32_t)(n & 1), PP = nd.P, tsh = nd.tile_shift;
+  const uint32_t PP = nd.P, tsh = nd.tile_shift, buf = inbuf(n);
   const uint32_t first = t << tsh;
   const uint32_t nt = min(1u << tsh, nd.N - first);
   const PopDev* pops;
   const uint64_t* pthr;
   load_tables(nd, sl.spops, kTilePopLds, sl.sthr, pops, pthr);
   for (uint32_t c = threadIdx.x; c < nd.n_classes; c += kB) {
-    sl.wq[c] = nd.cls_wq[c];
+    sl.c.wq[c] = nd.cls_wq[c];
     sl.wp[c] = (uint8_t)nd.cls_port[c];
   }
   for (uint32_t j = threadIdx.x; j < nt * PP; j += kB) sl.u.acc[j] = 0;
-  if (threadIdx.x == 0) sl.next = kB;
-  const size_t ti = (size_t)par * nd.n_tiles + t;
+  if (threadIdx.x == 0) { sl.next = 0; sl.hq_next = 0; sl.hq_n = 0; }
+  const size_t ti = (size_t)buf * nd.n_tiles + t;
   const uint32_t cnt = min(nd.bin_cnt[ti], nd.bin_cap[t]);
   const uint32_t ovf = nd.ovf_flag[ti];
-  const uint32_t* bin = nd.bins + (size_t)par * nd.bins_total + nd.bin_off[t];
+  const uint32_t* bin = nd.bins + (size_t)buf * nd.bins_total + nd.bin_off[t];
   __syncthreads();
   bool bad = false;
   for (uint32_t j = threadIdx.x; j < cnt; j += kB) {
     const uint32_t e = bin[j];
     const uint32_t cls = e & (uint32_t)(kMaxClasses - 1), loc = e >> kBinLocalShift;
     if (loc >= nt || cls >= nd.n_classes) { bad = true; continue; }
-    const int64_t v = sl.wq[cls] * (int64_t)((e >> kBinMultShift) & kMaxMult);
+    const int64_t v = sl.c.wq[cls] * (int64_t)((e >> kBinMultShift) & kMaxMult);
     atomicAdd((unsigned long long*)&sl.u.acc[loc * PP + sl.wp[cls]], (unsigned long long)v);
   }
   if (bad) atomicOr(&nd.ctrl->overflow, 4u);  // a malformed entry: reported, not added
   __syncthreads();
   if (ovf) {  // block-uniform: events that did not fit the bin
-    int64_t* g = nd.acc + ((size_t)par * nd.N + first) * PP;
+    int64_t* g = nd.acc + ((size_t)buf * nd.N + first) * PP;
     for (uint32_t j = threadIdx.x; j < nt * PP; j += kB) {
       const int64_t v = g[j];
       if (v != 0) { sl.u.acc[j] += v; g[j] = 0; }
@@ -760,24 +894,51 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
   uint32_t nacc = 0, nrej = 0;
   bool capped = false, mover = false;
   if (kAdexOn && !kLif) {
-    // AdEx only: work queue over the tile's neurons
-    uint32_t loc = threadIdx.x;
-    AdexItem<P> w;
-    if (loc < nt) {
+    // AdEx only: work queue over the tile's neurons; each lane holds its
+    // current neuron and has the next one's state already loaded, so the
+    // loads of a refill overlap the substeps of the current neuron
+    auto fetch = [&](uint32_t l, AdexItem<P>& it) {
       int64_t a[kMaxPorts];
 #pragma unroll
-      for (int p = 0; p < kMaxPorts; ++p) a[p] = (p < (int)PP) ? sl.u.acc[loc * PP + p] : 0;
-      adex_load<P>(nd, pops, pthr, n, first + loc, a, w);
+      for (int p = 0; p < kMaxPorts; ++p) a[p] = (p < (int)PP) ? sl.u.acc[l * PP + p] : 0;
+      adex_load<P>(nd, pops, pthr, n, first + l, a, it);
+    };
+    for (uint32_t l = threadIdx.x; l < nt; l += kB) {
+      const uint32_t i = first + l;
+      const bool hot = nd.V[i] >= pops[find_pop(pops, nd.npop, i)].V_T;
+      const uint64_t hb = __ballot(hot);
+      if ((threadIdx.x & 31) == 0) sl.hot[l >> 5] = (uint32_t)(hb >> (threadIdx.x & 32));
+      if (hot) {
+        const uint32_t k = atomicAdd(&sl.hq_n, 1u);
+        if (k < kHotCap) sl.hq[k] = (uint16_t)l;
+        else atomicAnd(&sl.hot[l >> 5], ~(1u << (l & 31)));  // list full: taken in index order
+      }
+    }
+    __syncthreads();
+    auto claim = [&]() -> uint32_t {
+      const uint32_t h = atomicAdd(&sl.hq_next, 1u);
+      if (h < min(sl.hq_n, kHotCap)) return sl.hq[h];
+      for (;;) {
+        const uint32_t c = atomicAdd(&sl.next, 1u);
+        if (c >= nt) return nt;
+        if (!((sl.hot[c >> 5] >> (c & 31)) & 1u)) return c;
+      }
+    };
+    uint32_t loc = claim(), nloc = nt;
+    AdexItem<P> w, nx;
+    if (loc < nt) {
+      fetch(loc, w);
+      nloc = claim();
+      if (nloc < nt) fetch(nloc, nx);
     }
     while (loc < nt) {
-      if (adex_substep<P>(*w.pp, w.y, w.h, w.t, w.it, w.mult, w.Ie, nacc, nrej, capped)) {
-        sl.u.acc[loc * PP] = (int64_t)adex_store<P>(nd, first + loc, w, mover);
-        loc = atomicAdd(&sl.next, 1u);
+      if (adex_substep<P>(w.q, w.y, w.h, w.t, w.it, w.mult, w.Ie, nacc, nrej, capped)) {
+        sl.c.mk[loc] = (uint8_t)adex_store<P>(nd, first + loc, w, mover);
+        loc = nloc;
         if (loc < nt) {
-          int64_t a[kMaxPorts];
-#pragma unroll
-          for (int p = 0; p < kMaxPorts; ++p) a[p] = (p < (int)PP) ? sl.u.acc[loc * PP + p] : 0;
-          adex_load<P>(nd, pops, pthr, n, first + loc, a, w);
+          w = nx;
+          nloc = claim();
+          if (nloc < nt) fetch(nloc, nx);
         }
       }
     }
@@ -786,57 +947,84 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
       int64_t a[kMaxPorts];
 #pragma unroll
       for (int p = 0; p < kMaxPorts; ++p) a[p] = (p < (int)PP) ? sl.u.acc[loc * PP + p] : 0;
-      sl.u.acc[loc * PP] =
-          (int64_t)neuron_step<kLif, kAdexOn, P>(nd, pops, pthr, n, first + loc, a, nacc, nrej, capped, mover);
+      sl.c.mk[loc] =
+          (uint8_t)neuron_step<kLif, kAdexOn, P>(nd, pops, pthr, n, first + loc, a, nacc, nrej, capped, mover);
     }
   }
   __syncthreads();
-  // spike lists of the tile's 256-neuron sub-blocks (gid order): ballots of
-  // all sub-blocks, one barrier, then the writes
-  const uint32_t ub0 = first / kB, nsub = (nt + kB - 1) / kB;
+  // spikes of the tile: counts per (256-neuron sub-block, wave), one atomic for
+  // the tile's positions; a neuron's position follows sub-block, wave, lane
+  const uint32_t nsub = (nt + kB - 1) / kB;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint32_t k = 0; k < nsub; ++k) {
     const uint32_t loc = k * kB + threadIdx.x;
-    const bool spk = loc < nt && sl.u.acc[loc * PP] != 0;
-    const uint64_t bal = __ballot(spk);
+    const uint64_t bal = __ballot(loc < nt && sl.c.mk[loc] != 0);
     if (lane == 0) sl.wcnt[k][wv] = __popcll(bal);
   }
   __syncthreads();
-  const size_t sb = (size_t)par * nd.nblk_upd;
   uint32_t spikes = 0;
-  for (uint32_t k = 0; k < nsub; ++k) {
-    const uint32_t loc = k * kB + threadIdx.x;
-    const uint32_t m = loc < nt ? (uint32_t)sl.u.acc[loc * PP] : 0u;
-    const uint64_t bal = __ballot(m != 0);
-    uint32_t woff = 0, tot = 0;
+  for (uint32_t k = 0; k < nsub; ++k)
 #pragma unroll
-    for (int q = 0; q < kB / 64; ++q) {
-      if (q < wv) woff += sl.wcnt[k][q];
-      tot += sl.wcnt[k][q];
-    }
-    if (m) nd.stage[(sb + ub0 + k) * kB + woff + __popcll(bal & lanemask_lt())] = (first + loc) | (m << kMultShift);
-    if (threadIdx.x == 0) { nd.stage_cnt[sb + ub0 + k] = tot; sl.sub_cnt[k] = tot; }
-    spikes += tot;
-  }
-  __syncthreads();  // the LDS input is dead from here: it holds the delay-1 selection
-  BinLds& sh = sl.u.d1;
+    for (int q = 0; q < kB / 64; ++q) spikes += sl.wcnt[k][q];
+  BinLds& sh = sl.u.d1;  // the LDS input is dead from here: it holds the selection
   uint64_t pairs = 0, events = 0;
   if (spikes) {  // block-uniform
+    if (threadIdx.x == 0)
+      sl.emit = __hip_atomic_fetch_add(&nd.ring_cnt[n % nd.R], spikes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     dlv_init(nd, sh);
     __syncthreads();
-    const uint32_t par1 = par ^ 1u;
+    const uint64_t pos_n = step_pos(nd, n);
+    uint32_t before = 0;  // spikes of the sub-blocks before k
+    uint32_t has2 = 0;    // sub-blocks where this thread's neuron has a delay-2 group
     for (uint32_t k = 0; k < nsub; ++k) {  // block-uniform
-      const uint32_t c = sl.sub_cnt[k];
-      if (threadIdx.x < c) {
-        const uint32_t entry = nd.stage[(sb + ub0 + k) * kB + threadIdx.x];
-        const uint32_t src = entry & kGidMask;
-        const uint64_t mask = nd.src_mask[src];
-        if ((mask >> 1) & 1ull) dlv_probe(nd, sh, entry, nd.grp_ptr[src], mask, 1);
+      uint32_t woff = 0, ktot = 0;
+#pragma unroll
+      for (int q = 0; q < kB / 64; ++q) {
+        if (q < wv) woff += sl.wcnt[k][q];
+        ktot += sl.wcnt[k][q];
+      }
+      const uint32_t loc = k * kB + threadIdx.x;
+      const uint32_t m = loc < nt ? sl.c.mk[loc] : 0u;
+      const uint64_t bal = __ballot(m != 0);
+      if (m) {
+        const uint32_t i = first + loc;
+        const uint32_t entry = i | (m << kMultShift);
+        const uint64_t mask = nd.src_mask[i];
+        const uint32_t gp = nd.grp_ptr[i];
+        emit_spike(nd, n, pos_n, sl.emit + before + woff + (uint32_t)__popcll(bal & lanemask_lt()), entry, gp, mask);
+        if ((mask >> 1) & 1ull) dlv_probe(nd, sh, entry, gp, mask, 1, inbuf(n + 1));
+        if ((mask >> 2) & 1ull) has2 |= 1u << k;
+      }
+      before += ktot;
+      __syncthreads();
+      if (sh.npair > (uint32_t)(kSelChunk - kB)) {
+        pairs += sh.npair;
+        events += dlv_flush(nd, sh, inbuf(n + 1));
+      }
+    }
+    __syncthreads();
+    if (sh.npair) {
+      pairs += sh.npair;
+      events += dlv_flush(nd, sh, inbuf(n + 1));
+    }
+    if (__syncthreads_or(has2 != 0)) {
+      for (uint32_t k = 0; k < nsub; ++k) {  // block-uniform
+        if ((has2 >> k) & 1u) {
+          const uint32_t loc = k * kB + threadIdx.x;
+          const uint32_t i = first + loc;
+          dlv_probe(nd, sh, i | ((uint32_t)sl.c.mk[loc] << kMultShift), nd.grp_ptr[i], nd.src_mask[i], 2,
+                    inbuf(n + 2));
+        }
+        __syncthreads();
+        if (sh.npair > (uint32_t)(kSelChunk - kB)) {
+          pairs += sh.npair;
+          events += dlv_flush(nd, sh, inbuf(n + 2));
+        }
       }
       __syncthreads();
-      if (sh.npair > (uint32_t)(kSelChunk - kB) || (k + 1 == nsub && sh.npair > 0)) {
+      if (sh.npair) {
         pairs += sh.npair;
-        events += dlv_flush(nd, sh, par1);
+        events += dlv_flush(nd, sh, inbuf(n + 2));
       }
     }
   }
@@ -846,7 +1034,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     sr = block_sum(nrej, sl.red);
   }
   if (threadIdx.x == 0) {
-    uint64_t* st = nd.blk_stats + (size_t)kBlkStats * ub0;
+    uint64_t* st = nd.blk_stats + (size_t)kBlkStats * (first / kB);
     st[0] += sa;
     st[1] += sr;
     st[2] += spikes;
@@ -857,78 +1045,22 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
   if (mover) atomicOr(&nd.ctrl->overflow, 1u);
 }
 
-// Spikes of step f = n-1, read from the update blocks' lists of that step:
-// block b appends the entries [i0, i1) (ranks within step f, gid order) to
-// the raster ring and, if kDeliver, records them for later steps and selects
-// their delay-2 groups.  Entries are taken in rounds of at most one per thread.
-template <bool kDeliver, class L>
-__device__ void walk_step(const NetDev& nd, uint64_t f, uint64_t base_f, uint64_t i0, uint64_t i1, L& sh,
-                          uint32_t par1, uint64_t& pairs, uint64_t& events) {
-  const size_t sb = (size_t)(f & 1) * nd.nblk_upd;
-  SpikeRec* rec = nd.recent + (size_t)(f % nd.R) * nd.N;
-  uint64_t run = 0;
-  for (uint32_t t0 = 0; t0 < nd.nblk_upd && run < i1; t0 += kB) {  // block-uniform
-    const uint32_t ub = t0 + threadIdx.x;
-    const uint32_t cc = (ub < nd.nblk_upd) ? nd.stage_cnt[sb + ub] : 0;
-    uint64_t tsum;
-    const uint64_t p_ub = run + block_excl_scan(cc, sh.red, &tsum);
-    const uint64_t lo = p_ub > i0 ? p_ub : i0;
-    const uint64_t hi = (p_ub + cc < i1) ? p_ub + cc : i1;
-    const uint32_t mine = hi > lo ? (uint32_t)(hi - lo) : 0u;
-    const uint32_t rounds = (uint32_t)block_max(mine, sh.red);
-    for (uint32_t r = 0; r < rounds; ++r) {  // block-uniform
-      if (r < mine) {
-        const uint64_t e = lo + r;
-        const uint32_t entry = nd.stage[(sb + ub) * kB + (e - p_ub)];
-        nd.log[(base_f + e) & nd.log_mask] = entry;
-        if (kDeliver) {
-          const uint32_t src = entry & kGidMask;
-          const uint64_t mask = nd.src_mask[src];
-          const uint32_t gp = nd.grp_ptr[src];
-          SpikeRec sr;
-          sr.entry = entry; sr.grp_ptr = gp; sr.mask = mask;
-          rec[e] = sr;
-          dlv_probe(nd, sh, entry, gp, mask, 2);
-        }
-      }
-      if (kDeliver) {
-        __syncthreads();
-        if (sh.npair > (uint32_t)(kSelChunk - kB)) {  // LDS nearly full: deliver now
-          pairs += sh.npair;
-          events += dlv_flush(nd, sh, par1);
-        }
-      }
-    }
-    run += tsum;
-  }
-}
-
-// Delivery blocks of step n: the input of step n+1 from the spikes of step
-// n-1 (delay 2; read from the update blocks' lists of that step, which these
-// blocks also append to the raster ring and record) and of steps
-// n-2 .. n+1-Dmax (delays >= 3; from the recent-spike records).  Block b owns
-// an equal share of all these items (one item = one in-flight spike).
+// Delivery blocks of step n: the input of step n+1 from the spikes of steps
+// n-2 .. n+1-Dmax whose delay d >= 3 expires now, read from their selection
+// records.  Item (spike, d) number e goes to block e mod G, so that every
+// block sees every delay (hits concentrate on the common delays).
 template <class L>
 __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t G, L& sh) {
   const uint32_t R = nd.R, dmax = nd.dmax;
   dlv_init(nd, sh);
   const uint32_t dseg = threadIdx.x + 1;  // delay of this item segment (threads 0..63)
-  uint64_t cnt = 0;
-  uint32_t slt = 0;
-  if (threadIdx.x < 64 && dseg >= 3 && dseg <= dmax && n + 1 >= dseg) {
-    slt = (uint32_t)((n + 1 - dseg) % R);
-    cnt = nd.ring_cnt[slt];
-  }
-  uint64_t base1 = 0;
-  if (n >= 2) base1 = nd.ring_base[(n - 2) % R] + nd.ring_cnt[(n - 2) % R];
-  uint64_t c = 0;
-  if (n >= 1) {
-    const size_t sb = (size_t)((n - 1) & 1) * nd.nblk_upd;
-    for (uint32_t ub = threadIdx.x; ub < nd.nblk_upd; ub += kB) c += nd.stage_cnt[sb + ub];
-  }
-  const uint64_t tot1 = block_sum(c, sh.red);  // spikes of step n-1
   if (threadIdx.x < 64) {
-    if (dseg == 2) cnt = tot1;
+    uint64_t cnt = 0;
+    uint32_t slt = 0;
+    if (dseg >= 3 && dseg <= dmax && n + 1 >= dseg) {
+      slt = (uint32_t)((n + 1 - dseg) % R);
+      cnt = nd.ring_cnt[slt];
+    }
     const uint64_t incl = wave_incl_scan(cnt);
     sh.seg[dseg] = incl - cnt;
     if (dseg == 64) sh.seg[65] = incl;
@@ -936,39 +1068,26 @@ __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t
   }
   __syncthreads();
   const uint64_t items = sh.seg[65];
-  const uint64_t ipb = (items + G - 1) / G;
-  const uint64_t i0 = (uint64_t)b * ipb;
-  const uint64_t i1 = (i0 + ipb < items) ? i0 + ipb : items;
-  if (b == 0 && threadIdx.x == 0 && n >= 1) {
-    nd.ring_base[(n - 1) % R] = base1;
-    nd.ring_cnt[(n - 1) % R] = (uint32_t)tot1;
-    nd.chunk_base[(n - 1) & (nd.chunk_ring - 1)] = base1;
-  }
-  const uint32_t par1 = (uint32_t)((n + 1) & 1);
+  const uint32_t b1 = inbuf(n + 1);
   uint64_t pairs = 0, events = 0;
-  // delay 2: spikes of step n-1
-  const uint64_t e1 = (i1 < tot1) ? i1 : tot1;
-  if (i0 < e1) walk_step<true>(nd, n - 1, base1, i0, e1, sh, par1, pairs, events);
-  __syncthreads();
-  if (sh.npair > 0) {
-    pairs += sh.npair;
-    events += dlv_flush(nd, sh, par1);
-  }
-  // delays >= 3: recent-spike records
-  const uint64_t s0 = (i0 > tot1) ? i0 : tot1;
-  for (uint64_t c0 = s0; c0 < i1; c0 += kSelChunk) {  // block-uniform
+  const uint64_t mine = (b < items) ? (items - b + G - 1) / G : 0;
+  for (uint64_t j0 = 0; j0 < mine; j0 += kSelChunk) {  // block-uniform
 #pragma unroll
     for (int q = 0; q < kSelPerThread; ++q) {
-      const uint64_t e = c0 + (uint64_t)q * kB + threadIdx.x;
-      if (e >= i1) continue;
-      uint32_t d = 3;
-      while (d < 64 && sh.seg[d + 1] <= e) ++d;
-      const SpikeRec r = nd.recent[(size_t)sh.slot[d] * nd.N + (e - sh.seg[d])];
-      dlv_probe(nd, sh, r.entry, r.grp_ptr, r.mask, d);
+      const uint64_t j = j0 + (uint64_t)q * kB + threadIdx.x;
+      if (j >= mine) continue;
+      const uint64_t e = b + (uint64_t)G * j;
+      uint32_t lo = 3, hi = 65;  // segment d: seg[d] <= e < seg[d + 1]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sh.seg[mid] <= e) lo = mid; else hi = mid;
+      }
+      const SpikeRec r = nd.recent[(size_t)sh.slot[lo] * nd.N + (e - sh.seg[lo])];
+      dlv_probe(nd, sh, r.entry, r.grp_ptr, r.mask, lo, b1);
     }
     __syncthreads();
     pairs += sh.npair;
-    events += dlv_flush(nd, sh, par1);
+    events += dlv_flush(nd, sh, b1);
   }
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add((unsigned long long*)&nd.sel_stats[2 * b], (unsigned long long)pairs, __ATOMIC_RELAXED,
@@ -980,14 +1099,15 @@ __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t
 
 // One simulation step n, direct delivery: blocks [0, nblk_upd) update the
 // neurons (LIF exact integration, Sec. 2.1/2.3; AdEx RK45, Sec. 2.1/2.4),
-// stage their spikes and deliver their delay-1 groups; the remaining blocks
-// deliver the earlier steps' spikes whose delay expires now.  All deliveries
-// go to the input of step n+1, the update reads the input of step n
-// (double-buffered by parity).
+// emit their spikes and deliver their delay-1 and delay-2 groups; the
+// remaining blocks deliver the earlier steps' spikes whose delay (>= 3)
+// expires now.  The update reads the input buffer of step n; deliveries go to
+// the buffers of the steps they arrive at.
 template <bool kLif, bool kAdexOn, int P>
 __global__ void __launch_bounds__(kB) k_step(NetDev nd, uint32_t rel) {
   __shared__ StepLds lds;
   const uint64_t n = nd.ctrl->step_base + rel;
+  if (blockIdx.x == 0 && threadIdx.x == 0) step_books(nd, n);
   if (blockIdx.x < nd.nblk_upd) {
     update_block<kLif, kAdexOn, P>(nd, n, blockIdx.x, lds.upd);
   } else {
@@ -996,43 +1116,19 @@ __global__ void __launch_bounds__(kB) k_step(NetDev nd, uint32_t rel) {
 }
 
 // One simulation step n, binned delivery: blocks [0, n_tiles) are the tile
-// blocks (input from their bins, update, delay-1 binning), the remaining
-// blocks bin the earlier steps' spikes whose delay expires now.
+// blocks (input from their bins, update, emission, delay-1 and delay-2
+// binning), the remaining blocks bin the earlier steps' spikes whose delay
+// expires now.
 template <bool kLif, bool kAdexOn, int P>
 __global__ void __launch_bounds__(kB) k_step_binned(NetDev nd, uint32_t rel) {
   __shared__ BinStepLds lds;
   const uint64_t n = nd.ctrl->step_base + rel;
+  if (blockIdx.x == 0 && threadIdx.x == 0) step_books(nd, n);
   if (blockIdx.x < nd.n_tiles) {
     tile_block<kLif, kAdexOn, P>(nd, n, blockIdx.x, lds.tile);
   } else {
     deliver_block(nd, n, blockIdx.x - nd.n_tiles, gridDim.x - nd.n_tiles, lds.dlv);
   }
-}
-
-// Raster ring for the last simulated step (step_base - 1): its spikes are
-// otherwise appended by the next step's delivery blocks.  Idempotent.
-__global__ void __launch_bounds__(kB) k_log_tail(NetDev nd) {
-  __shared__ DirectLds sh;
-  const uint64_t sbase = nd.ctrl->step_base;
-  if (sbase == 0) return;  // block-uniform
-  const uint64_t f = sbase - 1;
-  const uint32_t R = nd.R;
-  const uint64_t base_f = (f >= 1) ? nd.ring_base[(f - 1) % R] + nd.ring_cnt[(f - 1) % R] : 0;
-  const size_t sb = (size_t)(f & 1) * nd.nblk_upd;
-  uint64_t c = 0;
-  for (uint32_t ub = threadIdx.x; ub < nd.nblk_upd; ub += kB) c += nd.stage_cnt[sb + ub];
-  const uint64_t tot = block_sum(c, sh.red);
-  const uint64_t G = gridDim.x;
-  const uint64_t ipb = (tot + G - 1) / G;
-  const uint64_t i0 = blockIdx.x * ipb;
-  const uint64_t i1 = (i0 + ipb < tot) ? i0 + ipb : tot;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    nd.ring_base[f % R] = base_f;
-    nd.ring_cnt[f % R] = (uint32_t)tot;
-    nd.chunk_base[f & (nd.chunk_ring - 1)] = base_f;
-  }
-  uint64_t pairs = 0, events = 0;
-  if (i0 < i1) walk_step<false>(nd, f, base_f, i0, i1, sh, 0u, pairs, events);
 }
 
 __global__ void k_advance(Ctrl* ctrl, uint32_t steps) {
@@ -1051,13 +1147,13 @@ __global__ void __launch_bounds__(kB) k_poisson_counts(NetDev nd, uint64_t step,
 // Readback of the binned input pending for the step of parity par, on one
 // port, for gids [first, first + n): block = one tile, entries decoded and
 // added to out[gid - first] (which holds the tile's spill already).
-__global__ void __launch_bounds__(kB) k_pending_input(NetDev nd, uint32_t par, uint32_t first, uint32_t n,
+__global__ void __launch_bounds__(kB) k_pending_input(NetDev nd, uint32_t buf, uint32_t first, uint32_t n,
                                                       uint32_t port, int64_t* out) {
   const uint32_t t = (first >> nd.tile_shift) + blockIdx.x;
   const uint32_t tfirst = t << nd.tile_shift;
-  const size_t ti = (size_t)par * nd.n_tiles + t;
+  const size_t ti = (size_t)buf * nd.n_tiles + t;
   const uint32_t cnt = min(nd.bin_cnt[ti], nd.bin_cap[t]);
-  const uint32_t* bin = nd.bins + (size_t)par * nd.bins_total + nd.bin_off[t];
+  const uint32_t* bin = nd.bins + (size_t)buf * nd.bins_total + nd.bin_off[t];
   for (uint32_t j = threadIdx.x; j < cnt; j += kB) {
     const uint32_t e = bin[j];
     const uint32_t cls = e & (uint32_t)(kMaxClasses - 1);
@@ -1115,21 +1211,16 @@ hipError_t launch_step(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t
   return hipGetLastError();
 }
 
-hipError_t launch_log_tail(const NetDev& nd, hipStream_t s) {
-  hipLaunchKernelGGL(k_log_tail, dim3(nd.fresh_grid), dim3(kB), 0, s, nd);
-  return hipGetLastError();
-}
-
 hipError_t launch_advance(Ctrl* ctrl, uint32_t steps, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ctrl, steps);
   return hipGetLastError();
 }
 
-hipError_t launch_pending_input(const NetDev& nd, uint32_t par, uint32_t first, uint32_t n, uint32_t port,
+hipError_t launch_pending_input(const NetDev& nd, uint32_t buf, uint32_t first, uint32_t n, uint32_t port,
                                 int64_t* out, hipStream_t s) {
   if (n == 0 || nd.n_tiles == 0) return hipSuccess;
   const uint32_t t0 = first >> nd.tile_shift, t1 = (first + n - 1) >> nd.tile_shift;
-  hipLaunchKernelGGL(k_pending_input, dim3(t1 - t0 + 1), dim3(kB), 0, s, nd, par, first, n, port, out);
+  hipLaunchKernelGGL(k_pending_input, dim3(t1 - t0 + 1), dim3(kB), 0, s, nd, buf, first, n, port, out);
   return hipGetLastError();
 }
 

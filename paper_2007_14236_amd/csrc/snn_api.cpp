@@ -758,7 +758,10 @@ snn_status snn_build(snn_net* net) {
 
   NetDev& nd = net->nd;
   memset(&nd, 0, sizeof nd);
-  nd.N = N; nd.P = P; nd.npop = npop; nd.dmax = dmax_used; nd.R = dmax_used + 1;
+  nd.N = N; nd.P = P; nd.npop = npop; nd.dmax = dmax_used;
+  // step slots: the steps delivery reads (n+1-Dmax .. n-2), the previous step's
+  // count, the current step's counter and the next step's (cleared): >= 3
+  nd.R = std::max<uint32_t>(dmax_used + 1, 3);
   nd.npois = (uint32_t)(pois_thr.size() / kPoisKmax);
   nd.nblk_upd = (N + kUpdBlock - 1) / kUpdBlock;
   nd.pad0 = (net->has_lif ? 1u : 0u) | (net->has_adex ? 2u : 0u);
@@ -883,8 +886,8 @@ snn_status snn_build(snn_net* net) {
     HIPCHK(net, hipMemcpy(d_g, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
     nd.w = d_w; nd.h = d_h; nd.g = d_g;
   }
-  int64_t* d_acc; ALLOC(d_acc, int64_t, (size_t)2 * N * P);
-  HIPCHK(net, hipMemsetAsync(d_acc, 0, (size_t)2 * N * P * 8, s));
+  int64_t* d_acc; ALLOC(d_acc, int64_t, (size_t)kInBuf * N * P);
+  HIPCHK(net, hipMemsetAsync(d_acc, 0, (size_t)kInBuf * N * P * 8, s));
   nd.acc = d_acc;
 
   // ---- delivery mode: direct atomics or bins per target tile ----
@@ -929,16 +932,24 @@ snn_status snn_build(snn_net* net) {
         const uint64_t want = net->cfg.bin_capacity ? (uint64_t)net->cfg.bin_capacity
                                                     : std::max<uint64_t>(1ull << 18, indeg[t] >> 3);
         cap[t] = (uint32_t)std::min<uint64_t>(indeg[t], want);
+        tot += cap[t];
+      }
+      // bin positions are 32-bit: shrink the capacities if they would not fit
+      // (events beyond a capacity are still delivered, by the spill path)
+      const uint64_t shrink = tot / (1ull << 31) + 1;
+      tot = 0;
+      for (uint64_t t = 0; t < nt; ++t) {
+        cap[t] = (uint32_t)(cap[t] / shrink);
         off[t] = tot;
         tot += cap[t];
       }
-      uint32_t* d_bins; ALLOC(d_bins, uint32_t, std::max<uint64_t>(1, 2 * tot));
-      uint32_t* d_bcnt; ALLOC(d_bcnt, uint32_t, 2 * nt);
-      uint32_t* d_bovf; ALLOC(d_bovf, uint32_t, 2 * nt);
+      uint32_t* d_bins; ALLOC(d_bins, uint32_t, std::max<uint64_t>(1, kInBuf * tot));
+      uint32_t* d_bcnt; ALLOC(d_bcnt, uint32_t, kInBuf * nt);
+      uint32_t* d_bovf; ALLOC(d_bovf, uint32_t, kInBuf * nt);
       uint64_t* d_boff; ALLOC(d_boff, uint64_t, nt);
       uint32_t* d_bcap; ALLOC(d_bcap, uint32_t, nt);
-      HIPCHK(net, hipMemsetAsync(d_bcnt, 0, 2 * nt * 4, s));
-      HIPCHK(net, hipMemsetAsync(d_bovf, 0, 2 * nt * 4, s));
+      HIPCHK(net, hipMemsetAsync(d_bcnt, 0, kInBuf * nt * 4, s));
+      HIPCHK(net, hipMemsetAsync(d_bovf, 0, kInBuf * nt * 4, s));
       HIPCHK(net, hipMemcpyAsync(d_boff, off.data(), nt * 8, hipMemcpyHostToDevice, s));
       HIPCHK(net, hipMemcpyAsync(d_bcap, cap.data(), nt * 4, hipMemcpyHostToDevice, s));
       HIPCHK(net, hipStreamSynchronize(s));
@@ -951,24 +962,20 @@ snn_status snn_build(snn_net* net) {
   // ---- spike buffers ----
   net->drain_steps = std::max<uint64_t>(kGraphSteps, std::min<uint64_t>(1000, ((1ull << 25) / N) / kGraphSteps * kGraphSteps));
   net->log_cap = next_pow2((uint64_t)N * (nd.R + net->drain_steps + kGraphSteps + 1));
-  uint32_t* d_stage; ALLOC(d_stage, uint32_t, (size_t)2 * nd.nblk_upd * kUpdBlock);
-  uint32_t* d_scnt; ALLOC(d_scnt, uint32_t, (size_t)2 * nd.nblk_upd);
   uint32_t* d_log; ALLOC(d_log, uint32_t, net->log_cap);
   uint64_t* d_rb; ALLOC(d_rb, uint64_t, nd.R);
   uint32_t* d_rc; ALLOC(d_rc, uint32_t, nd.R);
   uint64_t* d_cb; ALLOC(d_cb, uint64_t, kChunkRing);
-  HIPCHK(net, hipMemsetAsync(d_scnt, 0, (size_t)2 * nd.nblk_upd * 4, s));
   HIPCHK(net, hipMemsetAsync(d_rb, 0, nd.R * 8, s));
   HIPCHK(net, hipMemsetAsync(d_rc, 0, nd.R * 4, s));
   HIPCHK(net, hipMemsetAsync(d_cb, 0, kChunkRing * 8, s));
-  nd.stage = d_stage; nd.stage_cnt = d_scnt; nd.log = d_log; nd.ring_base = d_rb; nd.ring_cnt = d_rc;
+  nd.log = d_log; nd.ring_base = d_rb; nd.ring_cnt = d_rc;
   nd.chunk_base = d_cb; nd.log_mask = net->log_cap - 1; nd.chunk_ring = kChunkRing;
 
   // ---- selection / delivery ----
   // delivery blocks: binned delivery reserves bin space once per touched tile
   // and chunk, so it wants few, large chunks (at most 256 blocks)
   nd.sel_grid = std::min<uint32_t>(nd.n_tiles ? 256 : 2048, std::max<uint32_t>(64, nd.nblk_upd));
-  nd.fresh_grid = std::min<uint32_t>(256, std::max<uint32_t>(16, nd.nblk_upd));
   const size_t nstat = (size_t)2 * nd.sel_grid;
   ALLOC(nd.sel_stats, uint64_t, nstat);
   HIPCHK(net, hipMemsetAsync(nd.sel_stats, 0, nstat * 8, s));
@@ -1031,7 +1038,6 @@ snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms) {
   for (uint64_t k = 0; k < steps; ++k) {
     HIPCHK(net, launch_step(net->nd, 0, net->stream, ev[0], ev[1]));
     HIPCHK(net, launch_advance(net->nd.ctrl, 1, net->stream));
-    HIPCHK(net, launch_log_tail(net->nd, net->stream));
     HIPCHK(net, hipEventSynchronize(ev[1]));
     float ms = 0.f;
     HIPCHK(net, hipEventElapsedTime(&ms, ev[0], ev[1]));
@@ -1120,8 +1126,8 @@ snn_status snn_get_input(snn_net* net, uint32_t first, uint32_t n, uint32_t port
   snn_status st = enter(net);
   if (st) return st;
   HIPCHK(net, hipStreamSynchronize(net->stream));
-  const uint32_t par = (uint32_t)(net->cur_step & 1);
-  const int64_t* base = net->nd.acc + (size_t)par * net->N * net->P;
+  const uint32_t buf = (uint32_t)(net->cur_step % kInBuf);
+  const int64_t* base = net->nd.acc + (size_t)buf * net->N * net->P;
   if (!net->nd.n_tiles || n == 0) {
     if (n) HIPCHK(net, hipMemcpy2D(out, 8, base + (size_t)first * net->P + port, net->P * 8, 8, n, hipMemcpyDeviceToHost));
     return leave(net);
@@ -1131,7 +1137,7 @@ snn_status snn_get_input(snn_net* net, uint32_t first, uint32_t n, uint32_t port
   if (!d) return fail(net, SNN_E_NOMEM, "allocation failed");
   hipError_t e = hipMemcpy2DAsync(d, 8, base + (size_t)first * net->P + port, net->P * 8, 8, n,
                                   hipMemcpyDeviceToDevice, net->stream);
-  if (e == hipSuccess) e = launch_pending_input(net->nd, par, first, n, port, d, net->stream);
+  if (e == hipSuccess) e = launch_pending_input(net->nd, buf, first, n, port, d, net->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
   if (e == hipSuccess) e = hipMemcpy(out, d, (size_t)n * 8, hipMemcpyDeviceToHost);
   dev_free(net, d);
@@ -1215,7 +1221,6 @@ snn_status record_graph(snn_net* net, uint32_t steps, hipGraphExec_t* out) {
     e = launch_step(net->nd, r, net->stream);
   }
   if (e == hipSuccess) e = launch_advance(net->nd.ctrl, steps, net->stream);
-  if (e == hipSuccess) e = launch_log_tail(net->nd, net->stream);
   hipError_t e2 = hipStreamEndCapture(net->stream, &g);
   if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "capture: %s", hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(net, SNN_E_DEVICE, "end capture: %s", hipGetErrorString(e2));

@@ -3,13 +3,14 @@
 // HBM layout (all arrays device-resident for the life of the network):
 //   neuron state (SoA, fp32): V (LIF: V - E_L), I_e, and per model
 //     LIF-exp: I_syn[N][P];  AdEx: w, g[N][P], h;  refr (int32) for LIF.
-//   acc[2][N][P]  int64 fixed-point input, double-buffered by step parity
-//                 (direct delivery: all input; binned delivery: only the
-//                 events that did not fit their tile's bin).
+//   acc[3][N][P]  int64 fixed-point input, one buffer per arrival step
+//                 n, n+1, n+2 (index step % 3; direct delivery: all input;
+//                 binned delivery: only the events that did not fit their
+//                 tile's bin).
 //   binned delivery: targets are cut into tiles of 2^tile_shift neurons;
-//     bins[2][bins_total] u32 entries local << 15 | mult << 10 | class, the
+//     bins[3][bins_total] u32 entries local << 15 | mult << 10 | class, the
 //     tile t region at bin_off[t] holding up to bin_cap[t] entries,
-//     bin_cnt[2][n_tiles] entries written, ovf_flag[2][n_tiles] set when a
+//     bin_cnt[3][n_tiles] entries written, ovf_flag[3][n_tiles] set when a
 //     tile's events spilled into acc.
 //   CSR by (source, delay group):
 //     src_mask[N]   u64, bit d set <=> source has a group with delay d steps
@@ -17,10 +18,12 @@
 //     grp_off[G+1]  u64, first synapse of each group (groups ordered by delay)
 //     payload[S]    u32, target << b | weight class (class -> port, w_q),
 //                   b = 32 - bits(N), at most 1024 classes
-//   spike buffer: stage[2][nblk][256] per-update-block spike lists of the
-//     last two steps, log[CAP] ring of compacted per-step spike lists
-//     (gid | mult << 27) with ring_base/ring_cnt per step slot (Dmax + 1),
-//     recent[Dmax + 1][N] selection records of the spikes in flight.
+//   spikes, per step slot s = step % R (R = max(Dmax + 1, 3)):
+//     ring_cnt[s]   spikes of the step (the emitting blocks' atomic cursor),
+//     ring_base[s]  their first position in log[CAP], the raster ring
+//                   (gid | mult << 27, any order within a step),
+//     recent[s][N]  16-byte selection records (entry, first group, delay
+//                   mask) read by later steps' delivery.
 //   selection and delivery keep the selected (synapse offset, group size,
 //     multiplicity) records in LDS only.
 #pragma once
@@ -35,10 +38,11 @@ constexpr int kPoisKmax = 128;
 constexpr int kMultShift = 27;
 constexpr uint32_t kGidMask = (1u << kMultShift) - 1;
 constexpr uint32_t kMaxMult = 31;
-constexpr int kUpdBlock = 256;      // neurons per update block (= stage segment)
+constexpr int kUpdBlock = 256;      // neurons per update block
+constexpr int kInBuf = 3;           // input buffers: arrival steps n, n+1, n+2
 constexpr int kBlkStats = 5;   // per update block: rk accepted, rk rejected, spikes, delay-1 pairs, events
 constexpr int kTileAccWords = 4096; // int64 LDS accumulators of a tile block (tile neurons x ports)
-constexpr uint32_t kMaxTiles = 2048; // tiles of the binned delivery
+constexpr uint32_t kMaxTiles = 1024; // tiles of the binned delivery
 constexpr int kBinLocalShift = 15;   // bin entry: local target << 15 | mult << 10 | class
 constexpr int kBinMultShift = 10;
 constexpr int kTagConn = 1;
@@ -98,12 +102,11 @@ struct Ctrl {
 };
 
 struct NetDev {
-  uint32_t N, P, npop, dmax;   // dmax = largest delay present (ring has dmax+1 slots)
+  uint32_t N, P, npop, dmax;   // dmax = largest delay present
   uint32_t npois, pad2;        // Poisson threshold tables
-  uint32_t R, nblk_upd, sel_grid, pad0;  // pad0: bit 0 LIF present, bit 1 AdEx present
-  uint32_t fresh_grid, pad3;
+  uint32_t R, nblk_upd, sel_grid, pad0;  // R step slots; pad0: bit 0 LIF present, bit 1 AdEx present
   uint32_t n_tiles, tile_shift;  // binned delivery (n_tiles == 0: direct atomics)
-  uint64_t bins_total;           // bin entries per parity
+  uint64_t bins_total;           // bin entries per input buffer
   uint64_t log_mask;           // CAP - 1
   uint64_t chunk_ring;         // slots of chunk_base (power of two)
   uint64_t n_groups, n_syn;
@@ -119,7 +122,6 @@ struct NetDev {
   int64_t* acc;
   uint32_t* bins; uint32_t* bin_cnt; uint32_t* ovf_flag; const uint64_t* bin_off; const uint32_t* bin_cap;
   // spikes
-  uint32_t* stage; uint32_t* stage_cnt;
   uint32_t* log; uint64_t* ring_base; uint32_t* ring_cnt; uint64_t* chunk_base;
   SpikeRec* recent;            // [R][N] selection records of the last R steps' spikes
   // selection / delivery
