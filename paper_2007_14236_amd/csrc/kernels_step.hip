@@ -330,15 +330,15 @@ struct UpdTables {
 
 struct UpdLds {
   uint32_t wcnt[kB / 64];
-  uint32_t emit;  // first position of the block's spikes in the step
   uint64_t red[kB / 64];
   union {
     UpdTables t;  // population and Poisson tables, during the update
     DirectLds d;  // selection of the block's delay-1 and delay-2 groups, after it
   } u;
 };
-// the weight classes of DirectLds lie beyond the tables: loaded with them
-static_assert(sizeof(SelLds) >= sizeof(UpdTables), "class cache must not overlap the update tables");
+// the weight classes of DirectLds and its pair counter lie beyond the tables:
+// the classes are loaded with the tables, the counter cleared while they are read
+static_assert(offsetof(SelLds, npair) >= sizeof(UpdTables), "selection state must not overlap the update tables");
 
 // LDS of a tile block: the tile's int64 input (dead after the update, then
 // reused by the delay-1 binning), weight classes, population and Poisson tables
@@ -357,8 +357,9 @@ struct TileLds {
   uint32_t wcnt[kTileSubs][kB / 64];
   uint64_t red[kB / 64];
   uint32_t emit;  // first position of the tile's spikes in the step
-  // AdEx work queue: neurons at or above V_T (likely to spike and to need many
-  // substeps) first, from a short list, then the others in index order
+  // AdEx work queue: neurons at or above V_T + 4 Delta_T (about to spike: a
+  // spike step takes ~100 substeps) first, from a short list, then the others
+  // in index order
   uint32_t next, hq_next, hq_n;
   uint16_t hq[kHotCap];
   uint32_t hot[kTileAccWords / 32];
@@ -659,8 +660,13 @@ __device__ __forceinline__ void load_tables(const NetDev& nd, PopDev* spops, uin
     for (uint32_t w = threadIdx.x; w < words; w += kB)
       reinterpret_cast<uint32_t*>(spops)[w] = reinterpret_cast<const uint32_t*>(nd.pops)[w];
   }
-  if (lds_thr)
-    for (uint32_t w = threadIdx.x; w < nd.npois * kPoisKmax; w += kB) sthr[w] = nd.pois_thr[w];
+  if (lds_thr) {
+    const uint32_t len = nd.pois_len;
+    for (uint32_t w = threadIdx.x; w < nd.npois * len; w += kB) {
+      const uint32_t q = w / len, k = w - q * len;
+      sthr[q * kPoisKmax + k] = nd.pois_thr[q * kPoisKmax + k];
+    }
+  }
   pops = lds_pops ? spops : nd.pops;
   pthr = lds_thr ? sthr : nd.pois_thr;
 }
@@ -698,11 +704,10 @@ __device__ __forceinline__ void emit_spike(const NetDev& nd, uint64_t n, uint64_
 }
 
 // Direct-delivery update block: 256 neurons, input from acc[n % 3] (read and
-// cleared); spikes get their positions from one atomic on the step's counter
-// (wave ballot + lane prefix + block prefix inside the block), their raster
-// entries and records written here; their delay-1 and delay-2 groups are
-// delivered at once, each group by the whole wave (consecutive lanes,
-// consecutive synapses), into the buffers of steps n + 1 and n + 2.
+// cleared); spikes get their positions from one atomic per wave on the step's
+// counter (wave ballot + lane prefix), their raster entries and records are
+// written here, and their delay-1 and delay-2 groups are delivered at once by
+// the block's flat scan into the buffers of steps n + 1 and n + 2.
 template <bool kLif, bool kAdexOn, int P>
 __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds& sl) {
   const PopDev* pops;
@@ -732,9 +737,17 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint64_t bal = __ballot(spk);
+  // each wave reserves its spikes' positions in the step with one atomic
+  uint32_t wpos = 0;
+  if (bal) {
+    if (lane == 0)
+      wpos = __hip_atomic_fetch_add(&nd.ring_cnt[n % nd.R], (uint32_t)__popcll(bal), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    wpos = __shfl(wpos, 0, 64) + (uint32_t)__popcll(bal & lanemask_lt());
+  }
   if (lane == 0) sl.wcnt[wv] = __popcll(bal);
   // a spiking neuron's delay mask, first group and the offsets of its delay-1
-  // and delay-2 groups, loaded while the block reserves its positions
+  // and delay-2 groups, loaded while the wave's atomic is in flight
   uint64_t mask = 0, o1 = 0, o2 = 0;
   uint32_t gp = 0, l1 = 0, l2 = 0;
   if (spk) {
@@ -747,29 +760,19 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
       l2 = (uint32_t)(nd.grp_off[g2 + 1] - o2);
     }
   }
+  if (spk) emit_spike(nd, n, step_pos(nd, n), wpos, entry, gp, mask);
+  if (threadIdx.x == 0) sl.u.d.npair = 0;  // the tables are dead from here
   __syncthreads();
-  uint32_t woff = 0, btot = 0;
+  uint32_t btot = 0;
 #pragma unroll
-  for (int w = 0; w < kB / 64; ++w) {
-    if (w < wv) woff += sl.wcnt[w];
-    btot += sl.wcnt[w];
-  }
-  // spikes: positions, raster entries and records; their delay-1 and delay-2
-  // groups selected into LDS (the tables are dead now) and delivered by the
-  // block's flat scan into the buffers of steps n+1 and n+2
+  for (int w = 0; w < kB / 64; ++w) btot += sl.wcnt[w];
+  // delay-1 and delay-2 groups of the block's spikes: selected into LDS and
+  // delivered by the block's flat scan into the buffers of steps n+1 and n+2
   uint64_t pairs = 0, events = 0;
   if (btot) {  // block-uniform
     DirectLds& sh = sl.u.d;
-    if (threadIdx.x == 0) {
-      sl.emit = __hip_atomic_fetch_add(&nd.ring_cnt[n % nd.R], btot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      sh.npair = 0;
-    }
-    __syncthreads();
-    if (spk) {
-      emit_spike(nd, n, step_pos(nd, n), sl.emit + woff + (uint32_t)__popcll(bal & lanemask_lt()), entry, gp, mask);
-      if (l1) sel_add(sh, o1, l1, entry >> kMultShift, inbuf(n + 1));
-      if (l2) sel_add(sh, o2, l2, entry >> kMultShift, inbuf(n + 2));
-    }
+    if (l1) sel_add(sh, o1, l1, entry >> kMultShift, inbuf(n + 1));
+    if (l2) sel_add(sh, o2, l2, entry >> kMultShift, inbuf(n + 2));
     __syncthreads();
     if (sh.npair) {
       pairs += sh.npair;
@@ -905,7 +908,8 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     };
     for (uint32_t l = threadIdx.x; l < nt; l += kB) {
       const uint32_t i = first + l;
-      const bool hot = nd.V[i] >= pops[find_pop(pops, nd.npop, i)].V_T;
+      const PopDev& hp = pops[find_pop(pops, nd.npop, i)];
+      const bool hot = nd.V[i] >= hp.V_T + 4.f * hp.Delta_T;
       const uint64_t hb = __ballot(hot);
       if ((threadIdx.x & 31) == 0) sl.hot[l >> 5] = (uint32_t)(hb >> (threadIdx.x & 32));
       if (hot) {

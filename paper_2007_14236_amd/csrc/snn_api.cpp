@@ -763,6 +763,14 @@ snn_status snn_build(snn_net* net) {
   // count, the current step's counter and the next step's (cleared): >= 3
   nd.R = std::max<uint32_t>(dmax_used + 1, 3);
   nd.npois = (uint32_t)(pois_thr.size() / kPoisKmax);
+  // the inverse-CDF search stops at the first threshold of 2^32, so the
+  // entries past it in any table are never read
+  nd.pois_len = 1;
+  for (uint32_t q = 0; q < nd.npois; ++q) {
+    uint32_t k = 0;
+    while (k < kPoisKmax - 1 && pois_thr[(size_t)q * kPoisKmax + k] < (1ull << 32)) ++k;
+    nd.pois_len = std::max<uint32_t>(nd.pois_len, k + 1);
+  }
   nd.nblk_upd = (N + kUpdBlock - 1) / kUpdBlock;
   nd.pad0 = (net->has_lif ? 1u : 0u) | (net->has_adex ? 2u : 0u);
   hipStream_t s = net->stream;

@@ -103,7 +103,7 @@ struct Ctrl {
 
 struct NetDev {
   uint32_t N, P, npop, dmax;   // dmax = largest delay present
-  uint32_t npois, pad2;        // Poisson threshold tables
+  uint32_t npois, pois_len;    // Poisson threshold tables; entries read at most (the rest are never reached)
   uint32_t R, nblk_upd, sel_grid, pad0;  // R step slots; pad0: bit 0 LIF present, bit 1 AdEx present
   uint32_t n_tiles, tile_shift;  // binned delivery (n_tiles == 0: direct atomics)
   uint64_t bins_total;           // bin entries per input buffer
