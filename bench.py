@@ -45,6 +45,23 @@ BYTES_PER_PAIR = 28
 BYTES_PER_SPIKE = 28
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, or None when the kernel sources have changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["kernel_sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["kernel_sources_sha256"] or workload not in rec["workloads"]:
+        return None
+    return rec["workloads"][workload]["bytes_per_launch"]
+
+
 def bytes_per_step_neurons(spec: dict, delivery: str) -> int:
     tot = 0
     for p in spec["populations"]:
@@ -185,7 +202,8 @@ def main():
     roofline = {
         "kernel": "k_step_binned" if mode == "binned" else "k_step", "bound": "hbm",
         "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": measured_traffic(args.workload) if args.delivery == "auto" else None,
         "avg_launch_us": round(dlv_ms * 1e3, 3), "bytes_per_launch": round(dlv_bytes),
         "neuron_bytes_per_launch": neuron_bytes,
         "events_per_launch": round(ev_p, 1), "pairs_per_launch": round(pr_p, 1),
@@ -244,11 +262,16 @@ def bench_sweep(args, S, W, torch):
     step) against the same instances simulated one after another."""
     specs = [W.brunel_sweep_instance(i) for i in range(args.instances)]
     steps = args.steps
+    print(f"[bench] building the batch: {args.instances} instances, "
+          f"{sum(W.total_neurons(sp) for sp in specs)} neurons, "
+          f"{sum(W.count_synapses(sp) for sp in specs):.4g} synapses", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     net = S.Net(specs, record=True, delivery=args.delivery, tile_neurons=args.tile_neurons,
                 bin_capacity=args.bin_capacity)
     build_s = time.perf_counter() - t0
     mode = "binned" if net.counters()["delivery"] == 2 else "direct"
+    print(f"[bench] built in {build_s:.1f} s ({mode} delivery); warm-up {args.warmup} steps", file=sys.stderr,
+          flush=True)
     net.simulate(args.warmup)
     torch.cuda.synchronize()
     c0 = net.counters()
@@ -258,6 +281,7 @@ def bench_sweep(args, S, W, torch):
     wall = time.perf_counter() - t0
     c1 = net.counters()
     events = c1["events"] - c0["events"]
+    print(f"[bench] batch: {steps} steps in {wall:.3f} s; sequential sample next", file=sys.stderr, flush=True)
     net.close()
     del net
     # sequential baseline: a sample of the instances, one at a time, same steps
@@ -275,6 +299,7 @@ def bench_sweep(args, S, W, torch):
         seq_wall += time.perf_counter() - t0
         seq_events += n1.counters()["events"] - e0
         n1.close()
+        print(f"[bench] sequential instance {i + 1}/{nseq} done", file=sys.stderr, flush=True)
     bio = steps * specs[0]["dt"] * 1e-3
     sizes = [W.total_neurons(sp) for sp in specs]
     seq_est = seq_wall * args.instances / nseq

@@ -165,8 +165,11 @@ struct snn_net {
   uint32_t tile_neurons = 0;       // binned delivery (0: direct)
 
   // host raster
+  // host raster: drained entries (gid | mult << 27) with their step, in step
+  // order; within a step sorted by gid from index r_sorted on only when read
   std::vector<uint64_t> r_step;
-  std::vector<uint32_t> r_gid, r_mult;
+  std::vector<uint32_t> r_entry;
+  size_t r_sorted = 0;
 
   double build_ms = 0.0, sim_ms = 0.0;
 };
@@ -303,6 +306,7 @@ double from_device_state(const snn_net* net, int var, uint32_t i, float v) {
 }
 
 snn_status drain(snn_net* net);
+void sort_raster(snn_net* net);
 snn_status build_graphs(snn_net* net);
 
 }  // namespace
@@ -1071,6 +1075,7 @@ snn_status snn_get_spikes(snn_net* net, uint64_t step_lo, uint64_t step_hi, uint
                           uint32_t* mult, size_t cap, size_t* n_out) {
   if (!net || !n_out) return SNN_E_INVALID;
   net->err.clear();
+  sort_raster(net);
   const auto lo = std::lower_bound(net->r_step.begin(), net->r_step.end(), step_lo);
   const auto hi = std::lower_bound(net->r_step.begin(), net->r_step.end(), step_hi);
   const size_t a = (size_t)(lo - net->r_step.begin()), b = (size_t)(hi - net->r_step.begin());
@@ -1079,8 +1084,8 @@ snn_status snn_get_spikes(snn_net* net, uint64_t step_lo, uint64_t step_hi, uint
   const size_t m = std::min(n, cap);
   for (size_t j = 0; j < m; ++j) {
     if (step) step[j] = net->r_step[a + j];
-    if (gid) gid[j] = net->r_gid[a + j];
-    if (mult) mult[j] = net->r_mult[a + j];
+    if (gid) gid[j] = net->r_entry[a + j] & kGidMask;
+    if (mult) mult[j] = net->r_entry[a + j] >> kMultShift;
   }
   return SNN_OK;
 }
@@ -1244,6 +1249,20 @@ snn_status build_graphs(snn_net* net) {
   return record_graph(net, 1, &net->graph_1);
 }
 
+// Order the entries drained since the last read by gid within each step.
+void sort_raster(snn_net* net) {
+  const size_t n = net->r_entry.size();
+  size_t i = net->r_sorted;
+  while (i < n) {
+    size_t j = i + 1;
+    while (j < n && net->r_step[j] == net->r_step[i]) ++j;
+    std::sort(net->r_entry.begin() + (long)i, net->r_entry.begin() + (long)j,
+              [](uint32_t x, uint32_t y) { return (x & kGidMask) < (y & kGidMask); });
+    i = j;
+  }
+  net->r_sorted = n;
+}
+
 // Copy the spikes of steps [drained_step, cur_step) from the device ring
 // into the host raster (sorted by gid within a step).
 snn_status drain(snn_net* net) {
@@ -1269,15 +1288,14 @@ snn_status drain(snn_net* net) {
   if (first_part) HIPCHK(net, hipMemcpy(buf.data(), nd.log + p0, first_part * 4, hipMemcpyDeviceToHost));
   if (total > first_part)
     HIPCHK(net, hipMemcpy(buf.data() + first_part, nd.log, (total - first_part) * 4, hipMemcpyDeviceToHost));
+  net->r_step.reserve(net->r_step.size() + total);
+  net->r_entry.reserve(net->r_entry.size() + total);
   for (uint64_t n = a; n < b; ++n) {
     const uint64_t s0 = cb[n % kChunkRing] - base_a;
     const uint64_t s1 = (n + 1 < b) ? cb[(n + 1) % kChunkRing] - base_a : total;
-    std::sort(buf.begin() + (long)s0, buf.begin() + (long)s1,
-              [](uint32_t x, uint32_t y) { return (x & kGidMask) < (y & kGidMask); });
     for (uint64_t q = s0; q < s1; ++q) {
       net->r_step.push_back(n);
-      net->r_gid.push_back(buf[q] & kGidMask);
-      net->r_mult.push_back(buf[q] >> kMultShift);
+      net->r_entry.push_back(buf[q]);
     }
   }
   net->drained_step = b;
