@@ -463,6 +463,25 @@ __device__ __forceinline__ uint32_t sel_advance(const SelLds& sh, uint32_t np, u
   return lo;
 }
 
+constexpr int kUnroll = 4;  // events per lane and round of a flat scan
+
+// Events e0, e0 + kB, ... (kUnroll of them, those below ev) of a lane: their
+// records r[] and synapse words pl[], all loads issued before any is used.
+__device__ __forceinline__ void sel_gather(const NetDev& nd, const SelLds& sh, uint32_t np, uint64_t ev,
+                                           uint64_t e0, uint32_t& lo, uint32_t* r, uint32_t* pl) {
+#pragma unroll
+  for (int q = 0; q < kUnroll; ++q) {
+    const uint64_t e = e0 + (uint64_t)q * kB;
+    if (e < ev) lo = sel_advance(sh, np, lo, e);
+    r[q] = lo;
+  }
+#pragma unroll
+  for (int q = 0; q < kUnroll; ++q) {
+    const uint64_t e = e0 + (uint64_t)q * kB;
+    pl[q] = (e < ev) ? nd.payload[sh.p_off[r[q]] + (e - sh.p_st[r[q]])] : 0u;
+  }
+}
+
 // Direct delivery of the chunk (flat scan of the synapses of its selected
 // groups): every synapse is one item, consecutive lanes take consecutive
 // synapses of a group, and each adds multiplicity x quantised weight to the
@@ -475,25 +494,20 @@ __device__ uint64_t dlv_flush(const NetDev& nd, DirectLds& sh, uint32_t /*buf: p
   const size_t bstride = (size_t)nd.N * nd.P;
   const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u, P = nd.P;
   uint32_t lo = 0;
-  for (uint64_t e = threadIdx.x; e < ev; e += 2 * kB) {  // two independent events per lane and round
-    const uint64_t e1 = e + kB;
-    lo = sel_advance(sh, np, lo, e);
-    const uint32_t lo1 = (e1 < ev) ? sel_advance(sh, np, lo, e1) : lo;
-    const uint32_t pl0 = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
-    const uint32_t pl1 = (e1 < ev) ? nd.payload[sh.p_off[lo1] + (e1 - sh.p_st[lo1])] : 0u;
+  for (uint64_t e0 = threadIdx.x; e0 < ev; e0 += kUnroll * kB) {  // independent events per lane and round
+    uint32_t r[kUnroll], pl[kUnroll];
+    sel_gather(nd, sh, np, ev, e0, lo, r, pl);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (q == 1 && e1 >= ev) break;
-      const uint32_t pl = q ? pl1 : pl0, r = q ? lo1 : lo;
-      const uint32_t cls = pl & cls_mask;
+    for (int q = 0; q < kUnroll; ++q) {
+      if (e0 + (uint64_t)q * kB >= ev) break;
+      const uint32_t cls = pl[q] & cls_mask;
       const bool in_lds = cls < kClsLds;
-      const int64_t v = (in_lds ? sh.wq[cls] : nd.cls_wq[cls]) * (int64_t)sh.p_mult[r];
+      const int64_t v = (in_lds ? sh.wq[cls] : nd.cls_wq[cls]) * (int64_t)sh.p_mult[r[q]];
       const uint32_t port = in_lds ? sh.wp[cls] : nd.cls_port[cls];
-      int64_t* acc = nd.acc + bstride * sh.p_buf[r];
-      __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl >> cls_bits) * P + port],
+      int64_t* acc = nd.acc + bstride * sh.p_buf[r[q]];
+      __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl[q] >> cls_bits) * P + port],
                              (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    lo = lo1;
   }
   __syncthreads();
   if (threadIdx.x == 0) sh.npair = 0;
@@ -531,21 +545,16 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
   const uint32_t tsh = nd.tile_shift, lmask = (1u << tsh) - 1u, ntl = nd.n_tiles;
   bool bad = false;
   uint32_t lo = 0;
-  for (uint64_t e = threadIdx.x; e < ev; e += 2 * kB) {  // two independent events per lane and round
-    const uint64_t e1 = e + kB;
-    lo = sel_advance(sh, np, lo, e);
-    const uint32_t lo1 = (e1 < ev) ? sel_advance(sh, np, lo, e1) : lo;
-    const uint32_t pl0 = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
-    const uint32_t pl1 = (e1 < ev) ? nd.payload[sh.p_off[lo1] + (e1 - sh.p_st[lo1])] : 0u;
-    const uint32_t t0 = (pl0 >> cls_bits) >> tsh;
-    if (t0 < ntl) atomicAdd(&sh.tcnt[t0], 1u);
-    else bad = true;
-    if (e1 < ev) {
-      const uint32_t t1 = (pl1 >> cls_bits) >> tsh;
-      if (t1 < ntl) atomicAdd(&sh.tcnt[t1], 1u);
+  for (uint64_t e0 = threadIdx.x; e0 < ev; e0 += kUnroll * kB) {  // independent events per lane and round
+    uint32_t r[kUnroll], pl[kUnroll];
+    sel_gather(nd, sh, np, ev, e0, lo, r, pl);
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) {
+      if (e0 + (uint64_t)q * kB >= ev) break;
+      const uint32_t t = (pl[q] >> cls_bits) >> tsh;
+      if (t < ntl) atomicAdd(&sh.tcnt[t], 1u);
       else bad = true;
     }
-    lo = lo1;
   }
   __syncthreads();
   uint32_t* cnt = nd.bin_cnt + (size_t)buf * ntl;
@@ -562,26 +571,21 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
   __syncthreads();
   uint32_t* bins = nd.bins + (size_t)buf * nd.bins_total;
   lo = 0;
-  for (uint64_t e = threadIdx.x; e < ev; e += 2 * kB) {
-    const uint64_t e1 = e + kB;
-    lo = sel_advance(sh, np, lo, e);
-    const uint32_t lo1 = (e1 < ev) ? sel_advance(sh, np, lo, e1) : lo;
-    const uint32_t pl0 = nd.payload[sh.p_off[lo] + (e - sh.p_st[lo])];
-    const uint32_t pl1 = (e1 < ev) ? nd.payload[sh.p_off[lo1] + (e1 - sh.p_st[lo1])] : 0u;
+  for (uint64_t e0 = threadIdx.x; e0 < ev; e0 += kUnroll * kB) {
+    uint32_t r[kUnroll], pl[kUnroll];
+    sel_gather(nd, sh, np, ev, e0, lo, r, pl);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      if (q == 1 && e1 >= ev) break;
-      const uint32_t pl = q ? pl1 : pl0, r = q ? lo1 : lo;
-      const uint32_t tgt = pl >> cls_bits, t = tgt >> tsh;
+    for (int q = 0; q < kUnroll; ++q) {
+      if (e0 + (uint64_t)q * kB >= ev) break;
+      const uint32_t tgt = pl[q] >> cls_bits, t = tgt >> tsh;
       if (t >= ntl) continue;
       const uint32_t slot = atomicAdd(&sh.tcnt[t], 1u);
-      const uint32_t cls = pl & cls_mask, mult = sh.p_mult[r];
+      const uint32_t cls = pl[q] & cls_mask, mult = sh.p_mult[r[q]];
       if (slot < sh.tavail[t])
         bins[sh.tbase[t] + slot] = ((tgt & lmask) << kBinLocalShift) | (mult << kBinMultShift) | cls;
       else
         bin_spill(nd, buf, tgt, cls, mult, t);
     }
-    lo = lo1;
   }
   if (bad) atomicOr(&nd.ctrl->overflow, 4u);  // a target outside the tiles: reported, not written
   __syncthreads();
@@ -873,13 +877,21 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
   const uint32_t* bin = nd.bins + (size_t)buf * nd.bins_total + nd.bin_off[t];
   __syncthreads();
   bool bad = false;
-  for (uint32_t j = threadIdx.x; j < cnt; j += kB) {
-    const uint32_t e = bin[j];
+  auto add = [&](uint32_t e) {
     const uint32_t cls = e & (uint32_t)(kMaxClasses - 1), loc = e >> kBinLocalShift;
-    if (loc >= nt || cls >= nd.n_classes) { bad = true; continue; }
+    if (loc >= nt || cls >= nd.n_classes) { bad = true; return; }
     const int64_t v = sl.c.wq[cls] * (int64_t)((e >> kBinMultShift) & kMaxMult);
     atomicAdd((unsigned long long*)&sl.u.acc[loc * PP + sl.wp[cls]], (unsigned long long)v);
+  };
+  uint32_t j = threadIdx.x;
+  for (; j + 7 * kB < cnt; j += 8 * kB) {  // eight independent loads in flight per lane
+    uint32_t e[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = bin[j + q * kB];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) add(e[q]);
   }
+  for (; j < cnt; j += kB) add(bin[j]);
   if (bad) atomicOr(&nd.ctrl->overflow, 4u);  // a malformed entry: reported, not added
   __syncthreads();
   if (ovf) {  // block-uniform: events that did not fit the bin

@@ -160,7 +160,19 @@ struct snn_net {
   uint64_t log_cap = 0;
   uint64_t drain_steps = 0;
   hipGraphExec_t graph_k = nullptr, graph_1 = nullptr;
-  uint64_t* pinned = nullptr;
+  // raster drain, pipelined: the per-step counts and then the ring segment of
+  // a window of steps are copied to pinned memory behind the graphs, each
+  // collected one graph later, so the device never waits for the host
+  struct Drain {
+    int stage = 0;              // 0 idle, 1 counts copy in flight, 2 ring copy in flight
+    uint64_t a = 0, b = 0;      // window [a, b) of steps
+    uint64_t total = 0;         // entries of the window
+    std::vector<uint64_t> base; // ring position of each step of the window, then the end
+  } dj;
+  hipEvent_t ev_drain = nullptr;
+  uint64_t* pin_cb = nullptr;   // [kChunkRing] copy of the per-step ring positions
+  uint32_t* pin_rc = nullptr;   // [R] copy of the per-step spike counts
+  uint32_t* pinned = nullptr;   // staging of a window's ring entries
   size_t pinned_words = 0;
   uint32_t tile_neurons = 0;       // binned delivery (0: direct)
 
@@ -306,6 +318,8 @@ double from_device_state(const snn_net* net, int var, uint32_t i, float v) {
 }
 
 snn_status drain(snn_net* net);
+snn_status drain_start(snn_net* net);
+snn_status drain_advance(snn_net* net);
 void sort_raster(snn_net* net);
 snn_status build_graphs(snn_net* net);
 
@@ -351,6 +365,9 @@ void snn_destroy_net(snn_net* net) {
   if (net->graph_1) (void)hipGraphExecDestroy(net->graph_1);
   while (!net->allocs.empty()) dev_free(net, net->allocs.back().p);
   if (net->pinned) (void)hipHostFree(net->pinned);
+  if (net->pin_cb) (void)hipHostFree(net->pin_cb);
+  if (net->pin_rc) (void)hipHostFree(net->pin_rc);
+  if (net->ev_drain) (void)hipEventDestroy(net->ev_drain);
   if (net->ev_user) (void)hipEventDestroy(net->ev_user);
   if (net->stream) (void)hipStreamDestroy(net->stream);
   delete net;
@@ -973,7 +990,9 @@ snn_status snn_build(snn_net* net) {
 
   // ---- spike buffers ----
   net->drain_steps = std::max<uint64_t>(kGraphSteps, std::min<uint64_t>(1000, ((1ull << 25) / N) / kGraphSteps * kGraphSteps));
-  net->log_cap = next_pow2((uint64_t)N * (nd.R + net->drain_steps + kGraphSteps + 1));
+  // the ring holds a drain window plus the two graphs launched before its
+  // entries are copied out, at one spike per neuron and step
+  net->log_cap = next_pow2((uint64_t)N * (net->drain_steps + 3 * kGraphSteps + 1));
   uint32_t* d_log; ALLOC(d_log, uint32_t, net->log_cap);
   uint64_t* d_rb; ALLOC(d_rb, uint64_t, nd.R);
   uint32_t* d_rc; ALLOC(d_rc, uint32_t, nd.R);
@@ -986,8 +1005,11 @@ snn_status snn_build(snn_net* net) {
 
   // ---- selection / delivery ----
   // delivery blocks: binned delivery reserves bin space once per touched tile
-  // and chunk, so it wants few, large chunks (at most 256 blocks)
-  nd.sel_grid = std::min<uint32_t>(nd.n_tiles ? 256 : 2048, std::max<uint32_t>(64, nd.nblk_upd));
+  // and chunk, so it wants few, large chunks
+  // (at least 256; more for networks whose steps carry many events, about one
+  // block per 4 M synapses, at most 1024)
+  nd.sel_grid = nd.n_tiles ? (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(256, net->n_syn >> 22))
+                           : std::min<uint32_t>(2048, std::max<uint32_t>(64, nd.nblk_upd));
   const size_t nstat = (size_t)2 * nd.sel_grid;
   ALLOC(nd.sel_stats, uint64_t, nstat);
   HIPCHK(net, hipMemsetAsync(nd.sel_stats, 0, nstat * 8, s));
@@ -997,6 +1019,10 @@ snn_status snn_build(snn_net* net) {
   ALLOC(nd.ctrl, Ctrl, 1);
   HIPCHK(net, hipMemsetAsync(nd.ctrl, 0, sizeof(Ctrl), s));
   net->pinned_words = 0;
+  HIPCHK(net, hipHostMalloc((void**)&net->pin_cb, kChunkRing * 8, hipHostMallocDefault));
+  HIPCHK(net, hipHostMalloc((void**)&net->pin_rc, (size_t)nd.R * 4, hipHostMallocDefault));
+  HIPCHK(net, hipEventCreateWithFlags(&net->ev_drain, hipEventDisableTiming));
+  net->dj = snn_net::Drain();
   HIPCHK(net, hipStreamSynchronize(s));
 #undef ALLOC
   net->built = true;
@@ -1025,11 +1051,19 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
       net->cur_step += 1;
       left -= 1;
     }
-    if (net->cur_step - net->drained_step >= net->drain_steps || left == 0) {
-      st = drain(net);
+    // a pending drain stage is collected now: its copy sits before the graph
+    // just launched, which keeps the device busy meanwhile
+    if (net->dj.stage) {
+      st = drain_advance(net);
+      if (st) return st;
+    }
+    if (net->dj.stage == 0 && net->cur_step - net->drained_step >= net->drain_steps) {
+      st = drain_start(net);
       if (st) return st;
     }
   }
+  st = drain(net);
+  if (st) return st;
   HIPCHK(net, hipStreamSynchronize(net->stream));
   net->sim_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   Ctrl c;
@@ -1263,42 +1297,77 @@ void sort_raster(snn_net* net) {
   net->r_sorted = n;
 }
 
-// Copy the spikes of steps [drained_step, cur_step) from the device ring
-// into the host raster (sorted by gid within a step).
-snn_status drain(snn_net* net) {
-  HIPCHK(net, hipStreamSynchronize(net->stream));
-  const uint64_t a = net->drained_step, b = net->cur_step;
-  if (b <= a) return SNN_OK;
-  if (net->cfg.flags & SNN_F_NO_SPIKE_RECORD) {
-    net->drained_step = b;
+// Drain stage 0 -> 1: copy the per-step ring positions and counts of the
+// steps [drained_step, cur_step) to pinned memory behind the launched work.
+snn_status drain_start(snn_net* net) {
+  snn_net::Drain& d = net->dj;
+  d.a = net->drained_step;
+  d.b = net->cur_step;
+  net->drained_step = d.b;
+  if (d.b <= d.a || (net->cfg.flags & SNN_F_NO_SPIKE_RECORD)) return SNN_OK;
+  const NetDev& nd = net->nd;
+  HIPCHK(net, hipMemcpyAsync(net->pin_cb, nd.chunk_base, kChunkRing * 8, hipMemcpyDeviceToHost, net->stream));
+  HIPCHK(net, hipMemcpyAsync(net->pin_rc, nd.ring_cnt, (size_t)nd.R * 4, hipMemcpyDeviceToHost, net->stream));
+  HIPCHK(net, hipEventRecord(net->ev_drain, net->stream));
+  d.stage = 1;
+  return SNN_OK;
+}
+
+// Drain stage 1 -> 2 (positions known: copy the window's ring entries to the
+// pinned staging buffer) or 2 -> 0 (append them to the host raster).  Waits
+// for the stage's copy.
+snn_status drain_advance(snn_net* net) {
+  snn_net::Drain& d = net->dj;
+  const NetDev& nd = net->nd;
+  if (d.stage == 0) return SNN_OK;
+  HIPCHK(net, hipEventSynchronize(net->ev_drain));
+  if (d.stage == 1) {
+    const uint64_t base_a = net->pin_cb[d.a % kChunkRing];
+    const uint64_t end = net->pin_cb[(d.b - 1) % kChunkRing] + net->pin_rc[(d.b - 1) % nd.R];
+    d.total = end - base_a;
+    if (d.total > net->log_cap) return fail(net, SNN_E_OVERFLOW, "spike ring overrun");
+    d.base.resize(d.b - d.a + 1);
+    for (uint64_t n = d.a; n < d.b; ++n) d.base[n - d.a] = net->pin_cb[n % kChunkRing] - base_a;
+    d.base[d.b - d.a] = d.total;
+    if (d.total > net->pinned_words) {  // no copy is in flight into the staging buffer now
+      if (net->pinned) HIPCHK(net, hipHostFree(net->pinned));
+      net->pinned = nullptr;
+      const size_t words = std::max<size_t>(d.total, 2 * net->pinned_words);
+      HIPCHK(net, hipHostMalloc((void**)&net->pinned, words * 4, hipHostMallocDefault));
+      net->pinned_words = words;
+    }
+    const uint64_t p0 = base_a & nd.log_mask;
+    const uint64_t first_part = std::min<uint64_t>(d.total, net->log_cap - p0);
+    if (first_part)
+      HIPCHK(net, hipMemcpyAsync(net->pinned, nd.log + p0, first_part * 4, hipMemcpyDeviceToHost, net->stream));
+    if (d.total > first_part)
+      HIPCHK(net, hipMemcpyAsync(net->pinned + first_part, nd.log, (d.total - first_part) * 4, hipMemcpyDeviceToHost,
+                                 net->stream));
+    HIPCHK(net, hipEventRecord(net->ev_drain, net->stream));
+    d.stage = 2;
     return SNN_OK;
   }
-  const NetDev& nd = net->nd;
-  std::vector<uint64_t> cb(kChunkRing);
-  std::vector<uint32_t> rc(nd.R);
-  HIPCHK(net, hipMemcpy(cb.data(), nd.chunk_base, kChunkRing * 8, hipMemcpyDeviceToHost));
-  HIPCHK(net, hipMemcpy(rc.data(), nd.ring_cnt, nd.R * 4, hipMemcpyDeviceToHost));
-  const uint64_t base_a = cb[a % kChunkRing];
-  const uint64_t end = cb[(b - 1) % kChunkRing] + rc[(b - 1) % nd.R];
-  const uint64_t total = end - base_a;
-  if (total > net->log_cap) return fail(net, SNN_E_OVERFLOW, "spike ring overrun");
-  std::vector<uint32_t> buf(total);
-  const uint64_t p0 = base_a & nd.log_mask;
-  const uint64_t first_part = std::min<uint64_t>(total, net->log_cap - p0);
-  if (first_part) HIPCHK(net, hipMemcpy(buf.data(), nd.log + p0, first_part * 4, hipMemcpyDeviceToHost));
-  if (total > first_part)
-    HIPCHK(net, hipMemcpy(buf.data() + first_part, nd.log, (total - first_part) * 4, hipMemcpyDeviceToHost));
-  net->r_step.reserve(net->r_step.size() + total);
-  net->r_entry.reserve(net->r_entry.size() + total);
-  for (uint64_t n = a; n < b; ++n) {
-    const uint64_t s0 = cb[n % kChunkRing] - base_a;
-    const uint64_t s1 = (n + 1 < b) ? cb[(n + 1) % kChunkRing] - base_a : total;
-    for (uint64_t q = s0; q < s1; ++q) {
+  net->r_step.reserve(net->r_step.size() + d.total);
+  net->r_entry.reserve(net->r_entry.size() + d.total);
+  for (uint64_t n = d.a; n < d.b; ++n)
+    for (uint64_t q = d.base[n - d.a]; q < d.base[n - d.a + 1]; ++q) {
       net->r_step.push_back(n);
-      net->r_entry.push_back(buf[q]);
+      net->r_entry.push_back(net->pinned[q]);
     }
+  d.stage = 0;
+  return SNN_OK;
+}
+
+// Everything simulated so far into the host raster (waits for the device).
+snn_status drain(snn_net* net) {
+  snn_status st;
+  while (net->dj.stage)
+    if ((st = drain_advance(net))) return st;
+  if (net->cur_step > net->drained_step) {
+    if ((st = drain_start(net))) return st;
+    while (net->dj.stage)
+      if ((st = drain_advance(net))) return st;
   }
-  net->drained_step = b;
   return SNN_OK;
 }
 
