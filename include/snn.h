@@ -82,8 +82,8 @@ typedef struct snn_config {
 #define SNN_F_NO_SPIKE_RECORD 1u /* do not keep the spike raster on the host */
 /* How a step's synaptic events are summed into the targets' integer inputs
    (Sec. 2.2; the sum is the same either way).  Neither flag: binned for
-   networks with AdEx neurons when they fit its limits (at most 1024 tiles),
-   else direct. */
+   networks of 5e8 synapses or more when they fit its limits (at most 1024
+   tiles), else direct. */
 #define SNN_F_DELIVERY_DIRECT 2u /* each event one device-scope int64 atomic add */
 #define SNN_F_DELIVERY_BINNED 4u /* each event a 32-bit entry in its target tile's
                                     bin, summed in LDS by the tile's block at the

@@ -16,7 +16,9 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <utility>
+#include <thread>
 #include <vector>
 
 #include "../../include/snn.h"
@@ -29,6 +31,7 @@ namespace {
 
 constexpr uint32_t kGraphSteps = 100;
 constexpr uint64_t kChunkRing = 4096;  // >= drain interval + graph length
+constexpr uint64_t kBinnedMinSynapses = 500000000;  // default delivery: binned from this size on
 
 struct HostPop {
   int32_t model = 0;
@@ -948,11 +951,12 @@ snn_status snn_build(snn_net* net) {
       return fail(net, SNN_E_UNSUPPORTED, "binned delivery: %llu tiles (at most %u) or %llu synapses onto one tile",
                   (unsigned long long)nt, kMaxTiles, (unsigned long long)max_in);
     net->tile_neurons = 0;
-    // default: binned where events are dense (AdEx networks: 4.0e6 events per
-    // step at 10^6 neurons, 257 us per step binned against 483 us direct),
-    // direct where the step is latency-bound (LIF microcircuit: 21 us direct,
-    // 31 us binned at its best tile size)
-    const bool want = forced || (!(net->cfg.flags & SNN_F_DELIVERY_DIRECT) && net->has_adex);
+    // default: binned for large networks, whose steps carry millions of events
+    // (10^6 AdEx neurons, 10^9 synapses: 176 us per step binned, 320 us direct;
+    // 128 Brunel instances, 8.7e9 synapses: 1.7 ms binned, 6.7 ms direct), direct
+    // below, where the step is latency-bound (microcircuit stand-in, 3e8
+    // synapses: 17 us direct, 25 us binned at its best tile size)
+    const bool want = forced || (!(net->cfg.flags & SNN_F_DELIVERY_DIRECT) && total_syn >= kBinnedMinSynapses);
     if (fits && want) {
       std::vector<uint64_t> off(nt);
       std::vector<uint32_t> cap(nt);
@@ -1283,16 +1287,36 @@ snn_status build_graphs(snn_net* net) {
   return record_graph(net, 1, &net->graph_1);
 }
 
-// Order the entries drained since the last read by gid within each step.
+// Order the entries drained since the last read by gid within each step
+// (steps are independent: large rasters are split over the host's cores).
 void sort_raster(snn_net* net) {
-  const size_t n = net->r_entry.size();
-  size_t i = net->r_sorted;
-  while (i < n) {
-    size_t j = i + 1;
-    while (j < n && net->r_step[j] == net->r_step[i]) ++j;
-    std::sort(net->r_entry.begin() + (long)i, net->r_entry.begin() + (long)j,
-              [](uint32_t x, uint32_t y) { return (x & kGidMask) < (y & kGidMask); });
-    i = j;
+  const size_t n = net->r_entry.size(), lo = net->r_sorted;
+  if (lo >= n) return;
+  auto sort_steps = [net](size_t a, size_t b) {  // [a, b) starts and ends on step boundaries
+    size_t i = a;
+    while (i < b) {
+      size_t j = i + 1;
+      while (j < b && net->r_step[j] == net->r_step[i]) ++j;
+      std::sort(net->r_entry.begin() + (long)i, net->r_entry.begin() + (long)j,
+                [](uint32_t x, uint32_t y) { return (x & kGidMask) < (y & kGidMask); });
+      i = j;
+    }
+  };
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n - lo < (1u << 20) || hw == 1) {
+    sort_steps(lo, n);
+  } else {
+    std::vector<size_t> cut{lo};
+    for (unsigned t = 1; t < hw; ++t) {
+      size_t c = lo + (n - lo) * t / hw;
+      while (c < n && c > cut.back() && net->r_step[c] == net->r_step[c - 1]) ++c;  // to a step boundary
+      cut.push_back(std::max(c, cut.back()));
+    }
+    cut.push_back(n);
+    std::vector<std::thread> th;
+    for (size_t t = 0; t + 1 < cut.size(); ++t)
+      if (cut[t + 1] > cut[t]) th.emplace_back(sort_steps, cut[t], cut[t + 1]);
+    for (auto& x : th) x.join();
   }
   net->r_sorted = n;
 }
@@ -1347,8 +1371,11 @@ snn_status drain_advance(snn_net* net) {
     d.stage = 2;
     return SNN_OK;
   }
-  net->r_step.reserve(net->r_step.size() + d.total);
-  net->r_entry.reserve(net->r_entry.size() + d.total);
+  const size_t need = net->r_step.size() + d.total;
+  if (need > net->r_step.capacity()) {  // geometric growth: an exact reserve per window copies the raster each time
+    net->r_step.reserve(std::max(need, 2 * net->r_step.capacity()));
+    net->r_entry.reserve(std::max(need, 2 * net->r_entry.capacity()));
+  }
   for (uint64_t n = d.a; n < d.b; ++n)
     for (uint64_t q = d.base[n - d.a]; q < d.base[n - d.a + 1]; ++q) {
       net->r_step.push_back(n);
