@@ -43,6 +43,16 @@ HBM_PEAK_GBS = 8000.0
 #    P synaptic currents; AdEx: V, w, h, P conductances) and I_e read;
 #    direct delivery also reads its P int64 inputs.
 BYTES_PER_EVENT = {"direct": 4 + 16, "binned": 4 + 8}
+FP32_PEAK_TFLOPS = 157.3
+
+
+def rk45_flops_per_attempt(ports: int) -> int:
+    """fp32 operations of one attempted Cash-Karp substep of the AdEx model
+    with `ports` conductances (fma = 2, exp2 / log2 / min / max / reciprocal =
+    1): 6 right-hand sides of 15 + 4P, stage sums, fifth-order solution, error
+    estimate and error ratio of 60 per each of the 2 + P components, and 9 of
+    step control."""
+    return 6 * (15 + 4 * ports) + 60 * (2 + ports) + 9
 BYTES_PER_PAIR = 28
 BYTES_PER_SPIKE = 28
 
@@ -254,8 +264,18 @@ def main():
                          "neurons": W.total_neurons(spec), "synapses": W.count_synapses(spec), "dt_ms": dt,
                          "t_bio_s": bio_s, "parallelism": "single GPU"}
         out["paper_context"] = {"rtf_rtx2080ti": 70.0, "note": "alpha conductances in the paper"}
+        att_p = (c3["rk_accepted"] + c3["rk_rejected"] - c2["rk_accepted"] - c2["rk_rejected"]) / ps
+        fpa = rk45_flops_per_attempt(2)
+        tflops = att_p * fpa / (dlv_ms * 1e-3) / 1e12 if dlv_ms > 0 else 0.0
         out["rk45"] = {"accepted_per_step": (c1["rk_accepted"] - c0["rk_accepted"]) / args.steps,
                        "rejected_per_step": (c1["rk_rejected"] - c0["rk_rejected"]) / args.steps}
+        out["rk45_fp32_roofline"] = {"kernel": roofline["kernel"], "bound": "alu", "achieved": round(tflops, 3),
+                                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                     "frac": round(tflops / FP32_PEAK_TFLOPS, 5), "flops_per_attempt": fpa,
+                                     "attempts_per_launch": round(att_p, 1),
+                                     "note": "attempted substeps x flops per attempt / step-kernel duration; the "
+                                             "step is bounded by the serial RK45 chain of neurons in their spike "
+                                             "step (~100 attempts), not by throughput"}
     net.close()
     if not args.no_cpu_baseline and args.workload == "microcircuit":
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -344,9 +364,9 @@ def bench_serve(args):
     trace = V.request_trace(args.requests, rate_hz=args.rate)
     check = (0, 1, len(trace) - 1)
     out = {}
-    for name, mb in (("batched", 64), ("fifo", 1)):
+    for name, mb, nw in (("batched", 64, 4), ("fifo", 1, 1)):
         log(f"serving {len(trace)} requests, {name}")
-        rep = V.Server(max_batch=mb, log=log, digest_ids=set(check)).serve(trace)
+        rep = V.Server(max_batch=mb, workers=nw, log=log, digest_ids=set(check)).serve(trace)
         lat = rep.latencies()
         out[name] = {"requests_per_s": len(trace) / rep.makespan_s, "makespan_s": rep.makespan_s,
                      "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
@@ -364,7 +384,7 @@ def bench_serve(args):
            "p50_latency_s": out["batched"]["p50_latency_s"], "p99_latency_s": out["batched"]["p99_latency_s"],
            "batched": out["batched"], "fifo": out["fifo"],
            "throughput_vs_fifo": out["batched"]["requests_per_s"] / out["fifo"]["requests_per_s"],
-           "identical_alone_and_batched": same,
+           "identical_alone_and_batched": same, "workers": 4,
            "config": {"workload": f"serving trace: {len(trace)} requests, Poisson arrivals at {args.rate:g}/s, "
                                   "alternately microcircuit stand-in at scale U[0.1,1] and balanced AdEx with "
                                   "N ~ U[10k,200k], K = 1000, each for U[0.1,2] s of biological time",

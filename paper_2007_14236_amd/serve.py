@@ -1,15 +1,18 @@
 """Batched serving of simulation requests on one GPU.
 
 A request is a network specification and a biological duration.  Requests
-arrive over time; each model family has a worker that, whenever its previous
-batch is done, packs the queued requests of its family that fit the
-device-memory budget and binned delivery's capacity as independent instances
-of one network (``snn_begin_instance``) and advances them together in the same
-kernels, on the network's own stream beside the other family's batches; each
-request completes, with its own raster, when the batch reaches its duration.
-Instances draw exactly what they would draw alone, so a request's result does
-not depend on what it was batched with.  With ``max_batch=1`` one worker
-serves the requests one at a time in arrival order (the FIFO baseline).
+arrive over time into one queue.  A pool of workers takes them: a free worker
+packs the queued requests of the oldest request's model family that fit the
+memory left in the budget (by the estimate below) and binned delivery's
+resident capacity as independent instances of one network
+(``snn_begin_instance``) and advances them together in the same kernels, on
+the network's own stream; the workers' batches overlap on the device, so a
+request that arrives while others run is admitted as soon as a worker and
+memory are free.  Each request completes, with its own raster, when its batch
+reaches its duration.  Instances draw exactly what they would draw alone, so
+a request's result does not depend on what it was batched with.  With one
+worker and ``max_batch=1`` the same loop serves the requests one at a time in
+arrival order (the FIFO baseline).
 
 Only host-side scheduling lives here: every simulation step runs in the
 library's kernels through the C ABI.
@@ -134,15 +137,15 @@ def neuron_ports(spec: dict) -> int:
 
 class Server:
     """Batching scheduler over the C ABI.  `budget_bytes` bounds the estimated
-    device memory of the batches in flight; `max_batch` bounds the instances of
-    a batch, and a batch stays within what binned delivery holds.  With
-    max_batch > 1 each model family has its own worker (its batches run on
-    their own stream, beside the other family's); with max_batch = 1 one
-    worker serves all requests in arrival order."""
+    device memory of the batches in flight, `workers` how many run at once,
+    `max_batch` the instances of one batch; a batch also stays within what
+    binned delivery holds resident."""
 
-    def __init__(self, budget_bytes: int = 200 << 30, max_batch: int = 64, log=None, digest_ids=None):
+    def __init__(self, budget_bytes: int = 200 << 30, max_batch: int = 64, workers: int = 4, log=None,
+                 digest_ids=None):
         self.budget = budget_bytes
         self.max_batch = max_batch
+        self.workers = workers
         self.log = log
         self.digest_ids = digest_ids  # requests whose raster digest is taken (None: all)
         self.lock = threading.Lock()
@@ -207,41 +210,54 @@ class Server:
             self.log(f"batch of {len(batch)} {batch[0].family} requests done at {time.perf_counter() - t0:.2f} s "
                      f"(started {start:.2f} s; {done} steps simulated in {t_sim:.2f} s, rasters {t_ras:.2f} s)")
 
-    def _worker(self, family, trace, t0, rep, budget, errors):
-        """Serve the requests of `family` (None: all) in real time."""
-        mine = [r for r in trace if family is None or r.family == family]
-        queue: list = []
-        nxt = served = 0
-        try:
-            while served < len(mine):
-                now = time.perf_counter() - t0
-                while nxt < len(mine) and mine[nxt].arrival_s <= now:
-                    queue.append(mine[nxt])
-                    nxt += 1
-                if not queue:
-                    time.sleep(max(0.0, min(0.002, mine[nxt].arrival_s - now)))
-                    continue
-                batch = self._take_batch(queue, budget)
-                self._serve_batch(batch, t0, rep)
-                served += len(batch)
-        except Exception as e:  # reported by serve()
-            errors.append(e)
-
     def serve(self, trace: list) -> ServeReport:
         """Serve the trace in real time (arrivals released at their times)."""
         rep = ServeReport()
         errors: list = []
+        state = {"next": 0, "queue": [], "in_flight": 0, "taken": 0}
+        cv = threading.Condition(self.lock)
         t0 = time.perf_counter()
-        if self.max_batch == 1:
-            self._worker(None, trace, t0, rep, self.budget, errors)
-        else:
-            fams = sorted({r.family for r in trace})
-            threads = [threading.Thread(target=self._worker, args=(f, trace, t0, rep, self.budget // len(fams), errors))
-                       for f in fams]
-            for th in threads:
-                th.start()
-            for th in threads:
-                th.join()
+
+        def release(now):  # with the lock held: arrivals up to `now` into the queue
+            while state["next"] < len(trace) and trace[state["next"]].arrival_s <= now:
+                state["queue"].append(trace[state["next"]])
+                state["next"] += 1
+
+        def worker():
+            try:
+                while True:
+                    with cv:
+                        while True:
+                            if errors or state["taken"] == len(trace):
+                                return
+                            now = time.perf_counter() - t0
+                            release(now)
+                            free = self.budget - state["in_flight"]
+                            q = state["queue"]
+                            if q and (q[0].est_bytes <= free or state["in_flight"] == 0):
+                                batch = self._take_batch(q, max(free, 0))
+                                used = sum(r.est_bytes for r in batch)
+                                state["in_flight"] += used
+                                state["taken"] += len(batch)
+                                break
+                            wait = (trace[state["next"]].arrival_s - now) if state["next"] < len(trace) else 0.05
+                            cv.wait(timeout=min(max(wait, 0.0005), 0.05))
+                    try:
+                        self._serve_batch(batch, t0, rep)
+                    finally:
+                        with cv:
+                            state["in_flight"] -= used
+                            cv.notify_all()
+            except Exception as e:  # reported by serve()
+                with cv:
+                    errors.append(e)
+                    cv.notify_all()
+
+        threads = [threading.Thread(target=worker) for _ in range(max(1, self.workers))]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
         if errors:
             raise errors[0]
         rep.makespan_s = max(r.finish_s for r in rep.results) - min(r.arrival_s for r in trace)

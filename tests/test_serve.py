@@ -32,6 +32,34 @@ def _req(rid, family, nbytes):
     return V.Request(rid, 0.01 * rid, family, {}, 100, nbytes)
 
 
+def test_pool_serves_every_request_once_within_budget(monkeypatch):
+    """Host logic of the worker pool, the device replaced by a recorder: every
+    request is served once, no more than `workers` batches run at once, and the
+    estimated bytes in flight stay within the budget."""
+    import threading
+    import time
+    active, peak, bytes_peak, seen = [0], [0], [0], []
+    lock = threading.Lock()
+
+    def fake_batch(self, batch, t0, rep):
+        with lock:
+            active[0] += 1
+            peak[0] = max(peak[0], active[0])
+            seen.extend(r.rid for r in batch)
+            bytes_peak[0] = max(bytes_peak[0], sum(r.est_bytes for r in batch))
+        time.sleep(0.01)
+        for r in batch:
+            rep.results.append(V.Result(r.rid, r.arrival_s, 0.0, time.perf_counter() - t0, len(batch), 0, ""))
+        with lock:
+            active[0] -= 1
+
+    monkeypatch.setattr(V.Server, "_serve_batch", fake_batch)
+    reqs = [V.Request(i, 0.002 * i, "ab"[i % 2], {}, 10, 40) for i in range(40)]
+    rep = V.Server(budget_bytes=200, max_batch=8, workers=3).serve(reqs)
+    assert sorted(seen) == list(range(40)) and len(rep.results) == 40
+    assert peak[0] <= 3 and bytes_peak[0] <= 200
+
+
 def test_batches_take_the_oldest_family_in_order_within_budget():
     srv = V.Server(budget_bytes=100, max_batch=3)
     q = [_req(0, "a", 30), _req(1, "b", 10), _req(2, "a", 30), _req(3, "a", 30), _req(4, "a", 30)]
@@ -66,7 +94,7 @@ def test_served_results_equal_requests_alone():
     for i in range(6):
         spec = W.brunel_lif(n=300 + 50 * i, k=30, g=5.0, nu_ext=300.0, delay=("uniform", 0.1, 3.0), seed=500 + i)
         reqs.append(V.Request(i, 0.0, "lif", spec, 200 + 37 * i, V.estimate_bytes(spec)))
-    rep = V.Server(max_batch=4).serve(reqs)
+    rep = V.Server(max_batch=4, workers=2).serve(reqs)
     assert rep.batches == 2 and len(rep.results) == 6
     assert sorted(r.batch_size for r in rep.results) == [2, 2, 4, 4, 4, 4]
     for r in rep.results:
