@@ -57,9 +57,10 @@ BYTES_PER_PAIR = 28
 BYTES_PER_SPIKE = 28
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch of the step kernel from the committed counter
-    summary, or None when the kernel sources have changed since it was taken."""
+    summary, or None when the kernel sources have changed since it was taken
+    (or it was taken for another kernel on this workload)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -70,6 +71,8 @@ def measured_traffic(workload: str):
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
     if h.hexdigest() != rec["kernel_sources_sha256"] or workload not in rec["workloads"]:
+        return None
+    if rec["workloads"][workload]["kernel"] != kernel:
         return None
     return rec["workloads"][workload]["bytes_per_launch"]
 
@@ -107,6 +110,8 @@ def parse():
     ap.add_argument("--instances", type=int, default=128, help="sweep: number of instances")
     ap.add_argument("--seq-instances", type=int, default=16,
                     help="sweep: instances also run one by one (sequential baseline sample)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (delivery mode, tile size, delivery blocks chosen by timing)")
     ap.add_argument("--delivery", choices=["auto", "direct", "binned"], default="auto",
                     help="how events are summed: device atomics, or bins per target tile summed in LDS")
     ap.add_argument("--tile-neurons", type=int, default=0, help="binned delivery: neurons per tile (0: library)")
@@ -180,8 +185,17 @@ def main():
     dt = spec["dt"]
     print(f"[bench] building {spec['name']}: {W.total_neurons(spec)} neurons, "
           f"{W.count_synapses(spec):.4g} synapses", file=sys.stderr, flush=True)
+    tuned, tune_s = None, 0.0
+    kw = dict(delivery=args.delivery, tile_neurons=args.tile_neurons, bin_capacity=args.bin_capacity)
+    if not args.no_tune and args.delivery == "auto" and not args.tile_neurons:
+        from paper_2007_14236_amd import autotune as A
+        t0 = time.perf_counter()
+        best, table = A.tune(spec, log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        tune_s = time.perf_counter() - t0
+        tuned = {"chosen": best, "candidates": table, "seconds": round(tune_s, 2)}
+        kw = dict(best, bin_capacity=args.bin_capacity)
     t0 = time.perf_counter()
-    net = S.Net(spec, delivery=args.delivery, tile_neurons=args.tile_neurons, bin_capacity=args.bin_capacity)
+    net = S.Net(spec, **kw)
     build_s = time.perf_counter() - t0
     mode = "binned" if net.counters()["delivery"] == 2 else "direct"
     net.simulate(args.warmup)
@@ -219,7 +233,7 @@ def main():
         "kernel": "k_step_binned" if mode == "binned" else "k_step", "bound": "hbm",
         "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": measured_traffic(args.workload) if args.delivery == "auto" else None,
+        "traffic": measured_traffic(args.workload, "k_step_binned" if mode == "binned" else "k_step"),
         "avg_launch_us": round(dlv_ms * 1e3, 3), "bytes_per_launch": round(dlv_bytes),
         "neuron_bytes_per_launch": neuron_bytes,
         "events_per_launch": round(ev_p, 1), "pairs_per_launch": round(pr_p, 1),
@@ -257,6 +271,7 @@ def main():
         "paper_context": {"rtf_rtx2080ti": 1.055, "rtf_v100": 1.641,
                           "note": "real microcircuit (this is a synthetic stand-in of the same size)"},
         "roofline": roofline,
+        "autotune": tuned,
     }
     if args.workload == "adex":
         out["config"] = {"workload": "balanced AdEx network: 1,000,000 neurons (800k E / 200k I), in-degree 1000, "
@@ -291,9 +306,17 @@ def bench_sweep(args, S, W, torch):
     print(f"[bench] building the batch: {args.instances} instances, "
           f"{sum(W.total_neurons(sp) for sp in specs)} neurons, "
           f"{sum(W.count_synapses(sp) for sp in specs):.4g} synapses", file=sys.stderr, flush=True)
+    kw = dict(delivery=args.delivery, tile_neurons=args.tile_neurons, bin_capacity=args.bin_capacity)
+    tuned = None
+    if not args.no_tune and args.delivery == "auto" and not args.tile_neurons:
+        from paper_2007_14236_amd import autotune as A
+        t0 = time.perf_counter()
+        best, table = A.tune(specs, steps=200, warmup=100,
+                             log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+        tuned = {"chosen": best, "candidates": table, "seconds": round(time.perf_counter() - t0, 2)}
+        kw = dict(best, bin_capacity=args.bin_capacity)
     t0 = time.perf_counter()
-    net = S.Net(specs, record=True, delivery=args.delivery, tile_neurons=args.tile_neurons,
-                bin_capacity=args.bin_capacity)
+    net = S.Net(specs, record=True, **kw)
     build_s = time.perf_counter() - t0
     mode = "binned" if net.counters()["delivery"] == 2 else "direct"
     print(f"[bench] built in {build_s:.1f} s ({mode} delivery); warm-up {args.warmup} steps", file=sys.stderr,
@@ -338,7 +361,7 @@ def bench_sweep(args, S, W, torch):
     out = {"metric": METRIC, "value": events / wall, "unit": "events/s", "n_gpus": 1, "steps": steps,
            "warmup": args.warmup, "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32 state, i64 fixed-point input", "data": "synthetic",
-           "rtf": wall / bio, "build_s": build_s, "delivery": mode,
+           "rtf": wall / bio, "build_s": build_s, "delivery": mode, "autotune": tuned,
            "batched_instance_seconds_per_wall_second": args.instances * bio / wall,
            "sequential_sample": {"instances": nseq, "delivery": "faster of direct and binned per instance",
                                  "wall_s": seq_wall, "events_per_s": seq_events / seq_wall,

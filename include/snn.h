@@ -75,9 +75,12 @@ typedef struct snn_config {
                                of two in [256, 4096 / P2] with P2 the port count
                                rounded up to a power of two; 0 = library choice */
   uint32_t bin_capacity;    /* binned delivery: entries per tile bin (each of
-                               two parities); 0 = library choice, at most the
-                               number of synapses onto the tile.  Events beyond
-                               it are still delivered exactly (by atomics)    */
+                               three input buffers); 0 = library choice, at most
+                               the number of synapses onto the tile.  Events
+                               beyond it are still delivered exactly (atomics) */
+  uint32_t delivery_blocks; /* blocks that deliver delays >= 3, 1..8192;
+                               0 = library choice                             */
+  uint32_t reserved;        /* 0                                              */
 } snn_config;
 #define SNN_F_NO_SPIKE_RECORD 1u /* do not keep the spike raster on the host */
 /* How a step's synaptic events are summed into the targets' integer inputs
@@ -147,6 +150,8 @@ typedef struct snn_counters {
                               bin full and were added by atomics instead     */
   uint32_t delivery;       /* 1 direct, 2 binned (after build)                */
   uint32_t tile_neurons;   /* binned delivery: neurons per target tile        */
+  uint32_t delivery_blocks; /* blocks delivering delays >= 3                  */
+  uint32_t pad;
 } snn_counters;
 
 /* ---- lifecycle ---------------------------------------------------------- */

@@ -191,6 +191,20 @@ struct snn_net {
 
 namespace {
 
+// Copies on the library's own stream, waited for: never on the legacy default
+// stream, which would have to order itself against every blocking stream of
+// the process (and fails while another thread captures a graph).
+hipError_t copy_sync(snn_net* net, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, net->stream);
+  return e == hipSuccess ? hipStreamSynchronize(net->stream) : e;
+}
+
+hipError_t copy2d_sync(snn_net* net, void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                       size_t height, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpy2DAsync(dst, dpitch, src, spitch, width, height, kind, net->stream);
+  return e == hipSuccess ? hipStreamSynchronize(net->stream) : e;
+}
+
 snn_status fail(snn_net* net, snn_status code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -337,6 +351,7 @@ snn_status snn_create_net(const snn_config* cfg, const snn_device* dev, snn_net*
   if (!(cfg->dt_ms > 0) || cfg->max_delay_steps < 1 || cfg->max_delay_steps > 63) return SNN_E_INVALID;
   if ((cfg->flags & SNN_F_DELIVERY_DIRECT) && (cfg->flags & SNN_F_DELIVERY_BINNED)) return SNN_E_INVALID;
   if (cfg->flags & ~(SNN_F_NO_SPIKE_RECORD | SNN_F_DELIVERY_DIRECT | SNN_F_DELIVERY_BINNED)) return SNN_E_INVALID;
+  if (cfg->delivery_blocks > 8192 || cfg->reserved) return SNN_E_INVALID;
   if (cfg->tile_neurons && (cfg->tile_neurons < 256 || cfg->tile_neurons > (uint32_t)kTileAccWords ||
                             (cfg->tile_neurons & (cfg->tile_neurons - 1))))
     return SNN_E_INVALID;
@@ -556,7 +571,7 @@ snn_status snn_set_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
     std::vector<int32_t> buf(n);
     for (uint32_t j = 0; j < n; ++j) buf[j] = (int32_t)v[nv == 1 ? 0 : j];
     if (!nd.refr) return fail(net, SNN_E_INVALID, "no refractory state in this network");
-    HIPCHK(net, hipMemcpy(nd.refr + first, buf.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, nd.refr + first, buf.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
     return leave(net);
   }
   float* base = nullptr;
@@ -574,9 +589,9 @@ snn_status snn_set_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
   std::vector<float> buf(n);
   for (uint32_t j = 0; j < n; ++j) buf[j] = to_device_state(net, var, first + j, v[nv == 1 ? 0 : j]);
   if (stride == 1) {
-    HIPCHK(net, hipMemcpy(base + first, buf.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, base + first, buf.data(), n * sizeof(float), hipMemcpyHostToDevice));
   } else {
-    HIPCHK(net, hipMemcpy2D(base + (size_t)first * stride + off, stride * sizeof(float), buf.data(), sizeof(float),
+    HIPCHK(net, copy2d_sync(net, base + (size_t)first * stride + off, stride * sizeof(float), buf.data(), sizeof(float),
                             sizeof(float), n, hipMemcpyHostToDevice));
   }
   return leave(net);
@@ -611,7 +626,7 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
   if (var == SNN_V_REFR) {
     if (!nd.refr) return fail(net, SNN_E_INVALID, "no refractory state in this network");
     std::vector<int32_t> buf(n);
-    HIPCHK(net, hipMemcpy(buf.data(), nd.refr + first, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(net, copy_sync(net, buf.data(), nd.refr + first, n * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (uint32_t j = 0; j < n; ++j) out[j] = buf[j];
     return leave(net);
   }
@@ -629,9 +644,9 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
   if (!base) return fail(net, SNN_E_INVALID, "state variable not present in this network");
   std::vector<float> buf(n);
   if (stride == 1) {
-    HIPCHK(net, hipMemcpy(buf.data(), base + first, n * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(net, copy_sync(net, buf.data(), base + first, n * sizeof(float), hipMemcpyDeviceToHost));
   } else {
-    HIPCHK(net, hipMemcpy2D(buf.data(), sizeof(float), base + (size_t)first * stride + off, stride * sizeof(float),
+    HIPCHK(net, copy2d_sync(net, buf.data(), sizeof(float), base + (size_t)first * stride + off, stride * sizeof(float),
                             sizeof(float), n, hipMemcpyDeviceToHost));
   }
   for (uint32_t j = 0; j < n; ++j) out[j] = from_device_state(net, var, first + j, buf[j]);
@@ -864,14 +879,14 @@ snn_status snn_build(snn_net* net) {
   if (nbig > big_cap) return fail(net, SNN_E_UNSUPPORTED, "too many connection groups above 16384 synapses");
   if (nbig) {  // rare: very large groups are sorted on the host
     std::vector<uint64_t> big(nbig);
-    HIPCHK(net, hipMemcpy(big.data(), d_big, nbig * 8, hipMemcpyDeviceToHost));
+    HIPCHK(net, copy_sync(net, big.data(), d_big, nbig * 8, hipMemcpyDeviceToHost));
     for (uint64_t gi : big) {
       uint64_t be[2];
-      HIPCHK(net, hipMemcpy(be, d_goff + gi, 16, hipMemcpyDeviceToHost));
+      HIPCHK(net, copy_sync(net, be, d_goff + gi, 16, hipMemcpyDeviceToHost));
       std::vector<uint32_t> seg(be[1] - be[0]);
-      HIPCHK(net, hipMemcpy(seg.data(), d_pay + be[0], seg.size() * 4, hipMemcpyDeviceToHost));
+      HIPCHK(net, copy_sync(net, seg.data(), d_pay + be[0], seg.size() * 4, hipMemcpyDeviceToHost));
       std::sort(seg.begin(), seg.end());
-      HIPCHK(net, hipMemcpy(d_pay + be[0], seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(net, copy_sync(net, d_pay + be[0], seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
     }
   }
   dev_free(net, d_big); dev_free(net, d_nbig);
@@ -891,18 +906,18 @@ snn_status snn_build(snn_net* net) {
     hv[i] = (pp.model == SNN_AEIF_COND_EXP) ? (float)V : (float)(V - pp.E_L);
     hie[i] = (float)net->Ie[i];
   }
-  HIPCHK(net, hipMemcpy(d_V, hv.data(), N * 4, hipMemcpyHostToDevice));
-  HIPCHK(net, hipMemcpy(d_Ie, hie.data(), N * 4, hipMemcpyHostToDevice));
+  HIPCHK(net, copy_sync(net, d_V, hv.data(), N * 4, hipMemcpyHostToDevice));
+  HIPCHK(net, copy_sync(net, d_Ie, hie.data(), N * 4, hipMemcpyHostToDevice));
   nd.V = d_V; nd.Ie = d_Ie;
   std::vector<float> hp((size_t)N * P);
   if (net->has_lif) {
     int32_t* d_r; ALLOC(d_r, int32_t, N);
-    HIPCHK(net, hipMemcpy(d_r, net->refr.data(), N * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, d_r, net->refr.data(), N * 4, hipMemcpyHostToDevice));
     nd.refr = d_r;
     float* d_I; ALLOC(d_I, float, (size_t)N * P);
     for (uint32_t i = 0; i < N; ++i)
       for (uint32_t q = 0; q < P; ++q) hp[(size_t)i * P + q] = (float)net->Isyn[(size_t)i * kMaxPorts + q];
-    HIPCHK(net, hipMemcpy(d_I, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, d_I, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
     nd.Isyn = d_I;
   }
   if (net->has_adex) {
@@ -913,9 +928,9 @@ snn_status snn_build(snn_net* net) {
     for (uint32_t i = 0; i < N; ++i) { hw[i] = (float)net->w[i]; hh[i] = (float)net->h[i]; }
     for (uint32_t i = 0; i < N; ++i)
       for (uint32_t q = 0; q < P; ++q) hp[(size_t)i * P + q] = (float)net->g[(size_t)i * kMaxPorts + q];
-    HIPCHK(net, hipMemcpy(d_w, hw.data(), N * 4, hipMemcpyHostToDevice));
-    HIPCHK(net, hipMemcpy(d_h, hh.data(), N * 4, hipMemcpyHostToDevice));
-    HIPCHK(net, hipMemcpy(d_g, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, d_w, hw.data(), N * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, d_h, hh.data(), N * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, d_g, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
     nd.w = d_w; nd.h = d_h; nd.g = d_g;
   }
   int64_t* d_acc; ALLOC(d_acc, int64_t, (size_t)kInBuf * N * P);
@@ -1014,6 +1029,7 @@ snn_status snn_build(snn_net* net) {
   // block per 4 M synapses, at most 1024)
   nd.sel_grid = nd.n_tiles ? (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(256, net->n_syn >> 22))
                            : std::min<uint32_t>(2048, std::max<uint32_t>(64, nd.nblk_upd));
+  if (net->cfg.delivery_blocks) nd.sel_grid = net->cfg.delivery_blocks;
   const size_t nstat = (size_t)2 * nd.sel_grid;
   ALLOC(nd.sel_stats, uint64_t, nstat);
   HIPCHK(net, hipMemsetAsync(nd.sel_stats, 0, nstat * 8, s));
@@ -1071,7 +1087,7 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
   HIPCHK(net, hipStreamSynchronize(net->stream));
   net->sim_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   Ctrl c;
-  HIPCHK(net, hipMemcpy(&c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
+  HIPCHK(net, copy_sync(net, &c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
   if (c.overflow) return fail(net, SNN_E_OVERFLOW, "device range check failed (flags 0x%x)", c.overflow);
   return leave(net);
 }
@@ -1140,15 +1156,15 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   if (st) return st;
   HIPCHK(net, hipStreamSynchronize(net->stream));
   Ctrl c;
-  HIPCHK(net, hipMemcpy(&c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
+  HIPCHK(net, copy_sync(net, &c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
   std::vector<uint64_t> ss((size_t)2 * net->nd.sel_grid);
-  HIPCHK(net, hipMemcpy(ss.data(), net->nd.sel_stats, ss.size() * 8, hipMemcpyDeviceToHost));
+  HIPCHK(net, copy_sync(net, ss.data(), net->nd.sel_stats, ss.size() * 8, hipMemcpyDeviceToHost));
   for (size_t b = 0; b < ss.size() / 2; ++b) {
     out->pairs += ss[2 * b];
     out->events += ss[2 * b + 1];
   }
   std::vector<uint64_t> bs((size_t)kBlkStats * net->nd.nblk_upd);
-  HIPCHK(net, hipMemcpy(bs.data(), net->nd.blk_stats, bs.size() * 8, hipMemcpyDeviceToHost));
+  HIPCHK(net, copy_sync(net, bs.data(), net->nd.blk_stats, bs.size() * 8, hipMemcpyDeviceToHost));
   for (size_t b = 0; b < net->nd.nblk_upd; ++b) {
     const uint64_t* st = &bs[(size_t)kBlkStats * b];
     out->rk_accepted += st[0];
@@ -1166,6 +1182,7 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   out->spill_events = c.spill_events;
   out->delivery = net->tile_neurons ? 2u : 1u;
   out->tile_neurons = net->tile_neurons;
+  out->delivery_blocks = net->nd.sel_grid;
   return leave(net);
 }
 
@@ -1180,7 +1197,7 @@ snn_status snn_get_input(snn_net* net, uint32_t first, uint32_t n, uint32_t port
   const uint32_t buf = (uint32_t)(net->cur_step % kInBuf);
   const int64_t* base = net->nd.acc + (size_t)buf * net->N * net->P;
   if (!net->nd.n_tiles || n == 0) {
-    if (n) HIPCHK(net, hipMemcpy2D(out, 8, base + (size_t)first * net->P + port, net->P * 8, 8, n, hipMemcpyDeviceToHost));
+    if (n) HIPCHK(net, copy2d_sync(net, out, 8, base + (size_t)first * net->P + port, net->P * 8, 8, n, hipMemcpyDeviceToHost));
     return leave(net);
   }
   // binned: the spilled part (acc) plus the entries waiting in the tiles' bins
@@ -1190,7 +1207,7 @@ snn_status snn_get_input(snn_net* net, uint32_t first, uint32_t n, uint32_t port
                                   hipMemcpyDeviceToDevice, net->stream);
   if (e == hipSuccess) e = launch_pending_input(net->nd, buf, first, n, port, d, net->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
-  if (e == hipSuccess) e = hipMemcpy(out, d, (size_t)n * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = copy_sync(net, out, d, (size_t)n * 8, hipMemcpyDeviceToHost);
   dev_free(net, d);
   if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "input readback: %s", hipGetErrorString(e));
   return leave(net);
@@ -1215,7 +1232,7 @@ snn_status snn_poisson_counts(snn_net* net, uint64_t step, uint32_t first, uint3
   if (!d) return fail(net, SNN_E_NOMEM, "allocation failed");
   hipError_t e = launch_poisson_counts(net->nd, step, first, n, d, net->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
-  if (e == hipSuccess) e = hipMemcpy(k, d, (size_t)n * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = copy_sync(net, k, d, (size_t)n * 4, hipMemcpyDeviceToHost);
   dev_free(net, d);
   if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "poisson counts: %s", hipGetErrorString(e));
   return leave(net);
@@ -1235,10 +1252,10 @@ snn_status snn_export_synapses(snn_net* net, uint32_t* src, uint32_t* delay, uin
   const uint32_t N = net->N;
   std::vector<uint64_t> mask(N), goff(net->n_groups + 1);
   std::vector<uint32_t> gp((size_t)N + 1), pay(net->n_syn);
-  HIPCHK(net, hipMemcpy(mask.data(), net->nd.src_mask, (size_t)N * 8, hipMemcpyDeviceToHost));
-  HIPCHK(net, hipMemcpy(gp.data(), net->nd.grp_ptr, ((size_t)N + 1) * 4, hipMemcpyDeviceToHost));
-  HIPCHK(net, hipMemcpy(goff.data(), net->nd.grp_off, (net->n_groups + 1) * 8, hipMemcpyDeviceToHost));
-  if (net->n_syn) HIPCHK(net, hipMemcpy(pay.data(), net->nd.payload, net->n_syn * 4, hipMemcpyDeviceToHost));
+  HIPCHK(net, copy_sync(net, mask.data(), net->nd.src_mask, (size_t)N * 8, hipMemcpyDeviceToHost));
+  HIPCHK(net, copy_sync(net, gp.data(), net->nd.grp_ptr, ((size_t)N + 1) * 4, hipMemcpyDeviceToHost));
+  HIPCHK(net, copy_sync(net, goff.data(), net->nd.grp_off, (net->n_groups + 1) * 8, hipMemcpyDeviceToHost));
+  if (net->n_syn) HIPCHK(net, copy_sync(net, pay.data(), net->nd.payload, net->n_syn * 4, hipMemcpyDeviceToHost));
   size_t e = 0;
   for (uint32_t s = 0; s < N; ++s) {
     uint64_t m = mask[s];

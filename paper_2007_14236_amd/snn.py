@@ -36,7 +36,8 @@ class SnnError(RuntimeError):
 
 class Config(C.Structure):
     _fields_ = [("dt_ms", C.c_double), ("seed", C.c_uint64), ("max_delay_steps", C.c_uint32),
-                ("flags", C.c_uint32), ("tile_neurons", C.c_uint32), ("bin_capacity", C.c_uint32)]
+                ("flags", C.c_uint32), ("tile_neurons", C.c_uint32), ("bin_capacity", C.c_uint32),
+                ("delivery_blocks", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -53,7 +54,7 @@ class Counters(C.Structure):
                 ("n_synapses", C.c_uint64), ("n_groups", C.c_uint64), ("device_bytes", C.c_uint64),
                 ("build_ms", C.c_double), ("simulate_ms", C.c_double), ("overflow", C.c_uint32),
                 ("max_delay_used", C.c_uint32), ("spill_events", C.c_uint64), ("delivery", C.c_uint32),
-                ("tile_neurons", C.c_uint32)]
+                ("tile_neurons", C.c_uint32), ("delivery_blocks", C.c_uint32), ("pad", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -149,7 +150,7 @@ class Net:
     advance together in the same kernels."""
 
     def __init__(self, spec, allocator: TorchAllocator | None = None, record: bool = True, build: bool = True,
-                 delivery: str = "auto", tile_neurons: int = 0, bin_capacity: int = 0):
+                 delivery: str = "auto", tile_neurons: int = 0, bin_capacity: int = 0, delivery_blocks: int = 0):
         self.L = lib()
         specs = list(spec) if isinstance(spec, (list, tuple)) else [spec]
         self.spec = spec
@@ -159,7 +160,7 @@ class Net:
             if sp["dt"] != dt or sp["dmax"] != dmax:
                 raise ValueError("all instances of a batch share dt and Dmax")
         flags = (0 if record else F_NO_SPIKE_RECORD) | DELIVERY[delivery]
-        cfg = Config(dt, specs[0]["seed"], dmax, flags, tile_neurons, bin_capacity)
+        cfg = Config(dt, specs[0]["seed"], dmax, flags, tile_neurons, bin_capacity, delivery_blocks, 0)
         self._dev = self.alloc.device_struct()
         h = C.c_void_p()
         self._check(self.L.snn_create_net(C.byref(cfg), C.byref(self._dev), C.byref(h)), None)
