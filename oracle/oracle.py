@@ -15,11 +15,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-LIF_DELTA, LIF_EXP, AEIF_COND_EXP = 0, 1, 2
+LIF_DELTA, LIF_EXP, AEIF_COND_EXP, AEIF_COND_BETA = 0, 1, 2, 3
 FP64, FP32SO = 0, 1
-MODEL_IDS = {"lif_delta": LIF_DELTA, "lif_exp": LIF_EXP, "aeif_cond_exp": AEIF_COND_EXP}
+MODEL_IDS = {"lif_delta": LIF_DELTA, "lif_exp": LIF_EXP, "aeif_cond_exp": AEIF_COND_EXP,
+             "aeif_cond_beta": AEIF_COND_BETA}
 DELAY_IDS = {"const": 0, "uniform": 1, "normal": 2}
-VAR_IDS = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6}
+VAR_IDS = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6, "g_rise": 7}
 MAX_PORTS = 4
 POISSON_KMAX = 128
 
@@ -33,6 +34,7 @@ class PopParams(C.Structure):
         ("a", C.c_double), ("b", C.c_double), ("V_peak", C.c_double), ("V_r", C.c_double),
         ("tau_syn", C.c_double * MAX_PORTS), ("E_rev", C.c_double * MAX_PORTS),
         ("rk_eps", C.c_double), ("rk_hmin", C.c_double), ("adex_no_exp", C.c_int32),
+        ("tau_rise", C.c_double * MAX_PORTS),
     ]
 
 
@@ -152,9 +154,11 @@ def pop_params(model: str, ports: int, params: dict) -> PopParams:
         setattr(p, k, float(params.get(k, v)))
     ts = list(params.get("tau_syn", [1.0] * ports))
     er = list(params.get("E_rev", [0.0] * ports))
+    tr = list(params.get("tau_rise", ts))  # default: rise = decay, the alpha function
     for i in range(MAX_PORTS):
         p.tau_syn[i] = float(ts[i]) if i < len(ts) else 1.0
         p.E_rev[i] = float(er[i]) if i < len(er) else 0.0
+        p.tau_rise[i] = float(tr[i]) if i < len(tr) else 1.0
     p.adex_no_exp = int(params.get("adex_no_exp", 0))
     return p
 

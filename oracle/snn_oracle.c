@@ -170,7 +170,7 @@ struct orc_net {
   orc_syn* syn;
   uint64_t* off;            /* N*(dmax+1)+1 */
   /* state (double; FP32SO mode keeps float copies for LIF) */
-  double* V; double* Ie; double* w; double* g; double* I; double* h; int32_t* refr;
+  double* V; double* Ie; double* w; double* g; double* gr; double* I; double* h; int32_t* refr;
   float* Vf; float* If; float* Ief;
   /* integer input accumulator for the next step, N*P */
   int64_t* acc;
@@ -188,6 +188,9 @@ struct orc_net {
 };
 
 static void set_err(orc_net* o, const char* m) { snprintf(o->err, sizeof o->err, "%s", m); }
+static int is_adex(const orc_pop_params* pp) {
+  return pp->model == ORC_AEIF_COND_EXP || pp->model == ORC_AEIF_COND_BETA;
+}
 const char* orc_last_error(const orc_net* o) { return o ? o->err : "null net"; }
 
 orc_net* orc_create(double dt_ms, uint64_t seed, uint32_t max_delay_steps, int mode) {
@@ -201,7 +204,7 @@ void orc_destroy(orc_net* o) {
   if (!o) return;
   free(o->pops); free(o->pop_first); free(o->pop_of); free(o->proj); free(o->pois); free(o->pois_of);
   free(o->shift); free(o->syn); free(o->off);
-  free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->I); free(o->h); free(o->refr);
+  free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->gr); free(o->I); free(o->h); free(o->refr);
   free(o->Vf); free(o->If); free(o->Ief); free(o->acc);
   free(o->spk_step); free(o->spk_gid); free(o->spk_mult); free(o->spk_at);
   free(o);
@@ -210,7 +213,11 @@ void orc_destroy(orc_net* o) {
 int64_t orc_population(orc_net* o, uint32_t n, const orc_pop_params* p) {
   if (o->built) { set_err(o, "population after build"); return -1; }
   if (n == 0 || p->n_ports < 1 || p->n_ports > ORC_MAX_PORTS) { set_err(o, "bad population"); return -1; }
+  if (p->model < ORC_LIF_DELTA || p->model > ORC_AEIF_COND_BETA) { set_err(o, "bad model"); return -1; }
   if (p->model == ORC_LIF_DELTA && p->n_ports != 1) { set_err(o, "lif_delta has one port"); return -1; }
+  if (p->model == ORC_AEIF_COND_BETA)
+    for (uint32_t q = 0; q < p->n_ports; ++q)
+      if (!(p->tau_rise[q] > 0) || !(p->tau_syn[q] > 0)) { set_err(o, "beta time constants"); return -1; }
   o->pops = (orc_pop_params*)realloc(o->pops, (o->n_pops + 1) * sizeof(orc_pop_params));
   o->pop_first = (uint32_t*)realloc(o->pop_first, (o->n_pops + 1) * sizeof(uint32_t));
   o->pops[o->n_pops] = *p;
@@ -270,6 +277,7 @@ static void alloc_state(orc_net* o) {
   o->Ie = (double*)calloc(N, sizeof(double));
   o->w = (double*)calloc(N, sizeof(double));
   o->g = (double*)calloc(N * P, sizeof(double));
+  o->gr = (double*)calloc(N * P, sizeof(double));
   o->I = (double*)calloc(N * P, sizeof(double));
   o->h = (double*)malloc(N * sizeof(double));
   for (size_t i = 0; i < N; ++i) o->h[i] = o->dt;
@@ -281,15 +289,16 @@ static void alloc_state(orc_net* o) {
   for (size_t i = 0; i < N; ++i) o->V[i] = o->pops[o->pop_of[i]].E_L; /* rest */
   for (size_t i = 0; i < N; ++i) {
     const orc_pop_params* pp = &o->pops[o->pop_of[i]];
-    if (pp->model != ORC_AEIF_COND_EXP) o->Vf[i] = (float)(o->V[i] - pp->E_L);
+    if (!is_adex(pp)) o->Vf[i] = (float)(o->V[i] - pp->E_L);
   }
 }
 
-/* var: 0 V_m, 1 I_e, 2 w, 3 g[port], 4 I_syn[port], 5 refractory, 6 h */
+/* var: 0 V_m, 1 I_e, 2 w, 3 g[port], 4 I_syn[port], 5 refractory, 6 h,
+   7 r[port] (rising variable of a beta port) */
 int orc_set_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port, const double* v) {
   if (o->N == 0 || (uint64_t)first + n > o->N) { set_err(o, "range"); return -1; }
   alloc_state(o);
-  if ((var == 3 || var == 4) && port >= o->P) { set_err(o, "port"); return -1; }
+  if ((var == 3 || var == 4 || var == 7) && port >= o->P) { set_err(o, "port"); return -1; }
   for (uint32_t j = 0; j < n; ++j) {
     uint32_t i = first + j;
     const orc_pop_params* pp = &o->pops[o->pop_of[i]];
@@ -297,7 +306,7 @@ int orc_set_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port
       case 0:
         o->V[i] = v[j];
         /* LIF keeps y = V - E_L; the float copy is rounded once from double */
-        if (pp->model != ORC_AEIF_COND_EXP) o->Vf[i] = (float)(v[j] - pp->E_L);
+        if (!is_adex(pp)) o->Vf[i] = (float)(v[j] - pp->E_L);
         break;
       case 1: o->Ie[i] = v[j]; o->Ief[i] = (float)v[j]; break;
       case 2: o->w[i] = v[j]; break;
@@ -305,6 +314,7 @@ int orc_set_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port
       case 4: o->I[(size_t)i * o->P + port] = v[j]; o->If[(size_t)i * o->P + port] = (float)v[j]; break;
       case 5: o->refr[i] = (int32_t)v[j]; break;
       case 6: o->h[i] = v[j]; break;
+      case 7: o->gr[(size_t)i * o->P + port] = v[j]; break;
       default: set_err(o, "var"); return -1;
     }
   }
@@ -314,12 +324,12 @@ int orc_set_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port
 int orc_get_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port, double* v) {
   if (o->N == 0 || (uint64_t)first + n > o->N) { set_err(o, "range"); return -1; }
   alloc_state(o);
-  if ((var == 3 || var == 4) && port >= o->P) { set_err(o, "port"); return -1; }
+  if ((var == 3 || var == 4 || var == 7) && port >= o->P) { set_err(o, "port"); return -1; }
   int f32 = (o->mode == ORC_FP32SO);
   for (uint32_t j = 0; j < n; ++j) {
     uint32_t i = first + j;
     const orc_pop_params* pp = &o->pops[o->pop_of[i]];
-    int lif = pp->model != ORC_AEIF_COND_EXP;
+    int lif = !is_adex(pp);
     switch (var) {
       case 0: v[j] = (lif && f32) ? (double)o->Vf[i] + pp->E_L : o->V[i]; break;
       case 1: v[j] = o->Ie[i]; break;
@@ -328,6 +338,7 @@ int orc_get_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port
       case 4: v[j] = (lif && f32) ? (double)o->If[(size_t)i * o->P + port] : o->I[(size_t)i * o->P + port]; break;
       case 5: v[j] = (double)o->refr[i]; break;
       case 6: v[j] = o->h[i]; break;
+      case 7: v[j] = o->gr[(size_t)i * o->P + port]; break;
       default: set_err(o, "var"); return -1;
     }
   }
@@ -563,11 +574,27 @@ int orc_lif_exp_step32(const orc_pop_params* pp, double dt, float* y, float* I, 
 /*   C dV/dt = -g_L (V - E_L) + g_L Delta_T exp((V - V_T)/Delta_T)            */
 /*             - sum_p g_p (V - E_rev,p) - w + I_e                            */
 /*   tau_w dw/dt = a (V - E_L) - w                                            */
-/*   dg_p/dt = -g_p / tau_syn,p      (exponential conductance per port)       */
+/* Conductance of port p, either                                              */
+/*   exponential:  dg_p/dt = -g_p / tau_syn,p                                 */
+/*   beta (Sec. 2.1 example; alpha when tau_rise = tau_decay, Sec. 2.4):      */
+/*                 dg_p/dt = r_p - g_p / tau_decay,p,  dr_p/dt = -r_p/tau_rise */
+/*   an input of weight w at t0 adds g0 w to r_p, giving                       */
+/*   g(t) = g0 w (e^{-s/td} - e^{-s/tr}) / (1/tr - 1/td), s = t - t0           */
+/*   (g0 w s e^{-s/t} for tr = td = t), whose peak is w (see orc_beta_g0).     */
 /* The synaptic current is taken with the sign that makes an excitatory       */
 /* conductance depolarise.  The exponential uses min(V, V_peak).  At a reset  */
 /* (V >= V_peak after an accepted substep) V -> V_r and w -> w + b.           */
 /* ------------------------------------------------------------------------ */
+double orc_beta_g0(double tr, double td) {
+  /* alpha limit: g = g0 w s e^{-s/t} peaks at s = t with value g0 w t / e */
+  if (fabs(td - tr) <= 1e-12 * td) return exp(1.0) / td;
+  /* peak of e^{-s/td} - e^{-s/tr} at s* = ln(td/tr) / (1/tr - 1/td) */
+  double rate = 1.0 / tr - 1.0 / td;
+  double sp = log(td / tr) / rate;
+  double peak = (exp(-sp / td) - exp(-sp / tr)) / rate;
+  return 1.0 / peak;
+}
+
 void orc_adex_rhs(const orc_pop_params* pp, double I_e, const double* y, double* dy) {
   uint32_t P = pp->n_ports;
   double V = y[0], w = y[1];
@@ -577,7 +604,14 @@ void orc_adex_rhs(const orc_pop_params* pp, double I_e, const double* y, double*
   double ex = pp->adex_no_exp ? 0.0 : pp->g_L * pp->Delta_T * exp((Vc - pp->V_T) / pp->Delta_T);
   dy[0] = (-pp->g_L * (V - pp->E_L) + ex - isyn - w + I_e) / pp->C_m;
   dy[1] = (pp->a * (V - pp->E_L) - w) / pp->tau_w;
-  for (uint32_t p = 0; p < P; ++p) dy[2 + p] = -y[2 + p] / pp->tau_syn[p];
+  if (pp->model == ORC_AEIF_COND_BETA) {
+    for (uint32_t p = 0; p < P; ++p) {
+      dy[2 + p] = y[2 + P + p] - y[2 + p] / pp->tau_syn[p];
+      dy[2 + P + p] = -y[2 + P + p] / pp->tau_rise[p];
+    }
+  } else {
+    for (uint32_t p = 0; p < P; ++p) dy[2 + p] = -y[2 + p] / pp->tau_syn[p];
+  }
 }
 
 /* Cash-Karp embedded 5(4) Runge-Kutta pair (Cash & Karp 1990), the adaptive
@@ -614,13 +648,19 @@ void orc_cash_karp_tableau(double* c, double* a, double* b5, double* b4) {
 
 int orc_adex_step(const orc_pop_params* pp, double dt, double* y, double* hcar, double I_e, const double* x,
                   uint64_t* nacc, uint64_t* nrej) {
-  uint32_t P = pp->n_ports, NV = 2 + P;
+  int beta = pp->model == ORC_AEIF_COND_BETA;
+  uint32_t P = pp->n_ports, NV = beta ? 2 + 2 * P : 2 + P;
   double errcon = pow(5.0 / RK_SAFETY, 1.0 / RK_PGROW);
   double eps = pp->rk_eps > 0 ? pp->rk_eps : 1e-6;
   double hmin = pp->rk_hmin > 0 ? pp->rk_hmin : 1e-8;
-  /* conductance jump by the weight delivered at this step */
-  for (uint32_t p = 0; p < P; ++p) y[2 + p] += x[p];
-  double k[6][2 + ORC_MAX_PORTS], ytmp[2 + ORC_MAX_PORTS], y5[2 + ORC_MAX_PORTS], err[2 + ORC_MAX_PORTS];
+  /* jump by the weight delivered at this step: of the conductance itself
+     (exponential), or of its rising variable (beta) */
+  for (uint32_t p = 0; p < P; ++p) {
+    if (beta) y[2 + P + p] += orc_beta_g0(pp->tau_rise[p], pp->tau_syn[p]) * x[p];
+    else y[2 + p] += x[p];
+  }
+  double k[6][2 + 2 * ORC_MAX_PORTS], ytmp[2 + 2 * ORC_MAX_PORTS], y5[2 + 2 * ORC_MAX_PORTS],
+      err[2 + 2 * ORC_MAX_PORTS];
   double t = 0.0;
   double h = *hcar;
   if (!(h > 0) || h > dt) h = dt;
@@ -783,12 +823,16 @@ int orc_simulate(orc_net* o, uint64_t steps) {
           o->V[i] = y + pp->E_L;
         }
       } else {
-        double yv[2 + ORC_MAX_PORTS];
+        double yv[2 + 2 * ORC_MAX_PORTS];
+        uint32_t np = pp->n_ports;
         yv[0] = o->V[i]; yv[1] = o->w[i];
-        for (uint32_t p = 0; p < pp->n_ports; ++p) yv[2 + p] = o->g[(size_t)i * P + p];
+        for (uint32_t p = 0; p < np; ++p) yv[2 + p] = o->g[(size_t)i * P + p];
+        for (uint32_t p = 0; p < np; ++p) yv[2 + np + p] = o->gr[(size_t)i * P + p];
         m = orc_adex_step(pp, o->dt, yv, &o->h[i], o->Ie[i], xd, &o->rk_acc, &o->rk_rej);
         o->V[i] = yv[0]; o->w[i] = yv[1];
-        for (uint32_t p = 0; p < pp->n_ports; ++p) o->g[(size_t)i * P + p] = yv[2 + p];
+        for (uint32_t p = 0; p < np; ++p) o->g[(size_t)i * P + p] = yv[2 + p];
+        if (pp->model == ORC_AEIF_COND_BETA)
+          for (uint32_t p = 0; p < np; ++p) o->gr[(size_t)i * P + p] = yv[2 + np + p];
       }
       if (m > 0) record_spike(o, n, i, (uint32_t)m);
     }

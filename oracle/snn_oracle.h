@@ -28,22 +28,24 @@ extern "C" {
 #endif
 
 enum { ORC_FP64 = 0, ORC_FP32SO = 1 };
-enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2 };
+enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2, ORC_AEIF_COND_BETA = 3 };
 enum { ORC_DELAY_CONST = 0, ORC_DELAY_UNIFORM = 1, ORC_DELAY_NORMAL_CLIPPED = 2 };
 enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2 };
 enum { ORC_MAX_PORTS = 4, ORC_POISSON_KMAX = 128 };
 
 /* Neuron-model parameters of one population (double, NEST units). */
 typedef struct {
-  int32_t model;        /* ORC_LIF_DELTA, ORC_LIF_EXP, ORC_AEIF_COND_EXP */
+  int32_t model;        /* ORC_LIF_DELTA, ORC_LIF_EXP, ORC_AEIF_COND_EXP,
+                           ORC_AEIF_COND_BETA                            */
   uint32_t n_ports;     /* receptor ports (1..ORC_MAX_PORTS)              */
   double tau_m, C_m, E_L, V_th, V_reset, t_ref;               /* LIF      */
   double g_L, Delta_T, V_T, tau_w, a, b, V_peak, V_r;         /* AdEx     */
-  double tau_syn[ORC_MAX_PORTS];                              /* ms       */
+  double tau_syn[ORC_MAX_PORTS];   /* ms; the decay time for beta ports     */
   double E_rev[ORC_MAX_PORTS];                                /* mV (AdEx)*/
   double rk_eps;        /* relative tolerance of the adaptive RK45 (AdEx) */
   double rk_hmin;       /* smallest substep; accepted regardless (ms)     */
   int32_t adex_no_exp;  /* test switch: drop the exponential term         */
+  double tau_rise[ORC_MAX_PORTS];  /* ms; rise time of beta ports          */
 } orc_pop_params;
 
 typedef struct orc_net orc_net;
@@ -111,15 +113,21 @@ int orc_lif_exp_step64(const orc_pop_params*, double dt, double* y, double* I, i
 int orc_lif_exp_step32(const orc_pop_params*, double dt, float* y, float* I, int32_t* refr, float I_e, const float* x);
 /* LIF propagators in double: out = {P22, P20, P11[0..P-1], P21[0..P-1]} */
 void orc_lif_propagators(const orc_pop_params*, double dt, double* out);
-/* AdEx: y = {V, w, g_0..g_{P-1}}, h carried step size.  Adds x to g at step start,
-   integrates one dt with Cash-Karp RK45.  Returns the number of resets (multiplicity).
-   acc/rej count accepted/rejected substeps. */
+/* AdEx: y = {V, w, g_0..g_{P-1}} (exponential ports) or
+   {V, w, g_0..g_{P-1}, r_0..r_{P-1}} (beta ports, r the rising variable);
+   h carried step size.  At step start the delivered weight x[p] is added to
+   g_p (exponential) or g0_p x[p] to r_p (beta, g0_p from orc_beta_g0), then
+   one dt is integrated with Cash-Karp RK45.  Returns the number of resets
+   (multiplicity).  acc/rej count accepted/rejected substeps. */
 int orc_adex_step(const orc_pop_params*, double dt, double* y, double* h, double I_e,
                   const double* x, uint64_t* acc, uint64_t* rej);
 /* Cash-Karp tableau as used: c[6], a[6*6] (row-major, strictly lower), b5[6], b4[6] */
 void orc_cash_karp_tableau(double* c, double* a, double* b5, double* b4);
 /* AdEx right-hand side (for pins): dy = f(y) */
 void orc_adex_rhs(const orc_pop_params*, double I_e, const double* y, double* dy);
+/* Beta-port normalisation: the value added to r per unit weight, so that a
+   lone input of weight w gives a conductance peaking at exactly w. */
+double orc_beta_g0(double tau_rise, double tau_decay);
 
 const char* orc_last_error(const orc_net*);
 
