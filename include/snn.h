@@ -96,6 +96,12 @@ typedef struct snn_config {
 #define SNN_LIF_PSC_DELTA 0  /* LIF, delta PSCs: weights in mV, one port      */
 #define SNN_LIF_PSC_EXP 1    /* LIF, exponential PSCs: weights in pA          */
 #define SNN_AEIF_COND_EXP 2  /* AdEx, exponential conductances: weights in nS */
+/* AdEx with beta-function conductances (the receptor model of the Sec. 2.1
+   example; tau_rise = tau_decay gives the alpha function of Sec. 2.4): per
+   port dg/dt = r - g/tau_decay, dr/dt = -r/tau_rise, and an input of weight
+   w (nS) adds g0 w to r, g0 chosen so that a lone input's conductance peaks
+   at exactly w.  A network may mix it with SNN_AEIF_COND_EXP populations. */
+#define SNN_AEIF_COND_BETA 3
 
 /* model parameters (snn_set_param); all apply to whole populations */
 #define SNN_P_TAU_M 0    /* LIF membrane time constant (ms)                   */
@@ -115,8 +121,9 @@ typedef struct snn_config {
 #define SNN_P_RK_EPS 14  /* AdEx RK45 relative tolerance                      */
 #define SNN_P_RK_HMIN 15 /* AdEx smallest RK45 substep (ms)                   */
 /* port parameters (snn_set_port_param) */
-#define SNN_PP_TAU_SYN 0 /* synaptic time constant (ms)                       */
+#define SNN_PP_TAU_SYN 0 /* synaptic (for beta ports: decay) time constant (ms) */
 #define SNN_PP_E_REV 1   /* AdEx reversal potential (mV)                      */
+#define SNN_PP_TAU_RISE 2 /* beta ports: rise time constant (ms), default 1   */
 
 /* state variables (snn_set_state / snn_get_state), per neuron */
 #define SNN_V_M 0        /* membrane potential (mV)                           */
@@ -126,6 +133,7 @@ typedef struct snn_config {
 #define SNN_V_I_SYN 4    /* LIF-exp synaptic current of `port` (pA)           */
 #define SNN_V_REFR 5     /* remaining refractory steps                        */
 #define SNN_V_H 6        /* AdEx carried RK45 step size (ms)                  */
+#define SNN_V_G_RISE 7   /* beta port's rising variable r of `port` (nS/ms)   */
 
 /* delay distributions (in ms; converted to steps of dt, rounded half up,
    clipped to [1, Dmax]) */

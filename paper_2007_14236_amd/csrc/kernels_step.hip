@@ -140,16 +140,22 @@ __device__ __forceinline__ bool lif_exp_step(const PopDev& pp, float& y, float* 
 // AdEx parameters of one neuron as the integrator uses them, held in
 // registers for the whole step (the population record may sit behind a
 // generic pointer that the compiler would otherwise reload every substep).
-template <int P>
+template <int P, bool kBeta>
 struct AdexPar {
   float V_peak, g_L, gLDT, V_T, k_exp, E_L, inv_C, a, inv_tau_w, b, V_r;
   float dt, hmin, inv_eps;
   float E_rev[P], inv_tau_syn[P];
+  float inv_tau_rise[kBeta ? P : 1];
 };
 
-template <int P>
-__device__ __forceinline__ AdexPar<P> adex_par(const PopDev& pp) {
-  AdexPar<P> q;
+// State variables of the integrator: V, w, the port conductances, and with
+// beta ports their rising variables.
+template <int P, bool kBeta>
+constexpr int kAdexVars = kBeta ? 2 + 2 * P : 2 + P;
+
+template <int P, bool kBeta>
+__device__ __forceinline__ AdexPar<P, kBeta> adex_par(const PopDev& pp) {
+  AdexPar<P, kBeta> q;
   q.V_peak = pp.V_peak; q.g_L = pp.g_L; q.V_T = pp.V_T;
   q.gLDT = pp.g_L * pp.Delta_T;
   q.k_exp = pp.inv_Delta_T * 1.4426950408889634f;  // exp(x / Delta_T) = 2^(x k_exp)
@@ -161,15 +167,23 @@ __device__ __forceinline__ AdexPar<P> adex_par(const PopDev& pp) {
   q.inv_eps = 1.f / pp.rk_eps;
 #pragma unroll
   for (int p = 0; p < P; ++p) { q.E_rev[p] = pp.E_rev[p]; q.inv_tau_syn[p] = pp.inv_tau_syn[p]; }
+  if constexpr (kBeta) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) q.inv_tau_rise[p] = pp.inv_tau_rise[p];
+  }
   return q;
 }
 
-// AdEx with exponential conductances (Sec. 2.4, Table 2), right-hand side in
-// fp32.  y = (V, w, g_0..g_{P-1}); the synaptic current is sum g_p (V - E_p)
+// AdEx with conductance synapses (Sec. 2.4, Table 2), right-hand side in
+// fp32.  y = (V, w, g_0..g_{P-1}) with exponential conductances, dg/dt =
+// -g / tau; with beta conductances (Sec. 2.1 example; alpha when the two
+// times are equal) y continues with the rising variables r_0..r_{P-1}:
+// dg/dt = r - g / tau_decay, dr/dt = -r / tau_rise (an exponential port in
+// such a network keeps r = 0).  The synaptic current is sum g_p (V - E_p)
 // entering with the sign that lets an excitatory conductance depolarise; the
 // exponential uses min(V, V_peak).
-template <int P>
-__device__ __forceinline__ void adex_rhs(const AdexPar<P>& pp, float Ie, const float* y, float* dy) {
+template <int P, bool kBeta>
+__device__ __forceinline__ void adex_rhs(const AdexPar<P, kBeta>& pp, float Ie, const float* y, float* dy) {
   const float V = y[0], w = y[1];
   const float Vc = fminf(V, pp.V_peak);
   float isyn = 0.f;
@@ -178,8 +192,16 @@ __device__ __forceinline__ void adex_rhs(const AdexPar<P>& pp, float Ie, const f
   const float ex = pp.gLDT * __builtin_amdgcn_exp2f((Vc - pp.V_T) * pp.k_exp);
   dy[0] = (__builtin_fmaf(-pp.g_L, V - pp.E_L, ex) - isyn - w + Ie) * pp.inv_C;
   dy[1] = __builtin_fmaf(pp.a, V - pp.E_L, -w) * pp.inv_tau_w;
+  if constexpr (kBeta) {
 #pragma unroll
-  for (int p = 0; p < P; ++p) dy[2 + p] = -y[2 + p] * pp.inv_tau_syn[p];
+    for (int p = 0; p < P; ++p) {
+      dy[2 + p] = __builtin_fmaf(-y[2 + p], pp.inv_tau_syn[p], y[2 + P + p]);
+      dy[2 + P + p] = -y[2 + P + p] * pp.inv_tau_rise[p];
+    }
+  } else {
+#pragma unroll
+    for (int p = 0; p < P; ++p) dy[2 + p] = -y[2 + p] * pp.inv_tau_syn[p];
+  }
 }
 
 // One attempted substep of the Cash-Karp embedded 5(4) pair with the
@@ -192,11 +214,11 @@ __device__ __forceinline__ void adex_rhs(const AdexPar<P>& pp, float Ie, const f
 // true when the step is complete (t = dt, or the attempt cap reached).  The
 // stage sums are fma chains; the error ratio uses the hardware reciprocal (it
 // only steers the step size).
-template <int P>
-__device__ __forceinline__ bool adex_substep(const AdexPar<P>& pp, float* y, float& h, float& t, uint32_t& it,
+template <int P, bool kBeta>
+__device__ __forceinline__ bool adex_substep(const AdexPar<P, kBeta>& pp, float* y, float& h, float& t, uint32_t& it,
                                              uint32_t& mult, float Ie, uint32_t& nacc, uint32_t& nrej,
                                              bool& capped) {
-  constexpr int NV = 2 + P;
+  constexpr int NV = kAdexVars<P, kBeta>;
   const float dt = pp.dt;
   const float c21 = 1.f / 5.f;
   const float c31 = 3.f / 40.f, c32 = 9.f / 40.f;
@@ -215,22 +237,22 @@ __device__ __forceinline__ bool adex_substep(const AdexPar<P>& pp, float* y, flo
   bool last = false;
   if (h >= dt - t) { h = dt - t; last = true; }
   float k1[NV], k2[NV], k3[NV], k4[NV], k5[NV], k6[NV], yt[NV];
-  adex_rhs<P>(pp, Ie, y, k1);
+  adex_rhs<P, kBeta>(pp, Ie, y, k1);
 #pragma unroll
   for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(h, c21 * k1[i], y[i]);
-  adex_rhs<P>(pp, Ie, yt, k2);
+  adex_rhs<P, kBeta>(pp, Ie, yt, k2);
 #pragma unroll
   for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(h, __builtin_fmaf(c32, k2[i], c31 * k1[i]), y[i]);
-  adex_rhs<P>(pp, Ie, yt, k3);
+  adex_rhs<P, kBeta>(pp, Ie, yt, k3);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
     yt[i] = __builtin_fmaf(h, __builtin_fmaf(c43, k3[i], __builtin_fmaf(c42, k2[i], c41 * k1[i])), y[i]);
-  adex_rhs<P>(pp, Ie, yt, k4);
+  adex_rhs<P, kBeta>(pp, Ie, yt, k4);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
     yt[i] = __builtin_fmaf(
         h, __builtin_fmaf(c54, k4[i], __builtin_fmaf(c53, k3[i], __builtin_fmaf(c52, k2[i], c51 * k1[i]))), y[i]);
-  adex_rhs<P>(pp, Ie, yt, k5);
+  adex_rhs<P, kBeta>(pp, Ie, yt, k5);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
     yt[i] = __builtin_fmaf(
@@ -238,7 +260,7 @@ __device__ __forceinline__ bool adex_substep(const AdexPar<P>& pp, float* y, flo
         __builtin_fmaf(c65, k5[i],
                        __builtin_fmaf(c64, k4[i], __builtin_fmaf(c63, k3[i], __builtin_fmaf(c62, k2[i], c61 * k1[i])))),
         y[i]);
-  adex_rhs<P>(pp, Ie, yt, k6);
+  adex_rhs<P, kBeta>(pp, Ie, yt, k6);
   float errmax = 0.f;
   float y5[NV];
 #pragma unroll
@@ -271,15 +293,15 @@ __device__ __forceinline__ bool adex_substep(const AdexPar<P>& pp, float* y, flo
 
 // One dt of the AdEx model: substeps until the step end, h carried to the
 // next step (at most dt).  Returns the number of resets.
-template <int P>
+template <int P, bool kBeta>
 __device__ uint32_t adex_step(const PopDev& pop, float* y, float& h, float Ie, uint32_t& nacc, uint32_t& nrej,
                               bool& capped) {
-  const AdexPar<P> pp = adex_par<P>(pop);
+  const AdexPar<P, kBeta> pp = adex_par<P, kBeta>(pop);
   const float dt = pp.dt;
   if (!(h > 0.f) || h > dt) h = dt;
   float t = 0.f;
   uint32_t it = 0, mult = 0;
-  while (!adex_substep<P>(pp, y, h, t, it, mult, Ie, nacc, nrej, capped)) {
+  while (!adex_substep<P, kBeta>(pp, y, h, t, it, mult, Ie, nacc, nrej, capped)) {
   }
   if (h > dt) h = dt;
   return mult;
@@ -595,12 +617,43 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
   return ev;
 }
 
+// Synaptic state of AdEx neuron i into y[2..] with the step's input x (nS)
+// applied: added to g (exponential port) or, scaled by g0, to r (beta port).
+template <int P, bool kBeta>
+__device__ __forceinline__ void adex_load_syn(const NetDev& nd, const PopDev& pp, uint32_t i, const float* x,
+                                              float* y) {
+  if constexpr (!kBeta) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) y[2 + p] = nd.g[(size_t)i * nd.P + p] + x[p];
+  } else {
+    const bool beta = pp.model == kAdexBeta;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const float g = nd.g[(size_t)i * nd.P + p], r = nd.gr[(size_t)i * nd.P + p];
+      y[2 + p] = beta ? g : g + x[p];
+      y[2 + P + p] = beta ? __builtin_fmaf(pp.g0[p], x[p], r) : r;
+    }
+  }
+}
+
+template <int P, bool kBeta>
+__device__ __forceinline__ void adex_store_syn(const NetDev& nd, uint32_t i, const float* y) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) nd.g[(size_t)i * nd.P + p] = y[2 + p];
+  if constexpr (kBeta) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) nd.gr[(size_t)i * nd.P + p] = y[2 + P + p];
+  }
+}
+
 // ------------------------------------------------------------------ update
 // One neuron i at step n: Poisson count of the step added to its integer
 // input a[] (network input of step n, fixed point), conversion to fp32,
 // LIF exact integration (Sec. 2.1, 2.3) or AdEx RK45 (Sec. 2.1, 2.4).
 // Returns the number of spikes (resets) in the step, clamped to kMaxMult.
-template <bool kLif, bool kAdexOn, int P>
+// kAd: 0 no AdEx neurons, 1 AdEx with exponential ports only, 2 beta ports
+// present (the integrator then carries the rising variables of every port).
+template <bool kLif, int kAd, int P>
 __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* pops, const uint64_t* pthr,
                                                 uint64_t n, uint32_t i, int64_t* a, uint32_t& nacc, uint32_t& nrej,
                                                 bool& capped, bool& mover) {
@@ -616,7 +669,7 @@ __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* 
   for (int p = 0; p < kMaxPorts; ++p) x[p] = __fmul_rn((float)a[p], pp.scale[p]);
   const float Ie = nd.Ie[i];
   uint32_t m = 0;
-  if (kLif && pp.model != kAdex) {
+  if (kLif && pp.model < kAdex) {
     float y = nd.V[i];
     int32_t r = nd.refr[i];
     bool s;
@@ -635,19 +688,18 @@ __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* 
     nd.refr[i] = r;
     m = s ? 1u : 0u;
   }
-  if constexpr (kAdexOn) {
-    if (pp.model == kAdex) {
-      float y[2 + P];
+  if constexpr (kAd != 0) {
+    constexpr bool kBeta = kAd == 2;
+    if (pp.model >= kAdex) {
+      float y[kAdexVars<P, kBeta>];
       y[0] = nd.V[i];
       y[1] = nd.w[i];
-#pragma unroll
-      for (int p = 0; p < P; ++p) y[2 + p] = nd.g[(size_t)i * nd.P + p] + x[p];
+      adex_load_syn<P, kBeta>(nd, pp, i, x, y);
       float h = nd.h[i];
-      m = adex_step<P>(pp, y, h, Ie, nacc, nrej, capped);
+      m = adex_step<P, kBeta>(pp, y, h, Ie, nacc, nrej, capped);
       nd.V[i] = y[0];
       nd.w[i] = y[1];
-#pragma unroll
-      for (int p = 0; p < P; ++p) nd.g[(size_t)i * nd.P + p] = y[2 + p];
+      adex_store_syn<P, kBeta>(nd, i, y);
       nd.h[i] = h;
     }
   }
@@ -712,7 +764,7 @@ __device__ __forceinline__ void emit_spike(const NetDev& nd, uint64_t n, uint64_
 // counter (wave ballot + lane prefix), their raster entries and records are
 // written here, and their delay-1 and delay-2 groups are delivered at once by
 // the block's flat scan into the buffers of steps n + 1 and n + 2.
-template <bool kLif, bool kAdexOn, int P>
+template <bool kLif, int kAd, int P>
 __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds& sl) {
   const PopDev* pops;
   const uint64_t* pthr;
@@ -735,7 +787,7 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
         if (a[p] != 0) acc[p] = 0;
       }
     }
-    const uint32_t m = neuron_step<kLif, kAdexOn, P>(nd, pops, pthr, n, i, a, nacc, nrej, capped, mover);
+    const uint32_t m = neuron_step<kLif, kAd, P>(nd, pops, pthr, n, i, a, nacc, nrej, capped, mover);
     spk = m > 0;
     entry = i | (m << kMultShift);
   }
@@ -784,7 +836,7 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
     }
   }
   uint64_t sa = 0, sr = 0;
-  if (kAdexOn) {
+  if (kAd != 0) {
     sa = block_sum(nacc, sl.red);
     sr = block_sum(nrej, sl.red);
   } else {
@@ -804,17 +856,17 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
 
 // AdEx neuron i at step n as one lane's work item: state and folded input
 // loaded, then advanced one RK45 substep per call of adex_substep.
-template <int P>
+template <int P, bool kBeta>
 struct AdexItem {
-  AdexPar<P> q;
-  float y[2 + P];
+  AdexPar<P, kBeta> q;
+  float y[kAdexVars<P, kBeta>];
   float h, t, Ie;
   uint32_t it, mult;
 };
 
-template <int P>
+template <int P, bool kBeta>
 __device__ __forceinline__ void adex_load(const NetDev& nd, const PopDev* pops, const uint64_t* pthr, uint64_t n,
-                                          uint32_t i, int64_t* a, AdexItem<P>& w) {
+                                          uint32_t i, int64_t* a, AdexItem<P, kBeta>& w) {
   const PopDev& pp = pops[find_pop(pops, nd.npop, i)];
   if (pp.pois >= 0) {
     const uint32_t k = poisson_draw(pthr + (size_t)pp.pois * kPoisKmax, pp.seed, i - pp.gid_base, n);
@@ -822,11 +874,13 @@ __device__ __forceinline__ void adex_load(const NetDev& nd, const PopDev* pops, 
     for (int p = 0; p < kMaxPorts; ++p)
       if (p == pp.pois_port) a[p] += (int64_t)k * pp.pois_wq;
   }
-  w.q = adex_par<P>(pp);
+  w.q = adex_par<P, kBeta>(pp);
   w.y[0] = nd.V[i];
   w.y[1] = nd.w[i];
+  float x[P];
 #pragma unroll
-  for (int p = 0; p < P; ++p) w.y[2 + p] = nd.g[(size_t)i * nd.P + p] + __fmul_rn((float)a[p], pp.scale[p]);
+  for (int p = 0; p < P; ++p) x[p] = __fmul_rn((float)a[p], pp.scale[p]);
+  adex_load_syn<P, kBeta>(nd, pp, i, x, w.y);
   w.h = nd.h[i];
   if (!(w.h > 0.f) || w.h > pp.dt) w.h = pp.dt;
   w.Ie = nd.Ie[i];
@@ -835,12 +889,11 @@ __device__ __forceinline__ void adex_load(const NetDev& nd, const PopDev* pops, 
   w.mult = 0;
 }
 
-template <int P>
-__device__ __forceinline__ uint32_t adex_store(const NetDev& nd, uint32_t i, AdexItem<P>& w, bool& mover) {
+template <int P, bool kBeta>
+__device__ __forceinline__ uint32_t adex_store(const NetDev& nd, uint32_t i, AdexItem<P, kBeta>& w, bool& mover) {
   nd.V[i] = w.y[0];
   nd.w[i] = w.y[1];
-#pragma unroll
-  for (int p = 0; p < P; ++p) nd.g[(size_t)i * nd.P + p] = w.y[2 + p];
+  adex_store_syn<P, kBeta>(nd, i, w.y);
   nd.h[i] = (w.h > w.q.dt) ? w.q.dt : w.h;
   uint32_t m = w.mult;
   if (m > kMaxMult) { mover = true; m = kMaxMult; }
@@ -857,7 +910,7 @@ __device__ __forceinline__ uint32_t adex_store(const NetDev& nd, uint32_t i, Ade
 // a lane whose neuron has reached the step end takes the next one, so waves
 // stay full while neurons near a spike need many RK45 substeps and the
 // others one.
-template <bool kLif, bool kAdexOn, int P>
+template <bool kLif, int kAd, int P>
 __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl) {
   const uint32_t PP = nd.P, tsh = nd.tile_shift, buf = inbuf(n);
   const uint32_t first = t << tsh;
@@ -908,15 +961,15 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
   }
   uint32_t nacc = 0, nrej = 0;
   bool capped = false, mover = false;
-  if (kAdexOn && !kLif) {
+  if (kAd != 0 && !kLif) {
     // AdEx only: work queue over the tile's neurons; each lane holds its
     // current neuron and has the next one's state already loaded, so the
     // loads of a refill overlap the substeps of the current neuron
-    auto fetch = [&](uint32_t l, AdexItem<P>& it) {
+    auto fetch = [&](uint32_t l, AdexItem<P, kAd == 2>& it) {
       int64_t a[kMaxPorts];
 #pragma unroll
       for (int p = 0; p < kMaxPorts; ++p) a[p] = (p < (int)PP) ? sl.u.acc[l * PP + p] : 0;
-      adex_load<P>(nd, pops, pthr, n, first + l, a, it);
+      adex_load<P, kAd == 2>(nd, pops, pthr, n, first + l, a, it);
     };
     for (uint32_t l = threadIdx.x; l < nt; l += kB) {
       const uint32_t i = first + l;
@@ -941,15 +994,15 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
       }
     };
     uint32_t loc = claim(), nloc = nt;
-    AdexItem<P> w, nx;
+    AdexItem<P, kAd == 2> w, nx;
     if (loc < nt) {
       fetch(loc, w);
       nloc = claim();
       if (nloc < nt) fetch(nloc, nx);
     }
     while (loc < nt) {
-      if (adex_substep<P>(w.q, w.y, w.h, w.t, w.it, w.mult, w.Ie, nacc, nrej, capped)) {
-        sl.c.mk[loc] = (uint8_t)adex_store<P>(nd, first + loc, w, mover);
+      if (adex_substep<P, kAd == 2>(w.q, w.y, w.h, w.t, w.it, w.mult, w.Ie, nacc, nrej, capped)) {
+        sl.c.mk[loc] = (uint8_t)adex_store<P, kAd == 2>(nd, first + loc, w, mover);
         loc = nloc;
         if (loc < nt) {
           w = nx;
@@ -964,7 +1017,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
 #pragma unroll
       for (int p = 0; p < kMaxPorts; ++p) a[p] = (p < (int)PP) ? sl.u.acc[loc * PP + p] : 0;
       sl.c.mk[loc] =
-          (uint8_t)neuron_step<kLif, kAdexOn, P>(nd, pops, pthr, n, first + loc, a, nacc, nrej, capped, mover);
+          (uint8_t)neuron_step<kLif, kAd, P>(nd, pops, pthr, n, first + loc, a, nacc, nrej, capped, mover);
     }
   }
   __syncthreads();
@@ -1045,7 +1098,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     }
   }
   uint64_t sa = 0, sr = 0;
-  if (kAdexOn) {
+  if (kAd != 0) {
     sa = block_sum(nacc, sl.red);
     sr = block_sum(nrej, sl.red);
   }
@@ -1119,13 +1172,13 @@ __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t
 // remaining blocks deliver the earlier steps' spikes whose delay (>= 3)
 // expires now.  The update reads the input buffer of step n; deliveries go to
 // the buffers of the steps they arrive at.
-template <bool kLif, bool kAdexOn, int P>
+template <bool kLif, int kAd, int P>
 __global__ void __launch_bounds__(kB) k_step(NetDev nd, uint32_t rel) {
   __shared__ StepLds lds;
   const uint64_t n = nd.ctrl->step_base + rel;
   if (blockIdx.x == 0 && threadIdx.x == 0) step_books(nd, n);
   if (blockIdx.x < nd.nblk_upd) {
-    update_block<kLif, kAdexOn, P>(nd, n, blockIdx.x, lds.upd);
+    update_block<kLif, kAd, P>(nd, n, blockIdx.x, lds.upd);
   } else {
     deliver_block(nd, n, blockIdx.x - nd.nblk_upd, gridDim.x - nd.nblk_upd, lds.dlv);
   }
@@ -1135,13 +1188,13 @@ __global__ void __launch_bounds__(kB) k_step(NetDev nd, uint32_t rel) {
 // blocks (input from their bins, update, emission, delay-1 and delay-2
 // binning), the remaining blocks bin the earlier steps' spikes whose delay
 // expires now.
-template <bool kLif, bool kAdexOn, int P>
+template <bool kLif, int kAd, int P>
 __global__ void __launch_bounds__(kB) k_step_binned(NetDev nd, uint32_t rel) {
   __shared__ BinStepLds lds;
   const uint64_t n = nd.ctrl->step_base + rel;
   if (blockIdx.x == 0 && threadIdx.x == 0) step_books(nd, n);
   if (blockIdx.x < nd.n_tiles) {
-    tile_block<kLif, kAdexOn, P>(nd, n, blockIdx.x, lds.tile);
+    tile_block<kLif, kAd, P>(nd, n, blockIdx.x, lds.tile);
   } else {
     deliver_block(nd, n, blockIdx.x - nd.n_tiles, gridDim.x - nd.n_tiles, lds.dlv);
   }
@@ -1190,33 +1243,40 @@ static void launch(K kernel, dim3 grid, dim3 blk, hipStream_t s, hipEvent_t star
   else hipLaunchKernelGGL(kernel, grid, blk, 0, s, args...);
 }
 
-template <template <bool, bool, int> class Sel>
-static void launch_variant(const NetDev& nd, dim3 grid, hipStream_t s, hipEvent_t start, hipEvent_t stop,
-                           uint32_t rel) {
-  // which models are present is encoded in nd.pad0: bit 0 LIF, bit 1 AdEx
-  const bool lif = nd.pad0 & 1u, adex = nd.pad0 & 2u;
+template <template <bool, int, int> class Sel, bool kLif, int kAd>
+static void launch_ports(const NetDev& nd, dim3 grid, hipStream_t s, hipEvent_t start, hipEvent_t stop,
+                         uint32_t rel) {
   const dim3 blk(kB);
-  if (!adex) {
-    launch(Sel<true, false, 1>::fn(), grid, blk, s, start, stop, nd, rel);
-  } else {
-    switch (nd.P) {
-      case 1: if (lif) launch(Sel<true, true, 1>::fn(), grid, blk, s, start, stop, nd, rel);
-              else launch(Sel<false, true, 1>::fn(), grid, blk, s, start, stop, nd, rel); break;
-      case 2: if (lif) launch(Sel<true, true, 2>::fn(), grid, blk, s, start, stop, nd, rel);
-              else launch(Sel<false, true, 2>::fn(), grid, blk, s, start, stop, nd, rel); break;
-      case 3: if (lif) launch(Sel<true, true, 3>::fn(), grid, blk, s, start, stop, nd, rel);
-              else launch(Sel<false, true, 3>::fn(), grid, blk, s, start, stop, nd, rel); break;
-      default: if (lif) launch(Sel<true, true, 4>::fn(), grid, blk, s, start, stop, nd, rel);
-               else launch(Sel<false, true, 4>::fn(), grid, blk, s, start, stop, nd, rel); break;
-    }
+  switch (nd.P) {
+    case 1: launch(Sel<kLif, kAd, 1>::fn(), grid, blk, s, start, stop, nd, rel); break;
+    case 2: launch(Sel<kLif, kAd, 2>::fn(), grid, blk, s, start, stop, nd, rel); break;
+    case 3: launch(Sel<kLif, kAd, 3>::fn(), grid, blk, s, start, stop, nd, rel); break;
+    default: launch(Sel<kLif, kAd, 4>::fn(), grid, blk, s, start, stop, nd, rel); break;
   }
 }
 
-template <bool A, bool B, int C>
+template <template <bool, int, int> class Sel>
+static void launch_variant(const NetDev& nd, dim3 grid, hipStream_t s, hipEvent_t start, hipEvent_t stop,
+                           uint32_t rel) {
+  // which models are present is encoded in nd.pad0: bit 0 LIF, bit 1 AdEx,
+  // bit 2 AdEx with beta ports
+  const bool lif = nd.pad0 & 1u, adex = nd.pad0 & 2u, beta = nd.pad0 & 4u;
+  if (!adex) {
+    launch(Sel<true, 0, 1>::fn(), grid, dim3(kB), s, start, stop, nd, rel);
+  } else if (!beta) {
+    if (lif) launch_ports<Sel, true, 1>(nd, grid, s, start, stop, rel);
+    else launch_ports<Sel, false, 1>(nd, grid, s, start, stop, rel);
+  } else {
+    if (lif) launch_ports<Sel, true, 2>(nd, grid, s, start, stop, rel);
+    else launch_ports<Sel, false, 2>(nd, grid, s, start, stop, rel);
+  }
+}
+
+template <bool A, int B, int C>
 struct SelDirect {
   static auto fn() { return k_step<A, B, C>; }
 };
-template <bool A, bool B, int C>
+template <bool A, int B, int C>
 struct SelBinned {
   static auto fn() { return k_step_binned<A, B, C>; }
 };

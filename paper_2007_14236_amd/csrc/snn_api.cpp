@@ -42,6 +42,8 @@ struct HostPop {
   double rk_eps = 1e-6, rk_hmin = 1e-8;
   double tau_syn[kMaxPorts] = {2.0, 2.0, 2.0, 2.0};
   double E_rev[kMaxPorts] = {0.0, -85.0, 0.0, 0.0};
+  double tau_rise[kMaxPorts] = {1.0, 1.0, 1.0, 1.0};
+  bool adex() const { return model == SNN_AEIF_COND_EXP || model == SNN_AEIF_COND_BETA; }
 };
 
 struct HostProj {
@@ -144,7 +146,7 @@ struct snn_net {
   uint32_t N = 0;
   // host state before build (per port arrays are [N][kMaxPorts])
   std::vector<double> V, Ie, w, h;
-  std::vector<double> g, Isyn;
+  std::vector<double> g, gr, Isyn;
   std::vector<int32_t> refr;
 
   // after build
@@ -154,7 +156,7 @@ struct snn_net {
   std::vector<int64_t> cls_wq;     // classes sorted by (port, w_q)
   std::vector<uint32_t> cls_port;
   uint32_t cls_bits = 6;
-  bool has_lif = false, has_adex = false;
+  bool has_lif = false, has_adex = false, has_beta = false;
   NetDev nd{};
   std::vector<DevAlloc> allocs;
   size_t dev_bytes = 0;
@@ -292,6 +294,17 @@ snn_status leave(snn_net* net) {
   return SNN_OK;
 }
 
+// Beta-port input scale: a lone input of weight w adds g0 w to r; then
+// g(s) = g0 w (e^{-s/td} - e^{-s/tr}) / (1/tr - 1/td), whose maximum, at
+// s* = ln(td/tr) / (1/tr - 1/td), must equal w.  Equal time constants give
+// the alpha function g0 w s e^{-s/t}, maximal at s = t: g0 = e / t.
+double beta_g0(double tr, double td) {
+  if (std::fabs(td - tr) <= 1e-12 * td) return std::exp(1.0) / td;
+  const double k = 1.0 / tr - 1.0 / td;
+  const double s_star = std::log(td / tr) / k;
+  return k / (std::exp(-s_star / td) - std::exp(-s_star / tr));
+}
+
 void lif_propagators(const HostPop& p, double dt, PopDev& d) {
   const double P22 = exp(-dt / p.tau_m);
   const double P20 = p.tau_m / p.C_m * (1.0 - P22);
@@ -324,13 +337,13 @@ uint64_t next_pow2(uint64_t x) {
 // device value of state variable `var` for neuron i (and the inverse)
 float to_device_state(const snn_net* net, int var, uint32_t i, double v) {
   const HostPop& pp = net->pops[pop_of(net, i)];
-  if (var == SNN_V_M && pp.model != SNN_AEIF_COND_EXP) return (float)(v - pp.E_L);
+  if (var == SNN_V_M && !pp.adex()) return (float)(v - pp.E_L);
   return (float)v;
 }
 
 double from_device_state(const snn_net* net, int var, uint32_t i, float v) {
   const HostPop& pp = net->pops[pop_of(net, i)];
-  if (var == SNN_V_M && pp.model != SNN_AEIF_COND_EXP) return (double)v + pp.E_L;
+  if (var == SNN_V_M && !pp.adex()) return (double)v + pp.E_L;
   return (double)v;
 }
 
@@ -397,7 +410,7 @@ snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports,
   if (!net) return SNN_E_INVALID;
   net->err.clear();
   if (net->built) return fail(net, SNN_E_STATE, "snn_create after snn_build");
-  if (model < SNN_LIF_PSC_DELTA || model > SNN_AEIF_COND_EXP) return fail(net, SNN_E_INVALID, "unknown model %d", model);
+  if (model < SNN_LIF_PSC_DELTA || model > SNN_AEIF_COND_BETA) return fail(net, SNN_E_INVALID, "unknown model %d", model);
   if (n == 0 || n_ports < 1 || n_ports > (uint32_t)kMaxPorts) return fail(net, SNN_E_INVALID, "bad size or port count");
   if (model == SNN_LIF_PSC_DELTA && n_ports != 1) return fail(net, SNN_E_INVALID, "LIF delta has one port");
   if ((uint64_t)net->N + n > kMaxNeurons) return fail(net, SNN_E_UNSUPPORTED, "more than 2^26 neurons");
@@ -407,7 +420,7 @@ snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports,
   p.ports = n_ports;
   p.first = net->N;
   p.inst = (uint32_t)net->insts.size() - 1;
-  if (model == SNN_AEIF_COND_EXP) {
+  if (p.adex()) {
     p.C_m = 281.0; p.E_L = -70.6; p.t_ref = 0.0;
     for (int q = 0; q < kMaxPorts; ++q) p.tau_syn[q] = 1.0;
   }
@@ -419,6 +432,7 @@ snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports,
   net->h.resize(net->N, net->cfg.dt_ms);
   net->refr.resize(net->N, 0);
   net->g.resize((size_t)net->N * kMaxPorts, 0.0);
+  net->gr.resize((size_t)net->N * kMaxPorts, 0.0);
   net->Isyn.resize((size_t)net->N * kMaxPorts, 0.0);
   if (first_gid) *first_gid = p.first;
   return SNN_OK;
@@ -484,6 +498,9 @@ snn_status snn_set_port_param(snn_net* net, uint32_t first, uint32_t n, uint32_t
       p.tau_syn[port] = value;
     } else if (param == SNN_PP_E_REV) {
       p.E_rev[port] = value;
+    } else if (param == SNN_PP_TAU_RISE) {
+      if (!(value > 0)) return fail(net, SNN_E_INVALID, "tau_rise must be positive");
+      p.tau_rise[port] = value;
     } else {
       return fail(net, SNN_E_INVALID, "unknown port parameter %d", param);
     }
@@ -514,7 +531,7 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
     const HostPop& pp = net->pops[pop_of(net, t)];
     if (pp.inst != inst) return fail(net, SNN_E_INVALID, "a projection must stay inside one instance");
     if (port >= pp.ports) return fail(net, SNN_E_INVALID, "port %u out of range for target population", port);
-    if (pp.model == SNN_AEIF_COND_EXP && weight < 0) return fail(net, SNN_E_INVALID, "conductance weights must be >= 0");
+    if (pp.adex() && weight < 0) return fail(net, SNN_E_INVALID, "conductance weights must be >= 0");
     t = pp.first + pp.n;
   }
   if (net->projs.size() >= (1u << 23)) return fail(net, SNN_E_UNSUPPORTED, "too many projections");
@@ -557,6 +574,7 @@ snn_status snn_set_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
         case SNN_V_I_SYN: net->Isyn[(size_t)i * kMaxPorts + port] = x; break;
         case SNN_V_REFR: net->refr[i] = (int32_t)x; break;
         case SNN_V_H: net->h[i] = x; break;
+        case SNN_V_G_RISE: net->gr[(size_t)i * kMaxPorts + port] = x; break;
         default: return fail(net, SNN_E_INVALID, "unknown state variable %d", var);
       }
     }
@@ -566,7 +584,8 @@ snn_status snn_set_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
   if (st) return st;
   HIPCHK(net, hipStreamSynchronize(net->stream));
   const NetDev& nd = net->nd;
-  if ((var == SNN_V_G || var == SNN_V_I_SYN) && port >= net->P) return fail(net, SNN_E_INVALID, "port out of range");
+  if ((var == SNN_V_G || var == SNN_V_I_SYN || var == SNN_V_G_RISE) && port >= net->P)
+    return fail(net, SNN_E_INVALID, "port out of range");
   if (var == SNN_V_REFR) {
     std::vector<int32_t> buf(n);
     for (uint32_t j = 0; j < n; ++j) buf[j] = (int32_t)v[nv == 1 ? 0 : j];
@@ -583,6 +602,7 @@ snn_status snn_set_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
     case SNN_V_G: base = nd.g; stride = net->P; off = port; break;
     case SNN_V_I_SYN: base = nd.Isyn; stride = net->P; off = port; break;
     case SNN_V_H: base = nd.h; break;
+    case SNN_V_G_RISE: base = nd.gr; stride = net->P; off = port; break;
     default: return fail(net, SNN_E_INVALID, "unknown state variable %d", var);
   }
   if (!base) return fail(net, SNN_E_INVALID, "state variable not present in this network");
@@ -613,6 +633,7 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
         case SNN_V_I_SYN: out[j] = net->Isyn[(size_t)i * kMaxPorts + port]; break;
         case SNN_V_REFR: out[j] = net->refr[i]; break;
         case SNN_V_H: out[j] = net->h[i]; break;
+        case SNN_V_G_RISE: out[j] = net->gr[(size_t)i * kMaxPorts + port]; break;
         default: return fail(net, SNN_E_INVALID, "unknown state variable %d", var);
       }
     }
@@ -622,7 +643,8 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
   if (st) return st;
   HIPCHK(net, hipStreamSynchronize(net->stream));
   const NetDev& nd = net->nd;
-  if ((var == SNN_V_G || var == SNN_V_I_SYN) && port >= net->P) return fail(net, SNN_E_INVALID, "port out of range");
+  if ((var == SNN_V_G || var == SNN_V_I_SYN || var == SNN_V_G_RISE) && port >= net->P)
+    return fail(net, SNN_E_INVALID, "port out of range");
   if (var == SNN_V_REFR) {
     if (!nd.refr) return fail(net, SNN_E_INVALID, "no refractory state in this network");
     std::vector<int32_t> buf(n);
@@ -639,6 +661,7 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
     case SNN_V_G: base = nd.g; stride = net->P; off = port; break;
     case SNN_V_I_SYN: base = nd.Isyn; stride = net->P; off = port; break;
     case SNN_V_H: base = nd.h; break;
+    case SNN_V_G_RISE: base = nd.gr; stride = net->P; off = port; break;
     default: return fail(net, SNN_E_INVALID, "unknown state variable %d", var);
   }
   if (!base) return fail(net, SNN_E_INVALID, "state variable not present in this network");
@@ -667,8 +690,13 @@ snn_status snn_build(snn_net* net) {
   uint32_t P = 1;
   for (const HostPop& p : net->pops) {
     P = std::max(P, p.ports);
-    if (p.model == SNN_AEIF_COND_EXP) {
+    if (p.adex()) {
       net->has_adex = true;
+      if (p.model == SNN_AEIF_COND_BETA) {
+        net->has_beta = true;
+        for (uint32_t q = 0; q < p.ports; ++q)
+          if (!(p.tau_rise[q] > 0) || !(p.tau_syn[q] > 0)) return fail(net, SNN_E_INVALID, "invalid beta time constants");
+      }
       if (p.t_ref != 0.0) return fail(net, SNN_E_UNSUPPORTED, "AdEx refractory time must be 0");
       if (!(p.Delta_T > 0) || !(p.tau_w > 0) || !(p.C_m > 0) || !(p.rk_eps > 0))
         return fail(net, SNN_E_INVALID, "invalid AdEx parameters");
@@ -772,13 +800,20 @@ snn_status snn_build(snn_net* net) {
     memset(&d, 0, sizeof d);
     d.first = p.first; d.n = p.n; d.model = p.model; d.n_ports = (int32_t)p.ports;
     d.gid_base = net->insts[p.inst].first_gid; d.seed = net->insts[p.inst].seed;
-    if (p.model != SNN_AEIF_COND_EXP) lif_propagators(p, dt, d);
+    if (!p.adex()) lif_propagators(p, dt, d);
     d.inv_C = (float)(1.0 / p.C_m); d.g_L = (float)p.g_L; d.E_L = (float)p.E_L; d.Delta_T = (float)p.Delta_T;
     d.inv_Delta_T = (float)(1.0 / p.Delta_T); d.V_T = (float)p.V_T; d.inv_tau_w = (float)(1.0 / p.tau_w);
     d.a = (float)p.a; d.b = (float)p.b; d.V_peak = (float)p.V_peak; d.V_r = (float)p.V_r;
     for (int q = 0; q < kMaxPorts; ++q) {
       d.E_rev[q] = (float)p.E_rev[q];
       d.inv_tau_syn[q] = (float)(1.0 / p.tau_syn[q]);
+      if (p.model == SNN_AEIF_COND_BETA) {
+        d.inv_tau_rise[q] = (float)(1.0 / p.tau_rise[q]);
+        d.g0[q] = (float)beta_g0(p.tau_rise[q], p.tau_syn[q]);
+      } else {
+        d.inv_tau_rise[q] = 1.f;  // r stays 0 for exponential ports
+        d.g0[q] = 0.f;
+      }
       d.scale[q] = (q < (int)P) ? (float)ldexp(1.0, -net->shift[k * P + q]) : 0.f;
     }
     d.rk_eps = (float)p.rk_eps; d.rk_hmin = (float)p.rk_hmin; d.dt = (float)dt;
@@ -811,7 +846,7 @@ snn_status snn_build(snn_net* net) {
     nd.pois_len = std::max<uint32_t>(nd.pois_len, k + 1);
   }
   nd.nblk_upd = (N + kUpdBlock - 1) / kUpdBlock;
-  nd.pad0 = (net->has_lif ? 1u : 0u) | (net->has_adex ? 2u : 0u);
+  nd.pad0 = (net->has_lif ? 1u : 0u) | (net->has_adex ? 2u : 0u) | (net->has_beta ? 4u : 0u);
   hipStream_t s = net->stream;
 #define ALLOC(ptr, T, count)                                                              \
   do {                                                                                    \
@@ -903,7 +938,7 @@ snn_status snn_build(snn_net* net) {
   for (uint32_t i = 0; i < N; ++i) {
     const HostPop& pp = net->pops[pop_of(net, i)];
     const double V = std::isnan(net->V[i]) ? pp.E_L : net->V[i];
-    hv[i] = (pp.model == SNN_AEIF_COND_EXP) ? (float)V : (float)(V - pp.E_L);
+    hv[i] = pp.adex() ? (float)V : (float)(V - pp.E_L);
     hie[i] = (float)net->Ie[i];
   }
   HIPCHK(net, copy_sync(net, d_V, hv.data(), N * 4, hipMemcpyHostToDevice));
@@ -932,6 +967,13 @@ snn_status snn_build(snn_net* net) {
     HIPCHK(net, copy_sync(net, d_h, hh.data(), N * 4, hipMemcpyHostToDevice));
     HIPCHK(net, copy_sync(net, d_g, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
     nd.w = d_w; nd.h = d_h; nd.g = d_g;
+    if (net->has_beta) {
+      float* d_gr; ALLOC(d_gr, float, (size_t)N * P);
+      for (uint32_t i = 0; i < N; ++i)
+        for (uint32_t q = 0; q < P; ++q) hp[(size_t)i * P + q] = (float)net->gr[(size_t)i * kMaxPorts + q];
+      HIPCHK(net, copy_sync(net, d_gr, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
+      nd.gr = d_gr;
+    }
   }
   int64_t* d_acc; ALLOC(d_acc, int64_t, (size_t)kInBuf * N * P);
   HIPCHK(net, hipMemsetAsync(d_acc, 0, (size_t)kInBuf * N * P * 8, s));

@@ -2,7 +2,8 @@
 //
 // HBM layout (all arrays device-resident for the life of the network):
 //   neuron state (SoA, fp32): V (LIF: V - E_L), I_e, and per model
-//     LIF-exp: I_syn[N][P];  AdEx: w, g[N][P], h;  refr (int32) for LIF.
+//     LIF-exp: I_syn[N][P];  AdEx: w, g[N][P], h, and with beta ports the
+//     rising variables r[N][P];  refr (int32) for LIF.
 //   acc[3][N][P]  int64 fixed-point input, one buffer per arrival step
 //                 n, n+1, n+2 (index step % 3; direct delivery: all input;
 //                 binned delivery: only the events that did not fit their
@@ -48,7 +49,7 @@ constexpr int kBinMultShift = 10;
 constexpr int kTagConn = 1;
 constexpr int kTagPoisson = 2;
 
-enum Model : int32_t { kLifDelta = 0, kLifExp = 1, kAdex = 2 };
+enum Model : int32_t { kLifDelta = 0, kLifExp = 1, kAdex = 2, kAdexBeta = 3 };
 
 // Parameters of one population as the kernels use them (fp32, propagators
 // precomputed in double on the host).
@@ -62,6 +63,8 @@ struct PopDev {
   // AdEx
   float inv_C, g_L, E_L, Delta_T, inv_Delta_T, V_T, inv_tau_w, a, b, V_peak, V_r;
   float E_rev[kMaxPorts], inv_tau_syn[kMaxPorts];
+  // beta ports: 1/tau_rise and the input scale g0 (exponential ports: 1, 0)
+  float inv_tau_rise[kMaxPorts], g0[kMaxPorts];
   float rk_eps, rk_hmin, dt;
   // fixed-point input conversion: x = (float)acc * scale[port], scale = 2^-S
   float scale[kMaxPorts];
@@ -104,7 +107,7 @@ struct Ctrl {
 struct NetDev {
   uint32_t N, P, npop, dmax;   // dmax = largest delay present
   uint32_t npois, pois_len;    // Poisson threshold tables; entries read at most (the rest are never reached)
-  uint32_t R, nblk_upd, sel_grid, pad0;  // R step slots; pad0: bit 0 LIF present, bit 1 AdEx present
+  uint32_t R, nblk_upd, sel_grid, pad0;  // R step slots; pad0: bit 0 LIF, bit 1 AdEx, bit 2 beta ports present
   uint32_t n_tiles, tile_shift;  // binned delivery (n_tiles == 0: direct atomics)
   uint64_t bins_total;           // bin entries per input buffer
   uint64_t log_mask;           // CAP - 1
@@ -116,7 +119,7 @@ struct NetDev {
   const uint32_t* cls_port;    // [n_classes]
   uint32_t n_classes, cls_bits; // payload = target << cls_bits | class
   // state
-  float* V; float* Ie; float* Isyn; float* w; float* g; float* h; int32_t* refr;
+  float* V; float* Ie; float* Isyn; float* w; float* g; float* gr; float* h; int32_t* refr;
   // CSR
   const uint64_t* src_mask; const uint32_t* grp_ptr; const uint64_t* grp_off; const uint32_t* payload;
   int64_t* acc;

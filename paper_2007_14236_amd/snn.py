@@ -18,11 +18,11 @@ LIB_PATH = os.path.join(HERE, "libsnn.so")
 
 SNN_OK = 0
 ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "STATE", -4: "OVERFLOW", -5: "DEVICE", -7: "UNSUPPORTED"}
-MODELS = {"lif_delta": 0, "lif_exp": 1, "aeif_cond_exp": 2}
+MODELS = {"lif_delta": 0, "lif_exp": 1, "aeif_cond_exp": 2, "aeif_cond_beta": 3}
 PARAMS = {"tau_m": 0, "C_m": 1, "E_L": 2, "V_th": 3, "V_reset": 4, "t_ref": 5, "g_L": 6, "Delta_T": 7,
           "V_T": 8, "tau_w": 9, "a": 10, "b": 11, "V_peak": 12, "V_r": 13, "rk_eps": 14, "rk_hmin": 15}
-PORT_PARAMS = {"tau_syn": 0, "E_rev": 1}
-STATE = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6}
+PORT_PARAMS = {"tau_syn": 0, "E_rev": 1, "tau_rise": 2}
+STATE = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6, "g_rise": 7}
 DELAYS = {"const": 0, "uniform": 1, "normal": 2}
 F_NO_SPIKE_RECORD = 1
 F_DELIVERY_DIRECT = 2

@@ -192,6 +192,37 @@ def adex_balanced(n: int = 1_000_000, k: int = 1000, seed: int = 1, dmax: int = 
                 projections=projs, poisson=pois)
 
 
+def adex_balanced_alpha(n: int = 1_000_000, k: int = 1000, seed: int = 1, dmax: int = 63,
+                        delay=("normal", 0.5, 0.25), w_ex: float = 0.05, w_in: float = 0.35,
+                        poisson_rate: float = 20000.0, w_poisson: float = 0.37) -> dict:
+    """The balanced network as Sec. 2.4 and Table 1 give it: AdEx neurons with
+    alpha-function conductances (beta ports with rise = decay = 1 ms; port 0
+    E_rev 0 mV, port 1 E_rev -85 mV), N_in = N_ex/4, CI = CE/4, peak
+    conductances W_ex 0.05, W_in 0.35, W_poisson 0.37 nS, Poisson 20 kHz on
+    port 0, delays normal with mean 0.5 ms and standard deviation 0.25 ms
+    (clipped to at least one step), Table 2 neuron parameters, RK45 tolerance
+    1e-6."""
+    ne = (n * 4) // 5
+    ni = n - ne
+    ke = (k * 4) // 5
+    ki = k - ke
+    prm = dict(ADEX_T2)
+    prm["tau_rise"] = list(prm["tau_syn"])
+    pops = [
+        dict(name="E", model="aeif_cond_beta", n=ne, ports=2, params=dict(prm),
+             V0=initial_v(seed, ne, prm["E_L"], prm["V_T"], stream=7), I_e=0.0),
+        dict(name="I", model="aeif_cond_beta", n=ni, ports=2, params=dict(prm),
+             V0=initial_v(seed, ni, prm["E_L"], prm["V_T"], stream=8), I_e=0.0),
+    ]
+    projs = []
+    for tgt in ("E", "I"):
+        projs.append(dict(src="E", tgt=tgt, K=ke, weight=w_ex, delay=tuple(delay), port=0))
+        projs.append(dict(src="I", tgt=tgt, K=ki, weight=w_in, delay=tuple(delay), port=1))
+    pois = [dict(tgt=t, rate=poisson_rate, n_inputs=1, weight=w_poisson, port=0) for t in ("E", "I")]
+    return dict(name=f"adex_alpha_n{n}_k{k}", dt=DT, seed=seed, dmax=dmax, populations=pops,
+                projections=projs, poisson=pois)
+
+
 def brunel_sweep_instance(i: int) -> dict:
     """Instance i of the batched sweep: N ~ U[2000, 40000] (multiple of 5,
     80/20), in-degree 0.1 N, g ~ U[3, 7], drive nu ~ U[10, 30] Hz from
