@@ -46,12 +46,15 @@ BYTES_PER_EVENT = {"direct": 4 + 16, "binned": 4 + 8}
 FP32_PEAK_TFLOPS = 157.3
 
 
-def rk45_flops_per_attempt(ports: int) -> int:
+def rk45_flops_per_attempt(ports: int, beta: bool = False) -> int:
     """fp32 operations of one attempted Cash-Karp substep of the AdEx model
     with `ports` conductances (fma = 2, exp2 / log2 / min / max / reciprocal =
-    1): 6 right-hand sides of 15 + 4P, stage sums, fifth-order solution, error
-    estimate and error ratio of 60 per each of the 2 + P components, and 9 of
-    step control."""
+    1): 6 right-hand sides of 15 + 4P (beta ports: 15 + 6P, the rising
+    variable's decay and its fma into dg/dt), stage sums, fifth-order
+    solution, error estimate and error ratio of 60 per each of the 2 + P
+    (beta: 2 + 2P) components, and 9 of step control."""
+    if beta:
+        return 6 * (15 + 6 * ports) + 60 * (2 + 2 * ports) + 9
     return 6 * (15 + 4 * ports) + 60 * (2 + ports) + 9
 BYTES_PER_PAIR = 28
 BYTES_PER_SPIKE = 28
@@ -83,6 +86,8 @@ def bytes_per_step_neurons(spec: dict, delivery: str) -> int:
         ports = p["ports"]
         if p["model"] == "aeif_cond_exp":
             b = 8 * 3 + 8 * ports + 4
+        elif p["model"] == "aeif_cond_beta":
+            b = 8 * 3 + 16 * ports + 4
         elif p["model"] == "lif_exp":
             b = 8 * 2 + 8 * ports + 4
         else:
@@ -104,9 +109,15 @@ def parse():
     ap.add_argument("--k-ext", type=int, default=None)
     ap.add_argument("--requests", type=int, default=60, help="serve: requests in the arrival trace")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
-    ap.add_argument("--workload", choices=["microcircuit", "adex", "sweep", "serve"], default="microcircuit",
-                    help="microcircuit (default line); adex: 1e6 AdEx neurons, in-degree 1000; "
-                         "sweep: batched Brunel instances vs the same instances run one by one")
+    ap.add_argument("--workload", choices=["microcircuit", "adex", "alpha", "alpha_scan", "sweep", "serve"],
+                    default="microcircuit",
+                    help="microcircuit (default line); adex: 1e6 AdEx neurons, in-degree 1000, exponential "
+                         "conductances; alpha: the balanced network with alpha conductances and normal delays "
+                         "(--neurons, --indegree); alpha_scan: its simulation time over N at in-degree 1000 and "
+                         "over the in-degree at N = 30000; sweep: batched Brunel instances vs the same instances "
+                         "run one by one")
+    ap.add_argument("--neurons", type=int, default=1_000_000, help="alpha: number of neurons")
+    ap.add_argument("--indegree", type=int, default=1000, help="alpha: in-degree")
     ap.add_argument("--instances", type=int, default=128, help="sweep: number of instances")
     ap.add_argument("--seq-instances", type=int, default=16,
                     help="sweep: instances also run one by one (sequential baseline sample)")
@@ -177,8 +188,12 @@ def main():
         return bench_sweep(args, S, W, torch)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "alpha_scan":
+        return bench_alpha_scan(args, S, W, torch)
     if args.workload == "adex":
         spec = W.adex_balanced()
+    elif args.workload == "alpha":
+        spec = W.adex_balanced_alpha(n=args.neurons, k=args.indegree)
     else:
         kw = {} if args.k_ext is None else {"k_ext": args.k_ext}
         spec = W.microcircuit(scale=1.0, **kw)
@@ -273,14 +288,24 @@ def main():
         "roofline": roofline,
         "autotune": tuned,
     }
-    if args.workload == "adex":
-        out["config"] = {"workload": "balanced AdEx network: 1,000,000 neurons (800k E / 200k I), in-degree 1000, "
-                                     "exponential conductances on 2 ports, RK45 rtol 1e-6, delays U[1,2) ms",
-                         "neurons": W.total_neurons(spec), "synapses": W.count_synapses(spec), "dt_ms": dt,
-                         "t_bio_s": bio_s, "parallelism": "single GPU"}
-        out["paper_context"] = {"rtf_rtx2080ti": 70.0, "note": "alpha conductances in the paper"}
+    if args.workload in ("adex", "alpha"):
+        if args.workload == "adex":
+            out["config"] = {"workload": "balanced AdEx network: 1,000,000 neurons (800k E / 200k I), in-degree "
+                                         "1000, exponential conductances on 2 ports, RK45 rtol 1e-6, delays U[1,2) ms",
+                             "neurons": W.total_neurons(spec), "synapses": W.count_synapses(spec), "dt_ms": dt,
+                             "t_bio_s": bio_s, "parallelism": "single GPU"}
+            out["paper_context"] = {"rtf_rtx2080ti": 70.0, "note": "alpha conductances in the paper"}
+        else:
+            out["config"] = {"workload": f"balanced AdEx network as in Sec. 2.4 / Table 1: {W.total_neurons(spec):,} "
+                                         f"neurons (80% E / 20% I), in-degree {args.indegree}, alpha conductances "
+                                         "(tau 1 ms) on 2 ports, peak weights 0.05 / 0.35 / 0.37 nS, Poisson 20 kHz, "
+                                         "delays normal 0.5 +- 0.25 ms, RK45 rtol 1e-6",
+                             "neurons": W.total_neurons(spec), "synapses": W.count_synapses(spec), "dt_ms": dt,
+                             "t_bio_s": bio_s, "parallelism": "single GPU"}
+            out["paper_context"] = {"rtf_rtx2080ti": 70.0 if args.neurons == 1_000_000 and args.indegree == 1000
+                                    else None, "rate_hz_table1": 30.7}
         att_p = (c3["rk_accepted"] + c3["rk_rejected"] - c2["rk_accepted"] - c2["rk_rejected"]) / ps
-        fpa = rk45_flops_per_attempt(2)
+        fpa = rk45_flops_per_attempt(2, beta=args.workload == "alpha")
         tflops = att_p * fpa / (dlv_ms * 1e-3) / 1e12 if dlv_ms > 0 else 0.0
         out["rk45"] = {"accepted_per_step": (c1["rk_accepted"] - c0["rk_accepted"]) / args.steps,
                        "rejected_per_step": (c1["rk_rejected"] - c0["rk_rejected"]) / args.steps}
@@ -295,6 +320,50 @@ def main():
     if not args.no_cpu_baseline and args.workload == "microcircuit":
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def bench_alpha_scan(args, S, W, torch):
+    """Simulation time per biological second of the alpha-conductance
+    balanced network (Sec. 2.4, Table 1) over the number of neurons at
+    in-degree 1000, and over the in-degree at 30,000 neurons (the two scans of
+    the paper's balanced-network results): each point built, warmed up for
+    `--warmup` steps and timed over `--steps` steps with the library's default
+    delivery."""
+    points = [("N", n, 1000) for n in (10_000, 30_000, 100_000, 300_000, 1_000_000)]
+    points += [("K", 30_000, k) for k in (1000, 3000, 10_000, 20_000, 30_000)]
+    rows = []
+    for scan, n, k in points:
+        spec = W.adex_balanced_alpha(n=n, k=k)
+        t0 = time.perf_counter()
+        net = S.Net(spec)
+        build_s = time.perf_counter() - t0
+        net.simulate(args.warmup)
+        torch.cuda.synchronize()
+        c0 = net.counters()
+        t0 = time.perf_counter()
+        net.simulate(args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        c1 = net.counters()
+        bio = args.steps * spec["dt"] * 1e-3
+        ev = c1["events"] - c0["events"]
+        row = {"scan": scan, "neurons": n, "indegree": k, "synapses": W.count_synapses(spec),
+               "delivery": "binned" if c1["delivery"] == 2 else "direct", "build_s": round(build_s, 2),
+               "rtf": round(wall / bio, 4), "events_per_s": round(ev / wall),
+               "rate_hz": round((c1["spikes"] - c0["spikes"]) / bio / n, 2)}
+        net.close()
+        rows.append(row)
+        print(f"[bench] {row}", file=sys.stderr, flush=True)
+    big = [r for r in rows if r["neurons"] == 1_000_000 and r["indegree"] == 1000][0]
+    out = {"metric": METRIC, "value": big["rtf"], "unit": "s wall / s bio (1e6 neurons, in-degree 1000)",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": big["rtf"] * 0.1, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 state, i64 fixed-point input", "data": "synthetic",
+           "config": {"workload": "alpha-conductance balanced network scans (Sec. 2.4, Table 1): N at in-degree "
+                                  "1000; in-degree at N = 30,000", "parallelism": "single GPU"},
+           "paper_context": {"rtf_rtx2080ti_1e6": 70.0, "rate_hz_table1": 30.7},
+           "points": rows}
     print(json.dumps(out), flush=True)
 
 
