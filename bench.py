@@ -127,6 +127,8 @@ def parse():
                     help="how events are summed: device atomics, or bins per target tile summed in LDS")
     ap.add_argument("--tile-neurons", type=int, default=0, help="binned delivery: neurons per tile (0: library)")
     ap.add_argument("--bin-capacity", type=int, default=0, help="binned delivery: entries per tile bin (0: library)")
+    ap.add_argument("--delivery-blocks", type=int, default=0,
+                    help="blocks that deliver delays of 3 steps or more (0: library)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -201,7 +203,8 @@ def main():
     print(f"[bench] building {spec['name']}: {W.total_neurons(spec)} neurons, "
           f"{W.count_synapses(spec):.4g} synapses", file=sys.stderr, flush=True)
     tuned, tune_s = None, 0.0
-    kw = dict(delivery=args.delivery, tile_neurons=args.tile_neurons, bin_capacity=args.bin_capacity)
+    kw = dict(delivery=args.delivery, tile_neurons=args.tile_neurons, bin_capacity=args.bin_capacity,
+              delivery_blocks=args.delivery_blocks)
     if not args.no_tune and args.delivery == "auto" and not args.tile_neurons:
         from paper_2007_14236_amd import autotune as A
         t0 = time.perf_counter()
