@@ -1213,9 +1213,9 @@ __global__ void __launch_bounds__(kB) k_poisson_counts(NetDev nd, uint64_t step,
   out[j] = (pp.pois >= 0) ? poisson_draw(nd.pois_thr + (size_t)pp.pois * kPoisKmax, pp.seed, i - pp.gid_base, step) : 0u;
 }
 
-// Readback of the binned input pending for the step of parity par, on one
-// port, for gids [first, first + n): block = one tile, entries decoded and
-// added to out[gid - first] (which holds the tile's spill already).
+// Readback of the binned input pending in input buffer buf, on one port, for
+// gids [first, first + n): block = one tile, entries decoded and added to
+// out[gid - first] (which holds the tile's spill already).
 __global__ void __launch_bounds__(kB) k_pending_input(NetDev nd, uint32_t buf, uint32_t first, uint32_t n,
                                                       uint32_t port, int64_t* out) {
   const uint32_t t = (first >> nd.tile_shift) + blockIdx.x;
