@@ -105,6 +105,10 @@ def lib():
                                     P64, P64]
         L.orc_cash_karp_tableau.argtypes = [PD, PD, PD, PD]
         L.orc_adex_rhs.argtypes = [C.POINTER(PopParams), C.c_double, PD, PD]
+        L.orc_prepare.argtypes = [C.c_void_p]
+        L.orc_target_synapses.restype = C.c_int64
+        L.orc_target_synapses.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, P32, P32, P32, PI64]
+        L.orc_sampled_input.argtypes = [C.c_void_p, C.c_uint32, P32, C.c_uint64, P64, P32, P32, C.c_uint64, PI64]
         L.orc_last_error.restype = C.c_char_p
         L.orc_last_error.argtypes = [C.c_void_p]
         _lib = L
@@ -183,6 +187,18 @@ def adex_rhs(params: PopParams, I_e: float, y) -> np.ndarray:
     return dy
 
 
+def lif_exp_step32(params: PopParams, dt: float, y: float, I, refr: int, I_e: float, x):
+    """One step of the fp32 same-operation-order LIF-exp update.  Returns
+    (y, I, refr, spiked) with y = V - E_L."""
+    yy = C.c_float(y)
+    Ia = np.ascontiguousarray(I, dtype=np.float32).copy()
+    xa = np.ascontiguousarray(x, dtype=np.float32)
+    rr = C.c_int32(refr)
+    s = lib().orc_lif_exp_step32(C.byref(params), dt, C.byref(yy), _ptr(Ia, C.c_float), C.byref(rr),
+                                 C.c_float(I_e), _ptr(xa, C.c_float))
+    return yy.value, Ia, rr.value, int(s)
+
+
 def adex_step(params: PopParams, dt: float, y, h: float, I_e: float, x):
     """One dt of the AdEx oracle.  Returns (y_new, h_new, mult, n_acc, n_rej)."""
     y = np.array(y, dtype=np.float64)
@@ -198,7 +214,11 @@ def adex_step(params: PopParams, dt: float, y, h: float, I_e: float, x):
 class OracleNet:
     """Oracle instance built from a specification dictionary."""
 
-    def __init__(self, spec: dict, mode: int = FP64):
+    def __init__(self, spec: dict, mode: int = FP64, build: bool = True):
+        """build=False prepares state, Poisson drive and fixed-point exponents
+        but draws no synapse table: for the sampled checks of networks whose
+        table does not fit (target_synapses, sampled_input, poisson_count,
+        shift_of); such a network cannot be simulated."""
         self.L = lib()
         self.spec = spec
         self.mode = mode
@@ -231,7 +251,7 @@ class OracleNet:
             if np.ndim(ie) == 0:
                 ie = np.full(tn, float(ie))
             self.set_state("I_e", t0, np.asarray(ie, dtype=np.float64))
-        self._check(self.L.orc_build(self.h) == 0)
+        self._check((self.L.orc_build(self.h) if build else self.L.orc_prepare(self.h)) == 0)
 
     def _check(self, ok):
         if not ok:
@@ -289,6 +309,30 @@ class OracleNet:
         if self.L.orc_poisson_count(self.h, gid, step, C.byref(k)) != 0:
             return -1
         return int(k.value)
+
+    def target_synapses(self, t: int):
+        """(source, delay, port, w_q) of the synapses onto target t, drawn one
+        by one by the fixed-indegree rule."""
+        n = self.L.orc_target_synapses(self.h, t, 0, None, None, None, None)
+        self._check(n >= 0)
+        src = np.zeros(n, np.uint32); d = np.zeros(n, np.uint32); port = np.zeros(n, np.uint32)
+        wq = np.zeros(n, np.int64)
+        self.L.orc_target_synapses(self.h, t, n, _ptr(src, C.c_uint32), _ptr(d, C.c_uint32), _ptr(port, C.c_uint32),
+                                   _ptr(wq, C.c_int64))
+        return src, d, port, wq
+
+    def sampled_input(self, targets, step, gid, mult, target_step: int) -> np.ndarray:
+        """Input delivered at target_step to the given targets by the spikes
+        (step, gid, mult), sorted by (step, gid): array [len(targets)][P]."""
+        t = np.ascontiguousarray(targets, dtype=np.uint32)
+        st = np.ascontiguousarray(step, dtype=np.uint64)
+        g = np.ascontiguousarray(gid, dtype=np.uint32)
+        m = np.ascontiguousarray(mult, dtype=np.uint32)
+        out = np.zeros((len(t), self.P), dtype=np.int64)
+        self._check(self.L.orc_sampled_input(self.h, len(t), _ptr(t, C.c_uint32), len(st), _ptr(st, C.c_uint64),
+                                             _ptr(g, C.c_uint32), _ptr(m, C.c_uint32), target_step,
+                                             _ptr(out, C.c_int64)) == 0)
+        return out
 
     def record_input(self, max_steps: int) -> np.ndarray:
         buf = np.zeros((max_steps, self.N, self.P), dtype=np.int64)

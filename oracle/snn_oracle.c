@@ -211,7 +211,7 @@ void orc_destroy(orc_net* o) {
 }
 
 int64_t orc_population(orc_net* o, uint32_t n, const orc_pop_params* p) {
-  if (o->built) { set_err(o, "population after build"); return -1; }
+  if (o->built || o->shift) { set_err(o, "population after build"); return -1; }
   if (n == 0 || p->n_ports < 1 || p->n_ports > ORC_MAX_PORTS) { set_err(o, "bad population"); return -1; }
   if (p->model < ORC_LIF_DELTA || p->model > ORC_AEIF_COND_BETA) { set_err(o, "bad model"); return -1; }
   if (p->model == ORC_LIF_DELTA && p->n_ports != 1) { set_err(o, "lif_delta has one port"); return -1; }
@@ -237,7 +237,7 @@ static uint32_t pop_index(const orc_net* o, uint32_t gid) {
 int orc_connect_fixed_indegree(orc_net* o, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
                                uint32_t tgt_n, uint32_t indegree, double weight, int delay_kind,
                                double da, double db, uint32_t port) {
-  if (o->built) { set_err(o, "connect after build"); return -1; }
+  if (o->built || o->shift) { set_err(o, "connect after build"); return -1; }
   if ((uint64_t)src_first + src_n > o->N || (uint64_t)tgt_first + tgt_n > o->N || src_n == 0) {
     set_err(o, "range"); return -1;
   }
@@ -253,7 +253,7 @@ int orc_connect_fixed_indegree(orc_net* o, uint32_t src_first, uint32_t src_n, u
 
 int orc_poisson(orc_net* o, uint32_t tgt_first, uint32_t tgt_n, double rate_hz, uint32_t n_inputs,
                 double weight, uint32_t port) {
-  if (o->built) { set_err(o, "poisson after build"); return -1; }
+  if (o->built || o->shift) { set_err(o, "poisson after build"); return -1; }
   if ((uint64_t)tgt_first + tgt_n > o->N) { set_err(o, "range"); return -1; }
   orc_pois q;
   memset(&q, 0, sizeof q);
@@ -363,11 +363,13 @@ static uint32_t draw_delay(const uint64_t* thr, uint32_t dmax, uint32_t u) {
   return dmax;
 }
 
-int orc_build(orc_net* o) {
-  if (o->built) { set_err(o, "built twice"); return -1; }
+/* Everything of the build but the synapse table: state, Poisson drive per
+   neuron, fixed-point exponents.  Idempotent. */
+static int prepare(orc_net* o) {
+  if (o->shift) return 0;
   if (o->N == 0) { set_err(o, "empty"); return -1; }
   alloc_state(o);
-  uint32_t P = o->P, D1 = o->dmax + 1;
+  uint32_t P = o->P;
   /* Poisson drive per neuron (at most one) */
   o->pois_of = (int32_t*)malloc(o->N * sizeof(int32_t));
   for (uint32_t i = 0; i < o->N; ++i) o->pois_of[i] = -1;
@@ -409,17 +411,39 @@ int orc_build(orc_net* o) {
   }
   for (size_t k = 0; k < (size_t)o->n_pops * P; ++k) o->shift[k] = orc_fixed_point_shift(maxw[k]);
   free(maxw);
+  return 0;
+}
 
-  /* fixed-indegree rule: for target t of projection p and k < K, one Philox
-     block per pair of synapses: counter (t, p<<40 | k>>1, CONN, 0), key
-     (seed, 0); synapse k uses words 2(k&1) (source) and 2(k&1)+1 (delay).
-     source = first + floor(u64 * n_src / 2^64); autapses and multapses kept. */
+/* fixed-indegree rule: for target t of projection p and k < K, one Philox
+   block per pair of synapses: counter (t, p<<40 | k>>1, CONN, 0), key
+   (seed, 0); synapse k uses words 2(k&1) (source) and 2(k&1)+1 (delay).
+   source = first + floor(u64 * n_src / 2^64); autapses and multapses kept.
+   blk holds the block of the pair k belongs to (drawn when k is even). */
+static void draw_synapse(const orc_net* o, uint32_t p, uint32_t t, uint32_t k, uint64_t blk[4], uint32_t* src,
+                         uint32_t* d) {
+  const orc_proj* pr = &o->proj[p];
+  if ((k & 1u) == 0) {
+    uint64_t ctr[4] = {t, ((uint64_t)p << 40) | (uint64_t)(k >> 1), ORC_TAG_CONN, 0};
+    uint64_t key[2] = {o->seed, 0};
+    orc_philox4x64_10(ctr, key, blk);
+  }
+  uint64_t us = blk[2 * (k & 1u)];
+  uint64_t ud = blk[2 * (k & 1u) + 1];
+  *src = pr->src_first + (uint32_t)(((unsigned __int128)us * pr->src_n) >> 64);
+  *d = draw_delay(pr->dthr, o->dmax, (uint32_t)(ud >> 32));
+}
+
+int orc_prepare(orc_net* o) { return prepare(o); }
+
+int orc_build(orc_net* o) {
+  if (o->built) { set_err(o, "built twice"); return -1; }
+  if (prepare(o) != 0) return -1;
+  uint32_t P = o->P, D1 = o->dmax + 1;
   uint64_t total = 0;
   for (uint32_t p = 0; p < o->n_proj; ++p) total += (uint64_t)o->proj[p].K * o->proj[p].tgt_n;
   o->n_syn = total;
   o->syn = (orc_syn*)malloc((total ? total : 1) * sizeof(orc_syn));
   uint64_t pos = 0;
-  uint64_t key[2] = {o->seed, 0};
   for (uint32_t p = 0; p < o->n_proj; ++p) {
     const orc_proj* pr = &o->proj[p];
     for (uint32_t j = 0; j < pr->tgt_n; ++j) {
@@ -429,16 +453,10 @@ int orc_build(orc_net* o) {
       int64_t wq = llrint(ldexp(pr->weight, S));
       uint64_t blk[4] = {0, 0, 0, 0};
       for (uint32_t k = 0; k < pr->K; ++k) {
-        if ((k & 1u) == 0) {
-          uint64_t ctr[4] = {t, ((uint64_t)p << 40) | (uint64_t)(k >> 1), ORC_TAG_CONN, 0};
-          orc_philox4x64_10(ctr, key, blk);
-        }
-        uint64_t us = blk[2 * (k & 1u)];
-        uint64_t ud = blk[2 * (k & 1u) + 1];
-        uint32_t s = pr->src_first + (uint32_t)(((unsigned __int128)us * pr->src_n) >> 64);
+        uint32_t s, d;
+        draw_synapse(o, p, t, k, blk, &s, &d);
         orc_syn sy;
-        sy.src = s; sy.tgt = t; sy.port = (uint8_t)pr->port; sy.wq = wq;
-        sy.d = (uint8_t)draw_delay(pr->dthr, o->dmax, (uint32_t)(ud >> 32));
+        sy.src = s; sy.tgt = t; sy.port = (uint8_t)pr->port; sy.wq = wq; sy.d = (uint8_t)d;
         o->syn[pos++] = sy;
       }
     }
@@ -740,7 +758,7 @@ static uint32_t poisson_draw(const orc_net* o, const orc_pois* q, uint32_t gid, 
 }
 
 int orc_poisson_count(const orc_net* o, uint32_t gid, uint64_t step, uint32_t* k) {
-  if (!o->built || gid >= o->N || o->pois_of[gid] < 0) return -1;
+  if (!o->shift || gid >= o->N || o->pois_of[gid] < 0) return -1;
   *k = poisson_draw(o, &o->pois[o->pois_of[gid]], gid, step);
   return 0;
 }
@@ -774,6 +792,69 @@ int orc_replay_input(const orc_net* o, uint64_t n_spk, const uint64_t* step, con
   if (!o->built) return -1;
   memset(out, 0, (size_t)o->N * o->P * sizeof(int64_t));
   deliver_into(o, target_step, n_spk, step, gid, mult, out);
+  return 0;
+}
+
+/* Sampled checks of networks too large for the synapse table: the synapses
+   onto one target, drawn one by one by the rule above (in projection order,
+   then draw index), and the delivered input of sampled targets by the
+   definition -- for each synapse (s, d, port, w_q) onto t, the multiplicity
+   of the spike of s at step target_step - d times w_q -- from a spike list
+   sorted by (step, gid). */
+int64_t orc_target_synapses(orc_net* o, uint32_t t, uint64_t cap, uint32_t* src, uint32_t* d, uint32_t* port,
+                            int64_t* wq) {
+  if (prepare(o) != 0 || t >= o->N) return -1;
+  uint64_t n = 0;
+  for (uint32_t p = 0; p < o->n_proj; ++p) {
+    const orc_proj* pr = &o->proj[p];
+    if (t < pr->tgt_first || t - pr->tgt_first >= pr->tgt_n) continue;
+    int64_t w = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * o->P + pr->port]));
+    uint64_t blk[4] = {0, 0, 0, 0};
+    for (uint32_t k = 0; k < pr->K; ++k, ++n) {
+      uint32_t s, dd;
+      draw_synapse(o, p, t, k, blk, &s, &dd);
+      if (n < cap) { src[n] = s; d[n] = dd; port[n] = pr->port; wq[n] = w; }
+    }
+  }
+  return (int64_t)n;
+}
+
+static uint32_t spike_mult(uint64_t n_spk, const uint64_t* st, const uint32_t* gid, const uint32_t* mult,
+                           uint64_t step, uint32_t g) {
+  uint64_t lo = 0, hi = n_spk;  /* first entry >= (step, g) */
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (st[mid] < step || (st[mid] == step && gid[mid] < g)) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < n_spk && st[lo] == step && gid[lo] == g) ? mult[lo] : 0;
+}
+
+int orc_sampled_input(orc_net* o, uint32_t nt, const uint32_t* tgt, uint64_t n_spk, const uint64_t* step,
+                      const uint32_t* gid, const uint32_t* mult, uint64_t target_step, int64_t* out) {
+  if (prepare(o) != 0) return -1;
+  for (uint64_t i = 1; i < n_spk; ++i)
+    if (step[i] < step[i - 1] || (step[i] == step[i - 1] && gid[i] <= gid[i - 1])) {
+      set_err(o, "spikes not sorted by (step, gid)"); return -1;
+    }
+  uint32_t P = o->P;
+  for (uint32_t j = 0; j < nt; ++j) {
+    uint32_t t = tgt[j];
+    if (t >= o->N) { set_err(o, "target out of range"); return -1; }
+    for (uint32_t q = 0; q < P; ++q) out[(size_t)j * P + q] = 0;
+    for (uint32_t p = 0; p < o->n_proj; ++p) {
+      const orc_proj* pr = &o->proj[p];
+      if (t < pr->tgt_first || t - pr->tgt_first >= pr->tgt_n) continue;
+      int64_t w = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * P + pr->port]));
+      uint64_t blk[4] = {0, 0, 0, 0};
+      for (uint32_t k = 0; k < pr->K; ++k) {
+        uint32_t s, d;
+        draw_synapse(o, p, t, k, blk, &s, &d);
+        if (target_step < d) continue;
+        out[(size_t)j * P + pr->port] += (int64_t)spike_mult(n_spk, step, gid, mult, target_step - d, s) * w;
+      }
+    }
+  }
   return 0;
 }
 
@@ -875,6 +956,6 @@ void orc_get_synapses(const orc_net* o, uint32_t* src, uint32_t* delay, uint32_t
 }
 
 int orc_shift_of(const orc_net* o, uint32_t gid, uint32_t port) {
-  if (!o->built || gid >= o->N || port >= o->P) return -1000;
+  if (!o->shift || gid >= o->N || port >= o->P) return -1000;
   return o->shift[o->pop_of[gid] * o->P + port];
 }

@@ -105,6 +105,19 @@ int      orc_record_input(orc_net*, int64_t* buf, uint64_t max_steps);
 int      orc_replay_input(const orc_net*, uint64_t n_spk, const uint64_t* step, const uint32_t* gid,
                           const uint32_t* mult, uint64_t target_step, int64_t* out);
 
+/* ---- sampled checks at sizes where the synapse table does not fit ---- */
+/* State, Poisson drive and fixed-point exponents without the synapse table
+   (orc_shift_of, orc_poisson_count and the two calls below then work). */
+int      orc_prepare(orc_net*);
+/* Synapses onto target t (projection order, then draw index): up to cap of
+   them into the arrays; returns how many there are, -1 on error. */
+int64_t  orc_target_synapses(orc_net*, uint32_t t, uint64_t cap, uint32_t* src, uint32_t* delay, uint32_t* port,
+                             int64_t* wq);
+/* Input delivered to targets tgt[0..nt) at target_step by the spikes given
+   (sorted by (step, gid)): out[j*P + port]. */
+int      orc_sampled_input(orc_net*, uint32_t nt, const uint32_t* tgt, uint64_t n_spk, const uint64_t* step,
+                           const uint32_t* gid, const uint32_t* mult, uint64_t target_step, int64_t* out);
+
 /* ---- single-neuron update steps, exposed for the pins ---- */
 /* LIF: y = V - E_L.  x[] = converted input per port.  Returns 1 on spike. */
 int orc_lif_delta_step64(const orc_pop_params*, double dt, double* y, int32_t* refr, double I_e, double x);
