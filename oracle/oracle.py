@@ -187,6 +187,15 @@ def adex_rhs(params: PopParams, I_e: float, y) -> np.ndarray:
     return dy
 
 
+def lif_delta_step32(params: PopParams, dt: float, y: float, refr: int, I_e: float, x: float):
+    """One step of the fp32 same-operation-order LIF-delta update.  Returns
+    (y, refr, spiked) with y = V - E_L."""
+    yy = C.c_float(y)
+    rr = C.c_int32(refr)
+    s = lib().orc_lif_delta_step32(C.byref(params), dt, C.byref(yy), C.byref(rr), C.c_float(I_e), C.c_float(x))
+    return yy.value, rr.value, int(s)
+
+
 def lif_exp_step32(params: PopParams, dt: float, y: float, I, refr: int, I_e: float, x):
     """One step of the fp32 same-operation-order LIF-exp update.  Returns
     (y, I, refr, spiked) with y = V - E_L."""

@@ -14,7 +14,10 @@ outputs the oracle computes one by one (its synapse table would not fit):
 Workloads: the 77,169-neuron microcircuit stand-in (3.0e8 synapses, direct
 delivery with 128 delivery blocks), the 10^6-neuron AdEx network with
 exponential ports and the 10^6-neuron alpha-port network of Table 1 (10^9
-synapses each, binned delivery, 2048-neuron tiles, 512 delivery blocks)."""
+synapses each, binned delivery, 2048-neuron tiles, 512 delivery blocks), and
+the batched sweep of 128 Brunel instances (3.0e6 neurons, 8.7e9 synapses,
+binned, 4096-neuron tiles), checked instance by instance against the oracle
+of that instance alone."""
 import sys
 
 import numpy as np
@@ -174,3 +177,48 @@ def pois_of(spec, k):
             return q
     return None
 
+
+
+def test_sweep_128_instances_sampled(snn):
+    """Eight of the 128 batched instances (smallest, largest and six more):
+    sampled delivered inputs bit-exact against each instance's own oracle
+    from the instance's spikes, and one LIF-delta update of sampled neurons
+    bit-exact."""
+    specs = [W.brunel_sweep_instance(i) for i in range(128)]
+    g = snn.Net(specs, delivery="binned", tile_neurons=4096)
+    g.simulate(120)
+    step = g.counters()["steps"]
+    st, gid, m = g.spikes(0, step)
+    sizes = [W.total_neurons(sp) for sp in specs]
+    firsts = np.cumsum([0] + sizes)[:-1]
+    pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 3, 17, 40, 64, 90, 127})
+    acc = g.get_input(0)
+    V0, R0, Ie = g.get_state("V_m"), g.get_state("refr"), g.get_state("I_e")
+    g.simulate(1)
+    V1, R1 = g.get_state("V_m"), g.get_state("refr")
+    _, sp_gid, _ = g.spikes(step, step + 1)
+    spiked = set(sp_gid.tolist())
+    rng = np.random.default_rng(11)
+    total_nonzero = 0
+    for i in pick:
+        sp, f, n = specs[i], int(firsts[i]), sizes[i]
+        o = O.OracleNet(sp, build=False)
+        sel = (gid >= f) & (gid < f + n)
+        loc = np.sort(rng.choice(n, size=min(n, 150), replace=False))
+        ref = o.sampled_input(loc, st[sel], gid[sel] - f, m[sel], step)[:, 0]
+        assert np.array_equal(acc[f + loc], ref), (i, step)
+        total_nonzero += int(np.count_nonzero(ref))
+        bounds, params = pop_of(sp)
+        q = sp["poisson"][0]
+        for j in loc:
+            k = int(np.searchsorted(bounds, j, side="right") - 1)
+            S = o.shift_of(int(j), 0)
+            xin = int(acc[f + j]) + o.poisson_count(int(j), step) * int(np.rint(np.ldexp(q["weight"], S)))
+            x = np.float32(xin) * np.float32(2.0 ** -S)
+            E_L = sp["populations"][k]["params"]["E_L"]
+            y, r, s = O.lif_delta_step32(params[k], sp["dt"], float(np.float32(V0[f + j] - E_L)), int(R0[f + j]),
+                                         float(np.float32(Ie[f + j])), float(x))
+            assert np.float32(V1[f + j] - E_L) == np.float32(y), (i, j)
+            assert int(R1[f + j]) == r and ((f + int(j)) in spiked) == bool(s), (i, j)
+    assert total_nonzero > 20, total_nonzero
+    g.close()
