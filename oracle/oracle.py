@@ -21,6 +21,9 @@ MODEL_IDS = {"lif_delta": LIF_DELTA, "lif_exp": LIF_EXP, "aeif_cond_exp": AEIF_C
              "aeif_cond_beta": AEIF_COND_BETA}
 DELAY_IDS = {"const": 0, "uniform": 1, "normal": 2}
 VAR_IDS = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6, "g_rise": 7}
+# connection rules; a projection's "K" is the in-degree, the out-degree or the
+# number of synapses (unused for all_to_all and one_to_one)
+RULE_IDS = {"fixed_indegree": 0, "fixed_outdegree": 1, "all_to_all": 2, "one_to_one": 3, "fixed_total_number": 4}
 MAX_PORTS = 4
 POISSON_KMAX = 128
 
@@ -68,6 +71,8 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_population.restype = C.c_int64
         L.orc_population.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(PopParams)]
+        L.orc_connect.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                  C.c_double, C.c_int, C.c_double, C.c_double, C.c_uint32]
         L.orc_connect_fixed_indegree.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                                  C.c_uint32, C.c_double, C.c_int, C.c_double, C.c_double,
                                                  C.c_uint32]
@@ -246,8 +251,9 @@ class OracleNet:
             s0, sn = self.ranges[pr["src"]]
             t0, tn = self.ranges[pr["tgt"]]
             kind, a, b = (list(pr["delay"]) + [0.0, 0.0])[:3]
-            self._check(self.L.orc_connect_fixed_indegree(self.h, s0, sn, t0, tn, pr["K"], pr["weight"],
-                                                          DELAY_IDS[kind], a, b, pr["port"]) == 0)
+            rule = RULE_IDS[pr.get("rule", "fixed_indegree")]
+            self._check(self.L.orc_connect(self.h, rule, int(pr.get("K", 0)), s0, sn, t0, tn, pr["weight"],
+                                           DELAY_IDS[kind], a, b, pr["port"]) == 0)
         for q in spec.get("poisson", []):
             t0, tn = self.ranges[q["tgt"]]
             self._check(self.L.orc_poisson(self.h, t0, tn, q["rate"], q["n_inputs"], q["weight"],

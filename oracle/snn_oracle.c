@@ -129,6 +129,8 @@ int orc_fixed_point_shift(double max_abs_w) {
 /* ------------------------------------------------------------------------ */
 typedef struct {
   uint32_t src_first, src_n, tgt_first, tgt_n, K, port;
+  int rule;
+  uint64_t n;     /* the rule's count (in-degree, out-degree, synapses) */
   double weight;
   uint64_t dthr[64];
 } orc_proj;
@@ -234,21 +236,53 @@ static uint32_t pop_index(const orc_net* o, uint32_t gid) {
   return k;
 }
 
-int orc_connect_fixed_indegree(orc_net* o, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
-                               uint32_t tgt_n, uint32_t indegree, double weight, int delay_kind,
-                               double da, double db, uint32_t port) {
+/* Connection rules (Sec. 2.1), autapses and multapses allowed:
+   fixed in-degree  -- every target draws n sources uniformly;
+   fixed out-degree -- every source draws n targets uniformly;
+   all-to-all       -- every (source, target) pair once;
+   one-to-one       -- source first + i onto target first + i (equal sizes);
+   fixed total      -- n synapses, source and target each drawn uniformly.
+   Every synapse draws its delay from the projection's table. */
+int orc_connect(orc_net* o, int rule, uint64_t n, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
+                uint32_t tgt_n, double weight, int delay_kind, double da, double db, uint32_t port) {
   if (o->built || o->shift) { set_err(o, "connect after build"); return -1; }
   if ((uint64_t)src_first + src_n > o->N || (uint64_t)tgt_first + tgt_n > o->N || src_n == 0) {
     set_err(o, "range"); return -1;
   }
+  if (rule < ORC_RULE_FIXED_INDEGREE || rule > ORC_RULE_FIXED_TOTAL_NUMBER) { set_err(o, "rule"); return -1; }
+  if (rule == ORC_RULE_ONE_TO_ONE && src_n != tgt_n) { set_err(o, "one-to-one needs equal sizes"); return -1; }
+  if ((rule == ORC_RULE_FIXED_INDEGREE || rule == ORC_RULE_FIXED_OUTDEGREE) && n > 0xffffffffull) {
+    set_err(o, "degree"); return -1;
+  }
+  if (rule == ORC_RULE_FIXED_TOTAL_NUMBER && tgt_n == 0 && n) { set_err(o, "range"); return -1; }
   orc_proj pr;
   memset(&pr, 0, sizeof pr);
   pr.src_first = src_first; pr.src_n = src_n; pr.tgt_first = tgt_first; pr.tgt_n = tgt_n;
-  pr.K = indegree; pr.port = port; pr.weight = weight;
+  pr.rule = rule; pr.n = n; pr.port = port; pr.weight = weight;
+  pr.K = (rule == ORC_RULE_FIXED_INDEGREE || rule == ORC_RULE_FIXED_OUTDEGREE) ? (uint32_t)n
+       : (rule == ORC_RULE_ALL_TO_ALL) ? src_n : (rule == ORC_RULE_ONE_TO_ONE) ? 1u : 0u;
   if (orc_delay_table(delay_kind, da, db, o->dt, o->dmax, pr.dthr) != 0) { set_err(o, "delay"); return -1; }
   o->proj = (orc_proj*)realloc(o->proj, (o->n_proj + 1) * sizeof(orc_proj));
   o->proj[o->n_proj++] = pr;
   return 0;
+}
+
+/* synapses the projection makes */
+static uint64_t proj_synapses(const orc_proj* pr) {
+  switch (pr->rule) {
+    case ORC_RULE_FIXED_INDEGREE: return (uint64_t)pr->K * pr->tgt_n;
+    case ORC_RULE_FIXED_OUTDEGREE: return pr->tgt_n ? (uint64_t)pr->K * pr->src_n : 0;
+    case ORC_RULE_ALL_TO_ALL: return (uint64_t)pr->src_n * pr->tgt_n;
+    case ORC_RULE_ONE_TO_ONE: return pr->tgt_n;
+    default: return pr->tgt_n ? pr->n : 0;
+  }
+}
+
+int orc_connect_fixed_indegree(orc_net* o, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
+                               uint32_t tgt_n, uint32_t indegree, double weight, int delay_kind,
+                               double da, double db, uint32_t port) {
+  return orc_connect(o, ORC_RULE_FIXED_INDEGREE, indegree, src_first, src_n, tgt_first, tgt_n, weight, delay_kind,
+                     da, db, port);
 }
 
 int orc_poisson(orc_net* o, uint32_t tgt_first, uint32_t tgt_n, double rate_hz, uint32_t n_inputs,
@@ -386,7 +420,7 @@ static int prepare(orc_net* o) {
   double* maxw = (double*)calloc((size_t)o->n_pops * P, sizeof(double));
   for (uint32_t p = 0; p < o->n_proj; ++p) {
     const orc_proj* pr = &o->proj[p];
-    if (pr->K == 0 || pr->tgt_n == 0) continue;
+    if (proj_synapses(pr) == 0) continue;
     for (uint32_t k = 0; k < o->n_pops; ++k) {
       uint32_t lo = o->pop_first[k];
       uint32_t hi = (k + 1 < o->n_pops) ? o->pop_first[k + 1] : o->N;
@@ -414,23 +448,49 @@ static int prepare(orc_net* o) {
   return 0;
 }
 
-/* fixed-indegree rule: for target t of projection p and k < K, one Philox
-   block per pair of synapses: counter (t, p<<40 | k>>1, CONN, 0), key
-   (seed, 0); synapse k uses words 2(k&1) (source) and 2(k&1)+1 (delay).
-   source = first + floor(u64 * n_src / 2^64); autapses and multapses kept.
-   blk holds the block of the pair k belongs to (drawn when k is even). */
-static void draw_synapse(const orc_net* o, uint32_t p, uint32_t t, uint32_t k, uint64_t blk[4], uint32_t* src,
-                         uint32_t* d) {
+/* Counters of the connection draws, key (seed, 0), tag CONN; p is the
+   projection's creation index, x << y a shift:
+   fixed in-degree  -- target t, draw k < n: block (t, p<<40 | k>>1), words
+                       2(k&1) (source) and 2(k&1)+1 (delay);
+   fixed out-degree -- source s, draw k < n: block (s, p<<40 | k>>1), words
+                       2(k&1) (target) and 2(k&1)+1 (delay);
+   all-to-all       -- target t, source index k: block (t, p<<40 | k>>1),
+                       word 2(k&1)+1 (delay);
+   one-to-one       -- target t: block (t, p<<40), word 1 (delay);
+   fixed total      -- synapse j < n: block (j, p<<40), words 0 (source),
+                       1 (target), 2 (delay).
+   A uniform index in a range of m is floor(u m / 2^64); a delay uses the top
+   32 bits of its word against the projection's threshold table. */
+static uint32_t uniform_index(uint64_t u, uint32_t m) { return (uint32_t)(((unsigned __int128)u * m) >> 64); }
+
+/* synapse k of entity e (target, source or synapse index, by rule) of
+   projection p; blk holds the block of the pair k belongs to */
+static void draw_synapse(const orc_net* o, uint32_t p, uint64_t e, uint32_t k, uint64_t blk[4], uint32_t* src,
+                         uint32_t* tgt, uint32_t* d) {
   const orc_proj* pr = &o->proj[p];
+  uint64_t key[2] = {o->seed, 0};
+  if (pr->rule == ORC_RULE_ONE_TO_ONE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER) {
+    uint64_t ctr[4] = {e, (uint64_t)p << 40, ORC_TAG_CONN, 0};
+    orc_philox4x64_10(ctr, key, blk);
+    if (pr->rule == ORC_RULE_ONE_TO_ONE) {
+      *tgt = (uint32_t)e; *src = pr->src_first + ((uint32_t)e - pr->tgt_first);
+      *d = draw_delay(pr->dthr, o->dmax, (uint32_t)(blk[1] >> 32));
+    } else {
+      *src = pr->src_first + uniform_index(blk[0], pr->src_n);
+      *tgt = pr->tgt_first + uniform_index(blk[1], pr->tgt_n);
+      *d = draw_delay(pr->dthr, o->dmax, (uint32_t)(blk[2] >> 32));
+    }
+    return;
+  }
   if ((k & 1u) == 0) {
-    uint64_t ctr[4] = {t, ((uint64_t)p << 40) | (uint64_t)(k >> 1), ORC_TAG_CONN, 0};
-    uint64_t key[2] = {o->seed, 0};
+    uint64_t ctr[4] = {e, ((uint64_t)p << 40) | (uint64_t)(k >> 1), ORC_TAG_CONN, 0};
     orc_philox4x64_10(ctr, key, blk);
   }
-  uint64_t us = blk[2 * (k & 1u)];
-  uint64_t ud = blk[2 * (k & 1u) + 1];
-  *src = pr->src_first + (uint32_t)(((unsigned __int128)us * pr->src_n) >> 64);
-  *d = draw_delay(pr->dthr, o->dmax, (uint32_t)(ud >> 32));
+  uint64_t u = blk[2 * (k & 1u)];
+  *d = draw_delay(pr->dthr, o->dmax, (uint32_t)(blk[2 * (k & 1u) + 1] >> 32));
+  if (pr->rule == ORC_RULE_FIXED_INDEGREE) { *tgt = (uint32_t)e; *src = pr->src_first + uniform_index(u, pr->src_n); }
+  else if (pr->rule == ORC_RULE_FIXED_OUTDEGREE) { *src = (uint32_t)e; *tgt = pr->tgt_first + uniform_index(u, pr->tgt_n); }
+  else { *tgt = (uint32_t)e; *src = pr->src_first + k; }  /* all-to-all */
 }
 
 int orc_prepare(orc_net* o) { return prepare(o); }
@@ -440,23 +500,28 @@ int orc_build(orc_net* o) {
   if (prepare(o) != 0) return -1;
   uint32_t P = o->P, D1 = o->dmax + 1;
   uint64_t total = 0;
-  for (uint32_t p = 0; p < o->n_proj; ++p) total += (uint64_t)o->proj[p].K * o->proj[p].tgt_n;
+  for (uint32_t p = 0; p < o->n_proj; ++p) total += proj_synapses(&o->proj[p]);
   o->n_syn = total;
   o->syn = (orc_syn*)malloc((total ? total : 1) * sizeof(orc_syn));
   uint64_t pos = 0;
   for (uint32_t p = 0; p < o->n_proj; ++p) {
     const orc_proj* pr = &o->proj[p];
-    for (uint32_t j = 0; j < pr->tgt_n; ++j) {
-      uint32_t t = pr->tgt_first + j;
-      uint32_t tp = o->pop_of[t];
-      int S = o->shift[tp * P + pr->port];
-      int64_t wq = llrint(ldexp(pr->weight, S));
+    if (proj_synapses(pr) == 0) continue;
+    /* entities: targets, sources (out-degree) or synapses (total number);
+       draws per entity: n, n, n_src, 1, 1 */
+    uint64_t ne = pr->rule == ORC_RULE_FIXED_OUTDEGREE ? pr->src_n
+                : pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER ? pr->n : pr->tgt_n;
+    uint64_t first = pr->rule == ORC_RULE_FIXED_OUTDEGREE ? pr->src_first
+                   : pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER ? 0 : pr->tgt_first;
+    uint32_t kn = pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER ? 1u : pr->K;
+    for (uint64_t j = 0; j < ne; ++j) {
       uint64_t blk[4] = {0, 0, 0, 0};
-      for (uint32_t k = 0; k < pr->K; ++k) {
-        uint32_t s, d;
-        draw_synapse(o, p, t, k, blk, &s, &d);
+      for (uint32_t k = 0; k < kn; ++k) {
+        uint32_t s, t, d;
+        draw_synapse(o, p, first + j, k, blk, &s, &t, &d);
         orc_syn sy;
-        sy.src = s; sy.tgt = t; sy.port = (uint8_t)pr->port; sy.wq = wq; sy.d = (uint8_t)d;
+        sy.src = s; sy.tgt = t; sy.port = (uint8_t)pr->port; sy.d = (uint8_t)d;
+        sy.wq = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * P + pr->port]));
         o->syn[pos++] = sy;
       }
     }
@@ -807,12 +872,15 @@ int64_t orc_target_synapses(orc_net* o, uint32_t t, uint64_t cap, uint32_t* src,
   uint64_t n = 0;
   for (uint32_t p = 0; p < o->n_proj; ++p) {
     const orc_proj* pr = &o->proj[p];
-    if (t < pr->tgt_first || t - pr->tgt_first >= pr->tgt_n) continue;
+    if (t < pr->tgt_first || t - pr->tgt_first >= pr->tgt_n || proj_synapses(pr) == 0) continue;
+    if (pr->rule == ORC_RULE_FIXED_OUTDEGREE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER) {
+      set_err(o, "the rule does not draw per target"); return -1;
+    }
     int64_t w = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * o->P + pr->port]));
     uint64_t blk[4] = {0, 0, 0, 0};
     for (uint32_t k = 0; k < pr->K; ++k, ++n) {
-      uint32_t s, dd;
-      draw_synapse(o, p, t, k, blk, &s, &dd);
+      uint32_t s, tt, dd;
+      draw_synapse(o, p, t, k, blk, &s, &tt, &dd);
       if (n < cap) { src[n] = s; d[n] = dd; port[n] = pr->port; wq[n] = w; }
     }
   }
@@ -844,12 +912,15 @@ int orc_sampled_input(orc_net* o, uint32_t nt, const uint32_t* tgt, uint64_t n_s
     for (uint32_t q = 0; q < P; ++q) out[(size_t)j * P + q] = 0;
     for (uint32_t p = 0; p < o->n_proj; ++p) {
       const orc_proj* pr = &o->proj[p];
-      if (t < pr->tgt_first || t - pr->tgt_first >= pr->tgt_n) continue;
+      if (t < pr->tgt_first || t - pr->tgt_first >= pr->tgt_n || proj_synapses(pr) == 0) continue;
+      if (pr->rule == ORC_RULE_FIXED_OUTDEGREE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER) {
+        set_err(o, "the rule does not draw per target"); return -1;
+      }
       int64_t w = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * P + pr->port]));
       uint64_t blk[4] = {0, 0, 0, 0};
       for (uint32_t k = 0; k < pr->K; ++k) {
-        uint32_t s, d;
-        draw_synapse(o, p, t, k, blk, &s, &d);
+        uint32_t s, tt, d;
+        draw_synapse(o, p, t, k, blk, &s, &tt, &d);
         if (target_step < d) continue;
         out[(size_t)j * P + pr->port] += (int64_t)spike_mult(n_spk, step, gid, mult, target_step - d, s) * w;
       }

@@ -31,6 +31,10 @@ enum { ORC_FP64 = 0, ORC_FP32SO = 1 };
 enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2, ORC_AEIF_COND_BETA = 3 };
 enum { ORC_DELAY_CONST = 0, ORC_DELAY_UNIFORM = 1, ORC_DELAY_NORMAL_CLIPPED = 2 };
 enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2 };
+/* connection rules (Sec. 2.1): the count n is the in-degree, the out-degree,
+   unused, unused, and the number of synapses, in that order */
+enum { ORC_RULE_FIXED_INDEGREE = 0, ORC_RULE_FIXED_OUTDEGREE = 1, ORC_RULE_ALL_TO_ALL = 2,
+       ORC_RULE_ONE_TO_ONE = 3, ORC_RULE_FIXED_TOTAL_NUMBER = 4 };
 enum { ORC_MAX_PORTS = 4, ORC_POISSON_KMAX = 128 };
 
 /* Neuron-model parameters of one population (double, NEST units). */
@@ -70,6 +74,10 @@ int      orc_connect_fixed_indegree(orc_net*, uint32_t src_first, uint32_t src_n
                                     uint32_t tgt_first, uint32_t tgt_n, uint32_t indegree,
                                     double weight, int delay_kind, double da, double db,
                                     uint32_t port);
+/* any rule; fixed in-degree is rule 0 with n = the in-degree */
+int      orc_connect(orc_net*, int rule, uint64_t n, uint32_t src_first, uint32_t src_n,
+                     uint32_t tgt_first, uint32_t tgt_n, double weight, int delay_kind, double da,
+                     double db, uint32_t port);
 int      orc_poisson(orc_net*, uint32_t tgt_first, uint32_t tgt_n, double rate_hz,
                      uint32_t n_inputs, double weight, uint32_t port);
 /* state variables (per neuron).  var: 0 V_m (mV), 1 I_e (pA), 2 w (pA),
@@ -110,7 +118,9 @@ int      orc_replay_input(const orc_net*, uint64_t n_spk, const uint64_t* step, 
    (orc_shift_of, orc_poisson_count and the two calls below then work). */
 int      orc_prepare(orc_net*);
 /* Synapses onto target t (projection order, then draw index): up to cap of
-   them into the arrays; returns how many there are, -1 on error. */
+   them into the arrays; returns how many there are, -1 on error (also when a
+   projection onto t draws per source or per synapse: fixed out-degree, fixed
+   total number). */
 int64_t  orc_target_synapses(orc_net*, uint32_t t, uint64_t cap, uint32_t* src, uint32_t* delay, uint32_t* port,
                              int64_t* wq);
 /* Input delivered to targets tgt[0..nt) at target_step by the spikes given
