@@ -200,6 +200,30 @@ snn_status snn_set_port_param(snn_net* net, uint32_t first, uint32_t n, uint32_t
 snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
                                       uint32_t tgt_n, uint32_t indegree, double weight, int32_t delay_kind,
                                       double delay_a, double delay_b, uint32_t port);
+/* Connection rules (Sec. 2.1), each with weight `weight`, receptor `port`
+   and a delay per synapse drawn from the given distribution; autapses and
+   multapses allowed:
+     SNN_RULE_FIXED_INDEGREE     every target draws n sources uniformly (as
+                                 snn_connect_fixed_indegree);
+     SNN_RULE_FIXED_OUTDEGREE    every source draws n targets uniformly;
+     SNN_RULE_ALL_TO_ALL         every (source, target) pair once (n unused);
+     SNN_RULE_ONE_TO_ONE         source src_first + i onto target tgt_first + i
+                                 (src_n == tgt_n; n unused);
+     SNN_RULE_FIXED_TOTAL_NUMBER n synapses, source and target each uniform.
+   Randomness: counter-based (Philox4x64-10, key (seed, 0)), counters
+   (target, p << 40 | k >> 1), (source, p << 40 | k >> 1), (target,
+   p << 40 | k >> 1), (target, p << 40), (synapse index, p << 40) with tag 1,
+   p the projection's creation index and gids counted from the instance's
+   first neuron.  SNN_E_INVALID for an unknown rule, unequal one-to-one sizes
+   or a degree above 2^32 - 1. */
+#define SNN_RULE_FIXED_INDEGREE 0
+#define SNN_RULE_FIXED_OUTDEGREE 1
+#define SNN_RULE_ALL_TO_ALL 2
+#define SNN_RULE_ONE_TO_ONE 3
+#define SNN_RULE_FIXED_TOTAL_NUMBER 4
+snn_status snn_connect(snn_net* net, int32_t rule, uint64_t n, uint32_t src_first, uint32_t src_n,
+                       uint32_t tgt_first, uint32_t tgt_n, double weight, int32_t delay_kind, double delay_a,
+                       double delay_b, uint32_t port);
 /* Poisson generator (Sec. 2.1, Table 1): every target in the range receives,
    independently, the summed spikes of n_inputs trains of rate_hz each, with
    weight `weight` on `port`, drawn per target and step.  At most one drive per

@@ -1,12 +1,19 @@
 // kernels_build.hip -- on-device connectivity build (the paper keeps this on
 // the host and names building it on the GPU as future work, Sec. 4).
 //
-// Fixed-indegree rule (Sec. 2.1): target t of projection p draws K sources
-// uniformly with replacement; one Philox4x64-10 block per pair of draws,
-// counter (t, p << 40 | k >> 1, CONN, 0), key (seed, 0), with t and p counted
-// inside the projection's instance and seed the instance's; draw k uses words
-// 2(k&1) (source: first + floor(u n_src / 2^64)) and 2(k&1)+1 (delay: top 32
-// bits against the projection's threshold table).
+// Connection rules (Sec. 2.1), one Philox4x64-10 block per work item, key
+// (seed, 0), tag CONN, gids and p counted inside the projection's instance:
+//   fixed in-degree  -- target t draws K sources: block (t, p << 40 | k >> 1),
+//                       words 2(k&1) (source) and 2(k&1)+1 (delay);
+//   fixed out-degree -- source s draws K targets: block (s, p << 40 | k >> 1),
+//                       words 2(k&1) (target) and 2(k&1)+1 (delay);
+//   all-to-all       -- target t, source index k: block (t, p << 40 | k >> 1),
+//                       word 2(k&1)+1 (delay);
+//   one-to-one       -- target t: block (t, p << 40), word 1 (delay);
+//   fixed total      -- synapse j: block (j, p << 40), words 0 (source),
+//                       1 (target), 2 (delay).
+// A uniform index in a range of m is floor(u m / 2^64); a delay is the top 32
+// bits of its word against the projection's threshold table.
 //
 // Layout (Sec. 2.2, Fig. 1): synapses grouped per source into connection
 // groups of equal delay, groups ordered by delay.  Build = counting sort by
@@ -50,6 +57,10 @@ __device__ __forceinline__ uint32_t find_pop(const uint32_t* pop_first, uint32_t
   return lo;
 }
 
+// The synapse draw of work item q (Sec. 2.1 rules; counter layout in the
+// header comment of the library): entity e and pair kp of projection p, up to
+// two synapses, each counted (histogram) or scattered into its (source,
+// delay) bucket.
 template <bool kScatter>
 __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, uint32_t nproj, uint64_t total_pairs,
                                              uint32_t dmax_cfg, uint32_t D1, uint32_t* cnt,
@@ -60,22 +71,51 @@ __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, u
     const uint32_t p = find_proj(projs, nproj, q);
     const ProjDev& pr = projs[p];
     const uint64_t local = q - pr.pair_begin;
-    const uint64_t tl = local / pr.kpairs;
-    const uint32_t kp = (uint32_t)(local - tl * pr.kpairs);
-    const uint32_t tgt = pr.tgt_first + (uint32_t)tl;
-    const U64x4 blk = philox4x64_10(tgt - pr.gid_base, ((uint64_t)pr.index << 40) | kp, kTagConn, 0, pr.seed, 0);
-    uint32_t cls = 0;
-    if (kScatter) cls = cls_of[(size_t)p * npop + find_pop(pop_first, npop, tgt)];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    const uint64_t e = local / pr.kpairs;
+    const uint32_t kp = (uint32_t)(local - e * pr.kpairs);
+    // entity gid (instance-local in the counter): target, source, or none
+    const uint32_t ent = pr.rule == kRuleOutDegree ? pr.src_first + (uint32_t)e
+                       : pr.rule == kRuleTotal ? 0u : pr.tgt_first + (uint32_t)e;
+    const uint64_t c0 = pr.rule == kRuleTotal ? e : (uint64_t)(ent - pr.gid_base);
+    const uint64_t c1 = ((uint64_t)pr.index << 40) | kp;
+    const U64x4 blk = philox4x64_10(c0, c1, kTagConn, 0, pr.seed, 0);
+    const int nh = (pr.rule == kRuleOneToOne || pr.rule == kRuleTotal) ? 1 : 2;
+    for (int h = 0; h < nh; ++h) {
       const uint32_t k = 2 * kp + h;
       if (k >= pr.K) break;
-      const uint32_t src = pr.src_first + (uint32_t)__umul64hi(blk.w[2 * h], (uint64_t)pr.src_n);
-      const uint32_t d = draw_delay(pr.thr, dmax_cfg, (uint32_t)(blk.w[2 * h + 1] >> 32));
+      uint32_t src, tgt, d;
+      switch (pr.rule) {
+        case kRuleOutDegree:
+          src = ent;
+          tgt = pr.tgt_first + (uint32_t)__umul64hi(blk.w[2 * h], (uint64_t)pr.tgt_n);
+          d = draw_delay(pr.thr, dmax_cfg, (uint32_t)(blk.w[2 * h + 1] >> 32));
+          break;
+        case kRuleAllToAll:
+          src = pr.src_first + k;
+          tgt = ent;
+          d = draw_delay(pr.thr, dmax_cfg, (uint32_t)(blk.w[2 * h + 1] >> 32));
+          break;
+        case kRuleOneToOne:
+          src = pr.src_first + (uint32_t)e;
+          tgt = ent;
+          d = draw_delay(pr.thr, dmax_cfg, (uint32_t)(blk.w[1] >> 32));
+          break;
+        case kRuleTotal:
+          src = pr.src_first + (uint32_t)__umul64hi(blk.w[0], (uint64_t)pr.src_n);
+          tgt = pr.tgt_first + (uint32_t)__umul64hi(blk.w[1], (uint64_t)pr.tgt_n);
+          d = draw_delay(pr.thr, dmax_cfg, (uint32_t)(blk.w[2] >> 32));
+          break;
+        default:  // fixed in-degree
+          src = pr.src_first + (uint32_t)__umul64hi(blk.w[2 * h], (uint64_t)pr.src_n);
+          tgt = ent;
+          d = draw_delay(pr.thr, dmax_cfg, (uint32_t)(blk.w[2 * h + 1] >> 32));
+          break;
+      }
       const uint64_t bucket = (uint64_t)src * D1 + d;
       if (!kScatter) {
         atomicAdd(&cnt[bucket], 1u);
       } else {
+        const uint32_t cls = cls_of[(size_t)p * npop + find_pop(pop_first, npop, tgt)];
         const unsigned long long slot = atomicAdd(&cursor[bucket], 1ull);
         payload[slot] = (tgt << cls_bits) | cls;
       }

@@ -47,11 +47,33 @@ struct HostPop {
 };
 
 struct HostProj {
-  uint32_t src_first, src_n, tgt_first, tgt_n, K, port;
+  uint32_t src_first, src_n, tgt_first, tgt_n;
+  uint32_t K;      // draws per entity: in-degree, out-degree, n_src (all-to-all), 1 (one-to-one, total)
+  uint32_t port;
   uint32_t inst, local;  // instance and creation index within it
   double weight;
   int32_t kind;
   double da, db;
+  int32_t rule = SNN_RULE_FIXED_INDEGREE;
+  uint64_t n = 0;  // the rule's count (fixed total number: synapses)
+  // synapses the projection makes
+  uint64_t synapses() const {
+    switch (rule) {
+      case SNN_RULE_FIXED_OUTDEGREE: return tgt_n ? (uint64_t)K * src_n : 0;
+      case SNN_RULE_FIXED_TOTAL_NUMBER: return tgt_n ? n : 0;
+      default: return (uint64_t)K * tgt_n;
+    }
+  }
+  // work-item entities: sources (out-degree), synapses (total) or targets
+  uint64_t entities() const {
+    return rule == SNN_RULE_FIXED_OUTDEGREE ? src_n : rule == SNN_RULE_FIXED_TOTAL_NUMBER ? n : tgt_n;
+  }
+  // synapses onto a target: exact for the rules drawn per target, the mean otherwise
+  double per_target() const {
+    if (rule == SNN_RULE_FIXED_OUTDEGREE) return tgt_n ? (double)K * src_n / tgt_n : 0.0;
+    if (rule == SNN_RULE_FIXED_TOTAL_NUMBER) return tgt_n ? (double)n / tgt_n : 0.0;
+    return (double)K;
+  }
 };
 
 struct HostPois {
@@ -508,9 +530,9 @@ snn_status snn_set_port_param(snn_net* net, uint32_t first, uint32_t n, uint32_t
   return SNN_OK;
 }
 
-snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
-                                      uint32_t tgt_n, uint32_t indegree, double weight, int32_t delay_kind,
-                                      double delay_a, double delay_b, uint32_t port) {
+snn_status snn_connect(snn_net* net, int32_t rule, uint64_t n, uint32_t src_first, uint32_t src_n,
+                       uint32_t tgt_first, uint32_t tgt_n, double weight, int32_t delay_kind, double delay_a,
+                       double delay_b, uint32_t port) {
   if (!net) return SNN_E_INVALID;
   net->err.clear();
   if (net->built) return fail(net, SNN_E_STATE, "connect after snn_build");
@@ -521,6 +543,11 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
   if (delay_kind == SNN_DELAY_UNIFORM && !(delay_b > delay_a)) return fail(net, SNN_E_INVALID, "uniform delay needs b > a");
   if (delay_kind == SNN_DELAY_NORMAL_CLIPPED && !(delay_b > 0)) return fail(net, SNN_E_INVALID, "normal delay needs sd > 0");
   if (!std::isfinite(weight)) return fail(net, SNN_E_INVALID, "weight must be finite");
+  if (rule < SNN_RULE_FIXED_INDEGREE || rule > SNN_RULE_FIXED_TOTAL_NUMBER)
+    return fail(net, SNN_E_INVALID, "unknown connection rule %d", rule);
+  if (rule == SNN_RULE_ONE_TO_ONE && src_n != tgt_n) return fail(net, SNN_E_INVALID, "one-to-one needs src_n == tgt_n");
+  if ((rule == SNN_RULE_FIXED_INDEGREE || rule == SNN_RULE_FIXED_OUTDEGREE) && n > 0xffffffffull)
+    return fail(net, SNN_E_INVALID, "degree above 2^32 - 1");
   const uint32_t inst = net->pops[pop_of(net, src_first)].inst;
   for (uint32_t t = src_first; t < src_first + src_n;) {
     const HostPop& pp = net->pops[pop_of(net, t)];
@@ -535,9 +562,18 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
     t = pp.first + pp.n;
   }
   if (net->projs.size() >= (1u << 23)) return fail(net, SNN_E_UNSUPPORTED, "too many projections");
-  net->projs.push_back({src_first, src_n, tgt_first, tgt_n, indegree, port, inst, net->insts[inst].n_proj++, weight,
-                        delay_kind, delay_a, delay_b});
+  const uint32_t K = (rule == SNN_RULE_FIXED_INDEGREE || rule == SNN_RULE_FIXED_OUTDEGREE) ? (uint32_t)n
+                   : rule == SNN_RULE_ALL_TO_ALL ? src_n : 1u;
+  net->projs.push_back({src_first, src_n, tgt_first, tgt_n, K, port, inst, net->insts[inst].n_proj++, weight,
+                        delay_kind, delay_a, delay_b, rule, n});
   return SNN_OK;
+}
+
+snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
+                                      uint32_t tgt_n, uint32_t indegree, double weight, int32_t delay_kind,
+                                      double delay_a, double delay_b, uint32_t port) {
+  return snn_connect(net, SNN_RULE_FIXED_INDEGREE, indegree, src_first, src_n, tgt_first, tgt_n, weight, delay_kind,
+                     delay_a, delay_b, port);
 }
 
 snn_status snn_poisson(snn_net* net, uint32_t tgt_first, uint32_t tgt_n, double rate_hz, uint32_t n_inputs,
@@ -721,7 +757,7 @@ snn_status snn_build(snn_net* net) {
     return n > 0 && first < p.first + p.n && first + n > p.first;
   };
   for (const HostProj& pr : net->projs) {
-    if (pr.K == 0) continue;
+    if (pr.synapses() == 0) continue;
     for (uint32_t k = 0; k < npop; ++k)
       if (overlaps(k, pr.tgt_first, pr.tgt_n)) maxw[k * P + pr.port] = std::max(maxw[k * P + pr.port], fabs(pr.weight));
   }
@@ -736,7 +772,7 @@ snn_status snn_build(snn_net* net) {
   for (size_t p = 0; p < net->projs.size(); ++p) {
     const HostProj& pr = net->projs[p];
     for (uint32_t k = 0; k < npop; ++k) {
-      if (!overlaps(k, pr.tgt_first, pr.tgt_n) || pr.K == 0) continue;
+      if (!overlaps(k, pr.tgt_first, pr.tgt_n) || pr.synapses() == 0) continue;
       const int64_t wq = llrint(ldexp(pr.weight, net->shift[k * P + pr.port]));
       cls_key[p * npop + k] = {pr.port, wq};
       classes[{pr.port, wq}] = 0;
@@ -764,7 +800,7 @@ snn_status snn_build(snn_net* net) {
   std::vector<uint16_t> cls_of((size_t)std::max<size_t>(1, net->projs.size()) * npop, 0);
   for (size_t p = 0; p < net->projs.size(); ++p)
     for (uint32_t k = 0; k < npop; ++k)
-      if (overlaps(k, net->projs[p].tgt_first, net->projs[p].tgt_n) && net->projs[p].K)
+      if (overlaps(k, net->projs[p].tgt_first, net->projs[p].tgt_n) && net->projs[p].synapses())
         cls_of[p * npop + k] = (uint16_t)classes[cls_key[p * npop + k]];
   // projections, delay tables, largest delay present
   const uint32_t dmax_cfg = net->cfg.max_delay_steps;
@@ -776,13 +812,16 @@ snn_status snn_build(snn_net* net) {
     ProjDev& d = pd[p];
     memset(&d, 0, sizeof d);
     d.src_first = pr.src_first; d.src_n = pr.src_n; d.tgt_first = pr.tgt_first; d.tgt_n = pr.tgt_n;
-    d.K = pr.K; d.kpairs = (pr.K + 1) / 2; d.index = pr.local;
+    d.rule = (uint32_t)pr.rule;
+    const bool single = pr.rule == SNN_RULE_ONE_TO_ONE || pr.rule == SNN_RULE_FIXED_TOTAL_NUMBER;
+    d.K = pr.K; d.kpairs = single ? 1u : (pr.K + 1) / 2; d.index = pr.local;
     d.gid_base = net->insts[pr.inst].first_gid; d.seed = net->insts[pr.inst].seed;
     d.pair_begin = total_pairs;
     delay_thresholds(pr.kind, pr.da, pr.db, dt, dmax_cfg, d.thr);
-    total_pairs += (uint64_t)pr.tgt_n * d.kpairs;
-    total_syn += (uint64_t)pr.tgt_n * pr.K;
-    if (pr.K && pr.tgt_n) {
+    const uint64_t syn = pr.synapses();
+    if (syn) total_pairs += pr.entities() * d.kpairs;
+    total_syn += syn;
+    if (syn) {
       uint32_t dm = 1;
       while (dm < dmax_cfg && d.thr[dm] < (1ull << 32)) ++dm;
       dmax_used = std::max(dmax_used, dm);
@@ -994,11 +1033,15 @@ snn_status snn_build(snn_net* net) {
     const uint64_t nt = ((uint64_t)N + T - 1) / T;
     std::vector<uint64_t> indeg(nt, 0);  // synapses onto each tile: the most events it can get in one step
     for (const HostProj& pr : net->projs) {
-      if (!pr.K || !pr.tgt_n) continue;
+      if (!pr.synapses()) continue;
+      // rules that draw targets at random: the mean with a margin (a tile
+      // that receives more in one step spills the rest, exactly)
+      const bool drawn = pr.rule == SNN_RULE_FIXED_OUTDEGREE || pr.rule == SNN_RULE_FIXED_TOTAL_NUMBER;
       const uint64_t a = pr.tgt_first, b = a + pr.tgt_n;
       for (uint64_t t = a / T; t <= (b - 1) / T; ++t) {
         const uint64_t lo = std::max<uint64_t>(a, t * T), hi = std::min<uint64_t>(b, (t + 1) * T);
-        indeg[t] += (uint64_t)pr.K * (hi - lo);
+        const double m = pr.per_target() * (double)(hi - lo);
+        indeg[t] += drawn ? (uint64_t)std::ceil(1.25 * m + 64.0) : (uint64_t)m;
       }
     }
     uint64_t max_in = 0;

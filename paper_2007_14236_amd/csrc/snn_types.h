@@ -79,12 +79,19 @@ struct PopDev {
 
 static_assert(sizeof(PopDev) % 8 == 0, "PopDev is copied to LDS in 32-bit words");
 
+// connection rules; a work item of the build is one pair of draws of one
+// entity (target, source or, for the fixed total number, one synapse)
+enum Rule : uint32_t { kRuleInDegree = 0, kRuleOutDegree = 1, kRuleAllToAll = 2, kRuleOneToOne = 3, kRuleTotal = 4 };
+
 struct ProjDev {
-  uint32_t src_first, src_n, tgt_first, tgt_n, K, kpairs;
+  uint32_t src_first, src_n, tgt_first, tgt_n;
+  uint32_t K;              // draws per entity (in-degree, out-degree, n_src, 1, 1)
+  uint32_t kpairs;         // work items per entity: ceil(K / 2) (1 for one-to-one and fixed total)
   uint32_t index;          // creation index within its instance (Philox counter word 1, bits 40+)
   uint32_t gid_base;       // first gid of its instance (counters use instance-local gids)
+  uint32_t rule, pad;
   uint64_t seed;           // generator key of its instance
-  uint64_t pair_begin;     // prefix of tgt_n * kpairs over projections
+  uint64_t pair_begin;     // prefix of entities * kpairs over projections
   uint64_t thr[64];        // delay thresholds, thr[d] for d = 1..Dmax
 };
 

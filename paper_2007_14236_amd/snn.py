@@ -24,6 +24,9 @@ PARAMS = {"tau_m": 0, "C_m": 1, "E_L": 2, "V_th": 3, "V_reset": 4, "t_ref": 5, "
 PORT_PARAMS = {"tau_syn": 0, "E_rev": 1, "tau_rise": 2}
 STATE = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6, "g_rise": 7}
 DELAYS = {"const": 0, "uniform": 1, "normal": 2}
+# connection rules; a projection's "K" is the in-degree, the out-degree or the
+# number of synapses (unused for all_to_all and one_to_one)
+RULES = {"fixed_indegree": 0, "fixed_outdegree": 1, "all_to_all": 2, "one_to_one": 3, "fixed_total_number": 4}
 F_NO_SPIKE_RECORD = 1
 F_DELIVERY_DIRECT = 2
 F_DELIVERY_BINNED = 4
@@ -72,6 +75,8 @@ _SIGS = {
     "snn_set_port_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
     "snn_connect_fixed_indegree": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                                C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
+    "snn_connect": (C.c_int32, [_P, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
     "snn_poisson": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double, C.c_uint32]),
     "snn_set_state": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_uint32, C.POINTER(C.c_double),
                                   C.c_size_t]),
@@ -194,8 +199,8 @@ class Net:
             s0, sn = ranges[pr["src"]]
             t0, tn = ranges[pr["tgt"]]
             kind, a, b = (list(pr["delay"]) + [0.0, 0.0])[:3]
-            self._check(self.L.snn_connect_fixed_indegree(self.h, s0, sn, t0, tn, pr["K"], float(pr["weight"]),
-                                                          DELAYS[kind], float(a), float(b), pr["port"]))
+            self._check(self.L.snn_connect(self.h, RULES[pr.get("rule", "fixed_indegree")], int(pr.get("K", 0)), s0, sn,
+                                           t0, tn, float(pr["weight"]), DELAYS[kind], float(a), float(b), pr["port"]))
         for q in spec.get("poisson", []):
             t0, tn = ranges[q["tgt"]]
             self._check(self.L.snn_poisson(self.h, t0, tn, float(q["rate"]), int(q["n_inputs"]),

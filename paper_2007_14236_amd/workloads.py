@@ -237,7 +237,13 @@ def brunel_sweep_instance(i: int) -> dict:
 
 def count_synapses(spec: dict) -> int:
     sizes = {p["name"]: p["n"] for p in spec["populations"]}
-    return int(sum(pr["K"] * sizes[pr["tgt"]] for pr in spec["projections"]))
+    total = 0
+    for pr in spec["projections"]:
+        rule, ns, nt = pr.get("rule", "fixed_indegree"), sizes[pr["src"]], sizes[pr["tgt"]]
+        total += {"fixed_indegree": pr.get("K", 0) * nt, "fixed_outdegree": pr.get("K", 0) * ns if nt else 0,
+                  "all_to_all": ns * nt, "one_to_one": nt,
+                  "fixed_total_number": pr.get("K", 0) if nt else 0}[rule]
+    return int(total)
 
 
 def population_ranges(spec: dict) -> dict:
