@@ -15,10 +15,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-LIF_DELTA, LIF_EXP, AEIF_COND_EXP, AEIF_COND_BETA = 0, 1, 2, 3
+LIF_DELTA, LIF_EXP, AEIF_COND_EXP, AEIF_COND_BETA, SPIKE_GENERATOR, PARROT = 0, 1, 2, 3, 4, 5
 FP64, FP32SO = 0, 1
 MODEL_IDS = {"lif_delta": LIF_DELTA, "lif_exp": LIF_EXP, "aeif_cond_exp": AEIF_COND_EXP,
-             "aeif_cond_beta": AEIF_COND_BETA}
+             "aeif_cond_beta": AEIF_COND_BETA, "spike_generator": SPIKE_GENERATOR, "parrot_neuron": PARROT}
 DELAY_IDS = {"const": 0, "uniform": 1, "normal": 2}
 VAR_IDS = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6, "g_rise": 7}
 # connection rules; a projection's "K" is the in-degree, the out-degree or the
@@ -71,6 +71,7 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_population.restype = C.c_int64
         L.orc_population.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(PopParams)]
+        L.orc_set_spike_times.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
         L.orc_connect.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                   C.c_double, C.c_int, C.c_double, C.c_double, C.c_uint32]
         L.orc_connect_fixed_indegree.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -246,6 +247,11 @@ class OracleNet:
             self._check(first >= 0)
             self.ranges[p["name"]] = (int(first), p["n"])
         self.N = sum(p["n"] for p in spec["populations"])
+        for p in spec["populations"]:  # after every population: state is sized then
+            for j, times in enumerate(p.get("spike_times", []) or []):
+                t = np.ascontiguousarray(times, dtype=np.float64)
+                self._check(self.L.orc_set_spike_times(self.h, self.ranges[p["name"]][0] + j, len(t),
+                                                       _ptr(t, C.c_double)) == 0)
         self.P = max(p["ports"] for p in spec["populations"])
         for pr in spec["projections"]:
             s0, sn = self.ranges[pr["src"]]

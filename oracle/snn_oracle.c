@@ -173,6 +173,8 @@ struct orc_net {
   uint64_t* off;            /* N*(dmax+1)+1 */
   /* state (double; FP32SO mode keeps float copies for LIF) */
   double* V; double* Ie; double* w; double* g; double* gr; double* I; double* h; int32_t* refr;
+  /* spike generators: per neuron its emission steps (ascending) and cursor */
+  uint64_t** gen_steps; uint64_t* gen_n; uint64_t* gen_pos;
   float* Vf; float* If; float* Ief;
   /* integer input accumulator for the next step, N*P */
   int64_t* acc;
@@ -207,6 +209,8 @@ void orc_destroy(orc_net* o) {
   free(o->pops); free(o->pop_first); free(o->pop_of); free(o->proj); free(o->pois); free(o->pois_of);
   free(o->shift); free(o->syn); free(o->off);
   free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->gr); free(o->I); free(o->h); free(o->refr);
+  if (o->gen_steps) for (uint32_t i = 0; i < o->N; ++i) free(o->gen_steps[i]);
+  free(o->gen_steps); free(o->gen_n); free(o->gen_pos);
   free(o->Vf); free(o->If); free(o->Ief); free(o->acc);
   free(o->spk_step); free(o->spk_gid); free(o->spk_mult); free(o->spk_at);
   free(o);
@@ -215,7 +219,11 @@ void orc_destroy(orc_net* o) {
 int64_t orc_population(orc_net* o, uint32_t n, const orc_pop_params* p) {
   if (o->built || o->shift) { set_err(o, "population after build"); return -1; }
   if (n == 0 || p->n_ports < 1 || p->n_ports > ORC_MAX_PORTS) { set_err(o, "bad population"); return -1; }
-  if (p->model < ORC_LIF_DELTA || p->model > ORC_AEIF_COND_BETA) { set_err(o, "bad model"); return -1; }
+  if (o->V) { set_err(o, "population after state was set"); return -1; }
+  if (p->model < ORC_LIF_DELTA || p->model > ORC_PARROT) { set_err(o, "bad model"); return -1; }
+  if ((p->model == ORC_SPIKE_GENERATOR || p->model == ORC_PARROT) && p->n_ports != 1) {
+    set_err(o, "devices have one port"); return -1;
+  }
   if (p->model == ORC_LIF_DELTA && p->n_ports != 1) { set_err(o, "lif_delta has one port"); return -1; }
   if (p->model == ORC_AEIF_COND_BETA)
     for (uint32_t q = 0; q < p->n_ports; ++q)
@@ -285,6 +293,30 @@ int orc_connect_fixed_indegree(orc_net* o, uint32_t src_first, uint32_t src_n, u
                      da, db, port);
 }
 
+static void alloc_state(orc_net* o);
+
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return x < y ? -1 : x > y;
+}
+
+int orc_set_spike_times(orc_net* o, uint32_t gid, uint64_t n, const double* t_ms) {
+  if (o->built) { set_err(o, "spike times after build"); return -1; }
+  if (gid >= o->N) { set_err(o, "range"); return -1; }
+  alloc_state(o);
+  if (o->pops[o->pop_of[gid]].model != ORC_SPIKE_GENERATOR) { set_err(o, "not a spike generator"); return -1; }
+  uint64_t* st = (uint64_t*)malloc((n ? n : 1) * sizeof(uint64_t));
+  for (uint64_t j = 0; j < n; ++j) {
+    double r = floor(t_ms[j] / o->dt + 0.5);  /* steps of dt, half up */
+    if (!(r >= 1.0)) { free(st); set_err(o, "spike time below dt"); return -1; }
+    st[j] = (uint64_t)r - 1;
+  }
+  qsort(st, (size_t)n, sizeof(uint64_t), cmp_u64);
+  free(o->gen_steps[gid]);
+  o->gen_steps[gid] = st; o->gen_n[gid] = n; o->gen_pos[gid] = 0;
+  return 0;
+}
+
 int orc_poisson(orc_net* o, uint32_t tgt_first, uint32_t tgt_n, double rate_hz, uint32_t n_inputs,
                 double weight, uint32_t port) {
   if (o->built || o->shift) { set_err(o, "poisson after build"); return -1; }
@@ -316,6 +348,9 @@ static void alloc_state(orc_net* o) {
   o->h = (double*)malloc(N * sizeof(double));
   for (size_t i = 0; i < N; ++i) o->h[i] = o->dt;
   o->refr = (int32_t*)calloc(N, sizeof(int32_t));
+  o->gen_steps = (uint64_t**)calloc(N, sizeof(uint64_t*));
+  o->gen_n = (uint64_t*)calloc(N, sizeof(uint64_t));
+  o->gen_pos = (uint64_t*)calloc(N, sizeof(uint64_t));
   o->Vf = (float*)calloc(N, sizeof(float));
   o->If = (float*)calloc(N * P, sizeof(float));
   o->Ief = (float*)calloc(N, sizeof(float));
@@ -445,6 +480,23 @@ static int prepare(orc_net* o) {
   }
   for (size_t k = 0; k < (size_t)o->n_pops * P; ++k) o->shift[k] = orc_fixed_point_shift(maxw[k]);
   free(maxw);
+  /* parrots count arriving spikes: every weight onto them must be 1 */
+  for (uint32_t k = 0; k < o->n_pops; ++k) {
+    if (o->pops[k].model != ORC_PARROT) continue;
+    uint32_t lo = o->pop_first[k], hi = (k + 1 < o->n_pops) ? o->pop_first[k + 1] : o->N;
+    for (uint32_t p = 0; p < o->n_proj; ++p) {
+      const orc_proj* pr = &o->proj[p];
+      if (proj_synapses(pr) && pr->tgt_first < hi && pr->tgt_first + pr->tgt_n > lo && pr->weight != 1.0) {
+        set_err(o, "weights onto parrot neurons must be 1"); return -1;
+      }
+    }
+    for (uint32_t q = 0; q < o->n_pois; ++q) {
+      const orc_pois* pq = &o->pois[q];
+      if (pq->tgt_n && pq->tgt_first < hi && pq->tgt_first + pq->tgt_n > lo && pq->weight != 1.0) {
+        set_err(o, "weights onto parrot neurons must be 1"); return -1;
+      }
+    }
+  }
   return 0;
 }
 
@@ -960,7 +1012,14 @@ int orc_simulate(orc_net* o, uint64_t steps) {
         xf[p] = ldexpf((float)xin[p], -S);
       }
       int m = 0;
-      if (pp->model == ORC_LIF_DELTA) {
+      if (pp->model == ORC_SPIKE_GENERATOR) {
+        /* skip times already passed, then count the ones of this step */
+        while (o->gen_pos[i] < o->gen_n[i] && o->gen_steps[i][o->gen_pos[i]] < n) o->gen_pos[i]++;
+        while (o->gen_pos[i] < o->gen_n[i] && o->gen_steps[i][o->gen_pos[i]] == n) { o->gen_pos[i]++; m++; }
+      } else if (pp->model == ORC_PARROT) {
+        /* unit weights: the input is the number of arriving spikes */
+        m = xin[0] > 0 ? (int)(xin[0] >> o->shift[pk * P]) : 0;
+      } else if (pp->model == ORC_LIF_DELTA) {
         if (f32) m = orc_lif_delta_step32(pp, o->dt, &o->Vf[i], &o->refr[i], o->Ief[i], xf[0]);
         else {
           double y = o->V[i] - pp->E_L;

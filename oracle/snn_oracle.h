@@ -28,7 +28,8 @@ extern "C" {
 #endif
 
 enum { ORC_FP64 = 0, ORC_FP32SO = 1 };
-enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2, ORC_AEIF_COND_BETA = 3 };
+enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2, ORC_AEIF_COND_BETA = 3,
+       ORC_SPIKE_GENERATOR = 4, ORC_PARROT = 5 };
 enum { ORC_DELAY_CONST = 0, ORC_DELAY_UNIFORM = 1, ORC_DELAY_NORMAL_CLIPPED = 2 };
 enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2 };
 /* connection rules (Sec. 2.1): the count n is the in-degree, the out-degree,
@@ -80,6 +81,12 @@ int      orc_connect(orc_net*, int rule, uint64_t n, uint32_t src_first, uint32_
                      double db, uint32_t port);
 int      orc_poisson(orc_net*, uint32_t tgt_first, uint32_t tgt_n, double rate_hz,
                      uint32_t n_inputs, double weight, uint32_t port);
+/* Devices (Sec. 2.1).  A spike generator emits, in the update of step n, as
+   many spikes as it has times t with round(t / dt) - 1 = n (t >= dt; the
+   spike is then reported at t).  A parrot neuron emits, in the update of step
+   n, one spike per spike arriving at step n; the connections onto it (and a
+   Poisson drive) must have weight 1. */
+int      orc_set_spike_times(orc_net*, uint32_t gid, uint64_t n, const double* t_ms);
 /* state variables (per neuron).  var: 0 V_m (mV), 1 I_e (pA), 2 w (pA),
    3 g[port] (nS), 4 I_syn[port] (pA), 5 refractory counter, 6 h (ms) */
 int      orc_set_state(orc_net*, uint32_t first, uint32_t n, int var, uint32_t port, const double* v);
