@@ -102,6 +102,11 @@ typedef struct snn_config {
    w (nS) adds g0 w to r, g0 chosen so that a lone input's conductance peaks
    at exactly w.  A network may mix it with SNN_AEIF_COND_EXP populations. */
 #define SNN_AEIF_COND_BETA 3
+/* devices (Sec. 2.1), one port each: a spike generator emits its listed
+   times (snn_set_spike_times); a parrot neuron emits, at each step, one spike
+   per spike arriving then (multiplicity; every weight onto it must be 1) */
+#define SNN_SPIKE_GENERATOR 4
+#define SNN_PARROT_NEURON 5
 
 /* model parameters (snn_set_param); all apply to whole populations */
 #define SNN_P_TAU_M 0    /* LIF membrane time constant (ms)                   */
@@ -224,6 +229,12 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
 snn_status snn_connect(snn_net* net, int32_t rule, uint64_t n, uint32_t src_first, uint32_t src_n,
                        uint32_t tgt_first, uint32_t tgt_n, double weight, int32_t delay_kind, double delay_a,
                        double delay_b, uint32_t port);
+/* Spike times (ms) of spike-generator neuron `gid`, before snn_build: a time
+   t is emitted in the update of step round(t / dt) - 1 (rounded half up), so
+   the spike is reported at t; times in one step add up to the multiplicity
+   (at most 31).  SNN_E_INVALID for a time below dt or a neuron that is not a
+   spike generator; a later call replaces the list. */
+snn_status snn_set_spike_times(snn_net* net, uint32_t gid, const double* t_ms, size_t n);
 /* Poisson generator (Sec. 2.1, Table 1): every target in the range receives,
    independently, the summed spikes of n_inputs trains of rate_hz each, with
    weight `weight` on `port`, drawn per target and step.  At most one drive per

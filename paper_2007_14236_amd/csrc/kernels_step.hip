@@ -669,6 +669,20 @@ __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* 
   for (int p = 0; p < kMaxPorts; ++p) x[p] = __fmul_rn((float)a[p], pp.scale[p]);
   const float Ie = nd.Ie[i];
   uint32_t m = 0;
+  if (kLif && pp.model >= kSpikeGen) {
+    if (pp.model == kSpikeGen) {
+      // devices (Sec. 2.1): a generator emits one spike per listed step n
+      uint32_t c = nd.gen_next[i];
+      const uint32_t e = nd.gen_off[i + 1];
+      while (c < e && nd.gen_step[c] < n) ++c;
+      while (c < e && nd.gen_step[c] == n) { ++m; ++c; }
+      nd.gen_next[i] = c;
+    } else {
+      // a parrot repeats the spikes arriving now: with unit weights its
+      // input is their number (exact in fp32 up to 2^24)
+      m = a[0] > 0 ? (uint32_t)x[0] : 0u;
+    }
+  }
   if (kLif && pp.model < kAdex) {
     float y = nd.V[i];
     int32_t r = nd.refr[i];
@@ -690,7 +704,7 @@ __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* 
   }
   if constexpr (kAd != 0) {
     constexpr bool kBeta = kAd == 2;
-    if (pp.model >= kAdex) {
+    if (pp.model == kAdex || pp.model == kAdexBeta) {
       float y[kAdexVars<P, kBeta>];
       y[0] = nd.V[i];
       y[1] = nd.w[i];

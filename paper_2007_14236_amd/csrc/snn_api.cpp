@@ -165,6 +165,7 @@ struct snn_net {
   std::vector<HostPop> pops;
   std::vector<HostProj> projs;
   std::vector<HostPois> pois;
+  std::map<uint32_t, std::vector<uint64_t>> gen_steps;  // spike generator gid -> emission steps, ascending
   uint32_t N = 0;
   // host state before build (per port arrays are [N][kMaxPorts])
   std::vector<double> V, Ie, w, h;
@@ -432,9 +433,11 @@ snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports,
   if (!net) return SNN_E_INVALID;
   net->err.clear();
   if (net->built) return fail(net, SNN_E_STATE, "snn_create after snn_build");
-  if (model < SNN_LIF_PSC_DELTA || model > SNN_AEIF_COND_BETA) return fail(net, SNN_E_INVALID, "unknown model %d", model);
+  if (model < SNN_LIF_PSC_DELTA || model > SNN_PARROT_NEURON) return fail(net, SNN_E_INVALID, "unknown model %d", model);
   if (n == 0 || n_ports < 1 || n_ports > (uint32_t)kMaxPorts) return fail(net, SNN_E_INVALID, "bad size or port count");
   if (model == SNN_LIF_PSC_DELTA && n_ports != 1) return fail(net, SNN_E_INVALID, "LIF delta has one port");
+  if ((model == SNN_SPIKE_GENERATOR || model == SNN_PARROT_NEURON) && n_ports != 1)
+    return fail(net, SNN_E_INVALID, "devices have one port");
   if ((uint64_t)net->N + n > kMaxNeurons) return fail(net, SNN_E_UNSUPPORTED, "more than 2^26 neurons");
   HostPop p;
   p.model = model;
@@ -574,6 +577,24 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
                                       double delay_a, double delay_b, uint32_t port) {
   return snn_connect(net, SNN_RULE_FIXED_INDEGREE, indegree, src_first, src_n, tgt_first, tgt_n, weight, delay_kind,
                      delay_a, delay_b, port);
+}
+
+snn_status snn_set_spike_times(snn_net* net, uint32_t gid, const double* t_ms, size_t n) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "spike times after snn_build");
+  if (gid >= net->N || (n && !t_ms)) return fail(net, SNN_E_INVALID, "bad neuron or times");
+  if (net->pops[pop_of(net, gid)].model != SNN_SPIKE_GENERATOR)
+    return fail(net, SNN_E_INVALID, "neuron %u is not a spike generator", gid);
+  std::vector<uint64_t> st(n);
+  for (size_t j = 0; j < n; ++j) {
+    const double r = std::floor(t_ms[j] / net->cfg.dt_ms + 0.5);  // steps of dt, rounded half up
+    if (!(r >= 1.0) || r > 1e15) return fail(net, SNN_E_INVALID, "spike time %g below dt", t_ms[j]);
+    st[j] = (uint64_t)r - 1;  // emitted in this step's update, reported at t
+  }
+  std::sort(st.begin(), st.end());
+  net->gen_steps[gid] = std::move(st);
+  return SNN_OK;
 }
 
 snn_status snn_poisson(snn_net* net, uint32_t tgt_first, uint32_t tgt_n, double rate_hz, uint32_t n_inputs,
@@ -737,8 +758,16 @@ snn_status snn_build(snn_net* net) {
       if (!(p.Delta_T > 0) || !(p.tau_w > 0) || !(p.C_m > 0) || !(p.rk_eps > 0))
         return fail(net, SNN_E_INVALID, "invalid AdEx parameters");
     } else {
-      net->has_lif = true;
+      net->has_lif = true;  // LIF and devices share the kernels' non-AdEx path
       if (!(p.tau_m > 0) || !(p.C_m > 0) || p.t_ref < 0) return fail(net, SNN_E_INVALID, "invalid LIF parameters");
+    }
+    if (p.model == SNN_PARROT_NEURON) {  // parrots count arriving spikes: unit weights only
+      for (const HostProj& pr : net->projs)
+        if (pr.synapses() && pr.tgt_first < p.first + p.n && pr.tgt_first + pr.tgt_n > p.first && pr.weight != 1.0)
+          return fail(net, SNN_E_INVALID, "weights onto parrot neurons must be 1");
+      for (const HostPois& q : net->pois)
+        if (q.tgt_n && q.tgt_first < p.first + p.n && q.tgt_first + q.tgt_n > p.first && q.weight != 1.0)
+          return fail(net, SNN_E_INVALID, "weights onto parrot neurons must be 1");
     }
   }
   net->P = P;
@@ -1012,6 +1041,33 @@ snn_status snn_build(snn_net* net) {
         for (uint32_t q = 0; q < P; ++q) hp[(size_t)i * P + q] = (float)net->gr[(size_t)i * kMaxPorts + q];
       HIPCHK(net, copy_sync(net, d_gr, hp.data(), hp.size() * 4, hipMemcpyHostToDevice));
       nd.gr = d_gr;
+    }
+  }
+  if (!net->gen_steps.empty()) {  // spike generators: emission steps by neuron
+    std::vector<uint32_t> off((size_t)N + 1, 0);
+    std::vector<uint64_t> steps;
+    for (uint32_t i = 0; i < N; ++i) {
+      auto it = net->gen_steps.find(i);
+      if (it != net->gen_steps.end()) steps.insert(steps.end(), it->second.begin(), it->second.end());
+      if (steps.size() >= (1ull << 32)) return fail(net, SNN_E_UNSUPPORTED, "more than 2^32 generator times");
+      off[i + 1] = (uint32_t)steps.size();
+    }
+    if (steps.empty()) steps.push_back(0);
+    uint32_t* d_off; ALLOC(d_off, uint32_t, (size_t)N + 1);
+    uint32_t* d_next; ALLOC(d_next, uint32_t, N);
+    uint64_t* d_st; ALLOC(d_st, uint64_t, steps.size());
+    HIPCHK(net, copy_sync(net, d_off, off.data(), ((size_t)N + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, d_next, off.data(), (size_t)N * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, d_st, steps.data(), steps.size() * 8, hipMemcpyHostToDevice));
+    nd.gen_off = d_off; nd.gen_next = d_next; nd.gen_step = d_st;
+  } else {
+    bool gen = false;
+    for (const HostPop& p : net->pops) gen |= p.model == SNN_SPIKE_GENERATOR;
+    if (gen) {  // generators without times: empty lists
+      uint32_t* d_z; ALLOC(d_z, uint32_t, (size_t)2 * N + 1);
+      HIPCHK(net, hipMemsetAsync(d_z, 0, ((size_t)2 * N + 1) * 4, s));
+      uint64_t* d_st; ALLOC(d_st, uint64_t, 1);
+      nd.gen_off = d_z; nd.gen_next = d_z + N + 1; nd.gen_step = d_st;
     }
   }
   int64_t* d_acc; ALLOC(d_acc, int64_t, (size_t)kInBuf * N * P);

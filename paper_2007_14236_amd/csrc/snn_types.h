@@ -3,7 +3,8 @@
 // HBM layout (all arrays device-resident for the life of the network):
 //   neuron state (SoA, fp32): V (LIF: V - E_L), I_e, and per model
 //     LIF-exp: I_syn[N][P];  AdEx: w, g[N][P], h, and with beta ports the
-//     rising variables r[N][P];  refr (int32) for LIF.
+//     rising variables r[N][P];  refr (int32) for LIF;  spike generators:
+//     their emission steps (CSR by neuron) and a cursor per neuron.
 //   acc[3][N][P]  int64 fixed-point input, one buffer per arrival step
 //                 n, n+1, n+2 (index step % 3; direct delivery: all input;
 //                 binned delivery: only the events that did not fit their
@@ -49,7 +50,7 @@ constexpr int kBinMultShift = 10;
 constexpr int kTagConn = 1;
 constexpr int kTagPoisson = 2;
 
-enum Model : int32_t { kLifDelta = 0, kLifExp = 1, kAdex = 2, kAdexBeta = 3 };
+enum Model : int32_t { kLifDelta = 0, kLifExp = 1, kAdex = 2, kAdexBeta = 3, kSpikeGen = 4, kParrot = 5 };
 
 // Parameters of one population as the kernels use them (fp32, propagators
 // precomputed in double on the host).
@@ -127,6 +128,8 @@ struct NetDev {
   uint32_t n_classes, cls_bits; // payload = target << cls_bits | class
   // state
   float* V; float* Ie; float* Isyn; float* w; float* g; float* gr; float* h; int32_t* refr;
+  // spike generators: neuron i's emission steps gen_step[gen_off[i] .. gen_off[i+1]) ascending, its cursor gen_next[i]
+  const uint32_t* gen_off; const uint64_t* gen_step; uint32_t* gen_next;
   // CSR
   const uint64_t* src_mask; const uint32_t* grp_ptr; const uint64_t* grp_off; const uint32_t* payload;
   int64_t* acc;

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libsnn.so")
 
 SNN_OK = 0
 ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "STATE", -4: "OVERFLOW", -5: "DEVICE", -7: "UNSUPPORTED"}
-MODELS = {"lif_delta": 0, "lif_exp": 1, "aeif_cond_exp": 2, "aeif_cond_beta": 3}
+MODELS = {"lif_delta": 0, "lif_exp": 1, "aeif_cond_exp": 2, "aeif_cond_beta": 3, "spike_generator": 4,
+          "parrot_neuron": 5}
 PARAMS = {"tau_m": 0, "C_m": 1, "E_L": 2, "V_th": 3, "V_reset": 4, "t_ref": 5, "g_L": 6, "Delta_T": 7,
           "V_T": 8, "tau_w": 9, "a": 10, "b": 11, "V_peak": 12, "V_r": 13, "rk_eps": 14, "rk_hmin": 15}
 PORT_PARAMS = {"tau_syn": 0, "E_rev": 1, "tau_rise": 2}
@@ -75,6 +76,7 @@ _SIGS = {
     "snn_set_port_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
     "snn_connect_fixed_indegree": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                                C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
+    "snn_set_spike_times": (C.c_int32, [_P, C.c_uint32, C.POINTER(C.c_double), C.c_size_t]),
     "snn_connect": (C.c_int32, [_P, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                 C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
     "snn_poisson": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double, C.c_uint32]),
@@ -188,6 +190,9 @@ class Net:
             self._check(self.L.snn_create(self.h, MODELS[p["model"]], p["n"], p["ports"], C.byref(first)))
             ranges[p["name"]] = (first.value, p["n"])
             self.N += p["n"]
+            for j, times in enumerate(p.get("spike_times", []) or []):
+                t = np.ascontiguousarray(times, dtype=np.float64)
+                self._check(self.L.snn_set_spike_times(self.h, first.value + j, _ptr(t, C.c_double), len(t)))
             for k, v in p["params"].items():
                 if k in PARAMS:
                     self._check(self.L.snn_set_param(self.h, first.value, p["n"], PARAMS[k], float(v)))
