@@ -229,6 +229,23 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
 snn_status snn_connect(snn_net* net, int32_t rule, uint64_t n, uint32_t src_first, uint32_t src_n,
                        uint32_t tgt_first, uint32_t tgt_n, double weight, int32_t delay_kind, double delay_a,
                        double delay_b, uint32_t port);
+/* Multimeter (Sec. 2.1), before snn_build: record state variable `var`
+   (SNN_V_M, SNN_V_W, SNN_V_G, SNN_V_G_RISE, SNN_V_I_SYN or SNN_V_H; `port` for
+   the per-port ones) of the n neurons gids[0..n) after the update of every
+   step n with (n + 1) % interval == 0, i.e. at time (n + 1) dt.  The device
+   copies the values after each step; the host collects them while
+   simulating (one synchronisation per 100 steps while a multimeter exists).
+   *meter_id receives the recorder's index.  SNN_E_INVALID for an unknown
+   variable, a gid out of range or interval 0; at build, for a variable the
+   network does not have. */
+snn_status snn_multimeter(snn_net* net, int32_t var, uint32_t port, const uint32_t* gids, size_t n,
+                          uint32_t interval, uint32_t* meter_id);
+/* Samples of meter `meter_id` so far: steps[k] (the step after whose update
+   sample k was taken) and values[k * n_gids + j] (gid j of the meter, in the
+   variable's units: V in mV as set).  *n_out = number of samples; at most
+   cap are written (pass cap 0 to query the count). */
+snn_status snn_get_samples(snn_net* net, uint32_t meter_id, uint64_t* steps, double* values, size_t cap,
+                           size_t* n_out);
 /* Spike times (ms) of spike-generator neuron `gid`, before snn_build: a time
    t is emitted in the update of step round(t / dt) - 1 (rounded half up), so
    the spike is reported at t; times in one step add up to the multiplicity

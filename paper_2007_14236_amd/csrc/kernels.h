@@ -38,6 +38,10 @@ hipError_t launch_advance(Ctrl* ctrl, uint32_t steps, hipStream_t s);
 // for gids [first, first+n) to out[0..n) (device int64).
 hipError_t launch_pending_input(const NetDev& nd, uint32_t buf, uint32_t first, uint32_t n, uint32_t port,
                                 int64_t* out, hipStream_t s);
+// Multimeter: after the step ctrl->step_base + rel, copy *addr[c] for the nch
+// channels into buf[(step % window) * nch + c].
+hipError_t launch_sample(const float* const* addr, uint32_t nch, float* buf, uint32_t window, const Ctrl* ctrl,
+                         uint32_t rel, hipStream_t s);
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,
                                  hipStream_t s);
 

@@ -166,6 +166,20 @@ struct snn_net {
   std::vector<HostProj> projs;
   std::vector<HostPois> pois;
   std::map<uint32_t, std::vector<uint64_t>> gen_steps;  // spike generator gid -> emission steps, ascending
+  // multimeters: channel c = one variable of one neuron; the device keeps the
+  // last kGraphSteps steps of every channel, the host the due samples
+  struct Meter {
+    int32_t var;
+    uint32_t port, interval, ch0;
+    std::vector<uint32_t> gids;
+    std::vector<uint64_t> steps;
+    std::vector<double> values;  // [sample][gid]
+  };
+  std::vector<Meter> meters;
+  const float** d_addr = nullptr;
+  float* d_mbuf = nullptr;
+  uint32_t nch = 0;
+  std::vector<float> h_mbuf;
   uint32_t N = 0;
   // host state before build (per port arrays are [N][kMaxPorts])
   std::vector<double> V, Ie, w, h;
@@ -375,6 +389,7 @@ snn_status drain_start(snn_net* net);
 snn_status drain_advance(snn_net* net);
 void sort_raster(snn_net* net);
 snn_status build_graphs(snn_net* net);
+snn_status collect_samples(snn_net* net, uint64_t from, uint64_t to);
 
 }  // namespace
 
@@ -577,6 +592,40 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
                                       double delay_a, double delay_b, uint32_t port) {
   return snn_connect(net, SNN_RULE_FIXED_INDEGREE, indegree, src_first, src_n, tgt_first, tgt_n, weight, delay_kind,
                      delay_a, delay_b, port);
+}
+
+snn_status snn_multimeter(snn_net* net, int32_t var, uint32_t port, const uint32_t* gids, size_t n,
+                          uint32_t interval, uint32_t* meter_id) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "multimeter after snn_build");
+  if (var != SNN_V_M && var != SNN_V_W && var != SNN_V_G && var != SNN_V_G_RISE && var != SNN_V_I_SYN && var != SNN_V_H)
+    return fail(net, SNN_E_INVALID, "variable %d cannot be recorded", var);
+  if (interval == 0 || port >= (uint32_t)kMaxPorts || (n && !gids)) return fail(net, SNN_E_INVALID, "bad meter");
+  for (size_t j = 0; j < n; ++j)
+    if (gids[j] >= net->N) return fail(net, SNN_E_INVALID, "gid %u out of range", gids[j]);
+  if ((uint64_t)net->nch + n >= (1ull << 24)) return fail(net, SNN_E_UNSUPPORTED, "too many recorded channels");
+  snn_net::Meter m;
+  m.var = var; m.port = port; m.interval = interval; m.ch0 = net->nch;
+  m.gids.assign(gids, gids + n);
+  net->nch += (uint32_t)n;
+  net->meters.push_back(std::move(m));
+  if (meter_id) *meter_id = (uint32_t)net->meters.size() - 1;
+  return SNN_OK;
+}
+
+snn_status snn_get_samples(snn_net* net, uint32_t meter_id, uint64_t* steps, double* values, size_t cap,
+                           size_t* n_out) {
+  if (!net || !n_out) return SNN_E_INVALID;
+  net->err.clear();
+  if (meter_id >= net->meters.size()) return fail(net, SNN_E_INVALID, "no meter %u", meter_id);
+  const snn_net::Meter& m = net->meters[meter_id];
+  *n_out = m.steps.size();
+  const size_t k = std::min(cap, m.steps.size());
+  if (k && (!steps || !values)) return fail(net, SNN_E_INVALID, "null output");
+  for (size_t i = 0; i < k; ++i) steps[i] = m.steps[i];
+  std::copy(m.values.begin(), m.values.begin() + k * m.gids.size(), values);
+  return SNN_OK;
 }
 
 snn_status snn_set_spike_times(snn_net* net, uint32_t gid, const double* t_ms, size_t n) {
@@ -1184,6 +1233,28 @@ snn_status snn_build(snn_net* net) {
   HIPCHK(net, hipHostMalloc((void**)&net->pin_rc, (size_t)nd.R * 4, hipHostMallocDefault));
   HIPCHK(net, hipEventCreateWithFlags(&net->ev_drain, hipEventDisableTiming));
   net->dj = snn_net::Drain();
+  if (net->nch) {  // multimeter channels: the address of each recorded value
+    std::vector<const float*> addr(net->nch);
+    for (const snn_net::Meter& m : net->meters) {
+      const float* base = nullptr;
+      size_t stride = 1, off = 0;
+      switch (m.var) {
+        case SNN_V_M: base = nd.V; break;
+        case SNN_V_W: base = nd.w; break;
+        case SNN_V_H: base = nd.h; break;
+        case SNN_V_G: base = nd.g; stride = P; off = m.port; break;
+        case SNN_V_G_RISE: base = nd.gr; stride = P; off = m.port; break;
+        default: base = nd.Isyn; stride = P; off = m.port; break;
+      }
+      if (!base || (stride > 1 && m.port >= P))
+        return fail(net, SNN_E_INVALID, "a multimeter records a variable this network does not have");
+      for (size_t j = 0; j < m.gids.size(); ++j) addr[m.ch0 + j] = base + (size_t)m.gids[j] * stride + off;
+    }
+    ALLOC(net->d_addr, const float*, net->nch);
+    ALLOC(net->d_mbuf, float, (size_t)kGraphSteps * net->nch);
+    HIPCHK(net, copy_sync(net, net->d_addr, addr.data(), addr.size() * sizeof(float*), hipMemcpyHostToDevice));
+    net->h_mbuf.resize((size_t)kGraphSteps * net->nch);
+  }
   HIPCHK(net, hipStreamSynchronize(s));
 #undef ALLOC
   net->built = true;
@@ -1203,6 +1274,7 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
   const auto t0 = std::chrono::steady_clock::now();
   uint64_t left = steps;
   while (left > 0) {
+    const uint64_t from = net->cur_step;
     if (left >= kGraphSteps) {
       HIPCHK(net, hipGraphLaunch(net->graph_k, net->stream));
       net->cur_step += kGraphSteps;
@@ -1211,6 +1283,10 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
       HIPCHK(net, hipGraphLaunch(net->graph_1, net->stream));
       net->cur_step += 1;
       left -= 1;
+    }
+    if (net->nch) {  // the replay's samples, before the next one overwrites the device window
+      st = collect_samples(net, from, net->cur_step);
+      if (st) return st;
     }
     // a pending drain stage is collected now: its copy sits before the graph
     // just launched, which keeps the device busy meanwhile
@@ -1244,12 +1320,15 @@ snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms) {
   const auto t0 = std::chrono::steady_clock::now();
   for (uint64_t k = 0; k < steps; ++k) {
     HIPCHK(net, launch_step(net->nd, 0, net->stream, ev[0], ev[1]));
+    HIPCHK(net, launch_sample(net->d_addr, net->nch, net->d_mbuf, kGraphSteps, net->nd.ctrl, 0, net->stream));
     HIPCHK(net, launch_advance(net->nd.ctrl, 1, net->stream));
     HIPCHK(net, hipEventSynchronize(ev[1]));
     float ms = 0.f;
     HIPCHK(net, hipEventElapsedTime(&ms, ev[0], ev[1]));
     kernel_ms[0] += ms;
     net->cur_step += 1;
+    st = collect_samples(net, net->cur_step - 1, net->cur_step);
+    if (st) return st;
     if (net->cur_step - net->drained_step >= net->drain_steps || k + 1 == steps) {
       st = drain(net);
       if (st) return st;
@@ -1428,6 +1507,7 @@ snn_status record_graph(snn_net* net, uint32_t steps, hipGraphExec_t* out) {
   hipError_t e = hipSuccess;
   for (uint32_t r = 0; r < steps && e == hipSuccess; ++r) {
     e = launch_step(net->nd, r, net->stream);
+    if (e == hipSuccess) e = launch_sample(net->d_addr, net->nch, net->d_mbuf, kGraphSteps, net->nd.ctrl, r, net->stream);
   }
   if (e == hipSuccess) e = launch_advance(net->nd.ctrl, steps, net->stream);
   hipError_t e2 = hipStreamEndCapture(net->stream, &g);
@@ -1436,6 +1516,27 @@ snn_status record_graph(snn_net* net, uint32_t steps, hipGraphExec_t* out) {
   e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "instantiate: %s", hipGetErrorString(e));
+  return SNN_OK;
+}
+
+// Samples due in steps [from, to) (at most kGraphSteps of them, the device
+// window) copied from the device and appended to their meters.
+snn_status collect_samples(snn_net* net, uint64_t from, uint64_t to) {
+  if (!net->nch || to <= from) return SNN_OK;
+  HIPCHK(net, copy_sync(net, net->h_mbuf.data(), net->d_mbuf, net->h_mbuf.size() * sizeof(float),
+                        hipMemcpyDeviceToHost));
+  for (snn_net::Meter& m : net->meters) {
+    for (uint64_t n = from; n < to; ++n) {
+      if ((n + 1) % m.interval) continue;
+      const float* row = net->h_mbuf.data() + (size_t)(n % kGraphSteps) * net->nch + m.ch0;
+      m.steps.push_back(n);
+      for (size_t j = 0; j < m.gids.size(); ++j) {
+        double v = row[j];
+        if (m.var == SNN_V_M) v = from_device_state(net, SNN_V_M, m.gids[j], row[j]);
+        m.values.push_back(v);
+      }
+    }
+  }
   return SNN_OK;
 }
 

@@ -77,6 +77,10 @@ _SIGS = {
     "snn_connect_fixed_indegree": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                                C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
     "snn_set_spike_times": (C.c_int32, [_P, C.c_uint32, C.POINTER(C.c_double), C.c_size_t]),
+    "snn_multimeter": (C.c_int32, [_P, C.c_int32, C.c_uint32, C.POINTER(C.c_uint32), C.c_size_t, C.c_uint32,
+                                   C.POINTER(C.c_uint32)]),
+    "snn_get_samples": (C.c_int32, [_P, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.c_size_t,
+                                    C.POINTER(C.c_size_t)]),
     "snn_connect": (C.c_int32, [_P, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                 C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
     "snn_poisson": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double, C.c_uint32]),
@@ -174,6 +178,7 @@ class Net:
         self.h = h
         self.N = 0
         self.instances = []
+        self.meters = []  # multimeter ids in specification order (all instances)
         for sp in specs:
             iid = C.c_uint32()
             self._check(self.L.snn_begin_instance(self.h, int(sp["seed"]), C.byref(iid)))
@@ -210,6 +215,14 @@ class Net:
             t0, tn = ranges[q["tgt"]]
             self._check(self.L.snn_poisson(self.h, t0, tn, float(q["rate"]), int(q["n_inputs"]),
                                            float(q["weight"]), q["port"]))
+        # multimeters: "var", "interval", "port" and the recorded neurons as
+        # "gids" counted from the specification's first neuron
+        for mm in spec.get("multimeters", []):
+            g = np.ascontiguousarray(np.asarray(mm["gids"], dtype=np.int64) + first_gid, dtype=np.uint32)
+            mid = C.c_uint32()
+            self._check(self.L.snn_multimeter(self.h, STATE[mm["var"]], int(mm.get("port", 0)), _ptr(g, C.c_uint32),
+                                              len(g), int(mm.get("interval", 1)), C.byref(mid)))
+            self.meters.append(mid.value)
         for p in spec["populations"]:
             t0, tn = ranges[p["name"]]
             if p.get("V0") is not None:
@@ -272,6 +285,24 @@ class Net:
             self._check(self.L.snn_get_spikes(self.h, step_lo, step_hi, _ptr(st, C.c_uint64), _ptr(gid, C.c_uint32),
                                               _ptr(mult, C.c_uint32), m, C.byref(n)))
         return st, gid, mult
+
+    def samples(self, k: int = 0):
+        """(steps, values) of multimeter k: values[sample][neuron]."""
+        mid, width = self.meters[k], self._meter_width(k)
+        n = C.c_size_t(0)
+        self._check(self.L.snn_get_samples(self.h, mid, None, None, 0, C.byref(n)))
+        m = n.value
+        steps = np.zeros(m, np.uint64)
+        vals = np.zeros(m * width, np.float64)
+        if m:
+            self._check(self.L.snn_get_samples(self.h, mid, _ptr(steps, C.c_uint64), _ptr(vals, C.c_double), m,
+                                               C.byref(n)))
+        return steps, vals.reshape(m, width)
+
+    def _meter_width(self, k: int) -> int:
+        specs = list(self.spec) if isinstance(self.spec, (list, tuple)) else [self.spec]
+        widths = [len(mm["gids"]) for sp in specs for mm in sp.get("multimeters", [])]
+        return widths[k]
 
     def counters(self) -> dict:
         c = Counters()
