@@ -72,6 +72,7 @@ def lib():
         L.orc_population.restype = C.c_int64
         L.orc_population.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(PopParams)]
         L.orc_set_spike_times.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
+        L.orc_connect_list.argtypes = [C.c_void_p, C.c_uint64, P32, P32, PD, C.c_double, C.c_uint32]
         L.orc_connect.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                   C.c_double, C.c_int, C.c_double, C.c_double, C.c_uint32]
         L.orc_connect_fixed_indegree.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -254,6 +255,13 @@ class OracleNet:
                                                        _ptr(t, C.c_double)) == 0)
         self.P = max(p["ports"] for p in spec["populations"])
         for pr in spec["projections"]:
+            if pr.get("rule") == "list":  # user-defined: gids counted from the specification's first neuron
+                src = np.ascontiguousarray(pr["src_gids"], dtype=np.uint32)
+                tgt = np.ascontiguousarray(pr["tgt_gids"], dtype=np.uint32)
+                dl = np.ascontiguousarray(pr["delays_ms"], dtype=np.float64)
+                self._check(self.L.orc_connect_list(self.h, len(src), _ptr(src, C.c_uint32), _ptr(tgt, C.c_uint32),
+                                                    _ptr(dl, C.c_double), pr["weight"], pr["port"]) == 0)
+                continue
             s0, sn = self.ranges[pr["src"]]
             t0, tn = self.ranges[pr["tgt"]]
             kind, a, b = (list(pr["delay"]) + [0.0, 0.0])[:3]

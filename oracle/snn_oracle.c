@@ -131,6 +131,7 @@ typedef struct {
   uint32_t src_first, src_n, tgt_first, tgt_n, K, port;
   int rule;
   uint64_t n;     /* the rule's count (in-degree, out-degree, synapses) */
+  uint32_t* lsrc; uint32_t* ltgt; uint8_t* ldel;  /* user-defined list */
   double weight;
   uint64_t dthr[64];
 } orc_proj;
@@ -206,6 +207,7 @@ orc_net* orc_create(double dt_ms, uint64_t seed, uint32_t max_delay_steps, int m
 
 void orc_destroy(orc_net* o) {
   if (!o) return;
+  for (uint32_t p = 0; p < o->n_proj; ++p) { free(o->proj[p].lsrc); free(o->proj[p].ltgt); free(o->proj[p].ldel); }
   free(o->pops); free(o->pop_first); free(o->pop_of); free(o->proj); free(o->pois); free(o->pois_of);
   free(o->shift); free(o->syn); free(o->off);
   free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->gr); free(o->I); free(o->h); free(o->refr);
@@ -282,8 +284,39 @@ static uint64_t proj_synapses(const orc_proj* pr) {
     case ORC_RULE_FIXED_OUTDEGREE: return pr->tgt_n ? (uint64_t)pr->K * pr->src_n : 0;
     case ORC_RULE_ALL_TO_ALL: return (uint64_t)pr->src_n * pr->tgt_n;
     case ORC_RULE_ONE_TO_ONE: return pr->tgt_n;
-    default: return pr->tgt_n ? pr->n : 0;
+    default: return pr->tgt_n ? pr->n : 0;  /* fixed total number, list */
   }
+}
+
+int orc_connect_list(orc_net* o, uint64_t n, const uint32_t* src, const uint32_t* tgt, const double* delay_ms,
+                     double weight, uint32_t port) {
+  if (o->built || o->shift) { set_err(o, "connect after build"); return -1; }
+  if (n == 0) return 0;
+  orc_proj pr;
+  memset(&pr, 0, sizeof pr);
+  uint32_t smin = UINT32_MAX, smax = 0, tmin = UINT32_MAX, tmax = 0;
+  pr.lsrc = (uint32_t*)malloc(n * sizeof(uint32_t));
+  pr.ltgt = (uint32_t*)malloc(n * sizeof(uint32_t));
+  pr.ldel = (uint8_t*)malloc(n);
+  for (uint64_t j = 0; j < n; ++j) {
+    double r = floor(delay_ms[j] / o->dt + 0.5);
+    if (r < 1.0) r = 1.0;
+    if (src[j] >= o->N || tgt[j] >= o->N || !(r <= (double)o->dmax)) {
+      free(pr.lsrc); free(pr.ltgt); free(pr.ldel);
+      set_err(o, "list entry out of range"); return -1;
+    }
+    pr.lsrc[j] = src[j]; pr.ltgt[j] = tgt[j]; pr.ldel[j] = (uint8_t)r;
+    if (src[j] < smin) smin = src[j];
+    if (src[j] > smax) smax = src[j];
+    if (tgt[j] < tmin) tmin = tgt[j];
+    if (tgt[j] > tmax) tmax = tgt[j];
+  }
+  /* ranges: the bounding intervals of the listed gids */
+  pr.src_first = smin; pr.src_n = smax - smin + 1; pr.tgt_first = tmin; pr.tgt_n = tmax - tmin + 1;
+  pr.rule = ORC_RULE_LIST; pr.n = n; pr.K = 1; pr.port = port; pr.weight = weight;
+  o->proj = (orc_proj*)realloc(o->proj, (o->n_proj + 1) * sizeof(orc_proj));
+  o->proj[o->n_proj++] = pr;
+  return 0;
 }
 
 int orc_connect_fixed_indegree(orc_net* o, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
@@ -521,6 +554,10 @@ static void draw_synapse(const orc_net* o, uint32_t p, uint64_t e, uint32_t k, u
                          uint32_t* tgt, uint32_t* d) {
   const orc_proj* pr = &o->proj[p];
   uint64_t key[2] = {o->seed, 0};
+  if (pr->rule == ORC_RULE_LIST) {  /* user-defined: synapse e as listed */
+    *src = pr->lsrc[e]; *tgt = pr->ltgt[e]; *d = pr->ldel[e];
+    return;
+  }
   if (pr->rule == ORC_RULE_ONE_TO_ONE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER) {
     uint64_t ctr[4] = {e, (uint64_t)p << 40, ORC_TAG_CONN, 0};
     orc_philox4x64_10(ctr, key, blk);
@@ -561,11 +598,10 @@ int orc_build(orc_net* o) {
     if (proj_synapses(pr) == 0) continue;
     /* entities: targets, sources (out-degree) or synapses (total number);
        draws per entity: n, n, n_src, 1, 1 */
-    uint64_t ne = pr->rule == ORC_RULE_FIXED_OUTDEGREE ? pr->src_n
-                : pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER ? pr->n : pr->tgt_n;
-    uint64_t first = pr->rule == ORC_RULE_FIXED_OUTDEGREE ? pr->src_first
-                   : pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER ? 0 : pr->tgt_first;
-    uint32_t kn = pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER ? 1u : pr->K;
+    int per_syn = pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER || pr->rule == ORC_RULE_LIST;
+    uint64_t ne = pr->rule == ORC_RULE_FIXED_OUTDEGREE ? pr->src_n : per_syn ? pr->n : pr->tgt_n;
+    uint64_t first = pr->rule == ORC_RULE_FIXED_OUTDEGREE ? pr->src_first : per_syn ? 0 : pr->tgt_first;
+    uint32_t kn = per_syn ? 1u : pr->K;
     for (uint64_t j = 0; j < ne; ++j) {
       uint64_t blk[4] = {0, 0, 0, 0};
       for (uint32_t k = 0; k < kn; ++k) {
@@ -925,7 +961,7 @@ int64_t orc_target_synapses(orc_net* o, uint32_t t, uint64_t cap, uint32_t* src,
   for (uint32_t p = 0; p < o->n_proj; ++p) {
     const orc_proj* pr = &o->proj[p];
     if (t < pr->tgt_first || t - pr->tgt_first >= pr->tgt_n || proj_synapses(pr) == 0) continue;
-    if (pr->rule == ORC_RULE_FIXED_OUTDEGREE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER) {
+    if (pr->rule == ORC_RULE_FIXED_OUTDEGREE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER || pr->rule == ORC_RULE_LIST) {
       set_err(o, "the rule does not draw per target"); return -1;
     }
     int64_t w = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * o->P + pr->port]));
@@ -965,7 +1001,8 @@ int orc_sampled_input(orc_net* o, uint32_t nt, const uint32_t* tgt, uint64_t n_s
     for (uint32_t p = 0; p < o->n_proj; ++p) {
       const orc_proj* pr = &o->proj[p];
       if (t < pr->tgt_first || t - pr->tgt_first >= pr->tgt_n || proj_synapses(pr) == 0) continue;
-      if (pr->rule == ORC_RULE_FIXED_OUTDEGREE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER) {
+      if (pr->rule == ORC_RULE_FIXED_OUTDEGREE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER ||
+          pr->rule == ORC_RULE_LIST) {
         set_err(o, "the rule does not draw per target"); return -1;
       }
       int64_t w = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * P + pr->port]));

@@ -35,7 +35,7 @@ enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2 };
 /* connection rules (Sec. 2.1): the count n is the in-degree, the out-degree,
    unused, unused, and the number of synapses, in that order */
 enum { ORC_RULE_FIXED_INDEGREE = 0, ORC_RULE_FIXED_OUTDEGREE = 1, ORC_RULE_ALL_TO_ALL = 2,
-       ORC_RULE_ONE_TO_ONE = 3, ORC_RULE_FIXED_TOTAL_NUMBER = 4 };
+       ORC_RULE_ONE_TO_ONE = 3, ORC_RULE_FIXED_TOTAL_NUMBER = 4, ORC_RULE_LIST = 5 };
 enum { ORC_MAX_PORTS = 4, ORC_POISSON_KMAX = 128 };
 
 /* Neuron-model parameters of one population (double, NEST units). */
@@ -75,6 +75,11 @@ int      orc_connect_fixed_indegree(orc_net*, uint32_t src_first, uint32_t src_n
                                     uint32_t tgt_first, uint32_t tgt_n, uint32_t indegree,
                                     double weight, int delay_kind, double da, double db,
                                     uint32_t port);
+/* user-defined connections (Sec. 2.1): synapse j from src[j] onto tgt[j]
+   with delay delay_ms[j] (steps: rounded half up, at least 1, at most Dmax,
+   else an error), all with weight `weight` on `port` */
+int      orc_connect_list(orc_net*, uint64_t n, const uint32_t* src, const uint32_t* tgt, const double* delay_ms,
+                          double weight, uint32_t port);
 /* any rule; fixed in-degree is rule 0 with n = the in-degree */
 int      orc_connect(orc_net*, int rule, uint64_t n, uint32_t src_first, uint32_t src_n,
                      uint32_t tgt_first, uint32_t tgt_n, double weight, int delay_kind, double da,

@@ -239,6 +239,9 @@ def count_synapses(spec: dict) -> int:
     sizes = {p["name"]: p["n"] for p in spec["populations"]}
     total = 0
     for pr in spec["projections"]:
+        if pr.get("rule") == "list":
+            total += len(pr["src_gids"])
+            continue
         rule, ns, nt = pr.get("rule", "fixed_indegree"), sizes[pr["src"]], sizes[pr["tgt"]]
         total += {"fixed_indegree": pr.get("K", 0) * nt, "fixed_outdegree": pr.get("K", 0) * ns if nt else 0,
                   "all_to_all": ns * nt, "one_to_one": nt,

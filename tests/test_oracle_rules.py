@@ -152,3 +152,36 @@ def test_bad_rules_rejected():
     spec["projections"][3]["src"] = "A"  # one-to-one between populations of different sizes
     with pytest.raises(RuntimeError):
         O.OracleNet(spec)
+
+
+def list_projection(rng, n_total, count, dmax_ms):
+    src = rng.integers(0, n_total, size=count)
+    tgt = rng.integers(0, n_total, size=count)
+    delays = np.round(rng.uniform(0.05, dmax_ms, size=count), 3)
+    return dict(rule="list", src_gids=src.tolist(), tgt_gids=tgt.tolist(), delays_ms=delays.tolist(),
+                weight=0.25, port=0)
+
+
+def test_list_connections_are_the_listed_synapses():
+    spec = rules_spec()
+    rng = np.random.default_rng(12)
+    n = sum(p["n"] for p in spec["populations"])
+    lp = list_projection(rng, n, 500, 1.9)
+    spec["projections"].append(lp)
+    base = O.OracleNet(rules_spec()).synapses()
+    syn = O.OracleNet(spec).synapses()
+    triples = lambda t: sorted(zip(t["src"].tolist(), t["delay"].tolist(), t["tgt"].tolist()))
+    steps = [max(1, int(np.floor(d / DT + 0.5))) for d in lp["delays_ms"]]
+    listed = list(zip(lp["src_gids"], steps, lp["tgt_gids"]))
+    assert triples(syn) == sorted(triples(base) + listed)
+
+
+def test_list_errors():
+    spec = rules_spec()
+    spec["projections"].append(dict(rule="list", src_gids=[0], tgt_gids=[1], delays_ms=[2.5], weight=1.0, port=0))
+    with pytest.raises(RuntimeError):  # 25 steps > Dmax 20
+        O.OracleNet(spec)
+    spec = rules_spec()
+    spec["projections"].append(dict(rule="list", src_gids=[0], tgt_gids=[10**6], delays_ms=[0.5], weight=1.0, port=0))
+    with pytest.raises(RuntimeError):
+        O.OracleNet(spec)
