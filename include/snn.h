@@ -226,6 +226,12 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
 #define SNN_RULE_ALL_TO_ALL 2
 #define SNN_RULE_ONE_TO_ONE 3
 #define SNN_RULE_FIXED_TOTAL_NUMBER 4
+/* User-defined connections (Sec. 2.1): n synapses src[j] -> tgt[j] (gids,
+   all inside one instance) with delays delay_ms[j] (steps of dt rounded half
+   up, at least one; SNN_E_INVALID above max_delay_steps), weight `weight` on
+   `port`.  The lists are copied. */
+snn_status snn_connect_list(snn_net* net, size_t n, const uint32_t* src, const uint32_t* tgt, const double* delay_ms,
+                            double weight, uint32_t port);
 snn_status snn_connect(snn_net* net, int32_t rule, uint64_t n, uint32_t src_first, uint32_t src_n,
                        uint32_t tgt_first, uint32_t tgt_n, double weight, int32_t delay_kind, double delay_a,
                        double delay_b, uint32_t port);

@@ -11,7 +11,8 @@
 //                       word 2(k&1)+1 (delay);
 //   one-to-one       -- target t: block (t, p << 40), word 1 (delay);
 //   fixed total      -- synapse j: block (j, p << 40), words 0 (source),
-//                       1 (target), 2 (delay).
+//                       1 (target), 2 (delay);
+//   user-defined     -- synapse j as listed (no draw).
 // A uniform index in a range of m is floor(u m / 2^64); a delay is the top 32
 // bits of its word against the projection's threshold table.
 //
@@ -76,6 +77,18 @@ __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, u
     // entity gid (instance-local in the counter): target, source, or none
     const uint32_t ent = pr.rule == kRuleOutDegree ? pr.src_first + (uint32_t)e
                        : pr.rule == kRuleTotal ? 0u : pr.tgt_first + (uint32_t)e;
+    if (pr.rule == kRuleList) {  // user-defined: synapse e as listed, no draw
+      const uint32_t src = pr.lsrc[e], tgt = pr.ltgt[e];
+      const uint64_t bucket = (uint64_t)src * D1 + pr.ldel[e];
+      if (!kScatter) {
+        atomicAdd(&cnt[bucket], 1u);
+      } else {
+        const uint32_t cls = cls_of[(size_t)p * npop + find_pop(pop_first, npop, tgt)];
+        const unsigned long long slot = atomicAdd(&cursor[bucket], 1ull);
+        payload[slot] = (tgt << cls_bits) | cls;
+      }
+      continue;
+    }
     const uint64_t c0 = pr.rule == kRuleTotal ? e : (uint64_t)(ent - pr.gid_base);
     const uint64_t c1 = ((uint64_t)pr.index << 40) | kp;
     const U64x4 blk = philox4x64_10(c0, c1, kTagConn, 0, pr.seed, 0);

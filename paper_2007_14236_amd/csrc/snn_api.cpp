@@ -55,23 +55,27 @@ struct HostProj {
   int32_t kind;
   double da, db;
   int32_t rule = SNN_RULE_FIXED_INDEGREE;
-  uint64_t n = 0;  // the rule's count (fixed total number: synapses)
+  uint64_t n = 0;  // the rule's count (fixed total number, list: synapses)
+  std::vector<uint32_t> lsrc, ltgt;  // user-defined list (rule kRuleList)
+  std::vector<uint8_t> ldel;
   // synapses the projection makes
   uint64_t synapses() const {
     switch (rule) {
       case SNN_RULE_FIXED_OUTDEGREE: return tgt_n ? (uint64_t)K * src_n : 0;
-      case SNN_RULE_FIXED_TOTAL_NUMBER: return tgt_n ? n : 0;
+      case SNN_RULE_FIXED_TOTAL_NUMBER:
+      case kRuleList: return tgt_n ? n : 0;
       default: return (uint64_t)K * tgt_n;
     }
   }
   // work-item entities: sources (out-degree), synapses (total) or targets
   uint64_t entities() const {
-    return rule == SNN_RULE_FIXED_OUTDEGREE ? src_n : rule == SNN_RULE_FIXED_TOTAL_NUMBER ? n : tgt_n;
+    return rule == SNN_RULE_FIXED_OUTDEGREE ? src_n : (rule == SNN_RULE_FIXED_TOTAL_NUMBER || rule == kRuleList) ? n
+                                                                                                       : tgt_n;
   }
   // synapses onto a target: exact for the rules drawn per target, the mean otherwise
   double per_target() const {
     if (rule == SNN_RULE_FIXED_OUTDEGREE) return tgt_n ? (double)K * src_n / tgt_n : 0.0;
-    if (rule == SNN_RULE_FIXED_TOTAL_NUMBER) return tgt_n ? (double)n / tgt_n : 0.0;
+    if (rule == SNN_RULE_FIXED_TOTAL_NUMBER || rule == kRuleList) return tgt_n ? (double)n / tgt_n : 0.0;
     return (double)K;
   }
 };
@@ -587,6 +591,49 @@ snn_status snn_connect(snn_net* net, int32_t rule, uint64_t n, uint32_t src_firs
   return SNN_OK;
 }
 
+snn_status snn_connect_list(snn_net* net, size_t n, const uint32_t* src, const uint32_t* tgt, const double* delay_ms,
+                            double weight, uint32_t port) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "connect after snn_build");
+  if (n == 0) return SNN_OK;
+  if (!src || !tgt || !delay_ms) return fail(net, SNN_E_INVALID, "null list");
+  if (!std::isfinite(weight)) return fail(net, SNN_E_INVALID, "weight must be finite");
+  if (net->projs.size() >= (1u << 23)) return fail(net, SNN_E_UNSUPPORTED, "too many projections");
+  HostProj pr{};
+  pr.lsrc.assign(src, src + n);
+  pr.ltgt.assign(tgt, tgt + n);
+  pr.ldel.resize(n);
+  uint32_t smin = UINT32_MAX, smax = 0, tmin = UINT32_MAX, tmax = 0;
+  for (size_t j = 0; j < n; ++j) {
+    if (src[j] >= net->N || tgt[j] >= net->N) return fail(net, SNN_E_INVALID, "list entry %zu out of range", j);
+    const double r = std::max(1.0, std::floor(delay_ms[j] / net->cfg.dt_ms + 0.5));  // steps, half up, >= 1
+    if (!(r <= (double)net->cfg.max_delay_steps))
+      return fail(net, SNN_E_INVALID, "delay %g ms above max_delay_steps", delay_ms[j]);
+    pr.ldel[j] = (uint8_t)r;
+    smin = std::min(smin, src[j]); smax = std::max(smax, src[j]);
+    tmin = std::min(tmin, tgt[j]); tmax = std::max(tmax, tgt[j]);
+  }
+  const uint32_t inst = net->pops[pop_of(net, smin)].inst;
+  if (net->pops[pop_of(net, smax)].inst != inst || net->pops[pop_of(net, tmin)].inst != inst ||
+      net->pops[pop_of(net, tmax)].inst != inst)
+    return fail(net, SNN_E_INVALID, "a projection must stay inside one instance");
+  for (uint32_t t = tmin; t <= tmax;) {  // ports of the target populations in the bounding range
+    const HostPop& pp = net->pops[pop_of(net, t)];
+    if (port >= pp.ports) return fail(net, SNN_E_INVALID, "port %u out of range for target population", port);
+    if (pp.adex() && weight < 0) return fail(net, SNN_E_INVALID, "conductance weights must be >= 0");
+    t = pp.first + pp.n;
+  }
+  // ranges: the bounding intervals of the listed gids (fixed-point exponents
+  // and weight classes are taken over the target range)
+  pr.src_first = smin; pr.src_n = smax - smin + 1; pr.tgt_first = tmin; pr.tgt_n = tmax - tmin + 1;
+  pr.K = 1; pr.port = port; pr.inst = inst; pr.local = net->insts[inst].n_proj++; pr.weight = weight;
+  pr.kind = SNN_DELAY_CONST; pr.da = net->cfg.dt_ms; pr.db = 0.0;
+  pr.rule = kRuleList; pr.n = n;
+  net->projs.push_back(std::move(pr));
+  return SNN_OK;
+}
+
 snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t src_n, uint32_t tgt_first,
                                       uint32_t tgt_n, uint32_t indegree, double weight, int32_t delay_kind,
                                       double delay_a, double delay_b, uint32_t port) {
@@ -891,7 +938,7 @@ snn_status snn_build(snn_net* net) {
     memset(&d, 0, sizeof d);
     d.src_first = pr.src_first; d.src_n = pr.src_n; d.tgt_first = pr.tgt_first; d.tgt_n = pr.tgt_n;
     d.rule = (uint32_t)pr.rule;
-    const bool single = pr.rule == SNN_RULE_ONE_TO_ONE || pr.rule == SNN_RULE_FIXED_TOTAL_NUMBER;
+    const bool single = pr.rule == SNN_RULE_ONE_TO_ONE || pr.rule == SNN_RULE_FIXED_TOTAL_NUMBER || pr.rule == kRuleList;
     d.K = pr.K; d.kpairs = single ? 1u : (pr.K + 1) / 2; d.index = pr.local;
     d.gid_base = net->insts[pr.inst].first_gid; d.seed = net->insts[pr.inst].seed;
     d.pair_begin = total_pairs;
@@ -899,7 +946,9 @@ snn_status snn_build(snn_net* net) {
     const uint64_t syn = pr.synapses();
     if (syn) total_pairs += pr.entities() * d.kpairs;
     total_syn += syn;
-    if (syn) {
+    if (syn && pr.rule == kRuleList) {
+      for (uint8_t v : pr.ldel) dmax_used = std::max<uint32_t>(dmax_used, v);
+    } else if (syn) {
       uint32_t dm = 1;
       while (dm < dmax_cfg && d.thr[dm] < (1ull << 32)) ++dm;
       dmax_used = std::max(dmax_used, dm);
@@ -996,6 +1045,19 @@ snn_status snn_build(snn_net* net) {
   uint16_t* d_clsof = nullptr;
   uint32_t* d_popfirst = nullptr;
   ALLOC(d_proj, ProjDev, std::max<size_t>(1, pd.size()));
+  std::vector<void*> list_bufs;  // user-defined lists, freed with the build's scratch
+  for (size_t p = 0; p < pd.size(); ++p) {
+    const HostProj& pr = net->projs[p];
+    if (pr.rule != kRuleList || !pr.synapses()) continue;
+    uint32_t* ls; ALLOC(ls, uint32_t, pr.n);
+    uint32_t* lt; ALLOC(lt, uint32_t, pr.n);
+    uint8_t* ld; ALLOC(ld, uint8_t, pr.n);
+    HIPCHK(net, copy_sync(net, ls, pr.lsrc.data(), pr.n * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, lt, pr.ltgt.data(), pr.n * 4, hipMemcpyHostToDevice));
+    HIPCHK(net, copy_sync(net, ld, pr.ldel.data(), pr.n, hipMemcpyHostToDevice));
+    pd[p].lsrc = ls; pd[p].ltgt = lt; pd[p].ldel = ld;
+    list_bufs.insert(list_bufs.end(), {ls, lt, ld});
+  }
   ALLOC(d_clsof, uint16_t, cls_of.size());
   ALLOC(d_popfirst, uint32_t, npop);
   std::vector<uint32_t> pf(npop);
@@ -1044,6 +1106,7 @@ snn_status snn_build(snn_net* net) {
   dev_free(net, d_big); dev_free(net, d_nbig);
   dev_free(net, d_cnt); dev_free(net, d_off); dev_free(net, d_ng); dev_free(net, d_gp64); dev_free(net, d_tmp);
   dev_free(net, d_proj); dev_free(net, d_clsof); dev_free(net, d_popfirst);
+  for (void* b : list_bufs) dev_free(net, b);
   nd.src_mask = d_mask; nd.grp_ptr = d_gp32; nd.grp_off = d_goff; nd.payload = d_pay;
   nd.n_groups = G; nd.n_syn = S;
   net->n_groups = G; net->n_syn = S;

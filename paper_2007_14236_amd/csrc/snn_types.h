@@ -82,7 +82,8 @@ static_assert(sizeof(PopDev) % 8 == 0, "PopDev is copied to LDS in 32-bit words"
 
 // connection rules; a work item of the build is one pair of draws of one
 // entity (target, source or, for the fixed total number, one synapse)
-enum Rule : uint32_t { kRuleInDegree = 0, kRuleOutDegree = 1, kRuleAllToAll = 2, kRuleOneToOne = 3, kRuleTotal = 4 };
+enum Rule : uint32_t { kRuleInDegree = 0, kRuleOutDegree = 1, kRuleAllToAll = 2, kRuleOneToOne = 3, kRuleTotal = 4,
+                       kRuleList = 5 };
 
 struct ProjDev {
   uint32_t src_first, src_n, tgt_first, tgt_n;
@@ -93,6 +94,9 @@ struct ProjDev {
   uint32_t rule, pad;
   uint64_t seed;           // generator key of its instance
   uint64_t pair_begin;     // prefix of entities * kpairs over projections
+  const uint32_t* lsrc;    // user-defined list: source, target and delay (steps) of synapse j
+  const uint32_t* ltgt;
+  const uint8_t* ldel;
   uint64_t thr[64];        // delay thresholds, thr[d] for d = 1..Dmax
 };
 

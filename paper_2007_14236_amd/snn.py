@@ -81,6 +81,8 @@ _SIGS = {
                                    C.POINTER(C.c_uint32)]),
     "snn_get_samples": (C.c_int32, [_P, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.c_size_t,
                                     C.POINTER(C.c_size_t)]),
+    "snn_connect_list": (C.c_int32, [_P, C.c_size_t, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                     C.POINTER(C.c_double), C.c_double, C.c_uint32]),
     "snn_connect": (C.c_int32, [_P, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                 C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
     "snn_poisson": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double, C.c_uint32]),
@@ -206,6 +208,13 @@ class Net:
                         self._check(self.L.snn_set_port_param(self.h, first.value, p["n"], port,
                                                               PORT_PARAMS[k], float(x)))
         for pr in spec["projections"]:
+            if pr.get("rule") == "list":  # user-defined: gids counted from the specification's first neuron
+                src = np.ascontiguousarray(np.asarray(pr["src_gids"], dtype=np.int64) + first_gid, dtype=np.uint32)
+                tgt = np.ascontiguousarray(np.asarray(pr["tgt_gids"], dtype=np.int64) + first_gid, dtype=np.uint32)
+                dl = np.ascontiguousarray(pr["delays_ms"], dtype=np.float64)
+                self._check(self.L.snn_connect_list(self.h, len(src), _ptr(src, C.c_uint32), _ptr(tgt, C.c_uint32),
+                                                    _ptr(dl, C.c_double), float(pr["weight"]), pr["port"]))
+                continue
             s0, sn = ranges[pr["src"]]
             t0, tn = ranges[pr["tgt"]]
             kind, a, b = (list(pr["delay"]) + [0.0, 0.0])[:3]

@@ -106,3 +106,45 @@ def test_rule_errors(snn):
     spec["projections"][0]["K"] = 2**33
     with pytest.raises(snn.SnnError):
         snn.Net(spec)
+
+
+def with_list(spec, seed=12, count=700):
+    rng = np.random.default_rng(seed)
+    n = sum(p["n"] for p in spec["populations"])
+    spec["projections"].append(dict(rule="list", src_gids=rng.integers(0, n, size=count).tolist(),
+                                    tgt_gids=rng.integers(0, n, size=count).tolist(),
+                                    delays_ms=np.round(rng.uniform(0.05, 1.9, size=count), 3).tolist(),
+                                    weight=0.25, port=0))
+    return spec
+
+
+@pytest.mark.parametrize("delivery", ["direct", "binned"])
+def test_list_csr_and_raster_bit_exact(snn, delivery):
+    spec = driven(with_list(rules_spec()))
+    tile = 256 if delivery == "binned" else 0
+    g = snn.Net(spec, delivery=delivery, tile_neurons=tile)
+    o = O.OracleNet(spec, O.FP32SO)
+    assert_same(canonical(g.synapses()), canonical(o.synapses()))
+    g.simulate(300)
+    o.simulate(300)
+    for x, y in zip(g.spikes(), o.spikes()):
+        assert np.array_equal(x.astype(np.int64), y.astype(np.int64))
+
+
+def test_list_inside_a_batch(snn):
+    specs = [with_list(rules_spec(seed=5), seed=1), with_list(rules_spec(seed=6), seed=2, count=300)]
+    g = snn.Net(specs)
+    syn = g.synapses()
+    first = 0
+    for sp in specs:
+        n = sum(p["n"] for p in sp["populations"])
+        sel = (syn["src"] >= first) & (syn["src"] < first + n)
+        assert_same(canonical({k: v[sel] for k, v in syn.items()}, first), canonical(O.OracleNet(sp).synapses()))
+        first += n
+
+
+def test_list_errors(snn):
+    spec = rules_spec()
+    spec["projections"].append(dict(rule="list", src_gids=[0], tgt_gids=[1], delays_ms=[2.5], weight=1.0, port=0))
+    with pytest.raises(snn.SnnError):  # 25 steps above Dmax = 20
+        snn.Net(spec)
