@@ -73,7 +73,9 @@ typedef struct snn_config {
   uint32_t flags;           /* SNN_F_* below                                    */
   uint32_t tile_neurons;    /* binned delivery: neurons per target tile, a power
                                of two in [256, 4096 / P2] with P2 the port count
-                               rounded up to a power of two; 0 = library choice */
+                               rounded up to a power of two; 0 = library choice
+                               (the largest, or for AdEx networks the largest
+                               that leaves at least 128 tiles, at least 256) */
   uint32_t bin_capacity;    /* binned delivery: entries per tile bin (each of
                                three input buffers); 0 = library choice, at most
                                the number of synapses onto the tile.  Events
@@ -85,8 +87,8 @@ typedef struct snn_config {
 #define SNN_F_NO_SPIKE_RECORD 1u /* do not keep the spike raster on the host */
 /* How a step's synaptic events are summed into the targets' integer inputs
    (Sec. 2.2; the sum is the same either way).  Neither flag: binned for
-   networks of 5e8 synapses or more when they fit its limits (at most 1024
-   tiles), else direct. */
+   networks of 5e8 synapses or more and for networks with AdEx neurons when
+   they fit its limits (at most 1024 tiles), else direct. */
 #define SNN_F_DELIVERY_DIRECT 2u /* each event one device-scope int64 atomic add */
 #define SNN_F_DELIVERY_BINNED 4u /* each event a 32-bit entry in its target tile's
                                     bin, summed in LDS by the tile's block at the

@@ -1195,7 +1195,14 @@ snn_status snn_build(snn_net* net) {
     if (net->cfg.tile_neurons > tmax)
       return fail(net, SNN_E_UNSUPPORTED, "tiles of %u neurons x %u ports exceed the %d LDS accumulators",
                   net->cfg.tile_neurons, P, kTileAccWords);
-    const uint32_t T = net->cfg.tile_neurons ? net->cfg.tile_neurons : tmax;
+    // default tile: the largest the ports allow; networks with AdEx neurons
+    // take smaller tiles while that keeps at least 128 tiles: a tile's update
+    // lasts as long as its slowest neuron (a spike step), so more tiles run
+    // more spike steps side by side (3e4 alpha-port neurons: 129 us per step
+    // with 256-neuron tiles, 187 us with 2048)
+    uint32_t T = net->cfg.tile_neurons ? net->cfg.tile_neurons : tmax;
+    if (!net->cfg.tile_neurons && net->has_adex)
+      while (T > 256 && ((uint64_t)N + T - 1) / T < 128) T >>= 1;
     uint32_t tsh = 0;
     while ((1u << tsh) < T) ++tsh;
     const uint64_t nt = ((uint64_t)N + T - 1) / T;
@@ -1220,18 +1227,21 @@ snn_status snn_build(snn_net* net) {
                   (unsigned long long)nt, kMaxTiles, (unsigned long long)max_in);
     net->tile_neurons = 0;
     // default: binned for large networks, whose steps carry millions of events
-    // (10^6 AdEx neurons, 10^9 synapses: 176 us per step binned, 320 us direct;
-    // 128 Brunel instances, 8.7e9 synapses: 1.7 ms binned, 6.7 ms direct), direct
-    // below, where the step is latency-bound (microcircuit stand-in, 3e8
-    // synapses: 17 us direct, 25 us binned at its best tile size)
-    const bool want = forced || (!(net->cfg.flags & SNN_F_DELIVERY_DIRECT) && total_syn >= kBinnedMinSynapses);
+    // (10^6 AdEx neurons, 10^9 synapses: 190 us per step binned, 611 us direct;
+    // 128 Brunel instances, 8.7e9 synapses: 1.5 ms binned, 6.7 ms direct), and
+    // for every network with AdEx neurons, whose tile blocks feed the RK45 from
+    // a work queue (3e4-3e5 alpha-port neurons: 1.5x faster than direct); direct
+    // for smaller LIF networks, where the step is latency-bound (microcircuit
+    // stand-in, 3e8 synapses: 15 us direct, 24 us binned at its best tile size)
+    const bool want = forced || (!(net->cfg.flags & SNN_F_DELIVERY_DIRECT) &&
+                                 (total_syn >= kBinnedMinSynapses || net->has_adex));
     if (fits && want) {
       std::vector<uint64_t> off(nt);
       std::vector<uint32_t> cap(nt);
       uint64_t tot = 0;
       for (uint64_t t = 0; t < nt; ++t) {
         const uint64_t want = net->cfg.bin_capacity ? (uint64_t)net->cfg.bin_capacity
-                                                    : std::max<uint64_t>(1ull << 18, indeg[t] >> 3);
+                                                    : std::max<uint64_t>(1ull << 14, indeg[t] >> 3);
         cap[t] = (uint32_t)std::min<uint64_t>(indeg[t], want);
         tot += cap[t];
       }
