@@ -254,6 +254,19 @@ snn_status snn_multimeter(snn_net* net, int32_t var, uint32_t port, const uint32
    cap are written (pass cap 0 to query the count). */
 snn_status snn_get_samples(snn_net* net, uint32_t meter_id, uint64_t* steps, double* values, size_t cap,
                            size_t* n_out);
+/* ---- checkpoint / resume ---------------------------------------------------- */
+/* Snapshot of a built network's dynamic state after the steps simulated so
+   far: neuron state, pending input (buffers of the next three steps, bins
+   and spill), the spike records delivery still reads, the step books and the
+   statistics.  snn_snapshot_size gives the bytes; snn_snapshot writes them
+   into the caller's host buffer (SNN_E_INVALID if cap is smaller).
+   snn_restore loads a snapshot into a network built from the same
+   specification (SNN_E_INVALID for another network's snapshot): simulating
+   on gives exactly what the original gives.  The restored network's raster
+   starts at the snapshot's step; multimeter samples are not part of it. */
+snn_status snn_snapshot_size(snn_net* net, size_t* bytes);
+snn_status snn_snapshot(snn_net* net, void* buf, size_t cap);
+snn_status snn_restore(snn_net* net, const void* buf, size_t size);
 /* Spike times (ms) of spike-generator neuron `gid`, before snn_build: a time
    t is emitted in the update of step round(t / dt) - 1 (rounded half up), so
    the spike is reported at t; times in one step add up to the multiplicity

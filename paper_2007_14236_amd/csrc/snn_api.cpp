@@ -395,6 +395,51 @@ void sort_raster(snn_net* net);
 snn_status build_graphs(snn_net* net);
 snn_status collect_samples(snn_net* net, uint64_t from, uint64_t to);
 
+// ---- snapshot layout: a header, then the dynamic device arrays in order ----
+struct SnapHeader {
+  char magic[8];
+  uint32_t version, N, P, R;
+  uint64_t n_tiles, bins_total, n_syn, n_groups, nblk, sel_grid, cur_step, bytes;
+};
+
+// The device arrays that change while simulating, with their sizes.
+std::vector<std::pair<void*, size_t>> state_arrays(const snn_net* net) {
+  const NetDev& nd = net->nd;
+  const size_t N = nd.N, P = nd.P;
+  std::vector<std::pair<void*, size_t>> a;
+  auto add = [&](const void* p, size_t bytes) {
+    if (p && bytes) a.push_back({const_cast<void*>(p), bytes});
+  };
+  add(nd.V, N * 4); add(nd.Ie, N * 4); add(nd.Isyn, N * P * 4); add(nd.refr, N * 4);
+  add(nd.w, N * 4); add(nd.g, N * P * 4); add(nd.gr, N * P * 4); add(nd.h, N * 4);
+  add(nd.gen_next, N * 4);
+  add(nd.acc, (size_t)kInBuf * N * P * 8);
+  if (nd.n_tiles) {
+    add(nd.bins, (size_t)kInBuf * nd.bins_total * 4);
+    add(nd.bin_cnt, (size_t)kInBuf * nd.n_tiles * 4);
+    add(nd.ovf_flag, (size_t)kInBuf * nd.n_tiles * 4);
+  }
+  add(nd.recent, (size_t)nd.R * N * sizeof(SpikeRec));
+  add(nd.ring_cnt, (size_t)nd.R * 4); add(nd.ring_base, (size_t)nd.R * 8);
+  add(nd.chunk_base, (size_t)nd.chunk_ring * 8);
+  add(nd.ctrl, sizeof(Ctrl));
+  add(nd.blk_stats, (size_t)kBlkStats * nd.nblk_upd * 8);
+  add(nd.sel_stats, (size_t)2 * nd.sel_grid * 8);
+  return a;
+}
+
+SnapHeader snap_header(const snn_net* net) {
+  SnapHeader h;
+  memset(&h, 0, sizeof h);
+  memcpy(h.magic, "SNNSNAP1", 8);
+  h.version = 1; h.N = net->nd.N; h.P = net->nd.P; h.R = net->nd.R;
+  h.n_tiles = net->nd.n_tiles; h.bins_total = net->nd.bins_total; h.n_syn = net->n_syn; h.n_groups = net->n_groups;
+  h.nblk = net->nd.nblk_upd; h.sel_grid = net->nd.sel_grid; h.cur_step = net->cur_step;
+  h.bytes = sizeof(SnapHeader);
+  for (const auto& x : state_arrays(net)) h.bytes += x.second;
+  return h;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -673,6 +718,67 @@ snn_status snn_get_samples(snn_net* net, uint32_t meter_id, uint64_t* steps, dou
   for (size_t i = 0; i < k; ++i) steps[i] = m.steps[i];
   std::copy(m.values.begin(), m.values.begin() + k * m.gids.size(), values);
   return SNN_OK;
+}
+
+snn_status snn_snapshot_size(snn_net* net, size_t* bytes) {
+  if (!net || !bytes) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "snapshot before snn_build");
+  *bytes = snap_header(net).bytes;
+  return SNN_OK;
+}
+
+snn_status snn_snapshot(snn_net* net, void* buf, size_t cap) {
+  if (!net || !buf) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "snapshot before snn_build");
+  snn_status st = enter(net);
+  if (st) return st;
+  st = drain(net);  // the raster so far, and no copy in flight
+  if (st) return st;
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  const SnapHeader h = snap_header(net);
+  if (cap < h.bytes) return fail(net, SNN_E_INVALID, "snapshot needs %llu bytes", (unsigned long long)h.bytes);
+  char* out = static_cast<char*>(buf);
+  memcpy(out, &h, sizeof h);
+  size_t off = sizeof h;
+  for (const auto& x : state_arrays(net)) {
+    HIPCHK(net, copy_sync(net, out + off, x.first, x.second, hipMemcpyDeviceToHost));
+    off += x.second;
+  }
+  return leave(net);
+}
+
+snn_status snn_restore(snn_net* net, const void* buf, size_t size) {
+  if (!net || !buf) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "restore before snn_build");
+  SnapHeader h;
+  if (size < sizeof h) return fail(net, SNN_E_INVALID, "not a snapshot");
+  memcpy(&h, buf, sizeof h);
+  SnapHeader mine = snap_header(net);
+  if (memcmp(h.magic, mine.magic, 8) || h.version != mine.version || h.N != mine.N || h.P != mine.P ||
+      h.R != mine.R || h.n_tiles != mine.n_tiles || h.bins_total != mine.bins_total || h.n_syn != mine.n_syn ||
+      h.n_groups != mine.n_groups || h.nblk != mine.nblk || h.sel_grid != mine.sel_grid || h.bytes != mine.bytes ||
+      size < h.bytes)
+    return fail(net, SNN_E_INVALID, "the snapshot is of another network");
+  snn_status st = enter(net);
+  if (st) return st;
+  st = drain(net);
+  if (st) return st;
+  HIPCHK(net, hipStreamSynchronize(net->stream));
+  const char* in = static_cast<const char*>(buf);
+  size_t off = sizeof h;
+  for (const auto& x : state_arrays(net)) {
+    HIPCHK(net, copy_sync(net, x.first, in + off, x.second, hipMemcpyHostToDevice));
+    off += x.second;
+  }
+  net->cur_step = net->drained_step = h.cur_step;
+  net->dj = snn_net::Drain();
+  net->r_step.clear();
+  net->r_entry.clear();
+  net->r_sorted = 0;
+  return leave(net);
 }
 
 snn_status snn_set_spike_times(snn_net* net, uint32_t gid, const double* t_ms, size_t n) {

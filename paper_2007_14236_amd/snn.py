@@ -76,6 +76,9 @@ _SIGS = {
     "snn_set_port_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
     "snn_connect_fixed_indegree": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                                C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
+    "snn_snapshot_size": (C.c_int32, [_P, C.POINTER(C.c_size_t)]),
+    "snn_snapshot": (C.c_int32, [_P, C.c_void_p, C.c_size_t]),
+    "snn_restore": (C.c_int32, [_P, C.c_void_p, C.c_size_t]),
     "snn_set_spike_times": (C.c_int32, [_P, C.c_uint32, C.POINTER(C.c_double), C.c_size_t]),
     "snn_multimeter": (C.c_int32, [_P, C.c_int32, C.c_uint32, C.POINTER(C.c_uint32), C.c_size_t, C.c_uint32,
                                    C.POINTER(C.c_uint32)]),
@@ -312,6 +315,19 @@ class Net:
         specs = list(self.spec) if isinstance(self.spec, (list, tuple)) else [self.spec]
         widths = [len(mm["gids"]) for sp in specs for mm in sp.get("multimeters", [])]
         return widths[k]
+
+    def snapshot(self) -> np.ndarray:
+        """The network's dynamic state after the steps simulated so far (bytes)."""
+        n = C.c_size_t(0)
+        self._check(self.L.snn_snapshot_size(self.h, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self.L.snn_snapshot(self.h, buf.ctypes.data_as(C.c_void_p), buf.size))
+        return buf
+
+    def restore(self, snap: np.ndarray):
+        """Load a snapshot of a network built from the same specification."""
+        b = np.ascontiguousarray(snap, dtype=np.uint8)
+        self._check(self.L.snn_restore(self.h, b.ctypes.data_as(C.c_void_p), b.size))
 
     def counters(self) -> dict:
         c = Counters()
