@@ -656,8 +656,8 @@ __device__ __forceinline__ void adex_store_syn(const NetDev& nd, uint32_t i, con
 template <bool kLif, int kAd, int P>
 __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* pops, const uint64_t* pthr,
                                                 uint64_t n, uint32_t i, int64_t* a, uint32_t& nacc, uint32_t& nrej,
-                                                bool& capped, bool& mover) {
-  const PopDev& pp = pops[find_pop(pops, nd.npop, i)];
+                                                bool& capped, bool& mover, uint32_t npop) {
+  const PopDev& pp = pops[find_pop(pops, npop, i)];
   if (pp.pois >= 0) {
     const uint32_t k = poisson_draw(pthr + (size_t)pp.pois * kPoisKmax, pp.seed, i - pp.gid_base, n);
 #pragma unroll
@@ -741,6 +741,36 @@ __device__ __forceinline__ void load_tables(const NetDev& nd, PopDev* spops, uin
   pthr = lds_thr ? sthr : nd.pois_thr;
 }
 
+// A tile block's population records and Poisson tables: all of them in LDS
+// when they fit; otherwise, when the populations overlapping the tile (a
+// contiguous run in gid order, a few even in a batch of many instances) fit,
+// those, with their Poisson tables renumbered in LDS; otherwise as
+// load_tables.  Returns the number of records at `pops`.  Visible after the
+// caller's next barrier.
+__device__ __forceinline__ uint32_t load_tile_tables(const NetDev& nd, uint32_t first, uint32_t nt, PopDev* spops,
+                                                     uint64_t* sthr, const PopDev*& pops, const uint64_t*& pthr) {
+  const uint32_t p0 = find_pop(nd.pops, nd.npop, first), p1 = find_pop(nd.pops, nd.npop, first + nt - 1);
+  const uint32_t np = p1 - p0 + 1;
+  if ((nd.npop <= kTilePopLds && nd.npois <= kPoisLds) || np > kTilePopLds || np > kPoisLds) {
+    load_tables(nd, spops, kTilePopLds, sthr, pops, pthr);
+    return nd.npop;
+  }
+  const uint32_t words = np * (uint32_t)(sizeof(PopDev) / 4);
+  for (uint32_t w = threadIdx.x; w < words; w += kB)
+    reinterpret_cast<uint32_t*>(spops)[w] = reinterpret_cast<const uint32_t*>(nd.pops + p0)[w];
+  const uint32_t len = nd.pois_len;
+  for (uint32_t w = threadIdx.x; w < np * len; w += kB) {
+    const uint32_t k = w / len, j = w - k * len;
+    const int32_t q = nd.pops[p0 + k].pois;
+    if (q >= 0) sthr[k * kPoisKmax + j] = nd.pois_thr[(size_t)q * kPoisKmax + j];
+  }
+  __syncthreads();
+  if (threadIdx.x < np && spops[threadIdx.x].pois >= 0) spops[threadIdx.x].pois = (int32_t)threadIdx.x;
+  pops = spops;
+  pthr = sthr;
+  return np;
+}
+
 __device__ __forceinline__ uint32_t inbuf(uint64_t n) { return (uint32_t)(n % kInBuf); }
 
 // First raster-ring position of the spikes of step n: the positions of the
@@ -801,7 +831,7 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
         if (a[p] != 0) acc[p] = 0;
       }
     }
-    const uint32_t m = neuron_step<kLif, kAd, P>(nd, pops, pthr, n, i, a, nacc, nrej, capped, mover);
+    const uint32_t m = neuron_step<kLif, kAd, P>(nd, pops, pthr, n, i, a, nacc, nrej, capped, mover, nd.npop);
     spk = m > 0;
     entry = i | (m << kMultShift);
   }
@@ -879,9 +909,9 @@ struct AdexItem {
 };
 
 template <int P, bool kBeta>
-__device__ __forceinline__ void adex_load(const NetDev& nd, const PopDev* pops, const uint64_t* pthr, uint64_t n,
-                                          uint32_t i, int64_t* a, AdexItem<P, kBeta>& w) {
-  const PopDev& pp = pops[find_pop(pops, nd.npop, i)];
+__device__ __forceinline__ void adex_load(const NetDev& nd, const PopDev* pops, uint32_t npop, const uint64_t* pthr,
+                                          uint64_t n, uint32_t i, int64_t* a, AdexItem<P, kBeta>& w) {
+  const PopDev& pp = pops[find_pop(pops, npop, i)];
   if (pp.pois >= 0) {
     const uint32_t k = poisson_draw(pthr + (size_t)pp.pois * kPoisKmax, pp.seed, i - pp.gid_base, n);
 #pragma unroll
@@ -931,7 +961,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
   const uint32_t nt = min(1u << tsh, nd.N - first);
   const PopDev* pops;
   const uint64_t* pthr;
-  load_tables(nd, sl.spops, kTilePopLds, sl.sthr, pops, pthr);
+  const uint32_t npop = load_tile_tables(nd, first, nt, sl.spops, sl.sthr, pops, pthr);
   for (uint32_t c = threadIdx.x; c < nd.n_classes; c += kB) {
     sl.c.wq[c] = nd.cls_wq[c];
     sl.wp[c] = (uint8_t)nd.cls_port[c];
@@ -983,11 +1013,11 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
       int64_t a[kMaxPorts];
 #pragma unroll
       for (int p = 0; p < kMaxPorts; ++p) a[p] = (p < (int)PP) ? sl.u.acc[l * PP + p] : 0;
-      adex_load<P, kAd == 2>(nd, pops, pthr, n, first + l, a, it);
+      adex_load<P, kAd == 2>(nd, pops, npop, pthr, n, first + l, a, it);
     };
     for (uint32_t l = threadIdx.x; l < nt; l += kB) {
       const uint32_t i = first + l;
-      const PopDev& hp = pops[find_pop(pops, nd.npop, i)];
+      const PopDev& hp = pops[find_pop(pops, npop, i)];
       const bool hot = nd.V[i] >= hp.V_T + 4.f * hp.Delta_T;
       const uint64_t hb = __ballot(hot);
       if ((threadIdx.x & 31) == 0) sl.hot[l >> 5] = (uint32_t)(hb >> (threadIdx.x & 32));
@@ -1031,7 +1061,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
 #pragma unroll
       for (int p = 0; p < kMaxPorts; ++p) a[p] = (p < (int)PP) ? sl.u.acc[loc * PP + p] : 0;
       sl.c.mk[loc] =
-          (uint8_t)neuron_step<kLif, kAd, P>(nd, pops, pthr, n, first + loc, a, nacc, nrej, capped, mover);
+          (uint8_t)neuron_step<kLif, kAd, P>(nd, pops, pthr, n, first + loc, a, nacc, nrej, capped, mover, npop);
     }
   }
   __syncthreads();
