@@ -128,7 +128,7 @@ def parse():
     ap.add_argument("--tile-neurons", type=int, default=0, help="binned delivery: neurons per tile (0: library)")
     ap.add_argument("--bin-capacity", type=int, default=0, help="binned delivery: entries per tile bin (0: library)")
     ap.add_argument("--delivery-blocks", type=int, default=0,
-                    help="blocks that deliver delays of 3 steps or more (0: library)")
+                    help="blocks that deliver delays of 2 steps or more (0: library)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     return ap.parse_args()

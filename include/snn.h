@@ -77,10 +77,10 @@ typedef struct snn_config {
                                (the largest, or for AdEx networks the largest
                                that leaves at least 128 tiles, at least 256) */
   uint32_t bin_capacity;    /* binned delivery: entries per tile bin (each of
-                               three input buffers); 0 = library choice, at most
+                               two input buffers); 0 = library choice, at most
                                the number of synapses onto the tile.  Events
                                beyond it are still delivered exactly (atomics) */
-  uint32_t delivery_blocks; /* blocks that deliver delays >= 3, 1..8192;
+  uint32_t delivery_blocks; /* blocks that deliver delays >= 2, 1..8192;
                                0 = library choice                             */
   uint32_t reserved;        /* 0                                              */
 } snn_config;
@@ -165,7 +165,7 @@ typedef struct snn_counters {
                               bin full and were added by atomics instead     */
   uint32_t delivery;       /* 1 direct, 2 binned (after build)                */
   uint32_t tile_neurons;   /* binned delivery: neurons per target tile        */
-  uint32_t delivery_blocks; /* blocks delivering delays >= 3                  */
+  uint32_t delivery_blocks; /* blocks delivering delays >= 2                  */
   uint32_t pad;
 } snn_counters;
 

@@ -314,7 +314,11 @@ constexpr uint32_t kClsLds = 256; // weight classes cached in LDS by direct deli
 constexpr int kSelPerThread = kSelChunk / kB;
 constexpr uint32_t kTilePopLds = 8;  // population tables a tile block keeps in LDS
 constexpr int kTileSubs = kTileAccWords / kB;  // most 256-neuron sub-blocks of a tile
-constexpr uint32_t kHotCap = 256;  // AdEx neurons of a tile queued ahead of the others
+constexpr uint32_t kHotCap = 256;
+// Delays of at least this many steps are delivered by the delivery blocks
+// (their spikes' records are complete when the step starts); delay-1 groups
+// by the blocks that emit the spikes, within the step.
+constexpr uint32_t kDlvMinDelay = 2;  // AdEx neurons of a tile queued ahead of the others
 
 // LDS of the selection: the selected (source, delay-group) records of one
 // chunk and their exclusive prefix of group sizes.
@@ -355,7 +359,7 @@ struct UpdLds {
   uint64_t red[kB / 64];
   union {
     UpdTables t;  // population and Poisson tables, during the update
-    DirectLds d;  // selection of the block's delay-1 and delay-2 groups, after it
+    DirectLds d;  // selection of the block's delay-1 groups, after it
   } u;
 };
 // the weight classes of DirectLds and its pair counter lie beyond the tables:
@@ -803,11 +807,11 @@ __device__ __forceinline__ void emit_spike(const NetDev& nd, uint64_t n, uint64_
   nd.recent[(size_t)(n % nd.R) * nd.N + pos] = r;
 }
 
-// Direct-delivery update block: 256 neurons, input from acc[n % 3] (read and
+// Direct-delivery update block: 256 neurons, input from acc[n % 2] (read and
 // cleared); spikes get their positions from one atomic per wave on the step's
 // counter (wave ballot + lane prefix), their raster entries and records are
-// written here, and their delay-1 and delay-2 groups are delivered at once by
-// the block's flat scan into the buffers of steps n + 1 and n + 2.
+// written here, and their delay-1 groups are delivered at once by the
+// block's flat scan into the buffer of step n + 1.
 template <bool kLif, int kAd, int P>
 __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds& sl) {
   const PopDev* pops;
@@ -847,18 +851,13 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
   }
   if (lane == 0) sl.wcnt[wv] = __popcll(bal);
   // a spiking neuron's delay mask, first group and the offsets of its delay-1
-  // and delay-2 groups, loaded while the wave's atomic is in flight
-  uint64_t mask = 0, o1 = 0, o2 = 0;
-  uint32_t gp = 0, l1 = 0, l2 = 0;
+  // group, loaded while the wave's atomic is in flight
+  uint64_t mask = 0, o1 = 0;
+  uint32_t gp = 0, l1 = 0;
   if (spk) {
     mask = nd.src_mask[i];
     gp = nd.grp_ptr[i];
     if ((mask >> 1) & 1ull) { o1 = nd.grp_off[gp]; l1 = (uint32_t)(nd.grp_off[gp + 1] - o1); }
-    if ((mask >> 2) & 1ull) {
-      const uint32_t g2 = gp + (uint32_t)__popcll(mask & 3ull);
-      o2 = nd.grp_off[g2];
-      l2 = (uint32_t)(nd.grp_off[g2 + 1] - o2);
-    }
   }
   if (spk) emit_spike(nd, n, step_pos(nd, n), wpos, entry, gp, mask);
   if (threadIdx.x == 0) sl.u.d.npair = 0;  // the tables are dead from here
@@ -866,13 +865,12 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
   uint32_t btot = 0;
 #pragma unroll
   for (int w = 0; w < kB / 64; ++w) btot += sl.wcnt[w];
-  // delay-1 and delay-2 groups of the block's spikes: selected into LDS and
-  // delivered by the block's flat scan into the buffers of steps n+1 and n+2
+  // delay-1 groups of the block's spikes: selected into LDS and delivered by
+  // the block's flat scan into the buffer of step n+1
   uint64_t pairs = 0, events = 0;
   if (btot) {  // block-uniform
     DirectLds& sh = sl.u.d;
     if (l1) sel_add(sh, o1, l1, entry >> kMultShift, inbuf(n + 1));
-    if (l2) sel_add(sh, o2, l2, entry >> kMultShift, inbuf(n + 2));
     __syncthreads();
     if (sh.npair) {
       pairs += sh.npair;
@@ -948,7 +946,7 @@ __device__ __forceinline__ uint32_t adex_store(const NetDev& nd, uint32_t i, Ade
 // written for step n during earlier steps, plus any spill) into int64 LDS
 // accumulators, updates the tile's neurons from them, emits their spikes
 // (one atomic on the step's counter for the whole tile) and bins the delay-1
-// and delay-2 groups of those spikes for steps n+1 and n+2.  The spike count
+// groups of those spikes for step n+1.  The spike count
 // of a neuron is kept in its (then dead) first LDS input slot until all
 // neurons are done.  AdEx-only networks take their neurons from a work queue:
 // a lane whose neuron has reached the step end takes the next one, so waves
@@ -1088,7 +1086,6 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     __syncthreads();
     const uint64_t pos_n = step_pos(nd, n);
     uint32_t before = 0;  // spikes of the sub-blocks before k
-    uint32_t has2 = 0;    // sub-blocks where this thread's neuron has a delay-2 group
     for (uint32_t k = 0; k < nsub; ++k) {  // block-uniform
       uint32_t woff = 0, ktot = 0;
 #pragma unroll
@@ -1106,7 +1103,6 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
         const uint32_t gp = nd.grp_ptr[i];
         emit_spike(nd, n, pos_n, sl.emit + before + woff + (uint32_t)__popcll(bal & lanemask_lt()), entry, gp, mask);
         if ((mask >> 1) & 1ull) dlv_probe(nd, sh, entry, gp, mask, 1, inbuf(n + 1));
-        if ((mask >> 2) & 1ull) has2 |= 1u << k;
       }
       before += ktot;
       __syncthreads();
@@ -1119,26 +1115,6 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     if (sh.npair) {
       pairs += sh.npair;
       events += dlv_flush(nd, sh, inbuf(n + 1));
-    }
-    if (__syncthreads_or(has2 != 0)) {
-      for (uint32_t k = 0; k < nsub; ++k) {  // block-uniform
-        if ((has2 >> k) & 1u) {
-          const uint32_t loc = k * kB + threadIdx.x;
-          const uint32_t i = first + loc;
-          dlv_probe(nd, sh, i | ((uint32_t)sl.c.mk[loc] << kMultShift), nd.grp_ptr[i], nd.src_mask[i], 2,
-                    inbuf(n + 2));
-        }
-        __syncthreads();
-        if (sh.npair > (uint32_t)(kSelChunk - kB)) {
-          pairs += sh.npair;
-          events += dlv_flush(nd, sh, inbuf(n + 2));
-        }
-      }
-      __syncthreads();
-      if (sh.npair) {
-        pairs += sh.npair;
-        events += dlv_flush(nd, sh, inbuf(n + 2));
-      }
     }
   }
   uint64_t sa = 0, sr = 0;
@@ -1159,7 +1135,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
 }
 
 // Delivery blocks of step n: the input of step n+1 from the spikes of steps
-// n-2 .. n+1-Dmax whose delay d >= 3 expires now, read from their selection
+// n-1 .. n+1-Dmax whose delay d >= 2 expires now, read from their selection
 // records.  Item (spike, d) number e goes to block e mod G, so that every
 // block sees every delay (hits concentrate on the common delays).
 template <class L>
@@ -1170,7 +1146,7 @@ __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t
   if (threadIdx.x < 64) {
     uint64_t cnt = 0;
     uint32_t slt = 0;
-    if (dseg >= 3 && dseg <= dmax && n + 1 >= dseg) {
+    if (dseg >= kDlvMinDelay && dseg <= dmax && n + 1 >= dseg) {
       slt = (uint32_t)((n + 1 - dseg) % R);
       cnt = nd.ring_cnt[slt];
     }
@@ -1190,7 +1166,7 @@ __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t
       const uint64_t j = j0 + (uint64_t)q * kB + threadIdx.x;
       if (j >= mine) continue;
       const uint64_t e = b + (uint64_t)G * j;
-      uint32_t lo = 3, hi = 65;  // segment d: seg[d] <= e < seg[d + 1]
+      uint32_t lo = kDlvMinDelay, hi = 65;  // segment d: seg[d] <= e < seg[d + 1]
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (sh.seg[mid] <= e) lo = mid; else hi = mid;
@@ -1212,8 +1188,8 @@ __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t
 
 // One simulation step n, direct delivery: blocks [0, nblk_upd) update the
 // neurons (LIF exact integration, Sec. 2.1/2.3; AdEx RK45, Sec. 2.1/2.4),
-// emit their spikes and deliver their delay-1 and delay-2 groups; the
-// remaining blocks deliver the earlier steps' spikes whose delay (>= 3)
+// emit their spikes and deliver their delay-1 groups; the remaining blocks
+// deliver the earlier steps' spikes whose delay (>= 2)
 // expires now.  The update reads the input buffer of step n; deliveries go to
 // the buffers of the steps they arrive at.
 template <bool kLif, int kAd, int P>
@@ -1229,9 +1205,9 @@ __global__ void __launch_bounds__(kB) k_step(NetDev nd, uint32_t rel) {
 }
 
 // One simulation step n, binned delivery: blocks [0, n_tiles) are the tile
-// blocks (input from their bins, update, emission, delay-1 and delay-2
-// binning), the remaining blocks bin the earlier steps' spikes whose delay
-// expires now.
+// blocks (input from their bins, update, emission, delay-1 binning), the
+// remaining blocks bin the earlier steps' spikes whose delay (>= 2) expires
+// now.
 template <bool kLif, int kAd, int P>
 __global__ void __launch_bounds__(kB) k_step_binned(NetDev nd, uint32_t rel) {
   __shared__ BinStepLds lds;

@@ -5,14 +5,14 @@
 //     LIF-exp: I_syn[N][P];  AdEx: w, g[N][P], h, and with beta ports the
 //     rising variables r[N][P];  refr (int32) for LIF;  spike generators:
 //     their emission steps (CSR by neuron) and a cursor per neuron.
-//   acc[3][N][P]  int64 fixed-point input, one buffer per arrival step
-//                 n, n+1, n+2 (index step % 3; direct delivery: all input;
+//   acc[2][N][P]  int64 fixed-point input, one buffer per arrival step n
+//                 (read) and n+1 (written) (index step % 2; direct: all input;
 //                 binned delivery: only the events that did not fit their
 //                 tile's bin).
 //   binned delivery: targets are cut into tiles of 2^tile_shift neurons;
-//     bins[3][bins_total] u32 entries local << 15 | mult << 10 | class, the
+//     bins[2][bins_total] u32 entries local << 15 | mult << 10 | class, the
 //     tile t region at bin_off[t] holding up to bin_cap[t] entries,
-//     bin_cnt[3][n_tiles] entries written, ovf_flag[3][n_tiles] set when a
+//     bin_cnt[2][n_tiles] entries written, ovf_flag[2][n_tiles] set when a
 //     tile's events spilled into acc.
 //   CSR by (source, delay group):
 //     src_mask[N]   u64, bit d set <=> source has a group with delay d steps
@@ -41,7 +41,7 @@ constexpr int kMultShift = 27;
 constexpr uint32_t kGidMask = (1u << kMultShift) - 1;
 constexpr uint32_t kMaxMult = 31;
 constexpr int kUpdBlock = 256;      // neurons per update block
-constexpr int kInBuf = 3;           // input buffers: arrival steps n, n+1, n+2
+constexpr int kInBuf = 2;           // input buffers: arrival steps n (read) and n+1 (written)
 constexpr int kBlkStats = 5;   // per update block: rk accepted, rk rejected, spikes, delay-1 pairs, events
 constexpr int kTileAccWords = 4096; // int64 LDS accumulators of a tile block (tile neurons x ports)
 constexpr uint32_t kMaxTiles = 1024; // tiles of the binned delivery

@@ -76,7 +76,7 @@ def estimate_bytes(spec: dict) -> int:
     n = W.total_neurons(spec)
     syn = W.count_synapses(spec)
     ports = max(p["ports"] for p in spec["populations"])
-    per_neuron = 64 + 16 * RECORD_SLOTS + 4 * 1301 + 3 * 8 * ports
+    per_neuron = 64 + 16 * RECORD_SLOTS + 4 * 1301 + 2 * 8 * ports
     return 2 * (4 * syn + n * per_neuron)
 
 
