@@ -256,7 +256,7 @@ snn_status snn_get_samples(snn_net* net, uint32_t meter_id, uint64_t* steps, dou
                            size_t* n_out);
 /* ---- checkpoint / resume ---------------------------------------------------- */
 /* Snapshot of a built network's dynamic state after the steps simulated so
-   far: neuron state, pending input (buffers of the next three steps, bins
+   far: neuron state, pending input (buffers of this and the next step, bins
    and spill), the spike records delivery still reads, the step books and the
    statistics.  snn_snapshot_size gives the bytes; snn_snapshot writes them
    into the caller's host buffer (SNN_E_INVALID if cap is smaller).

@@ -3,7 +3,7 @@
 The shapes that do not change results (every sum is over integers) but do
 change speed are chosen by timing: direct or binned delivery, the tile size of
 binned delivery (neurons per tile block, which is also the work-queue size of
-the RK45 update) and the number of blocks that deliver the delays >= 3.  Each
+the RK45 update) and the number of blocks that deliver the delays >= 2.  Each
 candidate is built as a fresh copy of the network, run for a warm-up and then
 timed over a short window; the fastest wins.  Results are kept per network
 signature for the life of the process (and in a JSON file if one is given).

@@ -1105,7 +1105,7 @@ snn_status snn_build(snn_net* net) {
   NetDev& nd = net->nd;
   memset(&nd, 0, sizeof nd);
   nd.N = N; nd.P = P; nd.npop = npop; nd.dmax = dmax_used;
-  // step slots: the steps delivery reads (n+1-Dmax .. n-2), the previous step's
+  // step slots: the steps delivery reads (n+1-Dmax .. n-1), the previous step's
   // count, the current step's counter and the next step's (cleared): >= 3
   nd.R = std::max<uint32_t>(dmax_used + 1, 3);
   nd.npois = (uint32_t)(pois_thr.size() / kPoisKmax);
