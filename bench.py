@@ -60,10 +60,10 @@ BYTES_PER_PAIR = 28
 BYTES_PER_SPIKE = 28
 
 
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, tile_neurons: int = 0):
     """HBM bytes per launch of the step kernel from the committed counter
     summary, or None when the kernel sources have changed since it was taken
-    (or it was taken for another kernel on this workload)."""
+    (or it was taken for another kernel or tile size on this workload)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -75,9 +75,10 @@ def measured_traffic(workload: str, kernel: str):
             h.update(f.read())
     if h.hexdigest() != rec["kernel_sources_sha256"] or workload not in rec["workloads"]:
         return None
-    if rec["workloads"][workload]["kernel"] != kernel:
+    ent = rec["workloads"][workload]
+    if ent["kernel"] != kernel or ent.get("tile_neurons", tile_neurons) != tile_neurons:
         return None
-    return rec["workloads"][workload]["bytes_per_launch"]
+    return ent["bytes_per_launch"]
 
 
 def bytes_per_step_neurons(spec: dict, delivery: str) -> int:
@@ -96,6 +97,39 @@ def bytes_per_step_neurons(spec: dict, delivery: str) -> int:
             b += 8 * ports
         tot += b * p["n"]
     return tot
+
+
+def step_roofline(net, specs: list, mode: str, profile_steps: int, workload: str) -> dict:
+    """HBM roofline of the step kernel: `profile_steps` further steps timed
+    with HIP events on the library's stream, the algorithmic bytes of those
+    steps (per-neuron state, per event, per selected pair, per spike) over
+    the average launch, and the measured traffic where it is on record."""
+    c2 = net.counters()
+    prof = net.profile(profile_steps)
+    c3 = net.counters()
+    ps = max(1, profile_steps)
+    ev_p = (c3["events"] - c2["events"]) / ps
+    pr_p = (c3["pairs"] - c2["pairs"]) / ps
+    sp_p = (c3["spikes"] - c2["spikes"]) / ps
+    dlv_ms = prof["step"] / ps
+    kernel = "k_step_binned" if mode == "binned" else "k_step"
+    neuron_bytes = sum(bytes_per_step_neurons(sp, mode) for sp in specs)
+    dlv_bytes = neuron_bytes + ev_p * BYTES_PER_EVENT[mode] + pr_p * BYTES_PER_PAIR + sp_p * BYTES_PER_SPIKE
+    achieved = dlv_bytes / (dlv_ms * 1e-3) / 1e9 if dlv_ms > 0 else 0.0
+    return {
+        "kernel": kernel, "bound": "hbm",
+        "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": measured_traffic(workload, kernel, c3["tile_neurons"]),
+        "avg_launch_us": round(dlv_ms * 1e3, 3), "bytes_per_launch": round(dlv_bytes),
+        "neuron_bytes_per_launch": neuron_bytes,
+        "events_per_launch": round(ev_p, 1), "pairs_per_launch": round(pr_p, 1),
+        "spikes_per_launch": round(sp_p, 1), "delivery": mode, "tile_neurons": c3["tile_neurons"],
+        "spill_events": c3["spill_events"],
+        "events_per_s_in_kernel": round(ev_p / (dlv_ms * 1e-3), 1) if dlv_ms > 0 else None,
+        "kernel_us_per_step": {k: round(v * 1e3 / ps, 3) for k, v in prof.items()},
+        "dominant_kernel_by_time": max(prof, key=prof.get),
+    }
 
 
 def parse():
@@ -234,33 +268,11 @@ def main():
     print(f"[bench] {args.steps} steps in {wall:.3f} s (RTF {wall / bio_s:.4f}); profiling "
           f"{args.profile_steps} steps", file=sys.stderr, flush=True)
 
-    # per-kernel device time with HIP events on the library's stream
     c2 = net.counters()
-    prof = net.profile(args.profile_steps)
+    roofline = step_roofline(net, [spec], mode, args.profile_steps, args.workload)
     c3 = net.counters()
     ps = max(1, args.profile_steps)
-    ev_p = (c3["events"] - c2["events"]) / ps
-    pr_p = (c3["pairs"] - c2["pairs"]) / ps
-    sp_p = (c3["spikes"] - c2["spikes"]) / ps
-    dlv_ms = prof["step"] / ps
-    dominant = max(prof, key=prof.get)
-    neuron_bytes = bytes_per_step_neurons(spec, mode)
-    dlv_bytes = neuron_bytes + ev_p * BYTES_PER_EVENT[mode] + pr_p * BYTES_PER_PAIR + sp_p * BYTES_PER_SPIKE
-    achieved = dlv_bytes / (dlv_ms * 1e-3) / 1e9 if dlv_ms > 0 else 0.0
-    roofline = {
-        "kernel": "k_step_binned" if mode == "binned" else "k_step", "bound": "hbm",
-        "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-        "traffic": measured_traffic(args.workload, "k_step_binned" if mode == "binned" else "k_step"),
-        "avg_launch_us": round(dlv_ms * 1e3, 3), "bytes_per_launch": round(dlv_bytes),
-        "neuron_bytes_per_launch": neuron_bytes,
-        "events_per_launch": round(ev_p, 1), "pairs_per_launch": round(pr_p, 1),
-        "spikes_per_launch": round(sp_p, 1), "delivery": mode, "tile_neurons": c3["tile_neurons"],
-        "spill_events": c3["spill_events"],
-        "events_per_s_in_kernel": round(ev_p / (dlv_ms * 1e-3), 1) if dlv_ms > 0 else None,
-        "kernel_us_per_step": {k: round(v * 1e3 / ps, 3) for k, v in prof.items()},
-        "dominant_kernel_by_time": dominant,
-    }
+    dlv_ms = roofline["avg_launch_us"] * 1e-3
     out = {
         "metric": METRIC,
         "value": events / wall,
@@ -402,7 +414,10 @@ def bench_sweep(args, S, W, torch):
     wall = time.perf_counter() - t0
     c1 = net.counters()
     events = c1["events"] - c0["events"]
-    print(f"[bench] batch: {steps} steps in {wall:.3f} s; sequential sample next", file=sys.stderr, flush=True)
+    print(f"[bench] batch: {steps} steps in {wall:.3f} s; profiling {args.profile_steps} steps", file=sys.stderr,
+          flush=True)
+    roofline = step_roofline(net, specs, mode, args.profile_steps, "sweep")
+    print("[bench] sequential sample next", file=sys.stderr, flush=True)
     net.close()
     del net
     # sequential baseline: a sample of the instances, one at a time, same steps,
@@ -442,7 +457,8 @@ def bench_sweep(args, S, W, torch):
            "config": {"workload": f"batched sweep of {args.instances} Brunel LIF instances, N in [2k, 40k], "
                                   "in-degree 0.1 N, g in [3,7], drive 10-30 Hz, delays U[0.1,3) ms",
                       "neurons": sum(sizes), "synapses": sum(W.count_synapses(sp) for sp in specs),
-                      "t_bio_s": bio, "parallelism": "single GPU"}}
+                      "t_bio_s": bio, "parallelism": "single GPU"},
+           "roofline": roofline}
     print(json.dumps(out), flush=True)
 
 
