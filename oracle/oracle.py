@@ -24,8 +24,20 @@ VAR_IDS = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6, "g
 # connection rules; a projection's "K" is the in-degree, the out-degree or the
 # number of synapses (unused for all_to_all and one_to_one)
 RULE_IDS = {"fixed_indegree": 0, "fixed_outdegree": 1, "all_to_all": 2, "one_to_one": 3, "fixed_total_number": 4}
+WEIGHT_IDS = {"uniform": 0, "normal": 1}
 MAX_PORTS = 4
 POISSON_KMAX = 128
+
+
+def weight_dist_args(wd: dict):
+    """(kind, a, b, lo, hi, levels) of a weight distribution: uniform on
+    [low, high), or normal(mean, sd) truncated to [low, high] (default
+    mean -+ 4 sd); `levels` bins (default 64)."""
+    L = int(wd.get("levels", 64))
+    if wd["kind"] == "uniform":
+        return WEIGHT_IDS["uniform"], float(wd["low"]), float(wd["high"]), 0.0, 0.0, L
+    m, sd = float(wd["mean"]), float(wd["sd"])
+    return (WEIGHT_IDS["normal"], m, sd, float(wd.get("low", m - 4 * sd)), float(wd.get("high", m + 4 * sd)), L)
 
 
 class PopParams(C.Structure):
@@ -73,6 +85,9 @@ def lib():
         L.orc_population.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(PopParams)]
         L.orc_set_spike_times.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
         L.orc_connect_list.argtypes = [C.c_void_p, C.c_uint64, P32, P32, PD, C.c_double, C.c_uint32]
+        L.orc_weight_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_double, C.c_double, C.c_double,
+                                              C.c_double, C.c_uint32]
+        L.orc_list_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
         L.orc_connect.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                   C.c_double, C.c_int, C.c_double, C.c_double, C.c_uint32]
         L.orc_connect_fixed_indegree.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -254,20 +269,25 @@ class OracleNet:
                 self._check(self.L.orc_set_spike_times(self.h, self.ranges[p["name"]][0] + j, len(t),
                                                        _ptr(t, C.c_double)) == 0)
         self.P = max(p["ports"] for p in spec["populations"])
-        for pr in spec["projections"]:
+        for ip, pr in enumerate(spec["projections"]):
             if pr.get("rule") == "list":  # user-defined: gids counted from the specification's first neuron
                 src = np.ascontiguousarray(pr["src_gids"], dtype=np.uint32)
                 tgt = np.ascontiguousarray(pr["tgt_gids"], dtype=np.uint32)
                 dl = np.ascontiguousarray(pr["delays_ms"], dtype=np.float64)
                 self._check(self.L.orc_connect_list(self.h, len(src), _ptr(src, C.c_uint32), _ptr(tgt, C.c_uint32),
-                                                    _ptr(dl, C.c_double), pr["weight"], pr["port"]) == 0)
+                                                    _ptr(dl, C.c_double), pr.get("weight", 0.0), pr["port"]) == 0)
+                if pr.get("weights") is not None and len(src):
+                    w = np.ascontiguousarray(pr["weights"], dtype=np.float64)
+                    self._check(self.L.orc_list_weights(self.h, ip, len(w), _ptr(w, C.c_double)) == 0)
                 continue
             s0, sn = self.ranges[pr["src"]]
             t0, tn = self.ranges[pr["tgt"]]
             kind, a, b = (list(pr["delay"]) + [0.0, 0.0])[:3]
             rule = RULE_IDS[pr.get("rule", "fixed_indegree")]
-            self._check(self.L.orc_connect(self.h, rule, int(pr.get("K", 0)), s0, sn, t0, tn, pr["weight"],
+            self._check(self.L.orc_connect(self.h, rule, int(pr.get("K", 0)), s0, sn, t0, tn, pr.get("weight", 0.0),
                                            DELAY_IDS[kind], a, b, pr["port"]) == 0)
+            if pr.get("weight_dist") is not None:
+                self._check(self.L.orc_weight_distribution(self.h, ip, *weight_dist_args(pr["weight_dist"])) == 0)
         for q in spec.get("poisson", []):
             t0, tn = self.ranges[q["tgt"]]
             self._check(self.L.orc_poisson(self.h, t0, tn, q["rate"], q["n_inputs"], q["weight"],

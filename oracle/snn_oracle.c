@@ -134,6 +134,12 @@ typedef struct {
   uint32_t* lsrc; uint32_t* ltgt; uint8_t* ldel;  /* user-defined list */
   double weight;
   uint64_t dthr[64];
+  /* weight levels (0: the fixed weight): values, draw thresholds (drawn
+     levels) or the level of every listed synapse (lists) */
+  uint32_t wlevels;
+  double* wlev;
+  uint64_t* wthr;
+  uint16_t* lwl;
 } orc_proj;
 
 typedef struct {
@@ -207,7 +213,10 @@ orc_net* orc_create(double dt_ms, uint64_t seed, uint32_t max_delay_steps, int m
 
 void orc_destroy(orc_net* o) {
   if (!o) return;
-  for (uint32_t p = 0; p < o->n_proj; ++p) { free(o->proj[p].lsrc); free(o->proj[p].ltgt); free(o->proj[p].ldel); }
+  for (uint32_t p = 0; p < o->n_proj; ++p) {
+    free(o->proj[p].lsrc); free(o->proj[p].ltgt); free(o->proj[p].ldel);
+    free(o->proj[p].wlev); free(o->proj[p].wthr); free(o->proj[p].lwl);
+  }
   free(o->pops); free(o->pop_first); free(o->pop_of); free(o->proj); free(o->pois); free(o->pois_of);
   free(o->shift); free(o->syn); free(o->off);
   free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->gr); free(o->I); free(o->h); free(o->refr);
@@ -324,6 +333,77 @@ int orc_connect_fixed_indegree(orc_net* o, uint32_t src_first, uint32_t src_n, u
                                double da, double db, uint32_t port) {
   return orc_connect(o, ORC_RULE_FIXED_INDEGREE, indegree, src_first, src_n, tgt_first, tgt_n, weight, delay_kind,
                      da, db, port);
+}
+
+/* Weight distributions: the discretisation stated in the header.  F is the
+   distribution function (uniform: (x - a) / (b - a); normal:
+   erfc(-(x - a) / (b sqrt 2)) / 2). */
+static int dbl_cmp(const void* pa, const void* pb) {
+  double a = *(const double*)pa, b = *(const double*)pb;
+  return a < b ? -1 : a > b ? 1 : 0;
+}
+
+static double weight_cdf(int kind, double a, double b, double x) {
+  if (kind == ORC_WEIGHT_UNIFORM) return (x - a) / (b - a);
+  return 0.5 * erfc(-(x - a) / (b * sqrt(2.0)));
+}
+
+int orc_weight_distribution(orc_net* o, uint32_t proj, int kind, double a, double b, double lo, double hi,
+                            uint32_t levels) {
+  if (o->built || o->shift) { set_err(o, "weights after build"); return -1; }
+  if (proj >= o->n_proj || o->proj[proj].rule == ORC_RULE_LIST) { set_err(o, "projection"); return -1; }
+  if (levels < 1 || levels > ORC_WEIGHT_LEVELS_MAX) { set_err(o, "levels"); return -1; }
+  if (kind == ORC_WEIGHT_UNIFORM) {
+    if (!(a < b)) { set_err(o, "uniform weights need a < b"); return -1; }
+    lo = a; hi = b;
+  } else if (kind == ORC_WEIGHT_NORMAL) {
+    if (!(b > 0) || !(lo < hi)) { set_err(o, "normal weights need sigma > 0 and lo < hi"); return -1; }
+  } else {
+    set_err(o, "weight distribution"); return -1;
+  }
+  double Flo = weight_cdf(kind, a, b, lo), Fhi = weight_cdf(kind, a, b, hi);
+  if (!(Fhi > Flo)) { set_err(o, "no probability in [lo, hi]"); return -1; }
+  orc_proj* pr = &o->proj[proj];
+  free(pr->wlev); free(pr->wthr);
+  pr->wlev = (double*)malloc(levels * sizeof(double));
+  pr->wthr = (uint64_t*)malloc(levels * sizeof(uint64_t));
+  pr->wlevels = levels;
+  for (uint32_t j = 0; j < levels; ++j) {
+    pr->wlev[j] = lo + (hi - lo) * (((double)j + 0.5) / (double)levels);
+    if (j + 1 == levels) { pr->wthr[j] = 1ull << 32; continue; }
+    double edge = lo + (hi - lo) * ((double)(j + 1) / (double)levels);
+    double q = (weight_cdf(kind, a, b, edge) - Flo) / (Fhi - Flo);
+    double t = floor(q * 4294967296.0);
+    if (t < 0) t = 0;
+    if (t > 4294967296.0) t = 4294967296.0;
+    pr->wthr[j] = (uint64_t)t;
+  }
+  return 0;
+}
+
+int orc_list_weights(orc_net* o, uint32_t proj, uint64_t n, const double* weights) {
+  if (o->built || o->shift) { set_err(o, "weights after build"); return -1; }
+  if (proj >= o->n_proj || o->proj[proj].rule != ORC_RULE_LIST || o->proj[proj].n != n) {
+    set_err(o, "list projection"); return -1;
+  }
+  /* levels: the distinct listed values, ascending (a library sort) */
+  double* v = (double*)malloc((n ? n : 1) * sizeof(double));
+  memcpy(v, weights, n * sizeof(double));
+  qsort(v, (size_t)n, sizeof(double), dbl_cmp);
+  uint64_t m = 0;
+  for (uint64_t j = 0; j < n; ++j)
+    if (m == 0 || v[j] != v[m - 1]) v[m++] = v[j];
+  if (m > ORC_WEIGHT_LEVELS_MAX) { free(v); set_err(o, "too many distinct weights"); return -1; }
+  orc_proj* pr = &o->proj[proj];
+  free(pr->wlev); free(pr->lwl);
+  pr->wlev = v; pr->wlevels = (uint32_t)m;
+  pr->lwl = (uint16_t*)malloc((n ? n : 1) * sizeof(uint16_t));
+  for (uint64_t j = 0; j < n; ++j) {
+    uint64_t lo = 0, hi = m;  /* the level holding weights[j] */
+    while (hi - lo > 1) { uint64_t mid = (lo + hi) / 2; if (v[mid] <= weights[j]) lo = mid; else hi = mid; }
+    pr->lwl[j] = (uint16_t)lo;
+  }
+  return 0;
 }
 
 static void alloc_state(orc_net* o);
@@ -495,7 +575,12 @@ static int prepare(orc_net* o) {
       if (pr->tgt_first < hi && pr->tgt_first + pr->tgt_n > lo) {
         if (pr->port >= o->pops[k].n_ports) { set_err(o, "port out of range"); free(maxw); return -1; }
         double aw = fabs(pr->weight);
+        for (uint32_t j = 0; j < pr->wlevels; ++j) aw = j ? fmax(aw, fabs(pr->wlev[j])) : fabs(pr->wlev[j]);
         if (aw > maxw[k * P + pr->port]) maxw[k * P + pr->port] = aw;
+        /* conductances jump by the weight: none may be negative */
+        int cond = o->pops[k].model == ORC_AEIF_COND_EXP || o->pops[k].model == ORC_AEIF_COND_BETA;
+        int neg = pr->wlevels ? pr->wlev[0] < 0 : pr->weight < 0;
+        if (cond && neg) { set_err(o, "conductance weights must be >= 0"); free(maxw); return -1; }
       }
     }
   }
@@ -519,7 +604,8 @@ static int prepare(orc_net* o) {
     uint32_t lo = o->pop_first[k], hi = (k + 1 < o->n_pops) ? o->pop_first[k + 1] : o->N;
     for (uint32_t p = 0; p < o->n_proj; ++p) {
       const orc_proj* pr = &o->proj[p];
-      if (proj_synapses(pr) && pr->tgt_first < hi && pr->tgt_first + pr->tgt_n > lo && pr->weight != 1.0) {
+      int unit = pr->wlevels ? (pr->wlevels == 1 && pr->wlev[0] == 1.0) : pr->weight == 1.0;
+      if (proj_synapses(pr) && pr->tgt_first < hi && pr->tgt_first + pr->tgt_n > lo && !unit) {
         set_err(o, "weights onto parrot neurons must be 1"); return -1;
       }
     }
@@ -582,6 +668,26 @@ static void draw_synapse(const orc_net* o, uint32_t p, uint64_t e, uint32_t k, u
   else { *tgt = (uint32_t)e; *src = pr->src_first + k; }  /* all-to-all */
 }
 
+/* quantised weight of synapse k of entity e of projection p onto target t:
+   the fixed weight, the level of a listed synapse, or the level drawn by the
+   weight distribution (block of tag WEIGHT; wblk holds the block of the four
+   draws k belongs to) */
+static int64_t synapse_wq(const orc_net* o, uint32_t p, uint64_t e, uint32_t k, uint32_t t, uint64_t wblk[4]) {
+  const orc_proj* pr = &o->proj[p];
+  int S = o->shift[o->pop_of[t] * o->P + pr->port];
+  if (pr->wlevels == 0) return llrint(ldexp(pr->weight, S));
+  if (pr->rule == ORC_RULE_LIST) return llrint(ldexp(pr->wlev[pr->lwl[e]], S));
+  if ((k & 3u) == 0) {
+    uint64_t key[2] = {o->seed, 0};
+    uint64_t ctr[4] = {e, ((uint64_t)p << 40) | (uint64_t)(k >> 2), ORC_TAG_WEIGHT, 0};
+    orc_philox4x64_10(ctr, key, wblk);
+  }
+  uint32_t u = (uint32_t)(wblk[k & 3u] >> 32);
+  uint32_t j = 0;
+  while ((uint64_t)u >= pr->wthr[j]) ++j;
+  return llrint(ldexp(pr->wlev[j], S));
+}
+
 int orc_prepare(orc_net* o) { return prepare(o); }
 
 int orc_build(orc_net* o) {
@@ -603,13 +709,13 @@ int orc_build(orc_net* o) {
     uint64_t first = pr->rule == ORC_RULE_FIXED_OUTDEGREE ? pr->src_first : per_syn ? 0 : pr->tgt_first;
     uint32_t kn = per_syn ? 1u : pr->K;
     for (uint64_t j = 0; j < ne; ++j) {
-      uint64_t blk[4] = {0, 0, 0, 0};
+      uint64_t blk[4] = {0, 0, 0, 0}, wblk[4] = {0, 0, 0, 0};
       for (uint32_t k = 0; k < kn; ++k) {
         uint32_t s, t, d;
         draw_synapse(o, p, first + j, k, blk, &s, &t, &d);
         orc_syn sy;
         sy.src = s; sy.tgt = t; sy.port = (uint8_t)pr->port; sy.d = (uint8_t)d;
-        sy.wq = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * P + pr->port]));
+        sy.wq = synapse_wq(o, p, first + j, k, t, wblk);
         o->syn[pos++] = sy;
       }
     }
@@ -964,11 +1070,11 @@ int64_t orc_target_synapses(orc_net* o, uint32_t t, uint64_t cap, uint32_t* src,
     if (pr->rule == ORC_RULE_FIXED_OUTDEGREE || pr->rule == ORC_RULE_FIXED_TOTAL_NUMBER || pr->rule == ORC_RULE_LIST) {
       set_err(o, "the rule does not draw per target"); return -1;
     }
-    int64_t w = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * o->P + pr->port]));
-    uint64_t blk[4] = {0, 0, 0, 0};
+    uint64_t blk[4] = {0, 0, 0, 0}, wblk[4] = {0, 0, 0, 0};
     for (uint32_t k = 0; k < pr->K; ++k, ++n) {
       uint32_t s, tt, dd;
       draw_synapse(o, p, t, k, blk, &s, &tt, &dd);
+      int64_t w = synapse_wq(o, p, t, k, t, wblk);
       if (n < cap) { src[n] = s; d[n] = dd; port[n] = pr->port; wq[n] = w; }
     }
   }
@@ -1005,11 +1111,11 @@ int orc_sampled_input(orc_net* o, uint32_t nt, const uint32_t* tgt, uint64_t n_s
           pr->rule == ORC_RULE_LIST) {
         set_err(o, "the rule does not draw per target"); return -1;
       }
-      int64_t w = llrint(ldexp(pr->weight, o->shift[o->pop_of[t] * P + pr->port]));
-      uint64_t blk[4] = {0, 0, 0, 0};
+      uint64_t blk[4] = {0, 0, 0, 0}, wblk[4] = {0, 0, 0, 0};
       for (uint32_t k = 0; k < pr->K; ++k) {
         uint32_t s, tt, d;
         draw_synapse(o, p, t, k, blk, &s, &tt, &d);
+        int64_t w = synapse_wq(o, p, t, k, t, wblk);
         if (target_step < d) continue;
         out[(size_t)j * P + pr->port] += (int64_t)spike_mult(n_spk, step, gid, mult, target_step - d, s) * w;
       }

@@ -31,7 +31,8 @@ enum { ORC_FP64 = 0, ORC_FP32SO = 1 };
 enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2, ORC_AEIF_COND_BETA = 3,
        ORC_SPIKE_GENERATOR = 4, ORC_PARROT = 5 };
 enum { ORC_DELAY_CONST = 0, ORC_DELAY_UNIFORM = 1, ORC_DELAY_NORMAL_CLIPPED = 2 };
-enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2 };
+enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2, ORC_TAG_WEIGHT = 3 };
+enum { ORC_WEIGHT_UNIFORM = 0, ORC_WEIGHT_NORMAL = 1, ORC_WEIGHT_LEVELS_MAX = 1024 };
 /* connection rules (Sec. 2.1): the count n is the in-degree, the out-degree,
    unused, unused, and the number of synapses, in that order */
 enum { ORC_RULE_FIXED_INDEGREE = 0, ORC_RULE_FIXED_OUTDEGREE = 1, ORC_RULE_ALL_TO_ALL = 2,
@@ -84,6 +85,23 @@ int      orc_connect_list(orc_net*, uint64_t n, const uint32_t* src, const uint3
 int      orc_connect(orc_net*, int rule, uint64_t n, uint32_t src_first, uint32_t src_n,
                      uint32_t tgt_first, uint32_t tgt_n, double weight, int delay_kind, double da,
                      double db, uint32_t port);
+/* Weights drawn from a probability distribution (Sec. 2.1), discretised:
+   the range [lo, hi] is cut into `levels` equal bins and a synapse takes the
+   midpoint of bin j, w_j = lo + (hi - lo) (j + 1/2) / levels, with the
+   probability the distribution, restricted to [lo, hi], gives that bin.
+   kind ORC_WEIGHT_UNIFORM: uniform on [a, b) (lo, hi ignored; a < b);
+   kind ORC_WEIGHT_NORMAL: normal of mean a and deviation b > 0, truncated to
+   [lo, hi].  The draw of synapse k of entity e (the first counter word of its
+   connection draw) is the top 32 bits of word k&3 of block
+   (e, p<<40 | k>>2, ORC_TAG_WEIGHT, 0) against thresholds
+   T_j = floor(2^32 (F(e_{j+1}) - F(lo)) / (F(hi) - F(lo))), e_{j+1} the upper
+   edge of bin j, T_{levels-1} = 2^32: the level is min{j : u32 < T_j}.
+   Applies to projection `proj` (creation index, not a list). */
+int      orc_weight_distribution(orc_net*, uint32_t proj, int kind, double a, double b, double lo, double hi,
+                                 uint32_t levels);
+/* per-connection weights of a user-defined list projection (weights[j] for
+   synapse j); at most ORC_WEIGHT_LEVELS_MAX distinct values */
+int      orc_list_weights(orc_net*, uint32_t proj, uint64_t n, const double* weights);
 int      orc_poisson(orc_net*, uint32_t tgt_first, uint32_t tgt_n, double rate_hz,
                      uint32_t n_inputs, double weight, uint32_t port);
 /* Devices (Sec. 2.1).  A spike generator emits, in the update of step n, as
