@@ -237,6 +237,37 @@ snn_status snn_connect_list(snn_net* net, size_t n, const uint32_t* src, const u
 snn_status snn_connect(snn_net* net, int32_t rule, uint64_t n, uint32_t src_first, uint32_t src_n,
                        uint32_t tgt_first, uint32_t tgt_n, double weight, int32_t delay_kind, double delay_a,
                        double delay_b, uint32_t port);
+/* Connection weights from a probability distribution (Sec. 2.1, weights
+   "through probability distributions"), for the projection created last
+   (snn_connect / snn_connect_fixed_indegree; its `weight` is then unused).
+   The distribution is discretised: [lo, hi] is cut into `levels` equal bins
+   and a synapse takes the midpoint of bin j,
+     w_j = lo + (hi - lo) (j + 1/2) / levels,
+   with the probability the distribution, restricted to [lo, hi], gives that
+   bin.  SNN_WEIGHT_UNIFORM: uniform on [a, b) (lo, hi ignored);
+   SNN_WEIGHT_NORMAL: normal of mean a and standard deviation b, truncated to
+   [lo, hi].  Synapse k of entity e (the first counter word of its connection
+   draw) draws the top 32 bits of word k&3 of Philox block
+   (e, p << 40 | k >> 2, tag 3) against thresholds
+   T_j = floor(2^32 (F(e_{j+1}) - F(lo)) / (F(hi) - F(lo))) (e_{j+1} the
+   upper edge of bin j, T_{levels-1} = 2^32); its level is min{j : u < T_j}.
+   Every (port, quantised level) pair of every target population takes one
+   of the network's weight classes (at most 1024, fewer above 2^22 neurons:
+   SNN_E_UNSUPPORTED at build).  SNN_E_STATE after build or with no
+   projection; SNN_E_INVALID for a list projection, levels outside 1..1024,
+   a <= b (uniform), b <= 0 or lo >= hi (normal), no probability in [lo, hi];
+   at build, negative levels onto conductance ports or levels other than a
+   single 1 onto parrot neurons. */
+#define SNN_WEIGHT_UNIFORM 0
+#define SNN_WEIGHT_NORMAL 1
+snn_status snn_weight_distribution(snn_net* net, int32_t kind, double a, double b, double lo, double hi,
+                                   uint32_t levels);
+/* Per-connection weights (Sec. 2.1, weights "through arrays") of the list
+   projection created last by snn_connect_list: weights[j] for its synapse j
+   (host array of n doubles, copied; n must equal the list's length; n == 0
+   does nothing).  The distinct values become weight classes as above (at
+   most 1024 distinct values, SNN_E_UNSUPPORTED beyond). */
+snn_status snn_list_weights(snn_net* net, const double* weights, size_t n);
 /* Multimeter (Sec. 2.1), before snn_build: record state variable `var`
    (SNN_V_M, SNN_V_W, SNN_V_G, SNN_V_G_RISE, SNN_V_I_SYN or SNN_V_H; `port` for
    the per-port ones) of the n neurons gids[0..n) after the update of every

@@ -8,12 +8,23 @@
 namespace snn {
 
 // ---- connectivity build ----
+// Weight levels of one projection (empty: its single weight): the class of
+// level j onto a target of population k is cls[(k - pop0) * levels + j];
+// drawn projections take j from thr (u32 draws), lists from lvl[synapse].
+struct ProjW {
+  const uint64_t* thr;
+  const uint16_t* cls;
+  const uint16_t* lvl;
+  uint32_t levels, pop0;
+};
+
 // total_pairs = sum over projections of tgt_n * ceil(K / 2)
 hipError_t launch_gen_count(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint32_t dmax_cfg,
                             uint32_t D1, uint32_t* cnt, hipStream_t s);
 hipError_t launch_gen_scatter(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint32_t dmax_cfg,
                               uint32_t D1, uint64_t* cursor, uint32_t* payload, const uint16_t* cls_of,
-                              const uint32_t* pop_first, uint32_t npop, uint32_t cls_bits, hipStream_t s);
+                              const ProjW* pw, const uint32_t* pop_first, uint32_t npop, uint32_t cls_bits,
+                              hipStream_t s);
 // exclusive scan of n u32 (in32) or u64 (in64) values into out; *total_dev receives the sum.
 // tmp must hold scan_tmp_words(n) u64 words.
 size_t scan_tmp_words(uint64_t n);

@@ -14,7 +14,11 @@
 //                       1 (target), 2 (delay);
 //   user-defined     -- synapse j as listed (no draw).
 // A uniform index in a range of m is floor(u m / 2^64); a delay is the top 32
-// bits of its word against the projection's threshold table.
+// bits of its word against the projection's threshold table.  A weight drawn
+// from a distribution (Sec. 2.1) is the level of the top 32 bits of word k&3
+// of block (c0, p << 40 | k >> 2) with tag WEIGHT, c0 the first counter word
+// of the synapse's connection draw and k its draw index (0 for one-to-one
+// and the fixed total number), against the level thresholds.
 //
 // Layout (Sec. 2.2, Fig. 1): synapses grouped per source into connection
 // groups of equal delay, groups ordered by delay.  Build = counting sort by
@@ -29,6 +33,7 @@ namespace snn {
 namespace {
 
 constexpr int kB = 256;
+constexpr int kTagWeight = 3;  // Philox tag of the weight draws (connections 1, Poisson 2)
 
 __device__ __forceinline__ uint32_t find_proj(const ProjDev* projs, uint32_t nproj, uint64_t q) {
   uint32_t lo = 0, hi = nproj;  // largest p with pair_begin <= q
@@ -42,6 +47,16 @@ __device__ __forceinline__ uint32_t find_proj(const ProjDev* projs, uint32_t npr
 __device__ __forceinline__ uint32_t draw_delay(const uint64_t* thr, uint32_t dmax, uint32_t u) {
   // smallest d in [1, dmax] with u < thr[d]; thr is non-decreasing, thr[dmax] = 2^32
   uint32_t lo = 1, hi = dmax;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if ((uint64_t)u < thr[mid]) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t draw_level(const uint64_t* thr, uint32_t levels, uint32_t u) {
+  // smallest j with u < thr[j]; thr[levels - 1] = 2^32
+  uint32_t lo = 0, hi = levels - 1;
   while (lo < hi) {
     uint32_t mid = (lo + hi) >> 1;
     if ((uint64_t)u < thr[mid]) hi = mid; else lo = mid + 1;
@@ -66,7 +81,8 @@ template <bool kScatter>
 __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, uint32_t nproj, uint64_t total_pairs,
                                              uint32_t dmax_cfg, uint32_t D1, uint32_t* cnt,
                                              unsigned long long* cursor, uint32_t* payload, const uint16_t* cls_of,
-                                             const uint32_t* pop_first, uint32_t npop, uint32_t cls_bits) {
+                                             const ProjW* pw, const uint32_t* pop_first, uint32_t npop,
+                                             uint32_t cls_bits) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total_pairs; q += stride) {
     const uint32_t p = find_proj(projs, nproj, q);
@@ -83,7 +99,9 @@ __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, u
       if (!kScatter) {
         atomicAdd(&cnt[bucket], 1u);
       } else {
-        const uint32_t cls = cls_of[(size_t)p * npop + find_pop(pop_first, npop, tgt)];
+        const uint32_t k = find_pop(pop_first, npop, tgt);
+        const ProjW& w = pw[p];
+        const uint32_t cls = w.levels ? w.cls[(k - w.pop0) * w.levels + w.lvl[e]] : cls_of[(size_t)p * npop + k];
         const unsigned long long slot = atomicAdd(&cursor[bucket], 1ull);
         payload[slot] = (tgt << cls_bits) | cls;
       }
@@ -93,6 +111,10 @@ __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, u
     const uint64_t c1 = ((uint64_t)pr.index << 40) | kp;
     const U64x4 blk = philox4x64_10(c0, c1, kTagConn, 0, pr.seed, 0);
     const int nh = (pr.rule == kRuleOneToOne || pr.rule == kRuleTotal) ? 1 : 2;
+    // weight draws of this item's synapses (scatter only, drawn projections)
+    U64x4 wblk = {};
+    if (kScatter && pw[p].levels)
+      wblk = philox4x64_10(c0, ((uint64_t)pr.index << 40) | (kp >> 1), kTagWeight, 0, pr.seed, 0);
     for (int h = 0; h < nh; ++h) {
       const uint32_t k = 2 * kp + h;
       if (k >= pr.K) break;
@@ -128,7 +150,15 @@ __global__ void __launch_bounds__(kB) k_gen(const ProjDev* __restrict__ projs, u
       if (!kScatter) {
         atomicAdd(&cnt[bucket], 1u);
       } else {
-        const uint32_t cls = cls_of[(size_t)p * npop + find_pop(pop_first, npop, tgt)];
+        const uint32_t kpop = find_pop(pop_first, npop, tgt);
+        const ProjW& w = pw[p];
+        uint32_t cls;
+        if (w.levels) {
+          const uint32_t j = draw_level(w.thr, w.levels, (uint32_t)(wblk.w[k & 3u] >> 32));
+          cls = w.cls[(kpop - w.pop0) * w.levels + j];
+        } else {
+          cls = cls_of[(size_t)p * npop + kpop];
+        }
         const unsigned long long slot = atomicAdd(&cursor[bucket], 1ull);
         payload[slot] = (tgt << cls_bits) | cls;
       }
@@ -347,17 +377,18 @@ hipError_t launch_gen_count(const ProjDev* projs, uint32_t nproj, uint64_t total
   if (total_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gen<false>, dim3(grid_for(total_pairs, kB, 65536)), dim3(kB), 0, s, projs, nproj, total_pairs,
                      dmax_cfg, D1, cnt, (unsigned long long*)nullptr, (uint32_t*)nullptr, (const uint16_t*)nullptr,
-                     (const uint32_t*)nullptr, 0u, 0u);
+                     (const ProjW*)nullptr, (const uint32_t*)nullptr, 0u, 0u);
   return hipGetLastError();
 }
 
 hipError_t launch_gen_scatter(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint32_t dmax_cfg,
                               uint32_t D1, uint64_t* cursor, uint32_t* payload, const uint16_t* cls_of,
-                              const uint32_t* pop_first, uint32_t npop, uint32_t cls_bits, hipStream_t s) {
+                              const ProjW* pw, const uint32_t* pop_first, uint32_t npop, uint32_t cls_bits,
+                              hipStream_t s) {
   if (total_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gen<true>, dim3(grid_for(total_pairs, kB, 65536)), dim3(kB), 0, s, projs, nproj, total_pairs,
-                     dmax_cfg, D1, (uint32_t*)nullptr, (unsigned long long*)cursor, payload, cls_of, pop_first, npop,
-                     cls_bits);
+                     dmax_cfg, D1, (uint32_t*)nullptr, (unsigned long long*)cursor, payload, cls_of, pw, pop_first,
+                     npop, cls_bits);
   return hipGetLastError();
 }
 

@@ -58,6 +58,15 @@ struct HostProj {
   uint64_t n = 0;  // the rule's count (fixed total number, list: synapses)
   std::vector<uint32_t> lsrc, ltgt;  // user-defined list (rule kRuleList)
   std::vector<uint8_t> ldel;
+  // weight levels (empty: the single weight): values, draw thresholds
+  // (distributions) or the level of every listed synapse (lists)
+  std::vector<double> wlev;
+  std::vector<uint64_t> wthr;
+  std::vector<uint16_t> lwl;
+  double wmin() const { return wlev.empty() ? weight : wlev.front(); }
+  double wmax_abs() const {
+    return wlev.empty() ? fabs(weight) : std::max(fabs(wlev.front()), fabs(wlev.back()));
+  }
   // synapses the projection makes
   uint64_t synapses() const {
     switch (rule) {
@@ -686,6 +695,72 @@ snn_status snn_connect_fixed_indegree(snn_net* net, uint32_t src_first, uint32_t
                      delay_a, delay_b, port);
 }
 
+// Weight distributions (Sec. 2.1), discretised: `levels` equal bins of
+// [lo, hi], bin j taking its midpoint with the probability the distribution,
+// restricted to [lo, hi], gives the bin.  F: uniform (x - a) / (b - a),
+// normal erfc(-(x - a) / (b sqrt 2)) / 2.
+static double weight_cdf(int32_t kind, double a, double b, double x) {
+  if (kind == SNN_WEIGHT_UNIFORM) return (x - a) / (b - a);
+  return 0.5 * erfc(-(x - a) / (b * sqrt(2.0)));
+}
+
+snn_status snn_weight_distribution(snn_net* net, int32_t kind, double a, double b, double lo, double hi,
+                                   uint32_t levels) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "weights after snn_build");
+  if (net->projs.empty()) return fail(net, SNN_E_STATE, "no projection to give weights to");
+  HostProj& pr = net->projs.back();
+  if (pr.rule == kRuleList) return fail(net, SNN_E_INVALID, "list projections take snn_list_weights");
+  if (levels < 1 || levels > (uint32_t)kMaxClasses) return fail(net, SNN_E_INVALID, "levels must be 1..%d", kMaxClasses);
+  if (kind == SNN_WEIGHT_UNIFORM) {
+    if (!(a < b) || !std::isfinite(a) || !std::isfinite(b)) return fail(net, SNN_E_INVALID, "uniform weights need a < b");
+    lo = a; hi = b;
+  } else if (kind == SNN_WEIGHT_NORMAL) {
+    if (!(b > 0) || !(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi))
+      return fail(net, SNN_E_INVALID, "normal weights need sd > 0 and lo < hi");
+  } else {
+    return fail(net, SNN_E_INVALID, "unknown weight distribution %d", kind);
+  }
+  const double Flo = weight_cdf(kind, a, b, lo), Fhi = weight_cdf(kind, a, b, hi);
+  if (!(Fhi > Flo)) return fail(net, SNN_E_INVALID, "the distribution has no probability in [lo, hi]");
+  pr.wlev.resize(levels);
+  pr.wthr.resize(levels);
+  for (uint32_t j = 0; j < levels; ++j) {
+    pr.wlev[j] = lo + (hi - lo) * (((double)j + 0.5) / (double)levels);
+    if (j + 1 == levels) { pr.wthr[j] = 1ull << 32; break; }
+    const double edge = lo + (hi - lo) * ((double)(j + 1) / (double)levels);
+    const double q = (weight_cdf(kind, a, b, edge) - Flo) / (Fhi - Flo);
+    const double t = std::min(4294967296.0, std::max(0.0, floor(q * 4294967296.0)));
+    pr.wthr[j] = (uint64_t)t;
+  }
+  pr.lwl.clear();
+  return SNN_OK;
+}
+
+snn_status snn_list_weights(snn_net* net, const double* weights, size_t n) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "weights after snn_build");
+  if (n == 0) return SNN_OK;
+  if (!weights) return fail(net, SNN_E_INVALID, "null weights");
+  if (net->projs.empty() || net->projs.back().rule != kRuleList || net->projs.back().n != n)
+    return fail(net, SNN_E_INVALID, "the last projection is not a list of %zu connections", n);
+  HostProj& pr = net->projs.back();
+  std::vector<double> v(weights, weights + n);
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(net, SNN_E_INVALID, "weights must be finite");
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  if (v.size() > (size_t)kMaxClasses) return fail(net, SNN_E_UNSUPPORTED, "more than %d distinct weights", kMaxClasses);
+  pr.lwl.resize(n);
+  for (size_t j = 0; j < n; ++j)
+    pr.lwl[j] = (uint16_t)(std::lower_bound(v.begin(), v.end(), weights[j]) - v.begin());
+  pr.wlev = std::move(v);
+  pr.wthr.clear();
+  return SNN_OK;
+}
+
 snn_status snn_multimeter(snn_net* net, int32_t var, uint32_t port, const uint32_t* gids, size_t n,
                           uint32_t interval, uint32_t* meter_id) {
   if (!net) return SNN_E_INVALID;
@@ -965,7 +1040,8 @@ snn_status snn_build(snn_net* net) {
     }
     if (p.model == SNN_PARROT_NEURON) {  // parrots count arriving spikes: unit weights only
       for (const HostProj& pr : net->projs)
-        if (pr.synapses() && pr.tgt_first < p.first + p.n && pr.tgt_first + pr.tgt_n > p.first && pr.weight != 1.0)
+        if (pr.synapses() && pr.tgt_first < p.first + p.n && pr.tgt_first + pr.tgt_n > p.first &&
+            (pr.wlev.empty() ? pr.weight != 1.0 : (pr.wlev.size() != 1 || pr.wlev[0] != 1.0)))
           return fail(net, SNN_E_INVALID, "weights onto parrot neurons must be 1");
       for (const HostPois& q : net->pois)
         if (q.tgt_n && q.tgt_first < p.first + p.n && q.tgt_first + q.tgt_n > p.first && q.weight != 1.0)
@@ -990,7 +1066,10 @@ snn_status snn_build(snn_net* net) {
   for (const HostProj& pr : net->projs) {
     if (pr.synapses() == 0) continue;
     for (uint32_t k = 0; k < npop; ++k)
-      if (overlaps(k, pr.tgt_first, pr.tgt_n)) maxw[k * P + pr.port] = std::max(maxw[k * P + pr.port], fabs(pr.weight));
+      if (overlaps(k, pr.tgt_first, pr.tgt_n)) {
+        maxw[k * P + pr.port] = std::max(maxw[k * P + pr.port], pr.wmax_abs());
+        if (net->pops[k].adex() && pr.wmin() < 0) return fail(net, SNN_E_INVALID, "conductance weights must be >= 0");
+      }
   }
   for (const HostPois& q : net->pois)
     for (uint32_t k = 0; k < npop; ++k)
@@ -1000,10 +1079,25 @@ snn_status snn_build(snn_net* net) {
   // weight classes: distinct (port, w_q) sorted, per (projection, target population)
   std::map<std::pair<uint32_t, int64_t>, uint32_t> classes;
   std::vector<std::pair<uint32_t, int64_t>> cls_key((size_t)net->projs.size() * npop, {0, 0});
+  // projections with weight levels: the classes of every (target population, level)
+  std::vector<uint32_t> wpop0(net->projs.size(), 0);
+  std::vector<std::vector<std::pair<uint32_t, int64_t>>> wkeys(net->projs.size());
   for (size_t p = 0; p < net->projs.size(); ++p) {
     const HostProj& pr = net->projs[p];
+    if (pr.synapses() == 0) continue;
+    if (!pr.wlev.empty()) {
+      const uint32_t k0 = pop_of(net, pr.tgt_first), k1 = pop_of(net, pr.tgt_first + pr.tgt_n - 1);
+      wpop0[p] = k0;
+      for (uint32_t k = k0; k <= k1; ++k)
+        for (double w : pr.wlev) {
+          const std::pair<uint32_t, int64_t> key{pr.port, llrint(ldexp(w, net->shift[k * P + pr.port]))};
+          wkeys[p].push_back(key);
+          classes[key] = 0;
+        }
+      continue;
+    }
     for (uint32_t k = 0; k < npop; ++k) {
-      if (!overlaps(k, pr.tgt_first, pr.tgt_n) || pr.synapses() == 0) continue;
+      if (!overlaps(k, pr.tgt_first, pr.tgt_n)) continue;
       const int64_t wq = llrint(ldexp(pr.weight, net->shift[k * P + pr.port]));
       cls_key[p * npop + k] = {pr.port, wq};
       classes[{pr.port, wq}] = 0;
@@ -1031,8 +1125,15 @@ snn_status snn_build(snn_net* net) {
   std::vector<uint16_t> cls_of((size_t)std::max<size_t>(1, net->projs.size()) * npop, 0);
   for (size_t p = 0; p < net->projs.size(); ++p)
     for (uint32_t k = 0; k < npop; ++k)
-      if (overlaps(k, net->projs[p].tgt_first, net->projs[p].tgt_n) && net->projs[p].synapses())
+      if (overlaps(k, net->projs[p].tgt_first, net->projs[p].tgt_n) && net->projs[p].synapses() &&
+          net->projs[p].wlev.empty())
         cls_of[p * npop + k] = (uint16_t)classes[cls_key[p * npop + k]];
+  std::vector<uint16_t> wcls;  // level classes of all projections, each [population][level]
+  std::vector<size_t> wcls_off(net->projs.size(), 0);
+  for (size_t p = 0; p < net->projs.size(); ++p) {
+    wcls_off[p] = wcls.size();
+    for (const auto& key : wkeys[p]) wcls.push_back((uint16_t)classes[key]);
+  }
   // projections, delay tables, largest delay present
   const uint32_t dmax_cfg = net->cfg.max_delay_steps;
   std::vector<ProjDev> pd(net->projs.size());
@@ -1164,6 +1265,37 @@ snn_status snn_build(snn_net* net) {
     pd[p].lsrc = ls; pd[p].ltgt = lt; pd[p].ldel = ld;
     list_bufs.insert(list_bufs.end(), {ls, lt, ld});
   }
+  // weight levels: thresholds, classes and listed levels, one table each
+  std::vector<uint64_t> wthr_all;
+  std::vector<uint16_t> lvl_all;
+  std::vector<ProjW> pw(std::max<size_t>(1, pd.size()));
+  std::vector<size_t> thr_off(pd.size(), 0), lvl_off(pd.size(), 0);
+  for (size_t p = 0; p < pd.size(); ++p) {
+    const HostProj& pr = net->projs[p];
+    memset(&pw[p], 0, sizeof(ProjW));
+    if (pr.wlev.empty() || !pr.synapses()) continue;
+    pw[p].levels = (uint32_t)pr.wlev.size();
+    pw[p].pop0 = wpop0[p];
+    thr_off[p] = wthr_all.size();
+    wthr_all.insert(wthr_all.end(), pr.wthr.begin(), pr.wthr.end());
+    lvl_off[p] = lvl_all.size();
+    lvl_all.insert(lvl_all.end(), pr.lwl.begin(), pr.lwl.end());
+  }
+  uint64_t* d_wthr; ALLOC(d_wthr, uint64_t, std::max<size_t>(1, wthr_all.size()));
+  uint16_t* d_wcls; ALLOC(d_wcls, uint16_t, std::max<size_t>(1, wcls.size()));
+  uint16_t* d_lvl; ALLOC(d_lvl, uint16_t, std::max<size_t>(1, lvl_all.size()));
+  ProjW* d_pw; ALLOC(d_pw, ProjW, pw.size());
+  for (size_t p = 0; p < pd.size(); ++p) {
+    if (!pw[p].levels) continue;
+    pw[p].thr = d_wthr + thr_off[p];
+    pw[p].cls = d_wcls + wcls_off[p];
+    pw[p].lvl = d_lvl + lvl_off[p];
+  }
+  if (!wthr_all.empty())
+    HIPCHK(net, copy_sync(net, d_wthr, wthr_all.data(), wthr_all.size() * 8, hipMemcpyHostToDevice));
+  if (!wcls.empty()) HIPCHK(net, copy_sync(net, d_wcls, wcls.data(), wcls.size() * 2, hipMemcpyHostToDevice));
+  if (!lvl_all.empty()) HIPCHK(net, copy_sync(net, d_lvl, lvl_all.data(), lvl_all.size() * 2, hipMemcpyHostToDevice));
+  HIPCHK(net, copy_sync(net, d_pw, pw.data(), pw.size() * sizeof(ProjW), hipMemcpyHostToDevice));
   ALLOC(d_clsof, uint16_t, cls_of.size());
   ALLOC(d_popfirst, uint32_t, npop);
   std::vector<uint32_t> pf(npop);
@@ -1187,7 +1319,7 @@ snn_status snn_build(snn_net* net) {
   HIPCHK(net, hipMemcpyAsync(d_goff + G, &S, 8, hipMemcpyHostToDevice, s));
   uint32_t* d_pay; ALLOC(d_pay, uint32_t, std::max<uint64_t>(1, S));
   HIPCHK(net, launch_gen_scatter(d_proj, (uint32_t)pd.size(), total_pairs, dmax_cfg, D1, d_off, d_pay, d_clsof,
-                                 d_popfirst, npop, net->cls_bits, s));
+                                 d_pw, d_popfirst, npop, net->cls_bits, s));
   const uint32_t big_cap = 4096;
   uint64_t* d_big; ALLOC(d_big, uint64_t, big_cap);
   uint32_t* d_nbig; ALLOC(d_nbig, uint32_t, 1);
@@ -1212,6 +1344,7 @@ snn_status snn_build(snn_net* net) {
   dev_free(net, d_big); dev_free(net, d_nbig);
   dev_free(net, d_cnt); dev_free(net, d_off); dev_free(net, d_ng); dev_free(net, d_gp64); dev_free(net, d_tmp);
   dev_free(net, d_proj); dev_free(net, d_clsof); dev_free(net, d_popfirst);
+  dev_free(net, d_wthr); dev_free(net, d_wcls); dev_free(net, d_lvl); dev_free(net, d_pw);
   for (void* b : list_bufs) dev_free(net, b);
   nd.src_mask = d_mask; nd.grp_ptr = d_gp32; nd.grp_off = d_goff; nd.payload = d_pay;
   nd.n_groups = G; nd.n_syn = S;

@@ -25,6 +25,7 @@ PARAMS = {"tau_m": 0, "C_m": 1, "E_L": 2, "V_th": 3, "V_reset": 4, "t_ref": 5, "
 PORT_PARAMS = {"tau_syn": 0, "E_rev": 1, "tau_rise": 2}
 STATE = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6, "g_rise": 7}
 DELAYS = {"const": 0, "uniform": 1, "normal": 2}
+WEIGHT_DISTS = {"uniform": 0, "normal": 1}
 # connection rules; a projection's "K" is the in-degree, the out-degree or the
 # number of synapses (unused for all_to_all and one_to_one)
 RULES = {"fixed_indegree": 0, "fixed_outdegree": 1, "all_to_all": 2, "one_to_one": 3, "fixed_total_number": 4}
@@ -88,6 +89,9 @@ _SIGS = {
                                      C.POINTER(C.c_double), C.c_double, C.c_uint32]),
     "snn_connect": (C.c_int32, [_P, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                 C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
+    "snn_weight_distribution": (C.c_int32, [_P, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
+                                            C.c_uint32]),
+    "snn_list_weights": (C.c_int32, [_P, C.POINTER(C.c_double), C.c_size_t]),
     "snn_poisson": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double, C.c_uint32]),
     "snn_set_state": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_uint32, C.POINTER(C.c_double),
                                   C.c_size_t]),
@@ -216,13 +220,27 @@ class Net:
                 tgt = np.ascontiguousarray(np.asarray(pr["tgt_gids"], dtype=np.int64) + first_gid, dtype=np.uint32)
                 dl = np.ascontiguousarray(pr["delays_ms"], dtype=np.float64)
                 self._check(self.L.snn_connect_list(self.h, len(src), _ptr(src, C.c_uint32), _ptr(tgt, C.c_uint32),
-                                                    _ptr(dl, C.c_double), float(pr["weight"]), pr["port"]))
+                                                    _ptr(dl, C.c_double), float(pr.get("weight", 0.0)), pr["port"]))
+                if pr.get("weights") is not None:  # one weight per listed connection
+                    w = np.ascontiguousarray(pr["weights"], dtype=np.float64)
+                    self._check(self.L.snn_list_weights(self.h, _ptr(w, C.c_double), len(w)))
                 continue
             s0, sn = ranges[pr["src"]]
             t0, tn = ranges[pr["tgt"]]
             kind, a, b = (list(pr["delay"]) + [0.0, 0.0])[:3]
             self._check(self.L.snn_connect(self.h, RULES[pr.get("rule", "fixed_indegree")], int(pr.get("K", 0)), s0, sn,
-                                           t0, tn, float(pr["weight"]), DELAYS[kind], float(a), float(b), pr["port"]))
+                                           t0, tn, float(pr.get("weight", 0.0)), DELAYS[kind], float(a), float(b),
+                                           pr["port"]))
+            wd = pr.get("weight_dist")
+            if wd is not None:  # uniform on [low, high), or normal(mean, sd) truncated to [low, high]
+                L = int(wd.get("levels", 64))
+                if wd["kind"] == "uniform":
+                    args = (WEIGHT_DISTS["uniform"], float(wd["low"]), float(wd["high"]), 0.0, 0.0, L)
+                else:
+                    m, sd = float(wd["mean"]), float(wd["sd"])
+                    args = (WEIGHT_DISTS["normal"], m, sd, float(wd.get("low", m - 4 * sd)),
+                            float(wd.get("high", m + 4 * sd)), L)
+                self._check(self.L.snn_weight_distribution(self.h, *args))
         for q in spec.get("poisson", []):
             t0, tn = ranges[q["tgt"]]
             self._check(self.L.snn_poisson(self.h, t0, tn, float(q["rate"]), int(q["n_inputs"]),
