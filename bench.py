@@ -141,6 +141,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10_000)
     ap.add_argument("--k-ext", type=int, default=None)
+    ap.add_argument("--weight-sd", type=float, default=0.0,
+                    help="microcircuit: draw every weight from a normal of this relative deviation (32 levels)")
     ap.add_argument("--requests", type=int, default=60, help="serve: requests in the arrival trace")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
     ap.add_argument("--workload", choices=["microcircuit", "adex", "alpha", "alpha_scan", "sweep", "serve"],
@@ -232,7 +234,7 @@ def main():
         spec = W.adex_balanced_alpha(n=args.neurons, k=args.indegree)
     else:
         kw = {} if args.k_ext is None else {"k_ext": args.k_ext}
-        spec = W.microcircuit(scale=1.0, **kw)
+        spec = W.microcircuit(scale=1.0, weight_sd=args.weight_sd, **kw)
     dt = spec["dt"]
     print(f"[bench] building {spec['name']}: {W.total_neurons(spec)} neurons, "
           f"{W.count_synapses(spec):.4g} synapses", file=sys.stderr, flush=True)
@@ -269,7 +271,8 @@ def main():
           f"{args.profile_steps} steps", file=sys.stderr, flush=True)
 
     c2 = net.counters()
-    roofline = step_roofline(net, [spec], mode, args.profile_steps, args.workload)
+    traffic_key = args.workload + ("_weight_sd" if args.weight_sd > 0 else "")
+    roofline = step_roofline(net, [spec], mode, args.profile_steps, traffic_key)
     c3 = net.counters()
     ps = max(1, args.profile_steps)
     dlv_ms = roofline["avg_launch_us"] * 1e-3
@@ -293,7 +296,9 @@ def main():
         "mean_rate_hz": spikes / bio_s / W.total_neurons(spec),
         "events_per_step": events / args.steps,
         "pairs_per_step": pairs / args.steps,
-        "config": {"workload": "cortical microcircuit stand-in: 8 LIF-exp populations, 77,169 neurons, 3.0e8 synapses",
+        "config": {"workload": "cortical microcircuit stand-in: 8 LIF-exp populations, 77,169 neurons, 3.0e8 synapses"
+                               + (f", weights normal (sd {args.weight_sd:g} of the mean, 32 levels)"
+                                  if args.weight_sd > 0 else ""),
                    "neurons": W.total_neurons(spec), "synapses": W.count_synapses(spec),
                    "populations": dict(zip(W.MC_NAMES, W.MC_SIZES)), "dt_ms": dt,
                    "t_bio_s": bio_s, "k_ext": spec["poisson"][0]["n_inputs"],

@@ -121,14 +121,17 @@ def _mc_table(seed: int = 11, base=MC_TABLE) -> np.ndarray:
 
 def microcircuit(scale: float = 1.0, k_scale: float | None = None, k_ext: int = 2800,
                  nu_bg: float = 8.0, seed: int = 1, total_synapses: float = 3.0e8,
-                 dmax: int = 63, table=MC_TABLE) -> dict:
+                 dmax: int = 63, table=MC_TABLE, weight_sd: float = 0.0, weight_levels: int = 32) -> dict:
     """Microcircuit stand-in: LIF neurons with exponential PSCs (one port,
     signed weights), tau_m 10 ms, C_m 250 pF, tau_syn 0.5 ms, E_L = V_reset =
     -65 mV, V_th -50 mV, t_ref 2 ms; w_E 87.8 pA (L4E->L2/3E doubled), w_I =
     -4 w_E; delays normal 1.5 +- 0.75 ms (E sources) and 0.75 +- 0.375 ms (I
     sources); Poisson background nu_bg x k_ext inputs with weight w_E.
     Population sizes are scaled by `scale`; in-degrees by `k_scale` (default:
-    `scale`, i.e. fixed connection probabilities)."""
+    `scale`, i.e. fixed connection probabilities).  weight_sd > 0 draws every
+    synaptic weight from a normal distribution of that relative deviation
+    around the projection's weight (truncated to mean +- 4 sd, which keeps
+    the sign for weight_sd < 0.25), discretised into `weight_levels` bins."""
     if k_scale is None:
         k_scale = scale
     p = _mc_table(base=table)
@@ -154,7 +157,10 @@ def microcircuit(scale: float = 1.0, k_scale: float | None = None, k_ext: int = 
             if s == 2 and t == 0:
                 w = 2.0 * w_e
             d = ("normal", 1.5, 0.75) if src_e else ("normal", 0.75, 0.375)
-            projs.append(dict(src=MC_NAMES[s], tgt=MC_NAMES[t], K=k, weight=w, delay=d, port=0))
+            pr = dict(src=MC_NAMES[s], tgt=MC_NAMES[t], K=k, weight=w, delay=d, port=0)
+            if weight_sd > 0:
+                pr["weight_dist"] = dict(kind="normal", mean=w, sd=abs(w) * weight_sd, levels=weight_levels)
+            projs.append(pr)
     pois = [dict(tgt=nm, rate=nu_bg, n_inputs=int(round(k_ext * k_scale)), weight=w_e, port=0)
             for nm in MC_NAMES]
     return dict(name=f"microcircuit_s{scale:g}", dt=DT, seed=seed, dmax=dmax, populations=pops,

@@ -47,6 +47,8 @@ def snn():
 
 CASES = {
     "microcircuit": (lambda: W.microcircuit(scale=1.0), dict(delivery="direct", delivery_blocks=128)),
+    "microcircuit_weight_sd": (lambda: W.microcircuit(scale=1.0, weight_sd=0.1),
+                               dict(delivery="direct", delivery_blocks=128)),
     "adex_1m": (lambda: W.adex_balanced(), dict(delivery="binned", tile_neurons=2048, delivery_blocks=512)),
     "alpha_1m": (lambda: W.adex_balanced_alpha(), dict(delivery="binned", tile_neurons=2048, delivery_blocks=512)),
 }

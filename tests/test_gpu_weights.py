@@ -120,3 +120,20 @@ def test_weight_errors(snn):
     spec["projections"][-1]["weights"] = spec["projections"][-1]["weights"][:-1]  # one short
     with pytest.raises(snn.SnnError):
         snn.Net(spec)
+
+
+@pytest.mark.parametrize("delivery", ["direct", "binned"])
+def test_microcircuit_normal_weights_raster_bit_exact(snn, delivery):
+    """the microcircuit stand-in with every weight normal (10 % deviation,
+    32 levels): rasters and potentials bit-exact for 1000 steps"""
+    from paper_2007_14236_amd import workloads as W
+    spec = W.microcircuit(scale=0.05, k_scale=0.25, k_ext=3500, seed=3, weight_sd=0.1)
+    g = snn.Net(spec, delivery=delivery, tile_neurons=512 if delivery == "binned" else 0)
+    g.simulate(1000)
+    o = O.OracleNet(spec, O.FP32SO)
+    o.simulate(1000)
+    a, b = g.spikes(), o.spikes()
+    assert len(b[0]) > 100
+    for x, y in zip(a, b):
+        assert np.array_equal(x.astype(np.int64), y.astype(np.int64))
+    assert np.array_equal(g.get_state("V_m").astype(np.float32), o.get_state("V_m").astype(np.float32))
