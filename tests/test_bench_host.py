@@ -57,3 +57,11 @@ def test_neuron_bytes_per_model():
     binned = 10 * 20 + 3 * (16 + 16 + 4) + 5 * (24 + 16 + 4) + 7 * (24 + 32 + 4)
     assert bench.bytes_per_step_neurons(spec, "binned") == binned
     assert bench.bytes_per_step_neurons(spec, "direct") == binned + 8 * (10 * 1 + 3 * 2 + 5 * 2 + 7 * 2)
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(os.path.dirname(bench.__file__), "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "exactly one GPU" in r.stderr and r.stdout == ""
