@@ -12,7 +12,8 @@ outputs the oracle computes one by one (its synapse table would not fit):
   and alpha ports) within 1e-4 of the fp64 RK45 step.
 
 Workloads: the 77,169-neuron microcircuit stand-in (3.0e8 synapses, direct
-delivery with 128 delivery blocks), the 10^6-neuron AdEx network with
+delivery with 128 delivery blocks; also with every weight drawn from a normal
+distribution, 32 levels), the 10^6-neuron AdEx network with
 exponential ports and the 10^6-neuron alpha-port network of Table 1 (10^9
 synapses each, binned delivery, 2048-neuron tiles, 512 delivery blocks), and
 the batched sweep of 128 Brunel instances (3.0e6 neurons, 8.7e9 synapses,
