@@ -88,6 +88,8 @@ def lib():
         L.orc_weight_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_double, C.c_double, C.c_double,
                                               C.c_double, C.c_uint32]
         L.orc_list_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
+        L.orc_state_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_uint32, C.c_int,
+                                             C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32]
         L.orc_connect.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                   C.c_double, C.c_int, C.c_double, C.c_double, C.c_uint32]
         L.orc_connect_fixed_indegree.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -300,6 +302,11 @@ class OracleNet:
             if np.ndim(ie) == 0:
                 ie = np.full(tn, float(ie))
             self.set_state("I_e", t0, np.asarray(ie, dtype=np.float64))
+            # state drawn from distributions, after the arrays: {"V_m": {...}, "I_e": {...}, ...}
+            for var, wd in (p.get("state_dists") or {}).items():
+                kind, a, b, lo, hi, _ = weight_dist_args(wd)
+                self._check(self.L.orc_state_distribution(self.h, t0, tn, VAR_IDS[var], int(wd.get("port", 0)),
+                                                          kind, a, b, lo, hi, int(wd.get("levels", 1024))) == 0)
         self._check((self.L.orc_build(self.h) if build else self.L.orc_prepare(self.h)) == 0)
 
     def _check(self, ok):

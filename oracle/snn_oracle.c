@@ -348,37 +348,72 @@ static double weight_cdf(int kind, double a, double b, double x) {
   return 0.5 * erfc(-(x - a) / (b * sqrt(2.0)));
 }
 
-int orc_weight_distribution(orc_net* o, uint32_t proj, int kind, double a, double b, double lo, double hi,
-                            uint32_t levels) {
-  if (o->built || o->shift) { set_err(o, "weights after build"); return -1; }
-  if (proj >= o->n_proj || o->proj[proj].rule == ORC_RULE_LIST) { set_err(o, "projection"); return -1; }
-  if (levels < 1 || levels > ORC_WEIGHT_LEVELS_MAX) { set_err(o, "levels"); return -1; }
+/* levels and thresholds of a discretised distribution (weights and states
+   alike); returns an error message or NULL */
+static const char* dist_levels(int kind, double a, double b, double lo, double hi, uint32_t levels, double* lev,
+                               uint64_t* thr) {
   if (kind == ORC_WEIGHT_UNIFORM) {
-    if (!(a < b)) { set_err(o, "uniform weights need a < b"); return -1; }
+    if (!(a < b)) return "uniform needs a < b";
     lo = a; hi = b;
   } else if (kind == ORC_WEIGHT_NORMAL) {
-    if (!(b > 0) || !(lo < hi)) { set_err(o, "normal weights need sigma > 0 and lo < hi"); return -1; }
+    if (!(b > 0) || !(lo < hi)) return "normal needs sigma > 0 and lo < hi";
   } else {
-    set_err(o, "weight distribution"); return -1;
+    return "distribution";
   }
   double Flo = weight_cdf(kind, a, b, lo), Fhi = weight_cdf(kind, a, b, hi);
-  if (!(Fhi > Flo)) { set_err(o, "no probability in [lo, hi]"); return -1; }
-  orc_proj* pr = &o->proj[proj];
-  free(pr->wlev); free(pr->wthr);
-  pr->wlev = (double*)malloc(levels * sizeof(double));
-  pr->wthr = (uint64_t*)malloc(levels * sizeof(uint64_t));
-  pr->wlevels = levels;
+  if (!(Fhi > Flo)) return "no probability in [lo, hi]";
   for (uint32_t j = 0; j < levels; ++j) {
-    pr->wlev[j] = lo + (hi - lo) * (((double)j + 0.5) / (double)levels);
-    if (j + 1 == levels) { pr->wthr[j] = 1ull << 32; continue; }
+    lev[j] = lo + (hi - lo) * (((double)j + 0.5) / (double)levels);
+    if (j + 1 == levels) { thr[j] = 1ull << 32; continue; }
     double edge = lo + (hi - lo) * ((double)(j + 1) / (double)levels);
     double q = (weight_cdf(kind, a, b, edge) - Flo) / (Fhi - Flo);
     double t = floor(q * 4294967296.0);
     if (t < 0) t = 0;
     if (t > 4294967296.0) t = 4294967296.0;
-    pr->wthr[j] = (uint64_t)t;
+    thr[j] = (uint64_t)t;
   }
+  return NULL;
+}
+
+int orc_weight_distribution(orc_net* o, uint32_t proj, int kind, double a, double b, double lo, double hi,
+                            uint32_t levels) {
+  if (o->built || o->shift) { set_err(o, "weights after build"); return -1; }
+  if (proj >= o->n_proj || o->proj[proj].rule == ORC_RULE_LIST) { set_err(o, "projection"); return -1; }
+  if (levels < 1 || levels > ORC_WEIGHT_LEVELS_MAX) { set_err(o, "levels"); return -1; }
+  double* lev = (double*)malloc(levels * sizeof(double));
+  uint64_t* thr = (uint64_t*)malloc(levels * sizeof(uint64_t));
+  const char* e = dist_levels(kind, a, b, lo, hi, levels, lev, thr);
+  if (e) { free(lev); free(thr); set_err(o, e); return -1; }
+  orc_proj* pr = &o->proj[proj];
+  free(pr->wlev); free(pr->wthr);
+  pr->wlev = lev; pr->wthr = thr; pr->wlevels = levels;
   return 0;
+}
+
+/* State drawn from a distribution: neuron i takes the level of the top 32
+   bits of word 0 of block (i, var << 8 | port, ORC_TAG_STATE, 0), key
+   (seed, 0), then is set as by orc_set_state. */
+int orc_state_distribution(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port, int kind, double a,
+                           double b, double lo, double hi, uint32_t levels) {
+  if (o->N == 0 || (uint64_t)first + n > o->N) { set_err(o, "range"); return -1; }
+  if (var == 5 || var < 0 || var > 7) { set_err(o, "var"); return -1; }
+  if (levels < 1 || levels > ORC_STATE_LEVELS_MAX) { set_err(o, "levels"); return -1; }
+  double* lev = (double*)malloc(levels * sizeof(double));
+  uint64_t* thr = (uint64_t*)malloc(levels * sizeof(uint64_t));
+  double* v = (double*)malloc((n ? n : 1) * sizeof(double));
+  const char* e = dist_levels(kind, a, b, lo, hi, levels, lev, thr);
+  if (e) { free(lev); free(thr); free(v); set_err(o, e); return -1; }
+  uint64_t key[2] = {o->seed, 0};
+  for (uint32_t j = 0; j < n; ++j) {
+    uint64_t ctr[4] = {first + j, ((uint64_t)var << 8) | port, ORC_TAG_STATE, 0}, blk[4];
+    orc_philox4x64_10(ctr, key, blk);
+    uint32_t u = (uint32_t)(blk[0] >> 32), l = 0;
+    while ((uint64_t)u >= thr[l]) ++l;
+    v[j] = lev[l];
+  }
+  int rc = orc_set_state(o, first, n, var, port, v);
+  free(lev); free(thr); free(v);
+  return rc;
 }
 
 int orc_list_weights(orc_net* o, uint32_t proj, uint64_t n, const double* weights) {

@@ -31,8 +31,8 @@ enum { ORC_FP64 = 0, ORC_FP32SO = 1 };
 enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2, ORC_AEIF_COND_BETA = 3,
        ORC_SPIKE_GENERATOR = 4, ORC_PARROT = 5 };
 enum { ORC_DELAY_CONST = 0, ORC_DELAY_UNIFORM = 1, ORC_DELAY_NORMAL_CLIPPED = 2 };
-enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2, ORC_TAG_WEIGHT = 3 };
-enum { ORC_WEIGHT_UNIFORM = 0, ORC_WEIGHT_NORMAL = 1, ORC_WEIGHT_LEVELS_MAX = 1024 };
+enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2, ORC_TAG_WEIGHT = 3, ORC_TAG_STATE = 4 };
+enum { ORC_WEIGHT_UNIFORM = 0, ORC_WEIGHT_NORMAL = 1, ORC_WEIGHT_LEVELS_MAX = 1024, ORC_STATE_LEVELS_MAX = 65536 };
 /* connection rules (Sec. 2.1): the count n is the in-degree, the out-degree,
    unused, unused, and the number of synapses, in that order */
 enum { ORC_RULE_FIXED_INDEGREE = 0, ORC_RULE_FIXED_OUTDEGREE = 1, ORC_RULE_ALL_TO_ALL = 2,
@@ -114,6 +114,14 @@ int      orc_set_spike_times(orc_net*, uint32_t gid, uint64_t n, const double* t
    3 g[port] (nS), 4 I_syn[port] (pA), 5 refractory counter, 6 h (ms) */
 int      orc_set_state(orc_net*, uint32_t first, uint32_t n, int var, uint32_t port, const double* v);
 int      orc_get_state(orc_net*, uint32_t first, uint32_t n, int var, uint32_t port, double* v);
+/* State variable `var` (not the refractory counter) of neurons first..first+n
+   drawn from a distribution, discretised as the weights are (uniform kind 0
+   on [a, b), truncated normal kind 1 of mean a and deviation b on [lo, hi],
+   `levels` <= ORC_STATE_LEVELS_MAX bins, midpoints): neuron i takes the
+   level of the top 32 bits of word 0 of block (i, var << 8 | port,
+   ORC_TAG_STATE, 0), then is set as by orc_set_state. */
+int      orc_state_distribution(orc_net*, uint32_t first, uint32_t n, int var, uint32_t port, int kind, double a,
+                                double b, double lo, double hi, uint32_t levels);
 int      orc_build(orc_net*);
 int      orc_simulate(orc_net*, uint64_t steps);
 uint64_t orc_current_step(const orc_net*);

@@ -230,3 +230,51 @@ def test_weight_distribution_errors():
     sp["projections"][0]["weight_dist"]["low"] = 0.0
     w, _ = levels_of(O.OracleNet(sp), sp, 0)
     assert w.min() > 0
+
+
+def state_spec():
+    from paper_2007_14236_amd import workloads as W
+    spec = W.brunel_lif(n=2000, k=20, seed=3)
+    for p in spec["populations"]:
+        p["state_dists"] = {"V_m": dict(kind="uniform", low=0.0, high=20.0, levels=4096),
+                            "I_e": dict(kind="normal", mean=100.0, sd=30.0, low=0.0, high=250.0, levels=500)}
+    return spec
+
+
+def test_state_distributions_match_numpy_philox_and_scipy_bins():
+    spec = state_spec()
+    o = O.OracleNet(spec)
+    key = [spec["seed"], 0]
+    for var, vid in (("V_m", 0), ("I_e", 1)):
+        wd = spec["populations"][0]["state_dists"][var]
+        L = wd["levels"]
+        if wd["kind"] == "uniform":
+            thr, lo, hi = thresholds("uniform", wd["low"], wd["high"], 0, 0, L)
+        else:
+            thr, lo, hi = thresholds("normal", wd["mean"], wd["sd"], wd["low"], wd["high"], L)
+        levels = lo + (hi - lo) * ((np.arange(L) + 0.5) / L)
+        got = o.get_state(var)
+        for i in range(0, 2000, 7):
+            u = int(numpy_block([i, vid << 8, 4, 0], key)[0]) >> 32
+            assert got[i] == levels[int(np.argmax(u < thr))], (var, i)
+    # frequencies: V uniform over 4096 bins in 16 groups; I_e against scipy's truncated normal
+    v = o.get_state("V_m")
+    assert stats.chisquare(np.bincount(np.floor(v / 1.25).astype(int), minlength=16)).pvalue > 1e-4
+    ie = o.get_state("I_e")
+    tn = stats.truncnorm(-100.0 / 30.0, 150.0 / 30.0, loc=100.0, scale=30.0)
+    assert abs(ie.mean() - tn.mean()) < 5 * tn.std() / np.sqrt(ie.size) + 0.5 ** 2
+    assert ie.min() >= 0.0 and ie.max() <= 250.0
+
+
+def test_state_distribution_overrides_arrays_and_errors():
+    spec = state_spec()
+    o = O.OracleNet(spec)
+    base = state_spec()
+    for p in base["populations"]:
+        p.pop("state_dists")
+    ob = O.OracleNet(base)
+    assert not np.array_equal(o.get_state("V_m"), ob.get_state("V_m"))  # drawn values replaced V0
+    spec = state_spec()
+    spec["populations"][0]["state_dists"]["V_m"]["levels"] = 0
+    with pytest.raises(RuntimeError):
+        O.OracleNet(spec)
