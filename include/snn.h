@@ -268,6 +268,20 @@ snn_status snn_weight_distribution(snn_net* net, int32_t kind, double a, double 
    does nothing).  The distinct values become weight classes as above (at
    most 1024 distinct values, SNN_E_UNSUPPORTED beyond). */
 snn_status snn_list_weights(snn_net* net, const double* weights, size_t n);
+/* State variable `var` (SNN_V_M, SNN_V_I_E, SNN_V_W, SNN_V_G, SNN_V_I_SYN,
+   SNN_V_H or SNN_V_G_RISE; `port` for the per-port ones) of neurons
+   first..first+n drawn from a distribution (Sec. 2.1: neuron parameters and
+   state "through probability distributions"), discretised like the weights
+   (kind SNN_WEIGHT_UNIFORM on [a, b) or SNN_WEIGHT_NORMAL of mean a and
+   deviation b truncated to [lo, hi]; `levels` equal bins, 1..65536, a value
+   is its bin's midpoint).  Neuron i takes the level of the top 32 bits of
+   word 0 of Philox block (i, var << 8 | port, tag 4) with its instance's key
+   (seed, 0), i counted from the instance's first neuron; the values are then
+   set as by snn_set_state (before or after build; a later call on the same
+   neurons wins).  SNN_E_INVALID for a bad range, the refractory counter, or
+   a bad distribution. */
+snn_status snn_state_distribution(snn_net* net, uint32_t first, uint32_t n, int32_t var, uint32_t port,
+                                  int32_t kind, double a, double b, double lo, double hi, uint32_t levels);
 /* Multimeter (Sec. 2.1), before snn_build: record state variable `var`
    (SNN_V_M, SNN_V_W, SNN_V_G, SNN_V_G_RISE, SNN_V_I_SYN or SNN_V_H; `port` for
    the per-port ones) of the n neurons gids[0..n) after the update of every

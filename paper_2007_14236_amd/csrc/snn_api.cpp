@@ -704,6 +704,36 @@ static double weight_cdf(int32_t kind, double a, double b, double x) {
   return 0.5 * erfc(-(x - a) / (b * sqrt(2.0)));
 }
 
+// Levels (bin midpoints) and draw thresholds of a discretised distribution;
+// returns an error message or nullptr.
+constexpr uint64_t kTagState = 4;           // Philox tag of state draws (connections 1, Poisson 2, weights 3)
+constexpr uint32_t kStateLevelsMax = 65536;  // bins of a state distribution
+
+static const char* dist_levels(int32_t kind, double a, double b, double lo, double hi, uint32_t levels,
+                               std::vector<double>& lev, std::vector<uint64_t>& thr) {
+  if (kind == SNN_WEIGHT_UNIFORM) {
+    if (!(a < b) || !std::isfinite(a) || !std::isfinite(b)) return "uniform distribution needs a < b";
+    lo = a; hi = b;
+  } else if (kind == SNN_WEIGHT_NORMAL) {
+    if (!(b > 0) || !(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi))
+      return "normal distribution needs sd > 0 and lo < hi";
+  } else {
+    return "unknown distribution";
+  }
+  const double Flo = weight_cdf(kind, a, b, lo), Fhi = weight_cdf(kind, a, b, hi);
+  if (!(Fhi > Flo)) return "the distribution has no probability in [lo, hi]";
+  lev.resize(levels);
+  thr.resize(levels);
+  for (uint32_t j = 0; j < levels; ++j) {
+    lev[j] = lo + (hi - lo) * (((double)j + 0.5) / (double)levels);
+    if (j + 1 == levels) { thr[j] = 1ull << 32; break; }
+    const double edge = lo + (hi - lo) * ((double)(j + 1) / (double)levels);
+    const double q = (weight_cdf(kind, a, b, edge) - Flo) / (Fhi - Flo);
+    thr[j] = (uint64_t)std::min(4294967296.0, std::max(0.0, floor(q * 4294967296.0)));
+  }
+  return nullptr;
+}
+
 snn_status snn_weight_distribution(snn_net* net, int32_t kind, double a, double b, double lo, double hi,
                                    uint32_t levels) {
   if (!net) return SNN_E_INVALID;
@@ -713,29 +743,54 @@ snn_status snn_weight_distribution(snn_net* net, int32_t kind, double a, double 
   HostProj& pr = net->projs.back();
   if (pr.rule == kRuleList) return fail(net, SNN_E_INVALID, "list projections take snn_list_weights");
   if (levels < 1 || levels > (uint32_t)kMaxClasses) return fail(net, SNN_E_INVALID, "levels must be 1..%d", kMaxClasses);
-  if (kind == SNN_WEIGHT_UNIFORM) {
-    if (!(a < b) || !std::isfinite(a) || !std::isfinite(b)) return fail(net, SNN_E_INVALID, "uniform weights need a < b");
-    lo = a; hi = b;
-  } else if (kind == SNN_WEIGHT_NORMAL) {
-    if (!(b > 0) || !(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi))
-      return fail(net, SNN_E_INVALID, "normal weights need sd > 0 and lo < hi");
-  } else {
-    return fail(net, SNN_E_INVALID, "unknown weight distribution %d", kind);
-  }
-  const double Flo = weight_cdf(kind, a, b, lo), Fhi = weight_cdf(kind, a, b, hi);
-  if (!(Fhi > Flo)) return fail(net, SNN_E_INVALID, "the distribution has no probability in [lo, hi]");
-  pr.wlev.resize(levels);
-  pr.wthr.resize(levels);
-  for (uint32_t j = 0; j < levels; ++j) {
-    pr.wlev[j] = lo + (hi - lo) * (((double)j + 0.5) / (double)levels);
-    if (j + 1 == levels) { pr.wthr[j] = 1ull << 32; break; }
-    const double edge = lo + (hi - lo) * ((double)(j + 1) / (double)levels);
-    const double q = (weight_cdf(kind, a, b, edge) - Flo) / (Fhi - Flo);
-    const double t = std::min(4294967296.0, std::max(0.0, floor(q * 4294967296.0)));
-    pr.wthr[j] = (uint64_t)t;
-  }
+  std::vector<double> lev;
+  std::vector<uint64_t> thr;
+  if (const char* e = dist_levels(kind, a, b, lo, hi, levels, lev, thr)) return fail(net, SNN_E_INVALID, "%s", e);
+  pr.wlev = std::move(lev);
+  pr.wthr = std::move(thr);
   pr.lwl.clear();
   return SNN_OK;
+}
+
+// Philox4x64-10 on the host (Salmon et al., SC'11; the same published
+// definition the device kernels use) for draws made while the network is
+// defined.
+static void philox_host(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  for (int r = 0; r < 10; ++r) {
+    const unsigned __int128 p0 = (unsigned __int128)M0 * c[0], p1 = (unsigned __int128)M1 * c[2];
+    const uint64_t n0 = (uint64_t)(p1 >> 64) ^ c[1] ^ k0, n2 = (uint64_t)(p0 >> 64) ^ c[3] ^ k1;
+    c[0] = n0; c[1] = (uint64_t)p1; c[2] = n2; c[3] = (uint64_t)p0;
+    k0 += W0; k1 += W1;
+  }
+}
+
+snn_status snn_state_distribution(snn_net* net, uint32_t first, uint32_t n, int32_t var, uint32_t port,
+                                  int32_t kind, double a, double b, double lo, double hi, uint32_t levels) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if ((uint64_t)first + n > net->N) return fail(net, SNN_E_INVALID, "bad state range");
+  if (var == SNN_V_REFR || var < SNN_V_M || var > SNN_V_G_RISE)
+    return fail(net, SNN_E_INVALID, "state variable %d cannot be drawn", var);
+  if (levels < 1 || levels > kStateLevelsMax) return fail(net, SNN_E_INVALID, "levels must be 1..%u", kStateLevelsMax);
+  std::vector<double> lev;
+  std::vector<uint64_t> thr;
+  if (const char* e = dist_levels(kind, a, b, lo, hi, levels, lev, thr)) return fail(net, SNN_E_INVALID, "%s", e);
+  std::vector<double> v(std::max<uint32_t>(1, n));
+  for (uint32_t i = first; i < first + n;) {  // population by population: instance seed and first gid
+    const HostPop& pp = net->pops[pop_of(net, i)];
+    const uint64_t seed = net->insts[pp.inst].seed, g0 = net->insts[pp.inst].first_gid;
+    const uint32_t end = std::min(first + n, pp.first + pp.n);
+    for (; i < end; ++i) {
+      uint64_t c[4] = {i - g0, ((uint64_t)var << 8) | port, kTagState, 0};
+      philox_host(c, seed, 0);
+      const uint32_t u = (uint32_t)(c[0] >> 32);
+      const size_t l = std::upper_bound(thr.begin(), thr.end(), (uint64_t)u) - thr.begin();  // min{l : u < thr[l]}
+      v[i - first] = lev[l];
+    }
+  }
+  return snn_set_state(net, first, n, var, port, v.data(), n);
 }
 
 snn_status snn_list_weights(snn_net* net, const double* weights, size_t n) {

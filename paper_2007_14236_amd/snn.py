@@ -92,6 +92,8 @@ _SIGS = {
     "snn_weight_distribution": (C.c_int32, [_P, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
                                             C.c_uint32]),
     "snn_list_weights": (C.c_int32, [_P, C.POINTER(C.c_double), C.c_size_t]),
+    "snn_state_distribution": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_uint32, C.c_int32,
+                                           C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32]),
     "snn_poisson": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double, C.c_uint32]),
     "snn_set_state": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_uint32, C.POINTER(C.c_double),
                                   C.c_size_t]),
@@ -259,6 +261,16 @@ class Net:
                 self.set_state("V_m", t0, np.asarray(p["V0"], dtype=np.float64))
             ie = p.get("I_e", 0.0)
             self.set_state("I_e", t0, np.atleast_1d(np.asarray(ie, dtype=np.float64)), n=tn)
+            # state drawn from distributions, after the arrays: {"V_m": {...}, "I_e": {...}, ...}
+            for var, wd in (p.get("state_dists") or {}).items():
+                L = int(wd.get("levels", 1024))
+                if wd["kind"] == "uniform":
+                    args = (WEIGHT_DISTS["uniform"], float(wd["low"]), float(wd["high"]), 0.0, 0.0, L)
+                else:
+                    m, sd = float(wd["mean"]), float(wd["sd"])
+                    args = (WEIGHT_DISTS["normal"], m, sd, float(wd.get("low", m - 4 * sd)),
+                            float(wd.get("high", m + 4 * sd)), L)
+                self._check(self.L.snn_state_distribution(self.h, t0, tn, STATE[var], int(wd.get("port", 0)), *args))
         return dict(ranges=ranges, first=first_gid, n=self.N - first_gid)
 
     def _check(self, rc, h=-1):

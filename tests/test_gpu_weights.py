@@ -137,3 +137,48 @@ def test_microcircuit_normal_weights_raster_bit_exact(snn, delivery):
     for x, y in zip(a, b):
         assert np.array_equal(x.astype(np.int64), y.astype(np.int64))
     assert np.array_equal(g.get_state("V_m").astype(np.float32), o.get_state("V_m").astype(np.float32))
+
+
+def lif_state_spec(n=2000, seed=3):
+    from paper_2007_14236_amd import workloads as W
+    spec = W.brunel_lif(n=n, k=40, seed=seed, nu_ext=100.0)
+    for p in spec["populations"]:
+        p["state_dists"] = {"V_m": dict(kind="uniform", low=0.0, high=20.0, levels=4096),
+                            "I_e": dict(kind="normal", mean=100.0, sd=30.0, low=0.0, high=250.0, levels=500)}
+    return spec
+
+
+@pytest.mark.parametrize("delivery", ["direct", "binned"])
+def test_state_distributions_bit_exact(snn, delivery):
+    """drawn potentials and currents equal the oracle's at build, and the
+    raster and potentials after 300 steps"""
+    spec = lif_state_spec()
+    g = snn.Net(spec, delivery=delivery, tile_neurons=512 if delivery == "binned" else 0)
+    o = O.OracleNet(spec, O.FP32SO)
+    for var in ("V_m", "I_e"):
+        assert np.array_equal(g.get_state(var).astype(np.float32), o.get_state(var).astype(np.float32)), var
+    g.simulate(300)
+    o.simulate(300)
+    a, b = g.spikes(), o.spikes()
+    assert len(b[0]) > 100
+    for x, y in zip(a, b):
+        assert np.array_equal(x.astype(np.int64), y.astype(np.int64))
+    assert np.array_equal(g.get_state("V_m").astype(np.float32), o.get_state("V_m").astype(np.float32))
+
+
+def test_state_distributions_per_instance_and_adex(snn):
+    from paper_2007_14236_amd import workloads as W
+    ad = W.adex_balanced(n=500, k=50, seed=9)
+    for p in ad["populations"]:
+        p["state_dists"] = {"V_m": dict(kind="normal", mean=-65.0, sd=4.0, levels=2000),
+                            "w": dict(kind="uniform", low=0.0, high=50.0, levels=100)}
+    specs = [lif_state_spec(n=300, seed=4), ad, lif_state_spec(n=700, seed=5)]
+    g = snn.Net(specs)
+    first = 0
+    for sp in specs:
+        n = sum(p["n"] for p in sp["populations"])
+        o = O.OracleNet(sp, O.FP32SO, build=False)
+        for var in ("V_m", "I_e") + (("w",) if sp is ad else ()):
+            assert np.array_equal(g.get_state(var, first, n).astype(np.float32),
+                                  o.get_state(var).astype(np.float32)), (sp["name"], var)
+        first += n
