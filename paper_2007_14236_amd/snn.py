@@ -169,7 +169,17 @@ class TorchAllocator:
 class Net:
     """A network on the GPU, defined from a specification dictionary, or a
     batch of independent networks (one instance per specification) that
-    advance together in the same kernels."""
+    advance together in the same kernels.
+
+    Specification: "dt", "seed", "dmax"; "populations" (name, model, n,
+    ports, params; optional V0 and I_e as scalars or arrays, "state_dists"
+    {variable: distribution}, "spike_times" for spike generators);
+    "projections" (src, tgt, rule, K, weight or "weight_dist", delay
+    (kind, a, b), port; or rule "list" with src_gids, tgt_gids, delays_ms and
+    a weight or per-connection "weights"); "poisson" (tgt, rate, n_inputs,
+    weight, port); "multimeters" (var, gids, interval, port).  A distribution
+    is {"kind": "uniform", "low", "high"} or {"kind": "normal", "mean", "sd",
+    "low", "high"} with "levels" bins (weights 64, states 1024 by default).
 
     def __init__(self, spec, allocator: TorchAllocator | None = None, record: bool = True, build: bool = True,
                  delivery: str = "auto", tile_neurons: int = 0, bin_capacity: int = 0, delivery_blocks: int = 0):
