@@ -179,7 +179,7 @@ class Net:
     a weight or per-connection "weights"); "poisson" (tgt, rate, n_inputs,
     weight, port); "multimeters" (var, gids, interval, port).  A distribution
     is {"kind": "uniform", "low", "high"} or {"kind": "normal", "mean", "sd",
-    "low", "high"} with "levels" bins (weights 64, states 1024 by default).
+    "low", "high"} with "levels" bins (weights 64, states 1024 by default)."""
 
     def __init__(self, spec, allocator: TorchAllocator | None = None, record: bool = True, build: bool = True,
                  delivery: str = "auto", tile_neurons: int = 0, bin_capacity: int = 0, delivery_blocks: int = 0):
