@@ -778,7 +778,9 @@ int orc_build(orc_net* o) {
 /* is propagated exactly over dt:                                             */
 /*   P22 = e^{-dt/tau_m},  P11 = e^{-dt/tau_s},  P20 = tau_m/C (1 - P22),     */
 /*   P21 = tau_m tau_s / (C (tau_s - tau_m)) (e^{-dt/tau_s} - e^{-dt/tau_m})  */
-/*   (limit dt/C e^{-dt/tau} when tau_s = tau_m).                             */
+/*       = (dt/C) e^{-dt/tau_m} (e^x - 1)/x,  x = dt (tau_s - tau_m)/(tau_m tau_s) */
+/*   (the second form has no cancellation when tau_s is close to tau_m; its   */
+/*   limit dt/C e^{-dt/tau} when tau_s = tau_m is x = 0).                     */
 /* A delta PSC adds its weight (mV) to y at the step it arrives.              */
 /* ------------------------------------------------------------------------ */
 void orc_lif_propagators(const orc_pop_params* pp, double dt, double* out) {
@@ -788,10 +790,12 @@ void orc_lif_propagators(const orc_pop_params* pp, double dt, double* out) {
   for (uint32_t p = 0; p < pp->n_ports; ++p) {
     double ts = pp->tau_syn[p];
     double P11 = (ts > 0) ? exp(-dt / ts) : 0.0;
-    double P21;
-    if (!(ts > 0)) P21 = 0.0;
-    else if (ts == pp->tau_m) P21 = dt / pp->C_m * exp(-dt / pp->tau_m);
-    else P21 = pp->tau_m * ts / (pp->C_m * (ts - pp->tau_m)) * (exp(-dt / ts) - exp(-dt / pp->tau_m));
+    double P21 = 0.0;
+    if (ts > 0) {
+      double x = dt * (ts - pp->tau_m) / (pp->tau_m * ts);
+      double q = (x == 0.0) ? 1.0 : expm1(x) / x;
+      P21 = dt / pp->C_m * exp(-dt / pp->tau_m) * q;
+    }
     out[2 + p] = P11;
     out[2 + pp->n_ports + p] = P21;
   }
