@@ -171,28 +171,39 @@ def parse():
 
 
 def cpu_baseline(steps: int) -> dict:
-    """Oracle (plain C, fp64, one thread) on the microcircuit stand-in at N/10
-    with the full in-degrees and drive: same per-neuron input statistics and
-    rates as the full network, one tenth of the neurons and synapses."""
+    """Oracle (plain C, fp64) on the microcircuit stand-in at N/10 with the
+    full in-degrees and drive: same per-neuron input statistics and rates as
+    the full network, one tenth of the neurons and synapses.  Timed twice:
+    the plain build on one thread, and the same source built with OpenMP on
+    all the host's cores (neuron and delivery loops split over threads; same
+    results).  The all-core leg is the reported value."""
     from oracle import oracle as O
     from paper_2007_14236_amd import workloads as W
     spec = W.microcircuit(scale=0.1, k_scale=1.0)
-    t0 = time.perf_counter()
-    net = O.OracleNet(spec, O.FP64)
-    t_build = time.perf_counter() - t0
-    net.simulate(1000)
-    e0 = net.events
-    t0 = time.perf_counter()
-    net.simulate(steps)
-    wall = time.perf_counter() - t0
-    ev = net.events - e0
     bio = steps * spec["dt"] * 1e-3
-    return {"value": ev / wall, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": (f"microcircuit stand-in at N/10 with full in-degrees ({net.N} neurons, "
-                       f"{W.count_synapses(spec):.3g} synapses), fp64 oracle, {steps} steps "
-                       f"({bio:g} s bio) after 1000 warm-up steps, one thread; build ({t_build:.1f} s) excluded"),
-            "rtf": wall / bio, "host": platform.processor() or platform.machine(),
-            "host_cpus": os.cpu_count()}
+    legs = {}
+    for name, omp in (("one_core", False), ("all_cores", True)):
+        t0 = time.perf_counter()
+        net = O.OracleNet(spec, O.FP64, openmp=omp)
+        t_build = time.perf_counter() - t0
+        net.simulate(1000)
+        e0 = net.events
+        t0 = time.perf_counter()
+        net.simulate(steps)
+        wall = time.perf_counter() - t0
+        ev = net.events - e0
+        legs[name] = {"value": ev / wall, "unit": "events/s", "cores": net.threads, "rtf": wall / bio,
+                      "build_s": round(t_build, 2)}
+        del net
+    out = dict(legs["all_cores"])
+    out.update({"kind": "oracle",
+                "sample": (f"microcircuit stand-in at N/10 with full in-degrees ({W.total_neurons(spec)} neurons, "
+                           f"{W.count_synapses(spec):.3g} synapses), fp64 oracle, {steps} steps ({bio:g} s bio) "
+                           "after 1000 warm-up steps, build excluded; OpenMP build on all host cores "
+                           "(one_core: the plain build on one thread)"),
+                "one_core": legs["one_core"],
+                "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()})
+    return out
 
 
 def copy_calibration(mib: int):

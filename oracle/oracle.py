@@ -14,6 +14,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# the same source built with OpenMP (the neuron and delivery loops split over
+# the host's cores; same results): used only to time the oracle on all cores
+LIB_OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
 
 LIF_DELTA, LIF_EXP, AEIF_COND_EXP, AEIF_COND_BETA, SPIKE_GENERATOR, PARROT = 0, 1, 2, 3, 4, 5
 FP64, FP32SO = 0, 1
@@ -53,90 +56,109 @@ class PopParams(C.Structure):
     ]
 
 
-def build_oracle(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (no fast-math, no FMA contraction)."""
+def build_oracle(force: bool = False, openmp: bool = False) -> str:
+    """Compile liboracle.so (or, openmp=True, liboracle_omp.so) with gcc (no
+    fast-math, no FMA contraction)."""
     src = os.path.join(HERE, "snn_oracle.c")
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
-        tmp = LIB_PATH + ".tmp"
+    hdr = os.path.join(HERE, "snn_oracle.h")
+    path = LIB_OMP_PATH if openmp else LIB_PATH
+    newest = max(os.path.getmtime(src), os.path.getmtime(hdr))
+    if force or not os.path.exists(path) or os.path.getmtime(path) < newest:
+        tmp = path + ".tmp"
+        extra = ["-fopenmp"] if openmp else []
         subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, src, "-lm"])
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+                               "-fPIC", "-shared"] + extra + ["-o", tmp, src, "-lm"])
+        os.replace(tmp, path)
+    return path
 
 
 _lib = None
+_lib_omp = None
+
+
+def lib_omp():
+    """The OpenMP build (loaded on first use)."""
+    global _lib_omp
+    if _lib_omp is None:
+        _lib_omp = _declare(C.CDLL(build_oracle(openmp=True)))
+    return _lib_omp
 
 
 def lib():
     global _lib
     if _lib is None:
-        build_oracle()
-        L = C.CDLL(LIB_PATH)
-        P64, P32, PU32, PI64, PD = (C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
-                                    C.POINTER(C.c_int64), C.POINTER(C.c_double))
-        L.orc_philox4x64_10.argtypes = [P64, P64, P64]
-        L.orc_delay_table.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_uint32, P64]
-        L.orc_poisson_table.argtypes = [C.c_double, C.c_uint32, P64]
-        L.orc_fixed_point_shift.argtypes = [C.c_double]
-        L.orc_create.restype = C.c_void_p
-        L.orc_create.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_int]
-        L.orc_destroy.argtypes = [C.c_void_p]
-        L.orc_population.restype = C.c_int64
-        L.orc_population.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(PopParams)]
-        L.orc_set_spike_times.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
-        L.orc_connect_list.argtypes = [C.c_void_p, C.c_uint64, P32, P32, PD, C.c_double, C.c_uint32]
-        L.orc_weight_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_double, C.c_double, C.c_double,
-                                              C.c_double, C.c_uint32]
-        L.orc_list_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
-        L.orc_state_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_uint32, C.c_int,
-                                             C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32]
-        L.orc_connect.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
-                                  C.c_double, C.c_int, C.c_double, C.c_double, C.c_uint32]
-        L.orc_connect_fixed_indegree.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
-                                                 C.c_uint32, C.c_double, C.c_int, C.c_double, C.c_double,
-                                                 C.c_uint32]
-        L.orc_poisson.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double,
-                                  C.c_uint32]
-        L.orc_set_state.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_uint32, PD]
-        L.orc_get_state.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_uint32, PD]
-        L.orc_build.argtypes = [C.c_void_p]
-        L.orc_simulate.argtypes = [C.c_void_p, C.c_uint64]
-        L.orc_current_step.restype = C.c_uint64
-        L.orc_current_step.argtypes = [C.c_void_p]
-        L.orc_n_events.restype = C.c_uint64
-        L.orc_n_events.argtypes = [C.c_void_p]
-        L.orc_n_spikes.restype = C.c_uint64
-        L.orc_n_spikes.argtypes = [C.c_void_p]
-        L.orc_get_spikes.argtypes = [C.c_void_p, P64, P32, P32]
-        L.orc_n_synapses.restype = C.c_uint64
-        L.orc_n_synapses.argtypes = [C.c_void_p]
-        L.orc_get_synapses.argtypes = [C.c_void_p, P32, P32, P32, P32, PI64]
-        L.orc_shift_of.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32]
-        L.orc_poisson_count.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, P32]
-        L.orc_record_input.argtypes = [C.c_void_p, PI64, C.c_uint64]
-        L.orc_replay_input.argtypes = [C.c_void_p, C.c_uint64, P64, P32, P32, C.c_uint64, PI64]
-        L.orc_lif_delta_step64.argtypes = [C.POINTER(PopParams), C.c_double, PD, C.POINTER(C.c_int32),
-                                           C.c_double, C.c_double]
-        L.orc_lif_delta_step32.argtypes = [C.POINTER(PopParams), C.c_double, C.POINTER(C.c_float),
-                                           C.POINTER(C.c_int32), C.c_float, C.c_float]
-        L.orc_lif_exp_step64.argtypes = [C.POINTER(PopParams), C.c_double, PD, PD, C.POINTER(C.c_int32),
-                                         C.c_double, PD]
-        L.orc_lif_exp_step32.argtypes = [C.POINTER(PopParams), C.c_double, C.POINTER(C.c_float),
-                                         C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_float,
-                                         C.POINTER(C.c_float)]
-        L.orc_lif_propagators.argtypes = [C.POINTER(PopParams), C.c_double, PD]
-        L.orc_adex_step.argtypes = [C.POINTER(PopParams), C.c_double, PD, PD, C.c_double, PD,
-                                    P64, P64]
-        L.orc_cash_karp_tableau.argtypes = [PD, PD, PD, PD]
-        L.orc_adex_rhs.argtypes = [C.POINTER(PopParams), C.c_double, PD, PD]
-        L.orc_prepare.argtypes = [C.c_void_p]
-        L.orc_target_synapses.restype = C.c_int64
-        L.orc_target_synapses.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, P32, P32, P32, PI64]
-        L.orc_sampled_input.argtypes = [C.c_void_p, C.c_uint32, P32, C.c_uint64, P64, P32, P32, C.c_uint64, PI64]
-        L.orc_last_error.restype = C.c_char_p
-        L.orc_last_error.argtypes = [C.c_void_p]
-        _lib = L
+        _lib = _declare(C.CDLL(build_oracle()))
     return _lib
+
+
+def _declare(L):
+    """ctypes signatures of the oracle's C functions."""
+    P64, P32, PU32, PI64, PD = (C.POINTER(C.c_uint64), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                C.POINTER(C.c_int64), C.POINTER(C.c_double))
+    L.orc_philox4x64_10.argtypes = [P64, P64, P64]
+    L.orc_delay_table.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_uint32, P64]
+    L.orc_poisson_table.argtypes = [C.c_double, C.c_uint32, P64]
+    L.orc_fixed_point_shift.argtypes = [C.c_double]
+    L.orc_create.restype = C.c_void_p
+    L.orc_create.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_int]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_population.restype = C.c_int64
+    L.orc_population.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(PopParams)]
+    L.orc_set_spike_times.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
+    L.orc_connect_list.argtypes = [C.c_void_p, C.c_uint64, P32, P32, PD, C.c_double, C.c_uint32]
+    L.orc_weight_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_double, C.c_double, C.c_double,
+                                          C.c_double, C.c_uint32]
+    L.orc_list_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
+    L.orc_state_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_uint32, C.c_int,
+                                         C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32]
+    L.orc_connect.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                              C.c_double, C.c_int, C.c_double, C.c_double, C.c_uint32]
+    L.orc_connect_fixed_indegree.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                             C.c_uint32, C.c_double, C.c_int, C.c_double, C.c_double,
+                                             C.c_uint32]
+    L.orc_poisson.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double,
+                              C.c_uint32]
+    L.orc_set_state.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_uint32, PD]
+    L.orc_get_state.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_uint32, PD]
+    L.orc_build.argtypes = [C.c_void_p]
+    L.orc_simulate.argtypes = [C.c_void_p, C.c_uint64]
+    L.orc_current_step.restype = C.c_uint64
+    L.orc_current_step.argtypes = [C.c_void_p]
+    L.orc_n_events.restype = C.c_uint64
+    L.orc_n_events.argtypes = [C.c_void_p]
+    L.orc_n_spikes.restype = C.c_uint64
+    L.orc_n_spikes.argtypes = [C.c_void_p]
+    L.orc_get_spikes.argtypes = [C.c_void_p, P64, P32, P32]
+    L.orc_n_synapses.restype = C.c_uint64
+    L.orc_n_synapses.argtypes = [C.c_void_p]
+    L.orc_get_synapses.argtypes = [C.c_void_p, P32, P32, P32, P32, PI64]
+    L.orc_shift_of.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32]
+    L.orc_poisson_count.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, P32]
+    L.orc_record_input.argtypes = [C.c_void_p, PI64, C.c_uint64]
+    L.orc_replay_input.argtypes = [C.c_void_p, C.c_uint64, P64, P32, P32, C.c_uint64, PI64]
+    L.orc_lif_delta_step64.argtypes = [C.POINTER(PopParams), C.c_double, PD, C.POINTER(C.c_int32),
+                                       C.c_double, C.c_double]
+    L.orc_lif_delta_step32.argtypes = [C.POINTER(PopParams), C.c_double, C.POINTER(C.c_float),
+                                       C.POINTER(C.c_int32), C.c_float, C.c_float]
+    L.orc_lif_exp_step64.argtypes = [C.POINTER(PopParams), C.c_double, PD, PD, C.POINTER(C.c_int32),
+                                     C.c_double, PD]
+    L.orc_lif_exp_step32.argtypes = [C.POINTER(PopParams), C.c_double, C.POINTER(C.c_float),
+                                     C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_float,
+                                     C.POINTER(C.c_float)]
+    L.orc_lif_propagators.argtypes = [C.POINTER(PopParams), C.c_double, PD]
+    L.orc_adex_step.argtypes = [C.POINTER(PopParams), C.c_double, PD, PD, C.c_double, PD,
+                                P64, P64]
+    L.orc_cash_karp_tableau.argtypes = [PD, PD, PD, PD]
+    L.orc_adex_rhs.argtypes = [C.POINTER(PopParams), C.c_double, PD, PD]
+    L.orc_prepare.argtypes = [C.c_void_p]
+    L.orc_target_synapses.restype = C.c_int64
+    L.orc_target_synapses.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, P32, P32, P32, PI64]
+    L.orc_sampled_input.argtypes = [C.c_void_p, C.c_uint32, P32, C.c_uint64, P64, P32, P32, C.c_uint64, PI64]
+    L.orc_last_error.restype = C.c_char_p
+    L.orc_last_error.argtypes = [C.c_void_p]
+    L.orc_threads.restype = C.c_int
+    L.orc_threads.argtypes = []
+    return L
 
 
 def _ptr(a, ctype):
@@ -247,12 +269,14 @@ def adex_step(params: PopParams, dt: float, y, h: float, I_e: float, x):
 class OracleNet:
     """Oracle instance built from a specification dictionary."""
 
-    def __init__(self, spec: dict, mode: int = FP64, build: bool = True):
+    def __init__(self, spec: dict, mode: int = FP64, build: bool = True, openmp: bool = False):
         """build=False prepares state, Poisson drive and fixed-point exponents
         but draws no synapse table: for the sampled checks of networks whose
         table does not fit (target_synapses, sampled_input, poisson_count,
-        shift_of); such a network cannot be simulated."""
-        self.L = lib()
+        shift_of); such a network cannot be simulated.  openmp=True runs on
+        the OpenMP build (all host cores, same results)."""
+        self.L = lib_omp() if openmp else lib()
+        self.threads = int(self.L.orc_threads())
         self.spec = spec
         self.mode = mode
         self.h = self.L.orc_create(spec["dt"], spec["seed"], spec["dmax"], mode)

@@ -25,6 +25,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
@@ -185,6 +188,7 @@ struct orc_net {
   float* Vf; float* If; float* Ief;
   /* integer input accumulator for the next step, N*P */
   int64_t* acc;
+  uint32_t* mult_now;       /* N: spike multiplicity of each neuron in the current step */
   uint64_t step;
   /* spike record */
   uint64_t n_spk, cap_spk;
@@ -222,7 +226,7 @@ void orc_destroy(orc_net* o) {
   free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->gr); free(o->I); free(o->h); free(o->refr);
   if (o->gen_steps) for (uint32_t i = 0; i < o->N; ++i) free(o->gen_steps[i]);
   free(o->gen_steps); free(o->gen_n); free(o->gen_pos);
-  free(o->Vf); free(o->If); free(o->Ief); free(o->acc);
+  free(o->Vf); free(o->If); free(o->Ief); free(o->acc); free(o->mult_now);
   free(o->spk_step); free(o->spk_gid); free(o->spk_mult); free(o->spk_at);
   free(o);
 }
@@ -503,6 +507,7 @@ static void alloc_state(orc_net* o) {
   o->If = (float*)calloc(N * P, sizeof(float));
   o->Ief = (float*)calloc(N, sizeof(float));
   o->acc = (int64_t*)calloc(N * P, sizeof(int64_t));
+  o->mult_now = (uint32_t*)calloc(N, sizeof(uint32_t));
   for (size_t i = 0; i < N; ++i) o->V[i] = o->pops[o->pop_of[i]].E_L; /* rest */
   for (size_t i = 0; i < N; ++i) {
     const orc_pop_params* pp = &o->pops[o->pop_of[i]];
@@ -1163,11 +1168,71 @@ int orc_sampled_input(orc_net* o, uint32_t nt, const uint32_t* tgt, uint64_t n_s
   return 0;
 }
 
+/* Update of neuron i at step n; returns its spike multiplicity.  The
+   accepted and rejected RK45 substeps are added to *ra and *rr. */
+static int update_neuron(orc_net* o, uint64_t n, uint32_t i, uint64_t* ra, uint64_t* rr) {
+  uint32_t P = o->P;
+  int f32 = (o->mode == ORC_FP32SO);
+  double xd[ORC_MAX_PORTS]; float xf[ORC_MAX_PORTS];
+  uint32_t pk = o->pop_of[i];
+  const orc_pop_params* pp = &o->pops[pk];
+  int64_t xin[ORC_MAX_PORTS];
+  for (uint32_t p = 0; p < P; ++p) { xin[p] = o->acc[(size_t)i * P + p]; o->acc[(size_t)i * P + p] = 0; }
+  if (o->pois_of[i] >= 0) {
+    const orc_pois* q = &o->pois[o->pois_of[i]];
+    int S = o->shift[pk * P + q->port];
+    int64_t wq = llrint(ldexp(q->weight, S));
+    xin[q->port] += (int64_t)poisson_draw(o, q, i, n) * wq;
+  }
+  for (uint32_t p = 0; p < pp->n_ports; ++p) {
+    int S = o->shift[pk * P + p];
+    xd[p] = ldexp((double)xin[p], -S);
+    xf[p] = ldexpf((float)xin[p], -S);
+  }
+  int m = 0;
+  if (pp->model == ORC_SPIKE_GENERATOR) {
+    /* skip times already passed, then count the ones of this step */
+    while (o->gen_pos[i] < o->gen_n[i] && o->gen_steps[i][o->gen_pos[i]] < n) o->gen_pos[i]++;
+    while (o->gen_pos[i] < o->gen_n[i] && o->gen_steps[i][o->gen_pos[i]] == n) { o->gen_pos[i]++; m++; }
+  } else if (pp->model == ORC_PARROT) {
+    /* unit weights: the input is the number of arriving spikes */
+    m = xin[0] > 0 ? (int)(xin[0] >> o->shift[pk * P]) : 0;
+  } else if (pp->model == ORC_LIF_DELTA) {
+    if (f32) m = orc_lif_delta_step32(pp, o->dt, &o->Vf[i], &o->refr[i], o->Ief[i], xf[0]);
+    else {
+      double y = o->V[i] - pp->E_L;
+      m = orc_lif_delta_step64(pp, o->dt, &y, &o->refr[i], o->Ie[i], xd[0]);
+      o->V[i] = y + pp->E_L;
+    }
+  } else if (pp->model == ORC_LIF_EXP) {
+    if (f32) m = orc_lif_exp_step32(pp, o->dt, &o->Vf[i], &o->If[(size_t)i * P], &o->refr[i], o->Ief[i], xf);
+    else {
+      double y = o->V[i] - pp->E_L;
+      m = orc_lif_exp_step64(pp, o->dt, &y, &o->I[(size_t)i * P], &o->refr[i], o->Ie[i], xd);
+      o->V[i] = y + pp->E_L;
+    }
+  } else {
+    double yv[2 + 2 * ORC_MAX_PORTS];
+    uint32_t np = pp->n_ports;
+    yv[0] = o->V[i]; yv[1] = o->w[i];
+    for (uint32_t p = 0; p < np; ++p) yv[2 + p] = o->g[(size_t)i * P + p];
+    for (uint32_t p = 0; p < np; ++p) yv[2 + np + p] = o->gr[(size_t)i * P + p];
+    m = orc_adex_step(pp, o->dt, yv, &o->h[i], o->Ie[i], xd, ra, rr);
+    o->V[i] = yv[0]; o->w[i] = yv[1];
+    for (uint32_t p = 0; p < np; ++p) o->g[(size_t)i * P + p] = yv[2 + p];
+    if (pp->model == ORC_AEIF_COND_BETA)
+      for (uint32_t p = 0; p < np; ++p) o->gr[(size_t)i * P + p] = yv[2 + np + p];
+  }
+  return m;
+}
+
+/* The neuron loop and the delivery loop carry OpenMP pragmas, which a plain
+   build ignores: the neurons of a step are independent (their spikes are
+   recorded afterwards, in gid order) and the delivered sums are integers
+   added atomically, so a build with OpenMP gives the same results. */
 int orc_simulate(orc_net* o, uint64_t steps) {
   if (!o->built) { set_err(o, "simulate before build"); return -1; }
   uint32_t P = o->P, D1 = o->dmax + 1;
-  double xd[ORC_MAX_PORTS]; float xf[ORC_MAX_PORTS];
-  int f32 = (o->mode == ORC_FP32SO);
   for (uint64_t it = 0; it < steps; ++it) {
     uint64_t n = o->step;
     if (o->rec && n < o->rec_max) memcpy(o->rec + (size_t)n * o->N * P, o->acc, (size_t)o->N * P * sizeof(int64_t));
@@ -1177,76 +1242,44 @@ int orc_simulate(orc_net* o, uint64_t steps) {
     }
     o->spk_at[n] = o->n_spk;
     /* update of step n */
-    for (uint32_t i = 0; i < o->N; ++i) {
-      uint32_t pk = o->pop_of[i];
-      const orc_pop_params* pp = &o->pops[pk];
-      int64_t xin[ORC_MAX_PORTS];
-      for (uint32_t p = 0; p < P; ++p) { xin[p] = o->acc[(size_t)i * P + p]; o->acc[(size_t)i * P + p] = 0; }
-      if (o->pois_of[i] >= 0) {
-        const orc_pois* q = &o->pois[o->pois_of[i]];
-        int S = o->shift[pk * P + q->port];
-        int64_t wq = llrint(ldexp(q->weight, S));
-        xin[q->port] += (int64_t)poisson_draw(o, q, i, n) * wq;
-      }
-      for (uint32_t p = 0; p < pp->n_ports; ++p) {
-        int S = o->shift[pk * P + p];
-        xd[p] = ldexp((double)xin[p], -S);
-        xf[p] = ldexpf((float)xin[p], -S);
-      }
-      int m = 0;
-      if (pp->model == ORC_SPIKE_GENERATOR) {
-        /* skip times already passed, then count the ones of this step */
-        while (o->gen_pos[i] < o->gen_n[i] && o->gen_steps[i][o->gen_pos[i]] < n) o->gen_pos[i]++;
-        while (o->gen_pos[i] < o->gen_n[i] && o->gen_steps[i][o->gen_pos[i]] == n) { o->gen_pos[i]++; m++; }
-      } else if (pp->model == ORC_PARROT) {
-        /* unit weights: the input is the number of arriving spikes */
-        m = xin[0] > 0 ? (int)(xin[0] >> o->shift[pk * P]) : 0;
-      } else if (pp->model == ORC_LIF_DELTA) {
-        if (f32) m = orc_lif_delta_step32(pp, o->dt, &o->Vf[i], &o->refr[i], o->Ief[i], xf[0]);
-        else {
-          double y = o->V[i] - pp->E_L;
-          m = orc_lif_delta_step64(pp, o->dt, &y, &o->refr[i], o->Ie[i], xd[0]);
-          o->V[i] = y + pp->E_L;
-        }
-      } else if (pp->model == ORC_LIF_EXP) {
-        if (f32) m = orc_lif_exp_step32(pp, o->dt, &o->Vf[i], &o->If[(size_t)i * P], &o->refr[i], o->Ief[i], xf);
-        else {
-          double y = o->V[i] - pp->E_L;
-          m = orc_lif_exp_step64(pp, o->dt, &y, &o->I[(size_t)i * P], &o->refr[i], o->Ie[i], xd);
-          o->V[i] = y + pp->E_L;
-        }
-      } else {
-        double yv[2 + 2 * ORC_MAX_PORTS];
-        uint32_t np = pp->n_ports;
-        yv[0] = o->V[i]; yv[1] = o->w[i];
-        for (uint32_t p = 0; p < np; ++p) yv[2 + p] = o->g[(size_t)i * P + p];
-        for (uint32_t p = 0; p < np; ++p) yv[2 + np + p] = o->gr[(size_t)i * P + p];
-        m = orc_adex_step(pp, o->dt, yv, &o->h[i], o->Ie[i], xd, &o->rk_acc, &o->rk_rej);
-        o->V[i] = yv[0]; o->w[i] = yv[1];
-        for (uint32_t p = 0; p < np; ++p) o->g[(size_t)i * P + p] = yv[2 + p];
-        if (pp->model == ORC_AEIF_COND_BETA)
-          for (uint32_t p = 0; p < np; ++p) o->gr[(size_t)i * P + p] = yv[2 + np + p];
-      }
-      if (m > 0) record_spike(o, n, i, (uint32_t)m);
-    }
+    uint64_t ra = 0, rr = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : ra, rr)
+    for (int64_t i = 0; i < (int64_t)o->N; ++i) o->mult_now[i] = (uint32_t)update_neuron(o, n, (uint32_t)i, &ra, &rr);
+    o->rk_acc += ra; o->rk_rej += rr;
+    for (uint32_t i = 0; i < o->N; ++i)
+      if (o->mult_now[i] > 0) record_spike(o, n, i, o->mult_now[i]);
     o->spk_at[n + 1] = o->n_spk;
     /* delivery: input of step n+1 */
-    for (uint32_t d = 1; d <= o->dmax && d <= n + 1; ++d) {
-      uint64_t nf = n + 1 - d;
+    uint64_t ev = 0;
+    int64_t dtop = (int64_t)(o->dmax < n + 1 ? o->dmax : n + 1);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : ev)
+    for (int64_t d = 1; d <= dtop; ++d) {
+      uint64_t nf = n + 1 - (uint64_t)d;
       for (uint64_t q = o->spk_at[nf]; q < o->spk_at[nf + 1]; ++q) {
         uint32_t s = o->spk_gid[q];
         int64_t m = (int64_t)o->spk_mult[q];
         uint64_t b = o->off[(size_t)s * D1 + d], e = o->off[(size_t)s * D1 + d + 1];
-        o->n_events += e - b;
+        ev += e - b;
         for (uint64_t r = b; r < e; ++r) {
           const orc_syn* sy = &o->syn[r];
+#pragma omp atomic
           o->acc[(size_t)sy->tgt * P + sy->port] += m * sy->wq;
         }
       }
     }
+    o->n_events += ev;
     o->step = n + 1;
   }
   return 0;
+}
+
+/* Threads the simulation loops run on (1 without OpenMP). */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 uint64_t orc_current_step(const orc_net* o) { return o->step; }

@@ -191,6 +191,9 @@ void orc_adex_rhs(const orc_pop_params*, double I_e, const double* y, double* dy
 double orc_beta_g0(double tau_rise, double tau_decay);
 
 const char* orc_last_error(const orc_net*);
+/* Threads the simulation loops use: 1, or OpenMP's thread count in a build
+   with -fopenmp (same results either way). */
+int orc_threads(void);
 
 #ifdef __cplusplus
 }

@@ -106,3 +106,20 @@ def test_c0_literal_is_subthreshold_and_c0a_active():
     n1.simulate(1000)
     rate = len(n1.spikes()[0]) / 1000 / 0.1
     assert 20.0 < rate < 200.0
+
+
+def test_openmp_build_gives_the_same_results():
+    """The oracle built with OpenMP (the all-core CPU baseline) simulates
+    exactly what the plain build simulates: rasters, potentials and event
+    counts of a small microcircuit and an AdEx net."""
+    from paper_2007_14236_amd import workloads as W
+    for spec, steps in ((W.c0(active=True), 300), (W.microcircuit(scale=0.05, k_scale=0.5), 300), (W.adex_balanced(n=400, k=40), 600)):
+        a = O.OracleNet(spec, O.FP64)
+        b = O.OracleNet(spec, O.FP64, openmp=True)
+        a.simulate(steps)
+        b.simulate(steps)
+        for x, y in zip(a.spikes(), b.spikes()):
+            assert np.array_equal(x, y)
+        assert len(a.spikes()[0]) > 0
+        assert np.array_equal(a.get_state("V_m"), b.get_state("V_m"))
+        assert a.events == b.events
