@@ -24,6 +24,8 @@ MODEL_IDS = {"lif_delta": LIF_DELTA, "lif_exp": LIF_EXP, "aeif_cond_exp": AEIF_C
              "aeif_cond_beta": AEIF_COND_BETA, "spike_generator": SPIKE_GENERATOR, "parrot_neuron": PARROT}
 DELAY_IDS = {"const": 0, "uniform": 1, "normal": 2}
 VAR_IDS = {"V_m": 0, "I_e": 1, "w": 2, "g": 3, "I_syn": 4, "refr": 5, "h": 6, "g_rise": 7}
+PARAM_IDS = {"tau_m": 0, "C_m": 1, "E_L": 2, "V_th": 3, "V_reset": 4, "t_ref": 5, "g_L": 6, "Delta_T": 7,
+             "V_T": 8, "tau_w": 9, "a": 10, "b": 11, "V_peak": 12, "V_r": 13, "rk_eps": 14, "rk_hmin": 15}
 # connection rules; a projection's "K" is the in-degree, the out-degree or the
 # number of synapses (unused for all_to_all and one_to_one)
 RULE_IDS = {"fixed_indegree": 0, "fixed_outdegree": 1, "all_to_all": 2, "one_to_one": 3, "fixed_total_number": 4}
@@ -109,6 +111,11 @@ def _declare(L):
     L.orc_weight_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_int, C.c_double, C.c_double, C.c_double,
                                           C.c_double, C.c_uint32]
     L.orc_list_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
+    L.orc_set_param.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, PD]
+    L.orc_get_param.restype = C.c_double
+    L.orc_get_param.argtypes = [C.c_void_p, C.c_uint32, C.c_int]
+    L.orc_param_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_int, C.c_double,
+                                         C.c_double, C.c_double, C.c_double, C.c_uint32]
     L.orc_state_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_uint32, C.c_int,
                                          C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32]
     L.orc_connect.argtypes = [C.c_void_p, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -201,7 +208,8 @@ def pop_params(model: str, ports: int, params: dict) -> PopParams:
                     g_L=30.0, Delta_T=2.0, V_T=-50.4, tau_w=144.0, a=4.0, b=80.5, V_peak=0.0,
                     V_r=-60.0, rk_eps=1e-6, rk_hmin=1e-8)
     for k, v in defaults.items():
-        setattr(p, k, float(params.get(k, v)))
+        x = params.get(k, v)
+        setattr(p, k, float(v if np.ndim(x) else x))  # per-neuron arrays are set afterwards
     ts = list(params.get("tau_syn", [1.0] * ports))
     er = list(params.get("E_rev", [0.0] * ports))
     tr = list(params.get("tau_rise", ts))  # default: rise = decay, the alpha function
@@ -289,6 +297,17 @@ class OracleNet:
             self._check(first >= 0)
             self.ranges[p["name"]] = (int(first), p["n"])
         self.N = sum(p["n"] for p in spec["populations"])
+        for p in spec["populations"]:  # per-neuron parameters: after every population, before any state
+            t0, tn = self.ranges[p["name"]]
+            for k, x in p["params"].items():
+                if k in PARAM_IDS and np.ndim(x):
+                    v = np.ascontiguousarray(x, dtype=np.float64)
+                    assert len(v) == tn
+                    self._check(self.L.orc_set_param(self.h, t0, tn, PARAM_IDS[k], _ptr(v, C.c_double)) == 0)
+            for k, wd in (p.get("param_dists") or {}).items():
+                kind, a, b, lo, hi, _ = weight_dist_args(wd)
+                self._check(self.L.orc_param_distribution(self.h, t0, tn, PARAM_IDS[k], kind, a, b, lo, hi,
+                                                          int(wd.get("levels", 1024))) == 0)
         for p in spec["populations"]:  # after every population: state is sized then
             for j, times in enumerate(p.get("spike_times", []) or []):
                 t = np.ascontiguousarray(times, dtype=np.float64)
@@ -345,6 +364,11 @@ class OracleNet:
     def set_state(self, var: str, first: int, values, port: int = 0):
         v = np.ascontiguousarray(values, dtype=np.float64)
         self._check(self.L.orc_set_state(self.h, first, len(v), VAR_IDS[var], port, _ptr(v, C.c_double)) == 0)
+
+    def get_param(self, name: str, first: int = 0, n: int | None = None) -> np.ndarray:
+        """Model parameter `name` of every neuron of [first, first + n)."""
+        n = self.N - first if n is None else n
+        return np.array([self.L.orc_get_param(self.h, first + j, PARAM_IDS[name]) for j in range(n)])
 
     def get_state(self, var: str, first: int = 0, n: int | None = None, port: int = 0) -> np.ndarray:
         n = self.N - first if n is None else n

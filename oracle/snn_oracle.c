@@ -171,6 +171,7 @@ struct orc_net {
   uint32_t N;
   uint32_t P;               /* ports per neuron slot (max over populations) */
   uint32_t* pop_of;         /* N */
+  orc_pop_params* npar;     /* N: each neuron's own parameters once any is set per neuron, else NULL */
   /* projections and Poisson drives */
   uint32_t n_proj; orc_proj* proj;
   uint32_t n_pois; orc_pois* pois;
@@ -207,6 +208,10 @@ static int is_adex(const orc_pop_params* pp) {
   return pp->model == ORC_AEIF_COND_EXP || pp->model == ORC_AEIF_COND_BETA;
 }
 const char* orc_last_error(const orc_net* o) { return o ? o->err : "null net"; }
+/* the parameters neuron i is updated with (pop: its population) */
+static const orc_pop_params* neuron_params(const orc_net* o, uint32_t i, uint32_t pop) {
+  return o->npar ? &o->npar[i] : &o->pops[pop];
+}
 
 orc_net* orc_create(double dt_ms, uint64_t seed, uint32_t max_delay_steps, int mode) {
   if (!(dt_ms > 0) || max_delay_steps < 1 || max_delay_steps > 63) return NULL;
@@ -221,7 +226,7 @@ void orc_destroy(orc_net* o) {
     free(o->proj[p].lsrc); free(o->proj[p].ltgt); free(o->proj[p].ldel);
     free(o->proj[p].wlev); free(o->proj[p].wthr); free(o->proj[p].lwl);
   }
-  free(o->pops); free(o->pop_first); free(o->pop_of); free(o->proj); free(o->pois); free(o->pois_of);
+  free(o->pops); free(o->pop_first); free(o->pop_of); free(o->npar); free(o->proj); free(o->pois); free(o->pois_of);
   free(o->shift); free(o->syn); free(o->off);
   free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->gr); free(o->I); free(o->h); free(o->refr);
   if (o->gen_steps) for (uint32_t i = 0; i < o->N; ++i) free(o->gen_steps[i]);
@@ -235,6 +240,7 @@ int64_t orc_population(orc_net* o, uint32_t n, const orc_pop_params* p) {
   if (o->built || o->shift) { set_err(o, "population after build"); return -1; }
   if (n == 0 || p->n_ports < 1 || p->n_ports > ORC_MAX_PORTS) { set_err(o, "bad population"); return -1; }
   if (o->V) { set_err(o, "population after state was set"); return -1; }
+  if (o->npar) { set_err(o, "population after per-neuron parameters"); return -1; }
   if (p->model < ORC_LIF_DELTA || p->model > ORC_PARROT) { set_err(o, "bad model"); return -1; }
   if ((p->model == ORC_SPIKE_GENERATOR || p->model == ORC_PARROT) && p->n_ports != 1) {
     set_err(o, "devices have one port"); return -1;
@@ -394,6 +400,70 @@ int orc_weight_distribution(orc_net* o, uint32_t proj, int kind, double a, doubl
   return 0;
 }
 
+int orc_set_param(orc_net* o, uint32_t first, uint32_t n, int param, const double* v) {
+  if (o->N == 0 || (uint64_t)first + n > o->N) { set_err(o, "range"); return -1; }
+  if (o->V) { set_err(o, "per-neuron parameters come before any state"); return -1; }
+  if (!o->npar) {
+    o->npar = (orc_pop_params*)malloc((size_t)o->N * sizeof(orc_pop_params));
+    for (uint32_t i = 0; i < o->N; ++i) o->npar[i] = o->pops[pop_index(o, i)];
+  }
+  for (uint32_t j = 0; j < n; ++j) {
+    orc_pop_params* q = &o->npar[first + j];
+    double x = v[j];
+    switch (param) {
+      case 0: q->tau_m = x; break;
+      case 1: q->C_m = x; break;
+      case 2: q->E_L = x; break;
+      case 3: q->V_th = x; break;
+      case 4: q->V_reset = x; break;
+      case 5: q->t_ref = x; break;
+      case 6: q->g_L = x; break;
+      case 7: q->Delta_T = x; break;
+      case 8: q->V_T = x; break;
+      case 9: q->tau_w = x; break;
+      case 10: q->a = x; break;
+      case 11: q->b = x; break;
+      case 12: q->V_peak = x; break;
+      case 13: q->V_r = x; break;
+      case 14: q->rk_eps = x; break;
+      case 15: q->rk_hmin = x; break;
+      default: set_err(o, "param"); return -1;
+    }
+  }
+  return 0;
+}
+
+double orc_get_param(const orc_net* o, uint32_t gid, int param) {
+  if (gid >= o->N) return NAN;
+  const orc_pop_params* q = neuron_params(o, gid, pop_index(o, gid));
+  const double v[16] = {q->tau_m, q->C_m, q->E_L, q->V_th, q->V_reset, q->t_ref, q->g_L, q->Delta_T,
+                        q->V_T, q->tau_w, q->a, q->b, q->V_peak, q->V_r, q->rk_eps, q->rk_hmin};
+  return (param >= 0 && param < 16) ? v[param] : NAN;
+}
+
+int orc_param_distribution(orc_net* o, uint32_t first, uint32_t n, int param, int kind, double a, double b,
+                           double lo, double hi, uint32_t levels) {
+  if (o->N == 0 || (uint64_t)first + n > o->N) { set_err(o, "range"); return -1; }
+  if (param < 0 || param > 15) { set_err(o, "param"); return -1; }
+  if (levels < 1 || levels > ORC_STATE_LEVELS_MAX) { set_err(o, "levels"); return -1; }
+  double* lev = (double*)malloc(levels * sizeof(double));
+  uint64_t* thr = (uint64_t*)malloc(levels * sizeof(uint64_t));
+  double* v = (double*)malloc((n ? n : 1) * sizeof(double));
+  const char* e = dist_levels(kind, a, b, lo, hi, levels, lev, thr);
+  if (e) { free(lev); free(thr); free(v); set_err(o, e); return -1; }
+  uint64_t key[2] = {o->seed, 0};
+  for (uint32_t j = 0; j < n; ++j) {
+    uint64_t ctr[4] = {first + j, (uint64_t)param << 8, ORC_TAG_PARAM, 0}, blk[4];
+    orc_philox4x64_10(ctr, key, blk);
+    uint32_t u = (uint32_t)(blk[0] >> 32), l = 0;
+    while ((uint64_t)u >= thr[l]) ++l;
+    v[j] = lev[l];
+  }
+  int rc = orc_set_param(o, first, n, param, v);
+  free(lev); free(thr); free(v);
+  return rc;
+}
+
 /* State drawn from a distribution: neuron i takes the level of the top 32
    bits of word 0 of block (i, var << 8 | port, ORC_TAG_STATE, 0), key
    (seed, 0), then is set as by orc_set_state. */
@@ -508,9 +578,9 @@ static void alloc_state(orc_net* o) {
   o->Ief = (float*)calloc(N, sizeof(float));
   o->acc = (int64_t*)calloc(N * P, sizeof(int64_t));
   o->mult_now = (uint32_t*)calloc(N, sizeof(uint32_t));
-  for (size_t i = 0; i < N; ++i) o->V[i] = o->pops[o->pop_of[i]].E_L; /* rest */
+  for (size_t i = 0; i < N; ++i) o->V[i] = neuron_params(o, (uint32_t)i, o->pop_of[i])->E_L; /* rest */
   for (size_t i = 0; i < N; ++i) {
-    const orc_pop_params* pp = &o->pops[o->pop_of[i]];
+    const orc_pop_params* pp = neuron_params(o, (uint32_t)i, o->pop_of[i]);
     if (!is_adex(pp)) o->Vf[i] = (float)(o->V[i] - pp->E_L);
   }
 }
@@ -523,7 +593,7 @@ int orc_set_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port
   if ((var == 3 || var == 4 || var == 7) && port >= o->P) { set_err(o, "port"); return -1; }
   for (uint32_t j = 0; j < n; ++j) {
     uint32_t i = first + j;
-    const orc_pop_params* pp = &o->pops[o->pop_of[i]];
+    const orc_pop_params* pp = neuron_params(o, i, o->pop_of[i]);
     switch (var) {
       case 0:
         o->V[i] = v[j];
@@ -550,7 +620,7 @@ int orc_get_state(orc_net* o, uint32_t first, uint32_t n, int var, uint32_t port
   int f32 = (o->mode == ORC_FP32SO);
   for (uint32_t j = 0; j < n; ++j) {
     uint32_t i = first + j;
-    const orc_pop_params* pp = &o->pops[o->pop_of[i]];
+    const orc_pop_params* pp = neuron_params(o, i, o->pop_of[i]);
     int lif = !is_adex(pp);
     switch (var) {
       case 0: v[j] = (lif && f32) ? (double)o->Vf[i] + pp->E_L : o->V[i]; break;
@@ -1175,7 +1245,7 @@ static int update_neuron(orc_net* o, uint64_t n, uint32_t i, uint64_t* ra, uint6
   int f32 = (o->mode == ORC_FP32SO);
   double xd[ORC_MAX_PORTS]; float xf[ORC_MAX_PORTS];
   uint32_t pk = o->pop_of[i];
-  const orc_pop_params* pp = &o->pops[pk];
+  const orc_pop_params* pp = neuron_params(o, i, pk);
   int64_t xin[ORC_MAX_PORTS];
   for (uint32_t p = 0; p < P; ++p) { xin[p] = o->acc[(size_t)i * P + p]; o->acc[(size_t)i * P + p] = 0; }
   if (o->pois_of[i] >= 0) {

@@ -31,7 +31,7 @@ enum { ORC_FP64 = 0, ORC_FP32SO = 1 };
 enum { ORC_LIF_DELTA = 0, ORC_LIF_EXP = 1, ORC_AEIF_COND_EXP = 2, ORC_AEIF_COND_BETA = 3,
        ORC_SPIKE_GENERATOR = 4, ORC_PARROT = 5 };
 enum { ORC_DELAY_CONST = 0, ORC_DELAY_UNIFORM = 1, ORC_DELAY_NORMAL_CLIPPED = 2 };
-enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2, ORC_TAG_WEIGHT = 3, ORC_TAG_STATE = 4 };
+enum { ORC_TAG_CONN = 1, ORC_TAG_POISSON = 2, ORC_TAG_WEIGHT = 3, ORC_TAG_STATE = 4, ORC_TAG_PARAM = 5 };
 enum { ORC_WEIGHT_UNIFORM = 0, ORC_WEIGHT_NORMAL = 1, ORC_WEIGHT_LEVELS_MAX = 1024, ORC_STATE_LEVELS_MAX = 65536 };
 /* connection rules (Sec. 2.1): the count n is the in-degree, the out-degree,
    unused, unused, and the number of synapses, in that order */
@@ -120,6 +120,20 @@ int      orc_get_state(orc_net*, uint32_t first, uint32_t n, int var, uint32_t p
    `levels` <= ORC_STATE_LEVELS_MAX bins, midpoints): neuron i takes the
    level of the top 32 bits of word 0 of block (i, var << 8 | port,
    ORC_TAG_STATE, 0), then is set as by orc_set_state. */
+/* Per-neuron model parameters (Sec. 2.1: neuron parameters from arrays or
+   probability distributions): parameter `param` (0 tau_m, 1 C_m, 2 E_L, 3 V_th,
+   4 V_reset, 5 t_ref, 6 g_L, 7 Delta_T, 8 V_T, 9 tau_w, 10 a, 11 b, 12 V_peak,
+   13 V_r, 14 rk_eps, 15 rk_hmin) of neurons first..first+n-1 set to v[j]; the
+   other parameters stay the population's.  Must come before any state is set
+   or drawn (a neuron starts at its own E_L). */
+int      orc_set_param(orc_net*, uint32_t first, uint32_t n, int param, const double* v);
+/* parameter `param` of neuron gid (NaN for a bad gid or parameter) */
+double   orc_get_param(const orc_net*, uint32_t gid, int param);
+/* The same parameter drawn per neuron: neuron i takes the level of the top 32
+   bits of word 0 of block (i, param << 8, ORC_TAG_PARAM, 0), key (seed, 0),
+   of the discretised distribution (as orc_state_distribution). */
+int      orc_param_distribution(orc_net*, uint32_t first, uint32_t n, int param, int kind, double a, double b,
+                                double lo, double hi, uint32_t levels);
 int      orc_state_distribution(orc_net*, uint32_t first, uint32_t n, int var, uint32_t port, int kind, double a,
                                 double b, double lo, double hi, uint32_t levels);
 int      orc_build(orc_net*);
