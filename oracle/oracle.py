@@ -45,6 +45,18 @@ def weight_dist_args(wd: dict):
     return (WEIGHT_IDS["normal"], m, sd, float(wd.get("low", m - 4 * sd)), float(wd.get("high", m + 4 * sd)), L)
 
 
+STDP_DEFAULTS = dict(tau_plus=20.0, tau_minus=20.0, lambda_=0.01, alpha=1.0, mu_plus=1, mu_minus=1, w_max=100.0)
+
+
+def stdp_args(sd: dict):
+    """(tau_plus, tau_minus, lambda, alpha, mu_plus, mu_minus, w_max) of a
+    projection's "stdp" entry (NEST-like defaults)."""
+    v = dict(STDP_DEFAULTS)
+    v.update({("lambda_" if k == "lambda" else k): x for k, x in sd.items()})
+    return (float(v["tau_plus"]), float(v["tau_minus"]), float(v["lambda_"]), float(v["alpha"]), int(v["mu_plus"]),
+            int(v["mu_minus"]), float(v["w_max"]))
+
+
 class PopParams(C.Structure):
     _fields_ = [
         ("model", C.c_int32), ("n_ports", C.c_uint32),
@@ -112,6 +124,8 @@ def _declare(L):
                                           C.c_double, C.c_uint32]
     L.orc_list_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_uint64, PD]
     L.orc_set_param.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, PD]
+    L.orc_stdp.argtypes = [C.c_void_p, C.c_uint32, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                           C.c_int, C.c_double]
     L.orc_get_param.restype = C.c_double
     L.orc_get_param.argtypes = [C.c_void_p, C.c_uint32, C.c_int]
     L.orc_param_distribution.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_int, C.c_double,
@@ -333,6 +347,8 @@ class OracleNet:
                                            DELAY_IDS[kind], a, b, pr["port"]) == 0)
             if pr.get("weight_dist") is not None:
                 self._check(self.L.orc_weight_distribution(self.h, ip, *weight_dist_args(pr["weight_dist"])) == 0)
+            if pr.get("stdp") is not None:
+                self._check(self.L.orc_stdp(self.h, ip, *stdp_args(pr["stdp"])) == 0)
         for q in spec.get("poisson", []):
             t0, tn = self.ranges[q["tgt"]]
             self._check(self.L.orc_poisson(self.h, t0, tn, q["rate"], q["n_inputs"], q["weight"],

@@ -143,6 +143,9 @@ typedef struct {
   double* wlev;
   uint64_t* wthr;
   uint16_t* lwl;
+  /* nearest-neighbour STDP (orc_stdp): plastic != 0 */
+  int plastic, mu_plus, mu_minus;
+  double tau_plus, tau_minus, lambda, alpha, w_max;
 } orc_proj;
 
 typedef struct {
@@ -155,6 +158,7 @@ typedef struct {
   uint32_t src, tgt;
   uint8_t d, port;
   int64_t wq;
+  int32_t plast;  /* projection index of a plastic synapse, -1 for a static one */
 } orc_syn;
 
 struct orc_net {
@@ -200,6 +204,13 @@ struct orc_net {
   int64_t* rec; uint64_t rec_max;
   /* counters */
   uint64_t rk_acc, rk_rej;
+  /* plasticity: per synapse (canonical index) its weight, the step of its
+     latest pre arrival (-1: none), the multiplicity arriving now and its
+     largest weight W; per neuron its latest spike step (-1: none); the
+     plastic synapses onto each target (tptr[t] .. tptr[t+1] in tidx) */
+  uint64_t n_plastic;
+  int64_t* pw; int64_t* last_pre; uint32_t* arr_m; int64_t* pwmax; int64_t* last_post;
+  uint64_t* tptr; uint64_t* tidx;
   uint64_t n_events;        /* synapse deliveries (group sizes summed) */
 };
 
@@ -228,6 +239,7 @@ void orc_destroy(orc_net* o) {
   }
   free(o->pops); free(o->pop_first); free(o->pop_of); free(o->npar); free(o->proj); free(o->pois); free(o->pois_of);
   free(o->shift); free(o->syn); free(o->off);
+  free(o->pw); free(o->last_pre); free(o->arr_m); free(o->pwmax); free(o->last_post); free(o->tptr); free(o->tidx);
   free(o->V); free(o->Ie); free(o->w); free(o->g); free(o->gr); free(o->I); free(o->h); free(o->refr);
   if (o->gen_steps) for (uint32_t i = 0; i < o->N; ++i) free(o->gen_steps[i]);
   free(o->gen_steps); free(o->gen_n); free(o->gen_pos);
@@ -490,6 +502,22 @@ int orc_state_distribution(orc_net* o, uint32_t first, uint32_t n, int var, uint
   return rc;
 }
 
+int orc_stdp(orc_net* o, uint32_t proj, double tau_plus, double tau_minus, double lambda, double alpha, int mu_plus,
+             int mu_minus, double w_max) {
+  if (o->built || o->shift) { set_err(o, "stdp after build"); return -1; }
+  if (proj >= o->n_proj) { set_err(o, "no such projection"); return -1; }
+  if (!(tau_plus > 0) || !(tau_minus > 0) || !(lambda > 0) || !(lambda <= 1) || !(alpha >= 0) ||
+      !(alpha * lambda <= 1) || !(w_max > 0) || (mu_plus != 0 && mu_plus != 1) || (mu_minus != 0 && mu_minus != 1)) {
+    set_err(o, "bad stdp parameters"); return -1;
+  }
+  orc_proj* pr = &o->proj[proj];
+  double lo = pr->wlevels ? pr->wlev[0] : pr->weight, hi = pr->wlevels ? pr->wlev[pr->wlevels - 1] : pr->weight;
+  if (lo < 0 || hi > w_max) { set_err(o, "plastic weights must lie in [0, w_max]"); return -1; }
+  pr->plastic = 1; pr->tau_plus = tau_plus; pr->tau_minus = tau_minus; pr->lambda = lambda; pr->alpha = alpha;
+  pr->mu_plus = mu_plus; pr->mu_minus = mu_minus; pr->w_max = w_max;
+  return 0;
+}
+
 int orc_list_weights(orc_net* o, uint32_t proj, uint64_t n, const double* weights) {
   if (o->built || o->shift) { set_err(o, "weights after build"); return -1; }
   if (proj >= o->n_proj || o->proj[proj].rule != ORC_RULE_LIST || o->proj[proj].n != n) {
@@ -646,6 +674,7 @@ static int syn_cmp(const void* pa, const void* pb) {
   if (a->tgt != b->tgt) return a->tgt < b->tgt ? -1 : 1;
   if (a->port != b->port) return a->port < b->port ? -1 : 1;
   if (a->wq != b->wq) return a->wq < b->wq ? -1 : 1;
+  if ((a->plast >= 0) != (b->plast >= 0)) return a->plast < 0 ? -1 : 1;  /* static before plastic */
   return 0;
 }
 
@@ -686,6 +715,7 @@ static int prepare(orc_net* o) {
         if (pr->port >= o->pops[k].n_ports) { set_err(o, "port out of range"); free(maxw); return -1; }
         double aw = fabs(pr->weight);
         for (uint32_t j = 0; j < pr->wlevels; ++j) aw = j ? fmax(aw, fabs(pr->wlev[j])) : fabs(pr->wlev[j]);
+        if (pr->plastic) aw = fmax(aw, pr->w_max);  /* a plastic weight grows up to w_max */
         if (aw > maxw[k * P + pr->port]) maxw[k * P + pr->port] = aw;
         /* conductances jump by the weight: none may be negative */
         int cond = o->pops[k].model == ORC_AEIF_COND_EXP || o->pops[k].model == ORC_AEIF_COND_BETA;
@@ -826,6 +856,7 @@ int orc_build(orc_net* o) {
         orc_syn sy;
         sy.src = s; sy.tgt = t; sy.port = (uint8_t)pr->port; sy.d = (uint8_t)d;
         sy.wq = synapse_wq(o, p, first + j, k, t, wblk);
+        sy.plast = pr->plastic ? (int32_t)p : -1;
         o->syn[pos++] = sy;
       }
     }
@@ -835,6 +866,32 @@ int orc_build(orc_net* o) {
   o->off = (uint64_t*)calloc((size_t)o->N * D1 + 1, sizeof(uint64_t));
   for (uint64_t e = 0; e < o->n_syn; ++e) o->off[(size_t)o->syn[e].src * D1 + o->syn[e].d + 1]++;
   for (size_t k = 1; k <= (size_t)o->N * D1; ++k) o->off[k] += o->off[k - 1];
+  /* plastic synapses: their weights, last arrivals and the index by target */
+  for (uint64_t e = 0; e < o->n_syn; ++e) o->n_plastic += o->syn[e].plast >= 0;
+  if (o->n_plastic) {
+    o->pw = (int64_t*)malloc(o->n_syn * sizeof(int64_t));
+    o->pwmax = (int64_t*)malloc(o->n_syn * sizeof(int64_t));
+    o->last_pre = (int64_t*)malloc(o->n_syn * sizeof(int64_t));
+    o->arr_m = (uint32_t*)calloc(o->n_syn, sizeof(uint32_t));
+    o->last_post = (int64_t*)malloc((size_t)o->N * sizeof(int64_t));
+    o->tptr = (uint64_t*)calloc((size_t)o->N + 1, sizeof(uint64_t));
+    o->tidx = (uint64_t*)malloc(o->n_plastic * sizeof(uint64_t));
+    for (uint32_t i = 0; i < o->N; ++i) o->last_post[i] = -1;
+    for (uint64_t e = 0; e < o->n_syn; ++e) {
+      const orc_syn* sy = &o->syn[e];
+      o->pw[e] = sy->wq;
+      o->last_pre[e] = -1;
+      o->pwmax[e] = 0;
+      if (sy->plast < 0) continue;
+      o->pwmax[e] = llrint(ldexp(o->proj[sy->plast].w_max, o->shift[o->pop_of[sy->tgt] * P + sy->port]));
+      o->tptr[sy->tgt + 1]++;
+    }
+    for (uint32_t i = 0; i < o->N; ++i) o->tptr[i + 1] += o->tptr[i];
+    uint64_t* fill = (uint64_t*)calloc((size_t)o->N, sizeof(uint64_t));
+    for (uint64_t e = 0; e < o->n_syn; ++e)
+      if (o->syn[e].plast >= 0) o->tidx[o->tptr[o->syn[e].tgt] + fill[o->syn[e].tgt]++] = e;
+    free(fill);
+  }
   /* spike record */
   o->cap_spk = 1024;
   o->spk_step = (uint64_t*)malloc(o->cap_spk * sizeof(uint64_t));
@@ -1296,6 +1353,61 @@ static int update_neuron(orc_net* o, uint64_t n, uint32_t i, uint64_t* ra, uint6
   return m;
 }
 
+/* Nearest-neighbour STDP (Sec. 2.1, after Morrison et al. 2008), with the
+   power-law weight dependence of Guetig et al. (2003) in fixed point.  A
+   synapse's spikes are its pre arrivals (step a: the update of step a
+   receives the spike) and its target's spikes (step k: emitted in the
+   update of step k); in one step the arrival comes first.  Pairs are
+   nearest neighbours: each post spike at k pairs with the synapse's latest
+   arrival a <= k (potentiation, time difference (k - a) dt), each arrival
+   at a with the target's latest spike k < a (depression, (a - k) dt).  With
+   W = w_max in the weight's fixed-point units and
+     F+(d) = round(lambda e^{-d dt / tau_plus} 2^32),
+     F-(d) = round(alpha lambda e^{-d dt / tau_minus} 2^32),
+   potentiation is w += floor(B+ F+ / 2^32), B+ = W (mu_plus = 0, additive)
+   or W - w (mu_plus = 1, multiplicative), then w = min(w, W); depression is
+   w -= floor(B- F- / 2^32), B- = W (mu_minus = 0) or w (mu_minus = 1), then
+   w = max(w, 0).  A spike of multiplicity m pairs m times.  Step n: the
+   input of step n + 1 is delivered with the weights as they are, then the
+   post spikes of step n potentiate, then the arrivals of step n + 1 depress
+   (and become the synapses' latest arrivals). */
+static int64_t stdp_fraction(double scale, double tau, double dt, uint64_t d) {
+  return llrint(ldexp(scale * exp(-((double)d * dt) / tau), 32));
+}
+
+static void stdp_step(orc_net* o, uint64_t n) {
+  for (uint64_t q = o->spk_at[n]; q < o->spk_at[n + 1]; ++q) {
+    uint32_t t = o->spk_gid[q], m = o->spk_mult[q];
+    for (uint64_t k = o->tptr[t]; k < o->tptr[t + 1]; ++k) {
+      uint64_t j = o->tidx[k];
+      if (o->last_pre[j] < 0) continue;
+      const orc_proj* pr = &o->proj[o->syn[j].plast];
+      int64_t F = stdp_fraction(pr->lambda, pr->tau_plus, o->dt, n - (uint64_t)o->last_pre[j]);
+      for (uint32_t c = 0; c < m; ++c) {
+        int64_t B = pr->mu_plus ? o->pwmax[j] - o->pw[j] : o->pwmax[j];
+        o->pw[j] += (B * F) >> 32;
+        if (o->pw[j] > o->pwmax[j]) o->pw[j] = o->pwmax[j];
+      }
+    }
+    o->last_post[t] = (int64_t)n;
+  }
+  for (uint64_t j = 0; j < o->n_syn; ++j) {
+    if (!o->arr_m[j]) continue;
+    const orc_proj* pr = &o->proj[o->syn[j].plast];
+    int64_t k = o->last_post[o->syn[j].tgt];
+    if (k >= 0) {
+      int64_t F = stdp_fraction(pr->alpha * pr->lambda, pr->tau_minus, o->dt, n + 1 - (uint64_t)k);
+      for (uint32_t c = 0; c < o->arr_m[j]; ++c) {
+        int64_t B = pr->mu_minus ? o->pw[j] : o->pwmax[j];
+        o->pw[j] -= (B * F) >> 32;
+        if (o->pw[j] < 0) o->pw[j] = 0;
+      }
+    }
+    o->last_pre[j] = (int64_t)(n + 1);
+    o->arr_m[j] = 0;
+  }
+}
+
 /* The neuron loop and the delivery loop carry OpenMP pragmas, which a plain
    build ignores: the neurons of a step are independent (their spikes are
    recorded afterwards, in gid order) and the delivered sums are integers
@@ -1332,12 +1444,15 @@ int orc_simulate(orc_net* o, uint64_t steps) {
         ev += e - b;
         for (uint64_t r = b; r < e; ++r) {
           const orc_syn* sy = &o->syn[r];
+          int64_t w = sy->plast >= 0 ? o->pw[r] : sy->wq;
 #pragma omp atomic
-          o->acc[(size_t)sy->tgt * P + sy->port] += m * sy->wq;
+          o->acc[(size_t)sy->tgt * P + sy->port] += m * w;
+          if (sy->plast >= 0) o->arr_m[r] = (uint32_t)m;  /* one source spike per step: one arrival */
         }
       }
     }
     o->n_events += ev;
+    if (o->n_plastic) stdp_step(o, n);
     o->step = n + 1;
   }
   return 0;
@@ -1366,7 +1481,7 @@ uint64_t orc_n_synapses(const orc_net* o) { return o->built ? o->n_syn : 0; }
 void orc_get_synapses(const orc_net* o, uint32_t* src, uint32_t* delay, uint32_t* tgt, uint32_t* port, int64_t* wq) {
   for (uint64_t e = 0; e < o->n_syn; ++e) {
     src[e] = o->syn[e].src; delay[e] = o->syn[e].d; tgt[e] = o->syn[e].tgt;
-    port[e] = o->syn[e].port; wq[e] = o->syn[e].wq;
+    port[e] = o->syn[e].port; wq[e] = o->syn[e].plast >= 0 ? o->pw[e] : o->syn[e].wq;
   }
 }
 

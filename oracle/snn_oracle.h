@@ -102,6 +102,16 @@ int      orc_weight_distribution(orc_net*, uint32_t proj, int kind, double a, do
 /* per-connection weights of a user-defined list projection (weights[j] for
    synapse j); at most ORC_WEIGHT_LEVELS_MAX distinct values */
 int      orc_list_weights(orc_net*, uint32_t proj, uint64_t n, const double* weights);
+/* Nearest-neighbour STDP (Sec. 2.1, after Morrison et al. 2008) on
+   projection `proj`: time constants tau_plus and tau_minus (ms), learning
+   rate lambda (0, 1], depression factor alpha (alpha lambda <= 1), weight
+   dependence mu_plus, mu_minus in {0 (additive), 1 (multiplicative)},
+   largest weight w_max > 0 (the weights start in [0, w_max]).  The rule and
+   its timing are stated at the top of the simulation loop in
+   snn_oracle.c.  orc_get_synapses reports a plastic synapse's current
+   weight. */
+int      orc_stdp(orc_net*, uint32_t proj, double tau_plus, double tau_minus, double lambda, double alpha, int mu_plus,
+                  int mu_minus, double w_max);
 int      orc_poisson(orc_net*, uint32_t tgt_first, uint32_t tgt_n, double rate_hz,
                      uint32_t n_inputs, double weight, uint32_t port);
 /* Devices (Sec. 2.1).  A spike generator emits, in the update of step n, as
