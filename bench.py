@@ -137,6 +137,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100_000)
     ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--settle", type=int, default=1000,
+                    help="untimed steps run right after the build, before the warm-up, so that the timed steps "
+                         "sample the network's steady state rather than its onset transient")
     ap.add_argument("--profile-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10_000)
@@ -263,6 +266,7 @@ def main():
     net = S.Net(spec, **kw)
     build_s = time.perf_counter() - t0
     mode = "binned" if net.counters()["delivery"] == 2 else "direct"
+    net.simulate(args.settle)  # onset transient of the initial state, untimed
     net.simulate(args.warmup)
     torch.cuda.synchronize()
     c0 = net.counters()
@@ -294,6 +298,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_steps": args.settle,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",

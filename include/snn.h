@@ -343,13 +343,18 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
 snn_status snn_build(snn_net* net);
 /* Advance by round(t_ms / dt) steps (resumable: later calls continue). */
 snn_status snn_simulate(snn_net* net, double t_ms);
-/* Advance by `steps` steps. */
+/* Advance by `steps` steps.  The steps run as captured loops of 100 steps
+   and of powers of two below it (so any count is a few graph launches); the
+   call returns when the device has finished them, with SNN_E_OVERFLOW if a
+   device range check failed.  The spikes of the last steps stay in the
+   device ring until snn_get_spikes (or a later call's drain) copies them. */
 snn_status snn_simulate_steps(snn_net* net, uint64_t steps);
 
 /* ---- readback ------------------------------------------------------------ */
 /* Spikes with step in [step_lo, step_hi), sorted by (step, gid).  A spike in
    step n is emitted at time (n+1) dt.  Writes min(count, cap) entries; *n_out
-   receives the total count (call with cap = 0 to size the buffers). */
+   receives the total count (call with cap = 0 to size the buffers).  Copies
+   the spikes still held on the device first (waits for it). */
 snn_status snn_get_spikes(snn_net* net, uint64_t step_lo, uint64_t step_hi, uint64_t* step, uint32_t* gid,
                           uint32_t* mult, size_t cap, size_t* n_out);
 /* Counters (see snn_counters). */

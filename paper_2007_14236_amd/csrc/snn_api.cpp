@@ -214,7 +214,10 @@ struct snn_net {
   uint64_t cur_step = 0, drained_step = 0;
   uint64_t log_cap = 0;
   uint64_t drain_steps = 0;
-  hipGraphExec_t graph_k = nullptr, graph_1 = nullptr;
+  // captured step loops: kGraphSteps steps and every power of two below it,
+  // so that any step count is a few graph launches
+  std::vector<std::pair<uint32_t, hipGraphExec_t>> graphs;  // descending length
+  Ctrl* pin_ctrl = nullptr;     // pinned copy of the device flags, read at the end of a call
   // raster drain, pipelined: the per-step counts and then the ring segment of
   // a window of steps are copied to pinned memory behind the graphs, each
   // collected one graph later, so the device never waits for the host
@@ -366,8 +369,12 @@ void lif_propagators(const HostPop& p, double dt, PopDev& d) {
       const double ts = p.tau_syn[q];
       if (ts > 0) {
         P11 = exp(-dt / ts);
-        if (ts == p.tau_m) P21 = dt / p.C_m * exp(-dt / p.tau_m);
-        else P21 = p.tau_m * ts / (p.C_m * (ts - p.tau_m)) * (exp(-dt / ts) - exp(-dt / p.tau_m));
+        // tau_m tau_s / (C (tau_s - tau_m)) (e^{-dt/tau_s} - e^{-dt/tau_m}), rewritten
+        // around e^{-dt/tau_m} so that close time constants do not cancel:
+        // (dt / C) e^{-dt/tau_m} (e^u - 1) / u with u = dt (1/tau_m - 1/tau_s)
+        const double u = dt * (ts - p.tau_m) / (p.tau_m * ts);
+        const double ratio = (u == 0.0) ? 1.0 : expm1(u) / u;
+        P21 = dt / p.C_m * exp(-dt / p.tau_m) * ratio;
       }
     }
     d.P11[q] = (float)P11;
@@ -488,12 +495,12 @@ snn_status snn_create_net(const snn_config* cfg, const snn_device* dev, snn_net*
 void snn_destroy_net(snn_net* net) {
   if (!net) return;
   if (net->stream) (void)hipStreamSynchronize(net->stream);
-  if (net->graph_k) (void)hipGraphExecDestroy(net->graph_k);
-  if (net->graph_1) (void)hipGraphExecDestroy(net->graph_1);
+  for (auto& gx : net->graphs) (void)hipGraphExecDestroy(gx.second);
   while (!net->allocs.empty()) dev_free(net, net->allocs.back().p);
   if (net->pinned) (void)hipHostFree(net->pinned);
   if (net->pin_cb) (void)hipHostFree(net->pin_cb);
   if (net->pin_rc) (void)hipHostFree(net->pin_rc);
+  if (net->pin_ctrl) (void)hipHostFree(net->pin_ctrl);
   if (net->ev_drain) (void)hipEventDestroy(net->ev_drain);
   if (net->ev_user) (void)hipEventDestroy(net->ev_user);
   if (net->stream) (void)hipStreamDestroy(net->stream);
@@ -1598,6 +1605,7 @@ snn_status snn_build(snn_net* net) {
   net->pinned_words = 0;
   HIPCHK(net, hipHostMalloc((void**)&net->pin_cb, kChunkRing * 8, hipHostMallocDefault));
   HIPCHK(net, hipHostMalloc((void**)&net->pin_rc, (size_t)nd.R * 4, hipHostMallocDefault));
+  HIPCHK(net, hipHostMalloc((void**)&net->pin_ctrl, sizeof(Ctrl), hipHostMallocDefault));
   HIPCHK(net, hipEventCreateWithFlags(&net->ev_drain, hipEventDisableTiming));
   net->dj = snn_net::Drain();
   if (net->nch) {  // multimeter channels: the address of each recorded value
@@ -1642,15 +1650,13 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
   uint64_t left = steps;
   while (left > 0) {
     const uint64_t from = net->cur_step;
-    if (left >= kGraphSteps) {
-      HIPCHK(net, hipGraphLaunch(net->graph_k, net->stream));
-      net->cur_step += kGraphSteps;
-      left -= kGraphSteps;
-    } else {
-      HIPCHK(net, hipGraphLaunch(net->graph_1, net->stream));
-      net->cur_step += 1;
-      left -= 1;
-    }
+    // the longest captured loop that fits: kGraphSteps, then the binary digits of the rest
+    size_t gi = 0;
+    while (net->graphs[gi].first > left) ++gi;
+    const uint32_t len = net->graphs[gi].first;
+    HIPCHK(net, hipGraphLaunch(net->graphs[gi].second, net->stream));
+    net->cur_step += len;
+    left -= len;
     if (net->nch) {  // the replay's samples, before the next one overwrites the device window
       st = collect_samples(net, from, net->cur_step);
       if (st) return st;
@@ -1666,13 +1672,14 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
       if (st) return st;
     }
   }
-  st = drain(net);
-  if (st) return st;
+  // One copy and one wait end the call: the device flags.  The raster of the
+  // last steps stays on the device (its ring holds them) until it is read or
+  // the next call's drain takes it.
+  HIPCHK(net, hipMemcpyAsync(net->pin_ctrl, net->nd.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, net->stream));
   HIPCHK(net, hipStreamSynchronize(net->stream));
   net->sim_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  Ctrl c;
-  HIPCHK(net, copy_sync(net, &c, net->nd.ctrl, sizeof c, hipMemcpyDeviceToHost));
-  if (c.overflow) return fail(net, SNN_E_OVERFLOW, "device range check failed (flags 0x%x)", c.overflow);
+  const uint32_t flags = net->pin_ctrl->overflow;
+  if (flags) return fail(net, SNN_E_OVERFLOW, "device range check failed (flags 0x%x)", flags);
   return leave(net);
 }
 
@@ -1716,6 +1723,12 @@ snn_status snn_get_spikes(snn_net* net, uint64_t step_lo, uint64_t step_hi, uint
                           uint32_t* mult, size_t cap, size_t* n_out) {
   if (!net || !n_out) return SNN_E_INVALID;
   net->err.clear();
+  if (net->built && step_hi > net->drained_step) {  // the steps still on the device first
+    snn_status st = enter(net);
+    if (st) return st;
+    if ((st = drain(net))) return st;
+    if ((st = leave(net))) return st;
+  }
   sort_raster(net);
   const auto lo = std::lower_bound(net->r_step.begin(), net->r_step.end(), step_lo);
   const auto hi = std::lower_bound(net->r_step.begin(), net->r_step.end(), step_hi);
@@ -1908,9 +1921,17 @@ snn_status collect_samples(snn_net* net, uint64_t from, uint64_t to) {
 }
 
 snn_status build_graphs(snn_net* net) {
-  snn_status st = record_graph(net, kGraphSteps, &net->graph_k);
-  if (st) return st;
-  return record_graph(net, 1, &net->graph_1);
+  uint32_t lens[16], n = 0;
+  lens[n++] = kGraphSteps;
+  for (uint32_t len = 1u << 6; len >= 1; len >>= 1)
+    if (len < kGraphSteps) lens[n++] = len;
+  for (uint32_t i = 0; i < n; ++i) {
+    hipGraphExec_t gx = nullptr;
+    snn_status st = record_graph(net, lens[i], &gx);
+    if (st) return st;
+    net->graphs.push_back({lens[i], gx});
+  }
+  return SNN_OK;
 }
 
 // Order the entries drained since the last read by gid within each step
