@@ -363,6 +363,15 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out);
    on `port` (network synapses only, Poisson excluded), in units of
    2^-shift(gid, port) of the weight unit. */
 snn_status snn_get_input(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int64_t* out);
+/* snn_get_input without any allocation, for callers that cannot allocate
+   device memory (code under stream capture, tight serving loops, harnesses
+   that forbid it).  Same arguments and result as snn_get_input; n is at most
+   262,144 (SNN_E_INVALID above).  Binned delivery stages the sum in a fixed
+   2 MiB device workspace of the library (one per GPU, held until the process
+   ends, its address resolved when the first network on that GPU is created);
+   calls that overlap on one GPU, from any threads or networks, race for it.
+   Calls no allocator, neither the caller's nor the runtime's. */
+snn_status snn_get_input_noalloc(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int64_t* out);
 /* Fixed-point exponent S of (gid, port): weights are stored as llrint(w 2^S). */
 snn_status snn_get_shift(snn_net* net, uint32_t gid, uint32_t port, int32_t* shift);
 /* Poisson counts the device draws for gids [first, first+n) at `step`

@@ -53,6 +53,11 @@ hipError_t launch_pending_input(const NetDev& nd, uint32_t buf, uint32_t first, 
 // channels into buf[(step % window) * nch + c].
 hipError_t launch_sample(const float* const* addr, uint32_t nch, float* buf, uint32_t window, const Ctrl* ctrl,
                          uint32_t rel, hipStream_t s);
+// Device address of this library's fixed readback workspace on `device`
+// (kNoAllocInputMax int64 values, one copy per GPU, held until the process
+// ends).  Resolved once per device; call with that device current first
+// (resolve = true), later calls only look it up.  Null if never resolved.
+hipError_t input_workspace(int device, bool resolve, int64_t** out);
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,
                                  hipStream_t s);
 

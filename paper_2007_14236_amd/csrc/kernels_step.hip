@@ -24,6 +24,8 @@
 //     before updating the tile's neurons.
 #include <hip/hip_ext.h>
 
+#include <mutex>
+
 #include "kernels.h"
 #include "philox_dev.h"
 
@@ -1318,6 +1320,31 @@ hipError_t launch_pending_input(const NetDev& nd, uint32_t buf, uint32_t first, 
   const uint32_t t0 = first >> nd.tile_shift, t1 = (first + n - 1) >> nd.tile_shift;
   hipLaunchKernelGGL(k_pending_input, dim3(t1 - t0 + 1), dim3(kB), 0, s, nd, buf, first, n, port, out);
   return hipGetLastError();
+}
+
+// Workspace of the allocation-free input readback: a file-scope device array.
+// Host code must not pass its name to a kernel or a copy (on the host the name
+// is only a stand-in); the device address comes from hipGetSymbolAddress, once
+// per device with that device current, and is kept per device.
+static __device__ __align__(256) int64_t scratch[kNoAllocInputMax];
+
+namespace {
+std::mutex g_ws_mu;
+int64_t* g_ws_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t input_workspace(int device, bool resolve, int64_t** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  if (!g_ws_ptr[device] && resolve) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_ws_ptr[device] = static_cast<int64_t*>(p);
+  }
+  *out = g_ws_ptr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,

@@ -170,6 +170,7 @@ struct snn_net {
   snn_device dev{};
   bool have_dev = false;
   hipStream_t stream = nullptr;
+  int device = 0;  // the device current at creation: the stream's and every allocation's
   hipEvent_t ev_user = nullptr;
   std::string err;
   bool built = false;
@@ -482,6 +483,14 @@ snn_status snn_create_net(const snn_config* cfg, const snn_device* dev, snn_net*
       delete net;
       return SNN_E_INVALID;
     }
+  }
+  if (hipGetDevice(&net->device) != hipSuccess) {
+    delete net;
+    return SNN_E_DEVICE;
+  }
+  {  // set-up of the allocation-free readback: its workspace address on this device, once
+    int64_t* ws = nullptr;
+    (void)input_workspace(net->device, true, &ws);  // a failure is reported by that entry point
   }
   if (hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&net->ev_user, hipEventDisableTiming) != hipSuccess) {
@@ -1810,6 +1819,33 @@ snn_status snn_get_input(snn_net* net, uint32_t first, uint32_t n, uint32_t port
   if (e == hipSuccess) e = copy_sync(net, out, d, (size_t)n * 8, hipMemcpyDeviceToHost);
   dev_free(net, d);
   if (e != hipSuccess) return fail(net, SNN_E_DEVICE, "input readback: %s", hipGetErrorString(e));
+  return leave(net);
+}
+
+snn_status snn_get_input_noalloc(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int64_t* out) {
+  if (!net || !out) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "not built");
+  if ((uint64_t)first + n > net->N || port >= net->P) return fail(net, SNN_E_INVALID, "bad range");
+  if (n > kNoAllocInputMax)
+    return fail(net, SNN_E_INVALID, "%u neurons: at most %u per call of the allocation-free readback", n,
+                kNoAllocInputMax);
+  int64_t* ws = nullptr;  // the device address of the workspace, resolved when the network was created
+  HIPCHK(net, input_workspace(net->device, false, &ws));
+  if (!ws) return fail(net, SNN_E_DEVICE, "readback workspace not available on device %d", net->device);
+  snn_status st = enter(net);
+  if (st) return st;
+  if (n == 0) return leave(net);
+  const uint32_t buf = (uint32_t)(net->cur_step % kInBuf);
+  const int64_t* src = net->nd.acc + (size_t)buf * net->N * net->P + (size_t)first * net->P + port;
+  if (!net->nd.n_tiles) {  // direct delivery: the accumulators hold the whole input
+    HIPCHK(net, copy2d_sync(net, out, 8, src, net->P * 8, 8, n, hipMemcpyDeviceToHost));
+    return leave(net);
+  }
+  // binned: the spilled part overwrites ws[0, n), then the bin entries are added
+  HIPCHK(net, hipMemcpy2DAsync(ws, 8, src, net->P * 8, 8, n, hipMemcpyDeviceToDevice, net->stream));
+  HIPCHK(net, launch_pending_input(net->nd, buf, first, n, port, ws, net->stream));
+  HIPCHK(net, copy_sync(net, out, ws, (size_t)n * 8, hipMemcpyDeviceToHost));
   return leave(net);
 }
 

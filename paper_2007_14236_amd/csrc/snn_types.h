@@ -47,6 +47,8 @@ constexpr int kTileAccWords = 4096; // int64 LDS accumulators of a tile block (t
 constexpr uint32_t kMaxTiles = 1024; // tiles of the binned delivery
 constexpr int kBinLocalShift = 15;   // bin entry: local target << 15 | mult << 10 | class
 constexpr int kBinMultShift = 10;
+constexpr uint32_t kNoAllocInputMax = 1u << 18;  // neurons per call of the allocation-free input readback
+constexpr int kMaxDevices = 64;
 constexpr int kTagConn = 1;
 constexpr int kTagPoisson = 2;
 

@@ -105,6 +105,7 @@ _SIGS = {
                                    C.POINTER(C.c_uint32), C.c_size_t, C.POINTER(C.c_size_t)]),
     "snn_get_counters": (C.c_int32, [_P, C.POINTER(Counters)]),
     "snn_get_input": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64)]),
+    "snn_get_input_noalloc": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_int64)]),
     "snn_get_shift": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32)]),
     "snn_poisson_counts": (C.c_int32, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
     "snn_profile_steps": (C.c_int32, [_P, C.c_uint64, C.POINTER(C.c_double)]),
@@ -378,6 +379,12 @@ class Net:
         n = self.N - first if n is None else n
         out = np.zeros(n, dtype=np.int64)
         self._check(self.L.snn_get_input(self.h, first, n, port, _ptr(out, C.c_int64)))
+        return out
+
+    def get_input_noalloc(self, port: int = 0, first: int = 0, n: int | None = None) -> np.ndarray:
+        n = self.N - first if n is None else n
+        out = np.zeros(n, dtype=np.int64)
+        self._check(self.L.snn_get_input_noalloc(self.h, first, n, port, _ptr(out, C.c_int64)))
         return out
 
     def shift(self, gid: int, port: int = 0) -> int:
