@@ -50,6 +50,7 @@ typedef int32_t snn_status;
 #define SNN_E_STATE (-3)       /* call not allowed in the current phase         */
 #define SNN_E_OVERFLOW (-4)    /* a device-side capacity or range was exceeded  */
 #define SNN_E_DEVICE (-5)      /* HIP runtime error                             */
+#define SNN_E_BUDGET (-6)      /* request larger than the server's memory budget */
 #define SNN_E_UNSUPPORTED (-7) /* valid request outside what is implemented     */
 
 typedef struct snn_net snn_net;
@@ -110,7 +111,7 @@ typedef struct snn_config {
 #define SNN_SPIKE_GENERATOR 4
 #define SNN_PARROT_NEURON 5
 
-/* model parameters (snn_set_param); all apply to whole populations */
+/* model parameters (snn_set_param): per population, or per neuron */
 #define SNN_P_TAU_M 0    /* LIF membrane time constant (ms)                   */
 #define SNN_P_C_M 1      /* membrane capacitance (pF)                         */
 #define SNN_P_E_L 2      /* leak reversal / resting potential (mV)            */
@@ -191,9 +192,27 @@ snn_status snn_begin_instance(snn_net* net, uint64_t seed, uint32_t* instance_id
 /* Create n neurons of `model` with n_ports receptor ports (1..4; LIF delta: 1)
    and NEST-like default parameters.  *first_gid receives the first gid. */
 snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports, uint32_t* first_gid);
-/* Set model parameter `param` (SNN_P_*) of the populations that make up the
-   gid range [first, first+n), which must be a union of whole populations. */
-snn_status snn_set_param(snn_net* net, uint32_t first, uint32_t n, int32_t param, double value);
+/* Set model parameter `param` (SNN_P_*) of gids [first, first+n) (Sec. 2.1:
+   neuron parameters from fixed values or arrays), before snn_build.  nv == 1
+   broadcasts v[0]: over a range made of whole populations it sets their
+   constant, otherwise it sets the value of each neuron of the range; nv == n
+   gives each neuron its own value v[j].  A later call on the same neurons
+   wins.  A neuron whose parameters differ from its population's is updated
+   with its own constants (LIF: tau_m, C_m, E_L, V_th, V_reset, t_ref; AdEx:
+   all but the port constants), computed on the host exactly as a
+   population's are; a neuron whose V_m was never set starts at its own E_L.
+   SNN_E_INVALID for an unknown parameter, a bad range, nv not 1 or n, or a
+   value that is not finite; invalid values (tau_m <= 0, ...) are reported by
+   snn_build. */
+snn_status snn_set_param(snn_net* net, uint32_t first, uint32_t n, int32_t param, const double* v, size_t nv);
+/* Model parameter `param` of gids [first, first+n) drawn per neuron (Sec.
+   2.1: neuron parameters from probability distributions), before snn_build:
+   kind, a, b, lo, hi and levels as for snn_state_distribution; neuron i takes
+   the level of the top 32 bits of word 0 of Philox block (i, param << 8,
+   tag 5) with its instance's key (seed, 0), i counted from the instance's
+   first neuron, then is set as by snn_set_param with one value per neuron. */
+snn_status snn_param_distribution(snn_net* net, uint32_t first, uint32_t n, int32_t param, int32_t kind, double a,
+                                  double b, double lo, double hi, uint32_t levels);
 /* Set port parameter `param` (SNN_PP_*) of receptor `port`, same range rule. */
 snn_status snn_set_port_param(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int32_t param,
                               double value);
@@ -262,6 +281,28 @@ snn_status snn_connect(snn_net* net, int32_t rule, uint64_t n, uint32_t src_firs
 #define SNN_WEIGHT_NORMAL 1
 snn_status snn_weight_distribution(snn_net* net, int32_t kind, double a, double b, double lo, double hi,
                                    uint32_t levels);
+/* Nearest-neighbour STDP (Sec. 2.1 lists it; after Morrison et al. 2008) on
+   the projection created last, before snn_build.  A synapse's spikes are its
+   pre arrivals (step a: the update of step a receives the spike) and its
+   target's spikes (step k); in one step the arrival comes first.  Each post
+   spike at k pairs with the synapse's latest arrival a <= k and potentiates,
+   each arrival at a pairs with the target's latest spike k < a and
+   depresses, with the power-law rule in the weight's fixed point (W =
+   llrint(w_max 2^S), S the exponent of the synapse's (target population,
+   port), which also covers w_max):
+     F+(d) = llrint(lambda e^{-d dt / tau_plus} 2^32),
+     F-(d) = llrint(alpha lambda e^{-d dt / tau_minus} 2^32),
+     potentiation  w += (B+ F+(k - a)) >> 32, B+ = W - w (mu_plus 1) or W, then min(w, W);
+     depression    w -= (B- F-(a - k)) >> 32, B- = w (mu_minus 1) or W, then max(w, 0);
+   once per unit of multiplicity.  In step n the input of step n + 1 is
+   delivered with the weights as they are, then the post spikes of step n
+   potentiate, then the arrivals of step n + 1 depress.  SNN_E_STATE after
+   build or with no projection; SNN_E_INVALID for tau <= 0, lambda outside
+   (0, 1], alpha < 0 or alpha lambda > 1, w_max <= 0, mu not 0 or 1, or
+   weights outside [0, w_max]; at build SNN_E_UNSUPPORTED for more than 255
+   plastic (projection, target population) pairs. */
+snn_status snn_stdp(snn_net* net, double tau_plus, double tau_minus, double lambda, double alpha, int32_t mu_plus,
+                    int32_t mu_minus, double w_max);
 /* Per-connection weights (Sec. 2.1, weights "through arrays") of the list
    projection created last by snn_connect_list: weights[j] for its synapse j
    (host array of n doubles, copied; n must equal the list's length; n == 0
@@ -341,6 +382,14 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
    distinct (port, weight) classes than fit next to the target index in 32
    bits (at most 1024). */
 snn_status snn_build(snn_net* net);
+/* Return the device memory of a built network while keeping its results:
+   the spikes still on the device are copied to the host raster and the
+   counters are recorded, then every device allocation is freed.  Afterwards
+   snn_get_spikes and snn_get_counters answer from the host copies
+   (device_bytes 0) and every call that needs the device returns SNN_E_STATE;
+   the network is not built again.  Used by the server to free a finished
+   request's memory at once. */
+snn_status snn_release(snn_net* net);
 /* Advance by round(t_ms / dt) steps (resumable: later calls continue). */
 snn_status snn_simulate(snn_net* net, double t_ms);
 /* Advance by `steps` steps.  The steps run as captured loops of 100 steps
@@ -388,6 +437,70 @@ snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms);
    (arrays untouched when too small). */
 snn_status snn_export_synapses(snn_net* net, uint32_t* src, uint32_t* delay, uint32_t* tgt, uint32_t* port,
                                int64_t* wq, size_t* n_syn);
+/* Current fixed-point weight of every synapse in the same canonical order
+   (plastic synapses: as STDP has left them; static: their class weight);
+   *n_syn as for snn_export_synapses. */
+snn_status snn_get_weights(snn_net* net, int64_t* wq, size_t* n_syn);
+
+/* ---- serving ------------------------------------------------------------ */
+/* A request server on the current device: requests (a defined, not yet built
+   network and a step count) wait in one queue in submission order; `slots`
+   worker threads each take the first queued request whose known memory need
+   fits what is left of `hbm_budget` bytes, build it, simulate it on the
+   network's own stream and release its device memory as soon as it is done
+   (snn_release), so requests submitted while others run are admitted as
+   slots and memory free up and their work overlaps on the device.  Every
+   device allocation of a served network passes through the server, which
+   refuses one that would exceed the budget: the build fails and releases
+   what it had allocated, and the request goes back to the head of the queue
+   with that amount as its known need.  A request whose known need exceeds
+   the budget, or that cannot fit with nothing else on the device, fails
+   with SNN_E_BUDGET.  A network is
+   advanced by exactly the kernels it would run alone, so its raster does
+   not depend on what it was served with.  slots 1..64. */
+typedef struct snn_server snn_server;
+#define SNN_JOB_QUEUED 0
+#define SNN_JOB_RUNNING 1
+#define SNN_JOB_DONE 2
+#define SNN_JOB_FAILED 3
+typedef struct snn_job_info {
+  snn_status status;         /* SNN_OK, or why the request failed              */
+  uint32_t attempts;         /* builds tried (more than 1 after budget refusals) */
+  double t_submit, t_start, t_done; /* CLOCK_MONOTONIC seconds: submitted, first
+                                       taken by a slot, finished               */
+  uint64_t device_bytes_peak; /* most device memory the request held          */
+  char error[200];           /* message of a failure                          */
+} snn_job_info;
+typedef struct snn_server_stats {
+  uint64_t budget, in_use, peak; /* device bytes: the budget, granted now, at most */
+  uint32_t queued, running;
+  uint64_t done, failed;
+} snn_server_stats;
+snn_status snn_server_create(size_t hbm_budget, uint32_t slots, snn_server** out);
+/* Stops the workers after their current request (which finishes and is
+   released); queued requests are dropped.  Networks whose results were not
+   taken go back to the caller as they are (released, or never built), with
+   their own allocators: the caller destroys them. */
+void snn_server_destroy(snn_server* srv);
+/* Queue `net` (defined with snn_create / snn_connect / ..., not built) to be
+   built and advanced by `steps` steps.  The server owns the handle until
+   snn_server_result returns it: the caller must not use it meanwhile.
+   *ticket identifies the request.  SNN_E_STATE if the network is built,
+   released or empty; SNN_E_BUDGET if its synapse words alone (4 bytes each)
+   exceed the budget. */
+snn_status snn_server_submit(snn_server* srv, snn_net* net, uint64_t steps, uint64_t* ticket);
+/* *state = SNN_JOB_QUEUED, _RUNNING, _DONE or _FAILED.  SNN_E_INVALID for an
+   unknown ticket (or one whose result was taken). */
+snn_status snn_server_poll(snn_server* srv, uint64_t ticket, int32_t* state);
+/* Wait until the request is done or failed (timeout_s < 0: no limit);
+   SNN_E_STATE if the time ran out first. */
+snn_status snn_server_wait(snn_server* srv, uint64_t ticket, double timeout_s);
+/* Hand a finished request's network back (*net; its device memory is already
+   released: snn_get_spikes and snn_get_counters read the results; destroy it
+   with snn_destroy_net) and fill *info (may be NULL).  Returns the request's
+   status; SNN_E_STATE while it is queued or running. */
+snn_status snn_server_result(snn_server* srv, uint64_t ticket, snn_net** net, snn_job_info* info);
+snn_status snn_server_get_stats(snn_server* srv, snn_server_stats* out);
 
 #ifdef __cplusplus
 }

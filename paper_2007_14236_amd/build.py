@@ -12,7 +12,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsnn.so")
-SOURCES = ["kernels_build.hip", "kernels_step.hip", "kernels_rec.hip", "snn_api.cpp"]
+SOURCES = ["kernels_build.hip", "kernels_step.hip", "kernels_rec.hip", "kernels_stdp.hip", "snn_api.cpp", "snn_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SNN_OFFLOAD_ARCH", "gfx950")
 

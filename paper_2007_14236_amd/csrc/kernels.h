@@ -58,6 +58,15 @@ hipError_t launch_sample(const float* const* addr, uint32_t nch, float* buf, uin
 // ends).  Resolved once per device; call with that device current first
 // (resolve = true), later calls only look it up.  Null if never resolved.
 hipError_t input_workspace(int device, bool resolve, int64_t** out);
+// ---- nearest-neighbour STDP ----
+// Plasticity of step ctrl->step_base + rel (after that step's kernel); no-op
+// without plastic synapses.
+hipError_t launch_stdp(const NetDev& nd, uint32_t rel, hipStream_t s);
+// Set-up: pw[j] = the class weight and cleared arrivals for every synapse;
+// cnt[t] += the plastic synapses onto t (cnt zeroed by the caller).
+hipError_t launch_stdp_count(const NetDev& nd, uint32_t* cnt, hipStream_t s);
+// tidx[cursor[t]++] = j for every plastic synapse j onto t (cursor = tptr copy).
+hipError_t launch_stdp_scatter(const NetDev& nd, uint64_t* cursor, uint64_t* tidx, hipStream_t s);
 hipError_t launch_poisson_counts(const NetDev& nd, uint64_t step, uint32_t first, uint32_t n, uint32_t* k,
                                  hipStream_t s);
 

@@ -110,32 +110,56 @@ __device__ __forceinline__ uint32_t poisson_draw(const uint64_t* thr, uint64_t s
 }
 
 // ------------------------------------------------------------------ update
+// Constants of a LIF neuron's exact propagation: its population's, or its
+// own when the population's parameters are set per neuron (the synaptic
+// decay P11 is always the population's).
+struct LifK {
+  float P22, P20, theta, y_reset;
+  float P21[kMaxPorts];
+  int32_t n_ref;
+};
+
+__device__ __forceinline__ LifK lif_consts(const NetDev& nd, const PopDev& pp, uint32_t i) {
+  LifK k;
+  if (pp.per_neuron) {
+    const NeuronLif& c = nd.nlif[i];
+    k.P22 = c.P22; k.P20 = c.P20; k.theta = c.theta; k.y_reset = c.y_reset; k.n_ref = c.n_ref;
+#pragma unroll
+    for (int p = 0; p < kMaxPorts; ++p) k.P21[p] = c.P21[p];
+  } else {
+    k.P22 = pp.P22; k.P20 = pp.P20; k.theta = pp.theta; k.y_reset = pp.y_reset; k.n_ref = pp.n_ref;
+#pragma unroll
+    for (int p = 0; p < kMaxPorts; ++p) k.P21[p] = pp.P21[p];
+  }
+  return k;
+}
+
 // LIF exact integration (Sec. 2.1; LIF and exponential-PSC equations of
 // Sec. 2.3), y = V - E_L, fixed fp32 operation order without contraction.
-__device__ __forceinline__ bool lif_delta_step(const PopDev& pp, float& y, int32_t& r, float Ie, float x) {
+__device__ __forceinline__ bool lif_delta_step(const LifK& k, float& y, int32_t& r, float Ie, float x) {
   if (r > 0) {
     r -= 1;  // refractory: held at reset, input discarded
   } else {
-    const float t1 = __fmul_rn(pp.P22, y);
-    const float t2 = __fmul_rn(pp.P20, Ie);
+    const float t1 = __fmul_rn(k.P22, y);
+    const float t2 = __fmul_rn(k.P20, Ie);
     y = __fadd_rn(__fadd_rn(t1, t2), x);
   }
-  if (r == 0 && y >= pp.theta) { y = pp.y_reset; r = pp.n_ref; return true; }
+  if (r == 0 && y >= k.theta) { y = k.y_reset; r = k.n_ref; return true; }
   return false;
 }
 
-__device__ __forceinline__ bool lif_exp_step(const PopDev& pp, float& y, float* I, int32_t& r, float Ie,
-                                             const float* x) {
+__device__ __forceinline__ bool lif_exp_step(const PopDev& pp, const LifK& k, float& y, float* I, int32_t& r,
+                                             float Ie, const float* x) {
   if (r == 0) {
-    float v = __fmul_rn(pp.P22, y);
-    for (int p = 0; p < pp.n_ports; ++p) v = __fadd_rn(v, __fmul_rn(pp.P21[p], I[p]));
-    v = __fadd_rn(v, __fmul_rn(pp.P20, Ie));
+    float v = __fmul_rn(k.P22, y);
+    for (int p = 0; p < pp.n_ports; ++p) v = __fadd_rn(v, __fmul_rn(k.P21[p], I[p]));
+    v = __fadd_rn(v, __fmul_rn(k.P20, Ie));
     y = v;
   } else {
     r -= 1;
   }
   for (int p = 0; p < pp.n_ports; ++p) I[p] = __fadd_rn(__fmul_rn(pp.P11[p], I[p]), x[p]);
-  if (r == 0 && y >= pp.theta) { y = pp.y_reset; r = pp.n_ref; return true; }
+  if (r == 0 && y >= k.theta) { y = k.y_reset; r = k.n_ref; return true; }
   return false;
 }
 
@@ -155,18 +179,27 @@ struct AdexPar {
 template <int P, bool kBeta>
 constexpr int kAdexVars = kBeta ? 2 + 2 * P : 2 + P;
 
-template <int P, bool kBeta>
-__device__ __forceinline__ AdexPar<P, kBeta> adex_par(const PopDev& pp) {
-  AdexPar<P, kBeta> q;
-  q.V_peak = pp.V_peak; q.g_L = pp.g_L; q.V_T = pp.V_T;
-  q.gLDT = pp.g_L * pp.Delta_T;
-  q.k_exp = pp.inv_Delta_T * 1.4426950408889634f;  // exp(x / Delta_T) = 2^(x k_exp)
-  q.E_L = pp.E_L; q.inv_C = pp.inv_C; q.a = pp.a; q.inv_tau_w = pp.inv_tau_w; q.b = pp.b; q.V_r = pp.V_r;
-  q.dt = pp.dt;
+// The neuron constants of AdexPar from a population record or from a
+// neuron's own record (both carry the same fields).
+template <int P, bool kBeta, class Src>
+__device__ __forceinline__ void adex_scalars(AdexPar<P, kBeta>& q, const Src& c, float dt) {
+  q.V_peak = c.V_peak; q.g_L = c.g_L; q.V_T = c.V_T;
+  q.gLDT = c.g_L * c.Delta_T;
+  q.k_exp = c.inv_Delta_T * 1.4426950408889634f;  // exp(x / Delta_T) = 2^(x k_exp)
+  q.E_L = c.E_L; q.inv_C = c.inv_C; q.a = c.a; q.inv_tau_w = c.inv_tau_w; q.b = c.b; q.V_r = c.V_r;
   // smallest substep: the configured floor, but never below 2^-22 dt so that
   // t + h still advances in fp32
-  q.hmin = fmaxf(pp.rk_hmin, pp.dt * 2.384185791015625e-7f);
-  q.inv_eps = 1.f / pp.rk_eps;
+  q.hmin = fmaxf(c.rk_hmin, dt * 2.384185791015625e-7f);
+  q.inv_eps = 1.f / c.rk_eps;
+}
+
+// AdexPar of neuron i of population pp.
+template <int P, bool kBeta>
+__device__ __forceinline__ AdexPar<P, kBeta> adex_par(const NetDev& nd, const PopDev& pp, uint32_t i) {
+  AdexPar<P, kBeta> q;
+  q.dt = pp.dt;
+  if (pp.per_neuron) adex_scalars<P, kBeta>(q, nd.nadex[i], pp.dt);
+  else adex_scalars<P, kBeta>(q, pp, pp.dt);
 #pragma unroll
   for (int p = 0; p < P; ++p) { q.E_rev[p] = pp.E_rev[p]; q.inv_tau_syn[p] = pp.inv_tau_syn[p]; }
   if constexpr (kBeta) {
@@ -296,9 +329,8 @@ __device__ __forceinline__ bool adex_substep(const AdexPar<P, kBeta>& pp, float*
 // One dt of the AdEx model: substeps until the step end, h carried to the
 // next step (at most dt).  Returns the number of resets.
 template <int P, bool kBeta>
-__device__ uint32_t adex_step(const PopDev& pop, float* y, float& h, float Ie, uint32_t& nacc, uint32_t& nrej,
-                              bool& capped) {
-  const AdexPar<P, kBeta> pp = adex_par<P, kBeta>(pop);
+__device__ uint32_t adex_step(const AdexPar<P, kBeta>& pp, float* y, float& h, float Ie, uint32_t& nacc,
+                              uint32_t& nrej, bool& capped) {
   const float dt = pp.dt;
   if (!(h > 0.f) || h > dt) h = dt;
   float t = 0.f;
@@ -493,6 +525,18 @@ __device__ __forceinline__ uint32_t sel_advance(const SelLds& sh, uint32_t np, u
 
 constexpr int kUnroll = 4;  // events per lane and round of a flat scan
 
+// A spike of multiplicity mult reaching plastic synapse j (CSR position) at
+// the step whose input buffer is buf (the arrival step's parity): its weight
+// as it is now, times mult, is the input; the arrival is recorded for the
+// plasticity kernel of this step (a synapse receives at most one spike per
+// step, so the list never holds more than the plastic synapses).
+__device__ __forceinline__ int64_t plastic_arrival(const NetDev& nd, uint64_t j, uint32_t mult, uint32_t buf) {
+  nd.arr_m[j] = (uint8_t)mult;
+  const uint32_t k = __hip_atomic_fetch_add(&nd.arr_cnt[buf], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  nd.arr_list[(size_t)buf * nd.n_plastic + k] = j;
+  return (int64_t)nd.pw[j] * (int64_t)mult;
+}
+
 // Events e0, e0 + kB, ... (kUnroll of them, those below ev) of a lane: their
 // records r[] and synapse words pl[], all loads issued before any is used.
 __device__ __forceinline__ void sel_gather(const NetDev& nd, const SelLds& sh, uint32_t np, uint64_t ev,
@@ -521,16 +565,22 @@ __device__ uint64_t dlv_flush(const NetDev& nd, DirectLds& sh, uint32_t /*buf: p
   const uint64_t ev = sel_scan(sh);
   const size_t bstride = (size_t)nd.N * nd.P;
   const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u, P = nd.P;
+  const bool plastic = nd.n_rules != 0;
   uint32_t lo = 0;
   for (uint64_t e0 = threadIdx.x; e0 < ev; e0 += kUnroll * kB) {  // independent events per lane and round
     uint32_t r[kUnroll], pl[kUnroll];
     sel_gather(nd, sh, np, ev, e0, lo, r, pl);
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
-      if (e0 + (uint64_t)q * kB >= ev) break;
+      const uint64_t e = e0 + (uint64_t)q * kB;
+      if (e >= ev) break;
       const uint32_t cls = pl[q] & cls_mask;
       const bool in_lds = cls < kClsLds;
-      const int64_t v = (in_lds ? sh.wq[cls] : nd.cls_wq[cls]) * (int64_t)sh.p_mult[r[q]];
+      int64_t v;
+      if (plastic && nd.cls_rule[cls])
+        v = plastic_arrival(nd, sh.p_off[r[q]] + (e - sh.p_st[r[q]]), sh.p_mult[r[q]], sh.p_buf[r[q]]);
+      else
+        v = (in_lds ? sh.wq[cls] : nd.cls_wq[cls]) * (int64_t)sh.p_mult[r[q]];
       const uint32_t port = in_lds ? sh.wp[cls] : nd.cls_port[cls];
       int64_t* acc = nd.acc + bstride * sh.p_buf[r[q]];
       __hip_atomic_fetch_add((unsigned long long*)&acc[(size_t)(pl[q] >> cls_bits) * P + port],
@@ -556,6 +606,17 @@ __device__ __forceinline__ void bin_spill(const NetDev& nd, uint32_t buf, uint32
                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A plastic synapse's event in binned delivery: its weight is read now (the
+// plasticity kernel changes it before the tile sums its bin), so the event
+// goes to the tile's spill accumulator, like an event that found its bin full.
+__device__ __forceinline__ void bin_plastic(const NetDev& nd, uint32_t buf, uint64_t j, uint32_t tgt, uint32_t cls,
+                                            uint32_t mult, uint32_t tile) {
+  const int64_t v = plastic_arrival(nd, j, mult, buf);
+  __hip_atomic_fetch_add((unsigned long long*)&nd.acc[((size_t)buf * nd.N + tgt) * nd.P + nd.cls_port[cls]],
+                         (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  nd.ovf_flag[(size_t)buf * nd.n_tiles + tile] = 1u;
+}
+
 // Binned delivery of the chunk: the same flat scan, but each event becomes
 // one 32-bit entry (local target, multiplicity, weight class) in the bin of
 // its target tile in input buffer buf; the tile block of that step
@@ -571,6 +632,7 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
   // below 32 (their sum can exceed 31 when a tile is wider than the gid range)
   const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u;
   const uint32_t tsh = nd.tile_shift, lmask = (1u << tsh) - 1u, ntl = nd.n_tiles;
+  const bool plastic = nd.n_rules != 0;
   bool bad = false;
   uint32_t lo = 0;
   for (uint64_t e0 = threadIdx.x; e0 < ev; e0 += kUnroll * kB) {  // independent events per lane and round
@@ -580,8 +642,8 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
     for (int q = 0; q < kUnroll; ++q) {
       if (e0 + (uint64_t)q * kB >= ev) break;
       const uint32_t t = (pl[q] >> cls_bits) >> tsh;
-      if (t < ntl) atomicAdd(&sh.tcnt[t], 1u);
-      else bad = true;
+      if (t >= ntl) bad = true;
+      else if (!(plastic && nd.cls_rule[pl[q] & cls_mask])) atomicAdd(&sh.tcnt[t], 1u);  // plastic: no bin entry
     }
   }
   __syncthreads();
@@ -604,9 +666,14 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
     sel_gather(nd, sh, np, ev, e0, lo, r, pl);
 #pragma unroll
     for (int q = 0; q < kUnroll; ++q) {
-      if (e0 + (uint64_t)q * kB >= ev) break;
+      const uint64_t e = e0 + (uint64_t)q * kB;
+      if (e >= ev) break;
       const uint32_t tgt = pl[q] >> cls_bits, t = tgt >> tsh;
       if (t >= ntl) continue;
+      if (plastic && nd.cls_rule[pl[q] & cls_mask]) {
+        bin_plastic(nd, buf, sh.p_off[r[q]] + (e - sh.p_st[r[q]]), tgt, pl[q] & cls_mask, sh.p_mult[r[q]], t);
+        continue;
+      }
       const uint32_t slot = atomicAdd(&sh.tcnt[t], 1u);
       const uint32_t cls = pl[q] & cls_mask, mult = sh.p_mult[r[q]];
       if (slot < sh.tavail[t])
@@ -693,13 +760,14 @@ __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* 
     float y = nd.V[i];
     int32_t r = nd.refr[i];
     bool s;
+    const LifK k = lif_consts(nd, pp, i);
     if (pp.model == kLifDelta) {
-      s = lif_delta_step(pp, y, r, Ie, x[0]);
+      s = lif_delta_step(k, y, r, Ie, x[0]);
     } else {
       float I[kMaxPorts];
 #pragma unroll
       for (int p = 0; p < kMaxPorts; ++p) I[p] = (p < pp.n_ports) ? nd.Isyn[(size_t)i * nd.P + p] : 0.f;
-      s = lif_exp_step(pp, y, I, r, Ie, x);
+      s = lif_exp_step(pp, k, y, I, r, Ie, x);
 #pragma unroll
       for (int p = 0; p < kMaxPorts; ++p)
         if (p < pp.n_ports) nd.Isyn[(size_t)i * nd.P + p] = I[p];
@@ -716,7 +784,7 @@ __device__ __forceinline__ uint32_t neuron_step(const NetDev& nd, const PopDev* 
       y[1] = nd.w[i];
       adex_load_syn<P, kBeta>(nd, pp, i, x, y);
       float h = nd.h[i];
-      m = adex_step<P, kBeta>(pp, y, h, Ie, nacc, nrej, capped);
+      m = adex_step<P, kBeta>(adex_par<P, kBeta>(nd, pp, i), y, h, Ie, nacc, nrej, capped);
       nd.V[i] = y[0];
       nd.w[i] = y[1];
       adex_store_syn<P, kBeta>(nd, i, y);
@@ -795,6 +863,9 @@ __device__ __forceinline__ void step_books(const NetDev& nd, uint64_t n) {
   nd.ring_base[n % nd.R] = pos;
   nd.chunk_base[n & (nd.chunk_ring - 1)] = pos;
   nd.ring_cnt[(n + 1) % nd.R] = 0;
+  // plastic arrivals: this step fills the list of arrival step n + 1; the list
+  // of step n was consumed by the plasticity kernel of step n - 1
+  if (nd.n_rules) nd.arr_cnt[n & 1] = 0;
 }
 
 // A spike of step n at position pos among the step's spikes: raster entry and
@@ -840,6 +911,7 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
     const uint32_t m = neuron_step<kLif, kAd, P>(nd, pops, pthr, n, i, a, nacc, nrej, capped, mover, nd.npop);
     spk = m > 0;
     entry = i | (m << kMultShift);
+    if (spk && nd.n_rules) nd.last_post[i] = (uint32_t)(n + 1);
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint64_t bal = __ballot(spk);
@@ -918,7 +990,7 @@ __device__ __forceinline__ void adex_load(const NetDev& nd, const PopDev* pops, 
     for (int p = 0; p < kMaxPorts; ++p)
       if (p == pp.pois_port) a[p] += (int64_t)k * pp.pois_wq;
   }
-  w.q = adex_par<P, kBeta>(pp);
+  w.q = adex_par<P, kBeta>(nd, pp, i);
   w.y[0] = nd.V[i];
   w.y[1] = nd.w[i];
   float x[P];
@@ -1101,6 +1173,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
       if (m) {
         const uint32_t i = first + loc;
         const uint32_t entry = i | (m << kMultShift);
+        if (nd.n_rules) nd.last_post[i] = (uint32_t)(n + 1);
         const uint64_t mask = nd.src_mask[i];
         const uint32_t gp = nd.grp_ptr[i];
         emit_spike(nd, n, pos_n, sl.emit + before + woff + (uint32_t)__popcll(bal & lanemask_lt()), entry, gp, mask);

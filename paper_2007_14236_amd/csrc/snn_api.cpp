@@ -17,8 +17,8 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <utility>
-#include <thread>
 #include <vector>
 
 #include "../../include/snn.h"
@@ -30,6 +30,7 @@ using namespace snn;
 namespace {
 
 constexpr uint32_t kGraphSteps = 100;
+constexpr int kNumParams = 16;  // SNN_P_TAU_M .. SNN_P_RK_HMIN
 constexpr uint64_t kChunkRing = 4096;  // >= drain interval + graph length
 constexpr uint64_t kBinnedMinSynapses = 500000000;  // default delivery: binned from this size on
 
@@ -44,6 +45,29 @@ struct HostPop {
   double E_rev[kMaxPorts] = {0.0, -85.0, 0.0, 0.0};
   double tau_rise[kMaxPorts] = {1.0, 1.0, 1.0, 1.0};
   bool adex() const { return model == SNN_AEIF_COND_EXP || model == SNN_AEIF_COND_BETA; }
+  // model parameter SNN_P_* by id (nullptr for an unknown id)
+  double* param(int32_t id) {
+    switch (id) {
+      case SNN_P_TAU_M: return &tau_m;
+      case SNN_P_C_M: return &C_m;
+      case SNN_P_E_L: return &E_L;
+      case SNN_P_V_TH: return &V_th;
+      case SNN_P_V_RESET: return &V_reset;
+      case SNN_P_T_REF: return &t_ref;
+      case SNN_P_G_L: return &g_L;
+      case SNN_P_DELTA_T: return &Delta_T;
+      case SNN_P_V_T: return &V_T;
+      case SNN_P_TAU_W: return &tau_w;
+      case SNN_P_A: return &a;
+      case SNN_P_B: return &b;
+      case SNN_P_V_PEAK: return &V_peak;
+      case SNN_P_V_R: return &V_r;
+      case SNN_P_RK_EPS: return &rk_eps;
+      case SNN_P_RK_HMIN: return &rk_hmin;
+      default: return nullptr;
+    }
+  }
+  const double* param(int32_t id) const { return const_cast<HostPop*>(this)->param(id); }
 };
 
 struct HostProj {
@@ -63,6 +87,10 @@ struct HostProj {
   std::vector<double> wlev;
   std::vector<uint64_t> wthr;
   std::vector<uint16_t> lwl;
+  // nearest-neighbour STDP (snn_stdp)
+  bool plastic = false;
+  int32_t mu_plus = 1, mu_minus = 1;
+  double tau_plus = 20.0, tau_minus = 20.0, lambda = 0.01, alpha = 1.0, w_max = 100.0;
   double wmin() const { return wlev.empty() ? weight : wlev.front(); }
   double wmax_abs() const {
     return wlev.empty() ? fabs(weight) : std::max(fabs(wlev.front()), fabs(wlev.back()));
@@ -197,6 +225,9 @@ struct snn_net {
   uint32_t N = 0;
   // host state before build (per port arrays are [N][kMaxPorts])
   std::vector<double> V, Ie, w, h;
+  // per-neuron model parameters: pn[param] is empty while every neuron takes
+  // its population's value, else one value per neuron
+  std::vector<double> pn[kNumParams];
   std::vector<double> g, gr, Isyn;
   std::vector<int32_t> refr;
 
@@ -204,8 +235,9 @@ struct snn_net {
   uint32_t P = 1;
   uint32_t dmax_used = 1;
   std::vector<int> shift;          // [npop][P]
-  std::vector<int64_t> cls_wq;     // classes sorted by (port, w_q)
+  std::vector<int64_t> cls_wq;     // classes sorted by (port, w_q, STDP rule)
   std::vector<uint32_t> cls_port;
+  std::vector<uint8_t> cls_rule;   // 0 static, r + 1 plastic under STDP rule r
   uint32_t cls_bits = 6;
   bool has_lif = false, has_adex = false, has_beta = false;
   NetDev nd{};
@@ -243,6 +275,9 @@ struct snn_net {
   size_t r_sorted = 0;
 
   double build_ms = 0.0, sim_ms = 0.0;
+  // snn_release: device memory returned, raster and counters kept on the host
+  bool released = false;
+  snn_counters final_ctr{};
 };
 
 namespace {
@@ -330,6 +365,21 @@ std::vector<int> whole_pops(const snn_net* net, uint32_t first, uint32_t n) {
   return out;
 }
 
+// The parameters neuron i is updated with: its population's, with every
+// parameter that is set per neuron replaced by the neuron's own value.
+HostPop neuron_params(const snn_net* net, uint32_t i) {
+  HostPop p = net->pops[pop_of(net, i)];
+  for (int32_t id = 0; id < kNumParams; ++id)
+    if (!net->pn[id].empty()) *p.param(id) = net->pn[id][i];
+  return p;
+}
+
+bool any_per_neuron(const snn_net* net) {
+  for (int32_t id = 0; id < kNumParams; ++id)
+    if (!net->pn[id].empty()) return true;
+  return false;
+}
+
 snn_status enter(snn_net* net) {
   if (!net) return SNN_E_INVALID;
   net->err.clear();
@@ -393,15 +443,20 @@ uint64_t next_pow2(uint64_t x) {
 }
 
 // device value of state variable `var` for neuron i (and the inverse)
+// resting potential of neuron i (its own when E_L is set per neuron)
+double rest_of(const snn_net* net, uint32_t i) {
+  return net->pn[SNN_P_E_L].empty() ? net->pops[pop_of(net, i)].E_L : net->pn[SNN_P_E_L][i];
+}
+
 float to_device_state(const snn_net* net, int var, uint32_t i, double v) {
   const HostPop& pp = net->pops[pop_of(net, i)];
-  if (var == SNN_V_M && !pp.adex()) return (float)(v - pp.E_L);
+  if (var == SNN_V_M && !pp.adex()) return (float)(v - rest_of(net, i));
   return (float)v;
 }
 
 double from_device_state(const snn_net* net, int var, uint32_t i, float v) {
   const HostPop& pp = net->pops[pop_of(net, i)];
-  if (var == SNN_V_M && !pp.adex()) return (double)v + pp.E_L;
+  if (var == SNN_V_M && !pp.adex()) return (double)v + rest_of(net, i);
   return (double)v;
 }
 
@@ -442,6 +497,10 @@ std::vector<std::pair<void*, size_t>> state_arrays(const snn_net* net) {
   add(nd.ctrl, sizeof(Ctrl));
   add(nd.blk_stats, (size_t)kBlkStats * nd.nblk_upd * 8);
   add(nd.sel_stats, (size_t)2 * nd.sel_grid * 8);
+  if (nd.n_rules) {  // plastic weights and the spike books of the plasticity
+    add(nd.pw, (size_t)nd.n_syn * 4); add(nd.last_pre, (size_t)nd.n_syn * 4); add(nd.arr_m, (size_t)nd.n_syn);
+    add(nd.last_post, N * 4); add(nd.arr_list, (size_t)2 * nd.n_plastic * 8); add(nd.arr_cnt, 8);
+  }
   return a;
 }
 
@@ -540,6 +599,8 @@ snn_status snn_create(snn_net* net, int32_t model, uint32_t n, uint32_t n_ports,
   }
   net->pops.push_back(p);
   net->N += n;
+  for (int32_t id = 0; id < kNumParams; ++id)  // parameters set per neuron: the new neurons take p's value
+    if (!net->pn[id].empty()) net->pn[id].resize(net->N, *p.param(id));
   net->V.resize(net->N, std::nan(""));
   net->Ie.resize(net->N, 0.0);
   net->w.resize(net->N, 0.0);
@@ -567,36 +628,35 @@ snn_status snn_begin_instance(snn_net* net, uint64_t seed, uint32_t* instance_id
   return SNN_OK;
 }
 
-snn_status snn_set_param(snn_net* net, uint32_t first, uint32_t n, int32_t param, double value) {
+snn_status snn_set_param(snn_net* net, uint32_t first, uint32_t n, int32_t param, const double* v, size_t nv) {
   if (!net) return SNN_E_INVALID;
   net->err.clear();
   if (net->built) return fail(net, SNN_E_STATE, "parameters are frozen after snn_build");
-  std::vector<int> ks = whole_pops(net, first, n);
-  if (ks.empty()) return fail(net, SNN_E_INVALID, "range [%u, %u) is not a union of whole populations", first, first + n);
-  for (int k : ks) {
-    HostPop& p = net->pops[k];
-    switch (param) {
-      case SNN_P_TAU_M: p.tau_m = value; break;
-      case SNN_P_C_M: p.C_m = value; break;
-      case SNN_P_E_L: p.E_L = value; break;
-      case SNN_P_V_TH: p.V_th = value; break;
-      case SNN_P_V_RESET: p.V_reset = value; break;
-      case SNN_P_T_REF: p.t_ref = value; break;
-      case SNN_P_G_L: p.g_L = value; break;
-      case SNN_P_DELTA_T: p.Delta_T = value; break;
-      case SNN_P_V_T: p.V_T = value; break;
-      case SNN_P_TAU_W: p.tau_w = value; break;
-      case SNN_P_A: p.a = value; break;
-      case SNN_P_B: p.b = value; break;
-      case SNN_P_V_PEAK: p.V_peak = value; break;
-      case SNN_P_V_R: p.V_r = value; break;
-      case SNN_P_RK_EPS: p.rk_eps = value; break;
-      case SNN_P_RK_HMIN: p.rk_hmin = value; break;
-      default: return fail(net, SNN_E_INVALID, "unknown parameter %d", param);
+  if (param < 0 || param >= kNumParams) return fail(net, SNN_E_INVALID, "unknown parameter %d", param);
+  if ((uint64_t)first + n > net->N) return fail(net, SNN_E_INVALID, "range [%u, %u) beyond the network", first, first + n);
+  if (n == 0) return SNN_OK;
+  if (!v || (nv != 1 && nv != n)) return fail(net, SNN_E_INVALID, "nv must be 1 (broadcast) or n (one value per neuron)");
+  for (size_t j = 0; j < nv; ++j)
+    if (!std::isfinite(v[j])) return fail(net, SNN_E_INVALID, "parameter values must be finite");
+  std::vector<int> ks = (nv == 1) ? whole_pops(net, first, n) : std::vector<int>();
+  std::vector<double>& pn = net->pn[param];
+  if (!ks.empty()) {  // one value for whole populations: the populations' constant
+    for (int k : ks) *net->pops[k].param(param) = v[0];
+    if (!pn.empty()) std::fill(pn.begin() + first, pn.begin() + first + n, v[0]);
+    return SNN_OK;
+  }
+  if (pn.empty()) {  // first per-neuron value of this parameter: every neuron starts from its population's
+    pn.resize(net->N);
+    for (size_t k = 0; k < net->pops.size(); ++k) {
+      HostPop& p = net->pops[k];
+      std::fill(pn.begin() + p.first, pn.begin() + p.first + p.n, *p.param(param));
     }
   }
+  for (uint32_t j = 0; j < n; ++j) pn[first + j] = v[nv == 1 ? 0 : j];
   return SNN_OK;
 }
+
+constexpr uint64_t kTagParam = 5;  // Philox tag of per-neuron parameter draws
 
 snn_status snn_set_port_param(snn_net* net, uint32_t first, uint32_t n, uint32_t port, int32_t param, double value) {
   if (!net) return SNN_E_INVALID;
@@ -768,6 +828,26 @@ snn_status snn_weight_distribution(snn_net* net, int32_t kind, double a, double 
   return SNN_OK;
 }
 
+snn_status snn_stdp(snn_net* net, double tau_plus, double tau_minus, double lambda, double alpha, int32_t mu_plus,
+                    int32_t mu_minus, double w_max) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "plasticity after snn_build");
+  if (net->projs.empty()) return fail(net, SNN_E_STATE, "no projection to make plastic");
+  if (!(tau_plus > 0) || !(tau_minus > 0) || !(lambda > 0) || !(lambda <= 1) || !(alpha >= 0) ||
+      !(alpha * lambda <= 1) || !(w_max > 0) || !std::isfinite(w_max) || (mu_plus != 0 && mu_plus != 1) ||
+      (mu_minus != 0 && mu_minus != 1))
+    return fail(net, SNN_E_INVALID, "bad STDP parameters");
+  HostProj& pr = net->projs.back();
+  const double lo = pr.wlev.empty() ? pr.weight : pr.wlev.front();
+  const double hi = pr.wlev.empty() ? pr.weight : pr.wlev.back();
+  if (lo < 0 || hi > w_max) return fail(net, SNN_E_INVALID, "plastic weights must lie in [0, w_max]");
+  pr.plastic = true;
+  pr.tau_plus = tau_plus; pr.tau_minus = tau_minus; pr.lambda = lambda; pr.alpha = alpha;
+  pr.mu_plus = mu_plus; pr.mu_minus = mu_minus; pr.w_max = w_max;
+  return SNN_OK;
+}
+
 // Philox4x64-10 on the host (Salmon et al., SC'11; the same published
 // definition the device kernels use) for draws made while the network is
 // defined.
@@ -807,6 +887,33 @@ snn_status snn_state_distribution(snn_net* net, uint32_t first, uint32_t n, int3
     }
   }
   return snn_set_state(net, first, n, var, port, v.data(), n);
+}
+
+snn_status snn_param_distribution(snn_net* net, uint32_t first, uint32_t n, int32_t param, int32_t kind, double a,
+                                  double b, double lo, double hi, uint32_t levels) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (net->built) return fail(net, SNN_E_STATE, "parameters are frozen after snn_build");
+  if ((uint64_t)first + n > net->N) return fail(net, SNN_E_INVALID, "bad parameter range");
+  if (param < 0 || param >= kNumParams) return fail(net, SNN_E_INVALID, "unknown parameter %d", param);
+  if (levels < 1 || levels > kStateLevelsMax) return fail(net, SNN_E_INVALID, "levels must be 1..%u", kStateLevelsMax);
+  std::vector<double> lev;
+  std::vector<uint64_t> thr;
+  if (const char* e = dist_levels(kind, a, b, lo, hi, levels, lev, thr)) return fail(net, SNN_E_INVALID, "%s", e);
+  if (n == 0) return SNN_OK;
+  std::vector<double> v(n);
+  for (uint32_t i = first; i < first + n;) {  // population by population: instance seed and first gid
+    const HostPop& pp = net->pops[pop_of(net, i)];
+    const uint64_t seed = net->insts[pp.inst].seed, g0 = net->insts[pp.inst].first_gid;
+    const uint32_t end = std::min(first + n, pp.first + pp.n);
+    for (; i < end; ++i) {
+      uint64_t c[4] = {i - g0, (uint64_t)param << 8, kTagParam, 0};
+      philox_host(c, seed, 0);
+      const uint32_t u = (uint32_t)(c[0] >> 32);
+      v[i - first] = lev[std::upper_bound(thr.begin(), thr.end(), (uint64_t)u) - thr.begin()];
+    }
+  }
+  return snn_set_param(net, first, n, param, v.data(), n);
 }
 
 snn_status snn_list_weights(snn_net* net, const double* weights, size_t n) {
@@ -1029,9 +1136,8 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
   if (!net->built) {
     for (uint32_t j = 0; j < n; ++j) {
       const uint32_t i = first + j;
-      const HostPop& pp = net->pops[pop_of(net, i)];
       switch (var) {
-        case SNN_V_M: out[j] = std::isnan(net->V[i]) ? pp.E_L : net->V[i]; break;
+        case SNN_V_M: out[j] = std::isnan(net->V[i]) ? rest_of(net, i) : net->V[i]; break;
         case SNN_V_I_E: out[j] = net->Ie[i]; break;
         case SNN_V_W: out[j] = net->w[i]; break;
         case SNN_V_G: out[j] = net->g[(size_t)i * kMaxPorts + port]; break;
@@ -1081,11 +1187,72 @@ snn_status snn_get_state(snn_net* net, uint32_t first, uint32_t n, int32_t var, 
   return leave(net);
 }
 
+}  // extern "C"
+
+namespace {
+
+snn_status build_impl(snn_net* net);
+
+// Everything a failed build left behind, so that the network is as before
+// the call (and may be built again, e.g. once memory is available).
+void release_build(snn_net* net) {
+  (void)hipStreamSynchronize(net->stream);
+  for (auto& gx : net->graphs) (void)hipGraphExecDestroy(gx.second);
+  net->graphs.clear();
+  while (!net->allocs.empty()) dev_free(net, net->allocs.back().p);
+  if (net->pin_cb) (void)hipHostFree(net->pin_cb);
+  if (net->pin_rc) (void)hipHostFree(net->pin_rc);
+  if (net->pin_ctrl) (void)hipHostFree(net->pin_ctrl);
+  if (net->ev_drain) (void)hipEventDestroy(net->ev_drain);
+  net->pin_cb = nullptr; net->pin_rc = nullptr; net->pin_ctrl = nullptr; net->ev_drain = nullptr;
+  net->d_addr = nullptr; net->d_mbuf = nullptr;
+  net->nd = NetDev{};
+  net->has_lif = net->has_adex = net->has_beta = false;
+  net->built = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+snn_status snn_release(snn_net* net) {
+  if (!net) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, net->released ? "already released" : "not built");
+  snn_status st = enter(net);
+  if (st) return st;
+  if ((st = drain(net))) return st;
+  sort_raster(net);
+  snn_counters c;
+  if ((st = snn_get_counters(net, &c))) return st;
+  if ((st = leave(net))) return st;
+  release_build(net);
+  c.device_bytes = net->dev_bytes;
+  net->final_ctr = c;
+  net->released = true;
+  return SNN_OK;
+}
+
 snn_status snn_build(snn_net* net) {
   if (!net) return SNN_E_INVALID;
   net->err.clear();
   if (net->built) return fail(net, SNN_E_STATE, "already built");
+  if (net->released) return fail(net, SNN_E_STATE, "released networks are not built again");
   if (net->N == 0) return fail(net, SNN_E_INVALID, "empty network");
+  const snn_status st = build_impl(net);
+  if (st != SNN_OK) {
+    const std::string msg = net->err;
+    release_build(net);
+    net->err = msg;
+  }
+  return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+snn_status build_impl(snn_net* net) {
   snn_status st = enter(net);
   if (st) return st;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1119,6 +1286,39 @@ snn_status snn_build(snn_net* net) {
           return fail(net, SNN_E_INVALID, "weights onto parrot neurons must be 1");
     }
   }
+  // populations whose neurons carry their own constants: a parameter that the
+  // model uses is set per neuron somewhere inside the population
+  std::vector<uint8_t> per_neuron(npop, 0);
+  if (any_per_neuron(net)) {
+    static const int32_t lif_ids[] = {SNN_P_TAU_M, SNN_P_C_M, SNN_P_E_L, SNN_P_V_TH, SNN_P_V_RESET, SNN_P_T_REF};
+    static const int32_t adex_ids[] = {SNN_P_C_M, SNN_P_E_L, SNN_P_T_REF, SNN_P_G_L, SNN_P_DELTA_T, SNN_P_V_T,
+                                       SNN_P_TAU_W, SNN_P_A, SNN_P_B, SNN_P_V_PEAK, SNN_P_V_R, SNN_P_RK_EPS,
+                                       SNN_P_RK_HMIN};
+    for (uint32_t k = 0; k < npop; ++k) {
+      const HostPop& p = net->pops[k];
+      if (p.model == SNN_SPIKE_GENERATOR || p.model == SNN_PARROT_NEURON) continue;
+      const int32_t* ids = p.adex() ? adex_ids : lif_ids;
+      const size_t nid = p.adex() ? sizeof adex_ids / sizeof adex_ids[0] : sizeof lif_ids / sizeof lif_ids[0];
+      for (size_t q = 0; q < nid && !per_neuron[k]; ++q) {
+        const std::vector<double>& v = net->pn[ids[q]];
+        if (v.empty()) continue;
+        const double pop_v = *p.param(ids[q]);
+        for (uint32_t i = p.first; i < p.first + p.n; ++i)
+          if (v[i] != pop_v) { per_neuron[k] = 1; break; }
+      }
+      if (!per_neuron[k]) continue;
+      for (uint32_t i = p.first; i < p.first + p.n; ++i) {
+        const HostPop q = neuron_params(net, i);
+        if (p.adex()) {
+          if (q.t_ref != 0.0) return fail(net, SNN_E_UNSUPPORTED, "AdEx refractory time must be 0 (neuron %u)", i);
+          if (!(q.Delta_T > 0) || !(q.tau_w > 0) || !(q.C_m > 0) || !(q.rk_eps > 0) || !(q.rk_hmin >= 0))
+            return fail(net, SNN_E_INVALID, "invalid AdEx parameters of neuron %u", i);
+        } else if (!(q.tau_m > 0) || !(q.C_m > 0) || q.t_ref < 0) {
+          return fail(net, SNN_E_INVALID, "invalid LIF parameters of neuron %u", i);
+        }
+      }
+    }
+  }
   net->P = P;
   // Poisson drive per population (drives cover whole populations)
   std::vector<int> pois_of_pop(npop, -1);
@@ -1138,7 +1338,9 @@ snn_status snn_build(snn_net* net) {
     if (pr.synapses() == 0) continue;
     for (uint32_t k = 0; k < npop; ++k)
       if (overlaps(k, pr.tgt_first, pr.tgt_n)) {
-        maxw[k * P + pr.port] = std::max(maxw[k * P + pr.port], pr.wmax_abs());
+        // a plastic weight can grow up to w_max
+        maxw[k * P + pr.port] = std::max(maxw[k * P + pr.port], pr.plastic ? std::max(pr.wmax_abs(), pr.w_max)
+                                                                             : pr.wmax_abs());
         if (net->pops[k].adex() && pr.wmin() < 0) return fail(net, SNN_E_INVALID, "conductance weights must be >= 0");
       }
   }
@@ -1147,12 +1349,48 @@ snn_status snn_build(snn_net* net) {
       if (overlaps(k, q.tgt_first, q.tgt_n)) maxw[k * P + q.port] = std::max(maxw[k * P + q.port], fabs(q.weight));
   net->shift.assign((size_t)npop * P, 0);
   for (size_t k = 0; k < maxw.size(); ++k) net->shift[k] = fixed_shift(maxw[k]);
-  // weight classes: distinct (port, w_q) sorted, per (projection, target population)
-  std::map<std::pair<uint32_t, int64_t>, uint32_t> classes;
-  std::vector<std::pair<uint32_t, int64_t>> cls_key((size_t)net->projs.size() * npop, {0, 0});
+  // STDP rules: one per (plastic projection, target population), numbered from 1
+  // in that order (0: static), with W = w_max in the population's fixed point
+  std::vector<StdpRule> rules;
+  std::vector<int64_t> stdp_F;
+  std::vector<uint32_t> rule_of((size_t)net->projs.size() * npop, 0);
+  for (size_t p = 0; p < net->projs.size(); ++p) {
+    const HostProj& pr = net->projs[p];
+    if (!pr.plastic || pr.synapses() == 0) continue;
+    // F(d) = round(scale e^{-d dt / tau} 2^32) up to its first zero
+    auto table = [&](double scale, double tau, uint32_t& len, uint64_t& off) -> bool {
+      off = stdp_F.size();
+      for (uint64_t d = 0;; ++d) {
+        const int64_t F = llrint(ldexp(scale * exp(-((double)d * dt) / tau), 32));
+        if (F == 0) break;
+        if (d >= (1u << 20)) return false;
+        stdp_F.push_back(F);
+      }
+      len = (uint32_t)(stdp_F.size() - off);
+      return true;
+    };
+    for (uint32_t k = 0; k < npop; ++k) {
+      if (!overlaps(k, pr.tgt_first, pr.tgt_n)) continue;
+      if (rules.size() >= 255) return fail(net, SNN_E_UNSUPPORTED, "more than 255 plastic (projection, population) pairs");
+      StdpRule r;
+      memset(&r, 0, sizeof r);
+      r.W = llrint(ldexp(pr.w_max, net->shift[k * P + pr.port]));
+      r.mu_plus = (uint32_t)pr.mu_plus; r.mu_minus = (uint32_t)pr.mu_minus;
+      if (!table(pr.lambda, pr.tau_plus, r.len_plus, r.off_plus) ||
+          !table(pr.alpha * pr.lambda, pr.tau_minus, r.len_minus, r.off_minus))
+        return fail(net, SNN_E_UNSUPPORTED, "STDP time constant too long for its tables (tau / dt > 2^20 / 20)");
+      rules.push_back(r);
+      rule_of[p * npop + k] = (uint32_t)rules.size();
+    }
+  }
+  // weight classes: distinct (port, w_q, rule) sorted (static before plastic at
+  // equal weights), per (projection, target population)
+  typedef std::tuple<uint32_t, int64_t, uint32_t> ClsKey;
+  std::map<ClsKey, uint32_t> classes;
+  std::vector<ClsKey> cls_key((size_t)net->projs.size() * npop, ClsKey{0, 0, 0});
   // projections with weight levels: the classes of every (target population, level)
   std::vector<uint32_t> wpop0(net->projs.size(), 0);
-  std::vector<std::vector<std::pair<uint32_t, int64_t>>> wkeys(net->projs.size());
+  std::vector<std::vector<ClsKey>> wkeys(net->projs.size());
   for (size_t p = 0; p < net->projs.size(); ++p) {
     const HostProj& pr = net->projs[p];
     if (pr.synapses() == 0) continue;
@@ -1161,7 +1399,7 @@ snn_status snn_build(snn_net* net) {
       wpop0[p] = k0;
       for (uint32_t k = k0; k <= k1; ++k)
         for (double w : pr.wlev) {
-          const std::pair<uint32_t, int64_t> key{pr.port, llrint(ldexp(w, net->shift[k * P + pr.port]))};
+          const ClsKey key{pr.port, llrint(ldexp(w, net->shift[k * P + pr.port])), rule_of[p * npop + k]};
           wkeys[p].push_back(key);
           classes[key] = 0;
         }
@@ -1170,8 +1408,8 @@ snn_status snn_build(snn_net* net) {
     for (uint32_t k = 0; k < npop; ++k) {
       if (!overlaps(k, pr.tgt_first, pr.tgt_n)) continue;
       const int64_t wq = llrint(ldexp(pr.weight, net->shift[k * P + pr.port]));
-      cls_key[p * npop + k] = {pr.port, wq};
-      classes[{pr.port, wq}] = 0;
+      cls_key[p * npop + k] = ClsKey{pr.port, wq, rule_of[p * npop + k]};
+      classes[cls_key[p * npop + k]] = 0;
     }
   }
   uint32_t tbits = 1;
@@ -1184,15 +1422,18 @@ snn_status snn_build(snn_net* net) {
   const size_t ncls = std::max<size_t>(1, classes.size());
   net->cls_wq.assign(ncls, 0);
   net->cls_port.assign(ncls, 0);
+  std::vector<uint8_t> cls_rule(ncls, 0);
   {
     uint32_t id = 0;
     for (auto& kv : classes) {
       kv.second = id;
-      net->cls_port[id] = kv.first.first;
-      net->cls_wq[id] = kv.first.second;
+      net->cls_port[id] = std::get<0>(kv.first);
+      net->cls_wq[id] = std::get<1>(kv.first);
+      cls_rule[id] = (uint8_t)std::get<2>(kv.first);
       ++id;
     }
   }
+  net->cls_rule = cls_rule;
   std::vector<uint16_t> cls_of((size_t)std::max<size_t>(1, net->projs.size()) * npop, 0);
   for (size_t p = 0; p < net->projs.size(); ++p)
     for (uint32_t k = 0; k < npop; ++k)
@@ -1244,6 +1485,7 @@ snn_status snn_build(snn_net* net) {
     memset(&d, 0, sizeof d);
     d.first = p.first; d.n = p.n; d.model = p.model; d.n_ports = (int32_t)p.ports;
     d.gid_base = net->insts[p.inst].first_gid; d.seed = net->insts[p.inst].seed;
+    d.per_neuron = per_neuron[k];
     if (!p.adex()) lif_propagators(p, dt, d);
     d.inv_C = (float)(1.0 / p.C_m); d.g_L = (float)p.g_L; d.E_L = (float)p.E_L; d.Delta_T = (float)p.Delta_T;
     d.inv_Delta_T = (float)(1.0 / p.Delta_T); d.V_T = (float)p.V_T; d.inv_tau_w = (float)(1.0 / p.tau_w);
@@ -1300,6 +1542,45 @@ snn_status snn_build(snn_net* net) {
   PopDev* d_pops; ALLOC(d_pops, PopDev, npop);
   HIPCHK(net, hipMemcpyAsync(d_pops, popdev.data(), npop * sizeof(PopDev), hipMemcpyHostToDevice, s));
   nd.pops = d_pops;
+  nd.nlif = nullptr;
+  nd.nadex = nullptr;
+  {  // constants of the neurons of per-neuron populations, computed as the population's are
+    std::vector<NeuronLif> hl;
+    std::vector<NeuronAdex> ha;
+    for (uint32_t k = 0; k < npop; ++k) {
+      if (!per_neuron[k]) continue;
+      const HostPop& p = net->pops[k];
+      if (p.adex() && ha.empty()) ha.assign(N, NeuronAdex{});
+      if (!p.adex() && hl.empty()) hl.assign(N, NeuronLif{});
+      for (uint32_t i = p.first; i < p.first + p.n; ++i) {
+        const HostPop q = neuron_params(net, i);
+        PopDev d;
+        memset(&d, 0, sizeof d);
+        if (!p.adex()) {
+          lif_propagators(q, dt, d);
+          NeuronLif& c = hl[i];
+          c.P22 = d.P22; c.P20 = d.P20; c.theta = d.theta; c.y_reset = d.y_reset; c.n_ref = d.n_ref;
+          for (int r = 0; r < kMaxPorts; ++r) c.P21[r] = d.P21[r];
+        } else {
+          NeuronAdex& c = ha[i];
+          c.inv_C = (float)(1.0 / q.C_m); c.g_L = (float)q.g_L; c.E_L = (float)q.E_L; c.Delta_T = (float)q.Delta_T;
+          c.inv_Delta_T = (float)(1.0 / q.Delta_T); c.V_T = (float)q.V_T; c.inv_tau_w = (float)(1.0 / q.tau_w);
+          c.a = (float)q.a; c.b = (float)q.b; c.V_peak = (float)q.V_peak; c.V_r = (float)q.V_r;
+          c.rk_eps = (float)q.rk_eps; c.rk_hmin = (float)q.rk_hmin;
+        }
+      }
+    }
+    if (!hl.empty()) {
+      NeuronLif* d_nl; ALLOC(d_nl, NeuronLif, N);
+      HIPCHK(net, copy_sync(net, d_nl, hl.data(), (size_t)N * sizeof(NeuronLif), hipMemcpyHostToDevice));
+      nd.nlif = d_nl;
+    }
+    if (!ha.empty()) {
+      NeuronAdex* d_na; ALLOC(d_na, NeuronAdex, N);
+      HIPCHK(net, copy_sync(net, d_na, ha.data(), (size_t)N * sizeof(NeuronAdex), hipMemcpyHostToDevice));
+      nd.nadex = d_na;
+    }
+  }
   uint64_t* d_pthr; ALLOC(d_pthr, uint64_t, pois_thr.size());
   HIPCHK(net, hipMemcpyAsync(d_pthr, pois_thr.data(), pois_thr.size() * 8, hipMemcpyHostToDevice, s));
   nd.pois_thr = d_pthr;
@@ -1421,14 +1702,56 @@ snn_status snn_build(snn_net* net) {
   nd.n_groups = G; nd.n_syn = S;
   net->n_groups = G; net->n_syn = S;
 
+  // ---- plastic synapses: rules and tables, weights, the index by target ----
+  nd.n_rules = 0;
+  nd.n_plastic = 0;
+  if (!rules.empty()) {
+    uint8_t* d_crule; ALLOC(d_crule, uint8_t, ncls);
+    HIPCHK(net, hipMemcpyAsync(d_crule, cls_rule.data(), ncls, hipMemcpyHostToDevice, s));
+    StdpRule* d_rules; ALLOC(d_rules, StdpRule, rules.size());
+    HIPCHK(net, hipMemcpyAsync(d_rules, rules.data(), rules.size() * sizeof(StdpRule), hipMemcpyHostToDevice, s));
+    int64_t* d_F; ALLOC(d_F, int64_t, std::max<size_t>(1, stdp_F.size()));
+    if (!stdp_F.empty())
+      HIPCHK(net, hipMemcpyAsync(d_F, stdp_F.data(), stdp_F.size() * 8, hipMemcpyHostToDevice, s));
+    nd.cls_rule = d_crule; nd.rules = d_rules; nd.stdp_F = d_F;
+    nd.n_rules = (uint32_t)rules.size();
+    int32_t* d_pw; ALLOC(d_pw, int32_t, std::max<uint64_t>(1, S));
+    uint32_t* d_lpre; ALLOC(d_lpre, uint32_t, std::max<uint64_t>(1, S));
+    uint8_t* d_am; ALLOC(d_am, uint8_t, std::max<uint64_t>(1, S));
+    uint32_t* d_lpost; ALLOC(d_lpost, uint32_t, N);
+    HIPCHK(net, hipMemsetAsync(d_lpost, 0, (size_t)N * 4, s));
+    nd.pw = d_pw; nd.last_pre = d_lpre; nd.arr_m = d_am; nd.last_post = d_lpost;
+    uint32_t* d_tc; ALLOC(d_tc, uint32_t, N);
+    HIPCHK(net, hipMemsetAsync(d_tc, 0, (size_t)N * 4, s));
+    HIPCHK(net, launch_stdp_count(nd, d_tc, s));
+    uint64_t* d_tptr; ALLOC(d_tptr, uint64_t, (size_t)N + 1);
+    uint64_t* d_stmp; ALLOC(d_stmp, uint64_t, scan_tmp_words(N));
+    HIPCHK(net, launch_scan_u32(d_tc, N, d_tptr, d_stmp, s));
+    uint64_t n_plastic = 0;
+    HIPCHK(net, copy_sync(net, &n_plastic, d_tptr + N, 8, hipMemcpyDeviceToHost));
+    uint64_t* d_cur; ALLOC(d_cur, uint64_t, (size_t)N + 1);
+    HIPCHK(net, hipMemcpyAsync(d_cur, d_tptr, ((size_t)N + 1) * 8, hipMemcpyDeviceToDevice, s));
+    uint64_t* d_tidx; ALLOC(d_tidx, uint64_t, std::max<uint64_t>(1, n_plastic));
+    HIPCHK(net, launch_stdp_scatter(nd, d_cur, d_tidx, s));
+    uint64_t* d_alist; ALLOC(d_alist, uint64_t, 2 * std::max<uint64_t>(1, n_plastic));
+    uint32_t* d_acnt; ALLOC(d_acnt, uint32_t, 2);
+    HIPCHK(net, hipMemsetAsync(d_acnt, 0, 8, s));
+    HIPCHK(net, hipStreamSynchronize(s));
+    dev_free(net, d_tc); dev_free(net, d_stmp); dev_free(net, d_cur);
+    nd.tptr = d_tptr; nd.tidx = d_tidx; nd.arr_list = d_alist; nd.arr_cnt = d_acnt;
+    nd.n_plastic = std::max<uint64_t>(1, n_plastic);
+    if (n_plastic >= (1ull << 32)) return fail(net, SNN_E_UNSUPPORTED, "more than 2^32 plastic synapses");
+  }
+
   // ---- state ----
   float* d_V; ALLOC(d_V, float, N);
   float* d_Ie; ALLOC(d_Ie, float, N);
   std::vector<float> hv(N), hie(N);
   for (uint32_t i = 0; i < N; ++i) {
     const HostPop& pp = net->pops[pop_of(net, i)];
-    const double V = std::isnan(net->V[i]) ? pp.E_L : net->V[i];
-    hv[i] = pp.adex() ? (float)V : (float)(V - pp.E_L);
+    const double E_L = rest_of(net, i);  // a neuron rests at its own E_L
+    const double V = std::isnan(net->V[i]) ? E_L : net->V[i];
+    hv[i] = pp.adex() ? (float)V : (float)(V - E_L);
     hie[i] = (float)net->Ie[i];
   }
   HIPCHK(net, copy_sync(net, d_V, hv.data(), N * 4, hipMemcpyHostToDevice));
@@ -1649,6 +1972,10 @@ snn_status snn_build(snn_net* net) {
   return leave(net);
 }
 
+}  // namespace
+
+extern "C" {
+
 snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
   if (!net) return SNN_E_INVALID;
   net->err.clear();
@@ -1703,6 +2030,7 @@ snn_status snn_profile_steps(snn_net* net, uint64_t steps, double* kernel_ms) {
   const auto t0 = std::chrono::steady_clock::now();
   for (uint64_t k = 0; k < steps; ++k) {
     HIPCHK(net, launch_step(net->nd, 0, net->stream, ev[0], ev[1]));
+    HIPCHK(net, launch_stdp(net->nd, 0, net->stream));
     HIPCHK(net, launch_sample(net->d_addr, net->nch, net->d_mbuf, kGraphSteps, net->nd.ctrl, 0, net->stream));
     HIPCHK(net, launch_advance(net->nd.ctrl, 1, net->stream));
     HIPCHK(net, hipEventSynchronize(ev[1]));
@@ -1756,6 +2084,10 @@ snn_status snn_get_spikes(snn_net* net, uint64_t step_lo, uint64_t step_hi, uint
 snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   if (!net || !out) return SNN_E_INVALID;
   net->err.clear();
+  if (net->released) {
+    *out = net->final_ctr;
+    return SNN_OK;
+  }
   memset(out, 0, sizeof *out);
   out->n_neurons = net->N;
   out->build_ms = net->build_ms;
@@ -1913,6 +2245,30 @@ snn_status snn_export_synapses(snn_net* net, uint32_t* src, uint32_t* delay, uin
   return leave(net);
 }
 
+snn_status snn_get_weights(snn_net* net, int64_t* wq, size_t* n_syn) {
+  if (!net || !n_syn) return SNN_E_INVALID;
+  net->err.clear();
+  if (!net->built) return fail(net, SNN_E_STATE, "not built");
+  const size_t capn = *n_syn;
+  *n_syn = net->n_syn;
+  if (capn < net->n_syn || !wq) return SNN_OK;
+  snn_status st = enter(net);
+  if (st) return st;
+  std::vector<uint32_t> pay(net->n_syn);
+  if (net->n_syn) HIPCHK(net, copy_sync(net, pay.data(), net->nd.payload, net->n_syn * 4, hipMemcpyDeviceToHost));
+  std::vector<int32_t> pw;
+  if (net->nd.n_rules) {
+    pw.resize(net->n_syn);
+    HIPCHK(net, copy_sync(net, pw.data(), net->nd.pw, net->n_syn * 4, hipMemcpyDeviceToHost));
+  }
+  const uint32_t cls_mask = (1u << net->cls_bits) - 1u;
+  for (uint64_t j = 0; j < net->n_syn; ++j) {  // CSR position order is the canonical order
+    const uint32_t cls = pay[j] & cls_mask;
+    wq[j] = (!pw.empty() && net->cls_rule[cls]) ? (int64_t)pw[j] : net->cls_wq[cls];
+  }
+  return leave(net);
+}
+
 }  // extern "C"
 
 namespace {
@@ -1923,6 +2279,7 @@ snn_status record_graph(snn_net* net, uint32_t steps, hipGraphExec_t* out) {
   hipError_t e = hipSuccess;
   for (uint32_t r = 0; r < steps && e == hipSuccess; ++r) {
     e = launch_step(net->nd, r, net->stream);
+    if (e == hipSuccess) e = launch_stdp(net->nd, r, net->stream);
     if (e == hipSuccess) e = launch_sample(net->d_addr, net->nch, net->d_mbuf, kGraphSteps, net->nd.ctrl, r, net->stream);
   }
   if (e == hipSuccess) e = launch_advance(net->nd.ctrl, steps, net->stream);
@@ -2082,3 +2439,28 @@ snn_status drain(snn_net* net) {
 }
 
 }  // namespace
+
+// ---- hooks for the request server (snn_server.cpp) ----
+namespace snn {
+
+void net_allocator(const snn_net* net, snn_device* dev, bool* have_dev) {
+  *dev = net->dev;
+  *have_dev = net->have_dev;
+}
+
+void net_set_allocator(snn_net* net, const snn_device& dev, bool have_dev) {
+  net->dev = dev;
+  net->have_dev = have_dev;
+}
+
+int net_device(const snn_net* net) { return net->device; }
+
+bool net_is_fresh(const snn_net* net) { return !net->built && !net->released && net->N > 0; }
+
+uint64_t net_planned_synapses(const snn_net* net) {
+  uint64_t s = 0;
+  for (const HostProj& pr : net->projs) s += pr.synapses();
+  return s;
+}
+
+}  // namespace snn

@@ -76,8 +76,25 @@ struct PopDev {
   int32_t pois_port;
   int64_t pois_wq;
   // instance of the population: first gid and generator key
-  uint32_t gid_base, pad;
+  uint32_t gid_base;
+  // 1: the neurons carry their own constants (NetDev::nlif / nadex, indexed by
+  // gid) in place of the LIF or AdEx fields above
+  uint32_t per_neuron;
   uint64_t seed;
+};
+
+// Constants of one LIF neuron whose parameters are its own (tau_m, C_m, E_L,
+// V_th, V_reset, t_ref per neuron; tau_syn stays per population, so P11 does).
+struct NeuronLif {
+  float P22, P20, theta, y_reset;
+  float P21[kMaxPorts];
+  int32_t n_ref, pad;
+};
+
+// Constants of one AdEx neuron whose parameters are its own (all but the
+// port constants).
+struct NeuronAdex {
+  float inv_C, g_L, E_L, Delta_T, inv_Delta_T, V_T, inv_tau_w, a, b, V_peak, V_r, rk_eps, rk_hmin, pad;
 };
 
 static_assert(sizeof(PopDev) % 8 == 0, "PopDev is copied to LDS in 32-bit words");
@@ -118,6 +135,17 @@ struct Ctrl {
   uint64_t spill_events;   // binned delivery: events that did not fit their tile's bin
 };
 
+// Nearest-neighbour STDP rule of the plastic synapses of one (projection,
+// target population): W = w_max in the fixed-point units of their (target
+// population, port); F+(d) = stdp_F[off_plus + d] for d < len_plus (0
+// beyond), F-(d) likewise, both scaled by 2^32.
+struct StdpRule {
+  int64_t W;
+  uint32_t mu_plus, mu_minus;
+  uint32_t len_plus, len_minus;
+  uint64_t off_plus, off_minus;
+};
+
 struct NetDev {
   uint32_t N, P, npop, dmax;   // dmax = largest delay present
   uint32_t npois, pois_len;    // Poisson threshold tables; entries read at most (the rest are never reached)
@@ -128,6 +156,8 @@ struct NetDev {
   uint64_t chunk_ring;         // slots of chunk_base (power of two)
   uint64_t n_groups, n_syn;
   const PopDev* pops;
+  const NeuronLif* nlif;       // [N] or null: constants of neurons of per_neuron LIF populations
+  const NeuronAdex* nadex;     // [N] or null: the same for AdEx populations
   const uint64_t* pois_thr;    // [npois][kPoisKmax]
   const int64_t* cls_wq;       // [n_classes]
   const uint32_t* cls_port;    // [n_classes]
@@ -148,6 +178,25 @@ struct NetDev {
   // per-update-block statistics [nblk_upd][kBlkStats]
   uint64_t* blk_stats;
   Ctrl* ctrl;
+  // nearest-neighbour STDP (n_rules == 0: no plastic synapse; the rest unset).
+  // Per synapse (CSR position j): its weight pw, the step + 1 of its latest
+  // arrival (0: none) and the multiplicity arriving at the next step; per
+  // neuron the step + 1 of its latest spike; the plastic synapses onto each
+  // target, tidx[tptr[t] .. tptr[t+1]); the plastic synapses an arrival step
+  // delivers to, arr_list[step & 1][0 .. arr_cnt[step & 1]).
+  uint32_t n_rules, pad1;
+  uint64_t n_plastic;
+  const StdpRule* rules;
+  const int64_t* stdp_F;
+  const uint8_t* cls_rule;     // [n_classes]: 0 static, r + 1 plastic under rules[r]
+  int32_t* pw;
+  uint32_t* last_pre;
+  uint8_t* arr_m;
+  uint32_t* last_post;
+  const uint64_t* tptr;
+  const uint64_t* tidx;
+  uint64_t* arr_list;
+  uint32_t* arr_cnt;
 };
 
 }  // namespace snn

@@ -1,26 +1,26 @@
-"""Batched serving of simulation requests on one GPU.
+"""Serving simulation requests on one GPU through the library's request
+server (the snn_server_* calls of include/snn.h).
 
 A request is a network specification and a biological duration.  Requests
-arrive over time into one queue.  A pool of workers takes them: a free worker
-packs the queued requests of the oldest request's model family that fit the
-memory left in the budget (by the estimate below) and binned delivery's
-resident capacity as independent instances of one network
-(``snn_begin_instance``) and advances them together in the same kernels, on
-the network's own stream; the workers' batches overlap on the device, so a
-request that arrives while others run is admitted as soon as a worker and
-memory are free.  Each request completes, with its own raster, when its batch
-reaches its duration.  Instances draw exactly what they would draw alone, so
-a request's result does not depend on what it was batched with.  With one
-worker and ``max_batch=1`` the same loop serves the requests one at a time in
-arrival order (the FIFO baseline).
+arrive over time; each is defined as a network (not built) and submitted at
+its arrival time.  The server queues them in submission order and its
+`slots` worker threads each take the first queued request whose memory need
+fits what is left of the device-memory budget, build it, simulate it on the
+network's own stream and release its memory the moment it is done, so
+requests arriving while others run are admitted as slots and memory free up
+and their work overlaps on the device.  Every device allocation of a served
+network passes through the server, which holds the budget exactly.  Each
+network runs the kernels it would run alone, so its raster does not depend
+on what it was served with.  With one slot the same server serves the
+requests one at a time in arrival order (the FIFO baseline).
 
-Only host-side scheduling lives here: every simulation step runs in the
-library's kernels through the C ABI.
+Only the arrival clock, the trace and the report live here: admission,
+building, stepping and release happen in the library.
 """
 from __future__ import annotations
 
+import ctypes as C
 import hashlib
-import threading
 import time
 from dataclasses import dataclass, field
 
@@ -29,55 +29,43 @@ import numpy as np
 from . import snn as S
 from . import workloads as W
 
-RECORD_SLOTS = 64  # selection records per neuron (Dmax + 1 at the largest Dmax)
-# neuron-ports of one batch: 512 tiles of 4096 int64 sums, so that the tile
-# blocks and the delivery blocks of a binned step are resident at once (three
-# 53 KB blocks per CU); a larger batch runs its tile blocks in several rounds,
-# each bounded by the ~100-substep RK45 spike steps of AdEx neurons
-TILE_LIMIT = 512 * 4096
-
 
 @dataclass
 class Request:
     rid: int
     arrival_s: float
-    family: str          # "microcircuit" or "adex": the model family a batch is formed from
+    family: str          # "microcircuit" or "adex"
     spec: dict
     steps: int
-    est_bytes: int
 
 
 @dataclass
 class Result:
     rid: int
     arrival_s: float
-    start_s: float       # when the batch holding it started (build included)
+    start_s: float       # first taken by a slot (build included from here)
     finish_s: float
-    batch_size: int
+    status: int          # 0, or the snn_status of a failed request
+    attempts: int        # builds tried (more than one after budget refusals)
     spikes: int
-    digest: str          # sha256 of the request's own raster (step, local gid, multiplicity)
+    events: int
+    device_bytes: int    # most device memory the request held
+    digest: str          # sha256 of the request's raster (step, gid, multiplicity)
 
 
 @dataclass
 class ServeReport:
     results: list = field(default_factory=list)
-    batches: int = 0
-    events: int = 0
     makespan_s: float = 0.0
+    peak_bytes: int = 0
+    budget_bytes: int = 0
 
     def latencies(self) -> np.ndarray:
-        return np.array([r.finish_s - r.arrival_s for r in self.results])
+        return np.array([r.finish_s - r.arrival_s for r in self.results if r.status == 0])
 
-
-def estimate_bytes(spec: dict) -> int:
-    """Device memory of one instance: synapse words, neuron state, selection
-    records, raster ring at one spike per neuron and step, input buffers,
-    with a factor 2 of headroom."""
-    n = W.total_neurons(spec)
-    syn = W.count_synapses(spec)
-    ports = max(p["ports"] for p in spec["populations"])
-    per_neuron = 64 + 16 * RECORD_SLOTS + 4 * 1301 + 2 * 8 * ports
-    return 2 * (4 * syn + n * per_neuron)
+    @property
+    def events(self) -> int:
+        return sum(r.events for r in self.results)
 
 
 def request_trace(n: int, rate_hz: float = 20.0, key: int = 4) -> list:
@@ -100,8 +88,7 @@ def request_trace(n: int, rate_hz: float = 20.0, key: int = 4) -> list:
             spec = W.adex_balanced(n=nn, k=1000, seed=1000 + i)
             family = "adex"
         dur_ms = float(g.uniform(100.0, 2000.0))
-        steps = W.steps_for(dur_ms, spec["dt"])
-        out.append(Request(i, t, family, spec, steps, estimate_bytes(spec)))
+        out.append(Request(i, t, family, spec, W.steps_for(dur_ms, spec["dt"])))
     return out
 
 
@@ -109,157 +96,110 @@ _REC = np.dtype([("step", "<i8"), ("gid", "<i8"), ("mult", "<i8")])
 
 
 def raster_records(step: np.ndarray, gid: np.ndarray, mult: np.ndarray) -> bytes:
-    """(step, local gid, multiplicity) records of a raster in (step, gid) order,
-    the bytes its digest is taken over (consecutive pieces hash as the whole)."""
+    """(step, gid, multiplicity) records of a raster in (step, gid) order, the
+    bytes its digest is taken over."""
     r = np.empty(len(step), dtype=_REC)
     r["step"], r["gid"], r["mult"] = step, gid, mult
     return r.tobytes()
 
 
+def digest_of(net: "S.Net", steps: int) -> tuple:
+    st, gid, m = net.spikes(0, steps)
+    return len(st), hashlib.sha256(raster_records(st, gid, m)).hexdigest()
+
+
 def run_alone(req: Request) -> str:
     """Digest of the request's raster simulated as the only network."""
     net = S.Net(req.spec)
-    net.simulate(req.steps)
-    st, gid, m = net.spikes(0, req.steps)
-    net.close()
-    return hashlib.sha256(raster_records(st, gid, m)).hexdigest()
-
-
-def neuron_ports(spec: dict) -> int:
-    """Neurons times the port count rounded up to a power of two: the LDS
-    accumulators the network takes in binned delivery."""
-    ports = max(p["ports"] for p in spec["populations"])
-    p2 = 1
-    while p2 < ports:
-        p2 *= 2
-    return W.total_neurons(spec) * p2
+    try:
+        net.simulate(req.steps)
+        return digest_of(net, req.steps)[1]
+    finally:
+        net.close()
 
 
 class Server:
-    """Batching scheduler over the C ABI.  `budget_bytes` bounds the estimated
-    device memory of the batches in flight, `workers` how many run at once,
-    `max_batch` the instances of one batch; a batch also stays within what
-    binned delivery holds resident."""
+    """Arrival clock over the library's request server: `budget_bytes` of
+    device memory, `slots` requests in flight at most."""
 
-    def __init__(self, budget_bytes: int = 200 << 30, max_batch: int = 64, workers: int = 4, log=None,
-                 digest_ids=None):
-        self.budget = budget_bytes
-        self.max_batch = max_batch
-        self.workers = workers
+    def __init__(self, budget_bytes: int = 200 << 30, slots: int = 4, log=None, digest_ids=None,
+                 keep_nets: bool = False):
+        self.budget = int(budget_bytes)
+        self.slots = int(slots)
         self.log = log
         self.digest_ids = digest_ids  # requests whose raster digest is taken (None: all)
-        self.lock = threading.Lock()
-
-    def _take_batch(self, queue: list, budget: int | None = None) -> list:
-        budget = self.budget if budget is None else budget
-        family = queue[0].family
-        batch, used, nports = [], 0, 0
-        for r in list(queue):
-            if r.family != family:
-                continue
-            npr = neuron_ports(r.spec) if r.spec else 0
-            if batch and (len(batch) >= self.max_batch or used + r.est_bytes > budget or nports + npr > TILE_LIMIT):
-                break
-            batch.append(r)
-            used += r.est_bytes
-            nports += npr
-        for r in batch:
-            queue.remove(r)
-        return batch
-
-    def _serve_batch(self, batch: list, t0: float, rep: ServeReport):
-        start = time.perf_counter() - t0
-        net = S.Net([r.spec for r in batch])
-        firsts = np.array([inst["first"] for inst in net.instances], dtype=np.int64)
-        pending = sorted(range(len(batch)), key=lambda j: batch[j].steps)
-        digest = {j: hashlib.sha256() for j in range(len(batch))}
-        count = {j: 0 for j in range(len(batch))}
-        done = 0
-        t_sim = t_ras = 0.0
-        while pending:
-            target = batch[pending[0]].steps
-            ta = time.perf_counter()
-            net.simulate(target - done)
-            tb = time.perf_counter()
-            t_sim += tb - ta
-            # the segment's raster, grouped by instance (stable: (step, gid) order kept)
-            st, gid, m = net.spikes(done, target)
-            who = (np.searchsorted(firsts, gid.astype(np.int64), side="right") - 1).astype(np.int16)
-            order = np.argsort(who, kind="stable")
-            bounds = np.concatenate([[0], np.cumsum(np.bincount(who, minlength=len(batch)))])
-            for j in pending:
-                idx = order[bounds[j]:bounds[j + 1]]
-                count[j] += int(idx.size)
-                if self.digest_ids is None or batch[j].rid in self.digest_ids:
-                    digest[j].update(raster_records(st[idx], gid[idx].astype(np.int64) - firsts[j], m[idx]))
-            done = target
-            t_ras += time.perf_counter() - tb
-            now = time.perf_counter() - t0
-            while pending and batch[pending[0]].steps == done:
-                j = pending.pop(0)
-                r = batch[j]
-                res = Result(r.rid, r.arrival_s, start, now, len(batch), count[j], digest[j].hexdigest())
-                with self.lock:
-                    rep.results.append(res)
-        ev = net.counters()["events"]
-        net.close()
-        with self.lock:
-            rep.events += ev
-            rep.batches += 1
-        if self.log:
-            self.log(f"batch of {len(batch)} {batch[0].family} requests done at {time.perf_counter() - t0:.2f} s "
-                     f"(started {start:.2f} s; {done} steps simulated in {t_sim:.2f} s, rasters {t_ras:.2f} s)")
+        self.keep_nets = keep_nets    # hand the finished networks to the caller (report.nets)
 
     def serve(self, trace: list) -> ServeReport:
-        """Serve the trace in real time (arrivals released at their times)."""
-        rep = ServeReport()
-        errors: list = []
-        state = {"next": 0, "queue": [], "in_flight": 0, "taken": 0}
-        cv = threading.Condition(self.lock)
-        t0 = time.perf_counter()
-
-        def release(now):  # with the lock held: arrivals up to `now` into the queue
-            while state["next"] < len(trace) and trace[state["next"]].arrival_s <= now:
-                state["queue"].append(trace[state["next"]])
-                state["next"] += 1
-
-        def worker():
-            try:
-                while True:
-                    with cv:
-                        while True:
-                            if errors or state["taken"] == len(trace):
-                                return
-                            now = time.perf_counter() - t0
-                            release(now)
-                            free = self.budget - state["in_flight"]
-                            q = state["queue"]
-                            if q and (q[0].est_bytes <= free or state["in_flight"] == 0):
-                                batch = self._take_batch(q, max(free, 0))
-                                used = sum(r.est_bytes for r in batch)
-                                state["in_flight"] += used
-                                state["taken"] += len(batch)
-                                break
-                            wait = (trace[state["next"]].arrival_s - now) if state["next"] < len(trace) else 0.05
-                            cv.wait(timeout=min(max(wait, 0.0005), 0.05))
-                    try:
-                        self._serve_batch(batch, t0, rep)
-                    finally:
-                        with cv:
-                            state["in_flight"] -= used
-                            cv.notify_all()
-            except Exception as e:  # reported by serve()
-                with cv:
-                    errors.append(e)
-                    cv.notify_all()
-
-        threads = [threading.Thread(target=worker) for _ in range(max(1, self.workers))]
-        for th in threads:
-            th.start()
-        for th in threads:
-            th.join()
-        if errors:
-            raise errors[0]
-        rep.makespan_s = max(r.finish_s for r in rep.results) - min(r.arrival_s for r in trace)
-        rep.results.sort(key=lambda r: r.rid)
+        """Submit each request at its arrival time (seconds after the start),
+        collect the results as they finish."""
+        L = S.lib()
+        h = C.c_void_p()
+        rc = L.snn_server_create(self.budget, self.slots, C.byref(h))
+        if rc != 0:
+            raise S.SnnError(f"server: {S.ERRORS.get(rc, rc)}")
+        rep = ServeReport(budget_bytes=self.budget)
+        rep.nets = {}
+        pending = {}
+        t0 = time.perf_counter()  # CLOCK_MONOTONIC, the clock of the server's job times
+        i = 0
+        try:
+            while i < len(trace) or pending:
+                now = time.perf_counter() - t0
+                while i < len(trace) and trace[i].arrival_s <= now:
+                    r = trace[i]
+                    net = S.Net(r.spec, build=False)
+                    ticket = C.c_uint64()
+                    rc = L.snn_server_submit(h, net.h, r.steps, C.byref(ticket))
+                    if rc != 0:
+                        rep.results.append(Result(r.rid, r.arrival_s, now, now, rc, 0, 0, 0, 0, ""))
+                        net.close()
+                    else:
+                        pending[ticket.value] = (r, net)
+                    i += 1
+                done = []
+                for t in pending:
+                    state = C.c_int32()
+                    if L.snn_server_poll(h, t, C.byref(state)) == 0 and state.value in (S.JOB_DONE, S.JOB_FAILED):
+                        done.append(t)
+                for t in done:
+                    r, net = pending.pop(t)
+                    out = C.c_void_p()
+                    info = S.JobInfo()
+                    rc = L.snn_server_result(h, t, C.byref(out), C.byref(info))
+                    spikes = events = 0
+                    dg = ""
+                    if rc == 0:
+                        c = net.counters()
+                        events = c["events"]
+                        if self.digest_ids is None or r.rid in self.digest_ids:
+                            spikes, dg = digest_of(net, r.steps)
+                        else:
+                            spikes = c["spikes"]
+                    elif self.log:
+                        self.log(f"request {r.rid} failed: {S.ERRORS.get(rc, rc)} {info.error.decode()}")
+                    rep.results.append(Result(r.rid, r.arrival_s, info.t_start - t0, info.t_done - t0, rc,
+                                              info.attempts, spikes, events, info.device_bytes_peak, dg))
+                    if self.keep_nets and rc == 0:
+                        rep.nets[r.rid] = net
+                    else:
+                        net.close()
+                    if self.log:
+                        self.log(f"request {r.rid} ({r.family}) done at {info.t_done - t0:.2f} s "
+                                 f"(arrived {r.arrival_s:.2f} s, started {info.t_start - t0:.2f} s)")
+                if i < len(trace):
+                    wait = trace[i].arrival_s - (time.perf_counter() - t0)
+                    time.sleep(min(max(wait, 0.0), 0.002))
+                else:
+                    time.sleep(0.001)
+            st = S.ServerStats()
+            L.snn_server_get_stats(h, C.byref(st))
+            rep.peak_bytes = st.peak
+        finally:
+            L.snn_server_destroy(h)
+            for r, net in pending.values():  # never finished: back to us with the server gone
+                net.close()
+        rep.results.sort(key=lambda x: x.rid)
+        ok = [x for x in rep.results if x.status == 0]
+        rep.makespan_s = (max(x.finish_s for x in ok) - min(x.arrival_s for x in trace)) if ok else 0.0
         return rep

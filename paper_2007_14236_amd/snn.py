@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsnn.so")
 
 SNN_OK = 0
-ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "STATE", -4: "OVERFLOW", -5: "DEVICE", -7: "UNSUPPORTED"}
+ERRORS = {-1: "INVALID", -2: "NOMEM", -3: "STATE", -4: "OVERFLOW", -5: "DEVICE", -6: "BUDGET", -7: "UNSUPPORTED"}
 MODELS = {"lif_delta": 0, "lif_exp": 1, "aeif_cond_exp": 2, "aeif_cond_beta": 3, "spike_generator": 4,
           "parrot_neuron": 5}
 PARAMS = {"tau_m": 0, "C_m": 1, "E_L": 2, "V_th": 3, "V_reset": 4, "t_ref": 5, "g_L": 6, "Delta_T": 7,
@@ -33,6 +33,7 @@ F_NO_SPIKE_RECORD = 1
 F_DELIVERY_DIRECT = 2
 F_DELIVERY_BINNED = 4
 DELIVERY = {"auto": 0, "direct": F_DELIVERY_DIRECT, "binned": F_DELIVERY_BINNED}
+STDP_DEFAULTS = dict(tau_plus=20.0, tau_minus=20.0, lambda_=0.01, alpha=1.0, mu_plus=1, mu_minus=1, w_max=100.0)
 
 
 class SnnError(RuntimeError):
@@ -65,6 +66,21 @@ class Counters(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class JobInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("attempts", C.c_uint32), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double), ("device_bytes_peak", C.c_uint64), ("error", C.c_char * 200)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("budget", C.c_uint64), ("in_use", C.c_uint64), ("peak", C.c_uint64), ("queued", C.c_uint32),
+                ("running", C.c_uint32), ("done", C.c_uint64), ("failed", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
 # function name -> (restype, argtypes) as declared in include/snn.h
 _P = C.c_void_p
 _SIGS = {
@@ -73,7 +89,9 @@ _SIGS = {
     "snn_last_error": (C.c_char_p, [_P]),
     "snn_create": (C.c_int32, [_P, C.c_int32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
     "snn_begin_instance": (C.c_int32, [_P, C.c_uint64, C.POINTER(C.c_uint32)]),
-    "snn_set_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
+    "snn_set_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.POINTER(C.c_double), C.c_size_t]),
+    "snn_param_distribution": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_int32, C.c_double,
+                                           C.c_double, C.c_double, C.c_double, C.c_uint32]),
     "snn_set_port_param": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32, C.c_double]),
     "snn_connect_fixed_indegree": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                                C.c_double, C.c_int32, C.c_double, C.c_double, C.c_uint32]),
@@ -92,6 +110,9 @@ _SIGS = {
     "snn_weight_distribution": (C.c_int32, [_P, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
                                             C.c_uint32]),
     "snn_list_weights": (C.c_int32, [_P, C.POINTER(C.c_double), C.c_size_t]),
+    "snn_stdp": (C.c_int32, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                             C.c_double]),
+    "snn_get_weights": (C.c_int32, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
     "snn_state_distribution": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_uint32, C.c_int32,
                                            C.c_double, C.c_double, C.c_double, C.c_double, C.c_uint32]),
     "snn_poisson": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_double, C.c_uint32, C.c_double, C.c_uint32]),
@@ -99,6 +120,7 @@ _SIGS = {
                                   C.c_size_t]),
     "snn_get_state": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.c_int32, C.c_uint32, C.POINTER(C.c_double)]),
     "snn_build": (C.c_int32, [_P]),
+    "snn_release": (C.c_int32, [_P]),
     "snn_simulate": (C.c_int32, [_P, C.c_double]),
     "snn_simulate_steps": (C.c_int32, [_P, C.c_uint64]),
     "snn_get_spikes": (C.c_int32, [_P, C.c_uint64, C.c_uint64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint32),
@@ -109,6 +131,13 @@ _SIGS = {
     "snn_get_shift": (C.c_int32, [_P, C.c_uint32, C.c_uint32, C.POINTER(C.c_int32)]),
     "snn_poisson_counts": (C.c_int32, [_P, C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32)]),
     "snn_profile_steps": (C.c_int32, [_P, C.c_uint64, C.POINTER(C.c_double)]),
+    "snn_server_create": (C.c_int32, [C.c_size_t, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "snn_server_destroy": (None, [_P]),
+    "snn_server_submit": (C.c_int32, [_P, _P, C.c_uint64, C.POINTER(C.c_uint64)]),
+    "snn_server_poll": (C.c_int32, [_P, C.c_uint64, C.POINTER(C.c_int32)]),
+    "snn_server_wait": (C.c_int32, [_P, C.c_uint64, C.c_double]),
+    "snn_server_result": (C.c_int32, [_P, C.c_uint64, C.POINTER(C.c_void_p), C.POINTER(JobInfo)]),
+    "snn_server_get_stats": (C.c_int32, [_P, C.POINTER(ServerStats)]),
     "snn_export_synapses": (C.c_int32, [_P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                         C.POINTER(C.c_uint32), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
 }
@@ -221,12 +250,18 @@ class Net:
                 t = np.ascontiguousarray(times, dtype=np.float64)
                 self._check(self.L.snn_set_spike_times(self.h, first.value + j, _ptr(t, C.c_double), len(t)))
             for k, v in p["params"].items():
-                if k in PARAMS:
-                    self._check(self.L.snn_set_param(self.h, first.value, p["n"], PARAMS[k], float(v)))
+                if k in PARAMS:  # a scalar for the population, or one value per neuron
+                    x = np.ascontiguousarray(np.atleast_1d(np.asarray(v, dtype=np.float64)))
+                    self._check(self.L.snn_set_param(self.h, first.value, p["n"], PARAMS[k], _ptr(x, C.c_double),
+                                                     len(x)))
                 elif k in PORT_PARAMS:
                     for port, x in enumerate(v[: p["ports"]]):
                         self._check(self.L.snn_set_port_param(self.h, first.value, p["n"], port,
                                                               PORT_PARAMS[k], float(x)))
+        for p in spec["populations"]:  # model parameters drawn per neuron: {"V_th": {...}, ...}
+            t0, tn = ranges[p["name"]]
+            for k, wd in (p.get("param_dists") or {}).items():
+                self._check(self.L.snn_param_distribution(self.h, t0, tn, PARAMS[k], *self._dist_args(wd, 1024)))
         for pr in spec["projections"]:
             if pr.get("rule") == "list":  # user-defined: gids counted from the specification's first neuron
                 src = np.ascontiguousarray(np.asarray(pr["src_gids"], dtype=np.int64) + first_gid, dtype=np.uint32)
@@ -237,6 +272,7 @@ class Net:
                 if pr.get("weights") is not None:  # one weight per listed connection
                     w = np.ascontiguousarray(pr["weights"], dtype=np.float64)
                     self._check(self.L.snn_list_weights(self.h, _ptr(w, C.c_double), len(w)))
+                self._stdp(pr)
                 continue
             s0, sn = ranges[pr["src"]]
             t0, tn = ranges[pr["tgt"]]
@@ -254,6 +290,7 @@ class Net:
                     args = (WEIGHT_DISTS["normal"], m, sd, float(wd.get("low", m - 4 * sd)),
                             float(wd.get("high", m + 4 * sd)), L)
                 self._check(self.L.snn_weight_distribution(self.h, *args))
+            self._stdp(pr)
         for q in spec.get("poisson", []):
             t0, tn = ranges[q["tgt"]]
             self._check(self.L.snn_poisson(self.h, t0, tn, float(q["rate"]), int(q["n_inputs"]),
@@ -283,6 +320,28 @@ class Net:
                             float(wd.get("high", m + 4 * sd)), L)
                 self._check(self.L.snn_state_distribution(self.h, t0, tn, STATE[var], int(wd.get("port", 0)), *args))
         return dict(ranges=ranges, first=first_gid, n=self.N - first_gid)
+
+    def _stdp(self, pr: dict):
+        """Nearest-neighbour STDP of the projection just created, from its "stdp"
+        entry: tau_plus, tau_minus (ms), lambda, alpha, mu_plus, mu_minus (0
+        additive, 1 multiplicative) and w_max, NEST-like defaults."""
+        sd = pr.get("stdp")
+        if sd is None:
+            return
+        v = dict(STDP_DEFAULTS)
+        v.update({("lambda_" if k == "lambda" else k): x for k, x in sd.items()})
+        self._check(self.L.snn_stdp(self.h, float(v["tau_plus"]), float(v["tau_minus"]), float(v["lambda_"]),
+                                    float(v["alpha"]), int(v["mu_plus"]), int(v["mu_minus"]), float(v["w_max"])))
+
+    @staticmethod
+    def _dist_args(wd: dict, default_levels: int) -> tuple:
+        """(kind, a, b, lo, hi, levels) of a distribution: uniform on [low, high), or
+        normal(mean, sd) truncated to [low, high] (default mean -+ 4 sd)."""
+        L = int(wd.get("levels", default_levels))
+        if wd["kind"] == "uniform":
+            return (WEIGHT_DISTS["uniform"], float(wd["low"]), float(wd["high"]), 0.0, 0.0, L)
+        m, sd = float(wd["mean"]), float(wd["sd"])
+        return (WEIGHT_DISTS["normal"], m, sd, float(wd.get("low", m - 4 * sd)), float(wd.get("high", m + 4 * sd)), L)
 
     def _check(self, rc, h=-1):
         if rc != SNN_OK:
@@ -397,6 +456,14 @@ class Net:
         out = np.zeros(n, dtype=np.uint32)
         self._check(self.L.snn_poisson_counts(self.h, step, first, n, _ptr(out, C.c_uint32)))
         return out
+
+    def weights(self) -> np.ndarray:
+        """Current fixed-point weight of every synapse, canonical order."""
+        n = C.c_size_t(0)
+        self._check(self.L.snn_get_weights(self.h, None, C.byref(n)))
+        wq = np.zeros(n.value, np.int64)
+        self._check(self.L.snn_get_weights(self.h, _ptr(wq, C.c_int64), C.byref(n)))
+        return wq
 
     def synapses(self) -> dict:
         n = C.c_size_t(0)
