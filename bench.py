@@ -148,7 +148,13 @@ def parse():
                     help="microcircuit: draw every weight from a normal of this relative deviation (32 levels)")
     ap.add_argument("--requests", type=int, default=60, help="serve: requests in the arrival trace")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
-    ap.add_argument("--slots", type=int, default=8, help="serve: requests in flight at once")
+    ap.add_argument("--slots", type=int, default=16, help="serve: requests in flight at once")
+    ap.add_argument("--serve-delivery-blocks", type=int, default=64,
+                    help="serve: delivery blocks of each served network (few, so that concurrent networks' "
+                         "kernels find free slots)")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="serve: hardware queues HIP opens for the process (GPU_MAX_HW_QUEUES, at most 32; "
+                         "0: HIP's default), so that that many request streams can run kernels at once")
     ap.add_argument("--workload", choices=["microcircuit", "adex", "alpha", "alpha_scan", "sweep", "serve"],
                     default="microcircuit",
                     help="microcircuit (default line); adex: 1e6 AdEx neurons, in-degree 1000, exponential "
@@ -223,6 +229,8 @@ def copy_calibration(mib: int):
 
 def main():
     args = parse()
+    if args.workload == "serve" and args.hw_queues:  # before anything initialises HIP
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, args.hw_queues)))
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the engine has no multi-GPU path)", file=sys.stderr)
@@ -501,7 +509,8 @@ def bench_serve(args):
     out = {}
     for name, slots in (("served", args.slots), ("fifo", 1)):
         log(f"serving {len(trace)} requests, {name} ({slots} slots)")
-        rep = V.Server(budget_bytes=budget, slots=slots, log=log, digest_ids=set(check)).serve(trace)
+        rep = V.Server(budget_bytes=budget, slots=slots, log=log, digest_ids=set(check),
+                       net_kw=dict(delivery_blocks=args.serve_delivery_blocks)).serve(trace)
         lat = rep.latencies()
         failed = [r.rid for r in rep.results if r.status != 0]
         if failed:
@@ -523,7 +532,8 @@ def bench_serve(args):
            "p50_latency_s": out["served"]["p50_latency_s"], "p99_latency_s": out["served"]["p99_latency_s"],
            "served": out["served"], "fifo": out["fifo"],
            "throughput_vs_fifo": out["served"]["requests_per_s"] / out["fifo"]["requests_per_s"],
-           "identical_alone_and_served": same,
+           "identical_alone_and_served": same, "delivery_blocks_per_request": args.serve_delivery_blocks,
+           "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "HIP default"),
            "config": {"workload": f"serving trace: {len(trace)} requests, Poisson arrivals at {args.rate:g}/s, "
                                   "alternately microcircuit stand-in at scale U[0.1,1] and balanced AdEx with "
                                   "N ~ U[10k,200k], K = 1000, each for U[0.1,2] s of biological time",

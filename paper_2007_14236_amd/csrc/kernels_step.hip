@@ -420,7 +420,7 @@ struct TileLds {
   // AdEx work queue: neurons at or above V_T + 4 Delta_T (about to spike: a
   // spike step takes ~100 substeps) first, from a short list, then the others
   // in index order
-  uint32_t next, hq_next, hq_n;
+  uint32_t next, hq_next, hq_next2, hq_n;
   uint16_t hq[kHotCap];
   uint32_t hot[kTileAccWords / 32];
 };
@@ -1039,7 +1039,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     sl.wp[c] = (uint8_t)nd.cls_port[c];
   }
   for (uint32_t j = threadIdx.x; j < nt * PP; j += kB) sl.u.acc[j] = 0;
-  if (threadIdx.x == 0) { sl.next = 0; sl.hq_next = 0; sl.hq_n = 0; }
+  if (threadIdx.x == 0) { sl.next = 0; sl.hq_next = 0; sl.hq_next2 = 0; sl.hq_n = 0; }
   const size_t ti = (size_t)buf * nd.n_tiles + t;
   const uint32_t cnt = min(nd.bin_cnt[ti], nd.bin_cap[t]);
   const uint32_t ovf = nd.ovf_flag[ti];
@@ -1100,15 +1100,28 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
       }
     }
     __syncthreads();
+    // the first 64 hot neurons go to one wave, a different one in co-resident
+    // blocks (dispatch places blocks b, b + 256, b + 512 on one CU), so that
+    // the long RK45 chains do not share a SIMD; further hot neurons to any wave
+    const uint32_t wv_hot = (blockIdx.x >> 8) & 3u;
+    const bool hot_wave = (threadIdx.x >> 6) == wv_hot;
     auto claim = [&]() -> uint32_t {
-      const uint32_t h = atomicAdd(&sl.hq_next, 1u);
-      if (h < min(sl.hq_n, kHotCap)) return sl.hq[h];
+      const uint32_t nh = min(sl.hq_n, kHotCap);
+      if (hot_wave) {
+        const uint32_t h = atomicAdd(&sl.hq_next, 1u);
+        if (h < min(nh, 64u)) return sl.hq[h];
+      }
+      if (nh > 64u) {
+        const uint32_t h = 64u + atomicAdd(&sl.hq_next2, 1u);
+        if (h < nh) return sl.hq[h];
+      }
       for (;;) {
         const uint32_t c = atomicAdd(&sl.next, 1u);
         if (c >= nt) return nt;
         if (!((sl.hot[c >> 5] >> (c & 31)) & 1u)) return c;
       }
     };
+    if (hot_wave) __builtin_amdgcn_s_setprio(2);  // the long chains issue first on their SIMD
     uint32_t loc = claim(), nloc = nt;
     AdexItem<P, kAd == 2> w, nx;
     if (loc < nt) {
@@ -1127,6 +1140,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
         }
       }
     }
+    if (hot_wave) __builtin_amdgcn_s_setprio(0);
   } else {
     for (uint32_t loc = threadIdx.x; loc < nt; loc += kB) {
       int64_t a[kMaxPorts];

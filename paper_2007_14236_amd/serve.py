@@ -108,9 +108,9 @@ def digest_of(net: "S.Net", steps: int) -> tuple:
     return len(st), hashlib.sha256(raster_records(st, gid, m)).hexdigest()
 
 
-def run_alone(req: Request) -> str:
+def run_alone(req: Request, **net_kw) -> str:
     """Digest of the request's raster simulated as the only network."""
-    net = S.Net(req.spec)
+    net = S.Net(req.spec, **net_kw)
     try:
         net.simulate(req.steps)
         return digest_of(net, req.steps)[1]
@@ -123,7 +123,8 @@ class Server:
     device memory, `slots` requests in flight at most."""
 
     def __init__(self, budget_bytes: int = 200 << 30, slots: int = 4, log=None, digest_ids=None,
-                 keep_nets: bool = False):
+                 keep_nets: bool = False, net_kw: dict | None = None):
+        self.net_kw = dict(net_kw or {})  # configuration of every served network (e.g. delivery_blocks)
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.log = log
@@ -148,7 +149,7 @@ class Server:
                 now = time.perf_counter() - t0
                 while i < len(trace) and trace[i].arrival_s <= now:
                     r = trace[i]
-                    net = S.Net(r.spec, build=False)
+                    net = S.Net(r.spec, build=False, **self.net_kw)
                     ticket = C.c_uint64()
                     rc = L.snn_server_submit(h, net.h, r.steps, C.byref(ticket))
                     if rc != 0:
