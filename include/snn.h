@@ -168,6 +168,9 @@ typedef struct snn_counters {
   uint32_t tile_neurons;   /* binned delivery: neurons per target tile        */
   uint32_t delivery_blocks; /* blocks delivering delays >= 2                  */
   uint32_t pad;
+  double last_call_device_ms; /* device time of the last snn_simulate_steps call,
+                                 HIP events on the library's stream around its
+                                 graph launches (kernels and the gaps between) */
 } snn_counters;
 
 /* ---- lifecycle ---------------------------------------------------------- */

@@ -200,6 +200,8 @@ struct snn_net {
   hipStream_t stream = nullptr;
   int device = 0;  // the device current at creation: the stream's and every allocation's
   hipEvent_t ev_user = nullptr;
+  hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // timing: first and last launch of a simulate call
+  double last_dev_ms = 0.0;                      // device time between them in the last call
   std::string err;
   bool built = false;
 
@@ -552,7 +554,8 @@ snn_status snn_create_net(const snn_config* cfg, const snn_device* dev, snn_net*
     (void)input_workspace(net->device, true, &ws);  // a failure is reported by that entry point
   }
   if (hipStreamCreateWithFlags(&net->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&net->ev_user, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&net->ev_user, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&net->ev_t0) != hipSuccess || hipEventCreate(&net->ev_t1) != hipSuccess) {
     delete net;
     return SNN_E_DEVICE;
   }
@@ -571,6 +574,8 @@ void snn_destroy_net(snn_net* net) {
   if (net->pin_ctrl) (void)hipHostFree(net->pin_ctrl);
   if (net->ev_drain) (void)hipEventDestroy(net->ev_drain);
   if (net->ev_user) (void)hipEventDestroy(net->ev_user);
+  if (net->ev_t0) (void)hipEventDestroy(net->ev_t0);
+  if (net->ev_t1) (void)hipEventDestroy(net->ev_t1);
   if (net->stream) (void)hipStreamDestroy(net->stream);
   delete net;
 }
@@ -1983,6 +1988,7 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
   snn_status st = enter(net);
   if (st) return st;
   const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(net, hipEventRecord(net->ev_t0, net->stream));
   uint64_t left = steps;
   while (left > 0) {
     const uint64_t from = net->cur_step;
@@ -2011,8 +2017,13 @@ snn_status snn_simulate_steps(snn_net* net, uint64_t steps) {
   // One copy and one wait end the call: the device flags.  The raster of the
   // last steps stays on the device (its ring holds them) until it is read or
   // the next call's drain takes it.
+  HIPCHK(net, hipEventRecord(net->ev_t1, net->stream));
   HIPCHK(net, hipMemcpyAsync(net->pin_ctrl, net->nd.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, net->stream));
   HIPCHK(net, hipStreamSynchronize(net->stream));
+  {
+    float ms = 0.f;
+    net->last_dev_ms = (hipEventElapsedTime(&ms, net->ev_t0, net->ev_t1) == hipSuccess) ? (double)ms : 0.0;
+  }
   net->sim_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   const uint32_t flags = net->pin_ctrl->overflow;
   if (flags) return fail(net, SNN_E_OVERFLOW, "device range check failed (flags 0x%x)", flags);
@@ -2092,6 +2103,7 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   out->n_neurons = net->N;
   out->build_ms = net->build_ms;
   out->simulate_ms = net->sim_ms;
+  out->last_call_device_ms = net->last_dev_ms;
   if (!net->built) return SNN_OK;
   snn_status st = enter(net);
   if (st) return st;
