@@ -168,7 +168,7 @@ __device__ __forceinline__ bool lif_exp_step(const PopDev& pp, const LifK& k, fl
 // generic pointer that the compiler would otherwise reload every substep).
 template <int P, bool kBeta>
 struct AdexPar {
-  float V_peak, g_L, gLDT, V_T, k_exp, E_L, inv_C, a, inv_tau_w, b, V_r;
+  float V_peak, g_L, gLDT_C, V_T, k_exp, E_L, inv_C, a, inv_tau_w, b, V_r;
   float dt, hmin, inv_eps;
   float E_rev[P], inv_tau_syn[P];
   float inv_tau_rise[kBeta ? P : 1];
@@ -184,7 +184,7 @@ constexpr int kAdexVars = kBeta ? 2 + 2 * P : 2 + P;
 template <int P, bool kBeta, class Src>
 __device__ __forceinline__ void adex_scalars(AdexPar<P, kBeta>& q, const Src& c, float dt) {
   q.V_peak = c.V_peak; q.g_L = c.g_L; q.V_T = c.V_T;
-  q.gLDT = c.g_L * c.Delta_T;
+  q.gLDT_C = c.g_L * c.Delta_T * c.inv_C;
   q.k_exp = c.inv_Delta_T * 1.4426950408889634f;  // exp(x / Delta_T) = 2^(x k_exp)
   q.E_L = c.E_L; q.inv_C = c.inv_C; q.a = c.a; q.inv_tau_w = c.inv_tau_w; q.b = c.b; q.V_r = c.V_r;
   // smallest substep: the configured floor, but never below 2^-22 dt so that
@@ -221,12 +221,16 @@ template <int P, bool kBeta>
 __device__ __forceinline__ void adex_rhs(const AdexPar<P, kBeta>& pp, float Ie, const float* y, float* dy) {
   const float V = y[0], w = y[1];
   const float Vc = fminf(V, pp.V_peak);
-  float isyn = 0.f;
+  const float d = V - pp.E_L;
+  // the exponential is the longest chain: the other currents are summed beside
+  // it and it enters last
+  const float ex = __builtin_amdgcn_exp2f((Vc - pp.V_T) * pp.k_exp);
+  float cur = Ie - w;
 #pragma unroll
-  for (int p = 0; p < P; ++p) isyn = __builtin_fmaf(y[2 + p], V - pp.E_rev[p], isyn);
-  const float ex = pp.gLDT * __builtin_amdgcn_exp2f((Vc - pp.V_T) * pp.k_exp);
-  dy[0] = (__builtin_fmaf(-pp.g_L, V - pp.E_L, ex) - isyn - w + Ie) * pp.inv_C;
-  dy[1] = __builtin_fmaf(pp.a, V - pp.E_L, -w) * pp.inv_tau_w;
+  for (int p = 0; p < P; ++p) cur = __builtin_fmaf(-y[2 + p], V - pp.E_rev[p], cur);
+  cur = __builtin_fmaf(-pp.g_L, d, cur);
+  dy[0] = __builtin_fmaf(pp.gLDT_C, ex, cur * pp.inv_C);
+  dy[1] = __builtin_fmaf(pp.a, d, -w) * pp.inv_tau_w;
   if constexpr (kBeta) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -246,55 +250,57 @@ __device__ __forceinline__ void adex_rhs(const AdexPar<P, kBeta>& pp, float Ie, 
 // 0.9 e^-1/5 (<= 5x) on success; the last substep lands on the step end.  A
 // reset (V >= V_peak) is applied after every accepted substep.  t is the time
 // reached inside the step, it the attempts so far, mult the resets.  Returns
-// true when the step is complete (t = dt, or the attempt cap reached).  The
-// stage sums are fma chains; the error ratio uses the hardware reciprocal (it
-// only steers the step size).
+// true when the step is complete (t = dt, or the attempt cap reached).  Each
+// stage state is y plus one fma per earlier stage (h folded into the
+// coefficients); the error ratio uses the hardware reciprocal (it only steers
+// the step size).
 template <int P, bool kBeta>
 __device__ __forceinline__ bool adex_substep(const AdexPar<P, kBeta>& pp, float* y, float& h, float& t, uint32_t& it,
                                              uint32_t& mult, float Ie, uint32_t& nacc, uint32_t& nrej,
                                              bool& capped) {
   constexpr int NV = kAdexVars<P, kBeta>;
   const float dt = pp.dt;
-  const float c21 = 1.f / 5.f;
-  const float c31 = 3.f / 40.f, c32 = 9.f / 40.f;
-  const float c41 = 3.f / 10.f, c42 = -9.f / 10.f, c43 = 6.f / 5.f;
-  const float c51 = -11.f / 54.f, c52 = 5.f / 2.f, c53 = -70.f / 27.f, c54 = 35.f / 27.f;
-  const float c61 = 1631.f / 55296.f, c62 = 175.f / 512.f, c63 = 575.f / 13824.f, c64 = 44275.f / 110592.f,
-              c65 = 253.f / 4096.f;
-  const float b1 = 37.f / 378.f, b3 = 250.f / 621.f, b4 = 125.f / 594.f, b6 = 512.f / 1771.f;
-  // error weights: fifth-order minus embedded fourth-order weights
-  const float e1 = (float)(37.0 / 378.0 - 2825.0 / 27648.0), e3 = (float)(250.0 / 621.0 - 18575.0 / 48384.0),
-              e4 = (float)(125.0 / 594.0 - 13525.0 / 55296.0), e5 = (float)(-277.0 / 14336.0),
-              e6 = (float)(512.0 / 1771.0 - 0.25);
   const float errcon = 1.89e-4f;  // (5 / 0.9)^-5
   const float hmin = pp.hmin;
   if (++it > kRkMaxIter) { capped = true; return true; }
   bool last = false;
   if (h >= dt - t) { h = dt - t; last = true; }
+  // stage coefficients times h: each stage state is y plus one fma per
+  // earlier stage, the newest last
+  const float a21 = h * (1.f / 5.f);
+  const float a31 = h * (3.f / 40.f), a32 = h * (9.f / 40.f);
+  const float a41 = h * (3.f / 10.f), a42 = h * (-9.f / 10.f), a43 = h * (6.f / 5.f);
+  const float a51 = h * (-11.f / 54.f), a52 = h * (5.f / 2.f), a53 = h * (-70.f / 27.f), a54 = h * (35.f / 27.f);
+  const float a61 = h * (1631.f / 55296.f), a62 = h * (175.f / 512.f), a63 = h * (575.f / 13824.f),
+              a64 = h * (44275.f / 110592.f), a65 = h * (253.f / 4096.f);
+  const float b1 = 37.f / 378.f, b3 = 250.f / 621.f, b4 = 125.f / 594.f, b6 = 512.f / 1771.f;
+  // error weights: fifth-order minus embedded fourth-order weights
+  const float e1 = (float)(37.0 / 378.0 - 2825.0 / 27648.0), e3 = (float)(250.0 / 621.0 - 18575.0 / 48384.0),
+              e4 = (float)(125.0 / 594.0 - 13525.0 / 55296.0), e5 = (float)(-277.0 / 14336.0),
+              e6 = (float)(512.0 / 1771.0 - 0.25);
   float k1[NV], k2[NV], k3[NV], k4[NV], k5[NV], k6[NV], yt[NV];
   adex_rhs<P, kBeta>(pp, Ie, y, k1);
 #pragma unroll
-  for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(h, c21 * k1[i], y[i]);
+  for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(a21, k1[i], y[i]);
   adex_rhs<P, kBeta>(pp, Ie, yt, k2);
 #pragma unroll
-  for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(h, __builtin_fmaf(c32, k2[i], c31 * k1[i]), y[i]);
+  for (int i = 0; i < NV; ++i) yt[i] = __builtin_fmaf(a32, k2[i], __builtin_fmaf(a31, k1[i], y[i]));
   adex_rhs<P, kBeta>(pp, Ie, yt, k3);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
-    yt[i] = __builtin_fmaf(h, __builtin_fmaf(c43, k3[i], __builtin_fmaf(c42, k2[i], c41 * k1[i])), y[i]);
+    yt[i] = __builtin_fmaf(a43, k3[i], __builtin_fmaf(a42, k2[i], __builtin_fmaf(a41, k1[i], y[i])));
   adex_rhs<P, kBeta>(pp, Ie, yt, k4);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
-    yt[i] = __builtin_fmaf(
-        h, __builtin_fmaf(c54, k4[i], __builtin_fmaf(c53, k3[i], __builtin_fmaf(c52, k2[i], c51 * k1[i]))), y[i]);
+    yt[i] = __builtin_fmaf(a54, k4[i],
+                           __builtin_fmaf(a53, k3[i], __builtin_fmaf(a52, k2[i], __builtin_fmaf(a51, k1[i], y[i]))));
   adex_rhs<P, kBeta>(pp, Ie, yt, k5);
 #pragma unroll
   for (int i = 0; i < NV; ++i)
     yt[i] = __builtin_fmaf(
-        h,
-        __builtin_fmaf(c65, k5[i],
-                       __builtin_fmaf(c64, k4[i], __builtin_fmaf(c63, k3[i], __builtin_fmaf(c62, k2[i], c61 * k1[i])))),
-        y[i]);
+        a65, k5[i],
+        __builtin_fmaf(a64, k4[i],
+                       __builtin_fmaf(a63, k3[i], __builtin_fmaf(a62, k2[i], __builtin_fmaf(a61, k1[i], y[i])))));
   adex_rhs<P, kBeta>(pp, Ie, yt, k6);
   float errmax = 0.f;
   float y5[NV];
@@ -305,7 +311,7 @@ __device__ __forceinline__ bool adex_substep(const AdexPar<P, kBeta>& pp, float*
     const float err =
         h * __builtin_fmaf(e6, k6[i],
                            __builtin_fmaf(e5, k5[i], __builtin_fmaf(e4, k4[i], __builtin_fmaf(e3, k3[i], e1 * k1[i]))));
-    const float scale = fabsf(y[i]) + fabsf(h * k1[i]) + 1.f;
+    const float scale = __builtin_fmaf(h, fabsf(k1[i]), fabsf(y[i])) + 1.f;  // h > 0
     errmax = fmaxf(errmax, fabsf(err) * __builtin_amdgcn_rcpf(scale));
   }
   errmax = errmax * pp.inv_eps;
@@ -420,7 +426,7 @@ struct TileLds {
   // AdEx work queue: neurons at or above V_T + 4 Delta_T (about to spike: a
   // spike step takes ~100 substeps) first, from a short list, then the others
   // in index order
-  uint32_t next, hq_next, hq_next2, hq_n;
+  uint32_t next, hq_next2, hq_n;
   uint16_t hq[kHotCap];
   uint32_t hot[kTileAccWords / 32];
 };
@@ -958,13 +964,12 @@ __device__ void update_block(const NetDev& nd, uint64_t n, uint32_t blk, UpdLds&
   } else {
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {  // no-return atomics: the block need not wait for a read
     uint64_t* st = nd.blk_stats + (size_t)kBlkStats * blk;
-    st[0] += sa;
-    st[1] += sr;
-    st[2] += btot;
-    st[3] += pairs;
-    st[4] += events;
+    const uint64_t v[kBlkStats] = {sa, sr, btot, pairs, events};
+#pragma unroll
+    for (int k = 0; k < kBlkStats; ++k)
+      if (v[k]) __hip_atomic_fetch_add(&st[k], v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (capped) atomicOr(&nd.ctrl->overflow, 2u);
   if (mover) atomicOr(&nd.ctrl->overflow, 1u);
@@ -1031,6 +1036,9 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
   const uint32_t PP = nd.P, tsh = nd.tile_shift, buf = inbuf(n);
   const uint32_t first = t << tsh;
   const uint32_t nt = min(1u << tsh, nd.N - first);
+  // first raster position of this step's spikes: the previous step's books are
+  // final, so it is read now rather than after the update
+  const uint64_t pos_n = step_pos(nd, n);
   const PopDev* pops;
   const uint64_t* pthr;
   const uint32_t npop = load_tile_tables(nd, first, nt, sl.spops, sl.sthr, pops, pthr);
@@ -1039,7 +1047,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     sl.wp[c] = (uint8_t)nd.cls_port[c];
   }
   for (uint32_t j = threadIdx.x; j < nt * PP; j += kB) sl.u.acc[j] = 0;
-  if (threadIdx.x == 0) { sl.next = 0; sl.hq_next = 0; sl.hq_next2 = 0; sl.hq_n = 0; }
+  if (threadIdx.x == 0) { sl.next = 0; sl.hq_next2 = 0; sl.hq_n = 0; }
   const size_t ti = (size_t)buf * nd.n_tiles + t;
   const uint32_t cnt = min(nd.bin_cnt[ti], nd.bin_cap[t]);
   const uint32_t ovf = nd.ovf_flag[ti];
@@ -1100,17 +1108,30 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
       }
     }
     __syncthreads();
-    // the first 64 hot neurons go to one wave, a different one in co-resident
-    // blocks (dispatch places blocks b, b + 256, b + 512 on one CU), so that
-    // the long RK45 chains do not share a SIMD; further hot neurons to any wave
-    const uint32_t wv_hot = (blockIdx.x >> 8) & 3u;
-    const bool hot_wave = (threadIdx.x >> 6) == wv_hot;
+    // The first 64 hot neurons go to one wave (a different one in blocks b,
+    // b + 256, b + 512, which dispatch places on one CU), lane by lane, and
+    // that wave runs only their substeps, at raised priority: a lane whose
+    // neuron is done idles, since refilling it would put neuron loads and
+    // Poisson draws between the substeps of the long chains.  Then the wave
+    // joins the others' queue.  Further hot neurons go to any wave first.
+    if ((threadIdx.x >> 6) == ((blockIdx.x >> 8) & 3u)) {
+      const uint32_t nh = min(min(sl.hq_n, kHotCap), 64u);
+      if (nh) {  // wave-uniform
+        __builtin_amdgcn_s_setprio(2);
+        uint32_t hl = ((threadIdx.x & 63u) < nh) ? (uint32_t)sl.hq[threadIdx.x & 63u] : nt;
+        AdexItem<P, kAd == 2> hw;
+        if (hl < nt) fetch(hl, hw);
+        while (hl < nt) {
+          if (adex_substep<P, kAd == 2>(hw.q, hw.y, hw.h, hw.t, hw.it, hw.mult, hw.Ie, nacc, nrej, capped)) {
+            sl.c.mk[hl] = (uint8_t)adex_store<P, kAd == 2>(nd, first + hl, hw, mover);
+            hl = nt;
+          }
+        }
+        __builtin_amdgcn_s_setprio(0);
+      }
+    }
     auto claim = [&]() -> uint32_t {
       const uint32_t nh = min(sl.hq_n, kHotCap);
-      if (hot_wave) {
-        const uint32_t h = atomicAdd(&sl.hq_next, 1u);
-        if (h < min(nh, 64u)) return sl.hq[h];
-      }
       if (nh > 64u) {
         const uint32_t h = 64u + atomicAdd(&sl.hq_next2, 1u);
         if (h < nh) return sl.hq[h];
@@ -1121,7 +1142,6 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
         if (!((sl.hot[c >> 5] >> (c & 31)) & 1u)) return c;
       }
     };
-    if (hot_wave) __builtin_amdgcn_s_setprio(2);  // the long chains issue first on their SIMD
     uint32_t loc = claim(), nloc = nt;
     AdexItem<P, kAd == 2> w, nx;
     if (loc < nt) {
@@ -1140,7 +1160,6 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
         }
       }
     }
-    if (hot_wave) __builtin_amdgcn_s_setprio(0);
   } else {
     for (uint32_t loc = threadIdx.x; loc < nt; loc += kB) {
       int64_t a[kMaxPorts];
@@ -1172,7 +1191,6 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
       sl.emit = __hip_atomic_fetch_add(&nd.ring_cnt[n % nd.R], spikes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     dlv_init(nd, sh);
     __syncthreads();
-    const uint64_t pos_n = step_pos(nd, n);
     uint32_t before = 0;  // spikes of the sub-blocks before k
     for (uint32_t k = 0; k < nsub; ++k) {  // block-uniform
       uint32_t woff = 0, ktot = 0;
@@ -1181,6 +1199,7 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
         if (q < wv) woff += sl.wcnt[k][q];
         ktot += sl.wcnt[k][q];
       }
+      if (ktot == 0) continue;  // block-uniform: nothing to emit or select
       const uint32_t loc = k * kB + threadIdx.x;
       const uint32_t m = loc < nt ? sl.c.mk[loc] : 0u;
       const uint64_t bal = __ballot(m != 0);
@@ -1211,13 +1230,12 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     sa = block_sum(nacc, sl.red);
     sr = block_sum(nrej, sl.red);
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {  // no-return atomics: the block need not wait for a read
     uint64_t* st = nd.blk_stats + (size_t)kBlkStats * (first / kB);
-    st[0] += sa;
-    st[1] += sr;
-    st[2] += spikes;
-    st[3] += pairs;
-    st[4] += events;
+    const uint64_t v[kBlkStats] = {sa, sr, (uint64_t)spikes, pairs, events};
+#pragma unroll
+    for (int k = 0; k < kBlkStats; ++k)
+      if (v[k]) __hip_atomic_fetch_add(&st[k], v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (capped) atomicOr(&nd.ctrl->overflow, 2u);
   if (mover) atomicOr(&nd.ctrl->overflow, 1u);
