@@ -382,10 +382,12 @@ struct DirectLds : SelLds {
 
 // binned delivery: events per target tile of the chunk, then each tile's
 // reserved position in its bin
+constexpr int kCidx = 1024;  // coarse index of a chunk's events
 struct BinLds : SelLds {
   uint32_t tcnt[kMaxTiles];   // events per tile, then the write cursor
   uint32_t tbase[kMaxTiles];  // absolute bin index of the reserved range
   uint32_t tavail[kMaxTiles]; // entries of the range inside the bin's capacity
+  uint16_t cidx[kCidx];       // the record holding event m << csh of the chunk
 };
 
 // LDS of a direct-delivery update block
@@ -623,34 +625,90 @@ __device__ __forceinline__ void bin_plastic(const NetDev& nd, uint32_t buf, uint
   nd.ovf_flag[(size_t)buf * nd.n_tiles + tile] = 1u;
 }
 
+constexpr int kLaneRun = 4;  // consecutive events per lane and round of the binned flush
+
+// Coarse index of the chunk's ev events over its np records: cidx[m] = the
+// record holding event m << csh.  Returns csh; ends with a barrier.
+__device__ __forceinline__ uint32_t build_cidx(BinLds& sh, uint32_t np, uint64_t ev) {
+  uint32_t csh = 6;
+  while (ev && ((ev - 1) >> csh) >= (uint64_t)kCidx) ++csh;
+  for (uint32_t i = threadIdx.x; i < np; i += kB) {
+    const uint64_t a = sh.p_st[i], b = a + sh.p_len[i];
+    for (uint64_t m = (a + (1ull << csh) - 1) >> csh; (m << csh) < b; ++m) sh.cidx[m] = (uint16_t)i;
+  }
+  __syncthreads();
+  return csh;
+}
+
+// Events e0 .. e0 + kLaneRun - 1 (those below ev) of a lane, consecutive
+// synapses that mostly share a record: their records r[] and synapse words
+// pl[], all loads issued before any is used.
+__device__ __forceinline__ void lane_gather(const NetDev& nd, const BinLds& sh, uint32_t np, uint64_t ev,
+                                            uint64_t e0, uint32_t csh, uint32_t* r, uint32_t* pl) {
+  uint32_t lo = sel_advance(sh, np, sh.cidx[e0 >> csh], e0);
+  uint64_t nxt = (lo + 1 < np) ? sh.p_st[lo + 1] : ~0ull;
+#pragma unroll
+  for (int q = 0; q < kLaneRun; ++q) {
+    const uint64_t e = e0 + q;
+    if (e < ev) {
+      while (e >= nxt) {
+        ++lo;
+        nxt = (lo + 1 < np) ? sh.p_st[lo + 1] : ~0ull;
+      }
+    }
+    r[q] = lo;
+  }
+#pragma unroll
+  for (int q = 0; q < kLaneRun; ++q) {
+    const uint64_t e = e0 + q;
+    pl[q] = (e < ev) ? nd.payload[sh.p_off[r[q]] + (e - sh.p_st[r[q]])] : 0u;
+  }
+}
+
 // Binned delivery of the chunk: the same flat scan, but each event becomes
 // one 32-bit entry (local target, multiplicity, weight class) in the bin of
-// its target tile in input buffer buf; the tile block of that step
-// sums its bin in LDS.  Two passes over the chunk's synapses: count the
-// events per tile (LDS), reserve each tile's range with one device atomic,
-// then write the entries.  Called by the whole block after a barrier;
-// returns the events delivered and resets the chunk.
+// its target tile in input buffer buf; the tile block of that step sums its
+// bin in LDS.  Two passes over the chunk's synapses: count the events per tile
+// (LDS), reserve each tile's range with one device atomic, then write the
+// entries.  A lane takes kLaneRun consecutive synapses per round (found from
+// a coarse index of the chunk's events), and a run of them onto one tile
+// takes one LDS atomic and consecutive entries.  Called by the whole block
+// after a barrier; returns the events delivered and resets the chunk.
 __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
   // every pair of a binned chunk arrives at the same step (buffer buf)
   const uint32_t np = sh.npair;
   const uint64_t ev = sel_scan(sh);
+  const uint32_t csh = build_cidx(sh, np, ev);
   // target = pl >> cls_bits, tile = target >> tile_shift: two shifts, each
   // below 32 (their sum can exceed 31 when a tile is wider than the gid range)
   const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u;
   const uint32_t tsh = nd.tile_shift, lmask = (1u << tsh) - 1u, ntl = nd.n_tiles;
   const bool plastic = nd.n_rules != 0;
+  constexpr uint32_t kNone = 0xffffffffu;
   bool bad = false;
-  uint32_t lo = 0;
-  for (uint64_t e0 = threadIdx.x; e0 < ev; e0 += kUnroll * kB) {  // independent events per lane and round
-    uint32_t r[kUnroll], pl[kUnroll];
-    sel_gather(nd, sh, np, ev, e0, lo, r, pl);
+  const uint64_t step = (uint64_t)kB * kLaneRun;
+  for (uint64_t b0 = 0; b0 < ev; b0 += step) {
+    const uint64_t e0 = b0 + (uint64_t)threadIdx.x * kLaneRun;
+    if (e0 >= ev) break;
+    uint32_t r[kLaneRun], pl[kLaneRun];
+    lane_gather(nd, sh, np, ev, e0, csh, r, pl);
+    uint32_t tp = kNone, k = 0;
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      if (e0 + (uint64_t)q * kB >= ev) break;
-      const uint32_t t = (pl[q] >> cls_bits) >> tsh;
-      if (t >= ntl) bad = true;
-      else if (!(plastic && nd.cls_rule[pl[q] & cls_mask])) atomicAdd(&sh.tcnt[t], 1u);  // plastic: no bin entry
+    for (int q = 0; q < kLaneRun; ++q) {
+      uint32_t t = kNone;
+      if (e0 + q < ev) {
+        t = (pl[q] >> cls_bits) >> tsh;
+        if (t >= ntl) { bad = true; t = kNone; }
+        else if (plastic && nd.cls_rule[pl[q] & cls_mask]) t = kNone;  // plastic: no bin entry
+      }
+      if (t != tp) {
+        if (k) atomicAdd(&sh.tcnt[tp], k);
+        tp = t;
+        k = 0;
+      }
+      if (t != kNone) ++k;
     }
+    if (k) atomicAdd(&sh.tcnt[tp], k);
   }
   __syncthreads();
   uint32_t* cnt = nd.bin_cnt + (size_t)buf * ntl;
@@ -666,24 +724,50 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
   }
   __syncthreads();
   uint32_t* bins = nd.bins + (size_t)buf * nd.bins_total;
-  lo = 0;
-  for (uint64_t e0 = threadIdx.x; e0 < ev; e0 += kUnroll * kB) {
-    uint32_t r[kUnroll], pl[kUnroll];
-    sel_gather(nd, sh, np, ev, e0, lo, r, pl);
+  for (uint64_t b0 = 0; b0 < ev; b0 += step) {
+    const uint64_t e0 = b0 + (uint64_t)threadIdx.x * kLaneRun;
+    if (e0 >= ev) break;
+    uint32_t r[kLaneRun], pl[kLaneRun], tt[kLaneRun], slot[kLaneRun];
+    lane_gather(nd, sh, np, ev, e0, csh, r, pl);
 #pragma unroll
-    for (int q = 0; q < kUnroll; ++q) {
-      const uint64_t e = e0 + (uint64_t)q * kB;
-      if (e >= ev) break;
-      const uint32_t tgt = pl[q] >> cls_bits, t = tgt >> tsh;
-      if (t >= ntl) continue;
-      if (plastic && nd.cls_rule[pl[q] & cls_mask]) {
-        bin_plastic(nd, buf, sh.p_off[r[q]] + (e - sh.p_st[r[q]]), tgt, pl[q] & cls_mask, sh.p_mult[r[q]], t);
-        continue;
+    for (int q = 0; q < kLaneRun; ++q) {
+      uint32_t t = kNone;
+      if (e0 + q < ev) {
+        t = (pl[q] >> cls_bits) >> tsh;
+        if (t >= ntl) {
+          t = kNone;
+        } else if (plastic && nd.cls_rule[pl[q] & cls_mask]) {
+          bin_plastic(nd, buf, sh.p_off[r[q]] + (e0 + q - sh.p_st[r[q]]), pl[q] >> cls_bits, pl[q] & cls_mask,
+                      sh.p_mult[r[q]], t);
+          t = kNone;
+        }
       }
-      const uint32_t slot = atomicAdd(&sh.tcnt[t], 1u);
-      const uint32_t cls = pl[q] & cls_mask, mult = sh.p_mult[r[q]];
-      if (slot < sh.tavail[t])
-        bins[sh.tbase[t] + slot] = ((tgt & lmask) << kBinLocalShift) | (mult << kBinMultShift) | cls;
+      tt[q] = t;
+    }
+    // a run of consecutive events onto one tile: one LDS atomic, consecutive slots
+#pragma unroll
+    for (int q = 0; q < kLaneRun; ++q) {
+      slot[q] = 0;
+      if (tt[q] == kNone) continue;
+      if (q > 0 && tt[q] == tt[q - 1]) {
+        slot[q] = slot[q - 1] + 1;
+      } else {
+        uint32_t k = 1;
+#pragma unroll
+        for (int j = q + 1; j < kLaneRun; ++j) {
+          if (tt[j] != tt[q]) break;
+          ++k;
+        }
+        slot[q] = atomicAdd(&sh.tcnt[tt[q]], k);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kLaneRun; ++q) {
+      const uint32_t t = tt[q];
+      if (t == kNone) continue;
+      const uint32_t tgt = pl[q] >> cls_bits, cls = pl[q] & cls_mask, mult = sh.p_mult[r[q]];
+      if (slot[q] < sh.tavail[t])
+        bins[sh.tbase[t] + slot[q]] = ((tgt & lmask) << kBinLocalShift) | (mult << kBinMultShift) | cls;
       else
         bin_spill(nd, buf, tgt, cls, mult, t);
     }
