@@ -167,7 +167,10 @@ typedef struct snn_counters {
   uint32_t delivery;       /* 1 direct, 2 binned (after build)                */
   uint32_t tile_neurons;   /* binned delivery: neurons per target tile        */
   uint32_t delivery_blocks; /* blocks delivering delays >= 2                  */
-  uint32_t pad;
+  uint32_t delivery_queue;  /* binned: 1 when the delivery blocks take contiguous
+                               ranges of the step's (spike, delay) items from a
+                               queue (batches of at least 8 instances of at most
+                               32 tiles each), 0 when each takes every G-th item */
   double last_call_device_ms; /* device time of the last snn_simulate_steps call,
                                  HIP events on the library's stream around its
                                  graph launches (kernels and the gaps between) */

@@ -372,6 +372,7 @@ struct SelLds {
   uint64_t seg[66];
   uint32_t slot[66];
   uint32_t npair;
+  uint64_t j0;  // delivery queue: first item of the block's current range
 };
 
 // direct delivery: weight classes cached for the atomic adds
@@ -605,13 +606,12 @@ __device__ uint64_t dlv_flush(const NetDev& nd, DirectLds& sh, uint32_t /*buf: p
 // its (target, port) and the tile flagged, so that the tile block of the next
 // step adds the spill to the bin's sum.
 __device__ __forceinline__ void bin_spill(const NetDev& nd, uint32_t buf, uint32_t tgt, uint32_t cls, uint32_t mult,
-                                       uint32_t tile) {
+                                       uint32_t tile, uint32_t& spills) {
   const int64_t v = nd.cls_wq[cls] * (int64_t)mult;
   __hip_atomic_fetch_add((unsigned long long*)&nd.acc[((size_t)buf * nd.N + tgt) * nd.P + nd.cls_port[cls]],
                          (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   nd.ovf_flag[(size_t)buf * nd.n_tiles + tile] = 1u;
-  __hip_atomic_fetch_add((unsigned long long*)&nd.ctrl->spill_events, 1ull, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+  ++spills;  // counted per lane, added to the step's total once per chunk
 }
 
 // A plastic synapse's event in binned delivery: its weight is read now (the
@@ -724,6 +724,7 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
   }
   __syncthreads();
   uint32_t* bins = nd.bins + (size_t)buf * nd.bins_total;
+  uint32_t spills = 0;
   for (uint64_t b0 = 0; b0 < ev; b0 += step) {
     const uint64_t e0 = b0 + (uint64_t)threadIdx.x * kLaneRun;
     if (e0 >= ev) break;
@@ -769,10 +770,13 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
       if (slot[q] < sh.tavail[t])
         bins[sh.tbase[t] + slot[q]] = ((tgt & lmask) << kBinLocalShift) | (mult << kBinMultShift) | cls;
       else
-        bin_spill(nd, buf, tgt, cls, mult, t);
+        bin_spill(nd, buf, tgt, cls, mult, t, spills);
     }
   }
   if (bad) atomicOr(&nd.ctrl->overflow, 4u);  // a target outside the tiles: reported, not written
+  if (spills)
+    __hip_atomic_fetch_add((unsigned long long*)&nd.ctrl->spill_events, (unsigned long long)spills, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < ntl; t += kB) sh.tcnt[t] = 0;
   if (threadIdx.x == 0) sh.npair = 0;
@@ -953,6 +957,7 @@ __device__ __forceinline__ void step_books(const NetDev& nd, uint64_t n) {
   nd.ring_base[n % nd.R] = pos;
   nd.chunk_base[n & (nd.chunk_ring - 1)] = pos;
   nd.ring_cnt[(n + 1) % nd.R] = 0;
+  nd.ctrl->dlv_next[(n + 1) & 3] = 0;  // the delivery queue of step n + 1 (step n uses slot n & 3)
   // plastic arrivals: this step fills the list of arrival step n + 1; the list
   // of step n was consumed by the plasticity kernel of step n - 1
   if (nd.n_rules) nd.arr_cnt[n & 1] = 0;
@@ -1327,8 +1332,15 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
 
 // Delivery blocks of step n: the input of step n+1 from the spikes of steps
 // n-1 .. n+1-Dmax whose delay d >= 2 expires now, read from their selection
-// records.  Item (spike, d) number e goes to block e mod G, so that every
-// block sees every delay (hits concentrate on the common delays).
+// records.  The items (spike, d) are ordered by delay, then by the spike's
+// position in its step (spikes of one tile lie together).  Two ways to share
+// them among the G blocks:
+//   strided: item e goes to block e mod G, so that every block sees every
+//     delay (hits and group sizes vary with the delay);
+//   queue (binned batches of many small instances): blocks take ranges of
+//     consecutive items from a queue until it is empty, so that a chunk holds
+//     spikes of few instances, whose targets lie in few tiles (longer runs per
+//     tile in the bins), and blocks that start late take less.
 template <class L>
 __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t G, L& sh) {
   const uint32_t R = nd.R, dmax = nd.dmax;
@@ -1350,26 +1362,48 @@ __device__ void deliver_block(const NetDev& nd, uint64_t n, uint32_t b, uint32_t
   const uint64_t items = sh.seg[65];
   const uint32_t b1 = inbuf(n + 1);
   uint64_t pairs = 0, events = 0;
-  const uint64_t mine = (b < items) ? (items - b + G - 1) / G : 0;
-  for (uint64_t j0 = 0; j0 < mine; j0 += kSelChunk) {  // block-uniform
-#pragma unroll
-    for (int q = 0; q < kSelPerThread; ++q) {
-      const uint64_t j = j0 + (uint64_t)q * kB + threadIdx.x;
-      if (j >= mine) continue;
-      const uint64_t e = b + (uint64_t)G * j;
-      uint32_t lo = kDlvMinDelay, hi = 65;  // segment d: seg[d] <= e < seg[d + 1]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (sh.seg[mid] <= e) lo = mid; else hi = mid;
-      }
-      const SpikeRec r = nd.recent[(size_t)sh.slot[lo] * nd.N + (e - sh.seg[lo])];
-      dlv_probe(nd, sh, r.entry, r.grp_ptr, r.mask, lo, b1);
+  auto select = [&](uint64_t e) {
+    uint32_t lo = kDlvMinDelay, hi = 65;  // segment d: seg[d] <= e < seg[d + 1]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (sh.seg[mid] <= e) lo = mid; else hi = mid;
     }
-    __syncthreads();
-    pairs += sh.npair;
-    events += dlv_flush(nd, sh, b1);
+    const SpikeRec r = nd.recent[(size_t)sh.slot[lo] * nd.N + (e - sh.seg[lo])];
+    dlv_probe(nd, sh, r.entry, r.grp_ptr, r.mask, lo, b1);
+  };
+  if (nd.dlv_queue) {
+    const uint64_t share = (items + G - 1) / G;
+    const uint64_t grab = share < 1 ? 1 : (share > (uint64_t)kSelChunk ? (uint64_t)kSelChunk : share);
+    for (;;) {  // block-uniform
+      if (threadIdx.x == 0)
+        sh.j0 = __hip_atomic_fetch_add(&nd.ctrl->dlv_next[n & 3], grab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const uint64_t j0 = sh.j0;
+      if (j0 >= items) break;
+      const uint64_t j1 = (j0 + grab < items) ? j0 + grab : items;
+#pragma unroll
+      for (int q = 0; q < kSelPerThread; ++q) {
+        const uint64_t e = j0 + (uint64_t)q * kB + threadIdx.x;
+        if (e < j1) select(e);
+      }
+      __syncthreads();
+      pairs += sh.npair;
+      events += dlv_flush(nd, sh, b1);  // ends with a barrier: j0 may be rewritten
+    }
+  } else {
+    const uint64_t mine = (b < items) ? (items - b + G - 1) / G : 0;
+    for (uint64_t j0 = 0; j0 < mine; j0 += kSelChunk) {  // block-uniform
+#pragma unroll
+      for (int q = 0; q < kSelPerThread; ++q) {
+        const uint64_t j = j0 + (uint64_t)q * kB + threadIdx.x;
+        if (j < mine) select(b + (uint64_t)G * j);
+      }
+      __syncthreads();
+      pairs += sh.npair;
+      events += dlv_flush(nd, sh, b1);
+    }
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && (pairs || events)) {
     __hip_atomic_fetch_add((unsigned long long*)&nd.sel_stats[2 * b], (unsigned long long)pairs, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add((unsigned long long*)&nd.sel_stats[2 * b + 1], (unsigned long long)events,

@@ -33,6 +33,8 @@ constexpr uint32_t kGraphSteps = 100;
 constexpr int kNumParams = 16;  // SNN_P_TAU_M .. SNN_P_RK_HMIN
 constexpr uint64_t kChunkRing = 4096;  // >= drain interval + graph length
 constexpr uint64_t kBinnedMinSynapses = 500000000;  // default delivery: binned from this size on
+constexpr uint64_t kQueueMinInstances = 8;          // binned batches with at least this many instances ...
+constexpr uint64_t kQueueMaxTilesPerInstance = 32;  // ... of at most this many tiles each use the delivery queue
 
 struct HostPop {
   int32_t model = 0;
@@ -1905,6 +1907,13 @@ snn_status build_impl(snn_net* net) {
       nd.bins = d_bins; nd.bin_cnt = d_bcnt; nd.ovf_flag = d_bovf; nd.bin_off = d_boff; nd.bin_cap = d_bcap;
       nd.n_tiles = (uint32_t)nt; nd.tile_shift = tsh; nd.bins_total = tot;
       net->tile_neurons = T;
+      // a batch of many small instances: consecutive spikes of a step belong to
+      // one instance, whose targets lie in a few tiles, so delivery blocks take
+      // contiguous item ranges from a queue (128 Brunel instances, 733 tiles:
+      // 1.26 -> 1.01 ms per step); a single network keeps the strided share,
+      // which balances delays with different hit rates and group sizes
+      const uint64_t ni = net->insts.size();
+      nd.dlv_queue = (ni >= kQueueMinInstances && nt <= kQueueMaxTilesPerInstance * ni) ? 1u : 0u;
     }
   }
 
@@ -2136,6 +2145,7 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   out->delivery = net->tile_neurons ? 2u : 1u;
   out->tile_neurons = net->tile_neurons;
   out->delivery_blocks = net->nd.sel_grid;
+  out->delivery_queue = net->nd.dlv_queue;
   return leave(net);
 }
 

@@ -133,6 +133,7 @@ struct Ctrl {
   uint32_t overflow;       // sticky flags (bit 0 mult, 1 rk iterations, 2 ranges)
   uint32_t pad;
   uint64_t spill_events;   // binned delivery: events that did not fit their tile's bin
+  uint64_t dlv_next[4];    // delivery queue: items of step n taken so far, slot n % 4
 };
 
 // Nearest-neighbour STDP rule of the plastic synapses of one (projection,
@@ -151,6 +152,7 @@ struct NetDev {
   uint32_t npois, pois_len;    // Poisson threshold tables; entries read at most (the rest are never reached)
   uint32_t R, nblk_upd, sel_grid, pad0;  // R step slots; pad0: bit 0 LIF, bit 1 AdEx, bit 2 beta ports present
   uint32_t n_tiles, tile_shift;  // binned delivery (n_tiles == 0: direct atomics)
+  uint32_t dlv_queue, pad3;      // binned delivery blocks take contiguous item ranges from a queue (batches)
   uint64_t bins_total;           // bin entries per input buffer
   uint64_t log_mask;           // CAP - 1
   uint64_t chunk_ring;         // slots of chunk_base (power of two)

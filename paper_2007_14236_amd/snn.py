@@ -60,7 +60,7 @@ class Counters(C.Structure):
                 ("n_synapses", C.c_uint64), ("n_groups", C.c_uint64), ("device_bytes", C.c_uint64),
                 ("build_ms", C.c_double), ("simulate_ms", C.c_double), ("overflow", C.c_uint32),
                 ("max_delay_used", C.c_uint32), ("spill_events", C.c_uint64), ("delivery", C.c_uint32),
-                ("tile_neurons", C.c_uint32), ("delivery_blocks", C.c_uint32), ("pad", C.c_uint32),
+                ("tile_neurons", C.c_uint32), ("delivery_blocks", C.c_uint32), ("delivery_queue", C.c_uint32),
                 ("last_call_device_ms", C.c_double)]
 
     def as_dict(self):

@@ -125,3 +125,56 @@ def test_binned_tile_too_large_for_ports_is_rejected(snn):
     spec = W.adex_balanced(n=2000, k=200, seed=5)  # two ports: tiles of at most 2048 neurons
     with pytest.raises(snn.SnnError):
         snn.Net(spec, delivery="binned", tile_neurons=4096)
+
+
+def _queue_batch():
+    """Ten small Brunel instances of uneven size (a batch of at least 8
+    instances of at most 32 tiles each: the delivery blocks share the items
+    through the queue), delays up to 2 ms, strong drive."""
+    return [W.brunel_lif(n=300 + 137 * i, k=10 + 3 * i, seed=40 + i, delay=("uniform", 0.1, 2.0), dmax=25,
+                         nu_ext=250.0 + 10 * i) for i in range(10)]
+
+
+@pytest.mark.parametrize("cap", [0, 24])
+def test_batch_delivery_queue_bit_exact(snn, cap):
+    """Binned delivery through the queue (and, with tiny bins, its spill path):
+    every instance's raster and per-step input equal the oracle's."""
+    specs = _queue_batch()
+    steps = 300
+    g = snn.Net(specs, delivery="binned", tile_neurons=256, bin_capacity=cap)
+    c = g.counters()
+    assert c["delivery_queue"] == 1
+    probe = (99, 200)
+    recs = []
+    for sp in specs:
+        o = O.OracleNet(sp, O.FP32SO)
+        rec = o.record_input(steps + 1)
+        o.simulate(steps + 1)
+        st, gid, m = o.spikes()
+        keep = st < steps
+        recs.append(((st[keep], gid[keep], m[keep]), rec))
+    done = 0
+    for n in probe:  # the input of step n + 1 after n + 1 steps
+        g.simulate(n + 1 - done)
+        done = n + 1
+        inp = g.get_input(0)
+        for inst, (_, rec) in zip(g.instances, recs):
+            assert np.array_equal(inp[inst["first"]:inst["first"] + inst["n"]], rec[n + 1][:, 0]), n
+    g.simulate(steps - done)
+    gs, gg, gm = g.spikes()
+    total = 0
+    for inst, ((os_, og, om), _) in zip(g.instances, recs):
+        sel = (gg >= inst["first"]) & (gg < inst["first"] + inst["n"])
+        assert np.array_equal(gs[sel], os_) and np.array_equal(gg[sel] - inst["first"], og)
+        assert np.array_equal(gm[sel], om)
+        total += len(os_)
+    assert total > 1000
+    c = g.counters()
+    assert c["overflow"] == 0
+    if cap:
+        assert c["spill_events"] > 0
+
+
+def test_single_network_keeps_the_strided_share(snn):
+    g = snn.Net(W.brunel_lif(n=3000, k=100, seed=3, nu_ext=250.0), delivery="binned", tile_neurons=256)
+    assert g.counters()["delivery_queue"] == 0
