@@ -316,7 +316,7 @@ __device__ __forceinline__ bool adex_substep(const AdexPar<P, kBeta>& pp, float*
   }
   errmax = errmax * pp.inv_eps;
   if (errmax > 1.f && h > hmin) {
-    const float ht = 0.9f * h * exp2f(-0.25f * __log2f(errmax));
+    const float ht = 0.9f * h * __builtin_amdgcn_exp2f(-0.25f * __builtin_amdgcn_logf(errmax));
     h = fmaxf(ht, 0.1f * h);
     h = fmaxf(h, hmin);
     ++nrej;
@@ -326,7 +326,8 @@ __device__ __forceinline__ bool adex_substep(const AdexPar<P, kBeta>& pp, float*
   t = last ? dt : t + h;
 #pragma unroll
   for (int i = 0; i < NV; ++i) y[i] = y5[i];
-  const float hn = fmaxf((errmax > errcon) ? 0.9f * h * exp2f(-0.2f * __log2f(errmax)) : 5.f * h, hmin);
+  const float hn =
+      fmaxf((errmax > errcon) ? 0.9f * h * __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(errmax)) : 5.f * h, hmin);
   if (y[0] >= pp.V_peak) { y[0] = pp.V_r; y[1] += pp.b; ++mult; }
   h = hn;
   return !(t < dt);
@@ -1150,12 +1151,15 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
     atomicAdd((unsigned long long*)&sl.u.acc[loc * PP + sl.wp[cls]], (unsigned long long)v);
   };
   uint32_t j = threadIdx.x;
-  for (; j + 7 * kB < cnt; j += 8 * kB) {  // eight independent loads in flight per lane
-    uint32_t e[8];
+  // independent loads in flight per lane: 16 (8 with beta ports, whose
+  // integrator leaves fewer registers)
+  constexpr int kBinLoads = (kAd == 2) ? 8 : 16;
+  for (; j + (kBinLoads - 1) * kB < cnt; j += kBinLoads * kB) {
+    uint32_t e[kBinLoads];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) e[q] = bin[j + q * kB];
+    for (int q = 0; q < kBinLoads; ++q) e[q] = bin[j + q * kB];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) add(e[q]);
+    for (int q = 0; q < kBinLoads; ++q) add(e[q]);
   }
   for (; j < cnt; j += kB) add(bin[j]);
   if (bad) atomicOr(&nd.ctrl->overflow, 4u);  // a malformed entry: reported, not added
@@ -1302,10 +1306,12 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
         if ((mask >> 1) & 1ull) dlv_probe(nd, sh, entry, gp, mask, 1, inbuf(n + 1));
       }
       before += ktot;
-      __syncthreads();
-      if (sh.npair > (uint32_t)(kSelChunk - kB)) {
-        pairs += sh.npair;
-        events += dlv_flush(nd, sh, inbuf(n + 1));
+      if (spikes > (uint32_t)(kSelChunk - kB)) {  // block-uniform: else the chunk cannot fill up
+        __syncthreads();
+        if (sh.npair > (uint32_t)(kSelChunk - kB)) {
+          pairs += sh.npair;
+          events += dlv_flush(nd, sh, inbuf(n + 1));
+        }
       }
     }
     __syncthreads();
