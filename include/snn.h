@@ -174,6 +174,12 @@ typedef struct snn_counters {
   double last_call_device_ms; /* device time of the last snn_simulate_steps call,
                                  HIP events on the library's stream around its
                                  graph launches (kernels and the gaps between) */
+  uint32_t tile_runs;       /* binned, LIF-only, no plastic synapses: 1 when the
+                               groups put on average at least 4 synapses on each
+                               tile they reach and the delivery's count pass reads
+                               their tile runs (recorded at build, 4 bytes per run,
+                               8 per group) instead of every synapse word     */
+  uint32_t pad;
 } snn_counters;
 
 /* ---- lifecycle ---------------------------------------------------------- */

@@ -37,6 +37,12 @@ hipError_t launch_grp_off(const uint32_t* cnt, const uint64_t* off, const uint64
 // sort every group's payload ascending; groups longer than 16384 are listed in big[] (count in *nbig)
 hipError_t launch_segsort(const uint64_t* grp_off, uint64_t n_groups, uint32_t* payload, uint64_t* big,
                           uint32_t* nbig, uint32_t big_cap, hipStream_t s);
+// Tile runs of every group (binned delivery with tile shift tsh): fill =
+// false counts them into cnt[g] (and sets *too_long for a group of
+// kRunMaxGroup synapses or more), fill = true writes them at run_desc[grp_run[g] ..].
+hipError_t launch_runs(bool fill, const uint64_t* grp_off, uint64_t n_groups, const uint32_t* payload,
+                       uint32_t cls_bits, uint32_t tsh, uint32_t* cnt, const uint64_t* grp_run, uint32_t* run_desc,
+                       uint32_t* too_long, hipStream_t s);
 
 // ---- per-step pipeline (step = ctrl->step_base + rel) ----
 // One step: update, spike emission and delay-1/-2 delivery, and delivery of

@@ -370,6 +370,66 @@ __global__ void __launch_bounds__(kSB) k_segsort_block(const uint64_t* __restric
   }
 }
 
+
+// ------------------------------------------------------------ tile runs
+// A group's synapses are sorted by target, so those onto one tile of the
+// binned delivery lie together: a run.  One wave per group finds the run
+// starts (a synapse whose tile differs from its predecessor's) with a ballot
+// over 64 synapses at a time.  Pass kFill = false counts them per group;
+// pass kFill = true writes run k of group g as run_desc[grp_run[g] + k] =
+// tile << kRunLenBits | length, in synapse order: each start closes the run
+// before it (the previous start in the window, or the run still open from
+// the earlier windows), and the last run closes at the group's end.  A group
+// of kRunMaxGroup synapses or more sets *too_long (no runs for the network).
+template <bool kFill>
+__global__ void __launch_bounds__(kB) k_runs(const uint64_t* __restrict__ grp_off, uint64_t n_groups,
+                                             const uint32_t* __restrict__ payload, uint32_t cls_bits, uint32_t tsh,
+                                             uint32_t* __restrict__ cnt, const uint64_t* __restrict__ grp_run,
+                                             uint32_t* __restrict__ run_desc, uint32_t* too_long) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * kB) >> 6;
+  for (uint64_t g = ((uint64_t)blockIdx.x * kB + threadIdx.x) >> 6; g < n_groups; g += nwaves) {
+    const uint64_t a = grp_off[g], b = grp_off[g + 1];
+    if (!kFill && lane == 0 && b - a >= kRunMaxGroup) atomicOr(too_long, 1u);
+    uint64_t runs = 0;                 // run starts before this window
+    uint32_t prev_tile = 0xffffffffu;  // tile of the synapse before the window
+    uint64_t open_pos = a;             // first synapse of the open run
+    uint32_t open_tile = 0;
+    const uint64_t base = kFill ? grp_run[g] : 0;
+    for (uint64_t j0 = a; j0 < b; j0 += 64) {  // wave-uniform
+      const uint64_t j = j0 + lane;
+      const bool in = j < b;
+      const uint32_t t = in ? (payload[j] >> cls_bits) >> tsh : 0xffffffffu;
+      const uint32_t left = __shfl(t, (int)(lane ? lane - 1 : 0), 64);
+      const bool start = in && t != (lane ? left : prev_tile);
+      const uint64_t m = __ballot(start);
+      if (kFill) {
+        const uint64_t below = m & ((1ull << lane) - 1ull);
+        const uint32_t pl = below ? 63u - (uint32_t)__clzll(below) : 0u;
+        const uint32_t tile_pl = __shfl(t, (int)pl, 64);
+        const uint64_t k = runs + (uint64_t)__popcll(below);
+        if (start && k > 0) {
+          const uint64_t pos = below ? j0 + pl : open_pos;
+          const uint32_t tile = below ? tile_pl : open_tile;
+          run_desc[base + k - 1] = (tile << kRunLenBits) | (uint32_t)(j - pos);
+        }
+      }
+      if (m) {
+        const uint32_t hb = 63u - (uint32_t)__clzll(m);
+        open_pos = j0 + hb;
+        open_tile = __shfl(t, (int)hb, 64);
+      }
+      const uint32_t last = (uint32_t)((b - j0 < 64 ? b - j0 : 64) - 1);
+      prev_tile = __shfl(t, (int)last, 64);
+      runs += (uint64_t)__popcll(m);
+    }
+    if (lane == 0) {
+      if (!kFill) cnt[g] = (uint32_t)runs;
+      else if (runs) run_desc[base + runs - 1] = (open_tile << kRunLenBits) | (uint32_t)(b - open_pos);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gen_count(const ProjDev* projs, uint32_t nproj, uint64_t total_pairs, uint32_t dmax_cfg,
@@ -434,6 +494,20 @@ hipError_t launch_segsort(const uint64_t* grp_off, uint64_t n_groups, uint32_t* 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_segsort_block, dim3(grid_for(n_groups, 1, 4096)), dim3(kSB), kBlockSortMax * sizeof(uint32_t),
                      s, grp_off, n_groups, payload, (unsigned long long*)big, nbig, big_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_runs(bool fill, const uint64_t* grp_off, uint64_t n_groups, const uint32_t* payload,
+                       uint32_t cls_bits, uint32_t tsh, uint32_t* cnt, const uint64_t* grp_run, uint32_t* run_desc,
+                       uint32_t* too_long, hipStream_t s) {
+  if (n_groups == 0) return hipSuccess;
+  const dim3 grid(grid_for(n_groups, kB / 64, 1u << 16));
+  if (fill)
+    hipLaunchKernelGGL(k_runs<true>, grid, dim3(kB), 0, s, grp_off, n_groups, payload, cls_bits, tsh, cnt, grp_run,
+                       run_desc, too_long);
+  else
+    hipLaunchKernelGGL(k_runs<false>, grid, dim3(kB), 0, s, grp_off, n_groups, payload, cls_bits, tsh, cnt, grp_run,
+                       run_desc, too_long);
   return hipGetLastError();
 }
 

@@ -441,9 +441,22 @@ union StepLds {
   DirectLds dlv;
 };
 
+// binned delivery with tile runs: each selected group's first run and run
+// count, and the exclusive prefix of the run counts
+struct BinRunLds : BinLds {
+  uint64_t p_run[kSelChunk];
+  uint32_t p_nrun[kSelChunk];
+  uint32_t q_st[kSelChunk];
+};
+
 union BinStepLds {
   TileLds tile;
   BinLds dlv;
+};
+
+union BinRunStepLds {
+  TileLds tile;
+  BinRunLds dlv;
 };
 
 __device__ __forceinline__ void dlv_load_classes(const NetDev& nd, DirectLds& sh) {
@@ -465,12 +478,13 @@ __device__ __forceinline__ void dlv_init(const NetDev& nd, BinLds& sh) {
 // reaches a connection group now iff its source has a group of delay d (bit d
 // of the delay mask); that group's index among the source's groups, which are
 // ordered by delay, is the number of lower bits set.
-__device__ __forceinline__ void sel_add(SelLds& sh, uint64_t off, uint32_t len, uint32_t mult, uint32_t buf) {
+__device__ __forceinline__ uint32_t sel_add(SelLds& sh, uint64_t off, uint32_t len, uint32_t mult, uint32_t buf) {
   const uint32_t k = atomicAdd(&sh.npair, 1u);  // LDS counter; callers keep k < kSelChunk
   sh.p_off[k] = off;
   sh.p_len[k] = len;
   sh.p_mult[k] = mult;
   sh.p_buf[k] = (uint8_t)buf;
+  return k;
 }
 
 __device__ __forceinline__ void dlv_probe(const NetDev& nd, SelLds& sh, uint32_t entry, uint32_t grp_ptr,
@@ -479,6 +493,18 @@ __device__ __forceinline__ void dlv_probe(const NetDev& nd, SelLds& sh, uint32_t
     const uint32_t g = grp_ptr + (uint32_t)__popcll(mask & ((1ull << d) - 1ull));
     const uint64_t off = nd.grp_off[g];
     sel_add(sh, off, (uint32_t)(nd.grp_off[g + 1] - off), entry >> kMultShift, buf);
+  }
+}
+
+// the same, recording the group's tile runs
+__device__ __forceinline__ void dlv_probe(const NetDev& nd, BinRunLds& sh, uint32_t entry, uint32_t grp_ptr,
+                                          uint64_t mask, uint32_t d, uint32_t buf) {
+  if ((mask >> d) & 1ull) {
+    const uint32_t g = grp_ptr + (uint32_t)__popcll(mask & ((1ull << d) - 1ull));
+    const uint64_t off = nd.grp_off[g], r0 = nd.grp_run[g];
+    const uint32_t k = sel_add(sh, off, (uint32_t)(nd.grp_off[g + 1] - off), entry >> kMultShift, buf);
+    sh.p_run[k] = r0;
+    sh.p_nrun[k] = (uint32_t)(nd.grp_run[g + 1] - r0);
   }
 }
 
@@ -529,6 +555,21 @@ __device__ __forceinline__ uint32_t sel_advance(const SelLds& sh, uint32_t np, u
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (sh.p_st[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// the same over a 32-bit prefix st[0 .. n)
+__device__ __forceinline__ uint32_t st_advance(const uint32_t* st, uint32_t n, uint32_t lo, uint32_t e) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (lo + 1 >= n || st[lo + 1] > e) return lo;
+    ++lo;
+  }
+  uint32_t hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (st[mid] <= e) lo = mid; else hi = mid;
   }
   return lo;
 }
@@ -666,51 +707,18 @@ __device__ __forceinline__ void lane_gather(const NetDev& nd, const BinLds& sh, 
   }
 }
 
-// Binned delivery of the chunk: the same flat scan, but each event becomes
-// one 32-bit entry (local target, multiplicity, weight class) in the bin of
-// its target tile in input buffer buf; the tile block of that step sums its
-// bin in LDS.  Two passes over the chunk's synapses: count the events per tile
-// (LDS), reserve each tile's range with one device atomic, then write the
-// entries.  A lane takes kLaneRun consecutive synapses per round (found from
-// a coarse index of the chunk's events), and a run of them onto one tile
-// takes one LDS atomic and consecutive entries.  Called by the whole block
-// after a barrier; returns the events delivered and resets the chunk.
-__device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
-  // every pair of a binned chunk arrives at the same step (buffer buf)
-  const uint32_t np = sh.npair;
-  const uint64_t ev = sel_scan(sh);
-  const uint32_t csh = build_cidx(sh, np, ev);
-  // target = pl >> cls_bits, tile = target >> tile_shift: two shifts, each
-  // below 32 (their sum can exceed 31 when a tile is wider than the gid range)
+// Second half of the binned flush, called by every thread once its part of
+// the count pass has added each touched tile's events to tcnt: one device
+// atomic per tile reserves its range, then the chunk's synapses are written
+// (as in the count pass, kLaneRun consecutive ones per lane), spills and
+// plastic synapses aside.  Resets the chunk; returns ev.
+__device__ __forceinline__ uint64_t bin_write(const NetDev& nd, BinLds& sh, uint32_t buf, uint32_t np, uint64_t ev,
+                                              uint32_t csh, bool bad) {
   const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u;
   const uint32_t tsh = nd.tile_shift, lmask = (1u << tsh) - 1u, ntl = nd.n_tiles;
   const bool plastic = nd.n_rules != 0;
   constexpr uint32_t kNone = 0xffffffffu;
-  bool bad = false;
   const uint64_t step = (uint64_t)kB * kLaneRun;
-  for (uint64_t b0 = 0; b0 < ev; b0 += step) {
-    const uint64_t e0 = b0 + (uint64_t)threadIdx.x * kLaneRun;
-    if (e0 >= ev) break;
-    uint32_t r[kLaneRun], pl[kLaneRun];
-    lane_gather(nd, sh, np, ev, e0, csh, r, pl);
-    uint32_t tp = kNone, k = 0;
-#pragma unroll
-    for (int q = 0; q < kLaneRun; ++q) {
-      uint32_t t = kNone;
-      if (e0 + q < ev) {
-        t = (pl[q] >> cls_bits) >> tsh;
-        if (t >= ntl) { bad = true; t = kNone; }
-        else if (plastic && nd.cls_rule[pl[q] & cls_mask]) t = kNone;  // plastic: no bin entry
-      }
-      if (t != tp) {
-        if (k) atomicAdd(&sh.tcnt[tp], k);
-        tp = t;
-        k = 0;
-      }
-      if (t != kNone) ++k;
-    }
-    if (k) atomicAdd(&sh.tcnt[tp], k);
-  }
   __syncthreads();
   uint32_t* cnt = nd.bin_cnt + (size_t)buf * ntl;
   for (uint32_t t = threadIdx.x; t < ntl; t += kB) {
@@ -783,6 +791,94 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
   if (threadIdx.x == 0) sh.npair = 0;
   __syncthreads();
   return ev;
+}
+
+// Binned delivery of the chunk: the same flat scan, but each event becomes
+// one 32-bit entry (local target, multiplicity, weight class) in the bin of
+// its target tile in input buffer buf; the tile block of that step sums its
+// bin in LDS.  Two passes over the chunk's synapses: count the events per tile
+// (LDS), reserve each tile's range with one device atomic, then write the
+// entries.  A lane takes kLaneRun consecutive synapses per round (found from
+// a coarse index of the chunk's events), and a run of them onto one tile
+// takes one LDS atomic and consecutive entries.  Called by the whole block
+// after a barrier; returns the events delivered and resets the chunk.
+__device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
+  // every pair of a binned chunk arrives at the same step (buffer buf)
+  const uint32_t np = sh.npair;
+  const uint64_t ev = sel_scan(sh);
+  const uint32_t csh = build_cidx(sh, np, ev);
+  // target = pl >> cls_bits, tile = target >> tile_shift: two shifts, each
+  // below 32 (their sum can exceed 31 when a tile is wider than the gid range)
+  const uint32_t cls_bits = nd.cls_bits, cls_mask = (1u << cls_bits) - 1u;
+  const uint32_t tsh = nd.tile_shift, ntl = nd.n_tiles;
+  const bool plastic = nd.n_rules != 0;
+  constexpr uint32_t kNone = 0xffffffffu;
+  bool bad = false;
+  const uint64_t step = (uint64_t)kB * kLaneRun;
+  for (uint64_t b0 = 0; b0 < ev; b0 += step) {
+    const uint64_t e0 = b0 + (uint64_t)threadIdx.x * kLaneRun;
+    if (e0 >= ev) break;
+    uint32_t r[kLaneRun], pl[kLaneRun];
+    lane_gather(nd, sh, np, ev, e0, csh, r, pl);
+    uint32_t tp = kNone, k = 0;
+#pragma unroll
+    for (int q = 0; q < kLaneRun; ++q) {
+      uint32_t t = kNone;
+      if (e0 + q < ev) {
+        t = (pl[q] >> cls_bits) >> tsh;
+        if (t >= ntl) { bad = true; t = kNone; }
+        else if (plastic && nd.cls_rule[pl[q] & cls_mask]) t = kNone;  // plastic: no bin entry
+      }
+      if (t != tp) {
+        if (k) atomicAdd(&sh.tcnt[tp], k);
+        tp = t;
+        k = 0;
+      }
+      if (t != kNone) ++k;
+    }
+    if (k) atomicAdd(&sh.tcnt[tp], k);
+  }
+  return bin_write(nd, sh, buf, np, ev, csh, bad);
+}
+
+// the same with the count pass over the chunk's tile runs (one 4-byte
+// descriptor per run instead of every synapse word: networks whose groups put
+// many synapses on each tile they touch, without plastic synapses)
+__device__ uint64_t dlv_flush(const NetDev& nd, BinRunLds& sh, uint32_t buf) {
+  const uint32_t np = sh.npair;
+  const uint64_t ev = sel_scan(sh);
+  const uint32_t csh = build_cidx(sh, np, ev);
+  uint64_t nr;
+  {  // exclusive prefix of the groups' run counts
+    uint32_t L[kSelPerThread];
+    uint64_t lsum = 0;
+#pragma unroll
+    for (int q = 0; q < kSelPerThread; ++q) {
+      const uint32_t i = threadIdx.x * kSelPerThread + q;
+      L[q] = (i < np) ? sh.p_nrun[i] : 0u;
+      lsum += L[q];
+    }
+    uint64_t run = block_excl_scan(lsum, sh.red, &nr);
+#pragma unroll
+    for (int q = 0; q < kSelPerThread; ++q) {
+      const uint32_t i = threadIdx.x * kSelPerThread + q;
+      if (i < np) sh.q_st[i] = (uint32_t)run;
+      run += L[q];
+    }
+    __syncthreads();
+  }
+  const uint32_t ntl = nd.n_tiles;
+  bool bad = false;
+  uint32_t pr = 0;
+  for (uint64_t r = threadIdx.x; r < nr; r += kB) {
+    pr = st_advance(sh.q_st, np, pr, (uint32_t)r);
+    const uint32_t d = nd.run_desc[sh.p_run[pr] + ((uint32_t)r - sh.q_st[pr])];
+    const uint32_t t = d >> kRunLenBits;
+    if (t < ntl) atomicAdd(&sh.tcnt[t], d & ((1u << kRunLenBits) - 1u));
+    else bad = true;
+  }
+  __syncthreads();
+  return bin_write(nd, sh, buf, np, ev, csh, bad);
 }
 
 // Synaptic state of AdEx neuron i into y[2..] with the step's input x (nS)
@@ -1451,6 +1547,21 @@ __global__ void __launch_bounds__(kB) k_step_binned(NetDev nd, uint32_t rel) {
   }
 }
 
+// The same for LIF-only networks with tile runs: the delivery blocks' count
+// pass reads the runs (a kernel of its own, so that the other step kernels
+// carry no code for it).
+template <bool kLif, int kAd, int P>
+__global__ void __launch_bounds__(kB) k_step_binned_runs(NetDev nd, uint32_t rel) {
+  __shared__ BinRunStepLds lds;
+  const uint64_t n = nd.ctrl->step_base + rel;
+  if (blockIdx.x == 0 && threadIdx.x == 0) step_books(nd, n);
+  if (blockIdx.x < nd.n_tiles) {
+    tile_block<kLif, kAd, P>(nd, n, blockIdx.x, lds.tile);
+  } else {
+    deliver_block(nd, n, blockIdx.x - nd.n_tiles, gridDim.x - nd.n_tiles, lds.dlv);
+  }
+}
+
 __global__ void k_advance(Ctrl* ctrl, uint32_t steps) {
   if (threadIdx.x == 0 && blockIdx.x == 0) ctrl->step_base += steps;
 }
@@ -1533,7 +1644,9 @@ struct SelBinned {
 };
 
 hipError_t launch_step(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
-  if (nd.n_tiles) launch_variant<SelBinned>(nd, dim3(nd.n_tiles + nd.sel_grid), s, start, stop, rel);
+  if (nd.n_tiles && nd.tile_runs)  // LIF-only networks
+    launch(k_step_binned_runs<true, 0, 1>, dim3(nd.n_tiles + nd.sel_grid), dim3(kB), s, start, stop, nd, rel);
+  else if (nd.n_tiles) launch_variant<SelBinned>(nd, dim3(nd.n_tiles + nd.sel_grid), s, start, stop, rel);
   else launch_variant<SelDirect>(nd, dim3(nd.nblk_upd + nd.sel_grid), s, start, stop, rel);
   return hipGetLastError();
 }

@@ -33,6 +33,7 @@ constexpr uint32_t kGraphSteps = 100;
 constexpr int kNumParams = 16;  // SNN_P_TAU_M .. SNN_P_RK_HMIN
 constexpr uint64_t kChunkRing = 4096;  // >= drain interval + graph length
 constexpr uint64_t kBinnedMinSynapses = 500000000;  // default delivery: binned from this size on
+constexpr uint64_t kRunMinMean = 4;  // tile runs when groups average this many synapses per touched tile
 constexpr uint64_t kQueueMinInstances = 8;          // binned batches with at least this many instances ...
 constexpr uint64_t kQueueMaxTilesPerInstance = 32;  // ... of at most this many tiles each use the delivery queue
 
@@ -1914,6 +1915,32 @@ snn_status build_impl(snn_net* net) {
       // which balances delays with different hit rates and group sizes
       const uint64_t ni = net->insts.size();
       nd.dlv_queue = (ni >= kQueueMinInstances && nt <= kQueueMaxTilesPerInstance * ni) ? 1u : 0u;
+      // tile runs: the synapses of a group onto one tile are contiguous (groups
+      // are sorted by target); where they are long on average, the count pass of
+      // the binned flush reads one descriptor per run instead of every synapse
+      const uint64_t G = nd.n_groups;
+      if (!nd.n_rules && !net->has_adex && G) {
+        uint32_t* d_rc; ALLOC(d_rc, uint32_t, G);
+        uint32_t* d_tl; ALLOC(d_tl, uint32_t, 1);
+        uint64_t* d_gr; ALLOC(d_gr, uint64_t, G + 1);
+        uint64_t* d_rt; ALLOC(d_rt, uint64_t, scan_tmp_words(G));
+        HIPCHK(net, hipMemsetAsync(d_tl, 0, 4, s));
+        HIPCHK(net, launch_runs(false, nd.grp_off, G, nd.payload, nd.cls_bits, tsh, d_rc, nullptr, nullptr, d_tl, s));
+        HIPCHK(net, launch_scan_u32(d_rc, G, d_gr, d_rt, s));
+        uint64_t total = 0;
+        uint32_t too_long = 0;
+        HIPCHK(net, hipMemcpyAsync(&total, d_gr + G, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(net, hipMemcpyAsync(&too_long, d_tl, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(net, hipStreamSynchronize(s));
+        dev_free(net, d_rc); dev_free(net, d_tl); dev_free(net, d_rt);
+        if (!too_long && total && nd.n_syn >= kRunMinMean * total) {
+          uint32_t* d_rd; ALLOC(d_rd, uint32_t, total);
+          HIPCHK(net, launch_runs(true, nd.grp_off, G, nd.payload, nd.cls_bits, tsh, nullptr, d_gr, d_rd, nullptr, s));
+          nd.grp_run = d_gr; nd.run_desc = d_rd; nd.tile_runs = 1;
+        } else {
+          dev_free(net, d_gr);
+        }
+      }
     }
   }
 
@@ -2146,6 +2173,7 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   out->tile_neurons = net->tile_neurons;
   out->delivery_blocks = net->nd.sel_grid;
   out->delivery_queue = net->nd.dlv_queue;
+  out->tile_runs = net->nd.tile_runs;
   return leave(net);
 }
 

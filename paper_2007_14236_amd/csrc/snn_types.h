@@ -47,6 +47,8 @@ constexpr int kTileAccWords = 4096; // int64 LDS accumulators of a tile block (t
 constexpr uint32_t kMaxTiles = 1024; // tiles of the binned delivery
 constexpr int kBinLocalShift = 15;   // bin entry: local target << 15 | mult << 10 | class
 constexpr int kBinMultShift = 10;
+constexpr int kRunLenBits = 22;                  // tile run descriptor: tile << 22 | length
+constexpr uint64_t kRunMaxGroup = 1ull << 20;     // tile runs only for groups below this size
 constexpr uint32_t kNoAllocInputMax = 1u << 18;  // neurons per call of the allocation-free input readback
 constexpr int kMaxDevices = 64;
 constexpr int kTagConn = 1;
@@ -152,7 +154,8 @@ struct NetDev {
   uint32_t npois, pois_len;    // Poisson threshold tables; entries read at most (the rest are never reached)
   uint32_t R, nblk_upd, sel_grid, pad0;  // R step slots; pad0: bit 0 LIF, bit 1 AdEx, bit 2 beta ports present
   uint32_t n_tiles, tile_shift;  // binned delivery (n_tiles == 0: direct atomics)
-  uint32_t dlv_queue, pad3;      // binned delivery blocks take contiguous item ranges from a queue (batches)
+  uint32_t dlv_queue, tile_runs; // binned delivery blocks take contiguous item ranges from a queue (batches);
+                                 // their count pass reads the groups' tile runs (grp_run, run_desc)
   uint64_t bins_total;           // bin entries per input buffer
   uint64_t log_mask;           // CAP - 1
   uint64_t chunk_ring;         // slots of chunk_base (power of two)
@@ -199,6 +202,11 @@ struct NetDev {
   const uint64_t* tidx;
   uint64_t* arr_list;
   uint32_t* arr_cnt;
+  // tile runs of the binned delivery: the synapses of group g onto one tile are
+  // run_desc[grp_run[g] .. grp_run[g+1]), each tile << kRunLenBits | length, in
+  // synapse order (a group is sorted by target)
+  const uint64_t* grp_run;
+  const uint32_t* run_desc;
 };
 
 }  // namespace snn

@@ -178,3 +178,45 @@ def test_batch_delivery_queue_bit_exact(snn, cap):
 def test_single_network_keeps_the_strided_share(snn):
     g = snn.Net(W.brunel_lif(n=3000, k=100, seed=3, nu_ext=250.0), delivery="binned", tile_neurons=256)
     assert g.counters()["delivery_queue"] == 0
+
+
+def _runs_net():
+    """LIF-delta network whose groups are long (one delay, ~300 synapses per
+    source) over few tiles: the binned delivery counts per tile run."""
+    return W.brunel_lif(n=2500, k=300, seed=21, delay=("const", 0.8, 0.0), dmax=25, nu_ext=200.0)
+
+
+@pytest.mark.parametrize("cap", [0, 16])
+def test_tile_runs_bit_exact(snn, cap):
+    """Delivery whose count pass reads the groups' tile runs (and, with tiny
+    bins, its spill path): raster and per-step input equal the oracle's."""
+    spec = _runs_net()
+    steps = 200
+    o = O.OracleNet(spec, O.FP32SO)
+    rec = o.record_input(steps + 1)
+    o.simulate(steps + 1)
+    g = snn.Net(spec, delivery="binned", tile_neurons=256, bin_capacity=cap)
+    assert g.counters()["tile_runs"] == 1
+    for n in range(steps):
+        g.simulate(1)
+        if n % 20 == 19:
+            assert np.array_equal(g.get_input(0), rec[n + 1][:, 0]), n
+    gs, gg, gm = g.spikes()
+    os_, og, om = o.spikes()
+    keep = os_ < steps
+    assert np.array_equal(gs, os_[keep]) and np.array_equal(gg, og[keep]) and np.array_equal(gm, om[keep])
+    assert len(gs) > 500
+    c = g.counters()
+    assert c["overflow"] == 0
+    if cap:
+        assert c["spill_events"] > 0
+
+
+def test_tile_runs_only_where_they_pay(snn):
+    """Short runs (random targets over many tiles), AdEx neurons or direct
+    delivery: no run index."""
+    a = snn.Net(W.brunel_lif(n=3000, k=100, seed=3, delay=("uniform", 0.1, 2.0), nu_ext=250.0), delivery="binned",
+                tile_neurons=256)
+    b = snn.Net(W.adex_balanced(n=2000, k=200, seed=5), delivery="binned", tile_neurons=256)
+    c = snn.Net(_runs_net(), delivery="direct")
+    assert [x.counters()["tile_runs"] for x in (a, b, c)] == [0, 0, 0]
