@@ -117,7 +117,7 @@ def step_roofline(net, specs: list, mode: str, steps: int, c0: dict, c1: dict, p
     c2 = net.counters()
     prof = net.profile(profile_steps) if profile_steps > 0 else {"step": 0.0}
     iso_ms = prof["step"] / max(1, profile_steps)
-    kernel = "k_step_binned" if mode == "binned" else "k_step"
+    kernel = "k_step" if mode != "binned" else "k_step_binned_runs" if c2.get("tile_runs") else "k_step_binned"
     neuron_bytes = sum(bytes_per_step_neurons(sp, mode) for sp in specs)
     dlv_bytes = neuron_bytes + ev_p * BYTES_PER_EVENT[mode] + pr_p * BYTES_PER_PAIR + sp_p * BYTES_PER_SPIKE
     achieved = dlv_bytes / (dev_ms * 1e-3) / 1e9 if dev_ms > 0 else 0.0

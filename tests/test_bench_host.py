@@ -45,7 +45,7 @@ def test_committed_traffic_record_is_well_formed():
     for src in rec["kernel_sources"]:
         assert os.path.exists(os.path.join(os.path.dirname(bench.__file__), src))
     for w, ent in rec["workloads"].items():
-        assert ent["kernel"] in ("k_step", "k_step_binned")
+        assert ent["kernel"] in ("k_step", "k_step_binned", "k_step_binned_runs")
         scaled = (ent["fetch_kib"] * 1.99975 + ent["write_kib"]) * 1024
         assert abs(ent["bytes_per_launch"] / scaled - 1) < 1e-4, w
 
