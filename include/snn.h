@@ -179,7 +179,11 @@ typedef struct snn_counters {
                                tile they reach and the delivery's count pass reads
                                their tile runs (recorded at build, 4 bytes per run,
                                8 per group) instead of every synapse word     */
-  uint32_t pad;
+  uint32_t tile_window;     /* binned: 1 when every tile overlaps at most 8
+                               populations, so that LIF-only networks run step
+                               kernels that read the population tables from a
+                               window in LDS; 0 otherwise (such LIF-only networks
+                               then run the kernels built for AdEx as well)   */
 } snn_counters;
 
 /* ---- lifecycle ---------------------------------------------------------- */

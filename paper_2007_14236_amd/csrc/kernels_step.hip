@@ -353,7 +353,7 @@ constexpr uint32_t kPoisLds = 8;  // Poisson threshold tables up to this count a
 constexpr int kSelChunk = 512;    // selected groups held in LDS at a time
 constexpr uint32_t kClsLds = 256; // weight classes cached in LDS by direct delivery (more: global)
 constexpr int kSelPerThread = kSelChunk / kB;
-constexpr uint32_t kTilePopLds = 8;  // population tables a tile block keeps in LDS
+static_assert(kTilePopLds <= kPoisLds, "a tile window's Poisson tables fit the LDS table");
 constexpr int kTileSubs = kTileAccWords / kB;  // most 256-neuron sub-blocks of a tile
 constexpr uint32_t kHotCap = 256;
 // Delays of at least this many steps are delivered by the delivery blocks
@@ -844,7 +844,7 @@ __device__ uint64_t dlv_flush(const NetDev& nd, BinLds& sh, uint32_t buf) {
 // the same with the count pass over the chunk's tile runs (one 4-byte
 // descriptor per run instead of every synapse word: networks whose groups put
 // many synapses on each tile they touch, without plastic synapses)
-__device__ uint64_t dlv_flush(const NetDev& nd, BinRunLds& sh, uint32_t buf) {
+__device__ __forceinline__ uint64_t dlv_flush(const NetDev& nd, BinRunLds& sh, uint32_t buf) {
   const uint32_t np = sh.npair;
   const uint64_t ev = sel_scan(sh);
   const uint32_t csh = build_cidx(sh, np, ev);
@@ -1006,6 +1006,31 @@ __device__ __forceinline__ void load_tables(const NetDev& nd, PopDev* spops, uin
   pthr = lds_thr ? sthr : nd.pois_thr;
 }
 
+// The population records p0 .. p0 + np - 1 (np <= kTilePopLds) and their
+// Poisson tables in LDS, the tables renumbered by window index.
+__device__ __forceinline__ void load_tile_window(const NetDev& nd, uint32_t p0, uint32_t np, PopDev* spops,
+                                                 uint64_t* sthr) {
+  const uint32_t words = np * (uint32_t)(sizeof(PopDev) / 4);
+  for (uint32_t w = threadIdx.x; w < words; w += kB)
+    reinterpret_cast<uint32_t*>(spops)[w] = reinterpret_cast<const uint32_t*>(nd.pops + p0)[w];
+  const uint32_t len = nd.pois_len;
+  for (uint32_t w = threadIdx.x; w < np * len; w += kB) {
+    const uint32_t k = w / len, j = w - k * len;
+    const int32_t q = nd.pops[p0 + k].pois;
+    if (q >= 0) sthr[k * kPoisKmax + j] = nd.pois_thr[(size_t)q * kPoisKmax + j];
+  }
+  __syncthreads();
+  if (threadIdx.x < np && spops[threadIdx.x].pois >= 0) spops[threadIdx.x].pois = (int32_t)threadIdx.x;
+}
+
+// Populations overlapping tile t: the first one and their number.
+__device__ __forceinline__ uint32_t tile_pops(const NetDev& nd, uint32_t t, uint32_t& p0) {
+  const uint32_t first = t << nd.tile_shift;
+  const uint32_t nt = min(1u << nd.tile_shift, nd.N - first);
+  p0 = find_pop(nd.pops, nd.npop, first);
+  return find_pop(nd.pops, nd.npop, first + nt - 1) - p0 + 1;
+}
+
 // A tile block's population records and Poisson tables: all of them in LDS
 // when they fit; otherwise, when the populations overlapping the tile (a
 // contiguous run in gid order, a few even in a batch of many instances) fit,
@@ -1020,17 +1045,7 @@ __device__ __forceinline__ uint32_t load_tile_tables(const NetDev& nd, uint32_t 
     load_tables(nd, spops, kTilePopLds, sthr, pops, pthr);
     return nd.npop;
   }
-  const uint32_t words = np * (uint32_t)(sizeof(PopDev) / 4);
-  for (uint32_t w = threadIdx.x; w < words; w += kB)
-    reinterpret_cast<uint32_t*>(spops)[w] = reinterpret_cast<const uint32_t*>(nd.pops + p0)[w];
-  const uint32_t len = nd.pois_len;
-  for (uint32_t w = threadIdx.x; w < np * len; w += kB) {
-    const uint32_t k = w / len, j = w - k * len;
-    const int32_t q = nd.pops[p0 + k].pois;
-    if (q >= 0) sthr[k * kPoisKmax + j] = nd.pois_thr[(size_t)q * kPoisKmax + j];
-  }
-  __syncthreads();
-  if (threadIdx.x < np && spops[threadIdx.x].pois >= 0) spops[threadIdx.x].pois = (int32_t)threadIdx.x;
+  load_tile_window(nd, p0, np, spops, sthr);
   pops = spops;
   pthr = sthr;
   return np;
@@ -1217,7 +1232,7 @@ __device__ __forceinline__ uint32_t adex_store(const NetDev& nd, uint32_t i, Ade
 // a lane whose neuron has reached the step end takes the next one, so waves
 // stay full while neurons near a spike need many RK45 substeps and the
 // others one.
-template <bool kLif, int kAd, int P>
+template <bool kLif, int kAd, int P, bool kWin = false>
 __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl) {
   const uint32_t PP = nd.P, tsh = nd.tile_shift, buf = inbuf(n);
   const uint32_t first = t << tsh;
@@ -1227,7 +1242,19 @@ __device__ void tile_block(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl
   const uint64_t pos_n = step_pos(nd, n);
   const PopDev* pops;
   const uint64_t* pthr;
-  const uint32_t npop = load_tile_tables(nd, first, nt, sl.spops, sl.sthr, pops, pthr);
+  uint32_t npop;
+  if constexpr (kWin) {
+    // the caller found the tile's populations to fit the LDS window: the
+    // tables are read from LDS only, with no generic loads (whose waits
+    // would also cover the block's global memory operations)
+    uint32_t p0;
+    npop = tile_pops(nd, t, p0);
+    load_tile_window(nd, p0, npop, sl.spops, sl.sthr);
+    pops = sl.spops;
+    pthr = sl.sthr;
+  } else {
+    npop = load_tile_tables(nd, first, nt, sl.spops, sl.sthr, pops, pthr);
+  }
   for (uint32_t c = threadIdx.x; c < nd.n_classes; c += kB) {
     sl.c.wq[c] = nd.cls_wq[c];
     sl.wp[c] = (uint8_t)nd.cls_port[c];
@@ -1531,6 +1558,14 @@ __global__ void __launch_bounds__(kB) k_step(NetDev nd, uint32_t rel) {
   }
 }
 
+// A tile block's step.  The LIF-only kernels run only where every tile's
+// populations fit the LDS window (the host launches the AdEx-capable kernel
+// for other LIF-only networks), so they read the tables from LDS only.
+template <bool kLif, int kAd, int P>
+__device__ __forceinline__ void tile_step(const NetDev& nd, uint64_t n, uint32_t t, TileLds& sl) {
+  tile_block<kLif, kAd, P, kAd == 0>(nd, n, t, sl);
+}
+
 // One simulation step n, binned delivery: blocks [0, n_tiles) are the tile
 // blocks (input from their bins, update, emission, delay-1 binning), the
 // remaining blocks bin the earlier steps' spikes whose delay (>= 2) expires
@@ -1541,7 +1576,7 @@ __global__ void __launch_bounds__(kB) k_step_binned(NetDev nd, uint32_t rel) {
   const uint64_t n = nd.ctrl->step_base + rel;
   if (blockIdx.x == 0 && threadIdx.x == 0) step_books(nd, n);
   if (blockIdx.x < nd.n_tiles) {
-    tile_block<kLif, kAd, P>(nd, n, blockIdx.x, lds.tile);
+    tile_step<kLif, kAd, P>(nd, n, blockIdx.x, lds.tile);
   } else {
     deliver_block(nd, n, blockIdx.x - nd.n_tiles, gridDim.x - nd.n_tiles, lds.dlv);
   }
@@ -1556,7 +1591,7 @@ __global__ void __launch_bounds__(kB) k_step_binned_runs(NetDev nd, uint32_t rel
   const uint64_t n = nd.ctrl->step_base + rel;
   if (blockIdx.x == 0 && threadIdx.x == 0) step_books(nd, n);
   if (blockIdx.x < nd.n_tiles) {
-    tile_block<kLif, kAd, P>(nd, n, blockIdx.x, lds.tile);
+    tile_step<kLif, kAd, P>(nd, n, blockIdx.x, lds.tile);
   } else {
     deliver_block(nd, n, blockIdx.x - nd.n_tiles, gridDim.x - nd.n_tiles, lds.dlv);
   }
@@ -1623,8 +1658,10 @@ static void launch_variant(const NetDev& nd, dim3 grid, hipStream_t s, hipEvent_
   // which models are present is encoded in nd.pad0: bit 0 LIF, bit 1 AdEx,
   // bit 2 AdEx with beta ports
   const bool lif = nd.pad0 & 1u, adex = nd.pad0 & 2u, beta = nd.pad0 & 4u;
-  if (!adex) {
+  if (!adex && (nd.tile_win || !nd.n_tiles)) {
     launch(Sel<true, 0, 1>::fn(), grid, dim3(kB), s, start, stop, nd, rel);
+  } else if (!adex) {  // binned, a tile overlaps more populations than its LDS window holds
+    launch_ports<Sel, true, 1>(nd, grid, s, start, stop, rel);
   } else if (!beta) {
     if (lif) launch_ports<Sel, true, 1>(nd, grid, s, start, stop, rel);
     else launch_ports<Sel, false, 1>(nd, grid, s, start, stop, rel);
@@ -1644,7 +1681,7 @@ struct SelBinned {
 };
 
 hipError_t launch_step(const NetDev& nd, uint32_t rel, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
-  if (nd.n_tiles && nd.tile_runs)  // LIF-only networks
+  if (nd.n_tiles && nd.tile_runs && nd.tile_win)  // LIF-only networks
     launch(k_step_binned_runs<true, 0, 1>, dim3(nd.n_tiles + nd.sel_grid), dim3(kB), s, start, stop, nd, rel);
   else if (nd.n_tiles) launch_variant<SelBinned>(nd, dim3(nd.n_tiles + nd.sel_grid), s, start, stop, rel);
   else launch_variant<SelDirect>(nd, dim3(nd.nblk_upd + nd.sel_grid), s, start, stop, rel);

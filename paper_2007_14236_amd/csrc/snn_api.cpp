@@ -1915,11 +1915,27 @@ snn_status build_impl(snn_net* net) {
       // which balances delays with different hit rates and group sizes
       const uint64_t ni = net->insts.size();
       nd.dlv_queue = (ni >= kQueueMinInstances && nt <= kQueueMaxTilesPerInstance * ni) ? 1u : 0u;
+      // populations overlapping each tile, counted as the tile block finds
+      // them (the last population starting at or before its first and last
+      // neuron): the LIF-only step kernels keep them in an LDS window
+      {
+        std::vector<uint32_t> firsts(nd.npop);
+        for (size_t k = 0; k < firsts.size(); ++k) firsts[k] = net->pops[k].first;
+        auto find = [&](uint64_t gid) {
+          return (uint64_t)(std::upper_bound(firsts.begin(), firsts.end(), (uint32_t)gid) - firsts.begin()) - 1;
+        };
+        uint64_t most = 0;
+        for (uint64_t t = 0; t < nt; ++t) {
+          const uint64_t lo = t << tsh, hi = std::min<uint64_t>(nd.N, (t + 1) << tsh) - 1;
+          most = std::max(most, find(hi) - find(lo) + 1);
+        }
+        nd.tile_win = most <= kTilePopLds ? 1u : 0u;
+      }
       // tile runs: the synapses of a group onto one tile are contiguous (groups
       // are sorted by target); where they are long on average, the count pass of
       // the binned flush reads one descriptor per run instead of every synapse
       const uint64_t G = nd.n_groups;
-      if (!nd.n_rules && !net->has_adex && G) {
+      if (!nd.n_rules && !net->has_adex && nd.tile_win && G) {
         uint32_t* d_rc; ALLOC(d_rc, uint32_t, G);
         uint32_t* d_tl; ALLOC(d_tl, uint32_t, 1);
         uint64_t* d_gr; ALLOC(d_gr, uint64_t, G + 1);
@@ -2174,6 +2190,7 @@ snn_status snn_get_counters(snn_net* net, snn_counters* out) {
   out->delivery_blocks = net->nd.sel_grid;
   out->delivery_queue = net->nd.dlv_queue;
   out->tile_runs = net->nd.tile_runs;
+  out->tile_window = net->nd.tile_win;
   return leave(net);
 }
 

@@ -149,6 +149,11 @@ struct StdpRule {
   uint64_t off_plus, off_minus;
 };
 
+// Populations a tile block keeps in its LDS window (binned delivery): a
+// LIF-only network whose every tile overlaps at most this many runs step
+// kernels that read the population tables from LDS only.
+constexpr uint32_t kTilePopLds = 8;
+
 struct NetDev {
   uint32_t N, P, npop, dmax;   // dmax = largest delay present
   uint32_t npois, pois_len;    // Poisson threshold tables; entries read at most (the rest are never reached)
@@ -156,6 +161,7 @@ struct NetDev {
   uint32_t n_tiles, tile_shift;  // binned delivery (n_tiles == 0: direct atomics)
   uint32_t dlv_queue, tile_runs; // binned delivery blocks take contiguous item ranges from a queue (batches);
                                  // their count pass reads the groups' tile runs (grp_run, run_desc)
+  uint32_t tile_win, pad_tw;     // binned: every tile overlaps at most kTilePopLds populations
   uint64_t bins_total;           // bin entries per input buffer
   uint64_t log_mask;           // CAP - 1
   uint64_t chunk_ring;         // slots of chunk_base (power of two)

@@ -61,7 +61,8 @@ class Counters(C.Structure):
                 ("build_ms", C.c_double), ("simulate_ms", C.c_double), ("overflow", C.c_uint32),
                 ("max_delay_used", C.c_uint32), ("spill_events", C.c_uint64), ("delivery", C.c_uint32),
                 ("tile_neurons", C.c_uint32), ("delivery_blocks", C.c_uint32), ("delivery_queue", C.c_uint32),
-                ("last_call_device_ms", C.c_double), ("tile_runs", C.c_uint32), ("pad", C.c_uint32)]
+                ("last_call_device_ms", C.c_double), ("tile_runs", C.c_uint32),
+                ("tile_window", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -139,11 +139,27 @@ def _queue_batch():
 def test_batch_delivery_queue_bit_exact(snn, cap):
     """Binned delivery through the queue (and, with tiny bins, its spill path):
     every instance's raster and per-step input equal the oracle's."""
-    specs = _queue_batch()
+    g = _batch_parity(snn, _queue_batch(), 256, cap)
+    assert g.counters()["delivery_queue"] == 1
+    if cap:
+        assert g.counters()["spill_events"] > 0
+
+
+@pytest.mark.parametrize("tile,window", [(256, 1), (4096, 0)])
+def test_batch_population_window(snn, tile, window):
+    """LIF-only batch: where every tile overlaps at most 8 populations, the
+    step kernels read the population tables from an LDS window; 4096-neuron
+    tiles overlap up to 13 of the batch's 20 populations, and the network
+    runs the kernel built for AdEx as well.  Both bit-exact."""
+    g = _batch_parity(snn, _queue_batch(), tile, 0)
+    assert g.counters()["tile_window"] == window
+
+
+def _batch_parity(snn, specs, tile, cap):
+    """Every instance's raster and its per-step input at two probe steps
+    equal the oracle's; returns the network after 300 steps."""
     steps = 300
-    g = snn.Net(specs, delivery="binned", tile_neurons=256, bin_capacity=cap)
-    c = g.counters()
-    assert c["delivery_queue"] == 1
+    g = snn.Net(specs, delivery="binned", tile_neurons=tile, bin_capacity=cap)
     probe = (99, 200)
     recs = []
     for sp in specs:
@@ -169,10 +185,8 @@ def test_batch_delivery_queue_bit_exact(snn, cap):
         assert np.array_equal(gm[sel], om)
         total += len(os_)
     assert total > 1000
-    c = g.counters()
-    assert c["overflow"] == 0
-    if cap:
-        assert c["spill_events"] > 0
+    assert g.counters()["overflow"] == 0
+    return g
 
 
 def test_single_network_keeps_the_strided_share(snn):
